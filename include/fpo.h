@@ -1,0 +1,180 @@
+/*
+ * fpo.h -- C ABI of libfpo, an MI355X (gfx950) library that builds the
+ * shallow out-of-core octree and the immediate decimated preview of FastPoints
+ * (arXiv 2302.05002) from a point buffer already resident in GPU memory.
+ *
+ * The problem statement follows the paper's program structure (sections
+ * "Program Structure" and "Implementation"): a point cloud comes in, a
+ * uniformly decimated preview is available first, and an octree is built
+ * without blocking the caller (section "Octree Construction": points are
+ * sorted hierarchically into chunks, chunks are indexed into local octrees,
+ * the local trees form one global tree; section "Immediate Low-Resolution
+ * Rendering": a decimation that visits every point).  The paper fixes no
+ * constants or orderings; the readings this library implements are:
+ *
+ *   - lattice: K = 21 bits per axis.  The cube is anchored at the bounding-box
+ *     minimum with side = the largest extent; scale = 2^21 / side computed in
+ *     double and rounded once to float (0 for side 0); the fine coordinate of
+ *     an axis value a is clamp(floor((a - min) * scale), 0, 2^21 - 1) with one
+ *     float subtraction and one float multiplication (NaN products map to 0).
+ *     A computed -0.0 extreme is reported as +0.0.
+ *   - count grid: G^3 cells, cell = fine >> (21 - log2 G), row-major [x][y][z].
+ *   - chunks: the maximal pyramid nodes holding 0 < count <= C points; a finest
+ *     cell with more than C points is an oversized chunk.  Chunks are listed in
+ *     Morton pre-order (octant = x<<2 | y<<1 | z); perm lists the points chunk
+ *     by chunk, ascending original index inside a chunk.
+ *   - octree: top-down from the root, which receives every point.  A node at
+ *     depth d receiving the set R is a leaf when |R| <= L or d == 21 - log2 S;
+ *     otherwise it keeps, for every occupied cell of an S^3 grid over its cube,
+ *     the point of lowest original index, and pushes the others to the child
+ *     octants.  Only non-empty children exist.  Nodes are listed by (depth,
+ *     Morton key); each node's points ascend.  The tree does not depend on G or
+ *     C.
+ *   - preview: every index i with H64(i) mod M == 0, ascending, where H64 is
+ *     h = i; h ^= h >> 31; h *= 0x9E3779B97F4A7C15; h ^= h >> 29;
+ *     h *= 0x9E3779B97F4A7C15; h ^= h >> 32 (all mod 2^64).
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an fpo_status; fpo_last_error() gives the text of the
+ *     last non-OK status of the calling thread.  Arguments are validated
+ *     before any GPU work is enqueued.
+ *   - Pointers marked "device" are HIP device pointers on the context's device;
+ *     the library never frees memory it did not allocate.
+ *   - The caller owns the workspace (size from fpo_workspace_size); result
+ *     arrays are views into it, valid until the workspace is reused or freed.
+ *   - Inputs must stay valid and unmodified until fpo_job_wait/poll reports a
+ *     status other than FPO_NOT_READY.
+ *   - A context may be used from several threads; a job from one at a time.
+ */
+#ifndef FPO_H
+#define FPO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FPO_OK = 0,
+    FPO_ERR_INVALID_ARG = 1,   /* bad parameter, size or pointer */
+    FPO_ERR_NONFINITE = 2,     /* a coordinate is NaN or infinite (reported by poll/wait) */
+    FPO_ERR_OUT_OF_MEMORY = 3, /* workspace too small, or a host/device allocation failed */
+    FPO_ERR_DEVICE = 4,        /* a HIP runtime call failed */
+    FPO_NOT_READY = 5,         /* poll: the build is still running */
+    FPO_ERR_REJECTED = 6,      /* reserved for admission control */
+    FPO_ERR_CANCELLED = 7      /* reserved */
+} fpo_status;
+
+typedef struct fpo_context fpo_context;
+typedef struct fpo_job fpo_job;
+
+#define FPO_BBOX_GIVEN 1u      /* fpo_params.flags: use bbox_min/bbox_max instead of computing it */
+
+/* Build parameters (names after the paper's "maxPointsPerChunk" style):
+ *   count_grid G: power of two, 1..512;  max_points_per_chunk C >= 1;
+ *   subsample_grid S: power of two, 1..256;  leaf_capacity L >= 1;
+ *   preview_modulus M >= 1.
+ * With FPO_BBOX_GIVEN, bbox_min <= bbox_max per axis, all finite; points
+ * outside the box clamp to its faces and are counted in fpo_result.n_outside. */
+typedef struct {
+    uint32_t count_grid;
+    uint32_t max_points_per_chunk;
+    uint32_t subsample_grid;
+    uint32_t leaf_capacity;
+    uint32_t preview_modulus;
+    uint32_t flags;
+    float bbox_min[3];
+    float bbox_max[3];
+} fpo_params;
+
+/* A point cloud: n points as three float32 arrays (structure of arrays),
+ * device pointers, n <= 2^32 - 1 (indices are 32-bit).  Point i is (x[i],
+ * y[i], z[i]); i is its original index. */
+typedef struct {
+    uint64_t n;
+    const float *x;
+    const float *y;
+    const float *z;
+} fpo_cloud;
+
+/* Result of a build.  Scalars are host values; arrays are device pointers
+ * into the workspace.
+ *   count_grid   uint32[G^3], row-major [cx][cy][cz]
+ *   chunk_*      num_chunks entries in Morton pre-order: level, key (Morton
+ *                key of the chunk's cell at that level), count, begin (offset
+ *                of the chunk in perm); chunk_oversized_any = 1 when some
+ *                finest cell holds more than C points
+ *   perm         uint32[n]: original indices, chunk by chunk, ascending inside
+ *   node_*       num_nodes entries in (depth, key) order: depth, key (Morton
+ *                key at that depth), child_mask (bit o = child octant o
+ *                exists), begin (offset into node_points), count
+ *   node_points  uint32[n]: original indices, node by node, ascending inside
+ *   preview_index uint32[preview_count], ascending */
+typedef struct {
+    uint64_t n;
+    float bbox_min[3], bbox_max[3];
+    float cube_size, scale;
+    uint64_t n_outside;
+    const uint32_t *count_grid;
+    uint32_t num_chunks;
+    const uint8_t *chunk_level;
+    const uint64_t *chunk_key;
+    const uint32_t *chunk_count;
+    const uint64_t *chunk_begin;
+    uint8_t chunk_oversized_any;
+    const uint32_t *perm;
+    uint32_t num_nodes;
+    const uint8_t *node_depth;
+    const uint64_t *node_key;
+    const uint8_t *node_child_mask;
+    const uint64_t *node_begin;
+    const uint32_t *node_count;
+    const uint32_t *node_points;
+    uint64_t preview_count;
+    const uint32_t *preview_index;
+} fpo_result;
+
+/* Creates a context on HIP device `device` (its streams, events and pinned
+ * host staging).  *out receives the handle; destroy it with
+ * fpo_context_destroy after every job of it has been released. */
+fpo_status fpo_context_create(int device, fpo_context **out);
+void fpo_context_destroy(fpo_context *ctx);
+
+/* Text of the last non-OK status returned to the calling thread ("" if none).
+ * The pointer stays valid until the thread's next fpo call. */
+const char *fpo_last_error(void);
+
+/* Worst-case workspace bytes of one build of n points with *p. */
+fpo_status fpo_workspace_size(uint64_t n, const fpo_params *p, uint64_t *bytes);
+
+/* Enqueues a build of *cloud on hip_stream (a hipStream_t; NULL = the
+ * context's own stream) using `workspace` (device, >= fpo_workspace_size
+ * bytes, 256-byte aligned, owned by the caller).  The preview kernels are
+ * enqueued first.  *out receives a job handle; release it with
+ * fpo_job_release.  Returns FPO_ERR_NONFINITE when a coordinate is not
+ * finite; other errors before any work is enqueued. */
+fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
+                            uint64_t workspace_bytes, void *hip_stream, fpo_job **out);
+
+/* FPO_OK once the preview of the job is complete, FPO_NOT_READY before. */
+fpo_status fpo_job_preview_ready(fpo_job *job);
+
+/* FPO_OK when the whole build is complete, FPO_NOT_READY while it runs, or
+ * the error that ended it.  Never blocks. */
+fpo_status fpo_job_poll(fpo_job *job);
+
+/* Blocks until the build is complete; returns its status. */
+fpo_status fpo_job_wait(fpo_job *job);
+
+/* Fills *out for a completed job (call after fpo_job_wait returned FPO_OK). */
+fpo_status fpo_job_result(fpo_job *job, fpo_result *out);
+
+/* Waits for the job if it still runs, then frees the handle (not the
+ * workspace). */
+void fpo_job_release(fpo_job *job);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,271 @@
+"""Python binding of libfpo: the MI355X (gfx950) octree build and decimated
+preview of FastPoints (arXiv 2302.05002).
+
+Argument marshalling only: every step runs in the HIP kernels of
+``csrc/`` behind the C ABI declared in ``include/fpo.h``.  PyTorch supplies
+device memory (the workspace and the inputs) and the stream.  There is no CPU
+fallback: importing works anywhere, but building needs ``libfpo.so`` (built by
+``paper_2302_05002_amd.build``) and a GPU, and fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfpo.so")
+
+FPO_OK, FPO_ERR_INVALID_ARG, FPO_ERR_NONFINITE, FPO_ERR_OUT_OF_MEMORY = 0, 1, 2, 3
+FPO_ERR_DEVICE, FPO_NOT_READY, FPO_ERR_REJECTED, FPO_ERR_CANCELLED = 4, 5, 6, 7
+FPO_BBOX_GIVEN = 1
+
+#: every symbol include/fpo.h declares
+EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_workspace_size",
+           "fpo_build_submit", "fpo_job_preview_ready", "fpo_job_poll", "fpo_job_wait",
+           "fpo_job_result", "fpo_job_release")
+
+
+class FpoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fpo status {status}: {msg}")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("count_grid", ctypes.c_uint32), ("max_points_per_chunk", ctypes.c_uint32),
+                ("subsample_grid", ctypes.c_uint32), ("leaf_capacity", ctypes.c_uint32),
+                ("preview_modulus", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("bbox_min", ctypes.c_float * 3), ("bbox_max", ctypes.c_float * 3)]
+
+
+class _Cloud(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("bbox_min", ctypes.c_float * 3), ("bbox_max", ctypes.c_float * 3),
+                ("cube_size", ctypes.c_float), ("scale", ctypes.c_float), ("n_outside", ctypes.c_uint64),
+                ("count_grid", ctypes.c_void_p), ("num_chunks", ctypes.c_uint32),
+                ("chunk_level", ctypes.c_void_p), ("chunk_key", ctypes.c_void_p),
+                ("chunk_count", ctypes.c_void_p), ("chunk_begin", ctypes.c_void_p),
+                ("chunk_oversized_any", ctypes.c_uint8), ("perm", ctypes.c_void_p),
+                ("num_nodes", ctypes.c_uint32), ("node_depth", ctypes.c_void_p), ("node_key", ctypes.c_void_p),
+                ("node_child_mask", ctypes.c_void_p), ("node_begin", ctypes.c_void_p),
+                ("node_count", ctypes.c_void_p), ("node_points", ctypes.c_void_p),
+                ("preview_count", ctypes.c_uint64), ("preview_index", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libfpo.so and declare its C signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libfpo.so is not built ({path}); run paper_2302_05002_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    vp, P = ctypes.c_void_p, ctypes.POINTER
+    lib.fpo_context_create.argtypes = [ctypes.c_int, P(vp)]
+    lib.fpo_context_create.restype = ctypes.c_int
+    lib.fpo_context_destroy.argtypes = [vp]
+    lib.fpo_context_destroy.restype = None
+    lib.fpo_last_error.argtypes = []
+    lib.fpo_last_error.restype = ctypes.c_char_p
+    lib.fpo_workspace_size.argtypes = [ctypes.c_uint64, P(_Params), P(ctypes.c_uint64)]
+    lib.fpo_workspace_size.restype = ctypes.c_int
+    lib.fpo_build_submit.argtypes = [vp, P(_Cloud), P(_Params), vp, ctypes.c_uint64, vp, P(vp)]
+    lib.fpo_build_submit.restype = ctypes.c_int
+    for f in ("fpo_job_preview_ready", "fpo_job_poll", "fpo_job_wait"):
+        getattr(lib, f).argtypes = [vp]
+        getattr(lib, f).restype = ctypes.c_int
+    lib.fpo_job_result.argtypes = [vp, P(_Result)]
+    lib.fpo_job_result.restype = ctypes.c_int
+    lib.fpo_job_release.argtypes = [vp]
+    lib.fpo_job_release.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != FPO_OK:
+        raise FpoError(st, _lib.fpo_last_error().decode())
+
+
+@dataclass
+class Params:
+    """G count grid, C max points per chunk, S subsample grid, L leaf capacity,
+    M preview modulus; bbox = ((xmin, ymin, zmin), (xmax, ymax, zmax)) to use a
+    caller-given box."""
+    count_grid: int = 64
+    max_points_per_chunk: int = 100_000
+    subsample_grid: int = 32
+    leaf_capacity: int = 10_000
+    preview_modulus: int = 64
+    bbox: tuple | None = None
+
+    def to_c(self) -> _Params:
+        p = _Params(self.count_grid, self.max_points_per_chunk, self.subsample_grid, self.leaf_capacity,
+                    self.preview_modulus, FPO_BBOX_GIVEN if self.bbox is not None else 0)
+        if self.bbox is not None:
+            for a in range(3):
+                p.bbox_min[a] = self.bbox[0][a]
+                p.bbox_max[a] = self.bbox[1][a]
+        return p
+
+
+def workspace_size(n: int, params: Params) -> int:
+    lib = load_library()
+    out = ctypes.c_uint64()
+    _check(lib.fpo_workspace_size(n, ctypes.byref(params.to_c()), ctypes.byref(out)))
+    return int(out.value)
+
+
+class Context:
+    """One device: its own stream and pinned staging."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: libfpo runs only on an MI355X (gfx950)")
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.fpo_context_create(device, ctypes.byref(h)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if self._h:
+            _lib.fpo_context_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, x, y, z, params: Params, workspace=None, stream=None) -> "Job":
+        """Enqueue a build of the device tensors x, y, z (float32, contiguous).
+        Allocates the workspace with torch when none is given."""
+        import torch
+        n = int(x.shape[0])
+        for t in (x, y, z):
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.shape[0] == n
+        need = workspace_size(n, params)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+        cloud = _Cloud(n, x.data_ptr(), y.data_ptr(), z.data_ptr())
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        h = ctypes.c_void_p()
+        _check(_lib.fpo_build_submit(self._h, ctypes.byref(cloud), ctypes.byref(params.to_c()),
+                                     ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                     ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        return Job(h, workspace, params, (x, y, z))
+
+    def build(self, x, y, z, params: Params, workspace=None, stream=None) -> "Result":
+        job = self.submit(x, y, z, params, workspace, stream)
+        job.wait()
+        return job.result()
+
+
+class Job:
+    def __init__(self, h, workspace, params, inputs):
+        self._h = h
+        self.workspace = workspace
+        self.params = params
+        self._inputs = inputs
+
+    def preview_ready(self) -> bool:
+        st = _lib.fpo_job_preview_ready(self._h)
+        if st == FPO_NOT_READY:
+            return False
+        _check(st)
+        return True
+
+    def poll(self) -> bool:
+        st = _lib.fpo_job_poll(self._h)
+        if st == FPO_NOT_READY:
+            return False
+        _check(st)
+        return True
+
+    def wait(self):
+        _check(_lib.fpo_job_wait(self._h))
+
+    def result(self) -> "Result":
+        r = _Result()
+        _check(_lib.fpo_job_result(self._h, ctypes.byref(r)))
+        return Result(r, self.workspace, self.params)
+
+    def release(self):
+        if self._h:
+            _lib.fpo_job_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class Result:
+    """Host scalars plus device tensors viewing the workspace."""
+
+    def __init__(self, r: _Result, ws, params: Params):
+        import torch
+        self.n = int(r.n)
+        self.bbox_min = np.array(r.bbox_min[:], dtype=np.float32)
+        self.bbox_max = np.array(r.bbox_max[:], dtype=np.float32)
+        self.cube_size = np.float32(r.cube_size)
+        self.scale = np.float32(r.scale)
+        self.n_outside = int(r.n_outside)
+        self.num_chunks = int(r.num_chunks)
+        self.num_nodes = int(r.num_nodes)
+        self.preview_count = int(r.preview_count)
+        self.chunk_oversized_any = int(r.chunk_oversized_any)
+        base = ws.data_ptr()
+        G = params.count_grid
+
+        def view(ptr, count, dtype, itemsize):
+            if count == 0 or not ptr:
+                return torch.empty(0, dtype=dtype, device=ws.device)
+            off = ptr - base
+            assert 0 <= off and off + count * itemsize <= ws.numel()
+            return ws[off:off + count * itemsize].view(dtype)
+
+        u8, i32, i64 = torch.uint8, torch.int32, torch.int64
+        self.count_grid = view(r.count_grid, G ** 3, i32, 4)
+        self.chunk_level = view(r.chunk_level, self.num_chunks, u8, 1)
+        self.chunk_key = view(r.chunk_key, self.num_chunks, i64, 8)
+        self.chunk_count = view(r.chunk_count, self.num_chunks, i32, 4)
+        self.chunk_begin = view(r.chunk_begin, self.num_chunks, i64, 8)
+        self.perm = view(r.perm, self.n, i32, 4)
+        self.node_depth = view(r.node_depth, self.num_nodes, u8, 1)
+        self.node_key = view(r.node_key, self.num_nodes, i64, 8)
+        self.node_child_mask = view(r.node_child_mask, self.num_nodes, u8, 1)
+        self.node_begin = view(r.node_begin, self.num_nodes, i64, 8)
+        self.node_count = view(r.node_count, self.num_nodes, i32, 4)
+        self.node_points = view(r.node_points, self.n, i32, 4)
+        self.preview_index = view(r.preview_index, self.preview_count, i32, 4)
+
+    def to_numpy(self) -> dict:
+        """Copy everything to host numpy arrays (unsigned dtypes)."""
+        def cpu(t, dt):
+            return t.cpu().numpy().view(dt)
+        return dict(
+            status=FPO_OK, n=self.n, bbox_min=self.bbox_min, bbox_max=self.bbox_max, cube_size=self.cube_size,
+            scale=self.scale, n_outside=self.n_outside,
+            count_grid=cpu(self.count_grid, np.uint32), chunk_level=cpu(self.chunk_level, np.uint8),
+            chunk_key=cpu(self.chunk_key, np.uint64), chunk_count=cpu(self.chunk_count, np.uint32),
+            chunk_begin=cpu(self.chunk_begin, np.uint64), chunk_oversized_any=self.chunk_oversized_any,
+            perm=cpu(self.perm, np.uint32), node_depth=cpu(self.node_depth, np.uint8),
+            node_key=cpu(self.node_key, np.uint64), node_child_mask=cpu(self.node_child_mask, np.uint8),
+            node_begin=cpu(self.node_begin, np.uint64), node_count=cpu(self.node_count, np.uint32),
+            node_points=cpu(self.node_points, np.uint32), preview_index=cpu(self.preview_index, np.uint32))

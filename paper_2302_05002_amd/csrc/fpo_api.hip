@@ -1,0 +1,548 @@
+// Host side of libfpo: argument checks, workspace layout and the launch
+// sequence of one build (C ABI in include/fpo.h).
+#include <mutex>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+#include <string>
+#include <vector>
+
+#include "../../include/fpo.h"
+#include "fpo_internal.h"
+
+using namespace fpo;
+
+namespace {
+
+thread_local std::string g_err;
+
+fpo_status fail(fpo_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail(FPO_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_pow2(uint32_t v) { return v && !(v & (v - 1)); }
+int ilog2(uint32_t v)
+{
+    int l = 0;
+    while ((1u << l) < v) ++l;
+    return l;
+}
+size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Small device counters read back by the host.
+struct Ctrs {
+    uint32_t num_chunks;
+    uint32_t num_wc;
+    uint32_t num_big;
+    uint32_t max_big;
+    uint32_t num_nodes;
+    uint32_t preview_count;
+    uint32_t oversized;
+    uint32_t internal_error;
+};
+
+// Byte offsets of every region of the workspace for (n, params).
+struct Plan {
+    uint64_t n;
+    int g, s, lam_w;
+    uint64_t G3, W3, P;      // finest cells, work-chunk-level cells, pyramid words
+    uint64_t maxC, maxW;
+    size_t total;
+    // results
+    size_t box, ctrs, grid, c_level, c_key, c_count, c_begin, perm;
+    size_t n_depth, n_key, n_mask, n_begin, n_count, n_points, pv_index;
+    // temporaries
+    size_t code, pyr, fc, ec, lc, fw, ew, lw_, w_level, w_key, w_count, w_start, w_begin;
+    size_t c_count_scan, cid, wid, wc_idx, wc_code, ms_temp, scan_temp;
+    size_t t, fr, shared_cnt, kd, loff, owned, node_base, lnode_key, lnode_mask, cut;
+    size_t big_list, big_nr, big_node, big_hkey, big_hval;
+    size_t nid, sorted_nid, pv_tiles, pv_offs;
+    uint64_t pv_ntiles;
+};
+
+Plan make_plan(uint64_t n, const fpo_params &p)
+{
+    Plan P{};
+    P.n = n;
+    P.g = ilog2(p.count_grid);
+    P.s = ilog2(p.subsample_grid);
+    P.lam_w = P.g < P.s ? P.g : P.s;
+    P.G3 = 1ull << (3 * P.g);
+    P.W3 = 1ull << (3 * P.lam_w);
+    P.P = pyr_off(P.g + 1);
+    const uint64_t nn = n ? n : 1;
+    P.maxC = nn < P.G3 ? nn : P.G3;
+    P.maxW = nn < P.W3 ? nn : P.W3;
+    P.pv_ntiles = preview_tiles(nn);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += a256(bytes ? bytes : 1);
+        return r;
+    };
+    P.box = take(sizeof(DevBox));
+    P.ctrs = take(sizeof(Ctrs));
+    P.grid = take(4 * P.G3);
+    P.c_level = take(P.maxC);
+    P.c_key = take(8 * P.maxC);
+    P.c_count = take(4 * P.maxC);
+    P.c_begin = take(8 * P.maxC);
+    P.perm = take(4 * nn);
+    P.n_depth = take(nn);
+    P.n_key = take(8 * nn);
+    P.n_mask = take(nn + 4);
+    P.n_begin = take(8 * nn);
+    P.n_count = take(4 * nn);
+    P.n_points = take(4 * nn);
+    P.pv_index = take(4 * nn);
+    P.code = take(8 * nn);
+    P.pyr = take(4 * P.P);
+    P.fc = take(4 * P.G3);
+    P.ec = take(4 * P.G3);
+    P.lc = take(P.G3);
+    P.fw = take(4 * P.W3);
+    P.ew = take(4 * P.W3);
+    P.lw_ = take(P.W3);
+    P.w_level = take(P.maxW);
+    P.w_key = take(8 * P.maxW);
+    P.w_count = take(4 * P.maxW);
+    P.w_start = take(8 * P.maxW);
+    P.w_begin = take(4 * P.maxW);
+    P.c_count_scan = take(4 * P.maxC);
+    P.cid = take(4 * nn);
+    P.wid = take(4 * nn);
+    P.wc_idx = take(4 * nn);
+    P.wc_code = take(8 * nn);
+    // chunks, work chunks and nodes each number at most n
+    P.ms_temp = take(multisplit_temp_bound(nn, nn));
+    uint64_t scan_max = P.G3 > (uint64_t)MAXD * P.maxW ? P.G3 : (uint64_t)MAXD * P.maxW;
+    if (P.pv_ntiles > scan_max) scan_max = P.pv_ntiles;
+    P.scan_temp = take(scan_temp_bytes(scan_max));
+    P.t = take(nn);
+    P.fr = take(4 * nn);
+    P.shared_cnt = take(4 * P.P);
+    P.kd = take(4 * MAXD * P.maxW);
+    P.loff = take(4 * MAXD * P.maxW);
+    P.owned = take(4 * MAXD * P.maxW);
+    P.node_base = take(4 * MAXD * P.maxW);
+    P.lnode_key = take(8 * nn);
+    P.lnode_mask = take(nn);
+    P.cut = take(P.maxW);
+    P.big_list = take(4 * P.maxW);
+    P.big_nr = take(4 * nn);
+    P.big_node = take(12 * nn);
+    // hash slots for work chunks above the LDS capacity: at most 4n in total
+    P.big_hkey = take(8 * 4 * nn);
+    P.big_hval = take(4 * 4 * nn);
+    P.nid = take(4 * nn);
+    P.sorted_nid = take(4 * nn);
+    P.pv_tiles = take(4 * P.pv_ntiles);
+    P.pv_offs = take(4 * P.pv_ntiles);
+    P.total = o;
+    return P;
+}
+
+fpo_status check_params(uint64_t n, const fpo_params *p)
+{
+    if (!p) return fail(FPO_ERR_INVALID_ARG, "params is NULL");
+    if (!is_pow2(p->count_grid) || p->count_grid > 512)
+        return fail(FPO_ERR_INVALID_ARG, "count_grid must be a power of two in 1..512 (got %u)", p->count_grid);
+    if (!is_pow2(p->subsample_grid) || p->subsample_grid > 256)
+        return fail(FPO_ERR_INVALID_ARG, "subsample_grid must be a power of two in 1..256 (got %u)", p->subsample_grid);
+    if (p->max_points_per_chunk == 0) return fail(FPO_ERR_INVALID_ARG, "max_points_per_chunk must be >= 1");
+    if (p->leaf_capacity == 0) return fail(FPO_ERR_INVALID_ARG, "leaf_capacity must be >= 1");
+    if (p->preview_modulus == 0) return fail(FPO_ERR_INVALID_ARG, "preview_modulus must be >= 1");
+    if (n > 0xffffffffull) return fail(FPO_ERR_INVALID_ARG, "n = %llu exceeds 2^32 - 1", (unsigned long long)n);
+    if (p->flags & ~FPO_BBOX_GIVEN) return fail(FPO_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
+    if (p->flags & FPO_BBOX_GIVEN)
+        for (int a = 0; a < 3; ++a) {
+            const float lo = p->bbox_min[a], hi = p->bbox_max[a];
+            if (!(lo == lo) || !(hi == hi) || lo - lo != 0.0f || hi - hi != 0.0f || lo > hi)
+                return fail(FPO_ERR_INVALID_ARG, "given bbox must be finite with min <= max on axis %d", a);
+        }
+    return FPO_OK;
+}
+
+}  // namespace
+
+struct fpo_context {
+    int device;
+    hipStream_t stream;
+    std::mutex mu;
+    std::vector<void *> pinned_free;
+};
+
+struct fpo_job {
+    fpo_context *ctx;
+    hipStream_t stream;
+    hipEvent_t ev_preview, ev_done;
+    void *pinned;                 // Ctrs + DevBox staging
+    fpo_status status;
+    fpo_result res;
+    bool waited;
+};
+
+namespace {
+
+constexpr size_t PINNED_BYTES = 1024;
+
+void *get_pinned(fpo_context *c)
+{
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!c->pinned_free.empty()) {
+        void *p = c->pinned_free.back();
+        c->pinned_free.pop_back();
+        return p;
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, PINNED_BYTES, hipHostMallocDefault) != hipSuccess) return nullptr;
+    return p;
+}
+
+void put_pinned(fpo_context *c, void *p)
+{
+    std::lock_guard<std::mutex> g(c->mu);
+    c->pinned_free.push_back(p);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fpo_last_error(void) { return g_err.c_str(); }
+
+fpo_status fpo_context_create(int device, fpo_context **out)
+{
+    if (!out) return fail(FPO_ERR_INVALID_ARG, "out is NULL");
+    int count = 0;
+    HIPCHK(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(FPO_ERR_INVALID_ARG, "device %d out of range (%d devices)", device, count);
+    HIPCHK(hipSetDevice(device));
+    fpo_context *c = new fpo_context();
+    c->device = device;
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail(FPO_ERR_DEVICE, "hipStreamCreate failed");
+    }
+    *out = c;
+    return FPO_OK;
+}
+
+void fpo_context_destroy(fpo_context *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    for (void *p : c->pinned_free) (void)hipHostFree(p);
+    (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+fpo_status fpo_workspace_size(uint64_t n, const fpo_params *p, uint64_t *bytes)
+{
+    fpo_status s = check_params(n, p);
+    if (s != FPO_OK) return s;
+    if (!bytes) return fail(FPO_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = make_plan(n, *p).total;
+    return FPO_OK;
+}
+
+fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
+                            uint64_t workspace_bytes, void *hip_stream, fpo_job **out)
+{
+    if (!ctx || !cloud || !out) return fail(FPO_ERR_INVALID_ARG, "NULL context, cloud or out");
+    fpo_status s = check_params(cloud->n, p);
+    if (s != FPO_OK) return s;
+    const uint64_t n = cloud->n;
+    if (n > 0 && (!cloud->x || !cloud->y || !cloud->z)) return fail(FPO_ERR_INVALID_ARG, "NULL coordinate array");
+    if (!workspace) return fail(FPO_ERR_INVALID_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(FPO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    const Plan P = make_plan(n, *p);
+    if (workspace_bytes < P.total)
+        return fail(FPO_ERR_OUT_OF_MEMORY, "workspace holds %llu bytes, the build needs %llu",
+                    (unsigned long long)workspace_bytes, (unsigned long long)P.total);
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->stream;
+
+    fpo_job *job = new fpo_job();
+    job->ctx = ctx;
+    job->stream = st;
+    job->status = FPO_OK;
+    job->waited = false;
+    job->pinned = get_pinned(ctx);
+    if (!job->pinned) {
+        delete job;
+        return fail(FPO_ERR_OUT_OF_MEMORY, "pinned host staging allocation failed");
+    }
+    if (hipEventCreateWithFlags(&job->ev_preview, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&job->ev_done, hipEventDisableTiming) != hipSuccess) {
+        put_pinned(ctx, job->pinned);
+        delete job;
+        return fail(FPO_ERR_DEVICE, "hipEventCreate failed");
+    }
+
+    char *ws = static_cast<char *>(workspace);
+    auto U32 = [&](size_t off) { return reinterpret_cast<uint32_t *>(ws + off); };
+    auto U64 = [&](size_t off) { return reinterpret_cast<uint64_t *>(ws + off); };
+    auto U8 = [&](size_t off) { return reinterpret_cast<uint8_t *>(ws + off); };
+    DevBox *box = reinterpret_cast<DevBox *>(ws + P.box);
+    Ctrs *ctrs = reinterpret_cast<Ctrs *>(ws + P.ctrs);
+    Ctrs *hctrs = static_cast<Ctrs *>(job->pinned);
+    DevBox *hbox = reinterpret_cast<DevBox *>(static_cast<char *>(job->pinned) + 256);
+    const int g = P.g, s_ = P.s;
+    const uint32_t G = p->count_grid;
+    (void)G;
+    const uint64_t M = p->preview_modulus;
+    void *stemp = ws + P.scan_temp;
+
+    fpo_result &R = job->res;
+    memset(&R, 0, sizeof(R));
+    R.n = n;
+    R.count_grid = U32(P.grid);
+    R.chunk_level = U8(P.c_level);
+    R.chunk_key = U64(P.c_key);
+    R.chunk_count = U32(P.c_count);
+    R.chunk_begin = U64(P.c_begin);
+    R.perm = U32(P.perm);
+    R.node_depth = U8(P.n_depth);
+    R.node_key = U64(P.n_key);
+    R.node_child_mask = U8(P.n_mask);
+    R.node_begin = U64(P.n_begin);
+    R.node_count = U32(P.n_count);
+    R.node_points = U32(P.n_points);
+    R.preview_index = U32(P.pv_index);
+
+#define JCHK(call)                                                                              \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) {                                                                 \
+            fpo_status fs_ = fail(FPO_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_));      \
+            fpo_job_release(job);                                                               \
+            return fs_;                                                                         \
+        }                                                                                       \
+    } while (0)
+
+    JCHK(hipMemsetAsync(ctrs, 0, sizeof(Ctrs), st));
+    if (n == 0) {
+        JCHK(hipMemsetAsync(U32(P.grid), 0, 4 * P.G3, st));
+        JCHK(hipEventRecord(job->ev_preview, st));
+        JCHK(hipEventRecord(job->ev_done, st));
+        if (p->flags & FPO_BBOX_GIVEN)
+            for (int a = 0; a < 3; ++a) { R.bbox_min[a] = p->bbox_min[a]; R.bbox_max[a] = p->bbox_max[a]; }
+        *out = job;
+        return FPO_OK;
+    }
+
+    // ---- step 5 first: the preview depends on n and M only ----
+    launch_preview_count(n, M, U32(P.pv_tiles), st);
+    scan_exclusive(U32(P.pv_tiles), U32(P.pv_offs), P.pv_ntiles, &ctrs->preview_count, stemp, st);
+    launch_preview_write(n, M, U32(P.pv_offs), U32(P.pv_index), st);
+    JCHK(hipEventRecord(job->ev_preview, st));
+
+    // ---- step 1: bbox, quantise, count ----
+    const int given = (p->flags & FPO_BBOX_GIVEN) ? 1 : 0;
+    launch_bbox_init(box, st);
+    launch_bbox(cloud->x, cloud->y, cloud->z, n, box, st);  // also detects non-finite values
+    launch_setup(box, given, p->bbox_min, p->bbox_max, st);
+    uint32_t *pyr = U32(P.pyr);
+    uint32_t *fine = pyr + pyr_off(g);
+    JCHK(hipMemsetAsync(fine, 0, 4 * P.G3, st));
+    launch_quantize(cloud->x, cloud->y, cloud->z, n, box, g, given, U64(P.code), fine, box, st);
+
+    // ---- step 2: pyramid, chunk cut, work-chunk cut ----
+    launch_pyramid(pyr, g, st);
+    launch_grid_export(fine, g, U32(P.grid), st);
+    launch_cut_flags(pyr, g, p->max_points_per_chunk, U32(P.fc), U8(P.lc), st);
+    scan_exclusive(U32(P.fc), U32(P.ec), P.G3, &ctrs->num_chunks, stemp, st);
+    launch_cut_table(pyr, g, U32(P.fc), U32(P.ec), U8(P.lc), U8(P.c_level), U64(P.c_key), U32(P.c_count), nullptr,
+                     p->max_points_per_chunk, &ctrs->oversized, st);
+    launch_cut_flags(pyr, P.lam_w, WC_CAP, U32(P.fw), U8(P.lw_), st);
+    scan_exclusive(U32(P.fw), U32(P.ew), P.W3, &ctrs->num_wc, stemp, st);
+    launch_cut_table(pyr, P.lam_w, U32(P.fw), U32(P.ew), U8(P.lw_), U8(P.w_level), U64(P.w_key), U32(P.w_count),
+                     U64(P.w_start), WC_CAP, nullptr, st);
+    JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
+    JCHK(hipMemcpyAsync(hbox, box, sizeof(DevBox), hipMemcpyDeviceToHost, st));
+    JCHK(hipStreamSynchronize(st));
+    if (hbox->nonfinite) {
+        fpo_job_release(job);
+        return fail(FPO_ERR_NONFINITE, "a coordinate is NaN or infinite");
+    }
+    const uint32_t num_chunks = hctrs->num_chunks, num_wc = hctrs->num_wc;
+
+    // chunk begins (u64) and work-chunk begins
+    scan_exclusive(U32(P.c_count), U32(P.c_count_scan), num_chunks, nullptr, stemp, st);
+    launch_u32_to_u64(U32(P.c_count_scan), U64(P.c_begin), num_chunks, st);
+    scan_exclusive(U32(P.w_count), U32(P.w_begin), num_wc, nullptr, stemp, st);
+
+    // ---- step 3: stable scatter by chunk (perm) and by work chunk ----
+    launch_point_keys(U64(P.code), n, g, U32(P.fc), U32(P.ec), P.lam_w, U32(P.fw), U32(P.ew), U32(P.cid), U32(P.wid), st);
+    multisplit(U32(P.cid), n, num_chunks, nullptr, U32(P.perm), nullptr, nullptr, ws + P.ms_temp, st);
+    multisplit(U32(P.wid), n, num_wc, U64(P.code), U32(P.wc_idx), nullptr, U64(P.wc_code), ws + P.ms_temp, st);
+
+    // ---- step 4: subsample ----
+    // host list of work chunks too large for the LDS path
+    std::vector<uint32_t> wcount(num_wc);
+    JCHK(hipMemcpyAsync(wcount.data(), U32(P.w_count), 4ull * num_wc, hipMemcpyDeviceToHost, st));
+    JCHK(hipStreamSynchronize(st));
+    std::vector<uint32_t> big;
+    uint32_t max_big = 0;
+    for (uint32_t w = 0; w < num_wc; ++w)
+        if (wcount[w] > WC_CAP) {
+            big.push_back(w);
+            if (wcount[w] > max_big) max_big = wcount[w];
+        }
+    if (!big.empty()) JCHK(hipMemcpyAsync(U32(P.big_list), big.data(), 4 * big.size(), hipMemcpyHostToDevice, st));
+
+    WcArgs A{};
+    A.num_wc = num_wc;
+    A.wc_begin = U32(P.w_begin);
+    A.wc_count = U32(P.w_count);
+    A.wc_level = U8(P.w_level);
+    A.wc_key = U64(P.w_key);
+    A.wc_start = U64(P.w_start);
+    A.wc_idx = U32(P.wc_idx);
+    A.wc_code = U64(P.wc_code);
+    A.t = U8(P.t);
+    A.fr = U32(P.fr);
+    A.shared_cnt = U32(P.shared_cnt);
+    A.kd = U32(P.kd);
+    A.loff = U32(P.loff);
+    A.lnode_key = U64(P.lnode_key);
+    A.lnode_mask = U8(P.lnode_mask);
+    A.cut = U8(P.cut);
+    A.big_list = U32(P.big_list);
+    A.num_big = (uint32_t)big.size();
+    A.big_nr = U32(P.big_nr);
+    A.big_node = U32(P.big_node);
+    A.big_hkey = U64(P.big_hkey);
+    A.big_hval = U32(P.big_hval);
+    A.lam_w = P.lam_w;
+    A.s = s_;
+    A.L = p->leaf_capacity;
+    A.dmax = KB - s_;
+    uint32_t big_grid = 0;
+    if (A.num_big) {
+        uint64_t cap = 1;
+        while (cap < 2ull * max_big) cap <<= 1;
+        A.big_hash_cap = cap;
+        uint64_t blocks = (4 * n) / cap;
+        if (blocks < 1) blocks = 1;
+        if (blocks > A.num_big) blocks = A.num_big;
+        if (blocks > 256) blocks = 256;
+        big_grid = (uint32_t)blocks;
+    }
+    if (g > 0) JCHK(hipMemsetAsync(U32(P.shared_cnt), 0, 4 * pyr_off(g), st));
+    JCHK(hipMemsetAsync(U32(P.kd), 0, 4ull * MAXD * num_wc, st));
+    launch_subsample_small(A, st);
+    launch_subsample_big(A, big_grid, st);
+    launch_decide(A, st);
+    launch_node_counts(A, U32(P.owned), st);
+    scan_exclusive(U32(P.owned), U32(P.node_base), (uint64_t)MAXD * num_wc, &ctrs->num_nodes, stemp, st);
+    JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
+    JCHK(hipStreamSynchronize(st));
+    const uint32_t num_nodes = hctrs->num_nodes;
+    launch_node_ids(A, U32(P.node_base), U32(P.nid), &ctrs->internal_error, st);
+    JCHK(hipMemsetAsync(U8(P.n_mask), 0, (num_nodes + 3) & ~3u, st));
+    launch_node_fill(A, U32(P.node_base), U8(P.n_depth), U64(P.n_key), U8(P.n_mask), st);
+    multisplit(U32(P.nid), n, num_nodes, nullptr, U32(P.n_points), U32(P.sorted_nid), nullptr, ws + P.ms_temp, st);
+    launch_node_ranges(U32(P.sorted_nid), n, U64(P.n_begin), U32(P.n_count), num_nodes, st);
+
+    JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
+    JCHK(hipMemcpyAsync(hbox, box, sizeof(DevBox), hipMemcpyDeviceToHost, st));
+    JCHK(hipEventRecord(job->ev_done, st));
+    JCHK(hipGetLastError());
+    R.num_chunks = num_chunks;
+    R.num_nodes = num_nodes;
+    *out = job;
+    return FPO_OK;
+#undef JCHK
+}
+
+fpo_status fpo_job_preview_ready(fpo_job *job)
+{
+    if (!job) return fail(FPO_ERR_INVALID_ARG, "job is NULL");
+    hipError_t e = hipEventQuery(job->ev_preview);
+    if (e == hipSuccess) return FPO_OK;
+    if (e == hipErrorNotReady) return FPO_NOT_READY;
+    return fail(FPO_ERR_DEVICE, "hipEventQuery: %s", hipGetErrorString(e));
+}
+
+static fpo_status finish(fpo_job *job)
+{
+    if (!job->waited) {
+        job->waited = true;
+        if (job->status == FPO_OK) {
+            const Ctrs *hc = static_cast<const Ctrs *>(job->pinned);
+            const DevBox *hb = reinterpret_cast<const DevBox *>(static_cast<const char *>(job->pinned) + 256);
+            fpo_result &R = job->res;
+            if (R.n > 0) {
+                for (int a = 0; a < 3; ++a) {
+                    R.bbox_min[a] = hb->lo[a];
+                    R.bbox_max[a] = hb->hi[a];
+                }
+                R.cube_size = hb->size;
+                R.scale = hb->scale;
+                R.n_outside = hb->n_outside;
+                R.preview_count = hc->preview_count;
+                R.chunk_oversized_any = hc->oversized ? 1 : 0;
+                if (hc->internal_error) {
+                    job->status = FPO_ERR_DEVICE;
+                    fail(FPO_ERR_DEVICE, "internal error: a point was left without a node");
+                }
+            }
+        }
+    }
+    return job->status;
+}
+
+fpo_status fpo_job_poll(fpo_job *job)
+{
+    if (!job) return fail(FPO_ERR_INVALID_ARG, "job is NULL");
+    hipError_t e = hipEventQuery(job->ev_done);
+    if (e == hipErrorNotReady) return FPO_NOT_READY;
+    if (e != hipSuccess) return fail(FPO_ERR_DEVICE, "hipEventQuery: %s", hipGetErrorString(e));
+    fpo_status s = finish(job);
+    return s == FPO_OK ? s : fail(s, "build failed (status %d)", (int)s);
+}
+
+fpo_status fpo_job_wait(fpo_job *job)
+{
+    if (!job) return fail(FPO_ERR_INVALID_ARG, "job is NULL");
+    hipError_t e = hipEventSynchronize(job->ev_done);
+    if (e != hipSuccess) return fail(FPO_ERR_DEVICE, "hipEventSynchronize: %s", hipGetErrorString(e));
+    fpo_status s = finish(job);
+    return s == FPO_OK ? s : fail(s, "build failed (status %d)", (int)s);
+}
+
+fpo_status fpo_job_result(fpo_job *job, fpo_result *out)
+{
+    if (!job || !out) return fail(FPO_ERR_INVALID_ARG, "NULL job or out");
+    if (!job->waited) return fail(FPO_ERR_INVALID_ARG, "the job has not been waited for");
+    if (job->status != FPO_OK) return fail(job->status, "the build failed");
+    *out = job->res;
+    return FPO_OK;
+}
+
+void fpo_job_release(fpo_job *job)
+{
+    if (!job) return;
+    (void)hipEventSynchronize(job->ev_done);
+    (void)hipEventDestroy(job->ev_preview);
+    (void)hipEventDestroy(job->ev_done);
+    if (job->pinned) put_pinned(job->ctx, job->pinned);
+    delete job;
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// Internal declarations shared by the kernels and the host orchestration of
+// libfpo.  Not part of the public C ABI (that is include/fpo.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fpo {
+
+constexpr int KB = 21;                       // bits per axis of the shared lattice
+constexpr uint32_t UMAX = (1u << KB) - 1u;
+constexpr int MAXD = 22;                     // depths 0..21
+
+// Work chunks (internal decomposition of the subsample step) up to WC_CAP
+// points are processed with their points in registers and LDS hash tables.
+constexpr int P1_BLOCK = 1024;
+constexpr int P1_ITEMS = 4;
+constexpr uint32_t WC_CAP = P1_BLOCK * P1_ITEMS;   // 4096
+constexpr uint32_t WC_HASH = 2 * WC_CAP;           // 8192 slots, load <= 1/2
+
+constexpr int MS_BLOCK = 256;                // multisplit block (4 waves)
+constexpr int MS_ITEMS = 16;                 // elements per thread
+constexpr uint32_t MS_TILE = MS_BLOCK * MS_ITEMS;  // 4096
+constexpr uint32_t MS_MAX_BINS = 4096;       // bins of one multisplit pass
+
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr uint32_t SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+
+// Values the device derives from the bounding box (written by k_setup).
+struct DevBox {
+    float lo[3];
+    float hi[3];
+    float size;
+    float scale;
+    uint32_t omin[3];    // order-preserving integer encodings (bbox reduction)
+    uint32_t omax[3];
+    uint32_t nonfinite;
+    uint32_t pad;
+    unsigned long long n_outside;
+};
+
+// Offsets of level l in a pyramid array holding levels 0..g back to back.
+__host__ __device__ inline uint64_t pyr_off(int l) { return ((1ull << (3 * l)) - 1ull) / 7ull; }
+
+// ---- launchers (fpo_kernels.hip) -------------------------------------------
+void launch_bbox_init(DevBox *box, hipStream_t st);
+void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, DevBox *box, hipStream_t st);
+void launch_setup(DevBox *box, int given, const float *lo, const float *hi, hipStream_t st);
+void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box,
+                     int g, int count_outside, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw,
+                     hipStream_t st);
+void launch_pyramid(uint32_t *pyr, int g, hipStream_t st);
+void launch_grid_export(const uint32_t *fine_morton, int g, uint32_t *rowmajor, hipStream_t st);
+void launch_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev,
+                      hipStream_t st);
+void launch_cut_table(const uint32_t *pyr, int lam, const uint32_t *flags, const uint32_t *excl,
+                      const uint8_t *lev, uint8_t *t_level, uint64_t *t_key, uint32_t *t_count,
+                      uint64_t *t_start, uint32_t thresh, uint32_t *over_flag, hipStream_t st);
+void launch_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t st);
+void launch_point_keys(const uint64_t *code, uint64_t n, int g, const uint32_t *flags_c, const uint32_t *excl_c,
+                       int lam_w, const uint32_t *flags_w, const uint32_t *excl_w, uint32_t *cid,
+                       uint32_t *wid, hipStream_t st);
+
+// Device-wide exclusive scan of n u32 values; *total (device) gets the sum.
+size_t scan_temp_bytes(uint64_t n);
+void scan_exclusive(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total, void *temp,
+                    hipStream_t st);
+
+// Stable multisplit (counting sort) of n elements by u32 keys in [0, nbins).
+size_t multisplit_temp_bytes(uint64_t n, uint32_t nbins);
+size_t multisplit_temp_bound(uint64_t n, uint64_t max_bins);   // for any nbins <= max_bins
+void multisplit(const uint32_t *keys, uint64_t n, uint32_t nbins, const uint64_t *payload,
+                uint32_t *vals_out, uint32_t *keys_out, uint64_t *payload_out, void *temp,
+                hipStream_t st);
+
+// Subsample step.
+struct WcArgs {
+    uint32_t num_wc;
+    const uint32_t *wc_begin;    // position of the work chunk's first point in work-chunk order
+    const uint32_t *wc_count;
+    const uint8_t *wc_level;
+    const uint64_t *wc_key;
+    const uint64_t *wc_start;    // first lattice cell (level lam_w) of each work chunk
+    const uint32_t *wc_idx;      // original index per position
+    const uint64_t *wc_code;     // Morton code per position
+    uint8_t *t;                  // tentative depth per position
+    uint32_t *fr;                // local node rank per position
+    uint32_t *shared_cnt;        // pyramid-shaped reaching counts of shared nodes
+    uint32_t *kd;                // [num_wc][MAXD] local node count per depth
+    uint32_t *loff;              // [num_wc][MAXD] offset of a depth's local nodes
+    uint64_t *lnode_key;         // local node keys, per work chunk region
+    uint8_t *lnode_mask;         // local node child masks
+    uint8_t *cut;                // per work chunk: first depth whose shared node is a leaf (or lw)
+    // big work chunks (more than WC_CAP points)
+    const uint32_t *big_list;
+    uint32_t num_big;
+    uint32_t *big_nr;            // per position scratch
+    uint32_t *big_node;          // per position scratch (3 arrays of n)
+    uint64_t *big_hkey;          // hash keys
+    uint32_t *big_hval;
+    uint64_t big_hash_cap;       // slots per block region
+    int lam_w;
+    int s;
+    uint32_t L;
+    int dmax;
+};
+void launch_subsample_small(const WcArgs &a, hipStream_t st);
+void launch_subsample_big(const WcArgs &a, uint32_t grid, hipStream_t st);
+void launch_decide(const WcArgs &a, hipStream_t st);
+void launch_node_counts(const WcArgs &a, uint32_t *owned, hipStream_t st);
+void launch_node_ids(const WcArgs &a, const uint32_t *node_base, uint32_t *nid_by_idx, uint32_t *err,
+                     hipStream_t st);
+void launch_node_fill(const WcArgs &a, const uint32_t *node_base, uint8_t *depth, uint64_t *key,
+                      uint8_t *mask, hipStream_t st);
+void launch_node_ranges(const uint32_t *sorted_keys, uint64_t n, uint64_t *begin, uint32_t *count,
+                        uint32_t num_nodes, hipStream_t st);
+
+// Preview.
+void launch_preview_count(uint64_t n, uint64_t m, uint32_t *tile_counts, hipStream_t st);
+void launch_preview_write(uint64_t n, uint64_t m, const uint32_t *tile_offsets, uint32_t *out,
+                          hipStream_t st);
+uint64_t preview_tiles(uint64_t n);
+
+}  // namespace fpo

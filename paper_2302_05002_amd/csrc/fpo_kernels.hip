@@ -1,0 +1,1234 @@
+// HIP kernels (gfx950, wave64) of the online shallow-octree build and the
+// decimated preview of FastPoints (arXiv 2302.05002).
+//
+// Path (section "Octree Construction": chunking, per-chunk indexing into local
+// octrees, one global tree; section "Immediate Low-Resolution Rendering": a
+// decimation that visits every point):
+//   1. bbox reduction, quantisation to the 21-bit lattice, count histogram
+//   2. count pyramid, chunk cut (and the internal work-chunk cut)
+//   3. stable multisplit by chunk -> perm; by work chunk -> work-chunk order
+//   4. per-node grid subsample (lowest original index wins a cell), computed
+//      per work chunk in LDS, then node ids and a stable multisplit by node
+//   5. hash-of-index preview with an ordered compaction
+// Nothing here is a dense contraction, so no MFMA: the bounds are HBM
+// bandwidth, LDS/global atomics and scan latency.
+#include "fpo_internal.h"
+
+namespace fpo {
+
+// ---- small helpers ------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Order-preserving map of a float to an unsigned integer (for min/max atomics).
+__device__ __forceinline__ uint32_t f2o(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float o2f(uint32_t o)
+{
+    uint32_t b = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+    return __uint_as_float(b);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if ((int)lane_id() >= o) v += t;
+    }
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Exclusive scan of one value per thread across the block; *total = sum.
+// lds must hold BLOCK/64 + 1 words.  Ends with a barrier so lds can be reused.
+template <int BLOCK>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *lds, uint32_t *total)
+{
+    constexpr int W = BLOCK / 64;
+    const uint32_t inc = wave_incl_sum(v);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 63) lds[w] = inc;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        uint32_t x = threadIdx.x < W ? lds[threadIdx.x] : 0u;
+        uint32_t xi = wave_incl_sum(x);
+        if (threadIdx.x < W) lds[threadIdx.x] = xi - x;
+        if (threadIdx.x == W - 1) lds[W] = xi;
+    }
+    __syncthreads();
+    const uint32_t r = lds[w] + inc - v;
+    *total = lds[W];
+    __syncthreads();
+    return r;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *lds)
+{
+    constexpr int W = BLOCK / 64;
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) lds[w] = v;
+    __syncthreads();
+    uint32_t t = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) t += lds[i];
+    __syncthreads();
+    return t;
+}
+
+// Spread the low 21 bits of a so that bit b lands on bit 3b.
+__device__ __forceinline__ uint64_t split3(uint32_t a)
+{
+    uint64_t x = a & 0x1fffffu;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+__device__ __forceinline__ uint32_t compact3(uint64_t x)
+{
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+    x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+    x = (x ^ (x >> 32)) & 0x1fffffull;
+    return (uint32_t)x;
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t k)
+{
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+__device__ __forceinline__ uint64_t match_peers(uint32_t key, bool valid, int nbits)
+{
+    uint64_t m = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (key >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return valid ? m : 0ull;
+}
+
+static inline uint32_t ceil_log2(uint64_t v)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < v) ++l;
+    return l;
+}
+static inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// ---- step 1a: bounding box ------------------------------------------------------
+
+__global__ void k_bbox_init(DevBox *box)
+{
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) {
+            box->omin[a] = 0xffffffffu;
+            box->omax[a] = 0u;
+        }
+        box->nonfinite = 0;
+        box->n_outside = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ x, const float *__restrict__ y,
+                                              const float *__restrict__ z, uint64_t n, int vec4, DevBox *box)
+{
+    uint32_t mn[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[3] = {0u, 0u, 0u};
+    uint32_t bad = 0;
+    const float *src[3] = {x, y, z};
+    const uint64_t n4 = vec4 ? n / 4 : 0;   // float4 loads only on 16-byte aligned inputs
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (int a = 0; a < 3; ++a) {
+        const float4 *p4 = reinterpret_cast<const float4 *>(src[a]);
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+            const float4 v = p4[i];
+            const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!isfinite(e[k])) { bad = 1; continue; }
+                const uint32_t o = f2o(e[k]);
+                mn[a] = min(mn[a], o);
+                mx[a] = max(mx[a], o);
+            }
+        }
+        for (uint64_t i = n4 * 4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            const float e = src[a][i];
+            if (!isfinite(e)) { bad = 1; continue; }
+            const uint32_t o = f2o(e);
+            mn[a] = min(mn[a], o);
+            mx[a] = max(mx[a], o);
+        }
+    }
+    __shared__ uint32_t s[7][4];
+    const int w = threadIdx.x >> 6;
+    for (int a = 0; a < 3; ++a) {
+        uint32_t v = mn[a], u = mx[a];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            v = min(v, (uint32_t)__shfl_xor(v, o, 64));
+            u = max(u, (uint32_t)__shfl_xor(u, o, 64));
+        }
+        if (lane_id() == 0) { s[a][w] = v; s[3 + a][w] = u; }
+    }
+    const uint64_t anybad = __ballot(bad != 0);
+    if (lane_id() == 0) s[6][w] = anybad ? 1u : 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) {
+            uint32_t v = s[a][0], u = s[3 + a][0];
+            for (int i = 1; i < 4; ++i) { v = min(v, s[a][i]); u = max(u, s[3 + a][i]); }
+            if (v != 0xffffffffu) atomicMin(&box->omin[a], v);
+            if (u != 0u) atomicMax(&box->omax[a], u);
+        }
+        if (s[6][0] | s[6][1] | s[6][2] | s[6][3]) atomicOr(&box->nonfinite, 1u);
+    }
+}
+
+// Cube anchored at the box minimum, side = largest extent, scale = 2^21/side
+// computed in double and rounded once to float (0 for a zero side).
+__global__ void k_setup(DevBox *box, int given, float gx0, float gy0, float gz0, float gx1, float gy1, float gz1)
+{
+    if (threadIdx.x != 0) return;
+    float lo[3], hi[3];
+    if (given) {
+        lo[0] = gx0; lo[1] = gy0; lo[2] = gz0;
+        hi[0] = gx1; hi[1] = gy1; hi[2] = gz1;
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            // +0.0f turns a -0.0 extreme into +0.0 (the two compare equal, so
+            // which one a reduction meets first must not show in the result)
+            lo[a] = __fadd_rn(o2f(box->omin[a]), 0.0f);
+            hi[a] = __fadd_rn(o2f(box->omax[a]), 0.0f);
+        }
+    }
+    float side = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        const float ext = __fsub_rn(hi[a], lo[a]);
+        if (ext > side) side = ext;
+        box->lo[a] = lo[a];
+        box->hi[a] = hi[a];
+    }
+    box->size = side;
+    box->scale = side > 0.0f ? (float)(2097152.0 / (double)side) : 0.0f;
+}
+
+__device__ __forceinline__ uint32_t quantize1(float a, float lo, float scale)
+{
+    const float t = __fmul_rn(__fsub_rn(a, lo), scale);
+    if (!(t > 0.0f)) return 0u;
+    if (t >= 2097151.0f) return UMAX;
+    return (uint32_t)floorf(t);
+}
+
+// ---- step 1b: quantise + count ---------------------------------------------------
+// One Morton code per point (x the most significant bit of each triple) and
+// one atomic increment of the finest count cell (Morton order internally).
+__global__ __launch_bounds__(256) void k_quantize(const float *__restrict__ x, const float *__restrict__ y,
+                                                  const float *__restrict__ z, uint64_t n, const DevBox *box,
+                                                  int g, int count_outside, uint64_t *__restrict__ code,
+                                                  uint32_t *__restrict__ fine, DevBox *box_rw)
+{
+    const float lx = box->lo[0], ly = box->lo[1], lz = box->lo[2], sc = box->scale;
+    const float hx = box->hi[0], hy = box->hi[1], hz = box->hi[2];
+    const int sh = 3 * (KB - g);
+    uint32_t outside = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float px = x[i], py = y[i], pz = z[i];
+        const uint32_t ux = quantize1(px, lx, sc), uy = quantize1(py, ly, sc), uz = quantize1(pz, lz, sc);
+        const uint64_t c = (split3(ux) << 2) | (split3(uy) << 1) | split3(uz);
+        code[i] = c;
+        atomicAdd(&fine[c >> sh], 1u);
+        if (count_outside)
+            outside += (px < lx || px > hx || py < ly || py > hy || pz < lz || pz > hz) ? 1u : 0u;
+    }
+    if (count_outside) {
+        outside = wave_sum(outside);
+        if (lane_id() == 0 && outside) atomicAdd(&box_rw->n_outside, (unsigned long long)outside);
+    }
+}
+
+// ---- step 2a: count pyramid ---------------------------------------------------------
+// Level l-1 cell k = sum of level-l cells 8k..8k+7 (Morton order).
+__global__ void k_pyr_level(uint32_t *pyr, int l)
+{
+    const uint64_t ncell = 1ull << (3 * (l - 1));
+    const uint32_t *src = pyr + pyr_off(l);
+    uint32_t *dst = pyr + pyr_off(l - 1);
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ncell;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t *c = src + 8 * k;
+        dst[k] = c[0] + c[1] + c[2] + c[3] + c[4] + c[5] + c[6] + c[7];
+    }
+}
+
+// Row-major [cx][cy][cz] export of the finest counts.
+__global__ void k_grid_export(const uint32_t *fine, int g, uint32_t *out)
+{
+    const uint64_t G = 1ull << g, ncell = G * G * G;
+    for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < ncell;
+         m += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t cx = compact3(m >> 2), cy = compact3(m >> 1), cz = compact3(m);
+        out[((uint64_t)cx * G + cy) * G + cz] = fine[m];
+    }
+}
+
+// ---- step 2b: chunk cut ---------------------------------------------------------------
+// A pyramid node (l, a), l <= lam, is a chunk when it is non-empty, holds at
+// most thresh points or l == lam, and l == 0 or its parent holds more than
+// thresh.  flags[m] = 1 at the first level-lam cell m of every chunk; lev[m] =
+// its level.  Chunks are disjoint, so at most one level can start at m.
+__global__ void k_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev)
+{
+    const uint64_t ncell = 1ull << (3 * lam);
+    for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < ncell;
+         m += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t f = 0;
+        uint8_t lv = 0;
+        for (int l = 0; l <= lam; ++l) {
+            const int sh = 3 * (lam - l);
+            const uint64_t a = m >> sh;
+            const uint32_t cnt = pyr[pyr_off(l) + a];
+            if (cnt == 0) break;
+            if (cnt <= thresh || l == lam) {
+                // the node at level l containing m is the chunk; it starts here
+                // only if m is its first cell
+                if ((m & ((1ull << sh) - 1ull)) == 0) { f = 1; lv = (uint8_t)l; }
+                break;
+            }
+        }
+        flags[m] = f;
+        lev[m] = lv;
+    }
+}
+
+__global__ void k_cut_table(const uint32_t *pyr, int lam, const uint32_t *flags, const uint32_t *excl,
+                            const uint8_t *lev, uint8_t *t_level, uint64_t *t_key, uint32_t *t_count,
+                            uint64_t *t_start, uint32_t thresh, uint32_t *over_flag)
+{
+    const uint64_t ncell = 1ull << (3 * lam);
+    for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < ncell;
+         m += (uint64_t)gridDim.x * blockDim.x) {
+        if (!flags[m]) continue;
+        const uint32_t id = excl[m];
+        const int l = lev[m];
+        const uint64_t key = m >> (3 * (lam - l));
+        t_level[id] = (uint8_t)l;
+        t_key[id] = key;
+        const uint32_t cnt = pyr[pyr_off(l) + key];
+        t_count[id] = cnt;
+        if (t_start) t_start[id] = m;
+        if (over_flag && cnt > thresh) atomicOr(over_flag, 1u);
+    }
+}
+
+__global__ void k_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = in[i];
+}
+
+// Chunk id and work-chunk id of every point: the last chunk starting at or
+// before the point's cell (the one containing it).
+__global__ __launch_bounds__(256) void k_point_keys(const uint64_t *__restrict__ code, uint64_t n, int g,
+                                                    const uint32_t *flags_c, const uint32_t *excl_c, int lam_w,
+                                                    const uint32_t *flags_w, const uint32_t *excl_w,
+                                                    uint32_t *__restrict__ cid, uint32_t *__restrict__ wid)
+{
+    const int shc = 3 * (KB - g), shw = 3 * (KB - lam_w);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t c = code[i];
+        const uint64_t mc = c >> shc, mw = c >> shw;
+        cid[i] = excl_c[mc] + flags_c[mc] - 1u;
+        wid[i] = excl_w[mw] + flags_w[mw] - 1u;
+    }
+}
+
+// ---- device-wide exclusive scan ------------------------------------------------------------
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const uint32_t *in, uint64_t n, uint32_t *tile_sum)
+{
+    __shared__ uint32_t lds[SCAN_BLOCK / 64 + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    uint32_t s = 0;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const uint64_t e = base + (uint64_t)j * SCAN_BLOCK + threadIdx.x;
+        if (e < n) s += in[e];
+    }
+    s = block_sum<SCAN_BLOCK>(s, lds);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = s;
+}
+
+// Single block: exclusive scan of the tile sums in place; *total = sum.
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t *tile_sum, uint32_t ntiles, uint32_t *total)
+{
+    __shared__ uint32_t lds[1024 / 64 + 1];
+    uint32_t carry = 0;
+    for (uint32_t b = 0; b < ntiles; b += 1024) {
+        const uint32_t i = b + threadIdx.x;
+        const uint32_t v = i < ntiles ? tile_sum[i] : 0u;
+        uint32_t t;
+        const uint32_t ex = block_excl_scan<1024>(v, lds, &t);
+        if (i < ntiles) tile_sum[i] = carry + ex;
+        carry += t;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(const uint32_t *in, uint32_t *out, uint64_t n,
+                                                          const uint32_t *tile_off)
+{
+    __shared__ uint32_t lds[SCAN_BLOCK / 64 + 1];
+    __shared__ uint32_t buf[SCAN_TILE];
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const uint64_t e = base + (uint64_t)j * SCAN_BLOCK + threadIdx.x;
+        buf[j * SCAN_BLOCK + threadIdx.x] = e < n ? in[e] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        v[j] = buf[threadIdx.x * SCAN_ITEMS + j];
+        s += v[j];
+    }
+    uint32_t t;
+    uint32_t run = block_excl_scan<SCAN_BLOCK>(s, lds, &t) + tile_off[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        buf[threadIdx.x * SCAN_ITEMS + j] = run;
+        run += v[j];
+    }
+    __syncthreads();
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const uint64_t e = base + (uint64_t)j * SCAN_BLOCK + threadIdx.x;
+        if (e < n) out[e] = buf[j * SCAN_BLOCK + threadIdx.x];
+    }
+}
+
+size_t scan_temp_bytes(uint64_t n)
+{
+    const uint64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    return ((tiles + 1) * 4 + 255) & ~(size_t)255;
+}
+
+void scan_exclusive(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total, void *temp, hipStream_t st)
+{
+    if (n == 0) {
+        if (total) (void)hipMemsetAsync(total, 0, 4, st);
+        return;
+    }
+    const uint32_t tiles = div_up(n, SCAN_TILE);
+    uint32_t *ts = static_cast<uint32_t *>(temp);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, n, ts);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, ts, tiles, total);
+    hipLaunchKernelGGL(k_scan_down, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, out, n, ts);
+}
+
+// ---- stable multisplit ------------------------------------------------------------------------
+// One pass sorts by a digit of <= 12 bits.  Tile = MS_TILE elements; wave w of
+// the block owns the contiguous sub-tile [w*T/4, (w+1)*T/4) and walks it in
+// rounds of 64 lanes in index order.  Ranks inside a round come from a ballot
+// match over the digit bits (lanes in index order), so equal digits keep
+// their input order: the sort is stable.
+
+__global__ __launch_bounds__(MS_BLOCK) void k_ms_count(const uint32_t *__restrict__ keys, uint64_t n, int shift,
+                                                       uint32_t nbins, int nbits, uint32_t *__restrict__ counts,
+                                                       uint32_t tiles)
+{
+    __shared__ uint16_t hist[MS_BLOCK / 64][MS_MAX_BINS];
+    const uint32_t tile = blockIdx.x;
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    for (uint32_t b = threadIdx.x; b < nbins; b += MS_BLOCK)
+        for (int k = 0; k < MS_BLOCK / 64; ++k) hist[k][b] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)tile * MS_TILE + (uint64_t)w * (MS_ITEMS * 64);
+    const uint32_t dmask = (nbits >= 32) ? 0xffffffffu : ((1u << nbits) - 1u);
+    for (int r = 0; r < MS_ITEMS; ++r) {
+        const uint64_t e = base + (uint64_t)r * 64 + lane;
+        const bool valid = e < n;
+        const uint32_t key = valid ? ((keys[e] >> shift) & dmask) : 0u;
+        const uint64_t peers = match_peers(key, valid, nbits);
+        if (valid && (peers & ((1ull << lane) - 1ull)) == 0) hist[w][key] += (uint16_t)__popcll(peers);
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nbins; b += MS_BLOCK) {
+        uint32_t t = 0;
+        for (int k = 0; k < MS_BLOCK / 64; ++k) t += hist[k][b];
+        counts[(uint64_t)b * tiles + tile] = t;
+    }
+}
+
+__global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+                                                         const uint64_t *__restrict__ pay, uint64_t n, int shift,
+                                                         uint32_t nbins, int nbits, const uint32_t *__restrict__ offsets,
+                                                         uint32_t tiles, uint32_t *__restrict__ keys_out,
+                                                         uint32_t *__restrict__ vals_out, uint64_t *__restrict__ pay_out)
+{
+    __shared__ uint16_t pre[MS_BLOCK / 64][MS_MAX_BINS];
+    __shared__ uint32_t tbase[MS_MAX_BINS];
+    const uint32_t tile = blockIdx.x;
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    for (uint32_t b = threadIdx.x; b < nbins; b += MS_BLOCK)
+        for (int k = 0; k < MS_BLOCK / 64; ++k) pre[k][b] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)tile * MS_TILE + (uint64_t)w * (MS_ITEMS * 64);
+    const uint32_t dmask = (nbits >= 32) ? 0xffffffffu : ((1u << nbits) - 1u);
+    uint32_t full[MS_ITEMS];
+#pragma unroll
+    for (int r = 0; r < MS_ITEMS; ++r) {
+        const uint64_t e = base + (uint64_t)r * 64 + lane;
+        full[r] = e < n ? keys[e] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < MS_ITEMS; ++r) {
+        const uint64_t e = base + (uint64_t)r * 64 + lane;
+        const bool valid = e < n;
+        const uint32_t key = (full[r] >> shift) & dmask;
+        const uint64_t peers = match_peers(key, valid, nbits);
+        if (valid && (peers & ((1ull << lane) - 1ull)) == 0) pre[w][key] += (uint16_t)__popcll(peers);
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nbins; b += MS_BLOCK) {
+        uint32_t acc = 0;
+        for (int k = 0; k < MS_BLOCK / 64; ++k) {
+            const uint32_t h = pre[k][b];
+            pre[k][b] = (uint16_t)acc;
+            acc += h;
+        }
+        tbase[b] = offsets[(uint64_t)b * tiles + tile];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < MS_ITEMS; ++r) {
+        const uint64_t e = base + (uint64_t)r * 64 + lane;
+        const bool valid = e < n;
+        const uint32_t key = (full[r] >> shift) & dmask;
+        const uint64_t peers = match_peers(key, valid, nbits);
+        if (!valid) continue;
+        const uint32_t before = pre[w][key];
+        const uint32_t pos = tbase[key] + before + (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+        if ((peers & ((1ull << lane) - 1ull)) == 0) pre[w][key] = (uint16_t)(before + __popcll(peers));
+        vals_out[pos] = vals ? vals[e] : (uint32_t)e;
+        if (keys_out) keys_out[pos] = full[r];
+        if (pay_out) pay_out[pos] = pay[e];
+    }
+}
+
+struct MsLayout {
+    uint32_t passes, dbits[4], nb[4], shift[4];
+    uint32_t tiles;
+    uint64_t counts_words;
+};
+
+static MsLayout ms_layout(uint64_t n, uint32_t nbins)
+{
+    MsLayout L{};
+    L.tiles = div_up(n ? n : 1, MS_TILE);
+    const uint32_t bits = ceil_log2(nbins);
+    if (nbins <= MS_MAX_BINS) {
+        L.passes = 1;
+        L.dbits[0] = bits;
+        L.nb[0] = nbins;
+        L.shift[0] = 0;
+    } else {
+        L.passes = (bits + 11) / 12;
+        const uint32_t per = (bits + L.passes - 1) / L.passes;
+        uint32_t done = 0;
+        for (uint32_t p = 0; p < L.passes; ++p) {
+            const uint32_t b = (bits - done) < per ? (bits - done) : per;
+            L.dbits[p] = b;
+            L.nb[p] = 1u << b;
+            L.shift[p] = done;
+            done += b;
+        }
+    }
+    uint32_t maxnb = 0;
+    for (uint32_t p = 0; p < L.passes; ++p) maxnb = L.nb[p] > maxnb ? L.nb[p] : maxnb;
+    L.counts_words = (uint64_t)maxnb * L.tiles;
+    return L;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t multisplit_temp_bytes(uint64_t n, uint32_t nbins)
+{
+    const MsLayout L = ms_layout(n, nbins);
+    size_t b = 2 * align256(L.counts_words * 4) + scan_temp_bytes(L.counts_words);
+    if (L.passes > 1) b += 2 * (align256(n * 4) * 2 + align256(n * 8));
+    return b;
+}
+
+size_t multisplit_temp_bound(uint64_t n, uint64_t max_bins)
+{
+    // the largest single pass (up to MS_MAX_BINS bins) and the multi-pass form
+    const uint32_t one = (uint32_t)(max_bins < MS_MAX_BINS ? max_bins : MS_MAX_BINS);
+    size_t b = multisplit_temp_bytes(n, one ? one : 1);
+    if (max_bins > MS_MAX_BINS) {
+        const uint64_t tiles = div_up(n ? n : 1, MS_TILE);
+        const size_t m = 2 * align256((uint64_t)MS_MAX_BINS * tiles * 4) + scan_temp_bytes((uint64_t)MS_MAX_BINS * tiles) +
+                         2 * (align256(n * 4) * 2 + align256(n * 8));
+        if (m > b) b = m;
+    }
+    return b;
+}
+
+void multisplit(const uint32_t *keys, uint64_t n, uint32_t nbins, const uint64_t *payload, uint32_t *vals_out,
+                uint32_t *keys_out, uint64_t *payload_out, void *temp, hipStream_t st)
+{
+    if (n == 0) return;
+    const MsLayout L = ms_layout(n, nbins);
+    char *p = static_cast<char *>(temp);
+    uint32_t *counts = reinterpret_cast<uint32_t *>(p); p += align256(L.counts_words * 4);
+    uint32_t *offs = reinterpret_cast<uint32_t *>(p); p += align256(L.counts_words * 4);
+    void *stemp = p; p += scan_temp_bytes(L.counts_words);
+    uint32_t *kb[2] = {nullptr, nullptr}, *vb[2] = {nullptr, nullptr};
+    uint64_t *pb[2] = {nullptr, nullptr};
+    if (L.passes > 1) {
+        for (int i = 0; i < 2; ++i) {
+            kb[i] = reinterpret_cast<uint32_t *>(p); p += align256(n * 4);
+            vb[i] = reinterpret_cast<uint32_t *>(p); p += align256(n * 4);
+            pb[i] = reinterpret_cast<uint64_t *>(p); p += align256(n * 8);
+        }
+    }
+    const uint32_t *kin = keys;
+    const uint32_t *vin = nullptr;
+    const uint64_t *pin = payload;
+    for (uint32_t ps = 0; ps < L.passes; ++ps) {
+        const bool last = ps + 1 == L.passes;
+        uint32_t *ko = last ? keys_out : kb[ps & 1];
+        uint32_t *vo = last ? vals_out : vb[ps & 1];
+        uint64_t *po = last ? payload_out : (payload ? pb[ps & 1] : nullptr);
+        hipLaunchKernelGGL(k_ms_count, dim3(L.tiles), dim3(MS_BLOCK), 0, st, kin, n, (int)L.shift[ps], L.nb[ps],
+                           (int)L.dbits[ps], counts, L.tiles);
+        scan_exclusive(counts, offs, (uint64_t)L.nb[ps] * L.tiles, nullptr, stemp, st);
+        hipLaunchKernelGGL(k_ms_scatter, dim3(L.tiles), dim3(MS_BLOCK), 0, st, kin, vin, pin, n, (int)L.shift[ps],
+                           L.nb[ps], (int)L.dbits[ps], offs, L.tiles, ko, vo, po);
+        kin = ko;
+        vin = vo;
+        pin = po;
+    }
+}
+
+// ---- step 4: per-node grid subsample -----------------------------------------------------------
+//
+// Work chunks (WCs) are the maximal pyramid nodes holding at most WC_CAP
+// points, cut no deeper than level lam_w = min(g, s).  Because lam_w <= s, the
+// subsample cells of every node (lattice level d + s >= s) never straddle two
+// WCs: each cell's lowest-index point is found inside one WC.  The only
+// cross-WC question is whether a node above a WC (a "shared" node, depth
+// < lw) is inner or a leaf, which depends on how many points reach it.  Each
+// WC therefore runs its whole subtree assuming its shared ancestors are inner,
+// posting its reaching count at every shared depth; a top-down pass then
+// finds the first shared leaf of each WC (its "cut"), and points whose
+// tentative depth is at or below the cut belong to that leaf.
+
+__device__ __forceinline__ void hash_insert_min(unsigned long long *hk, uint32_t *hv, uint64_t mask, uint64_t key,
+                                                uint32_t val)
+{
+    uint64_t h = mix64(key) & mask;
+    while (true) {
+        const unsigned long long k = *((volatile unsigned long long *)&hk[h]);
+        if (k == key) break;
+        if (k == ~0ull) {
+            const unsigned long long prev = atomicCAS(&hk[h], ~0ull, (unsigned long long)key);
+            if (prev == ~0ull || prev == key) break;
+        }
+        h = (h + 1) & mask;
+    }
+    atomicMin(&hv[h], val);
+}
+
+__device__ __forceinline__ uint32_t hash_lookup(const unsigned long long *hk, const uint32_t *hv, uint64_t mask,
+                                                uint64_t key)
+{
+    uint64_t h = mix64(key) & mask;
+    while (hk[h] != key) h = (h + 1) & mask;
+    return hv[h];
+}
+
+// Exclusive scan in place of arr[0..K) by the whole block; returns the total.
+template <int BLOCK>
+__device__ uint32_t block_scan_array(uint32_t *arr, uint32_t K, uint32_t *lds)
+{
+    uint32_t carry = 0;
+    for (uint32_t b = 0; b < K; b += BLOCK) {
+        const uint32_t i = b + threadIdx.x;
+        const uint32_t v = i < K ? arr[i] : 0u;
+        uint32_t t;
+        const uint32_t ex = block_excl_scan<BLOCK>(v, lds, &t);
+        if (i < K) arr[i] = carry + ex;
+        carry += t;
+        __syncthreads();
+    }
+    return carry;
+}
+
+// Per-item state for the WC loop: code, tentative depth (0xff = alive),
+// current node rank, final node rank.
+template <bool BIG>
+struct Items;
+
+template <>
+struct Items<false> {
+    uint64_t code[P1_ITEMS];
+    uint32_t st[P1_ITEMS], nr[P1_ITEMS], fr[P1_ITEMS];
+    uint32_t n;
+    __device__ void load(const WcArgs &a, uint32_t base, uint32_t n_)
+    {
+        n = n_;
+#pragma unroll
+        for (int j = 0; j < P1_ITEMS; ++j) {
+            const uint32_t pos = j * P1_BLOCK + threadIdx.x;
+            code[j] = pos < n ? a.wc_code[base + pos] : 0ull;
+            st[j] = 0xffu;
+            nr[j] = 0;
+            fr[j] = 0;
+        }
+    }
+    template <class F>
+    __device__ void each(F &&f)
+    {
+#pragma unroll
+        for (int j = 0; j < P1_ITEMS; ++j) {
+            const uint32_t pos = j * P1_BLOCK + threadIdx.x;
+            if (pos < n) f(pos, code[j], st[j], nr[j], fr[j]);
+        }
+    }
+    __device__ void store(const WcArgs &a, uint32_t base)
+    {
+#pragma unroll
+        for (int j = 0; j < P1_ITEMS; ++j) {
+            const uint32_t pos = j * P1_BLOCK + threadIdx.x;
+            if (pos < n) {
+                a.t[base + pos] = (uint8_t)st[j];
+                a.fr[base + pos] = fr[j];
+            }
+        }
+    }
+};
+
+template <>
+struct Items<true> {
+    const uint64_t *code;
+    uint8_t *t;
+    uint32_t *nr, *fr;
+    uint32_t n;
+    __device__ void load(const WcArgs &a, uint32_t base, uint32_t n_)
+    {
+        code = a.wc_code + base;
+        t = a.t + base;
+        nr = a.big_nr + base;
+        fr = a.fr + base;
+        n = n_;
+        for (uint32_t pos = threadIdx.x; pos < n; pos += P1_BLOCK) {
+            t[pos] = 0xffu;
+            nr[pos] = 0;
+            fr[pos] = 0;
+        }
+        __syncthreads();
+    }
+    template <class F>
+    __device__ void each(F &&f)
+    {
+        for (uint32_t pos = threadIdx.x; pos < n; pos += P1_BLOCK) {
+            const uint64_t c = code[pos];
+            uint32_t s = t[pos], r = nr[pos], q = fr[pos];
+            f(pos, c, s, r, q);
+            t[pos] = (uint8_t)s;
+            nr[pos] = r;
+            fr[pos] = q;
+        }
+    }
+    __device__ void store(const WcArgs &, uint32_t) {}
+};
+
+template <bool BIG>
+__device__ void subsample_wc(const WcArgs &a, uint32_t w, unsigned long long *hk, uint32_t *hv, uint64_t hmask,
+                             uint32_t *pmask, uint32_t *pbase, uint32_t *ncnt, uint32_t *red, Items<BIG> &it)
+{
+    const uint32_t n = a.wc_count[w];
+    const uint32_t base = a.wc_begin[w];
+    const int lw = a.wc_level[w];
+    const uint64_t wkey = a.wc_key[w];
+    it.load(a, base, n);
+    uint32_t Kprev = 0, prev_off = 0, loff = 0;
+    for (int d = 0; d < MAXD; ++d) {
+        uint32_t alive = 0;
+        it.each([&](uint32_t, uint64_t, uint32_t &s, uint32_t &, uint32_t &) { alive += (s == 0xffu); });
+        const uint32_t A = block_sum<P1_BLOCK>(alive, red);
+        if (A == 0) {
+            if (d - 1 >= lw)
+                for (uint32_t r = threadIdx.x; r < Kprev; r += P1_BLOCK) a.lnode_mask[base + prev_off + r] = 0;
+            break;
+        }
+        uint32_t Kd = 0;
+        if (d < lw) {
+            if (threadIdx.x == 0) atomicAdd(&a.shared_cnt[pyr_off(d) + (wkey >> (3 * (lw - d)))], A);
+        } else if (d == lw) {
+            Kd = 1;
+            it.each([&](uint32_t, uint64_t, uint32_t &s, uint32_t &r, uint32_t &) { if (s == 0xffu) r = 0; });
+            if (threadIdx.x == 0) {
+                ncnt[0] = A;
+                a.lnode_key[base + loff] = wkey;
+            }
+            __syncthreads();
+        } else {
+            for (uint32_t r = threadIdx.x; r < Kprev; r += P1_BLOCK) pmask[r] = 0;
+            __syncthreads();
+            const int osh = 3 * (KB - d);
+            it.each([&](uint32_t, uint64_t c, uint32_t &s, uint32_t &r, uint32_t &) {
+                if (s == 0xffu) atomicOr(&pmask[r], 1u << ((c >> osh) & 7u));
+            });
+            __syncthreads();
+            for (uint32_t r = threadIdx.x; r < Kprev; r += P1_BLOCK) {
+                const uint32_t m = pmask[r];
+                a.lnode_mask[base + prev_off + r] = (uint8_t)m;
+                pbase[r] = __popc(m);
+            }
+            __syncthreads();
+            Kd = block_scan_array<P1_BLOCK>(pbase, Kprev, red);
+            for (uint32_t r = threadIdx.x; r < Kd; r += P1_BLOCK) ncnt[r] = 0;
+            __syncthreads();
+            it.each([&](uint32_t, uint64_t c, uint32_t &s, uint32_t &r, uint32_t &) {
+                if (s != 0xffu) return;
+                const uint32_t o = (c >> osh) & 7u;
+                const uint32_t m = pmask[r];
+                r = pbase[r] + __popc(m & ((1u << o) - 1u));
+                atomicAdd(&ncnt[r], 1u);
+                a.lnode_key[base + loff + r] = c >> osh;
+            });
+            __syncthreads();
+        }
+        if (d >= lw && threadIdx.x == 0) {
+            a.kd[(uint64_t)w * MAXD + d] = Kd;
+            a.loff[(uint64_t)w * MAXD + d] = loff;
+        }
+        // subsample every inner node: lowest position (= lowest original
+        // index) per occupied cell of lattice level d + s
+        for (uint64_t h = threadIdx.x; h <= hmask; h += P1_BLOCK) {
+            hk[h] = ~0ull;
+            hv[h] = 0xffffffffu;
+        }
+        __syncthreads();
+        const int csh = 3 * (KB - d - a.s);
+        const bool deepest = d >= a.dmax;
+        it.each([&](uint32_t pos, uint64_t c, uint32_t &s, uint32_t &r, uint32_t &) {
+            if (s != 0xffu) return;
+            const bool inner = d < lw || (!deepest && ncnt[r] > a.L);
+            if (inner) hash_insert_min(hk, hv, hmask, c >> csh, pos);
+        });
+        __syncthreads();
+        it.each([&](uint32_t pos, uint64_t c, uint32_t &s, uint32_t &r, uint32_t &f) {
+            if (s != 0xffu) return;
+            const bool inner = d < lw || (!deepest && ncnt[r] > a.L);
+            if (!inner || hash_lookup(hk, hv, hmask, c >> csh) == pos) {
+                s = (uint32_t)d;
+                f = r;
+            }
+        });
+        __syncthreads();
+        if (d >= lw) {
+            prev_off = loff;
+            loff += Kd;
+            Kprev = Kd;
+        }
+    }
+    it.store(a, base);
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(P1_BLOCK) void k_subsample_small(WcArgs a)
+{
+    __shared__ unsigned long long hk[WC_HASH];
+    __shared__ uint32_t hv[WC_HASH];
+    __shared__ uint32_t pmask[WC_CAP];
+    __shared__ uint32_t pbase[WC_CAP];
+    __shared__ uint32_t ncnt[WC_CAP];
+    __shared__ uint32_t red[P1_BLOCK / 64 + 1];
+    for (uint32_t w = blockIdx.x; w < a.num_wc; w += gridDim.x) {
+        if (a.wc_count[w] > WC_CAP) continue;
+        Items<false> it;
+        subsample_wc<false>(a, w, hk, hv, WC_HASH - 1, pmask, pbase, ncnt, red, it);
+    }
+}
+
+__global__ __launch_bounds__(P1_BLOCK) void k_subsample_big(WcArgs a)
+{
+    __shared__ uint32_t red[P1_BLOCK / 64 + 1];
+    unsigned long long *hk = reinterpret_cast<unsigned long long *>(a.big_hkey) + (uint64_t)blockIdx.x * a.big_hash_cap;
+    uint32_t *hv = a.big_hval + (uint64_t)blockIdx.x * a.big_hash_cap;
+    for (uint32_t b = blockIdx.x; b < a.num_big; b += gridDim.x) {
+        const uint32_t w = a.big_list[b];
+        const uint32_t base = a.wc_begin[w];
+        const uint64_t N = a.wc_begin[a.num_wc - 1] + a.wc_count[a.num_wc - 1];
+        uint32_t *pmask = a.big_node + base;
+        uint32_t *pbase = a.big_node + N + base;
+        uint32_t *ncnt = a.big_node + 2 * N + base;
+        Items<true> it;
+        subsample_wc<true>(a, w, hk, hv, a.big_hash_cap - 1, pmask, pbase, ncnt, red, it);
+    }
+}
+
+// First shared depth of each WC whose node is a leaf (or empty); lw if none.
+__global__ void k_decide(WcArgs a)
+{
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < a.num_wc; w += gridDim.x * blockDim.x) {
+        const int lw = a.wc_level[w];
+        const uint64_t key = a.wc_key[w];
+        int cut = lw;
+        for (int d = 0; d < lw; ++d) {
+            const uint32_t R = a.shared_cnt[pyr_off(d) + (key >> (3 * (lw - d)))];
+            if (R <= a.L || d >= a.dmax) { cut = d; break; }
+        }
+        a.cut[w] = (uint8_t)cut;
+    }
+}
+
+// Index of the first WC inside the depth-d node that contains WC w.
+__device__ __forceinline__ uint32_t owner_of(const WcArgs &a, uint32_t w, int d)
+{
+    const int lw = a.wc_level[w];
+    const uint64_t node_start = (a.wc_key[w] >> (3 * (lw - d))) << (3 * (a.lam_w - d));
+    uint32_t lo = 0, hi = w;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.wc_start[mid] < node_start) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// owned[d * num_wc + w] = number of nodes at depth d attributed to WC w: the
+// shared node at depth d < lw when w is the first WC inside it, or w's local
+// nodes at depth d >= lw.  Depth-major order of (d, w) equals (depth, key).
+__global__ void k_node_counts(WcArgs a, uint32_t *owned)
+{
+    const uint64_t total = (uint64_t)MAXD * a.num_wc;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const int d = (int)(i / a.num_wc);
+        const uint32_t w = (uint32_t)(i % a.num_wc);
+        const int lw = a.wc_level[w];
+        const int cut = a.cut[w];
+        uint32_t v = 0;
+        if (d < lw) {
+            if (d <= cut) {
+                bool first = true;
+                if (w > 0) {
+                    const int lp = a.wc_level[w - 1];
+                    if (lp > d && (a.wc_key[w - 1] >> (3 * (lp - d))) == (a.wc_key[w] >> (3 * (lw - d)))) first = false;
+                }
+                const bool exists = d < cut || a.shared_cnt[pyr_off(d) + (a.wc_key[w] >> (3 * (lw - d)))] > 0;
+                v = (first && exists) ? 1u : 0u;
+            }
+        } else if (cut == lw) {
+            v = a.kd[(uint64_t)w * MAXD + d];
+        }
+        owned[i] = v;
+    }
+}
+
+// Node id of every point, written at its original index.
+__global__ __launch_bounds__(256) void k_node_ids(WcArgs a, const uint32_t *node_base, uint32_t *nid_by_idx,
+                                                  uint32_t *err)
+{
+    __shared__ uint32_t own_id[MAXD];
+    for (uint32_t w = blockIdx.x; w < a.num_wc; w += gridDim.x) {
+        const int lw = a.wc_level[w];
+        const int cut = a.cut[w];
+        if (threadIdx.x < (uint32_t)lw) {
+            const int d = threadIdx.x;
+            own_id[d] = node_base[(uint64_t)d * a.num_wc + owner_of(a, w, d)];
+        }
+        __syncthreads();
+        const uint32_t base = a.wc_begin[w], n = a.wc_count[w];
+        for (uint32_t pos = threadIdx.x; pos < n; pos += blockDim.x) {
+            int t = a.t[base + pos];
+            uint32_t id;
+            if (t >= MAXD) {  // never finalised: an internal error, reported to the host
+                atomicOr(err, 1u);
+                nid_by_idx[a.wc_idx[base + pos]] = 0;
+                continue;
+            }
+            if (cut < lw && t >= cut) t = cut;
+            if (t < lw) id = own_id[t];
+            else id = node_base[(uint64_t)t * a.num_wc + w] + a.fr[base + pos];
+            nid_by_idx[a.wc_idx[base + pos]] = id;
+        }
+        __syncthreads();
+    }
+}
+
+// Node table: depth and key of every node, and child masks.  Local nodes
+// carry the masks computed inside their WC; a shared node's mask is the OR of
+// the octants of its children (shared nodes or WC roots).
+__global__ void k_node_fill(WcArgs a, const uint32_t *node_base, uint8_t *depth, uint64_t *key, uint8_t *mask)
+{
+    const uint64_t total = (uint64_t)MAXD * a.num_wc;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const int d = (int)(i / a.num_wc);
+        const uint32_t w = (uint32_t)(i % a.num_wc);
+        const int lw = a.wc_level[w];
+        const int cut = a.cut[w];
+        const uint64_t wkey = a.wc_key[w];
+        if (d < lw) {
+            if (d > cut) continue;
+            bool first = true;
+            if (w > 0) {
+                const int lp = a.wc_level[w - 1];
+                if (lp > d && (a.wc_key[w - 1] >> (3 * (lp - d))) == (wkey >> (3 * (lw - d)))) first = false;
+            }
+            if (!first) continue;
+            if (!(d < cut || a.shared_cnt[pyr_off(d) + (wkey >> (3 * (lw - d)))] > 0)) continue;
+            const uint32_t id = node_base[i];
+            const uint64_t k = wkey >> (3 * (lw - d));
+            depth[id] = (uint8_t)d;
+            key[id] = k;
+            if (d > 0) {
+                const uint32_t pid = node_base[(uint64_t)(d - 1) * a.num_wc + owner_of(a, w, d - 1)];
+                atomicOr(reinterpret_cast<uint32_t *>(mask + (pid & ~3u)), (1u << (k & 7u)) << (8 * (pid & 3u)));
+            }
+        } else if (cut == lw) {
+            const uint32_t K = a.kd[(uint64_t)w * MAXD + d];
+            if (K == 0) continue;
+            const uint32_t id0 = node_base[i];
+            const uint64_t lo = a.wc_begin[w] + a.loff[(uint64_t)w * MAXD + d];
+            for (uint32_t r = 0; r < K; ++r) {
+                depth[id0 + r] = (uint8_t)d;
+                key[id0 + r] = a.lnode_key[lo + r];
+                const uint32_t m = a.lnode_mask[lo + r];
+                if (m) atomicOr(reinterpret_cast<uint32_t *>(mask + ((id0 + r) & ~3u)), m << (8 * ((id0 + r) & 3u)));
+            }
+            if (d == lw && lw > 0) {
+                const uint32_t pid = node_base[(uint64_t)(d - 1) * a.num_wc + owner_of(a, w, d - 1)];
+                atomicOr(reinterpret_cast<uint32_t *>(mask + (pid & ~3u)), (1u << (wkey & 7u)) << (8 * (pid & 3u)));
+            }
+        }
+    }
+}
+
+// Begin and count of every node from the node-sorted keys.
+__global__ void k_node_ranges(const uint32_t *sk, uint64_t n, uint64_t *begin, uint32_t *count, uint32_t nn)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = sk[i];
+        if (i == 0 || sk[i - 1] != k) begin[k] = i;
+        if (i + 1 == n || sk[i + 1] != k) count[k] = (uint32_t)(i + 1);  // end, fixed below
+    }
+}
+__global__ void k_node_count_fix(const uint64_t *begin, uint32_t *count, uint32_t nn)
+{
+    // count[k] currently holds the end (exclusive) of node k
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x)
+        count[k] = count[k] - (uint32_t)begin[k];
+}
+
+// ---- step 5: preview ---------------------------------------------------------------------------
+// Keep index i iff H64(i) mod M == 0, H64 a xorshift-multiply mix with the
+// golden-ratio constant; ordered compaction (count per tile, scan, write).
+
+__device__ __forceinline__ uint64_t h64(uint64_t i)
+{
+    const uint64_t phi = 0x9E3779B97F4A7C15ull;
+    uint64_t h = i;
+    h ^= h >> 31;
+    h *= phi;
+    h ^= h >> 29;
+    h *= phi;
+    h ^= h >> 32;
+    return h;
+}
+__device__ __forceinline__ bool keep(uint64_t i, uint64_t m) { return (m & (m - 1)) == 0 ? (h64(i) & (m - 1)) == 0 : (h64(i) % m) == 0; }
+
+constexpr int PV_BLOCK = 256, PV_ITEMS = 16;
+constexpr uint64_t PV_TILE = PV_BLOCK * PV_ITEMS;
+
+__global__ __launch_bounds__(PV_BLOCK) void k_preview_count(uint64_t n, uint64_t m, uint32_t *tc)
+{
+    __shared__ uint32_t red[PV_BLOCK / 64 + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * PV_TILE;
+    uint32_t c = 0;
+    for (int j = 0; j < PV_ITEMS; ++j) {
+        const uint64_t i = base + (uint64_t)j * PV_BLOCK + threadIdx.x;
+        c += (i < n && keep(i, m)) ? 1u : 0u;
+    }
+    c = block_sum<PV_BLOCK>(c, red);
+    if (threadIdx.x == 0) tc[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(PV_BLOCK) void k_preview_write(uint64_t n, uint64_t m, const uint32_t *toff, uint32_t *out)
+{
+    __shared__ uint32_t wcnt[PV_BLOCK / 64];
+    const uint64_t base = (uint64_t)blockIdx.x * PV_TILE;
+    uint32_t run = toff[blockIdx.x];
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    for (int j = 0; j < PV_ITEMS; ++j) {
+        const uint64_t i = base + (uint64_t)j * PV_BLOCK + threadIdx.x;
+        const bool k = i < n && keep(i, m);
+        const uint64_t b = __ballot(k);
+        if (lane == 0) wcnt[w] = (uint32_t)__popcll(b);
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (int q = 0; q < PV_BLOCK / 64; ++q) {
+            before += q < w ? wcnt[q] : 0u;
+            tot += wcnt[q];
+        }
+        if (k) out[run + before + (uint32_t)__popcll(b & ((1ull << lane) - 1ull))] = (uint32_t)i;
+        run += tot;
+        __syncthreads();
+    }
+}
+
+// ---- launchers -----------------------------------------------------------------------------------
+
+static uint32_t grid_for(uint64_t n, uint32_t block, uint32_t cap = 4096)
+{
+    uint64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+void launch_bbox_init(DevBox *box, hipStream_t st) { hipLaunchKernelGGL(k_bbox_init, dim3(1), dim3(64), 0, st, box); }
+
+void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, DevBox *box, hipStream_t st)
+{
+    const int vec4 = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(z)) & 15) == 0;
+    hipLaunchKernelGGL(k_bbox, dim3(grid_for((n + 3) / 4, 256, 2048)), dim3(256), 0, st, x, y, z, n, vec4, box);
+}
+
+void launch_setup(DevBox *box, int given, const float *lo, const float *hi, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, box, given, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]);
+}
+
+void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box, int g,
+                     int count_outside, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw, hipStream_t st)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_quantize, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, x, y, z, n, box, g, count_outside,
+                       code, fine_cnt, box_rw);
+}
+
+void launch_pyramid(uint32_t *pyr, int g, hipStream_t st)
+{
+    for (int l = g; l >= 1; --l) {
+        const uint64_t ncell = 1ull << (3 * (l - 1));
+        hipLaunchKernelGGL(k_pyr_level, dim3(grid_for(ncell, 256)), dim3(256), 0, st, pyr, l);
+    }
+}
+
+void launch_grid_export(const uint32_t *fine, int g, uint32_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_grid_export, dim3(grid_for(1ull << (3 * g), 256)), dim3(256), 0, st, fine, g, out);
+}
+
+void launch_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cut_flags, dim3(grid_for(1ull << (3 * lam), 256)), dim3(256), 0, st, pyr, lam, thresh, flags,
+                       lev);
+}
+
+void launch_cut_table(const uint32_t *pyr, int lam, const uint32_t *flags, const uint32_t *excl, const uint8_t *lev,
+                      uint8_t *t_level, uint64_t *t_key, uint32_t *t_count, uint64_t *t_start, uint32_t thresh,
+                      uint32_t *over_flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cut_table, dim3(grid_for(1ull << (3 * lam), 256)), dim3(256), 0, st, pyr, lam, flags, excl,
+                       lev, t_level, t_key, t_count, t_start, thresh, over_flag);
+}
+
+void launch_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t st)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_u32_to_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, in, out, n);
+}
+
+void launch_point_keys(const uint64_t *code, uint64_t n, int g, const uint32_t *flags_c, const uint32_t *excl_c,
+                       int lam_w, const uint32_t *flags_w, const uint32_t *excl_w, uint32_t *cid, uint32_t *wid,
+                       hipStream_t st)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_point_keys, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, code, n, g, flags_c, excl_c,
+                       lam_w, flags_w, excl_w, cid, wid);
+}
+
+void launch_subsample_small(const WcArgs &a, hipStream_t st)
+{
+    if (a.num_wc == 0) return;
+    const uint32_t grid = a.num_wc < 2048 ? a.num_wc : 2048;
+    hipLaunchKernelGGL(k_subsample_small, dim3(grid), dim3(P1_BLOCK), 0, st, a);
+}
+
+void launch_subsample_big(const WcArgs &a, uint32_t grid, hipStream_t st)
+{
+    if (a.num_big == 0) return;
+    hipLaunchKernelGGL(k_subsample_big, dim3(grid), dim3(P1_BLOCK), 0, st, a);
+}
+
+void launch_decide(const WcArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_decide, dim3(grid_for(a.num_wc, 256)), dim3(256), 0, st, a);
+}
+
+void launch_node_counts(const WcArgs &a, uint32_t *owned, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_node_counts, dim3(grid_for((uint64_t)MAXD * a.num_wc, 256)), dim3(256), 0, st, a, owned);
+}
+
+void launch_node_ids(const WcArgs &a, const uint32_t *node_base, uint32_t *nid_by_idx, uint32_t *err, hipStream_t st)
+{
+    const uint32_t grid = a.num_wc < 4096 ? a.num_wc : 4096;
+    hipLaunchKernelGGL(k_node_ids, dim3(grid), dim3(256), 0, st, a, node_base, nid_by_idx, err);
+}
+
+void launch_node_fill(const WcArgs &a, const uint32_t *node_base, uint8_t *depth, uint64_t *key, uint8_t *mask,
+                      hipStream_t st)
+{
+    hipLaunchKernelGGL(k_node_fill, dim3(grid_for((uint64_t)MAXD * a.num_wc, 256)), dim3(256), 0, st, a, node_base,
+                       depth, key, mask);
+}
+
+void launch_node_ranges(const uint32_t *sorted_keys, uint64_t n, uint64_t *begin, uint32_t *count, uint32_t num_nodes,
+                        hipStream_t st)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_node_ranges, dim3(grid_for(n, 256)), dim3(256), 0, st, sorted_keys, n, begin, count, num_nodes);
+    hipLaunchKernelGGL(k_node_count_fix, dim3(grid_for(num_nodes, 256)), dim3(256), 0, st, begin, count, num_nodes);
+}
+
+uint64_t preview_tiles(uint64_t n) { return (n + PV_TILE - 1) / PV_TILE; }
+
+void launch_preview_count(uint64_t n, uint64_t m, uint32_t *tc, hipStream_t st)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_preview_count, dim3((uint32_t)preview_tiles(n)), dim3(PV_BLOCK), 0, st, n, m, tc);
+}
+
+void launch_preview_write(uint64_t n, uint64_t m, const uint32_t *toff, uint32_t *out, hipStream_t st)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_preview_write, dim3((uint32_t)preview_tiles(n)), dim3(PV_BLOCK), 0, st, n, m, toff, out);
+}
+
+}  // namespace fpo

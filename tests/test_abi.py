@@ -1,0 +1,59 @@
+"""The C-ABI library loads and exports every symbol include/fpo.h declares
+(no compute call: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2302_05002_amd", "libfpo.so")
+HDR = os.path.join(ROOT, "include", "fpo.h")
+
+
+def declared_functions():
+    src = open(HDR).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fpo_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        import paper_2302_05002_amd.build as b
+        b.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_binding_exports():
+    import paper_2302_05002_amd as fpo
+    assert declared_functions() == sorted(fpo.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_argument_errors_without_gpu(lib):
+    """Validation runs before any GPU call: bad parameters are rejected with a
+    message, on any machine."""
+    import paper_2302_05002_amd as fpo
+    fpo.load_library(LIB)
+    for p in (fpo.Params(count_grid=3), fpo.Params(count_grid=1024), fpo.Params(subsample_grid=512),
+              fpo.Params(max_points_per_chunk=0), fpo.Params(leaf_capacity=0), fpo.Params(preview_modulus=0)):
+        with pytest.raises(fpo.FpoError) as e:
+            fpo.workspace_size(100, p)
+        assert e.value.status == fpo.FPO_ERR_INVALID_ARG and str(e.value)
+    with pytest.raises(fpo.FpoError):
+        fpo.workspace_size(1 << 33, fpo.Params())
+    assert fpo.workspace_size(1000, fpo.Params()) > 0
+    assert fpo.workspace_size(0, fpo.Params()) > 0
+
+
+def test_workspace_grows_with_n(lib):
+    import paper_2302_05002_amd as fpo
+    fpo.load_library(LIB)
+    a = fpo.workspace_size(10_000, fpo.Params())
+    b = fpo.workspace_size(1_000_000, fpo.Params())
+    assert b > a
