@@ -288,6 +288,13 @@ int oracle_build(uint64_t n, const float *x, const float *y, const float *z,
                 if (xyz[a][i] < out->bbox_min[a]) out->bbox_min[a] = xyz[a][i];
                 if (xyz[a][i] > out->bbox_max[a]) out->bbox_max[a] = xyz[a][i];
             }
+        /* -0.0 and +0.0 compare equal, so which one a min/max keeps depends on
+         * the visiting order; report +0.0 (x + 0.0f maps -0.0 to +0.0 and
+         * leaves every other value unchanged) */
+        for (int a = 0; a < 3; ++a) {
+            out->bbox_min[a] = out->bbox_min[a] + 0.0f;
+            out->bbox_max[a] = out->bbox_max[a] + 0.0f;
+        }
     }
     /* cube: side = largest extent (float subtraction), scale = 2^21 / side */
     float side = 0.0f;

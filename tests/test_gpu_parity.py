@@ -145,6 +145,14 @@ def test_given_bbox(ctx):
     assert got["n_outside"] > 0
 
 
+def test_signed_zero_extremes(ctx):
+    for xs in ([-0.0, 0.0, 1.0], [0.0, -0.0, 1.0], [1.0, -0.0, 0.0]):
+        x = np.array(xs, np.float32)
+        m = np.array([-1.0, -0.0, -0.0], np.float32)
+        got, _ = run_both(ctx, synth.Cloud(x, m, x.copy()), 4, 10, 4, 1, 2)
+        assert not np.signbit(got["bbox_min"][0]) and not np.signbit(got["bbox_max"][1])
+
+
 def test_nonfinite_rejected(ctx):
     import torch
     import paper_2302_05002_amd as fpo

@@ -213,3 +213,14 @@ def test_errors():
               oracle.Params(8, 0, 8, 10, 4), oracle.Params(8, 10, 512, 10, 4),
               oracle.Params(8, 10, 6, 10, 4), oracle.Params(8, 10, 8, 0, 4), oracle.Params(8, 10, 8, 10, 0)):
         assert oracle.build_octree(ok, ok, ok, p)["status"] == oracle.ERR_INVALID_ARG
+
+
+def test_signed_zero_extremes_reported_as_plus_zero():
+    """A box extreme of -0.0 is reported as +0.0 whatever the point order."""
+    for xs in ([-0.0, 0.0, 1.0], [0.0, -0.0, 1.0], [1.0, -0.0, 0.0]):
+        x = np.array(xs, np.float32)
+        m = np.array([-1.0, -0.0, -0.0], np.float32)  # max of this axis is a zero
+        r = oracle.build_octree(x, m, x.copy(), oracle.Params(4, 10, 4, 1, 2))
+        assert r["status"] == oracle.OK
+        assert np.signbit(r["bbox_min"][0]) == False and r["bbox_min"][0] == 0.0
+        assert np.signbit(r["bbox_max"][1]) == False and r["bbox_max"][1] == 0.0
