@@ -66,7 +66,7 @@ struct Plan {
     size_t n_depth, n_key, n_mask, n_begin, n_count, n_points, pv_index;
     // temporaries
     size_t code, pyr, fc, ec, lc, fw, ew, lw_, w_level, w_key, w_count, w_start, w_begin;
-    size_t c_count_scan, cid, wid, wc_idx, wc_code, ms_temp, scan_temp;
+    size_t c_count_scan, code_perm, wc_idx, wc_code, ms_temp, scan_temp;
     size_t t, fr, shared_cnt, kd, loff, owned, node_base, lnode_key, lnode_mask, cut;
     size_t big_list, big_nr, big_node, big_hkey, big_hval;
     size_t nid, sorted_nid, pv_tiles, pv_offs;
@@ -122,8 +122,7 @@ Plan make_plan(uint64_t n, const fpo_params &p)
     P.w_start = take(8 * P.maxW);
     P.w_begin = take(4 * P.maxW);
     P.c_count_scan = take(4 * P.maxC);
-    P.cid = take(4 * nn);
-    P.wid = take(4 * nn);
+    P.code_perm = take(8 * nn);
     P.wc_idx = take(4 * nn);
     P.wc_code = take(8 * nn);
     // chunks, work chunks and nodes each number at most n
@@ -372,6 +371,9 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     scan_exclusive(U32(P.fw), U32(P.ew), P.W3, &ctrs->num_wc, stemp, st);
     launch_cut_table(pyr, P.lam_w, U32(P.fw), U32(P.ew), U8(P.lw_), U8(P.w_level), U64(P.w_key), U32(P.w_count),
                      U64(P.w_start), WC_CAP, nullptr, st);
+    // cell -> chunk id and cell -> work-chunk id tables (in place of the scans)
+    launch_cell_ids(U32(P.fc), U32(P.ec), P.G3, st);
+    launch_cell_ids(U32(P.fw), U32(P.ew), P.W3, st);
     JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
     JCHK(hipMemcpyAsync(hbox, box, sizeof(DevBox), hipMemcpyDeviceToHost, st));
     JCHK(hipStreamSynchronize(st));
@@ -387,24 +389,30 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     scan_exclusive(U32(P.w_count), U32(P.w_begin), num_wc, nullptr, stemp, st);
 
     // ---- step 3: stable scatter by chunk (perm) and by work chunk ----
-    launch_point_keys(U64(P.code), n, g, U32(P.fc), U32(P.ec), P.lam_w, U32(P.fw), U32(P.ew), U32(P.cid), U32(P.wid), st);
-    multisplit(U32(P.cid), n, num_chunks, nullptr, U32(P.perm), nullptr, nullptr, ws + P.ms_temp, st);
-    multisplit(U32(P.wid), n, num_wc, U64(P.code), U32(P.wc_idx), nullptr, U64(P.wc_code), ws + P.ms_temp, st);
+    {
+        MsInput in;
+        in.code = U64(P.code);
+        in.table = U32(P.ec);
+        in.code_shift = 3 * (KB - g);
+        in.pay = U64(P.code);
+        MsOutput o;
+        o.vals = U32(P.perm);
+        o.pay = U64(P.code_perm);
+        multisplit(in, n, num_chunks, o, ws + P.ms_temp, st);
+    }
+    {
+        MsInput in;
+        in.code = U64(P.code);
+        in.table = U32(P.ew);
+        in.code_shift = 3 * (KB - P.lam_w);
+        in.pay = U64(P.code);
+        MsOutput o;
+        o.vals = U32(P.wc_idx);
+        o.pay = U64(P.wc_code);
+        multisplit(in, n, num_wc, o, ws + P.ms_temp, st);
+    }
 
     // ---- step 4: subsample ----
-    // host list of work chunks too large for the LDS path
-    std::vector<uint32_t> wcount(num_wc);
-    JCHK(hipMemcpyAsync(wcount.data(), U32(P.w_count), 4ull * num_wc, hipMemcpyDeviceToHost, st));
-    JCHK(hipStreamSynchronize(st));
-    std::vector<uint32_t> big;
-    uint32_t max_big = 0;
-    for (uint32_t w = 0; w < num_wc; ++w)
-        if (wcount[w] > WC_CAP) {
-            big.push_back(w);
-            if (wcount[w] > max_big) max_big = wcount[w];
-        }
-    if (!big.empty()) JCHK(hipMemcpyAsync(U32(P.big_list), big.data(), 4 * big.size(), hipMemcpyHostToDevice, st));
-
     WcArgs A{};
     A.num_wc = num_wc;
     A.wc_begin = U32(P.w_begin);
@@ -423,7 +431,7 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     A.lnode_mask = U8(P.lnode_mask);
     A.cut = U8(P.cut);
     A.big_list = U32(P.big_list);
-    A.num_big = (uint32_t)big.size();
+    A.num_big_dev = &ctrs->num_big;
     A.big_nr = U32(P.big_nr);
     A.big_node = U32(P.big_node);
     A.big_hkey = U64(P.big_hkey);
@@ -432,21 +440,10 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     A.s = s_;
     A.L = p->leaf_capacity;
     A.dmax = KB - s_;
-    uint32_t big_grid = 0;
-    if (A.num_big) {
-        uint64_t cap = 1;
-        while (cap < 2ull * max_big) cap <<= 1;
-        A.big_hash_cap = cap;
-        uint64_t blocks = (4 * n) / cap;
-        if (blocks < 1) blocks = 1;
-        if (blocks > A.num_big) blocks = A.num_big;
-        if (blocks > 256) blocks = 256;
-        big_grid = (uint32_t)blocks;
-    }
     if (g > 0) JCHK(hipMemsetAsync(U32(P.shared_cnt), 0, 4 * pyr_off(g), st));
     JCHK(hipMemsetAsync(U32(P.kd), 0, 4ull * MAXD * num_wc, st));
     launch_subsample_small(A, st);
-    launch_subsample_big(A, big_grid, st);
+    launch_subsample_big(A, st);
     launch_decide(A, st);
     launch_node_counts(A, U32(P.owned), st);
     scan_exclusive(U32(P.owned), U32(P.node_base), (uint64_t)MAXD * num_wc, &ctrs->num_nodes, stemp, st);
@@ -456,7 +453,14 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     launch_node_ids(A, U32(P.node_base), U32(P.nid), &ctrs->internal_error, st);
     JCHK(hipMemsetAsync(U8(P.n_mask), 0, (num_nodes + 3) & ~3u, st));
     launch_node_fill(A, U32(P.node_base), U8(P.n_depth), U64(P.n_key), U8(P.n_mask), st);
-    multisplit(U32(P.nid), n, num_nodes, nullptr, U32(P.n_points), U32(P.sorted_nid), nullptr, ws + P.ms_temp, st);
+    {
+        MsInput in;
+        in.keys = U32(P.nid);
+        MsOutput o;
+        o.vals = U32(P.n_points);
+        o.keys = U32(P.sorted_nid);
+        multisplit(in, n, num_nodes, o, ws + P.ms_temp, st);
+    }
     launch_node_ranges(U32(P.sorted_nid), n, U64(P.n_begin), U32(P.n_count), num_nodes, st);
 
     JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));

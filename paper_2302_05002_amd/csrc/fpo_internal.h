@@ -19,9 +19,11 @@ constexpr uint32_t WC_CAP = P1_BLOCK * P1_ITEMS;   // 4096
 constexpr uint32_t WC_HASH = 2 * WC_CAP;           // 8192 slots, load <= 1/2
 
 constexpr int MS_BLOCK = 256;                // multisplit block (4 waves)
-constexpr int MS_ITEMS = 16;                 // elements per thread
-constexpr uint32_t MS_TILE = MS_BLOCK * MS_ITEMS;  // 4096
-constexpr uint32_t MS_MAX_BINS = 4096;       // bins of one multisplit pass
+constexpr int MS_ITEMS = 8;                  // elements per thread
+constexpr uint32_t MS_TILE = MS_BLOCK * MS_ITEMS;  // 2048
+constexpr uint32_t MS_MAX_BINS = 2048;       // buckets a tile can hold (segments)
+constexpr uint32_t MS_ONE_PASS_BINS = 1024;  // beyond this, sort by digits (keeps the count matrix small)
+constexpr uint32_t MS_DIGIT_BITS = 10;
 
 constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 16;
@@ -58,21 +60,58 @@ void launch_cut_table(const uint32_t *pyr, int lam, const uint32_t *flags, const
                       const uint8_t *lev, uint8_t *t_level, uint64_t *t_key, uint32_t *t_count,
                       uint64_t *t_start, uint32_t thresh, uint32_t *over_flag, hipStream_t st);
 void launch_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t st);
-void launch_point_keys(const uint64_t *code, uint64_t n, int g, const uint32_t *flags_c, const uint32_t *excl_c,
-                       int lam_w, const uint32_t *flags_w, const uint32_t *excl_w, uint32_t *cid,
-                       uint32_t *wid, hipStream_t st);
-
 // Device-wide exclusive scan of n u32 values; *total (device) gets the sum.
 size_t scan_temp_bytes(uint64_t n);
 void scan_exclusive(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total, void *temp,
                     hipStream_t st);
 
-// Stable multisplit (counting sort) of n elements by u32 keys in [0, nbins).
+// Stable multisplit (counting sort) by u32 keys.
+struct MsInput {
+    const uint32_t *keys = nullptr;    // explicit keys, or
+    const uint64_t *code = nullptr;    // key = table[code[e] >> code_shift]
+    const uint32_t *table = nullptr;
+    int code_shift = 0;
+    const uint32_t *vals = nullptr;    // values (null: the input position)
+    const uint64_t *pay = nullptr;     // optional payload carried along
+};
+struct MsOutput {
+    uint32_t *vals = nullptr;          // values in sorted order (optional)
+    uint32_t *keys = nullptr;          // keys in sorted order (optional)
+    uint32_t *src = nullptr;           // input position of every output (optional, one pass only)
+    uint64_t *pay = nullptr;           // payload in sorted order (optional)
+};
+// Segments: contiguous input ranges, each sorted into its own contiguous
+// bucket range [b0, b0 + nb) (nb <= MS_MAX_BINS); output positions are global.
+struct MsSegments {
+    uint32_t nseg = 0;
+    const uint32_t *begin = nullptr, *len = nullptr, *b0 = nullptr, *nb = nullptr;
+    uint64_t max_cells = 0;            // bound on sum(nb * tiles)
+};
+struct MsArgs {
+    uint64_t n;
+    const uint32_t *keys;
+    const uint64_t *code;
+    const uint32_t *table;
+    int code_shift;
+    const uint32_t *vals;
+    const uint64_t *pay;
+    uint32_t shift, dbits, nbins, tiles;
+    uint32_t *counts, *offsets;
+    uint32_t *vals_out, *keys_out, *src_out;
+    uint64_t *pay_out;
+    uint32_t nseg;
+    const uint32_t *seg_begin, *seg_len, *seg_b0, *seg_nb, *seg_mat, *seg_tile_first, *seg_total_tiles;
+};
 size_t multisplit_temp_bytes(uint64_t n, uint32_t nbins);
 size_t multisplit_temp_bound(uint64_t n, uint64_t max_bins);   // for any nbins <= max_bins
-void multisplit(const uint32_t *keys, uint64_t n, uint32_t nbins, const uint64_t *payload,
-                uint32_t *vals_out, uint32_t *keys_out, uint64_t *payload_out, void *temp,
-                hipStream_t st);
+void multisplit(const MsInput &in, uint64_t n, uint32_t nbins, const MsOutput &out, void *temp, hipStream_t st);
+size_t multisplit_seg_temp_bytes(uint64_t n, uint32_t nseg, uint64_t max_cells);
+void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, uint64_t max_tiles,
+                          const MsOutput &out, void *temp, hipStream_t st);
+// Exclusive scan whose length is read on the device (*n_dev <= n_max).
+void scan_exclusive_dev(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t n_max, void *temp,
+                        hipStream_t st);
+void launch_cell_ids(const uint32_t *flags, uint32_t *excl_to_ids, uint64_t ncell, hipStream_t st);
 
 // Subsample step.
 struct WcArgs {
@@ -92,21 +131,21 @@ struct WcArgs {
     uint64_t *lnode_key;         // local node keys, per work chunk region
     uint8_t *lnode_mask;         // local node child masks
     uint8_t *cut;                // per work chunk: first depth whose shared node is a leaf (or lw)
-    // big work chunks (more than WC_CAP points)
-    const uint32_t *big_list;
-    uint32_t num_big;
+    // work chunks for the global-memory path (more than WC_CAP points, or
+    // cell keys too long for the LDS table), listed on the device
+    uint32_t *big_list;
+    uint32_t *num_big_dev;
     uint32_t *big_nr;            // per position scratch
-    uint32_t *big_node;          // per position scratch (3 arrays of n)
-    uint64_t *big_hkey;          // hash keys
+    uint32_t *big_node;          // 3 words of node scratch per position
+    uint64_t *big_hkey;          // 4 table slots per position
     uint32_t *big_hval;
-    uint64_t big_hash_cap;       // slots per block region
     int lam_w;
     int s;
     uint32_t L;
     int dmax;
 };
 void launch_subsample_small(const WcArgs &a, hipStream_t st);
-void launch_subsample_big(const WcArgs &a, uint32_t grid, hipStream_t st);
+void launch_subsample_big(const WcArgs &a, hipStream_t st);
 void launch_decide(const WcArgs &a, hipStream_t st);
 void launch_node_counts(const WcArgs &a, uint32_t *owned, hipStream_t st);
 void launch_node_ids(const WcArgs &a, const uint32_t *node_base, uint32_t *nid_by_idx, uint32_t *err,

@@ -129,6 +129,11 @@ __device__ __forceinline__ uint64_t match_peers(uint32_t key, bool valid, int nb
     return valid ? m : 0ull;
 }
 
+__device__ __forceinline__ uint32_t ceil_log2_dev(uint32_t v)
+{
+    return v <= 1 ? 0u : 32u - __clz(v - 1u);
+}
+
 static inline uint32_t ceil_log2(uint64_t v)
 {
     uint32_t l = 0;
@@ -156,29 +161,26 @@ __global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ x, const
 {
     uint32_t mn[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[3] = {0u, 0u, 0u};
     uint32_t bad = 0;
-    const float *src[3] = {x, y, z};
     const uint64_t n4 = vec4 ? n / 4 : 0;   // float4 loads only on 16-byte aligned inputs
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (int a = 0; a < 3; ++a) {
-        const float4 *p4 = reinterpret_cast<const float4 *>(src[a]);
-        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
-            const float4 v = p4[i];
-            const float e[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (!isfinite(e[k])) { bad = 1; continue; }
-                const uint32_t o = f2o(e[k]);
-                mn[a] = min(mn[a], o);
-                mx[a] = max(mx[a], o);
-            }
-        }
-        for (uint64_t i = n4 * 4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-            const float e = src[a][i];
-            if (!isfinite(e)) { bad = 1; continue; }
-            const uint32_t o = f2o(e);
-            mn[a] = min(mn[a], o);
-            mx[a] = max(mx[a], o);
-        }
+    const float4 *p4[3] = {reinterpret_cast<const float4 *>(x), reinterpret_cast<const float4 *>(y),
+                           reinterpret_cast<const float4 *>(z)};
+    auto acc = [&](int a, float e) {
+        if (!isfinite(e)) { bad = 1; return; }
+        const uint32_t o = f2o(e);
+        mn[a] = min(mn[a], o);
+        mx[a] = max(mx[a], o);
+    };
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        const float4 vx = p4[0][i], vy = p4[1][i], vz = p4[2][i];   // three loads in flight
+        acc(0, vx.x); acc(0, vx.y); acc(0, vx.z); acc(0, vx.w);
+        acc(1, vy.x); acc(1, vy.y); acc(1, vy.z); acc(1, vy.w);
+        acc(2, vz.x); acc(2, vz.y); acc(2, vz.z); acc(2, vz.w);
+    }
+    for (uint64_t i = n4 * 4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        acc(0, x[i]);
+        acc(1, y[i]);
+        acc(2, z[i]);
     }
     __shared__ uint32_t s[7][4];
     const int w = threadIdx.x >> 6;
@@ -242,27 +244,98 @@ __device__ __forceinline__ uint32_t quantize1(float a, float lo, float scale)
 }
 
 // ---- step 1b: quantise + count ---------------------------------------------------
-// One Morton code per point (x the most significant bit of each triple) and
-// one atomic increment of the finest count cell (Morton order internally).
-__global__ __launch_bounds__(256) void k_quantize(const float *__restrict__ x, const float *__restrict__ y,
-                                                  const float *__restrict__ z, uint64_t n, const DevBox *box,
-                                                  int g, int count_outside, uint64_t *__restrict__ code,
-                                                  uint32_t *__restrict__ fine, DevBox *box_rw)
+// One Morton code per point (x the most significant bit of each triple) and a
+// count per finest cell.  Global atomics cost ~40 ns each on this part, so a
+// block first aggregates the cells of its contiguous range of points in an
+// LDS hash table and flushes one atomic per distinct cell: scans emit points
+// surface by surface, so a range touches far fewer cells than it has points.
+constexpr int QZ_BLOCK = 256;
+constexpr int QZ_ITEMS = 4;
+constexpr uint32_t QZ_HASH = 8192;   // slots; flushed when half full
+
+__device__ __forceinline__ uint32_t hash32(uint32_t k)
 {
+    k ^= k >> 16;
+    k *= 0x7feb352du;
+    k ^= k >> 15;
+    k *= 0x846ca68bu;
+    k ^= k >> 16;
+    return k;
+}
+
+__device__ void qz_flush(uint32_t *hk, uint32_t *hc, uint32_t *fine)
+{
+    for (uint32_t h = threadIdx.x; h < QZ_HASH; h += QZ_BLOCK) {
+        const uint32_t k = hk[h];
+        if (k != 0xffffffffu) {
+            atomicAdd(&fine[k], hc[h]);
+            hk[h] = 0xffffffffu;
+            hc[h] = 0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__ x, const float *__restrict__ y,
+                                                       const float *__restrict__ z, uint64_t n, const DevBox *box,
+                                                       int g, int count_outside, uint64_t *__restrict__ code,
+                                                       uint32_t *__restrict__ fine, DevBox *box_rw, uint64_t per_block)
+{
+    __shared__ uint32_t hk[QZ_HASH];
+    __shared__ uint32_t hc[QZ_HASH];
+    __shared__ uint32_t used;
     const float lx = box->lo[0], ly = box->lo[1], lz = box->lo[2], sc = box->scale;
     const float hx = box->hi[0], hy = box->hi[1], hz = box->hi[2];
     const int sh = 3 * (KB - g);
-    uint32_t outside = 0;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const float px = x[i], py = y[i], pz = z[i];
-        const uint32_t ux = quantize1(px, lx, sc), uy = quantize1(py, ly, sc), uz = quantize1(pz, lz, sc);
-        const uint64_t c = (split3(ux) << 2) | (split3(uy) << 1) | split3(uz);
-        code[i] = c;
-        atomicAdd(&fine[c >> sh], 1u);
-        if (count_outside)
-            outside += (px < lx || px > hx || py < ly || py > hy || pz < lz || pz > hz) ? 1u : 0u;
+    for (uint32_t h = threadIdx.x; h < QZ_HASH; h += QZ_BLOCK) {
+        hk[h] = 0xffffffffu;
+        hc[h] = 0;
     }
+    if (threadIdx.x == 0) used = 0;
+    __syncthreads();
+    uint32_t outside = 0;
+    const uint64_t lo = (uint64_t)blockIdx.x * per_block;
+    const uint64_t hi = lo + per_block < n ? lo + per_block : n;
+    for (uint64_t r0 = lo; r0 < hi; r0 += QZ_BLOCK * QZ_ITEMS) {
+#pragma unroll
+        for (int j = 0; j < QZ_ITEMS; ++j) {
+            const uint64_t i = r0 + (uint64_t)j * QZ_BLOCK + threadIdx.x;
+            if (i >= hi) continue;
+            const float px = x[i], py = y[i], pz = z[i];
+            const uint32_t ux = quantize1(px, lx, sc), uy = quantize1(py, ly, sc), uz = quantize1(pz, lz, sc);
+            const uint64_t c = (split3(ux) << 2) | (split3(uy) << 1) | split3(uz);
+            code[i] = c;
+            const uint32_t cell = (uint32_t)(c >> sh);
+            uint32_t h = hash32(cell) & (QZ_HASH - 1);
+            while (true) {
+                uint32_t k = hk[h];
+                if (k == 0xffffffffu) {
+                    k = atomicCAS(&hk[h], 0xffffffffu, cell);
+                    if (k == 0xffffffffu) {
+                        atomicAdd(&used, 1u);
+                        k = cell;
+                    }
+                }
+                if (k == cell) {
+                    atomicAdd(&hc[h], 1u);
+                    break;
+                }
+                h = (h + 1) & (QZ_HASH - 1);
+            }
+            if (count_outside)
+                outside += (px < lx || px > hx || py < ly || py > hy || pz < lz || pz > hz) ? 1u : 0u;
+        }
+        __syncthreads();
+        // at most QZ_BLOCK * QZ_ITEMS new cells per round: keep the table at
+        // most half full before the next one
+        if (used > QZ_HASH / 2 - QZ_BLOCK * QZ_ITEMS) {
+            qz_flush(hk, hc, fine);
+            __syncthreads();
+            if (threadIdx.x == 0) used = 0;
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    qz_flush(hk, hc, fine);
     if (count_outside) {
         outside = wave_sum(outside);
         if (lane_id() == 0 && outside) atomicAdd(&box_rw->n_outside, (unsigned long long)outside);
@@ -349,27 +422,13 @@ __global__ void k_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n)
         out[i] = in[i];
 }
 
-// Chunk id and work-chunk id of every point: the last chunk starting at or
-// before the point's cell (the one containing it).
-__global__ __launch_bounds__(256) void k_point_keys(const uint64_t *__restrict__ code, uint64_t n, int g,
-                                                    const uint32_t *flags_c, const uint32_t *excl_c, int lam_w,
-                                                    const uint32_t *flags_w, const uint32_t *excl_w,
-                                                    uint32_t *__restrict__ cid, uint32_t *__restrict__ wid)
-{
-    const int shc = 3 * (KB - g), shw = 3 * (KB - lam_w);
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t c = code[i];
-        const uint64_t mc = c >> shc, mw = c >> shw;
-        cid[i] = excl_c[mc] + flags_c[mc] - 1u;
-        wid[i] = excl_w[mw] + flags_w[mw] - 1u;
-    }
-}
-
 // ---- device-wide exclusive scan ------------------------------------------------------------
 
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const uint32_t *in, uint64_t n, uint32_t *tile_sum)
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const uint32_t *in, uint64_t n, const uint32_t *n_dev,
+                                                            uint32_t *tile_sum)
 {
     __shared__ uint32_t lds[SCAN_BLOCK / 64 + 1];
+    if (n_dev && *n_dev < n) n = *n_dev;
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
     uint32_t s = 0;
     for (int j = 0; j < SCAN_ITEMS; ++j) {
@@ -384,6 +443,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const uint32_t *in, 
 __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *tile_sum, uint32_t ntiles, uint32_t *total)
 {
     __shared__ uint32_t lds[1024 / 64 + 1];
+    // tiles past a device-side length hold 0 (k_scan_reduce wrote 0 for them)
     uint32_t carry = 0;
     for (uint32_t b = 0; b < ntiles; b += 1024) {
         const uint32_t i = b + threadIdx.x;
@@ -397,11 +457,13 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *tile_sum, uint32_t 
 }
 
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(const uint32_t *in, uint32_t *out, uint64_t n,
-                                                          const uint32_t *tile_off)
+                                                          const uint32_t *n_dev, const uint32_t *tile_off)
 {
     __shared__ uint32_t lds[SCAN_BLOCK / 64 + 1];
     __shared__ uint32_t buf[SCAN_TILE];
+    if (n_dev && *n_dev < n) n = *n_dev;
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    if (base >= n) return;
     for (int j = 0; j < SCAN_ITEMS; ++j) {
         const uint64_t e = base + (uint64_t)j * SCAN_BLOCK + threadIdx.x;
         buf[j * SCAN_BLOCK + threadIdx.x] = e < n ? in[e] : 0u;
@@ -442,103 +504,235 @@ void scan_exclusive(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tot
     }
     const uint32_t tiles = div_up(n, SCAN_TILE);
     uint32_t *ts = static_cast<uint32_t *>(temp);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, n, ts);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, n, nullptr, ts);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, ts, tiles, total);
-    hipLaunchKernelGGL(k_scan_down, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, out, n, ts);
+    hipLaunchKernelGGL(k_scan_down, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, out, n, nullptr, ts);
+}
+
+void scan_exclusive_dev(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t n_max, void *temp,
+                        hipStream_t st)
+{
+    if (n_max == 0) return;
+    const uint32_t tiles = div_up(n_max, SCAN_TILE);
+    uint32_t *ts = static_cast<uint32_t *>(temp);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, n_max, n_dev, ts);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, ts, tiles, nullptr);
+    hipLaunchKernelGGL(k_scan_down, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, out, n_max, n_dev, ts);
+}
+
+__global__ void k_cell_ids(const uint32_t *flags, uint32_t *ids, uint64_t ncell)
+{
+    for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < ncell; m += (uint64_t)gridDim.x * blockDim.x)
+        ids[m] = ids[m] + flags[m] - 1u;
 }
 
 // ---- stable multisplit ------------------------------------------------------------------------
-// One pass sorts by a digit of <= 12 bits.  Tile = MS_TILE elements; wave w of
-// the block owns the contiguous sub-tile [w*T/4, (w+1)*T/4) and walks it in
-// rounds of 64 lanes in index order.  Ranks inside a round come from a ballot
-// match over the digit bits (lanes in index order), so equal digits keep
-// their input order: the sort is stable.
+// Counting sort of n elements by a key with at most MS_MAX_BINS buckets per
+// pass, stable (equal keys keep their input order).  Input ranges can be cut
+// into segments, each with its own contiguous range of buckets (a segment's
+// tiles only see its own buckets, so the count matrix stays small).
+//
+// Tile = MS_TILE elements.  Wave w owns the contiguous sub-tile [w*T/4,
+// (w+1)*T/4) and walks it in rounds of 64 lanes in input order; inside a
+// round, ranks among equal keys come from a ballot match over the key bits.
+// The scatter stages the tile in LDS in bucket order and then writes whole
+// bucket runs, so global writes are coalesced.
 
-__global__ __launch_bounds__(MS_BLOCK) void k_ms_count(const uint32_t *__restrict__ keys, uint64_t n, int shift,
-                                                       uint32_t nbins, int nbits, uint32_t *__restrict__ counts,
-                                                       uint32_t tiles)
+__device__ __forceinline__ uint32_t ms_key(const MsArgs &A, uint64_t e)
 {
-    __shared__ uint16_t hist[MS_BLOCK / 64][MS_MAX_BINS];
-    const uint32_t tile = blockIdx.x;
-    const int w = threadIdx.x >> 6, lane = lane_id();
-    for (uint32_t b = threadIdx.x; b < nbins; b += MS_BLOCK)
-        for (int k = 0; k < MS_BLOCK / 64; ++k) hist[k][b] = 0;
+    if (A.keys) return A.keys[e];
+    return A.table[A.code[e] >> A.code_shift];
+}
+
+// Tile t -> [lo, hi), its segment's bucket range, count-matrix location.
+struct MsTile {
+    uint64_t lo, hi;
+    uint32_t b0, nb, mat, ntile, tis;
+    bool ok;
+};
+
+template <bool SEG>
+__device__ __forceinline__ MsTile ms_tile(const MsArgs &A, uint32_t t)
+{
+    MsTile T{};
+    if (!SEG) {
+        T.lo = (uint64_t)t * MS_TILE;
+        T.hi = T.lo + MS_TILE < A.n ? T.lo + MS_TILE : A.n;
+        T.b0 = 0;
+        T.nb = A.nbins;
+        T.mat = 0;
+        T.ntile = A.tiles;
+        T.tis = t;
+        T.ok = t < A.tiles;
+        return T;
+    }
+    T.ok = t < *A.seg_total_tiles;
+    if (!T.ok) return T;
+    uint32_t lo = 0, hi = A.nseg;   // last segment with tile_first <= t
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (A.seg_tile_first[mid] <= t) lo = mid; else hi = mid;
+    }
+    const uint32_t sgm = lo;
+    T.tis = t - A.seg_tile_first[sgm];
+    const uint64_t sb = A.seg_begin[sgm], se = A.seg_begin[sgm] + A.seg_len[sgm];
+    T.lo = sb + (uint64_t)T.tis * MS_TILE;
+    T.hi = T.lo + MS_TILE < se ? T.lo + MS_TILE : se;
+    T.b0 = A.seg_b0[sgm];
+    T.nb = A.seg_nb[sgm];
+    T.mat = A.seg_mat[sgm];
+    T.ntile = A.seg_tile_first[sgm + 1] - A.seg_tile_first[sgm];
+    return T;
+}
+
+template <bool SEG>
+__global__ __launch_bounds__(MS_BLOCK) void k_ms_count(MsArgs A)
+{
+    __shared__ uint32_t hist[MS_MAX_BINS];
+    const MsTile T = ms_tile<SEG>(A, blockIdx.x);
+    if (!T.ok) return;
+    for (uint32_t b = threadIdx.x; b < T.nb; b += MS_BLOCK) hist[b] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)tile * MS_TILE + (uint64_t)w * (MS_ITEMS * 64);
-    const uint32_t dmask = (nbits >= 32) ? 0xffffffffu : ((1u << nbits) - 1u);
+    const uint32_t dmask = (1u << A.dbits) - 1u;
+    for (uint64_t e = T.lo + threadIdx.x; e < T.hi; e += MS_BLOCK)
+        atomicAdd(&hist[((ms_key(A, e) >> A.shift) & dmask) - T.b0], 1u);
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < T.nb; b += MS_BLOCK)
+        A.counts[(uint64_t)T.mat + (uint64_t)b * T.ntile + T.tis] = hist[b];
+}
+
+template <bool SEG>
+__global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
+{
+    constexpr int W = MS_BLOCK / 64;
+    constexpr int PER_WAVE = MS_ITEMS * 64;
+    __shared__ uint16_t pre[W][MS_MAX_BINS];
+    __shared__ uint32_t gbase[MS_MAX_BINS];   // global position of local slot 0 of a bucket (mod 2^32)
+    __shared__ unsigned long long stage[MS_TILE];   // (key, value) pairs, then payloads
+    __shared__ uint32_t red[MS_BLOCK / 64 + 1];
+    const MsTile T = ms_tile<SEG>(A, blockIdx.x);
+    if (!T.ok) return;
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const uint32_t dmask = (1u << A.dbits) - 1u;
+    const int nbits = (int)ceil_log2_dev(T.nb);
+    for (uint32_t b = threadIdx.x; b < T.nb; b += MS_BLOCK)
+        for (int k = 0; k < W; ++k) pre[k][b] = 0;
+    __syncthreads();
+    // phase 1: per-wave running counts; each lane keeps its offset inside its wave
+    const uint64_t wlo = T.lo + (uint64_t)w * PER_WAVE;
+    uint32_t full[MS_ITEMS];
+    uint16_t wof[MS_ITEMS];
+#pragma unroll
     for (int r = 0; r < MS_ITEMS; ++r) {
-        const uint64_t e = base + (uint64_t)r * 64 + lane;
-        const bool valid = e < n;
-        const uint32_t key = valid ? ((keys[e] >> shift) & dmask) : 0u;
+        const uint64_t e = wlo + (uint64_t)r * 64 + lane;
+        const bool valid = e < T.hi;
+        full[r] = valid ? ms_key(A, e) : 0u;
+        const uint32_t key = valid ? ((full[r] >> A.shift) & dmask) - T.b0 : 0u;
         const uint64_t peers = match_peers(key, valid, nbits);
-        if (valid && (peers & ((1ull << lane) - 1ull)) == 0) hist[w][key] += (uint16_t)__popcll(peers);
+        const uint64_t lt = peers & ((1ull << lane) - 1ull);
+        const uint32_t before = valid ? pre[w][key] : 0u;
+        wof[r] = (uint16_t)(before + __popcll(lt));
+        if (valid && lt == 0) pre[w][key] = (uint16_t)(before + __popcll(peers));
     }
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < nbins; b += MS_BLOCK) {
-        uint32_t t = 0;
-        for (int k = 0; k < MS_BLOCK / 64; ++k) t += hist[k][b];
-        counts[(uint64_t)b * tiles + tile] = t;
+    // phase 2: bucket starts inside the tile (exclusive scan over buckets, each
+    // thread owning a run of consecutive buckets), per-wave bases, global bases
+    {
+        const uint32_t per = (T.nb + MS_BLOCK - 1) / MS_BLOCK;
+        const uint32_t b0 = threadIdx.x * per;
+        uint32_t sum = 0;
+        for (uint32_t b = b0; b < b0 + per && b < T.nb; ++b)
+            for (int k = 0; k < W; ++k) sum += pre[k][b];
+        uint32_t tot;
+        uint32_t run = block_excl_scan<MS_BLOCK>(sum, red, &tot);
+        for (uint32_t b = b0; b < b0 + per && b < T.nb; ++b) {
+            const uint32_t loff = run;
+            for (int k = 0; k < W; ++k) {
+                const uint32_t h = pre[k][b];
+                pre[k][b] = (uint16_t)run;
+                run += h;
+            }
+            gbase[b] = A.offsets[(uint64_t)T.mat + (uint64_t)b * T.ntile + T.tis] - loff;
+        }
+    }
+    __syncthreads();
+    // phase 3: stage (key, value) in bucket order
+#pragma unroll
+    for (int r = 0; r < MS_ITEMS; ++r) {
+        const uint64_t e = wlo + (uint64_t)r * 64 + lane;
+        if (e >= T.hi) continue;
+        const uint32_t key = ((full[r] >> A.shift) & dmask) - T.b0;
+        const uint32_t slot = pre[w][key] + wof[r];
+        const uint32_t v = A.vals ? A.vals[e] : (uint32_t)e;
+        stage[slot] = ((unsigned long long)full[r] << 32) | v;
+        wof[r] = (uint16_t)slot;
+    }
+    __syncthreads();
+    // phase 4: write bucket runs
+    const uint32_t cnt = (uint32_t)(T.hi - T.lo);
+    uint32_t gp[MS_ITEMS];
+#pragma unroll
+    for (int i = 0; i < MS_ITEMS; ++i) {
+        const uint32_t k = i * MS_BLOCK + threadIdx.x;
+        if (k >= cnt) continue;
+        const unsigned long long kv = stage[k];
+        const uint32_t fk = (uint32_t)(kv >> 32);
+        const uint32_t key = ((fk >> A.shift) & dmask) - T.b0;
+        const uint32_t pos = gbase[key] + k;
+        gp[i] = pos;
+        if (A.vals_out) A.vals_out[pos] = (uint32_t)kv;
+        if (A.keys_out) A.keys_out[pos] = fk;
+    }
+    if (A.src_out || A.pay_out) {
+        // the input position (and payload) of every slot, through the same stage
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < MS_ITEMS; ++r) {
+            const uint64_t e = wlo + (uint64_t)r * 64 + lane;
+            if (e >= T.hi) continue;
+            stage[wof[r]] = A.pay ? A.pay[e] : e;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MS_ITEMS; ++i) {
+            const uint32_t k = i * MS_BLOCK + threadIdx.x;
+            if (k >= cnt) continue;
+            if (A.pay_out) A.pay_out[gp[i]] = stage[k];
+        }
+        if (A.src_out && A.pay_out) {
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < MS_ITEMS; ++r) {
+                const uint64_t e = wlo + (uint64_t)r * 64 + lane;
+                if (e >= T.hi) continue;
+                stage[wof[r]] = e;
+            }
+            __syncthreads();
+        }
+        if (A.src_out) {
+#pragma unroll
+            for (int i = 0; i < MS_ITEMS; ++i) {
+                const uint32_t k = i * MS_BLOCK + threadIdx.x;
+                if (k >= cnt) continue;
+                A.src_out[gp[i]] = (uint32_t)stage[k];
+            }
+        }
     }
 }
 
-__global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals,
-                                                         const uint64_t *__restrict__ pay, uint64_t n, int shift,
-                                                         uint32_t nbins, int nbits, const uint32_t *__restrict__ offsets,
-                                                         uint32_t tiles, uint32_t *__restrict__ keys_out,
-                                                         uint32_t *__restrict__ vals_out, uint64_t *__restrict__ pay_out)
+// Segment preparation: tiles per segment and count-matrix cells per segment.
+__global__ void k_ms_seg_prep(uint32_t nseg, const uint32_t *len, const uint32_t *nb, uint32_t *ntile, uint32_t *cells)
 {
-    __shared__ uint16_t pre[MS_BLOCK / 64][MS_MAX_BINS];
-    __shared__ uint32_t tbase[MS_MAX_BINS];
-    const uint32_t tile = blockIdx.x;
-    const int w = threadIdx.x >> 6, lane = lane_id();
-    for (uint32_t b = threadIdx.x; b < nbins; b += MS_BLOCK)
-        for (int k = 0; k < MS_BLOCK / 64; ++k) pre[k][b] = 0;
-    __syncthreads();
-    const uint64_t base = (uint64_t)tile * MS_TILE + (uint64_t)w * (MS_ITEMS * 64);
-    const uint32_t dmask = (nbits >= 32) ? 0xffffffffu : ((1u << nbits) - 1u);
-    uint32_t full[MS_ITEMS];
-#pragma unroll
-    for (int r = 0; r < MS_ITEMS; ++r) {
-        const uint64_t e = base + (uint64_t)r * 64 + lane;
-        full[r] = e < n ? keys[e] : 0u;
-    }
-#pragma unroll
-    for (int r = 0; r < MS_ITEMS; ++r) {
-        const uint64_t e = base + (uint64_t)r * 64 + lane;
-        const bool valid = e < n;
-        const uint32_t key = (full[r] >> shift) & dmask;
-        const uint64_t peers = match_peers(key, valid, nbits);
-        if (valid && (peers & ((1ull << lane) - 1ull)) == 0) pre[w][key] += (uint16_t)__popcll(peers);
-    }
-    __syncthreads();
-    for (uint32_t b = threadIdx.x; b < nbins; b += MS_BLOCK) {
-        uint32_t acc = 0;
-        for (int k = 0; k < MS_BLOCK / 64; ++k) {
-            const uint32_t h = pre[k][b];
-            pre[k][b] = (uint16_t)acc;
-            acc += h;
-        }
-        tbase[b] = offsets[(uint64_t)b * tiles + tile];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < MS_ITEMS; ++r) {
-        const uint64_t e = base + (uint64_t)r * 64 + lane;
-        const bool valid = e < n;
-        const uint32_t key = (full[r] >> shift) & dmask;
-        const uint64_t peers = match_peers(key, valid, nbits);
-        if (!valid) continue;
-        const uint32_t before = pre[w][key];
-        const uint32_t pos = tbase[key] + before + (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
-        if ((peers & ((1ull << lane) - 1ull)) == 0) pre[w][key] = (uint16_t)(before + __popcll(peers));
-        vals_out[pos] = vals ? vals[e] : (uint32_t)e;
-        if (keys_out) keys_out[pos] = full[r];
-        if (pay_out) pay_out[pos] = pay[e];
+    if (blockIdx.x == 0 && threadIdx.x == 0) ntile[nseg] = 0;
+    for (uint32_t sg = blockIdx.x * blockDim.x + threadIdx.x; sg < nseg; sg += gridDim.x * blockDim.x) {
+        const uint32_t t = (len[sg] + MS_TILE - 1) / MS_TILE;
+        ntile[sg] = t;
+        cells[sg] = t * nb[sg];
     }
 }
 
 struct MsLayout {
-    uint32_t passes, dbits[4], nb[4], shift[4];
+    uint32_t passes, dbits[4], shift[4], nb[4];
     uint32_t tiles;
     uint64_t counts_words;
 };
@@ -548,13 +742,13 @@ static MsLayout ms_layout(uint64_t n, uint32_t nbins)
     MsLayout L{};
     L.tiles = div_up(n ? n : 1, MS_TILE);
     const uint32_t bits = ceil_log2(nbins);
-    if (nbins <= MS_MAX_BINS) {
+    if (nbins <= MS_ONE_PASS_BINS) {
         L.passes = 1;
         L.dbits[0] = bits;
         L.nb[0] = nbins;
         L.shift[0] = 0;
     } else {
-        L.passes = (bits + 11) / 12;
+        L.passes = (bits + MS_DIGIT_BITS - 1) / MS_DIGIT_BITS;
         const uint32_t per = (bits + L.passes - 1) / L.passes;
         uint32_t done = 0;
         for (uint32_t p = 0; p < L.passes; ++p) {
@@ -583,20 +777,20 @@ size_t multisplit_temp_bytes(uint64_t n, uint32_t nbins)
 
 size_t multisplit_temp_bound(uint64_t n, uint64_t max_bins)
 {
-    // the largest single pass (up to MS_MAX_BINS bins) and the multi-pass form
-    const uint32_t one = (uint32_t)(max_bins < MS_MAX_BINS ? max_bins : MS_MAX_BINS);
+    // the largest single pass and the multi-pass form (digits of at most
+    // MS_DIGIT_BITS bits)
+    const uint32_t one = (uint32_t)(max_bins < MS_ONE_PASS_BINS ? max_bins : MS_ONE_PASS_BINS);
     size_t b = multisplit_temp_bytes(n, one ? one : 1);
-    if (max_bins > MS_MAX_BINS) {
+    if (max_bins > MS_ONE_PASS_BINS) {
         const uint64_t tiles = div_up(n ? n : 1, MS_TILE);
-        const size_t m = 2 * align256((uint64_t)MS_MAX_BINS * tiles * 4) + scan_temp_bytes((uint64_t)MS_MAX_BINS * tiles) +
-                         2 * (align256(n * 4) * 2 + align256(n * 8));
+        const uint64_t w = (1ull << MS_DIGIT_BITS) * tiles;
+        const size_t m = 2 * align256(w * 4) + scan_temp_bytes(w) + 2 * (align256(n * 4) * 2 + align256(n * 8));
         if (m > b) b = m;
     }
     return b;
 }
 
-void multisplit(const uint32_t *keys, uint64_t n, uint32_t nbins, const uint64_t *payload, uint32_t *vals_out,
-                uint32_t *keys_out, uint64_t *payload_out, void *temp, hipStream_t st)
+void multisplit(const MsInput &in, uint64_t n, uint32_t nbins, const MsOutput &out, void *temp, hipStream_t st)
 {
     if (n == 0) return;
     const MsLayout L = ms_layout(n, nbins);
@@ -613,23 +807,85 @@ void multisplit(const uint32_t *keys, uint64_t n, uint32_t nbins, const uint64_t
             pb[i] = reinterpret_cast<uint64_t *>(p); p += align256(n * 8);
         }
     }
-    const uint32_t *kin = keys;
-    const uint32_t *vin = nullptr;
-    const uint64_t *pin = payload;
+    MsArgs A{};
+    A.n = n;
+    A.keys = in.keys;
+    A.code = in.code;
+    A.table = in.table;
+    A.code_shift = in.code_shift;
+    A.vals = in.vals;
+    A.pay = in.pay;
+    A.tiles = L.tiles;
+    A.counts = counts;
+    A.offsets = offs;
     for (uint32_t ps = 0; ps < L.passes; ++ps) {
         const bool last = ps + 1 == L.passes;
-        uint32_t *ko = last ? keys_out : kb[ps & 1];
-        uint32_t *vo = last ? vals_out : vb[ps & 1];
-        uint64_t *po = last ? payload_out : (payload ? pb[ps & 1] : nullptr);
-        hipLaunchKernelGGL(k_ms_count, dim3(L.tiles), dim3(MS_BLOCK), 0, st, kin, n, (int)L.shift[ps], L.nb[ps],
-                           (int)L.dbits[ps], counts, L.tiles);
+        A.shift = L.shift[ps];
+        A.dbits = L.dbits[ps];
+        A.nbins = L.nb[ps];
+        A.vals_out = last ? out.vals : vb[ps & 1];
+        A.keys_out = last ? out.keys : kb[ps & 1];
+        A.pay_out = last ? out.pay : (in.pay ? pb[ps & 1] : nullptr);
+        A.src_out = (last && ps == 0) ? out.src : nullptr;
+        hipLaunchKernelGGL(k_ms_count<false>, dim3(L.tiles), dim3(MS_BLOCK), 0, st, A);
         scan_exclusive(counts, offs, (uint64_t)L.nb[ps] * L.tiles, nullptr, stemp, st);
-        hipLaunchKernelGGL(k_ms_scatter, dim3(L.tiles), dim3(MS_BLOCK), 0, st, kin, vin, pin, n, (int)L.shift[ps],
-                           L.nb[ps], (int)L.dbits[ps], offs, L.tiles, ko, vo, po);
-        kin = ko;
-        vin = vo;
-        pin = po;
+        hipLaunchKernelGGL(k_ms_scatter<false>, dim3(L.tiles), dim3(MS_BLOCK), 0, st, A);
+        A.keys = A.keys_out;
+        A.code = nullptr;
+        A.vals = A.vals_out;
+        A.pay = A.pay_out;
     }
+}
+
+size_t multisplit_seg_temp_bytes(uint64_t n, uint32_t nseg, uint64_t max_cells)
+{
+    return 5 * align256(4ull * (nseg + 1)) + 2 * align256(4 * max_cells) + scan_temp_bytes(max_cells > nseg + 1 ? max_cells : nseg + 1) + 256;
+}
+
+void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, uint64_t max_tiles,
+                          const MsOutput &out, void *temp, hipStream_t st)
+{
+    if (n == 0 || sg.nseg == 0) return;
+    char *p = static_cast<char *>(temp);
+    uint32_t *ntile = reinterpret_cast<uint32_t *>(p); p += align256(4ull * (sg.nseg + 1));
+    uint32_t *cells = reinterpret_cast<uint32_t *>(p); p += align256(4ull * (sg.nseg + 1));
+    uint32_t *tile_first = reinterpret_cast<uint32_t *>(p); p += align256(4ull * (sg.nseg + 1));
+    uint32_t *mat = reinterpret_cast<uint32_t *>(p); p += align256(4ull * (sg.nseg + 1));
+    uint32_t *tot = reinterpret_cast<uint32_t *>(p); p += align256(4ull * (sg.nseg + 1));
+    uint32_t *counts = reinterpret_cast<uint32_t *>(p); p += align256(4 * sg.max_cells);
+    uint32_t *offs = reinterpret_cast<uint32_t *>(p); p += align256(4 * sg.max_cells);
+    void *stemp = p;
+    hipLaunchKernelGGL(k_ms_seg_prep, dim3(div_up(sg.nseg, 256)), dim3(256), 0, st, sg.nseg, sg.len, sg.nb, ntile, cells);
+    // tile_first has nseg + 1 entries (the last one = total tiles)
+    scan_exclusive(ntile, tile_first, sg.nseg + 1, tot, stemp, st);
+    scan_exclusive(cells, mat, sg.nseg, tot + 1, stemp, st);
+    MsArgs A{};
+    A.n = n;
+    A.keys = in.keys;
+    A.code = in.code;
+    A.table = in.table;
+    A.code_shift = in.code_shift;
+    A.vals = in.vals;
+    A.pay = in.pay;
+    A.shift = 0;
+    A.dbits = 31;
+    A.counts = counts;
+    A.offsets = offs;
+    A.nseg = sg.nseg;
+    A.seg_begin = sg.begin;
+    A.seg_len = sg.len;
+    A.seg_b0 = sg.b0;
+    A.seg_nb = sg.nb;
+    A.seg_mat = mat;
+    A.seg_tile_first = tile_first;
+    A.seg_total_tiles = tot;
+    A.vals_out = out.vals;
+    A.keys_out = out.keys;
+    A.pay_out = out.pay;
+    A.src_out = out.src;
+    hipLaunchKernelGGL(k_ms_count<true>, dim3((uint32_t)max_tiles), dim3(MS_BLOCK), 0, st, A);
+    scan_exclusive_dev(counts, offs, tot + 1, sg.max_cells, stemp, st);
+    hipLaunchKernelGGL(k_ms_scatter<true>, dim3((uint32_t)max_tiles), dim3(MS_BLOCK), 0, st, A);
 }
 
 // ---- step 4: per-node grid subsample -----------------------------------------------------------
@@ -645,6 +901,8 @@ void multisplit(const uint32_t *keys, uint64_t n, uint32_t nbins, const uint64_t
 // finds the first shared leaf of each WC (its "cut"), and points whose
 // tentative depth is at or below the cut belong to that leaf.
 
+// Global-memory table (full 64-bit keys, separate values) for the work
+// chunks handled outside LDS.
 __device__ __forceinline__ void hash_insert_min(unsigned long long *hk, uint32_t *hv, uint64_t mask, uint64_t key,
                                                 uint32_t val)
 {
@@ -669,6 +927,11 @@ __device__ __forceinline__ uint32_t hash_lookup(const unsigned long long *hk, co
     return hv[h];
 }
 
+// LDS cell table: packed 64-bit entries (key << POS_BITS | position), one
+// atomicMin keeps the lowest position of a key.  Keys are relative to the work
+// chunk and hold at most 63 - POS_BITS bits, so an entry is never all ones
+// (the empty value).
+
 // Exclusive scan in place of arr[0..K) by the whole block; returns the total.
 template <int BLOCK>
 __device__ uint32_t block_scan_array(uint32_t *arr, uint32_t K, uint32_t *lds)
@@ -686,24 +949,27 @@ __device__ uint32_t block_scan_array(uint32_t *arr, uint32_t K, uint32_t *lds)
     return carry;
 }
 
-// Per-item state for the WC loop: code, tentative depth (0xff = alive),
-// current node rank, final node rank.
-template <bool BIG>
-struct Items;
+// Item states during the work-chunk loop: 0..21 = final (tentative) depth,
+// ST_ALIVE = not yet placed, ST_INNER = not yet placed and in an inner node
+// at the current depth.
+constexpr uint32_t ST_ALIVE = 0xffu;
+constexpr uint32_t ST_INNER = 0xfeu;
 
-template <>
-struct Items<false> {
-    uint64_t code[P1_ITEMS];
-    uint32_t st[P1_ITEMS], nr[P1_ITEMS], fr[P1_ITEMS];
+// Per-item state (code, state, current node rank, final node rank) in
+// registers (LDS path) or in global memory (BIG path).
+template <int BLOCK, int ITEMS, bool BIG>
+struct Items {
+    uint64_t code[ITEMS];
+    uint32_t st[ITEMS], nr[ITEMS], fr[ITEMS];
     uint32_t n;
     __device__ void load(const WcArgs &a, uint32_t base, uint32_t n_)
     {
         n = n_;
 #pragma unroll
-        for (int j = 0; j < P1_ITEMS; ++j) {
-            const uint32_t pos = j * P1_BLOCK + threadIdx.x;
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t pos = j * BLOCK + threadIdx.x;
             code[j] = pos < n ? a.wc_code[base + pos] : 0ull;
-            st[j] = 0xffu;
+            st[j] = ST_ALIVE;
             nr[j] = 0;
             fr[j] = 0;
         }
@@ -712,16 +978,16 @@ struct Items<false> {
     __device__ void each(F &&f)
     {
 #pragma unroll
-        for (int j = 0; j < P1_ITEMS; ++j) {
-            const uint32_t pos = j * P1_BLOCK + threadIdx.x;
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t pos = j * BLOCK + threadIdx.x;
             if (pos < n) f(pos, code[j], st[j], nr[j], fr[j]);
         }
     }
     __device__ void store(const WcArgs &a, uint32_t base)
     {
 #pragma unroll
-        for (int j = 0; j < P1_ITEMS; ++j) {
-            const uint32_t pos = j * P1_BLOCK + threadIdx.x;
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t pos = j * BLOCK + threadIdx.x;
             if (pos < n) {
                 a.t[base + pos] = (uint8_t)st[j];
                 a.fr[base + pos] = fr[j];
@@ -730,8 +996,8 @@ struct Items<false> {
     }
 };
 
-template <>
-struct Items<true> {
+template <int BLOCK, int ITEMS>
+struct Items<BLOCK, ITEMS, true> {
     const uint64_t *code;
     uint8_t *t;
     uint32_t *nr, *fr;
@@ -743,8 +1009,8 @@ struct Items<true> {
         nr = a.big_nr + base;
         fr = a.fr + base;
         n = n_;
-        for (uint32_t pos = threadIdx.x; pos < n; pos += P1_BLOCK) {
-            t[pos] = 0xffu;
+        for (uint32_t pos = threadIdx.x; pos < n; pos += BLOCK) {
+            t[pos] = ST_ALIVE;
             nr[pos] = 0;
             fr[pos] = 0;
         }
@@ -753,7 +1019,7 @@ struct Items<true> {
     template <class F>
     __device__ void each(F &&f)
     {
-        for (uint32_t pos = threadIdx.x; pos < n; pos += P1_BLOCK) {
+        for (uint32_t pos = threadIdx.x; pos < n; pos += BLOCK) {
             const uint64_t c = code[pos];
             uint32_t s = t[pos], r = nr[pos], q = fr[pos];
             f(pos, c, s, r, q);
@@ -765,55 +1031,83 @@ struct Items<true> {
     __device__ void store(const WcArgs &, uint32_t) {}
 };
 
-template <bool BIG>
-__device__ void subsample_wc(const WcArgs &a, uint32_t w, unsigned long long *hk, uint32_t *hv, uint64_t hmask,
-                             uint32_t *pmask, uint32_t *pbase, uint32_t *ncnt, uint32_t *red, Items<BIG> &it)
+// Runs the subtree of work chunk w assuming its shared ancestors are inner.
+// LDS path (BIG = false, at most CAP = BLOCK * ITEMS points): points in
+// registers; one LDS region of 3 * CAP words holds the node scratch (parent
+// masks, child bases, node counts) and then the cell table (2 * CAP packed
+// 32-bit entries).  BIG path: per-position state, node scratch and the cell table in
+// global memory; winners are decided on positions too, which are in original
+// index order inside a work chunk.  Returns false (LDS path only) when the
+// relative cell keys outgrow the packed entries: the chunk is then redone by
+// the BIG path.
+template <int BLOCK, int ITEMS, bool BIG>
+__device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint32_t *red,
+                             uint32_t *counter, uint32_t *gnode, unsigned long long *ghk, uint32_t *ghv,
+                             uint64_t gmask)
 {
+    constexpr uint32_t CAP = BLOCK * ITEMS;
+    constexpr uint32_t HASH = 2 * CAP;
+    constexpr int POS_BITS = (CAP <= 2048) ? 11 : (CAP <= 4096 ? 12 : 13);
+    constexpr int KEY_BITS = 31 - POS_BITS;   // packed 32-bit entries, never all ones
     const uint32_t n = a.wc_count[w];
     const uint32_t base = a.wc_begin[w];
     const int lw = a.wc_level[w];
     const uint64_t wkey = a.wc_key[w];
+    uint32_t *pmask, *pbase, *ncnt;
+    if (BIG) {
+        pmask = gnode;
+        pbase = gnode + n;
+        ncnt = gnode + 2 * n;
+    } else {
+        pmask = region;
+        pbase = region + CAP;
+        ncnt = region + 2 * CAP;
+    }
+    __shared__ uint32_t alive_at[MAXD];
+    if (threadIdx.x < MAXD) alive_at[threadIdx.x] = 0;   // the block may have run another work chunk
+    if (threadIdx.x == 0) { counter[0] = 0; counter[1] = 0; }
+    Items<BLOCK, ITEMS, BIG> it;
     it.load(a, base, n);
+    __syncthreads();
+    uint32_t A = n;   // alive points at the current depth
     uint32_t Kprev = 0, prev_off = 0, loff = 0;
     for (int d = 0; d < MAXD; ++d) {
-        uint32_t alive = 0;
-        it.each([&](uint32_t, uint64_t, uint32_t &s, uint32_t &, uint32_t &) { alive += (s == 0xffu); });
-        const uint32_t A = block_sum<P1_BLOCK>(alive, red);
         if (A == 0) {
             if (d - 1 >= lw)
-                for (uint32_t r = threadIdx.x; r < Kprev; r += P1_BLOCK) a.lnode_mask[base + prev_off + r] = 0;
+                for (uint32_t r = threadIdx.x; r < Kprev; r += BLOCK) a.lnode_mask[base + prev_off + r] = 0;
             break;
         }
+        const bool deepest = d >= a.dmax;
         uint32_t Kd = 0;
+        bool single_inner = false;   // d <= lw: one node holds every alive point
         if (d < lw) {
-            if (threadIdx.x == 0) atomicAdd(&a.shared_cnt[pyr_off(d) + (wkey >> (3 * (lw - d)))], A);
+            // shared node, assumed inner (d < lw <= s <= dmax)
+            if (threadIdx.x == 0) alive_at[d] = A;
+            single_inner = true;
         } else if (d == lw) {
             Kd = 1;
-            it.each([&](uint32_t, uint64_t, uint32_t &s, uint32_t &r, uint32_t &) { if (s == 0xffu) r = 0; });
-            if (threadIdx.x == 0) {
-                ncnt[0] = A;
-                a.lnode_key[base + loff] = wkey;
-            }
-            __syncthreads();
+            single_inner = !deepest && A > a.L;
+            it.each([&](uint32_t, uint64_t, uint32_t &st, uint32_t &r, uint32_t &) { if (st == ST_ALIVE) r = 0; });
+            if (threadIdx.x == 0) a.lnode_key[base + loff] = wkey;
         } else {
-            for (uint32_t r = threadIdx.x; r < Kprev; r += P1_BLOCK) pmask[r] = 0;
+            for (uint32_t r = threadIdx.x; r < Kprev; r += BLOCK) pmask[r] = 0;
             __syncthreads();
             const int osh = 3 * (KB - d);
-            it.each([&](uint32_t, uint64_t c, uint32_t &s, uint32_t &r, uint32_t &) {
-                if (s == 0xffu) atomicOr(&pmask[r], 1u << ((c >> osh) & 7u));
+            it.each([&](uint32_t, uint64_t c, uint32_t &st, uint32_t &r, uint32_t &) {
+                if (st == ST_ALIVE) atomicOr(&pmask[r], 1u << ((c >> osh) & 7u));
             });
             __syncthreads();
-            for (uint32_t r = threadIdx.x; r < Kprev; r += P1_BLOCK) {
+            for (uint32_t r = threadIdx.x; r < Kprev; r += BLOCK) {
                 const uint32_t m = pmask[r];
                 a.lnode_mask[base + prev_off + r] = (uint8_t)m;
                 pbase[r] = __popc(m);
             }
             __syncthreads();
-            Kd = block_scan_array<P1_BLOCK>(pbase, Kprev, red);
-            for (uint32_t r = threadIdx.x; r < Kd; r += P1_BLOCK) ncnt[r] = 0;
+            Kd = block_scan_array<BLOCK>(pbase, Kprev, red);
+            for (uint32_t r = threadIdx.x; r < Kd; r += BLOCK) ncnt[r] = 0;
             __syncthreads();
-            it.each([&](uint32_t, uint64_t c, uint32_t &s, uint32_t &r, uint32_t &) {
-                if (s != 0xffu) return;
+            it.each([&](uint32_t, uint64_t c, uint32_t &st, uint32_t &r, uint32_t &) {
+                if (st != ST_ALIVE) return;
                 const uint32_t o = (c >> osh) & 7u;
                 const uint32_t m = pmask[r];
                 r = pbase[r] + __popc(m & ((1u << o) - 1u));
@@ -826,69 +1120,189 @@ __device__ void subsample_wc(const WcArgs &a, uint32_t w, unsigned long long *hk
             a.kd[(uint64_t)w * MAXD + d] = Kd;
             a.loff[(uint64_t)w * MAXD + d] = loff;
         }
-        // subsample every inner node: lowest position (= lowest original
-        // index) per occupied cell of lattice level d + s
-        for (uint64_t h = threadIdx.x; h <= hmask; h += P1_BLOCK) {
-            hk[h] = ~0ull;
-            hv[h] = 0xffffffffu;
+        // inner flag per item (read before the region becomes the cell table)
+        if (d > lw)
+            it.each([&](uint32_t, uint64_t, uint32_t &st, uint32_t &r, uint32_t &) {
+                if (st == ST_ALIVE && !deepest && ncnt[r] > a.L) st = ST_INNER;
+            });
+        else if (single_inner)
+            it.each([&](uint32_t, uint64_t, uint32_t &st, uint32_t &, uint32_t &) {
+                if (st == ST_ALIVE) st = ST_INNER;
+            });
+        // cells of lattice level d + s; keys relative to the work chunk
+        const int csh = 3 * (KB - d - a.s);
+        const int rel_bits = 3 * (d + a.s - lw);
+        const uint64_t rel_mask = rel_bits >= 64 ? ~0ull : ((1ull << rel_bits) - 1ull);
+        bool mine_inner = false;
+        it.each([&](uint32_t, uint64_t, uint32_t &st, uint32_t &, uint32_t &) { mine_inner |= st == ST_INNER; });
+        // (also the barrier after which the node scratch becomes the cell table)
+        const bool any_inner = __syncthreads_or(mine_inner);
+        if (!any_inner) {
+            // every alive point sits in a leaf
+            it.each([&](uint32_t, uint64_t, uint32_t &st, uint32_t &r, uint32_t &f) {
+                if (st == ST_ALIVE) {
+                    st = (uint32_t)d;
+                    f = r;
+                }
+            });
+            A = 0;
+            if (d >= lw) {
+                prev_off = loff;
+                loff += Kd;
+                Kprev = Kd;
+            }
+            continue;
+        }
+        if (!BIG && rel_bits > KEY_BITS) return false;
+        if (BIG) {
+            for (uint64_t h = threadIdx.x; h <= gmask; h += BLOCK) {
+                ghk[h] = ~0ull;
+                ghv[h] = 0xffffffffu;
+            }
+        } else {
+            for (uint32_t h = threadIdx.x; h < HASH; h += BLOCK) region[h] = ~0u;
         }
         __syncthreads();
-        const int csh = 3 * (KB - d - a.s);
-        const bool deepest = d >= a.dmax;
-        it.each([&](uint32_t pos, uint64_t c, uint32_t &s, uint32_t &r, uint32_t &) {
-            if (s != 0xffu) return;
-            const bool inner = d < lw || (!deepest && ncnt[r] > a.L);
-            if (inner) hash_insert_min(hk, hv, hmask, c >> csh, pos);
-        });
-        __syncthreads();
-        it.each([&](uint32_t pos, uint64_t c, uint32_t &s, uint32_t &r, uint32_t &f) {
-            if (s != 0xffu) return;
-            const bool inner = d < lw || (!deepest && ncnt[r] > a.L);
-            if (!inner || hash_lookup(hk, hv, hmask, c >> csh) == pos) {
-                s = (uint32_t)d;
-                f = r;
+        uint32_t survive = 0;
+        if constexpr (BIG) {
+            it.each([&](uint32_t pos, uint64_t c, uint32_t &st, uint32_t &, uint32_t &) {
+                if (st != ST_INNER) return;
+                hash_insert_min(ghk, ghv, gmask, (c >> csh) & rel_mask, pos);
+            });
+            __syncthreads();
+            it.each([&](uint32_t pos, uint64_t c, uint32_t &st, uint32_t &r, uint32_t &f) {
+                if (st == ST_ALIVE) {   // leaf: every reaching point stays
+                    st = (uint32_t)d;
+                    f = r;
+                } else if (st == ST_INNER) {
+                    if (hash_lookup(ghk, ghv, gmask, (c >> csh) & rel_mask) == pos) {
+                        st = (uint32_t)d;
+                        f = r;
+                    } else {
+                        st = ST_ALIVE;
+                        ++survive;
+                    }
+                }
+            });
+        } else {
+            constexpr int HBITS = (HASH == 4096) ? 12 : (HASH == 8192 ? 13 : 14);
+            uint32_t slot[ITEMS];
+            uint32_t mine[ITEMS];   // key << POS_BITS | position; all ones once placed (or not inserting)
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t pos = j * BLOCK + threadIdx.x;
+                const uint32_t key = (uint32_t)((it.code[j] >> csh) & rel_mask);
+                mine[j] = (pos < n && it.st[j] == ST_INNER) ? ((key << POS_BITS) | pos) : 0xffffffffu;
+                slot[j] = rel_bits <= HBITS ? key : (key * 0x9E3779B1u) >> (32 - HBITS);
             }
-        });
+            bool any = true;
+            while (any) {
+                any = false;
+                uint32_t cur[ITEMS];
+#pragma unroll
+                for (int j = 0; j < ITEMS; ++j)
+                    if (mine[j] != 0xffffffffu) cur[j] = region[slot[j]];
+#pragma unroll
+                for (int j = 0; j < ITEMS; ++j) {
+                    if (mine[j] == 0xffffffffu) continue;
+                    uint32_t c = cur[j];
+                    if (c == 0xffffffffu) {
+                        c = atomicCAS(&region[slot[j]], 0xffffffffu, mine[j]);
+                        if (c == 0xffffffffu) { mine[j] = 0xffffffffu; continue; }   // new key: done
+                    }
+                    if ((c >> POS_BITS) == (mine[j] >> POS_BITS)) {
+                        if (c > mine[j]) atomicMin(&region[slot[j]], mine[j]);
+                        mine[j] = 0xffffffffu;                                      // our key: done
+                    } else {
+                        slot[j] = (slot[j] + 1) & (HASH - 1);                        // another key
+                        any = true;
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t pos = j * BLOCK + threadIdx.x;
+                if (pos >= n) continue;
+                if (it.st[j] == ST_ALIVE) {   // leaf: every reaching point stays
+                    it.st[j] = (uint32_t)d;
+                    it.fr[j] = it.nr[j];
+                } else if (it.st[j] == ST_INNER) {
+                    if ((region[slot[j]] & ((1u << POS_BITS) - 1u)) == pos) {
+                        it.st[j] = (uint32_t)d;
+                        it.fr[j] = it.nr[j];
+                    } else {
+                        it.st[j] = ST_ALIVE;
+                        ++survive;
+                    }
+                }
+            }
+        }
+        // survivors, counted per wave into an alternating counter
+        survive = wave_sum(survive);
+        if (lane_id() == 0 && survive) atomicAdd(&counter[(d + 1) & 1], survive);
         __syncthreads();
+        A = counter[(d + 1) & 1];
+        if (threadIdx.x == 0) counter[d & 1] = 0;   // reused two depths later, after the next barrier
         if (d >= lw) {
             prev_off = loff;
             loff += Kd;
             Kprev = Kd;
         }
     }
+    // reaching counts of the shared ancestors
+    if (threadIdx.x < (uint32_t)lw) {
+        const int d = threadIdx.x;
+        const uint32_t Ad = alive_at[d];
+        if (Ad) atomicAdd(&a.shared_cnt[pyr_off(d) + (wkey >> (3 * (lw - d)))], Ad);
+    }
     it.store(a, base);
     __syncthreads();
+    return true;
 }
 
-__global__ __launch_bounds__(P1_BLOCK) void k_subsample_small(WcArgs a)
+// LDS path for work chunks of at most BLOCK * ITEMS points whose size is above
+// MIN_N (the smaller ones run in a smaller instance with more blocks per CU).
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_subsample_lds(WcArgs a, uint32_t min_n)
 {
-    __shared__ unsigned long long hk[WC_HASH];
-    __shared__ uint32_t hv[WC_HASH];
-    __shared__ uint32_t pmask[WC_CAP];
-    __shared__ uint32_t pbase[WC_CAP];
-    __shared__ uint32_t ncnt[WC_CAP];
-    __shared__ uint32_t red[P1_BLOCK / 64 + 1];
+    constexpr uint32_t CAP = BLOCK * ITEMS;
+    __shared__ uint32_t region[3 * CAP];   // node scratch, then the cell table (2 * CAP entries)
+    __shared__ uint32_t red[BLOCK / 64 + 1];
+    __shared__ uint32_t counter[2];
     for (uint32_t w = blockIdx.x; w < a.num_wc; w += gridDim.x) {
-        if (a.wc_count[w] > WC_CAP) continue;
-        Items<false> it;
-        subsample_wc<false>(a, w, hk, hv, WC_HASH - 1, pmask, pbase, ncnt, red, it);
+        const uint32_t n = a.wc_count[w];
+        if (n <= min_n || n > CAP) continue;
+        const bool ok = subsample_wc<BLOCK, ITEMS, false>(a, w, region, red, counter, nullptr, nullptr, nullptr, 0);
+        if (!ok && threadIdx.x == 0) a.big_list[atomicAdd(a.num_big_dev, 1u)] = w;
+        __syncthreads();
     }
 }
 
+// Lists the work chunks too large for every LDS instance.
+__global__ void k_list_big(WcArgs a, uint32_t max_lds)
+{
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < a.num_wc; w += gridDim.x * blockDim.x)
+        if (a.wc_count[w] > max_lds) a.big_list[atomicAdd(a.num_big_dev, 1u)] = w;
+}
+
+// Work chunks listed for the global-memory path (too large, or keys too
+// long): table and node scratch in a region of 4 slots (table) and 3 words
+// (nodes) per point of the work chunk, at its position range, so any number
+// of blocks can run.
 __global__ __launch_bounds__(P1_BLOCK) void k_subsample_big(WcArgs a)
 {
     __shared__ uint32_t red[P1_BLOCK / 64 + 1];
-    unsigned long long *hk = reinterpret_cast<unsigned long long *>(a.big_hkey) + (uint64_t)blockIdx.x * a.big_hash_cap;
-    uint32_t *hv = a.big_hval + (uint64_t)blockIdx.x * a.big_hash_cap;
-    for (uint32_t b = blockIdx.x; b < a.num_big; b += gridDim.x) {
+    __shared__ uint32_t counter[2];
+    const uint32_t nb = *a.num_big_dev;
+    for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
         const uint32_t w = a.big_list[b];
-        const uint32_t base = a.wc_begin[w];
-        const uint64_t N = a.wc_begin[a.num_wc - 1] + a.wc_count[a.num_wc - 1];
-        uint32_t *pmask = a.big_node + base;
-        uint32_t *pbase = a.big_node + N + base;
-        uint32_t *ncnt = a.big_node + 2 * N + base;
-        Items<true> it;
-        subsample_wc<true>(a, w, hk, hv, a.big_hash_cap - 1, pmask, pbase, ncnt, red, it);
+        const uint32_t base = a.wc_begin[w], n = a.wc_count[w];
+        uint64_t cap = 1;
+        while (cap * 2 <= 4ull * n) cap *= 2;
+        unsigned long long *hk = reinterpret_cast<unsigned long long *>(a.big_hkey) + 4ull * base;
+        uint32_t *hv = a.big_hval + 4ull * base;
+        subsample_wc<P1_BLOCK, 1, true>(a, w, nullptr, red, counter, a.big_node + 3ull * base, hk, hv, cap - 1);
     }
 }
 
@@ -1115,7 +1529,7 @@ void launch_bbox_init(DevBox *box, hipStream_t st) { hipLaunchKernelGGL(k_bbox_i
 void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, DevBox *box, hipStream_t st)
 {
     const int vec4 = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(z)) & 15) == 0;
-    hipLaunchKernelGGL(k_bbox, dim3(grid_for((n + 3) / 4, 256, 2048)), dim3(256), 0, st, x, y, z, n, vec4, box);
+    hipLaunchKernelGGL(k_bbox, dim3(grid_for((n + 3) / 4, 256, 1024)), dim3(256), 0, st, x, y, z, n, vec4, box);
 }
 
 void launch_setup(DevBox *box, int given, const float *lo, const float *hi, hipStream_t st)
@@ -1127,8 +1541,14 @@ void launch_quantize(const float *x, const float *y, const float *z, uint64_t n,
                      int count_outside, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw, hipStream_t st)
 {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_quantize, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, x, y, z, n, box, g, count_outside,
-                       code, fine_cnt, box_rw);
+    // contiguous ranges of at least 16 rounds per block, at most 2048 blocks
+    const uint64_t round = QZ_BLOCK * QZ_ITEMS;
+    uint64_t per = (n + 2047) / 2048;
+    if (per < 16 * round) per = 16 * round;
+    per = (per + round - 1) / round * round;
+    const uint32_t grid = (uint32_t)((n + per - 1) / per);
+    hipLaunchKernelGGL(k_quantize, dim3(grid), dim3(QZ_BLOCK), 0, st, x, y, z, n, box, g, count_outside, code,
+                       fine_cnt, box_rw, per);
 }
 
 void launch_pyramid(uint32_t *pyr, int g, hipStream_t st)
@@ -1158,31 +1578,33 @@ void launch_cut_table(const uint32_t *pyr, int lam, const uint32_t *flags, const
                        lev, t_level, t_key, t_count, t_start, thresh, over_flag);
 }
 
+void launch_cell_ids(const uint32_t *flags, uint32_t *excl_to_ids, uint64_t ncell, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cell_ids, dim3(grid_for(ncell, 256)), dim3(256), 0, st, flags, excl_to_ids, ncell);
+}
+
 void launch_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t st)
 {
     if (n == 0) return;
     hipLaunchKernelGGL(k_u32_to_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, in, out, n);
 }
 
-void launch_point_keys(const uint64_t *code, uint64_t n, int g, const uint32_t *flags_c, const uint32_t *excl_c,
-                       int lam_w, const uint32_t *flags_w, const uint32_t *excl_w, uint32_t *cid, uint32_t *wid,
-                       hipStream_t st)
-{
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_point_keys, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, code, n, g, flags_c, excl_c,
-                       lam_w, flags_w, excl_w, cid, wid);
-}
-
 void launch_subsample_small(const WcArgs &a, hipStream_t st)
 {
     if (a.num_wc == 0) return;
-    const uint32_t grid = a.num_wc < 2048 ? a.num_wc : 2048;
-    hipLaunchKernelGGL(k_subsample_small, dim3(grid), dim3(P1_BLOCK), 0, st, a);
+    // size classes: <= 2048 points (256 threads, 4 blocks per CU) and <= 4096
+    // points (512 threads, 2 blocks per CU); larger ones go to the BIG path
+    hipLaunchKernelGGL(k_list_big, dim3(grid_for(a.num_wc, 256)), dim3(256), 0, st, a, WC_CAP);
+    const uint32_t g1 = a.num_wc < 2048 ? a.num_wc : 2048;
+    hipLaunchKernelGGL((k_subsample_lds<256, 8>), dim3(g1), dim3(256), 0, st, a, 0u);
+    const uint32_t g2 = a.num_wc < 1024 ? a.num_wc : 1024;
+    hipLaunchKernelGGL((k_subsample_lds<512, 8>), dim3(g2), dim3(512), 0, st, a, 2048u);
 }
 
-void launch_subsample_big(const WcArgs &a, uint32_t grid, hipStream_t st)
+void launch_subsample_big(const WcArgs &a, hipStream_t st)
 {
-    if (a.num_big == 0) return;
+    if (a.num_wc == 0) return;
+    const uint32_t grid = a.num_wc < 256 ? a.num_wc : 256;
     hipLaunchKernelGGL(k_subsample_big, dim3(grid), dim3(P1_BLOCK), 0, st, a);
 }
 
