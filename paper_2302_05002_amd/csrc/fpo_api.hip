@@ -52,6 +52,9 @@ struct Ctrs {
     uint32_t preview_count;
     uint32_t oversized;
     uint32_t internal_error;
+    uint32_t wc_flags[2];      // [0] a work chunk spans several chunks, [1] a chunk holds too many
+    uint32_t prefix_end;       // node_points range of the nodes spanning several chunks
+    uint32_t prefix_nodes;
 };
 
 // Byte offsets of every region of the workspace for (n, params).
@@ -66,10 +69,10 @@ struct Plan {
     size_t n_depth, n_key, n_mask, n_begin, n_count, n_points, pv_index;
     // temporaries
     size_t code, pyr, fc, ec, lc, fw, ew, lw_, w_level, w_key, w_count, w_start, w_begin;
-    size_t c_count_scan, code_perm, wc_idx, wc_code, ms_temp, scan_temp;
+    size_t c_count_scan, code_perm, wc_src, wc_code, ms_temp, scan_temp, seg_b0, seg_nb, wc_nested, wc_chunk;
     size_t t, fr, shared_cnt, kd, loff, owned, node_base, lnode_key, lnode_mask, cut;
     size_t big_list, big_nr, big_node, big_hkey, big_hval;
-    size_t nid, sorted_nid, pv_tiles, pv_offs;
+    size_t nid, sorted_nid, fx_keys, fx_vals, pv_tiles, pv_offs;
     uint64_t pv_ntiles;
 };
 
@@ -123,10 +126,19 @@ Plan make_plan(uint64_t n, const fpo_params &p)
     P.w_begin = take(4 * P.maxW);
     P.c_count_scan = take(4 * P.maxC);
     P.code_perm = take(8 * nn);
-    P.wc_idx = take(4 * nn);
+    P.wc_src = take(4 * nn);
+    P.seg_b0 = take(4 * P.maxC);
+    P.seg_nb = take(4 * P.maxC);
+    P.wc_nested = take(P.maxW);
+    P.wc_chunk = take(4 * P.maxW);
     P.wc_code = take(8 * nn);
     // chunks, work chunks and nodes each number at most n
-    P.ms_temp = take(multisplit_temp_bound(nn, nn));
+    {
+        const size_t a = multisplit_temp_bound(nn, nn);
+        // segmented work-chunk scatter: count matrix bounded by n + #work chunks
+        const size_t b = multisplit_seg_temp_bytes(nn, (uint32_t)P.maxC, nn + P.maxW);
+        P.ms_temp = take(a > b ? a : b);
+    }
     uint64_t scan_max = P.G3 > (uint64_t)MAXD * P.maxW ? P.G3 : (uint64_t)MAXD * P.maxW;
     if (P.pv_ntiles > scan_max) scan_max = P.pv_ntiles;
     P.scan_temp = take(scan_temp_bytes(scan_max));
@@ -148,6 +160,8 @@ Plan make_plan(uint64_t n, const fpo_params &p)
     P.big_hval = take(4 * 4 * nn);
     P.nid = take(4 * nn);
     P.sorted_nid = take(4 * nn);
+    P.fx_keys = take(4 * nn);
+    P.fx_vals = take(4 * nn);
     P.pv_tiles = take(4 * P.pv_ntiles);
     P.pv_offs = take(4 * P.pv_ntiles);
     P.total = o;
@@ -374,6 +388,9 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     // cell -> chunk id and cell -> work-chunk id tables (in place of the scans)
     launch_cell_ids(U32(P.fc), U32(P.ec), P.G3, st);
     launch_cell_ids(U32(P.fw), U32(P.ew), P.W3, st);
+    launch_wc_chunks(&ctrs->num_wc, P.maxW, U64(P.w_key), U8(P.w_level), g, pyr, U32(P.ec), U8(P.c_level),
+                     &ctrs->num_chunks, P.maxC, U32(P.wc_chunk), U32(P.seg_b0), U32(P.seg_nb), U8(P.wc_nested),
+                     ctrs->wc_flags, st);
     JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
     JCHK(hipMemcpyAsync(hbox, box, sizeof(DevBox), hipMemcpyDeviceToHost, st));
     JCHK(hipStreamSynchronize(st));
@@ -400,16 +417,30 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
         o.pay = U64(P.code_perm);
         multisplit(in, n, num_chunks, o, ws + P.ms_temp, st);
     }
+    // work-chunk order from perm order: chunk by chunk when every work chunk
+    // lies inside one chunk (one pass, few buckets per chunk), else globally
     {
         MsInput in;
-        in.code = U64(P.code);
+        in.code = U64(P.code_perm);
         in.table = U32(P.ew);
         in.code_shift = 3 * (KB - P.lam_w);
-        in.pay = U64(P.code);
+        in.pay = U64(P.code_perm);
         MsOutput o;
-        o.vals = U32(P.wc_idx);
         o.pay = U64(P.wc_code);
-        multisplit(in, n, num_wc, o, ws + P.ms_temp, st);
+        if (hctrs->wc_flags[0] == 0 && hctrs->wc_flags[1] == 0) {
+            MsSegments sg;
+            sg.nseg = num_chunks;
+            sg.begin = U32(P.c_count_scan);
+            sg.len = U32(P.c_count);
+            sg.b0 = U32(P.seg_b0);
+            sg.nb = U32(P.seg_nb);
+            sg.max_cells = n + num_wc;
+            o.src = U32(P.wc_src);
+            multisplit_segmented(in, n, sg, (n + MS_TILE - 1) / MS_TILE + num_chunks, o, ws + P.ms_temp, st);
+        } else {
+            o.vals = U32(P.wc_src);   // values = perm positions
+            multisplit(in, n, num_wc, o, ws + P.ms_temp, st);
+        }
     }
 
     // ---- step 4: subsample ----
@@ -420,7 +451,9 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     A.wc_level = U8(P.w_level);
     A.wc_key = U64(P.w_key);
     A.wc_start = U64(P.w_start);
-    A.wc_idx = U32(P.wc_idx);
+    A.wc_src = U32(P.wc_src);
+    A.perm = U32(P.perm);
+    A.wc_nested = U8(P.wc_nested);
     A.wc_code = U64(P.wc_code);
     A.t = U8(P.t);
     A.fr = U32(P.fr);
@@ -453,15 +486,45 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     launch_node_ids(A, U32(P.node_base), U32(P.nid), &ctrs->internal_error, st);
     JCHK(hipMemsetAsync(U8(P.n_mask), 0, (num_nodes + 3) & ~3u, st));
     launch_node_fill(A, U32(P.node_base), U8(P.n_depth), U64(P.n_key), U8(P.n_mask), st);
+    // node_points: node by node from perm order (chunk by chunk, ascending
+    // index inside a chunk), which is already the final order for every node
+    // inside one chunk
     {
         MsInput in;
         in.keys = U32(P.nid);
+        in.vals = U32(P.perm);
         MsOutput o;
         o.vals = U32(P.n_points);
         o.keys = U32(P.sorted_nid);
         multisplit(in, n, num_nodes, o, ws + P.ms_temp, st);
     }
     launch_node_ranges(U32(P.sorted_nid), n, U64(P.n_begin), U32(P.n_count), num_nodes, st);
+    // nodes spanning several chunks hold their points chunk by chunk: sort
+    // that prefix of node_points by (node, original index)
+    launch_above_chunk(num_nodes, U8(P.n_depth), U64(P.n_begin), U32(P.n_count), U32(P.n_points), U64(P.code), g,
+                       U32(P.ec), U8(P.c_level), &ctrs->prefix_end, &ctrs->prefix_nodes, st);
+    JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
+    JCHK(hipStreamSynchronize(st));
+    if (hctrs->prefix_end > 0) {
+        const uint64_t F = hctrs->prefix_end;
+        {
+            MsInput in;
+            in.keys = U32(P.n_points);     // original indices: sort by them first
+            in.vals = U32(P.sorted_nid);   // node ids ride along
+            MsOutput o;
+            o.keys = U32(P.fx_keys);
+            o.vals = U32(P.fx_vals);
+            multisplit(in, F, (uint32_t)n, o, ws + P.ms_temp, st);
+        }
+        {
+            MsInput in;
+            in.keys = U32(P.fx_vals);      // then stably by node
+            in.vals = U32(P.fx_keys);
+            MsOutput o;
+            o.vals = U32(P.n_points);
+            multisplit(in, F, hctrs->prefix_nodes, o, ws + P.ms_temp, st);
+        }
+    }
 
     JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
     JCHK(hipMemcpyAsync(hbox, box, sizeof(DevBox), hipMemcpyDeviceToHost, st));

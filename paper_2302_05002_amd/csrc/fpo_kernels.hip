@@ -1036,8 +1036,7 @@ struct Items<BLOCK, ITEMS, true> {
 // registers; one LDS region of 3 * CAP words holds the node scratch (parent
 // masks, child bases, node counts) and then the cell table (2 * CAP packed
 // 32-bit entries).  BIG path: per-position state, node scratch and the cell table in
-// global memory; winners are decided on positions too, which are in original
-// index order inside a work chunk.  Returns false (LDS path only) when the
+// global memory; winners are decided on original indices.  Returns false (LDS path only) when the
 // relative cell keys outgrow the packed entries: the chunk is then redone by
 // the BIG path.
 template <int BLOCK, int ITEMS, bool BIG>
@@ -1165,9 +1164,11 @@ __device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint
         __syncthreads();
         uint32_t survive = 0;
         if constexpr (BIG) {
+            // winners by original index: a work chunk spanning several chunks
+            // is not in index order
             it.each([&](uint32_t pos, uint64_t c, uint32_t &st, uint32_t &, uint32_t &) {
                 if (st != ST_INNER) return;
-                hash_insert_min(ghk, ghv, gmask, (c >> csh) & rel_mask, pos);
+                hash_insert_min(ghk, ghv, gmask, (c >> csh) & rel_mask, a.perm[a.wc_src[base + pos]]);
             });
             __syncthreads();
             it.each([&](uint32_t pos, uint64_t c, uint32_t &st, uint32_t &r, uint32_t &f) {
@@ -1175,7 +1176,7 @@ __device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint
                     st = (uint32_t)d;
                     f = r;
                 } else if (st == ST_INNER) {
-                    if (hash_lookup(ghk, ghv, gmask, (c >> csh) & rel_mask) == pos) {
+                    if (hash_lookup(ghk, ghv, gmask, (c >> csh) & rel_mask) == a.perm[a.wc_src[base + pos]]) {
                         st = (uint32_t)d;
                         f = r;
                     } else {
@@ -1272,18 +1273,19 @@ __global__ __launch_bounds__(BLOCK) void k_subsample_lds(WcArgs a, uint32_t min_
     __shared__ uint32_t counter[2];
     for (uint32_t w = blockIdx.x; w < a.num_wc; w += gridDim.x) {
         const uint32_t n = a.wc_count[w];
-        if (n <= min_n || n > CAP) continue;
+        if (n <= min_n || n > CAP || !a.wc_nested[w]) continue;
         const bool ok = subsample_wc<BLOCK, ITEMS, false>(a, w, region, red, counter, nullptr, nullptr, nullptr, 0);
         if (!ok && threadIdx.x == 0) a.big_list[atomicAdd(a.num_big_dev, 1u)] = w;
         __syncthreads();
     }
 }
 
-// Lists the work chunks too large for every LDS instance.
+// Lists the work chunks too large for every LDS instance, and those spanning
+// several chunks (their positions are not in original index order).
 __global__ void k_list_big(WcArgs a, uint32_t max_lds)
 {
     for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < a.num_wc; w += gridDim.x * blockDim.x)
-        if (a.wc_count[w] > max_lds) a.big_list[atomicAdd(a.num_big_dev, 1u)] = w;
+        if (a.wc_count[w] > max_lds || !a.wc_nested[w]) a.big_list[atomicAdd(a.num_big_dev, 1u)] = w;
 }
 
 // Work chunks listed for the global-memory path (too large, or keys too
@@ -1363,8 +1365,9 @@ __global__ void k_node_counts(WcArgs a, uint32_t *owned)
     }
 }
 
-// Node id of every point, written at its original index.
-__global__ __launch_bounds__(256) void k_node_ids(WcArgs a, const uint32_t *node_base, uint32_t *nid_by_idx,
+// Node id of every point, written at its perm position (perm positions of a
+// work chunk lie inside its chunk, so the writes stay local).
+__global__ __launch_bounds__(256) void k_node_ids(WcArgs a, const uint32_t *node_base, uint32_t *nid_perm,
                                                   uint32_t *err)
 {
     __shared__ uint32_t own_id[MAXD];
@@ -1380,17 +1383,84 @@ __global__ __launch_bounds__(256) void k_node_ids(WcArgs a, const uint32_t *node
         for (uint32_t pos = threadIdx.x; pos < n; pos += blockDim.x) {
             int t = a.t[base + pos];
             uint32_t id;
-            if (t >= MAXD) {  // never finalised: an internal error, reported to the host
+            if (t >= MAXD) {  // never placed: an internal error, reported to the host
                 atomicOr(err, 1u);
-                nid_by_idx[a.wc_idx[base + pos]] = 0;
+                nid_perm[a.wc_src[base + pos]] = 0;
                 continue;
             }
             if (cut < lw && t >= cut) t = cut;
             if (t < lw) id = own_id[t];
             else id = node_base[(uint64_t)t * a.num_wc + w] + a.fr[base + pos];
-            nid_by_idx[a.wc_idx[base + pos]] = id;
+            nid_perm[a.wc_src[base + pos]] = id;
         }
         __syncthreads();
+    }
+}
+
+// Chunk of every work chunk: the chunk holding the first occupied finest cell
+// of the work chunk (found by descending the count pyramid; an occupied cell
+// always lies inside a chunk).
+__global__ void k_wc_chunks(const uint32_t *num_wc_dev, const uint64_t *wc_key, const uint8_t *wc_level, int g,
+                            const uint32_t *pyr, const uint32_t *cid_table, const uint8_t *chunk_level,
+                            uint32_t *wc_chunk, uint8_t *wc_nested, uint32_t *flags)
+{
+    const uint32_t num_wc = *num_wc_dev;
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < num_wc; w += gridDim.x * blockDim.x) {
+        uint64_t m = wc_key[w];
+        for (int l = wc_level[w]; l < g; ++l) {
+            const uint32_t *ch = pyr + pyr_off(l + 1) + (m << 3);
+            uint32_t o = 0;
+            while (o < 7 && ch[o] == 0) ++o;   // the work chunk holds a point, so some child does
+            m = (m << 3) | o;
+        }
+        const uint32_t c = cid_table[m];
+        wc_chunk[w] = c;
+        const bool nested = chunk_level[c] <= wc_level[w];
+        wc_nested[w] = nested ? 1 : 0;
+        if (!nested) atomicOr(&flags[0], 1u);
+    }
+}
+
+// Work-chunk range of every chunk (work chunks inside one chunk are
+// consecutive in Morton order).
+__global__ void k_wc_segs(const uint32_t *num_wc_dev, const uint32_t *wc_chunk, uint32_t *seg_b0, uint32_t *seg_end)
+{
+    const uint32_t num_wc = *num_wc_dev;
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < num_wc; w += gridDim.x * blockDim.x) {
+        const uint32_t c = wc_chunk[w];
+        if (w == 0 || wc_chunk[w - 1] != c) seg_b0[c] = w;
+        if (w + 1 == num_wc || wc_chunk[w + 1] != c) seg_end[c] = w + 1;
+    }
+}
+
+__global__ void k_wc_chunks_nb(const uint32_t *num_chunks_dev, const uint32_t *seg_b0, uint32_t *seg_end_to_nb,
+                               uint32_t *flags)
+{
+    const uint32_t num_chunks = *num_chunks_dev;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < num_chunks; c += gridDim.x * blockDim.x) {
+        const uint32_t nb = seg_end_to_nb[c] - seg_b0[c];
+        seg_end_to_nb[c] = nb;
+        if (nb > MS_MAX_BINS) atomicOr(&flags[1], 1u);
+    }
+}
+
+// Nodes whose points lie in more than one chunk: depth below the level of the
+// chunk holding the node's first point (a node at depth >= g lies inside one
+// finest cell, so inside one chunk).
+__global__ void k_above_chunk(uint32_t num_nodes, const uint8_t *node_depth, const uint64_t *node_begin,
+                              const uint32_t *node_count, const uint32_t *node_points, const uint64_t *code, int g,
+                              const uint32_t *cid_table, const uint8_t *chunk_level, uint32_t *prefix_end,
+                              uint32_t *prefix_nodes)
+{
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < num_nodes; k += gridDim.x * blockDim.x) {
+        const int d = node_depth[k];
+        if (d >= g) continue;
+        const uint32_t first = node_points[node_begin[k]];
+        const uint32_t c = cid_table[code[first] >> (3 * (KB - g))];
+        if (chunk_level[c] > d) {
+            atomicMax(prefix_end, (uint32_t)(node_begin[k] + node_count[k]));
+            atomicMax(prefix_nodes, k + 1);
+        }
     }
 }
 
@@ -1618,10 +1688,32 @@ void launch_node_counts(const WcArgs &a, uint32_t *owned, hipStream_t st)
     hipLaunchKernelGGL(k_node_counts, dim3(grid_for((uint64_t)MAXD * a.num_wc, 256)), dim3(256), 0, st, a, owned);
 }
 
-void launch_node_ids(const WcArgs &a, const uint32_t *node_base, uint32_t *nid_by_idx, uint32_t *err, hipStream_t st)
+void launch_node_ids(const WcArgs &a, const uint32_t *node_base, uint32_t *nid_perm, uint32_t *err, hipStream_t st)
 {
     const uint32_t grid = a.num_wc < 4096 ? a.num_wc : 4096;
-    hipLaunchKernelGGL(k_node_ids, dim3(grid), dim3(256), 0, st, a, node_base, nid_by_idx, err);
+    hipLaunchKernelGGL(k_node_ids, dim3(grid), dim3(256), 0, st, a, node_base, nid_perm, err);
+}
+
+void launch_wc_chunks(const uint32_t *num_wc_dev, uint64_t max_wc, const uint64_t *wc_key, const uint8_t *wc_level,
+                      int g, const uint32_t *pyr, const uint32_t *cid_table, const uint8_t *chunk_level,
+                      const uint32_t *num_chunks_dev, uint64_t max_chunks, uint32_t *wc_chunk, uint32_t *seg_b0,
+                      uint32_t *seg_nb, uint8_t *wc_nested, uint32_t *flags, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_wc_chunks, dim3(grid_for(max_wc, 256)), dim3(256), 0, st, num_wc_dev, wc_key, wc_level, g, pyr,
+                       cid_table, chunk_level, wc_chunk, wc_nested, flags);
+    hipLaunchKernelGGL(k_wc_segs, dim3(grid_for(max_wc, 256)), dim3(256), 0, st, num_wc_dev, wc_chunk, seg_b0, seg_nb);
+    hipLaunchKernelGGL(k_wc_chunks_nb, dim3(grid_for(max_chunks, 256)), dim3(256), 0, st, num_chunks_dev, seg_b0, seg_nb,
+                       flags);
+}
+
+void launch_above_chunk(uint32_t num_nodes, const uint8_t *node_depth, const uint64_t *node_begin,
+                        const uint32_t *node_count, const uint32_t *node_points, const uint64_t *code, int g,
+                        const uint32_t *cid_table, const uint8_t *chunk_level, uint32_t *prefix_end,
+                        uint32_t *prefix_nodes, hipStream_t st)
+{
+    if (num_nodes == 0) return;
+    hipLaunchKernelGGL(k_above_chunk, dim3(grid_for(num_nodes, 256)), dim3(256), 0, st, num_nodes, node_depth, node_begin,
+                       node_count, node_points, code, g, cid_table, chunk_level, prefix_end, prefix_nodes);
 }
 
 void launch_node_fill(const WcArgs &a, const uint32_t *node_base, uint8_t *depth, uint64_t *key, uint8_t *mask,
