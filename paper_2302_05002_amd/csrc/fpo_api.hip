@@ -65,7 +65,7 @@ struct Plan {
     uint64_t maxC, maxW;
     size_t total;
     // results
-    size_t box, ctrs, grid, c_level, c_key, c_count, c_begin, perm;
+    size_t box, bbox_part, ctrs, grid, c_level, c_key, c_count, c_begin, perm;
     size_t n_depth, n_key, n_mask, n_begin, n_count, n_points, pv_index;
     // temporaries
     size_t code, pyr, fc, ec, lc, fw, ew, lw_, w_level, w_key, w_count, w_start, w_begin;
@@ -97,6 +97,7 @@ Plan make_plan(uint64_t n, const fpo_params &p)
         return r;
     };
     P.box = take(sizeof(DevBox));
+    P.bbox_part = take(8 * 4 * BBOX_MAX_BLOCKS);
     P.ctrs = take(sizeof(Ctrs));
     P.grid = take(4 * P.G3);
     P.c_level = take(P.maxC);
@@ -347,9 +348,9 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
         }                                                                                       \
     } while (0)
 
-    JCHK(hipMemsetAsync(ctrs, 0, sizeof(Ctrs), st));
+    launch_fill_u32(reinterpret_cast<uint32_t *>(ctrs), 0u, sizeof(Ctrs) / 4, st);
     if (n == 0) {
-        JCHK(hipMemsetAsync(U32(P.grid), 0, 4 * P.G3, st));
+        launch_fill_u32(U32(P.grid), 0u, P.G3, st);
         JCHK(hipEventRecord(job->ev_preview, st));
         JCHK(hipEventRecord(job->ev_done, st));
         if (p->flags & FPO_BBOX_GIVEN)
@@ -366,12 +367,13 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
 
     // ---- step 1: bbox, quantise, count ----
     const int given = (p->flags & FPO_BBOX_GIVEN) ? 1 : 0;
-    launch_bbox_init(box, st);
-    launch_bbox(cloud->x, cloud->y, cloud->z, n, box, st);  // also detects non-finite values
-    launch_setup(box, given, p->bbox_min, p->bbox_max, st);
+    // the scan runs with a given box too: it also detects non-finite values
+    const uint32_t nparts = bbox_blocks(n);
+    launch_bbox(cloud->x, cloud->y, cloud->z, n, U32(P.bbox_part), st);
+    launch_setup(box, U32(P.bbox_part), nparts, given, p->bbox_min, p->bbox_max, st);
     uint32_t *pyr = U32(P.pyr);
     uint32_t *fine = pyr + pyr_off(g);
-    JCHK(hipMemsetAsync(fine, 0, 4 * P.G3, st));
+    launch_fill_u32(fine, 0u, P.G3, st);
     launch_quantize(cloud->x, cloud->y, cloud->z, n, box, g, given, U64(P.code), fine, box, st);
 
     // ---- step 2: pyramid, chunk cut, work-chunk cut ----
@@ -473,8 +475,8 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     A.s = s_;
     A.L = p->leaf_capacity;
     A.dmax = KB - s_;
-    if (g > 0) JCHK(hipMemsetAsync(U32(P.shared_cnt), 0, 4 * pyr_off(g), st));
-    JCHK(hipMemsetAsync(U32(P.kd), 0, 4ull * MAXD * num_wc, st));
+    if (g > 0) launch_fill_u32(U32(P.shared_cnt), 0u, pyr_off(g), st);
+    launch_fill_u32(U32(P.kd), 0u, (uint64_t)MAXD * num_wc, st);
     launch_subsample_small(A, st);
     launch_subsample_big(A, st);
     launch_decide(A, st);
@@ -484,7 +486,7 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     JCHK(hipStreamSynchronize(st));
     const uint32_t num_nodes = hctrs->num_nodes;
     launch_node_ids(A, U32(P.node_base), U32(P.nid), &ctrs->internal_error, st);
-    JCHK(hipMemsetAsync(U8(P.n_mask), 0, (num_nodes + 3) & ~3u, st));
+    launch_fill_u32(U32(P.n_mask), 0u, (num_nodes + 3) / 4, st);
     launch_node_fill(A, U32(P.node_base), U8(P.n_depth), U64(P.n_key), U8(P.n_mask), st);
     // node_points: node by node from perm order (chunk by chunk, ascending
     // index inside a chunk), which is already the final order for every node

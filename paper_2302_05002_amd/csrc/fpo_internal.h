@@ -35,9 +35,7 @@ struct DevBox {
     float hi[3];
     float size;
     float scale;
-    uint32_t omin[3];    // order-preserving integer encodings (bbox reduction)
-    uint32_t omax[3];
-    uint32_t nonfinite;
+    uint32_t nonfinite;  // some coordinate is NaN or infinite
     uint32_t pad;
     unsigned long long n_outside;
 };
@@ -46,9 +44,16 @@ struct DevBox {
 __host__ __device__ inline uint64_t pyr_off(int l) { return ((1ull << (3 * l)) - 1ull) / 7ull; }
 
 // ---- launchers (fpo_kernels.hip) -------------------------------------------
-void launch_bbox_init(DevBox *box, hipStream_t st);
-void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, DevBox *box, hipStream_t st);
-void launch_setup(DevBox *box, int given, const float *lo, const float *hi, hipStream_t st);
+// Fill kernel (in place of hipMemsetAsync, which costs far more host time per
+// call and is not safe to record in a graph).
+void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t words, hipStream_t st);
+// Bounding box: per-block partials (8 words each: 3 min, 3 max in an
+// order-preserving integer encoding, a non-finite flag), reduced by k_setup.
+constexpr uint32_t BBOX_MAX_BLOCKS = 4096;
+uint32_t bbox_blocks(uint64_t n);
+void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, uint32_t *part, hipStream_t st);
+void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given, const float *lo, const float *hi,
+                  hipStream_t st);
 void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box,
                      int g, int count_outside, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw,
                      hipStream_t st);

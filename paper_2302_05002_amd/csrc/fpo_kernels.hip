@@ -144,44 +144,59 @@ static inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b
 
 // ---- step 1a: bounding box ------------------------------------------------------
 
-__global__ void k_bbox_init(DevBox *box)
+// Branch-free accumulation; each thread keeps two float4 loads per axis in
+// flight.
+__device__ __forceinline__ void bbox_acc(uint32_t &mn, uint32_t &mx, uint32_t &bad, float e)
 {
-    if (threadIdx.x == 0) {
-        for (int a = 0; a < 3; ++a) {
-            box->omin[a] = 0xffffffffu;
-            box->omax[a] = 0u;
-        }
-        box->nonfinite = 0;
-        box->n_outside = 0;
-    }
+    const bool fin = isfinite(e);
+    const uint32_t o = f2o(e);
+    mn = min(mn, fin ? o : 0xffffffffu);
+    mx = max(mx, fin ? o : 0u);
+    bad |= fin ? 0u : 1u;
 }
 
 __global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ x, const float *__restrict__ y,
-                                              const float *__restrict__ z, uint64_t n, int vec4, DevBox *box)
+                                              const float *__restrict__ z, uint64_t n, int vec4, uint32_t *part)
 {
     uint32_t mn[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[3] = {0u, 0u, 0u};
     uint32_t bad = 0;
     const uint64_t n4 = vec4 ? n / 4 : 0;   // float4 loads only on 16-byte aligned inputs
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const float4 *p4[3] = {reinterpret_cast<const float4 *>(x), reinterpret_cast<const float4 *>(y),
-                           reinterpret_cast<const float4 *>(z)};
-    auto acc = [&](int a, float e) {
-        if (!isfinite(e)) { bad = 1; return; }
-        const uint32_t o = f2o(e);
-        mn[a] = min(mn[a], o);
-        mx[a] = max(mx[a], o);
-    };
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
-        const float4 vx = p4[0][i], vy = p4[1][i], vz = p4[2][i];   // three loads in flight
-        acc(0, vx.x); acc(0, vx.y); acc(0, vx.z); acc(0, vx.w);
-        acc(1, vy.x); acc(1, vy.y); acc(1, vy.z); acc(1, vy.w);
-        acc(2, vz.x); acc(2, vz.y); acc(2, vz.z); acc(2, vz.w);
+    const float4 *px = reinterpret_cast<const float4 *>(x), *py = reinterpret_cast<const float4 *>(y),
+                 *pz = reinterpret_cast<const float4 *>(z);
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + stride < n4; i += 2 * stride) {
+        const float4 a0 = px[i], b0 = py[i], c0 = pz[i];
+        const float4 a1 = px[i + stride], b1 = py[i + stride], c1 = pz[i + stride];
+        bbox_acc(mn[0], mx[0], bad, a0.x); bbox_acc(mn[0], mx[0], bad, a0.y);
+        bbox_acc(mn[0], mx[0], bad, a0.z); bbox_acc(mn[0], mx[0], bad, a0.w);
+        bbox_acc(mn[1], mx[1], bad, b0.x); bbox_acc(mn[1], mx[1], bad, b0.y);
+        bbox_acc(mn[1], mx[1], bad, b0.z); bbox_acc(mn[1], mx[1], bad, b0.w);
+        bbox_acc(mn[2], mx[2], bad, c0.x); bbox_acc(mn[2], mx[2], bad, c0.y);
+        bbox_acc(mn[2], mx[2], bad, c0.z); bbox_acc(mn[2], mx[2], bad, c0.w);
+        bbox_acc(mn[0], mx[0], bad, a1.x); bbox_acc(mn[0], mx[0], bad, a1.y);
+        bbox_acc(mn[0], mx[0], bad, a1.z); bbox_acc(mn[0], mx[0], bad, a1.w);
+        bbox_acc(mn[1], mx[1], bad, b1.x); bbox_acc(mn[1], mx[1], bad, b1.y);
+        bbox_acc(mn[1], mx[1], bad, b1.z); bbox_acc(mn[1], mx[1], bad, b1.w);
+        bbox_acc(mn[2], mx[2], bad, c1.x); bbox_acc(mn[2], mx[2], bad, c1.y);
+        bbox_acc(mn[2], mx[2], bad, c1.z); bbox_acc(mn[2], mx[2], bad, c1.w);
     }
-    for (uint64_t i = n4 * 4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        acc(0, x[i]);
-        acc(1, y[i]);
-        acc(2, z[i]);
+    for (; i < n4; i += stride) {
+        const float4 a0 = px[i], b0 = py[i], c0 = pz[i];
+        bbox_acc(mn[0], mx[0], bad, a0.x); bbox_acc(mn[0], mx[0], bad, a0.y);
+        bbox_acc(mn[0], mx[0], bad, a0.z); bbox_acc(mn[0], mx[0], bad, a0.w);
+        bbox_acc(mn[1], mx[1], bad, b0.x); bbox_acc(mn[1], mx[1], bad, b0.y);
+        bbox_acc(mn[1], mx[1], bad, b0.z); bbox_acc(mn[1], mx[1], bad, b0.w);
+        bbox_acc(mn[2], mx[2], bad, c0.x); bbox_acc(mn[2], mx[2], bad, c0.y);
+        bbox_acc(mn[2], mx[2], bad, c0.z); bbox_acc(mn[2], mx[2], bad, c0.w);
     }
+    for (uint64_t j = n4 * 4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        bbox_acc(mn[0], mx[0], bad, x[j]);
+        bbox_acc(mn[1], mx[1], bad, y[j]);
+        bbox_acc(mn[2], mx[2], bad, z[j]);
+    }
+    // per-block partial box (same-address global atomics from every block
+    // would serialise); k_setup reduces the partials
     __shared__ uint32_t s[7][4];
     const int w = threadIdx.x >> 6;
     for (int a = 0; a < 3; ++a) {
@@ -196,22 +211,42 @@ __global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ x, const
     const uint64_t anybad = __ballot(bad != 0);
     if (lane_id() == 0) s[6][w] = anybad ? 1u : 0u;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int a = 0; a < 3; ++a) {
-            uint32_t v = s[a][0], u = s[3 + a][0];
-            for (int i = 1; i < 4; ++i) { v = min(v, s[a][i]); u = max(u, s[3 + a][i]); }
-            if (v != 0xffffffffu) atomicMin(&box->omin[a], v);
-            if (u != 0u) atomicMax(&box->omax[a], u);
-        }
-        if (s[6][0] | s[6][1] | s[6][2] | s[6][3]) atomicOr(&box->nonfinite, 1u);
+    if (threadIdx.x < 7) {
+        const int a = threadIdx.x;
+        uint32_t v = s[a][0];
+        for (int k = 1; k < 4; ++k) v = a < 3 ? min(v, s[a][k]) : (a < 6 ? max(v, s[a][k]) : (v | s[a][k]));
+        part[(uint64_t)blockIdx.x * 8 + a] = v;
     }
 }
 
-// Cube anchored at the box minimum, side = largest extent, scale = 2^21/side
-// computed in double and rounded once to float (0 for a zero side).
-__global__ void k_setup(DevBox *box, int given, float gx0, float gy0, float gz0, float gx1, float gy1, float gz1)
+// Reduces the per-block partial boxes (nparts of them), then, unless the box
+// is given: cube anchored at the box minimum, side = largest extent,
+// scale = 2^21/side computed in double and rounded once to float (0 for a
+// zero side).
+__global__ __launch_bounds__(256) void k_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given, float gx0,
+                                               float gy0, float gz0, float gx1, float gy1, float gz1)
 {
+    __shared__ uint32_t red[7][256];
+    uint32_t v[7] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u, 0u};
+    for (uint32_t b = threadIdx.x; b < nparts; b += 256) {
+        for (int a = 0; a < 3; ++a) {
+            v[a] = min(v[a], part[(uint64_t)b * 8 + a]);
+            v[3 + a] = max(v[3 + a], part[(uint64_t)b * 8 + 3 + a]);
+        }
+        v[6] |= part[(uint64_t)b * 8 + 6];
+    }
+    for (int a = 0; a < 7; ++a) red[a][threadIdx.x] = v[a];
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    for (uint32_t t = 1; t < 256; ++t) {
+        for (int a = 0; a < 3; ++a) {
+            v[a] = min(v[a], red[a][t]);
+            v[3 + a] = max(v[3 + a], red[3 + a][t]);
+        }
+        v[6] |= red[6][t];
+    }
+    box->nonfinite = v[6];
+    box->n_outside = 0;
     float lo[3], hi[3];
     if (given) {
         lo[0] = gx0; lo[1] = gy0; lo[2] = gz0;
@@ -220,8 +255,8 @@ __global__ void k_setup(DevBox *box, int given, float gx0, float gy0, float gz0,
         for (int a = 0; a < 3; ++a) {
             // +0.0f turns a -0.0 extreme into +0.0 (the two compare equal, so
             // which one a reduction meets first must not show in the result)
-            lo[a] = __fadd_rn(o2f(box->omin[a]), 0.0f);
-            hi[a] = __fadd_rn(o2f(box->omax[a]), 0.0f);
+            lo[a] = __fadd_rn(o2f(v[a]), 0.0f);
+            hi[a] = __fadd_rn(o2f(v[3 + a]), 0.0f);
         }
     }
     float side = 0.0f;
@@ -499,7 +534,7 @@ size_t scan_temp_bytes(uint64_t n)
 void scan_exclusive(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total, void *temp, hipStream_t st)
 {
     if (n == 0) {
-        if (total) (void)hipMemsetAsync(total, 0, 4, st);
+        if (total) launch_fill_u32(total, 0u, 1, st);
         return;
     }
     const uint32_t tiles = div_up(n, SCAN_TILE);
@@ -585,6 +620,9 @@ __device__ __forceinline__ MsTile ms_tile(const MsArgs &A, uint32_t t)
     return T;
 }
 
+// Count pass: equal keys of a wave round are grouped by a ballot match and
+// added once (consecutive points usually share their chunk), so LDS atomics
+// do not pile up on one counter.
 template <bool SEG>
 __global__ __launch_bounds__(MS_BLOCK) void k_ms_count(MsArgs A)
 {
@@ -594,8 +632,15 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_count(MsArgs A)
     for (uint32_t b = threadIdx.x; b < T.nb; b += MS_BLOCK) hist[b] = 0;
     __syncthreads();
     const uint32_t dmask = (1u << A.dbits) - 1u;
-    for (uint64_t e = T.lo + threadIdx.x; e < T.hi; e += MS_BLOCK)
-        atomicAdd(&hist[((ms_key(A, e) >> A.shift) & dmask) - T.b0], 1u);
+    const int nbits = (int)ceil_log2_dev(T.nb);
+    const int lane = lane_id();
+    for (uint64_t e0 = T.lo + (threadIdx.x & ~63u); e0 < T.hi; e0 += MS_BLOCK) {
+        const uint64_t e = e0 + lane;
+        const bool valid = e < T.hi;
+        const uint32_t key = valid ? ((ms_key(A, e) >> A.shift) & dmask) - T.b0 : 0u;
+        const uint64_t peers = match_peers(key, valid, nbits);
+        if (valid && (peers & ((1ull << lane) - 1ull)) == 0) atomicAdd(&hist[key], (uint32_t)__popcll(peers));
+    }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < T.nb; b += MS_BLOCK)
         A.counts[(uint64_t)T.mat + (uint64_t)b * T.ntile + T.tis] = hist[b];
@@ -1594,17 +1639,31 @@ static uint32_t grid_for(uint64_t n, uint32_t block, uint32_t cap = 4096)
     return (uint32_t)g;
 }
 
-void launch_bbox_init(DevBox *box, hipStream_t st) { hipLaunchKernelGGL(k_bbox_init, dim3(1), dim3(64), 0, st, box); }
-
-void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, DevBox *box, hipStream_t st)
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t words)
 {
-    const int vec4 = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(z)) & 15) == 0;
-    hipLaunchKernelGGL(k_bbox, dim3(grid_for((n + 3) / 4, 256, 1024)), dim3(256), 0, st, x, y, z, n, vec4, box);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
-void launch_setup(DevBox *box, int given, const float *lo, const float *hi, hipStream_t st)
+void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t words, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, box, given, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]);
+    if (words == 0) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(words, 256, 2048)), dim3(256), 0, st, p, v, words);
+}
+
+uint32_t bbox_blocks(uint64_t n) { return grid_for((n + 3) / 4, 256, BBOX_MAX_BLOCKS); }
+
+void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, uint32_t *part, hipStream_t st)
+{
+    const int vec4 = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(z)) & 15) == 0;
+    hipLaunchKernelGGL(k_bbox, dim3(bbox_blocks(n)), dim3(256), 0, st, x, y, z, n, vec4, part);
+}
+
+void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given, const float *lo, const float *hi,
+                  hipStream_t st)
+{
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, box, part, nparts, given, lo[0], lo[1], lo[2], hi[0], hi[1],
+                       hi[2]);
 }
 
 void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box, int g,
