@@ -284,9 +284,10 @@ __device__ __forceinline__ uint32_t quantize1(float a, float lo, float scale)
 // block first aggregates the cells of its contiguous range of points in an
 // LDS hash table and flushes one atomic per distinct cell: scans emit points
 // surface by surface, so a range touches far fewer cells than it has points.
-constexpr int QZ_BLOCK = 256;
+constexpr int QZ_BLOCK = 1024;
 constexpr int QZ_ITEMS = 4;
-constexpr uint32_t QZ_HASH = 8192;   // slots; flushed when half full
+constexpr uint32_t QZ_ROUND = QZ_BLOCK * QZ_ITEMS;
+constexpr uint32_t QZ_HASH = 16384;   // slots (128 KB of LDS with the counts); kept at most half full
 
 __device__ __forceinline__ uint32_t hash32(uint32_t k)
 {
@@ -310,6 +311,9 @@ __device__ void qz_flush(uint32_t *hk, uint32_t *hc, uint32_t *fine)
     }
 }
 
+// One block per compute unit, each over a contiguous range of points.  The
+// coordinates of the next round are loaded before the hash updates of the
+// current one, so the loads stay in flight while the LDS work runs.
 __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__ x, const float *__restrict__ y,
                                                        const float *__restrict__ z, uint64_t n, const DevBox *box,
                                                        int g, int count_outside, uint64_t *__restrict__ code,
@@ -318,6 +322,17 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
     __shared__ uint32_t hk[QZ_HASH];
     __shared__ uint32_t hc[QZ_HASH];
     __shared__ uint32_t used;
+    __shared__ uint32_t wsum[QZ_BLOCK / 64];
+    const uint64_t lo = (uint64_t)blockIdx.x * per_block;
+    const uint64_t hi = lo + per_block < n ? lo + per_block : n;
+    float px[QZ_ITEMS], py[QZ_ITEMS], pz[QZ_ITEMS];
+#pragma unroll
+    for (int j = 0; j < QZ_ITEMS; ++j) {
+        const uint64_t i = lo + (uint64_t)j * QZ_BLOCK + threadIdx.x;
+        px[j] = i < hi ? x[i] : 0.0f;
+        py[j] = i < hi ? y[i] : 0.0f;
+        pz[j] = i < hi ? z[i] : 0.0f;
+    }
     const float lx = box->lo[0], ly = box->lo[1], lz = box->lo[2], sc = box->scale;
     const float hx = box->hi[0], hy = box->hi[1], hz = box->hi[2];
     const int sh = 3 * (KB - g);
@@ -328,41 +343,51 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
     if (threadIdx.x == 0) used = 0;
     __syncthreads();
     uint32_t outside = 0;
-    const uint64_t lo = (uint64_t)blockIdx.x * per_block;
-    const uint64_t hi = lo + per_block < n ? lo + per_block : n;
-    for (uint64_t r0 = lo; r0 < hi; r0 += QZ_BLOCK * QZ_ITEMS) {
+    for (uint64_t r0 = lo; r0 < hi; r0 += QZ_ROUND) {
+        uint32_t cell[QZ_ITEMS];
 #pragma unroll
         for (int j = 0; j < QZ_ITEMS; ++j) {
             const uint64_t i = r0 + (uint64_t)j * QZ_BLOCK + threadIdx.x;
-            if (i >= hi) continue;
-            const float px = x[i], py = y[i], pz = z[i];
-            const uint32_t ux = quantize1(px, lx, sc), uy = quantize1(py, ly, sc), uz = quantize1(pz, lz, sc);
+            const uint32_t ux = quantize1(px[j], lx, sc), uy = quantize1(py[j], ly, sc), uz = quantize1(pz[j], lz, sc);
             const uint64_t c = (split3(ux) << 2) | (split3(uy) << 1) | split3(uz);
-            code[i] = c;
-            const uint32_t cell = (uint32_t)(c >> sh);
-            uint32_t h = hash32(cell) & (QZ_HASH - 1);
+            cell[j] = i < hi ? (uint32_t)(c >> sh) : 0xffffffffu;
+            if (i < hi) code[i] = c;
+            if (count_outside && i < hi)
+                outside += (px[j] < lx || px[j] > hx || py[j] < ly || py[j] > hy || pz[j] < lz || pz[j] > hz) ? 1u : 0u;
+        }
+        // next round's coordinates
+#pragma unroll
+        for (int j = 0; j < QZ_ITEMS; ++j) {
+            const uint64_t i = r0 + QZ_ROUND + (uint64_t)j * QZ_BLOCK + threadIdx.x;
+            px[j] = i < hi ? x[i] : 0.0f;
+            py[j] = i < hi ? y[i] : 0.0f;
+            pz[j] = i < hi ? z[i] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < QZ_ITEMS; ++j) {
+            const uint32_t cl = cell[j];
+            if (cl == 0xffffffffu) continue;
+            uint32_t h = hash32(cl) & (QZ_HASH - 1);
             while (true) {
                 uint32_t k = hk[h];
                 if (k == 0xffffffffu) {
-                    k = atomicCAS(&hk[h], 0xffffffffu, cell);
+                    k = atomicCAS(&hk[h], 0xffffffffu, cl);
                     if (k == 0xffffffffu) {
                         atomicAdd(&used, 1u);
-                        k = cell;
+                        k = cl;
                     }
                 }
-                if (k == cell) {
+                if (k == cl) {
                     atomicAdd(&hc[h], 1u);
                     break;
                 }
                 h = (h + 1) & (QZ_HASH - 1);
             }
-            if (count_outside)
-                outside += (px < lx || px > hx || py < ly || py > hy || pz < lz || pz > hz) ? 1u : 0u;
         }
         __syncthreads();
-        // at most QZ_BLOCK * QZ_ITEMS new cells per round: keep the table at
-        // most half full before the next one
-        if (used > QZ_HASH / 2 - QZ_BLOCK * QZ_ITEMS) {
+        // at most QZ_ROUND new cells per round: keep the table at most half
+        // full before the next one
+        if (used > QZ_HASH / 2 - QZ_ROUND) {
             qz_flush(hk, hc, fine);
             __syncthreads();
             if (threadIdx.x == 0) used = 0;
@@ -372,8 +397,15 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
     __syncthreads();
     qz_flush(hk, hc, fine);
     if (count_outside) {
+        // one atomic per block (the same counter for every block)
         outside = wave_sum(outside);
-        if (lane_id() == 0 && outside) atomicAdd(&box_rw->n_outside, (unsigned long long)outside);
+        if (lane_id() == 0) wsum[threadIdx.x >> 6] = outside;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int w = 0; w < QZ_BLOCK / 64; ++w) t += wsum[w];
+            if (t) atomicAdd(&box_rw->n_outside, (unsigned long long)t);
+        }
     }
 }
 
@@ -573,10 +605,30 @@ __global__ void k_cell_ids(const uint32_t *flags, uint32_t *ids, uint64_t ncell)
 // The scatter stages the tile in LDS in bucket order and then writes whole
 // bucket runs, so global writes are coalesced.
 
-__device__ __forceinline__ uint32_t ms_key(const MsArgs &A, uint64_t e)
+// Keys of items wlo + r*64 + lane, r < N, of a tile ending at hi (hi > the
+// tile's first element).  Indices past hi are clamped to hi - 1, so every load
+// is in bounds and none waits on a branch; the caller masks those items.  The
+// key source is chosen once, and all first-level loads are issued before the
+// dependent table loads.
+template <int N>
+__device__ __forceinline__ void ms_load_keys(const MsArgs &A, uint64_t wlo, uint64_t hi, int lane, uint32_t (&full)[N])
 {
-    if (A.keys) return A.keys[e];
-    return A.table[A.code[e] >> A.code_shift];
+    if (A.keys) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            const uint64_t e = wlo + (uint64_t)r * 64 + lane;
+            full[r] = A.keys[e < hi ? e : hi - 1];
+        }
+    } else {
+        uint64_t c[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            const uint64_t e = wlo + (uint64_t)r * 64 + lane;
+            c[r] = A.code[e < hi ? e : hi - 1];
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r) full[r] = A.table[c[r] >> A.code_shift];
+    }
 }
 
 // Tile t -> [lo, hi), its segment's bucket range, count-matrix location.
@@ -626,18 +678,24 @@ __device__ __forceinline__ MsTile ms_tile(const MsArgs &A, uint32_t t)
 template <bool SEG>
 __global__ __launch_bounds__(MS_BLOCK) void k_ms_count(MsArgs A)
 {
+    constexpr int PER_WAVE = MS_ITEMS * 64;
     __shared__ uint32_t hist[MS_MAX_BINS];
     const MsTile T = ms_tile<SEG>(A, blockIdx.x);
     if (!T.ok) return;
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const uint64_t wlo = T.lo + (uint64_t)w * PER_WAVE;
+    // all loads of the tile first, so their latencies overlap
+    uint32_t full[MS_ITEMS];
+    ms_load_keys(A, wlo, T.hi, lane, full);
     for (uint32_t b = threadIdx.x; b < T.nb; b += MS_BLOCK) hist[b] = 0;
     __syncthreads();
     const uint32_t dmask = (1u << A.dbits) - 1u;
     const int nbits = (int)ceil_log2_dev(T.nb);
-    const int lane = lane_id();
-    for (uint64_t e0 = T.lo + (threadIdx.x & ~63u); e0 < T.hi; e0 += MS_BLOCK) {
-        const uint64_t e = e0 + lane;
+#pragma unroll
+    for (int r = 0; r < MS_ITEMS; ++r) {
+        const uint64_t e = wlo + (uint64_t)r * 64 + lane;
         const bool valid = e < T.hi;
-        const uint32_t key = valid ? ((ms_key(A, e) >> A.shift) & dmask) - T.b0 : 0u;
+        const uint32_t key = valid ? ((full[r] >> A.shift) & dmask) - T.b0 : 0u;
         const uint64_t peers = match_peers(key, valid, nbits);
         if (valid && (peers & ((1ull << lane) - 1ull)) == 0) atomicAdd(&hist[key], (uint32_t)__popcll(peers));
     }
@@ -654,24 +712,49 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
     __shared__ uint16_t pre[W][MS_MAX_BINS];
     __shared__ uint32_t gbase[MS_MAX_BINS];   // global position of local slot 0 of a bucket (mod 2^32)
     __shared__ unsigned long long stage[MS_TILE];   // (key, value) pairs, then payloads
-    __shared__ uint32_t red[MS_BLOCK / 64 + 1];
+    // scan scratch, in the stage (unused until phase 3): 40 KB in all, four
+    // blocks per compute unit
+    uint32_t *red = reinterpret_cast<uint32_t *>(stage);
     const MsTile T = ms_tile<SEG>(A, blockIdx.x);
     if (!T.ok) return;
     const int w = threadIdx.x >> 6, lane = lane_id();
     const uint32_t dmask = (1u << A.dbits) - 1u;
     const int nbits = (int)ceil_log2_dev(T.nb);
+    // all loads of the tile first (keys, values, payloads), so their
+    // latencies overlap
+    const uint64_t wlo = T.lo + (uint64_t)w * PER_WAVE;
+    uint32_t full[MS_ITEMS], val[MS_ITEMS];
+    unsigned long long pay[MS_ITEMS];
+    ms_load_keys(A, wlo, T.hi, lane, full);
+    if (A.vals) {
+#pragma unroll
+        for (int r = 0; r < MS_ITEMS; ++r) {
+            const uint64_t e = wlo + (uint64_t)r * 64 + lane;
+            val[r] = A.vals[e < T.hi ? e : T.hi - 1];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < MS_ITEMS; ++r) val[r] = (uint32_t)(wlo + (uint64_t)r * 64 + lane);
+    }
+    if (A.pay) {
+#pragma unroll
+        for (int r = 0; r < MS_ITEMS; ++r) {
+            const uint64_t e = wlo + (uint64_t)r * 64 + lane;
+            pay[r] = A.pay[e < T.hi ? e : T.hi - 1];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < MS_ITEMS; ++r) pay[r] = wlo + (uint64_t)r * 64 + lane;
+    }
     for (uint32_t b = threadIdx.x; b < T.nb; b += MS_BLOCK)
         for (int k = 0; k < W; ++k) pre[k][b] = 0;
     __syncthreads();
     // phase 1: per-wave running counts; each lane keeps its offset inside its wave
-    const uint64_t wlo = T.lo + (uint64_t)w * PER_WAVE;
-    uint32_t full[MS_ITEMS];
     uint16_t wof[MS_ITEMS];
 #pragma unroll
     for (int r = 0; r < MS_ITEMS; ++r) {
         const uint64_t e = wlo + (uint64_t)r * 64 + lane;
         const bool valid = e < T.hi;
-        full[r] = valid ? ms_key(A, e) : 0u;
         const uint32_t key = valid ? ((full[r] >> A.shift) & dmask) - T.b0 : 0u;
         const uint64_t peers = match_peers(key, valid, nbits);
         const uint64_t lt = peers & ((1ull << lane) - 1ull);
@@ -708,8 +791,7 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
         if (e >= T.hi) continue;
         const uint32_t key = ((full[r] >> A.shift) & dmask) - T.b0;
         const uint32_t slot = pre[w][key] + wof[r];
-        const uint32_t v = A.vals ? A.vals[e] : (uint32_t)e;
-        stage[slot] = ((unsigned long long)full[r] << 32) | v;
+        stage[slot] = ((unsigned long long)full[r] << 32) | val[r];
         wof[r] = (uint16_t)slot;
     }
     __syncthreads();
@@ -735,7 +817,7 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
         for (int r = 0; r < MS_ITEMS; ++r) {
             const uint64_t e = wlo + (uint64_t)r * 64 + lane;
             if (e >= T.hi) continue;
-            stage[wof[r]] = A.pay ? A.pay[e] : e;
+            stage[wof[r]] = pay[r];
         }
         __syncthreads();
 #pragma unroll
@@ -1670,11 +1752,10 @@ void launch_quantize(const float *x, const float *y, const float *z, uint64_t n,
                      int count_outside, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw, hipStream_t st)
 {
     if (n == 0) return;
-    // contiguous ranges of at least 16 rounds per block, at most 2048 blocks
-    const uint64_t round = QZ_BLOCK * QZ_ITEMS;
-    uint64_t per = (n + 2047) / 2048;
-    if (per < 16 * round) per = 16 * round;
-    per = (per + round - 1) / round * round;
+    // one contiguous range per block, about one block per compute unit
+    // (each block holds 128 KB of LDS)
+    uint64_t per = (n + 255) / 256;
+    per = (per + 63) / 64 * 64;
     const uint32_t grid = (uint32_t)((n + per - 1) / per);
     hipLaunchKernelGGL(k_quantize, dim3(grid), dim3(QZ_BLOCK), 0, st, x, y, z, n, box, g, count_outside, code,
                        fine_cnt, box_rw, per);
