@@ -29,11 +29,67 @@ WORKLOADS = {
 
 
 def algorithmic_bytes(n: int, G: int, M: int) -> int:
-    """Bytes the path must move: bbox read 12/pt, quantise+count read 12/pt,
-    scatter read 12 + write 4 /pt, subsample read perm 4 + gather 12 + write
-    node_points 4 /pt, histogram written and read once (8 G^3), preview
+    """Bytes the whole path must move: bbox read 12/pt, quantise+count read
+    12/pt, scatter read 12 + write 4 /pt, subsample read perm 4 + gather 12 +
+    write node_points 4 /pt, histogram written and read once (8 G^3), preview
     4 N/M."""
     return 60 * n + 8 * G ** 3 + 4 * n // M
+
+
+# Algorithmic bytes of each timed kernel per build, from the per-step figures
+# above: (bytes(n, G, M), what they are).
+KERNEL_BYTES = {
+    "bbox": (lambda n, G, M: 12 * n, "read x, y, z once: 12 B/pt"),
+    "quantize": (lambda n, G, M: 12 * n + 4 * G ** 3, "read x, y, z again: 12 B/pt; write the count grid: 4 B/cell"),
+    "chunk_scatter": (lambda n, G, M: 16 * n, "re-read the points 12 B/pt, write perm 4 B/pt"),
+    "subsample": (lambda n, G, M: 16 * n, "read perm 4 B/pt, gather the coordinates once 12 B/pt"),
+    "node_ids": (lambda n, G, M: 4 * n, "one 4-byte id per point"),
+    "node_points": (lambda n, G, M: 4 * n, "write node_points 4 B/pt"),
+}
+
+KERNEL_NAMES = {
+    "bbox": "fpo::k_bbox",
+    "quantize": "fpo::k_quantize",
+    "chunk_scatter": "fpo::k_ms_scatter<false> (split into chunks)",
+    "subsample": "fpo::k_subsample_* (all size classes)",
+    "node_ids": "fpo::k_node_ids",
+    "node_points": "fpo::k_ms_scatter<false> (node_points split)",
+}
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per build of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE readings (profiles/traffic.json), scaled by the plain-copy
+    calibration factors; None when there is no reading for this kernel and
+    workload or the sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    from paper_2302_05002_amd.prof import source_digest
+    e = t.get("kernels", {}).get(f"{workload}/{kernel}")
+    if not e or e.get("source_digest") != source_digest():
+        return None
+    kib = e["fetch_kib"] * t["read_factor"] + e["write_kib"] * t["write_factor"]
+    return kib * 1024.0
+
+
+def cpu_baseline(cloud, p, seconds: float) -> dict:
+    """The CPU oracle as it stands (single thread) on the same workload,
+    repeated until `seconds` of work are done."""
+    import oracle
+    op = oracle.Params(p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity, p.preview_modulus)
+    runs, t_total = 0, 0.0
+    while runs == 0 or t_total < seconds:
+        t = time.perf_counter()
+        r = oracle.build_octree(cloud.x, cloud.y, cloud.z, op)
+        t_total += time.perf_counter() - t
+        assert r["status"] == oracle.OK
+        runs += 1
+    return {"value": runs * cloud.n / t_total, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole {cloud.n}-point workload, built {runs} times in {t_total:.1f} s "
+                      f"(single-threaded C, host CPU)"}
 
 
 def main():
@@ -70,22 +126,44 @@ def main():
     ws = torch.empty(fpo.workspace_size(n, params), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
 
-    def step():
+    def step(timed: bool):
         job = ctx.submit(x, y, z, params, workspace=ws, stream=stream)
         job.wait()
+        t = {k: job.timer(k) for k in KERNEL_BYTES} if timed else None
         job.release()
+        return t
 
     for _ in range(args.warmup):
-        step()
+        step(False)
+    # kernel timers: HIP events around the timed kernels, on the build's stream
+    ctx.set_timing(True)
+    timers = {k: [0.0, 0] for k in KERNEL_BYTES}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        for k, (ms_k, nl) in step(True).items():
+            timers[k][0] += ms_k
+            timers[k][1] += nl
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ctx.set_timing(False)
     ms = (t1 - t0) * 1000.0 / args.steps
     value = n / (ms / 1000.0)
     b_alg = algorithmic_bytes(n, p.count_grid, p.preview_modulus)
+
+    # dominant kernel: the most device time per build
+    dom = max(timers, key=lambda k: timers[k][0])
+    dom_ms = timers[dom][0] / args.steps
+    dom_launches = timers[dom][1] / args.steps
+    dom_bytes = KERNEL_BYTES[dom][0](n, p.count_grid, p.preview_modulus)
+    achieved = dom_bytes / (dom_ms / 1000.0) / 1e9
+    traffic = measured_traffic(dom, args.workload)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": KERNEL_NAMES[dom], "algorithmic_bytes": dom_bytes, "bytes_rule": KERNEL_BYTES[dom][1],
+                "ms_per_build": dom_ms, "launches_per_build": dom_launches,
+                "kernels_ms_per_build": {k: v[0] / args.steps for k, v in timers.items()}}
+
     out = {
         "metric": "octree-build points/s (bit-exact) + %HBM peak; batched/served vs plain",
         "value": value,
@@ -103,7 +181,10 @@ def main():
                    "subsample_grid": p.subsample_grid, "leaf_capacity": p.leaf_capacity,
                    "preview_modulus": p.preview_modulus, "parallelism": "single GPU"},
         "path_hbm_frac": b_alg / (ms / 1000.0) / (HBM_PEAK_GBS * 1e9),
+        "roofline": roofline,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cloud, p, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

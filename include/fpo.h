@@ -174,6 +174,31 @@ fpo_status fpo_job_result(fpo_job *job, fpo_result *out);
  * workspace). */
 void fpo_job_release(fpo_job *job);
 
+/* ---- kernel timing (for benchmarks) ----------------------------------------
+ * With timing enabled on a context, every later submit of it brackets the
+ * launches of each timed kernel below with HIP events recorded on the build's
+ * stream (a few microseconds of host time per event; off by default).  After
+ * fpo_job_wait returned FPO_OK, fpo_job_timer gives the summed device time of
+ * a timer's launches and their number (0 launches when the kernel did not run
+ * in this build). */
+typedef enum {
+    FPO_TIMER_BBOX = 0,          /* bounding-box scan, one launch (step 1) */
+    FPO_TIMER_QUANTIZE = 1,      /* quantise + count, one launch (step 1) */
+    FPO_TIMER_CHUNK_SCATTER = 2, /* scatter kernel of the stable split into chunks, one per digit pass (step 3) */
+    FPO_TIMER_SUBSAMPLE = 3,     /* per-work-chunk subsample kernels, every size class, bracketed together (step 4) */
+    FPO_TIMER_NODE_IDS = 4,      /* node id of every point (step 4) */
+    FPO_TIMER_NODE_POINTS = 5,   /* scatter kernel of the node_points split, one per digit pass (step 4) */
+    FPO_TIMER_COUNT = 6
+} fpo_timer;
+
+/* enable: 1 to time later submits of ctx, 0 to stop. */
+fpo_status fpo_context_set_timing(fpo_context *ctx, int enable);
+
+/* *ms = summed elapsed time of the timer's launches in the job, *launches =
+ * their number (either pointer may be NULL).  FPO_ERR_INVALID_ARG for an
+ * unknown timer, a job that was not timed or is not complete. */
+fpo_status fpo_job_timer(fpo_job *job, fpo_timer which, float *ms, uint32_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,10 @@ FPO_BBOX_GIVEN = 1
 #: every symbol include/fpo.h declares
 EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_workspace_size",
            "fpo_build_submit", "fpo_job_preview_ready", "fpo_job_poll", "fpo_job_wait",
-           "fpo_job_result", "fpo_job_release")
+           "fpo_job_result", "fpo_job_release", "fpo_context_set_timing", "fpo_job_timer")
+
+# fpo_timer values (include/fpo.h)
+TIMERS = {"bbox": 0, "quantize": 1, "chunk_scatter": 2, "subsample": 3, "node_ids": 4, "node_points": 5}
 
 
 class FpoError(RuntimeError):
@@ -87,6 +90,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_job_result.restype = ctypes.c_int
     lib.fpo_job_release.argtypes = [vp]
     lib.fpo_job_release.restype = None
+    lib.fpo_context_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.fpo_context_set_timing.restype = ctypes.c_int
+    lib.fpo_job_timer.argtypes = [vp, ctypes.c_int, P(ctypes.c_float), P(ctypes.c_uint32)]
+    lib.fpo_job_timer.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -149,6 +156,10 @@ class Context:
         except Exception:
             pass
 
+    def set_timing(self, enable: bool):
+        """Bracket the timed kernels of later submits with HIP events."""
+        _check(_lib.fpo_context_set_timing(self._h, 1 if enable else 0))
+
     def submit(self, x, y, z, params: Params, workspace=None, stream=None) -> "Job":
         """Enqueue a build of the device tensors x, y, z (float32, contiguous).
         Allocates the workspace with torch when none is given."""
@@ -202,6 +213,12 @@ class Job:
         r = _Result()
         _check(_lib.fpo_job_result(self._h, ctypes.byref(r)))
         return Result(r, self.workspace, self.params)
+
+    def timer(self, name: str):
+        """(summed device ms, launches) of a timer of a completed, timed job."""
+        ms, k = ctypes.c_float(), ctypes.c_uint32()
+        _check(_lib.fpo_job_timer(self._h, TIMERS[name], ctypes.byref(ms), ctypes.byref(k)))
+        return float(ms.value), int(k.value)
 
     def release(self):
         if self._h:

@@ -197,6 +197,8 @@ struct fpo_context {
     hipStream_t stream;
     std::mutex mu;
     std::vector<void *> pinned_free;
+    bool timing = false;
+    std::vector<hipEvent_t> ev_free;   // timing events, reused across jobs
 };
 
 struct fpo_job {
@@ -207,6 +209,8 @@ struct fpo_job {
     fpo_status status;
     fpo_result res;
     bool waited;
+    bool timed;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tm[FPO_TIMER_COUNT];
 };
 
 namespace {
@@ -230,6 +234,47 @@ void put_pinned(fpo_context *c, void *p)
 {
     std::lock_guard<std::mutex> g(c->mu);
     c->pinned_free.push_back(p);
+}
+
+hipEvent_t get_event(fpo_context *c)
+{
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        if (!c->ev_free.empty()) {
+            hipEvent_t e = c->ev_free.back();
+            c->ev_free.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets launches with a pair of timing events, kept by the job.
+struct JobTimer final : LaunchTimer {
+    fpo_job *job;
+    int which;
+    hipEvent_t first = nullptr;
+    JobTimer(fpo_job *j, int w) : job(j), which(w) {}
+    void begin(hipStream_t st) override;
+    void end(hipStream_t st) override;
+};
+
+void JobTimer::begin(hipStream_t st)
+{
+    first = job->timed ? get_event(job->ctx) : nullptr;
+    if (first) (void)hipEventRecord(first, st);
+}
+
+void JobTimer::end(hipStream_t st)
+{
+    if (!first) return;
+    hipEvent_t second = get_event(job->ctx);
+    if (!second) return;
+    (void)hipEventRecord(second, st);
+    job->tm[which].push_back({first, second});
+    first = nullptr;
 }
 
 }  // namespace
@@ -260,6 +305,7 @@ void fpo_context_destroy(fpo_context *c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     for (void *p : c->pinned_free) (void)hipHostFree(p);
+    for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -295,6 +341,7 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     job->stream = st;
     job->status = FPO_OK;
     job->waited = false;
+    job->timed = ctx->timing;
     job->pinned = get_pinned(ctx);
     if (!job->pinned) {
         delete job;
@@ -369,12 +416,18 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     const int given = (p->flags & FPO_BBOX_GIVEN) ? 1 : 0;
     // the scan runs with a given box too: it also detects non-finite values
     const uint32_t nparts = bbox_blocks(n);
+    JobTimer t_bbox(job, FPO_TIMER_BBOX), t_quant(job, FPO_TIMER_QUANTIZE), t_chunk(job, FPO_TIMER_CHUNK_SCATTER),
+        t_sub(job, FPO_TIMER_SUBSAMPLE), t_nid(job, FPO_TIMER_NODE_IDS), t_npts(job, FPO_TIMER_NODE_POINTS);
+    t_bbox.begin(st);
     launch_bbox(cloud->x, cloud->y, cloud->z, n, U32(P.bbox_part), st);
+    t_bbox.end(st);
     launch_setup(box, U32(P.bbox_part), nparts, given, p->bbox_min, p->bbox_max, st);
     uint32_t *pyr = U32(P.pyr);
     uint32_t *fine = pyr + pyr_off(g);
     launch_fill_u32(fine, 0u, P.G3, st);
+    t_quant.begin(st);
     launch_quantize(cloud->x, cloud->y, cloud->z, n, box, g, given, U64(P.code), fine, box, st);
+    t_quant.end(st);
 
     // ---- step 2: pyramid, chunk cut, work-chunk cut ----
     launch_pyramid(pyr, g, st);
@@ -417,7 +470,7 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
         MsOutput o;
         o.vals = U32(P.perm);
         o.pay = U64(P.code_perm);
-        multisplit(in, n, num_chunks, o, ws + P.ms_temp, st);
+        multisplit(in, n, num_chunks, o, ws + P.ms_temp, st, &t_chunk);
     }
     // work-chunk order from perm order: chunk by chunk when every work chunk
     // lies inside one chunk (one pass, few buckets per chunk), else globally
@@ -477,15 +530,19 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     A.dmax = KB - s_;
     if (g > 0) launch_fill_u32(U32(P.shared_cnt), 0u, pyr_off(g), st);
     launch_fill_u32(U32(P.kd), 0u, (uint64_t)MAXD * num_wc, st);
+    t_sub.begin(st);
     launch_subsample_small(A, st);
     launch_subsample_big(A, st);
+    t_sub.end(st);
     launch_decide(A, st);
     launch_node_counts(A, U32(P.owned), st);
     scan_exclusive(U32(P.owned), U32(P.node_base), (uint64_t)MAXD * num_wc, &ctrs->num_nodes, stemp, st);
     JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
     JCHK(hipStreamSynchronize(st));
     const uint32_t num_nodes = hctrs->num_nodes;
+    t_nid.begin(st);
     launch_node_ids(A, U32(P.node_base), U32(P.nid), &ctrs->internal_error, st);
+    t_nid.end(st);
     launch_fill_u32(U32(P.n_mask), 0u, (num_nodes + 3) / 4, st);
     launch_node_fill(A, U32(P.node_base), U8(P.n_depth), U64(P.n_key), U8(P.n_mask), st);
     // node_points: node by node from perm order (chunk by chunk, ascending
@@ -498,7 +555,7 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
         MsOutput o;
         o.vals = U32(P.n_points);
         o.keys = U32(P.sorted_nid);
-        multisplit(in, n, num_nodes, o, ws + P.ms_temp, st);
+        multisplit(in, n, num_nodes, o, ws + P.ms_temp, st, &t_npts);
     }
     launch_node_ranges(U32(P.sorted_nid), n, U64(P.n_begin), U32(P.n_count), num_nodes, st);
     // nodes spanning several chunks hold their points chunk by chunk: sort
@@ -611,7 +668,40 @@ void fpo_job_release(fpo_job *job)
     (void)hipEventDestroy(job->ev_preview);
     (void)hipEventDestroy(job->ev_done);
     if (job->pinned) put_pinned(job->ctx, job->pinned);
+    {
+        std::lock_guard<std::mutex> g(job->ctx->mu);
+        for (auto &v : job->tm)
+            for (auto &pr : v) {
+                job->ctx->ev_free.push_back(pr.first);
+                job->ctx->ev_free.push_back(pr.second);
+            }
+    }
     delete job;
+}
+
+fpo_status fpo_context_set_timing(fpo_context *ctx, int enable)
+{
+    if (!ctx) return fail(FPO_ERR_INVALID_ARG, "context is NULL");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->timing = enable != 0;
+    return FPO_OK;
+}
+
+fpo_status fpo_job_timer(fpo_job *job, fpo_timer which, float *ms, uint32_t *launches)
+{
+    if (!job) return fail(FPO_ERR_INVALID_ARG, "job is NULL");
+    if ((int)which < 0 || (int)which >= FPO_TIMER_COUNT) return fail(FPO_ERR_INVALID_ARG, "unknown timer %d", (int)which);
+    if (!job->timed) return fail(FPO_ERR_INVALID_ARG, "the job was submitted without timing");
+    if (!job->waited || job->status != FPO_OK) return fail(FPO_ERR_INVALID_ARG, "the job has not completed");
+    float total = 0.0f;
+    for (auto &pr : job->tm[which]) {
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, pr.first, pr.second));
+        total += t;
+    }
+    if (ms) *ms = total;
+    if (launches) *launches = (uint32_t)job->tm[which].size();
+    return FPO_OK;
 }
 
 }  // extern "C"

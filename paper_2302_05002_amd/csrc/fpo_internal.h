@@ -43,6 +43,13 @@ struct DevBox {
 // Offsets of level l in a pyramid array holding levels 0..g back to back.
 __host__ __device__ inline uint64_t pyr_off(int l) { return ((1ull << (3 * l)) - 1ull) / 7ull; }
 
+// Optional bracket around selected kernel launches (event timing).
+struct LaunchTimer {
+    virtual void begin(hipStream_t st) = 0;
+    virtual void end(hipStream_t st) = 0;
+    virtual ~LaunchTimer() {}
+};
+
 // ---- launchers (fpo_kernels.hip) -------------------------------------------
 // Fill kernel (in place of hipMemsetAsync, which costs far more host time per
 // call and is not safe to record in a graph).
@@ -109,7 +116,9 @@ struct MsArgs {
 };
 size_t multisplit_temp_bytes(uint64_t n, uint32_t nbins);
 size_t multisplit_temp_bound(uint64_t n, uint64_t max_bins);   // for any nbins <= max_bins
-void multisplit(const MsInput &in, uint64_t n, uint32_t nbins, const MsOutput &out, void *temp, hipStream_t st);
+// scatter_timer (optional) brackets every scatter-kernel launch.
+void multisplit(const MsInput &in, uint64_t n, uint32_t nbins, const MsOutput &out, void *temp, hipStream_t st,
+                LaunchTimer *scatter_timer = nullptr);
 size_t multisplit_seg_temp_bytes(uint64_t n, uint32_t nseg, uint64_t max_cells);
 void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, uint64_t max_tiles,
                           const MsOutput &out, void *temp, hipStream_t st);

@@ -917,7 +917,8 @@ size_t multisplit_temp_bound(uint64_t n, uint64_t max_bins)
     return b;
 }
 
-void multisplit(const MsInput &in, uint64_t n, uint32_t nbins, const MsOutput &out, void *temp, hipStream_t st)
+void multisplit(const MsInput &in, uint64_t n, uint32_t nbins, const MsOutput &out, void *temp, hipStream_t st,
+                LaunchTimer *scatter_timer)
 {
     if (n == 0) return;
     const MsLayout L = ms_layout(n, nbins);
@@ -956,7 +957,9 @@ void multisplit(const MsInput &in, uint64_t n, uint32_t nbins, const MsOutput &o
         A.src_out = (last && ps == 0) ? out.src : nullptr;
         hipLaunchKernelGGL(k_ms_count<false>, dim3(L.tiles), dim3(MS_BLOCK), 0, st, A);
         scan_exclusive(counts, offs, (uint64_t)L.nb[ps] * L.tiles, nullptr, stemp, st);
+        if (scatter_timer) scatter_timer->begin(st);
         hipLaunchKernelGGL(k_ms_scatter<false>, dim3(L.tiles), dim3(MS_BLOCK), 0, st, A);
+        if (scatter_timer) scatter_timer->end(st);
         A.keys = A.keys_out;
         A.code = nullptr;
         A.vals = A.vals_out;
