@@ -55,6 +55,7 @@ struct Ctrs {
     uint32_t wc_flags[2];      // [0] a work chunk spans several chunks, [1] a chunk holds too many
     uint32_t prefix_end;       // node_points range of the nodes spanning several chunks
     uint32_t prefix_nodes;
+    uint32_t cls_cnt[WC_CLASSES];   // work chunks per LDS size class
 };
 
 // Byte offsets of every region of the workspace for (n, params).
@@ -70,8 +71,8 @@ struct Plan {
     // temporaries
     size_t code, pyr, fc, ec, lc, fw, ew, lw_, w_level, w_key, w_count, w_start, w_begin;
     size_t c_count_scan, code_perm, wc_src, wc_code, ms_temp, scan_temp, seg_b0, seg_nb, wc_nested, wc_chunk;
-    size_t t, fr, shared_cnt, kd, loff, owned, node_base, lnode_key, lnode_mask, cut;
-    size_t big_list, big_nr, big_node, big_hkey, big_hval;
+    size_t t, fr, alive, alive_scan, kd, loff, owned, node_base, lnode_key, lnode_mask, cut;
+    size_t big_list, big_nr, big_node, big_hkey, big_hval, cls_list;
     size_t nid, sorted_nid, fx_keys, fx_vals, pv_tiles, pv_offs;
     uint64_t pv_ntiles;
 };
@@ -145,7 +146,8 @@ Plan make_plan(uint64_t n, const fpo_params &p)
     P.scan_temp = take(scan_temp_bytes(scan_max));
     P.t = take(nn);
     P.fr = take(4 * nn);
-    P.shared_cnt = take(4 * P.P);
+    P.alive = take(4 * MAXD * P.maxW);
+    P.alive_scan = take(4 * (MAXD * P.maxW + 1));
     P.kd = take(4 * MAXD * P.maxW);
     P.loff = take(4 * MAXD * P.maxW);
     P.owned = take(4 * MAXD * P.maxW);
@@ -154,6 +156,7 @@ Plan make_plan(uint64_t n, const fpo_params &p)
     P.lnode_mask = take(nn);
     P.cut = take(P.maxW);
     P.big_list = take(4 * P.maxW);
+    P.cls_list = take(4 * (uint64_t)WC_CLASSES * P.maxW);
     P.big_nr = take(4 * nn);
     P.big_node = take(12 * nn);
     // hash slots for work chunks above the LDS capacity: at most 4n in total
@@ -512,7 +515,8 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     A.wc_code = U64(P.wc_code);
     A.t = U8(P.t);
     A.fr = U32(P.fr);
-    A.shared_cnt = U32(P.shared_cnt);
+    A.alive = U32(P.alive);
+    A.alive_scan = U32(P.alive_scan);
     A.kd = U32(P.kd);
     A.loff = U32(P.loff);
     A.lnode_key = U64(P.lnode_key);
@@ -520,6 +524,8 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     A.cut = U8(P.cut);
     A.big_list = U32(P.big_list);
     A.num_big_dev = &ctrs->num_big;
+    A.cls_list = U32(P.cls_list);
+    A.cls_cnt = ctrs->cls_cnt;
     A.big_nr = U32(P.big_nr);
     A.big_node = U32(P.big_node);
     A.big_hkey = U64(P.big_hkey);
@@ -528,12 +534,13 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     A.s = s_;
     A.L = p->leaf_capacity;
     A.dmax = KB - s_;
-    if (g > 0) launch_fill_u32(U32(P.shared_cnt), 0u, pyr_off(g), st);
     launch_fill_u32(U32(P.kd), 0u, (uint64_t)MAXD * num_wc, st);
     t_sub.begin(st);
     launch_subsample_small(A, st);
     launch_subsample_big(A, st);
     t_sub.end(st);
+    scan_exclusive(U32(P.alive), U32(P.alive_scan), (uint64_t)MAXD * num_wc, U32(P.alive_scan) + (uint64_t)MAXD * num_wc,
+                   stemp, st);
     launch_decide(A, st);
     launch_node_counts(A, U32(P.owned), st);
     scan_exclusive(U32(P.owned), U32(P.node_base), (uint64_t)MAXD * num_wc, &ctrs->num_nodes, stemp, st);

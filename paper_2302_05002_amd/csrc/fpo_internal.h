@@ -17,6 +17,12 @@ constexpr int P1_BLOCK = 1024;
 constexpr int P1_ITEMS = 4;
 constexpr uint32_t WC_CAP = P1_BLOCK * P1_ITEMS;   // 4096
 constexpr uint32_t WC_HASH = 2 * WC_CAP;           // 8192 slots, load <= 1/2
+// Size classes of the LDS path.  Classes 0-4: work chunks of at most L points
+// (their own root is a leaf, so only the shared ancestors are subsampled),
+// up to 256 / 512 / 1024 / 2048 / 4096 points.  Classes 5-9: the general
+// subtree, same sizes.
+constexpr int WC_CLASSES = 10;
+constexpr int WC_GENERAL = 5;
 
 constexpr int MS_BLOCK = 256;                // multisplit block (4 waves)
 constexpr int MS_ITEMS = 8;                  // elements per thread
@@ -141,7 +147,9 @@ struct WcArgs {
     const uint64_t *wc_code;     // Morton code per position
     uint8_t *t;                  // tentative depth per position
     uint32_t *fr;                // local node rank per position
-    uint32_t *shared_cnt;        // pyramid-shaped reaching counts of shared nodes
+    uint32_t *alive;             // [MAXD][num_wc] points reaching each shared ancestor from a work
+                                 // chunk; after k_decide, the ancestor's whole reaching count (d <= cut)
+    const uint32_t *alive_scan;  // exclusive scan of alive over the flattened matrix (MAXD * num_wc + 1)
     uint32_t *kd;                // [num_wc][MAXD] local node count per depth
     uint32_t *loff;              // [num_wc][MAXD] offset of a depth's local nodes
     uint64_t *lnode_key;         // local node keys, per work chunk region
@@ -151,6 +159,10 @@ struct WcArgs {
     // cell keys too long for the LDS table), listed on the device
     uint32_t *big_list;
     uint32_t *num_big_dev;
+    // work chunks of the LDS path by size class (WC_CLASSES lists of up to
+    // num_wc entries each) and their counts
+    uint32_t *cls_list;
+    uint32_t *cls_cnt;
     uint32_t *big_nr;            // per position scratch
     uint32_t *big_node;          // 3 words of node scratch per position
     uint64_t *big_hkey;          // 4 table slots per position

@@ -129,6 +129,8 @@ __device__ __forceinline__ uint64_t match_peers(uint32_t key, bool valid, int nb
     return valid ? m : 0ull;
 }
 
+constexpr uint32_t ilog2_c(uint32_t v) { return v <= 1 ? 0 : 1 + ilog2_c(v >> 1); }
+
 __device__ __forceinline__ uint32_t ceil_log2_dev(uint32_t v)
 {
     return v <= 1 ? 0u : 32u - __clz(v - 1u);
@@ -1087,11 +1089,19 @@ constexpr uint32_t ST_INNER = 0xfeu;
 
 // Per-item state (code, state, current node rank, final node rank) in
 // registers (LDS path) or in global memory (BIG path).
+// LDS path: one packed word per item, state/depth in bits 0-7, the node rank
+// at the current depth in bits 8-19 and the rank of the node it is placed in
+// in bits 20-31 (at most 4096 points, so ranks fit 12 bits).
 template <int BLOCK, int ITEMS, bool BIG>
 struct Items {
+    static_assert(BLOCK * ITEMS <= 4096, "ranks are packed in 12 bits");
     uint64_t code[ITEMS];
-    uint32_t st[ITEMS], nr[ITEMS], fr[ITEMS];
+    uint32_t w[ITEMS];
     uint32_t n;
+    __device__ uint32_t st(int j) const { return w[j] & 0xffu; }
+    __device__ uint32_t nr(int j) const { return (w[j] >> 8) & 0xfffu; }
+    __device__ void set_st(int j, uint32_t v) { w[j] = (w[j] & ~0xffu) | v; }
+    __device__ void place(int j, uint32_t d) { w[j] = (w[j] & 0x000fff00u) | d | (nr(j) << 20); }
     __device__ void load(const WcArgs &a, uint32_t base, uint32_t n_)
     {
         n = n_;
@@ -1099,9 +1109,7 @@ struct Items {
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t pos = j * BLOCK + threadIdx.x;
             code[j] = pos < n ? a.wc_code[base + pos] : 0ull;
-            st[j] = ST_ALIVE;
-            nr[j] = 0;
-            fr[j] = 0;
+            w[j] = ST_ALIVE;
         }
     }
     template <class F>
@@ -1110,7 +1118,11 @@ struct Items {
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t pos = j * BLOCK + threadIdx.x;
-            if (pos < n) f(pos, code[j], st[j], nr[j], fr[j]);
+            if (pos < n) {
+                uint32_t s = w[j] & 0xffu, r = (w[j] >> 8) & 0xfffu, q = w[j] >> 20;
+                f(pos, code[j], s, r, q);
+                w[j] = s | (r << 8) | (q << 20);
+            }
         }
     }
     __device__ void store(const WcArgs &a, uint32_t base)
@@ -1119,8 +1131,8 @@ struct Items {
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t pos = j * BLOCK + threadIdx.x;
             if (pos < n) {
-                a.t[base + pos] = (uint8_t)st[j];
-                a.fr[base + pos] = fr[j];
+                a.t[base + pos] = (uint8_t)(w[j] & 0xffu);
+                a.fr[base + pos] = w[j] >> 20;
             }
         }
     }
@@ -1176,6 +1188,7 @@ __device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint
 {
     constexpr uint32_t CAP = BLOCK * ITEMS;
     constexpr uint32_t HASH = 2 * CAP;
+    constexpr uint32_t HLOG = ilog2_c(HASH);
     constexpr int POS_BITS = (CAP <= 2048) ? 11 : (CAP <= 4096 ? 12 : 13);
     constexpr int KEY_BITS = 31 - POS_BITS;   // packed 32-bit entries, never all ones
     const uint32_t n = a.wc_count[w];
@@ -1283,13 +1296,18 @@ __device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint
             continue;
         }
         if (!BIG && rel_bits > KEY_BITS) return false;
+        // LDS table of 2^hb slots, at least twice the alive points
+        uint32_t hb = ceil_log2_dev(2 * A);
+        if (hb < 6) hb = 6;
+        if (hb > HLOG) hb = HLOG;
+        const uint32_t hsize = 1u << hb;
         if (BIG) {
             for (uint64_t h = threadIdx.x; h <= gmask; h += BLOCK) {
                 ghk[h] = ~0ull;
                 ghv[h] = 0xffffffffu;
             }
         } else {
-            for (uint32_t h = threadIdx.x; h < HASH; h += BLOCK) region[h] = ~0u;
+            for (uint32_t h = threadIdx.x; h < hsize; h += BLOCK) region[h] = ~0u;
         }
         __syncthreads();
         uint32_t survive = 0;
@@ -1316,15 +1334,14 @@ __device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint
                 }
             });
         } else {
-            constexpr int HBITS = (HASH == 4096) ? 12 : (HASH == 8192 ? 13 : 14);
             uint32_t slot[ITEMS];
             uint32_t mine[ITEMS];   // key << POS_BITS | position; all ones once placed (or not inserting)
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) {
                 const uint32_t pos = j * BLOCK + threadIdx.x;
                 const uint32_t key = (uint32_t)((it.code[j] >> csh) & rel_mask);
-                mine[j] = (pos < n && it.st[j] == ST_INNER) ? ((key << POS_BITS) | pos) : 0xffffffffu;
-                slot[j] = rel_bits <= HBITS ? key : (key * 0x9E3779B1u) >> (32 - HBITS);
+                mine[j] = (pos < n && it.st(j) == ST_INNER) ? ((key << POS_BITS) | pos) : 0xffffffffu;
+                slot[j] = rel_bits <= (int)hb ? key : (key * 0x9E3779B1u) >> (32 - hb);
             }
             bool any = true;
             while (any) {
@@ -1345,7 +1362,7 @@ __device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint
                         if (c > mine[j]) atomicMin(&region[slot[j]], mine[j]);
                         mine[j] = 0xffffffffu;                                      // our key: done
                     } else {
-                        slot[j] = (slot[j] + 1) & (HASH - 1);                        // another key
+                        slot[j] = (slot[j] + 1) & (hsize - 1);                       // another key
                         any = true;
                     }
                 }
@@ -1355,15 +1372,13 @@ __device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint
             for (int j = 0; j < ITEMS; ++j) {
                 const uint32_t pos = j * BLOCK + threadIdx.x;
                 if (pos >= n) continue;
-                if (it.st[j] == ST_ALIVE) {   // leaf: every reaching point stays
-                    it.st[j] = (uint32_t)d;
-                    it.fr[j] = it.nr[j];
-                } else if (it.st[j] == ST_INNER) {
+                if (it.st(j) == ST_ALIVE) {   // leaf: every reaching point stays
+                    it.place(j, (uint32_t)d);
+                } else if (it.st(j) == ST_INNER) {
                     if ((region[slot[j]] & ((1u << POS_BITS) - 1u)) == pos) {
-                        it.st[j] = (uint32_t)d;
-                        it.fr[j] = it.nr[j];
+                        it.place(j, (uint32_t)d);
                     } else {
-                        it.st[j] = ST_ALIVE;
+                        it.set_st(j, ST_ALIVE);
                         ++survive;
                     }
                 }
@@ -1381,41 +1396,247 @@ __device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint
             Kprev = Kd;
         }
     }
-    // reaching counts of the shared ancestors
-    if (threadIdx.x < (uint32_t)lw) {
+    // points reaching each shared ancestor from this work chunk, one row per
+    // depth.  Plain stores, summed per ancestor later: thousands of work
+    // chunks share the top ancestors, and atomics on those few addresses
+    // would serialise and stall the memory pipeline.
+    if (threadIdx.x < (uint32_t)MAXD) {
         const int d = threadIdx.x;
-        const uint32_t Ad = alive_at[d];
-        if (Ad) atomicAdd(&a.shared_cnt[pyr_off(d) + (wkey >> (3 * (lw - d)))], Ad);
+        a.alive[(uint64_t)d * a.num_wc + w] = d < lw ? alive_at[d] : 0u;
     }
     it.store(a, base);
     __syncthreads();
     return true;
 }
 
-// LDS path for work chunks of at most BLOCK * ITEMS points whose size is above
-// MIN_N (the smaller ones run in a smaller instance with more blocks per CU).
+// LDS path: the work chunks of one size class (at most BLOCK * ITEMS points
+// each), from the class list.
 template <int BLOCK, int ITEMS>
-__global__ __launch_bounds__(BLOCK) void k_subsample_lds(WcArgs a, uint32_t min_n)
+__global__ __launch_bounds__(BLOCK) void k_subsample_lds(WcArgs a, int cls)
 {
     constexpr uint32_t CAP = BLOCK * ITEMS;
     __shared__ uint32_t region[3 * CAP];   // node scratch, then the cell table (2 * CAP entries)
     __shared__ uint32_t red[BLOCK / 64 + 1];
     __shared__ uint32_t counter[2];
-    for (uint32_t w = blockIdx.x; w < a.num_wc; w += gridDim.x) {
-        const uint32_t n = a.wc_count[w];
-        if (n <= min_n || n > CAP || !a.wc_nested[w]) continue;
+    const uint32_t cnt = a.cls_cnt[cls];
+    const uint32_t *list = a.cls_list + (uint64_t)cls * a.num_wc;
+    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const uint32_t w = list[i];
         const bool ok = subsample_wc<BLOCK, ITEMS, false>(a, w, region, red, counter, nullptr, nullptr, nullptr, 0);
         if (!ok && threadIdx.x == 0) a.big_list[atomicAdd(a.num_big_dev, 1u)] = w;
         __syncthreads();
     }
 }
 
-// Lists the work chunks too large for every LDS instance, and those spanning
-// several chunks (their positions are not in original index order).
-__global__ void k_list_big(WcArgs a, uint32_t max_lds)
+// Sorts the work chunks into the LDS size classes; those too large for every
+// class, and those spanning several chunks (their positions are not in
+// original index order), go to the global-memory list.  One atomic per wave
+// and class.
+__device__ __forceinline__ uint32_t wc_size_class(uint32_t n)
 {
-    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < a.num_wc; w += gridDim.x * blockDim.x)
-        if (a.wc_count[w] > max_lds || !a.wc_nested[w]) a.big_list[atomicAdd(a.num_big_dev, 1u)] = w;
+    return n <= 256 ? 0u : n <= 512 ? 1u : n <= 1024 ? 2u : n <= 2048 ? 3u : n <= WC_CAP ? 4u : 0xffu;
+}
+
+// Shared-ancestor pass of a work chunk whose own root is a leaf (at most L
+// points, so no local subtree below it): at every shared depth d < lw each
+// alive point competes for its cell of level d + s (relative to the work
+// chunk: 3(d + s - lw) bits), the lowest position wins and stays at depth d,
+// the others go on; what is left sits in the root at depth lw.  Each point
+// carries only its relative cell key at level lw - 1 + s (3(s - 1) <= 18
+// bits for s <= 7) and its state, packed in one word; the key of every
+// position is also kept in LDS.
+//
+// Cell table, one atomicMin of the position per point and round:
+//  - while the cell key fits the table it is the slot, and the entry is
+//    (31 - d) << 12 | position, so entries of shallower depths are replaced
+//    by the same atomicMin (no clearing per depth);
+//  - longer keys are hashed without probing: every point writes its
+//    position into slot h_r(cell), reads back the winning position and that
+//    position's key; points whose cell owns the slot are decided, the cells
+//    that collided try again with the next multiplier.  With at most a
+//    quarter of the slots used, few cells collide per round, and a round
+//    costs two dependent LDS reads, where linear probing costs as many load
+//    and CAS round trips as the longest probe chain of the block.
+// LDS operations of all items are issued together and waited for once.
+__constant__ uint32_t kFastMul[8] = {0x9E3779B1u, 0x85EBCA77u, 0xC2B2AE3Du, 0x27D4EB2Fu,
+                                     0x165667B1u, 0xD3A2646Du, 0xFD7046C5u, 0xB55A4F09u};
+
+template <int BLOCK, int ITEMS, int TLOG>
+__global__ __launch_bounds__(BLOCK) void k_subsample_fast(WcArgs a, int cls)
+{
+    constexpr uint32_t CAP = BLOCK * ITEMS;
+    constexpr uint32_t TSZ = 1u << TLOG;        // table entries
+    constexpr int NW = BLOCK / 64;
+    constexpr uint32_t ALIVE = 0xffu << 24;
+    constexpr uint32_t EMPTY = 0xffffffffu;
+    static_assert(CAP <= 4096, "positions are packed in 12 bits");
+    static_assert(TSZ >= 2 * CAP, "table of at least two slots per point");
+    __shared__ uint4 table4[TSZ / 4];
+    uint32_t *table = reinterpret_cast<uint32_t *>(table4);
+    __shared__ uint32_t keyat[CAP];
+    __shared__ uint32_t wsum[2][NW];
+    __shared__ uint32_t alive_at[MAXD];
+    const uint32_t cnt = a.cls_cnt[cls];
+    const uint32_t *list = a.cls_list + (uint64_t)cls * a.num_wc;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    // block-wide sum (every thread gets it); buffers alternate by parity
+    auto block_sum2 = [&](uint32_t v, int parity) -> uint32_t {
+        v = wave_sum(v);
+        if constexpr (NW == 1) {
+            return v;
+        } else {
+            if (lane == 0) wsum[parity][wv] = v;
+            __syncthreads();
+            uint32_t t = 0;
+#pragma unroll
+            for (int k = 0; k < NW; ++k) t += wsum[parity][k];
+            return t;
+        }
+    };
+    int par = 0;
+    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const uint32_t w = list[i];
+        const uint32_t n = a.wc_count[w], base = a.wc_begin[w];
+        const int lw = a.wc_level[w];
+        const int ksh = 3 * (KB - (lw - 1 + a.s));
+        const uint32_t kmask = (1u << (3 * (a.s - 1))) - 1u;
+        uint32_t it[ITEMS];   // relative key | state << 24 (0xff alive, else the depth it stays at)
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t pos = j * BLOCK + threadIdx.x;
+            const uint64_t c = a.wc_code[base + (pos < n ? pos : n - 1)];
+            it[j] = pos < n ? ((uint32_t)(c >> ksh) & kmask) | ALIVE : 0u;
+        }
+        if (threadIdx.x < (uint32_t)MAXD) alive_at[threadIdx.x] = 0;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) keyat[j * BLOCK + threadIdx.x] = it[j] & 0xffffffu;
+        for (uint32_t h = threadIdx.x; h < TSZ / 4; h += BLOCK) table4[h] = make_uint4(EMPTY, EMPTY, EMPTY, EMPTY);
+        uint32_t A = n;
+        bool clean = true;   // the table holds no hashed entries
+        for (int d = 0; d < lw && A > 0; ++d) {
+            if (threadIdx.x == 0) alive_at[d] = A;
+            const int rb = 3 * (d + a.s - lw);   // relative key bits at this depth
+            const int sh = 3 * (lw - 1 - d);
+            uint32_t won = 0;                    // bit j: item j stays at depth d
+            if (rb <= TLOG) {
+                if (!clean) {
+                    for (uint32_t h = threadIdx.x; h < TSZ / 4; h += BLOCK)
+                        table4[h] = make_uint4(EMPTY, EMPTY, EMPTY, EMPTY);
+                    clean = true;
+                }
+                __syncthreads();
+                const uint32_t tag = (31u - (uint32_t)d) << 12;
+#pragma unroll
+                for (int j = 0; j < ITEMS; ++j)
+                    if (it[j] >= ALIVE) atomicMin(&table[(it[j] & 0xffffffu) >> sh], tag | (j * BLOCK + threadIdx.x));
+                __syncthreads();
+                uint32_t cur[ITEMS];
+#pragma unroll
+                for (int j = 0; j < ITEMS; ++j) cur[j] = table[(it[j] & 0xffffffu) >> sh];
+#pragma unroll
+                for (int j = 0; j < ITEMS; ++j)
+                    if (it[j] >= ALIVE && cur[j] == (tag | (j * BLOCK + threadIdx.x))) won |= 1u << j;
+            } else {
+                // table of 2^hb slots, at least four per alive point
+                uint32_t hb = ceil_log2_dev(4 * A);
+                hb = hb < 6 ? 6 : (hb > (uint32_t)TLOG ? (uint32_t)TLOG : hb);
+                uint32_t pend = 0;   // bit j: item j's cell is not decided yet
+#pragma unroll
+                for (int j = 0; j < ITEMS; ++j)
+                    if (it[j] >= ALIVE) pend |= 1u << j;
+                for (int r = 0;; ++r) {
+                    const uint32_t mul = kFastMul[r & 7] + 2u * (uint32_t)(r >> 3);
+                    for (uint32_t h = threadIdx.x; h < (1u << hb) / 4; h += BLOCK)
+                        table4[h] = make_uint4(EMPTY, EMPTY, EMPTY, EMPTY);
+                    __syncthreads();
+                    uint32_t slot[ITEMS];
+#pragma unroll
+                    for (int j = 0; j < ITEMS; ++j) {
+                        slot[j] = (((it[j] & 0xffffffu) >> sh) * mul) >> (32 - hb);
+                        if ((pend >> j) & 1u) atomicMin(&table[slot[j]], j * BLOCK + threadIdx.x);
+                    }
+                    __syncthreads();
+                    uint32_t cur[ITEMS], ck[ITEMS];
+#pragma unroll
+                    for (int j = 0; j < ITEMS; ++j) cur[j] = table[slot[j]] & (CAP - 1);
+#pragma unroll
+                    for (int j = 0; j < ITEMS; ++j) ck[j] = keyat[cur[j]];
+#pragma unroll
+                    for (int j = 0; j < ITEMS; ++j) {
+                        if (!((pend >> j) & 1u)) continue;
+                        if ((ck[j] >> sh) == ((it[j] & 0xffffffu) >> sh)) {   // the slot is this cell's
+                            pend &= ~(1u << j);
+                            if (cur[j] == j * BLOCK + threadIdx.x) won |= 1u << j;
+                        }
+                    }
+                    clean = false;
+                    if (!__syncthreads_or(pend != 0)) break;
+                }
+            }
+            uint32_t surv = 0;
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                if (it[j] < ALIVE) continue;
+                if ((won >> j) & 1u) it[j] = (it[j] & 0xffffffu) | ((uint32_t)d << 24);
+                else ++surv;
+            }
+            A = block_sum2(surv, par);
+            par ^= 1;
+            __syncthreads();   // the table is reused next
+        }
+        // the rest sits in the root (a leaf) at depth lw
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t pos = j * BLOCK + threadIdx.x;
+            if (pos < n) {
+                a.t[base + pos] = (uint8_t)(it[j] >= ALIVE ? (uint32_t)lw : it[j] >> 24);
+                a.fr[base + pos] = 0;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < (uint32_t)MAXD) {
+            const int d = threadIdx.x;
+            a.alive[(uint64_t)d * a.num_wc + w] = d < lw ? alive_at[d] : 0u;
+        }
+        if (threadIdx.x == 0 && A > 0) {
+            a.kd[(uint64_t)w * MAXD + lw] = 1;
+            a.loff[(uint64_t)w * MAXD + lw] = 0;
+            a.lnode_key[base] = a.wc_key[w];
+            a.lnode_mask[base] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_list_classes(WcArgs a)
+{
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t w0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); w0 < a.num_wc; w0 += stride) {
+        const uint32_t w = w0 + lane_id();
+        const bool valid = w < a.num_wc;
+        uint32_t c = 0xfeu;
+        if (valid) {
+            const uint32_t n = a.wc_count[w];
+            c = wc_size_class(n);
+            if (!a.wc_nested[w]) c = 0xffu;
+            else if (c != 0xffu && !(n <= a.L && a.s <= 7)) c += WC_GENERAL;
+        }
+        for (uint32_t k = 0; k <= (uint32_t)WC_CLASSES; ++k) {
+            const uint32_t kc = k == (uint32_t)WC_CLASSES ? 0xffu : k;
+            const uint64_t m = __ballot(c == kc);
+            if (!m) continue;
+            uint32_t base = 0;
+            const int leader = __ffsll((long long)m) - 1;
+            if (lane_id() == leader)
+                base = atomicAdd(kc == 0xffu ? a.num_big_dev : &a.cls_cnt[kc], (uint32_t)__popcll(m));
+            base = __shfl(base, leader, 64);
+            if (c == kc) {
+                const uint32_t r = base + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
+                if (kc == 0xffu) a.big_list[r] = w;
+                else a.cls_list[(uint64_t)kc * a.num_wc + r] = w;
+            }
+        }
+    }
 }
 
 // Work chunks listed for the global-memory path (too large, or keys too
@@ -1439,14 +1660,35 @@ __global__ __launch_bounds__(P1_BLOCK) void k_subsample_big(WcArgs a)
 }
 
 // First shared depth of each WC whose node is a leaf (or empty); lw if none.
+// Reaching count of every shared ancestor (the sum of the rows posted by the
+// work chunks inside it: a range of the work-chunk order, found by binary
+// search on the first cells, summed as a difference of the row scan; u32
+// modular arithmetic is exact since every count is below 2^32), then per work
+// chunk the first shared depth whose node is a leaf (lw if none).  The
+// reaching counts up to that depth replace the posted rows.
+__device__ __forceinline__ uint32_t wc_lower_bound(const uint64_t *start, uint32_t lo, uint32_t hi, uint64_t v)
+{
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (start[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
 __global__ void k_decide(WcArgs a)
 {
-    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < a.num_wc; w += gridDim.x * blockDim.x) {
+    const uint32_t W = a.num_wc;
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
         const int lw = a.wc_level[w];
         const uint64_t key = a.wc_key[w];
         int cut = lw;
         for (int d = 0; d < lw; ++d) {
-            const uint32_t R = a.shared_cnt[pyr_off(d) + (key >> (3 * (lw - d)))];
+            const int sh = 3 * (a.lam_w - d);
+            const uint64_t node_start = (key >> (3 * (lw - d))) << sh;
+            const uint32_t lo = wc_lower_bound(a.wc_start, 0, w, node_start);
+            const uint32_t hi = wc_lower_bound(a.wc_start, w + 1, W, node_start + (1ull << sh));
+            const uint32_t R = a.alive_scan[(uint64_t)d * W + hi] - a.alive_scan[(uint64_t)d * W + lo];
+            a.alive[(uint64_t)d * W + w] = R;
             if (R <= a.L || d >= a.dmax) { cut = d; break; }
         }
         a.cut[w] = (uint8_t)cut;
@@ -1485,7 +1727,7 @@ __global__ void k_node_counts(WcArgs a, uint32_t *owned)
                     const int lp = a.wc_level[w - 1];
                     if (lp > d && (a.wc_key[w - 1] >> (3 * (lp - d))) == (a.wc_key[w] >> (3 * (lw - d)))) first = false;
                 }
-                const bool exists = d < cut || a.shared_cnt[pyr_off(d) + (a.wc_key[w] >> (3 * (lw - d)))] > 0;
+                const bool exists = d < cut || a.alive[(uint64_t)d * a.num_wc + w] > 0;
                 v = (first && exists) ? 1u : 0u;
             }
         } else if (cut == lw) {
@@ -1614,7 +1856,7 @@ __global__ void k_node_fill(WcArgs a, const uint32_t *node_base, uint8_t *depth,
                 if (lp > d && (a.wc_key[w - 1] >> (3 * (lp - d))) == (wkey >> (3 * (lw - d)))) first = false;
             }
             if (!first) continue;
-            if (!(d < cut || a.shared_cnt[pyr_off(d) + (wkey >> (3 * (lw - d)))] > 0)) continue;
+            if (!(d < cut || a.alive[(uint64_t)d * a.num_wc + w] > 0)) continue;
             const uint32_t id = node_base[i];
             const uint64_t k = wkey >> (3 * (lw - d));
             depth[id] = (uint8_t)d;
@@ -1805,13 +2047,22 @@ void launch_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_
 void launch_subsample_small(const WcArgs &a, hipStream_t st)
 {
     if (a.num_wc == 0) return;
-    // size classes: <= 2048 points (256 threads, 4 blocks per CU) and <= 4096
-    // points (512 threads, 2 blocks per CU); larger ones go to the BIG path
-    hipLaunchKernelGGL(k_list_big, dim3(grid_for(a.num_wc, 256)), dim3(256), 0, st, a, WC_CAP);
+    hipLaunchKernelGGL(k_list_classes, dim3(grid_for(a.num_wc, 256)), dim3(256), 0, st, a);
+    const uint32_t gs = a.num_wc < 8192 ? a.num_wc : 8192;
+    // work chunks whose own root is a leaf: shared ancestors only
+    hipLaunchKernelGGL((k_subsample_fast<64, 4, 10>), dim3(gs), dim3(64), 0, st, a, 0);
+    hipLaunchKernelGGL((k_subsample_fast<64, 8, 11>), dim3(gs), dim3(64), 0, st, a, 1);
+    hipLaunchKernelGGL((k_subsample_fast<64, 16, 12>), dim3(gs), dim3(64), 0, st, a, 2);
+    hipLaunchKernelGGL((k_subsample_fast<128, 16, 13>), dim3(gs), dim3(128), 0, st, a, 3);
+    hipLaunchKernelGGL((k_subsample_fast<256, 16, 13>), dim3(gs), dim3(256), 0, st, a, 4);
+    // the general subtree: single-wave blocks for the small classes, many per CU
+    hipLaunchKernelGGL((k_subsample_lds<64, 4>), dim3(gs), dim3(64), 0, st, a, WC_GENERAL + 0);
+    hipLaunchKernelGGL((k_subsample_lds<64, 8>), dim3(gs), dim3(64), 0, st, a, WC_GENERAL + 1);
+    hipLaunchKernelGGL((k_subsample_lds<64, 16>), dim3(gs), dim3(64), 0, st, a, WC_GENERAL + 2);
     const uint32_t g1 = a.num_wc < 2048 ? a.num_wc : 2048;
-    hipLaunchKernelGGL((k_subsample_lds<256, 8>), dim3(g1), dim3(256), 0, st, a, 0u);
+    hipLaunchKernelGGL((k_subsample_lds<256, 8>), dim3(g1), dim3(256), 0, st, a, WC_GENERAL + 3);
     const uint32_t g2 = a.num_wc < 1024 ? a.num_wc : 1024;
-    hipLaunchKernelGGL((k_subsample_lds<512, 8>), dim3(g2), dim3(512), 0, st, a, 2048u);
+    hipLaunchKernelGGL((k_subsample_lds<512, 8>), dim3(g2), dim3(512), 0, st, a, WC_GENERAL + 4);
 }
 
 void launch_subsample_big(const WcArgs &a, hipStream_t st)

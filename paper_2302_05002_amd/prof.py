@@ -89,7 +89,7 @@ def groups_per_build(path: str, counter: str, chunk_passes: int = 1, node_passes
             elif "k_quantize" in k:
                 sums["quantize"] += v
                 after_quant = True
-            elif "k_subsample" in k or "k_list_big" in k:
+            elif "k_subsample" in k or "k_list_classes" in k:
                 sums["subsample"] += v
             elif "k_node_ids" in k:
                 sums["node_ids"] += v
