@@ -53,8 +53,6 @@ struct Ctrs {
     uint32_t oversized;
     uint32_t internal_error;
     uint32_t wc_flags[2];      // [0] a work chunk spans several chunks, [1] a chunk holds too many
-    uint32_t prefix_end;       // node_points range of the nodes spanning several chunks
-    uint32_t prefix_nodes;
     uint32_t cls_cnt[WC_CLASSES];   // work chunks per LDS size class
 };
 
@@ -70,10 +68,10 @@ struct Plan {
     size_t n_depth, n_key, n_mask, n_begin, n_count, n_points, pv_index;
     // temporaries
     size_t code, pyr, fc, ec, lc, fw, ew, lw_, w_level, w_key, w_count, w_start, w_begin;
-    size_t c_count_scan, code_perm, wc_src, wc_code, ms_temp, scan_temp, seg_b0, seg_nb, wc_nested, wc_chunk;
+    size_t c_count_scan, code_perm, wc_orig, wc_code, ms_temp, scan_temp, seg_b0, seg_nb, wc_nested, wc_chunk;
     size_t t, fr, alive, alive_scan, kd, loff, owned, node_base, lnode_key, lnode_mask, cut;
     size_t big_list, big_nr, big_node, big_hkey, big_hval, cls_list;
-    size_t nid, sorted_nid, fx_keys, fx_vals, pv_tiles, pv_offs;
+    size_t nid, sorted_nid, pv_tiles, pv_offs;
     uint64_t pv_ntiles;
 };
 
@@ -128,7 +126,7 @@ Plan make_plan(uint64_t n, const fpo_params &p)
     P.w_begin = take(4 * P.maxW);
     P.c_count_scan = take(4 * P.maxC);
     P.code_perm = take(8 * nn);
-    P.wc_src = take(4 * nn);
+    P.wc_orig = take(4 * nn);
     P.seg_b0 = take(4 * P.maxC);
     P.seg_nb = take(4 * P.maxC);
     P.wc_nested = take(P.maxW);
@@ -164,8 +162,6 @@ Plan make_plan(uint64_t n, const fpo_params &p)
     P.big_hval = take(4 * 4 * nn);
     P.nid = take(4 * nn);
     P.sorted_nid = take(4 * nn);
-    P.fx_keys = take(4 * nn);
-    P.fx_vals = take(4 * nn);
     P.pv_tiles = take(4 * P.pv_ntiles);
     P.pv_offs = take(4 * P.pv_ntiles);
     P.total = o;
@@ -493,10 +489,12 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
             sg.b0 = U32(P.seg_b0);
             sg.nb = U32(P.seg_nb);
             sg.max_cells = n + num_wc;
-            o.src = U32(P.wc_src);
+            in.vals = U32(P.perm);   // original indices ride along
+            o.vals = U32(P.wc_orig);
             multisplit_segmented(in, n, sg, (n + MS_TILE - 1) / MS_TILE + num_chunks, o, ws + P.ms_temp, st);
         } else {
-            o.vals = U32(P.wc_src);   // values = perm positions
+            in.vals = U32(P.perm);
+            o.vals = U32(P.wc_orig);
             multisplit(in, n, num_wc, o, ws + P.ms_temp, st);
         }
     }
@@ -509,7 +507,7 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     A.wc_level = U8(P.w_level);
     A.wc_key = U64(P.w_key);
     A.wc_start = U64(P.w_start);
-    A.wc_src = U32(P.wc_src);
+    A.wc_orig = U32(P.wc_orig);
     A.perm = U32(P.perm);
     A.wc_nested = U8(P.wc_nested);
     A.wc_code = U64(P.wc_code);
@@ -548,49 +546,21 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     JCHK(hipStreamSynchronize(st));
     const uint32_t num_nodes = hctrs->num_nodes;
     t_nid.begin(st);
-    launch_node_ids(A, U32(P.node_base), U32(P.nid), &ctrs->internal_error, st);
+    launch_node_ids(A, U32(P.node_base), U32(P.nid), &ctrs->internal_error, n, st);
     t_nid.end(st);
     launch_fill_u32(U32(P.n_mask), 0u, (num_nodes + 3) / 4, st);
     launch_node_fill(A, U32(P.node_base), U8(P.n_depth), U64(P.n_key), U8(P.n_mask), st);
-    // node_points: node by node from perm order (chunk by chunk, ascending
-    // index inside a chunk), which is already the final order for every node
-    // inside one chunk
+    // node_points: the original indices 0..n-1 split stably by node id, so
+    // every node lists its points in ascending original index
     {
         MsInput in;
         in.keys = U32(P.nid);
-        in.vals = U32(P.perm);
         MsOutput o;
         o.vals = U32(P.n_points);
         o.keys = U32(P.sorted_nid);
         multisplit(in, n, num_nodes, o, ws + P.ms_temp, st, &t_npts);
     }
     launch_node_ranges(U32(P.sorted_nid), n, U64(P.n_begin), U32(P.n_count), num_nodes, st);
-    // nodes spanning several chunks hold their points chunk by chunk: sort
-    // that prefix of node_points by (node, original index)
-    launch_above_chunk(num_nodes, U8(P.n_depth), U64(P.n_begin), U32(P.n_count), U32(P.n_points), U64(P.code), g,
-                       U32(P.ec), U8(P.c_level), &ctrs->prefix_end, &ctrs->prefix_nodes, st);
-    JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
-    JCHK(hipStreamSynchronize(st));
-    if (hctrs->prefix_end > 0) {
-        const uint64_t F = hctrs->prefix_end;
-        {
-            MsInput in;
-            in.keys = U32(P.n_points);     // original indices: sort by them first
-            in.vals = U32(P.sorted_nid);   // node ids ride along
-            MsOutput o;
-            o.keys = U32(P.fx_keys);
-            o.vals = U32(P.fx_vals);
-            multisplit(in, F, (uint32_t)n, o, ws + P.ms_temp, st);
-        }
-        {
-            MsInput in;
-            in.keys = U32(P.fx_vals);      // then stably by node
-            in.vals = U32(P.fx_keys);
-            MsOutput o;
-            o.vals = U32(P.n_points);
-            multisplit(in, F, hctrs->prefix_nodes, o, ws + P.ms_temp, st);
-        }
-    }
 
     JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
     JCHK(hipMemcpyAsync(hbox, box, sizeof(DevBox), hipMemcpyDeviceToHost, st));

@@ -141,7 +141,7 @@ struct WcArgs {
     const uint8_t *wc_level;
     const uint64_t *wc_key;
     const uint64_t *wc_start;    // first lattice cell (level lam_w) of each work chunk
-    const uint32_t *wc_src;      // perm position of every work-chunk position
+    const uint32_t *wc_orig;     // original index of every work-chunk position
     const uint32_t *perm;        // original index per perm position
     const uint8_t *wc_nested;    // 1 when the work chunk lies inside one chunk
     const uint64_t *wc_code;     // Morton code per position
@@ -176,7 +176,7 @@ void launch_subsample_small(const WcArgs &a, hipStream_t st);
 void launch_subsample_big(const WcArgs &a, hipStream_t st);
 void launch_decide(const WcArgs &a, hipStream_t st);
 void launch_node_counts(const WcArgs &a, uint32_t *owned, hipStream_t st);
-void launch_node_ids(const WcArgs &a, const uint32_t *node_base, uint32_t *nid_perm, uint32_t *err,
+void launch_node_ids(const WcArgs &a, const uint32_t *node_base, uint32_t *nid_perm, uint32_t *err, uint64_t n,
                      hipStream_t st);
 // Chunk of every work chunk (the chunk holding its first occupied finest
 // cell), per chunk the range of its work chunks [b0, b0 + nb), per work chunk
@@ -187,14 +187,6 @@ void launch_wc_chunks(const uint32_t *num_wc_dev, uint64_t max_wc, const uint64_
                       int g, const uint32_t *pyr, const uint32_t *cid_table, const uint8_t *chunk_level,
                       const uint32_t *num_chunks_dev, uint64_t max_chunks, uint32_t *wc_chunk, uint32_t *seg_b0,
                       uint32_t *seg_nb, uint8_t *wc_nested, uint32_t *flags, hipStream_t st);
-// Nodes whose points lie in more than one chunk ("above" the chunk level):
-// *prefix_end = end of the last such node's range in node_points,
-// *prefix_nodes = one past its id.
-void launch_above_chunk(uint32_t num_nodes, const uint8_t *node_depth, const uint64_t *node_begin,
-                        const uint32_t *node_count, const uint32_t *node_points, const uint64_t *code, int g,
-                        const uint32_t *cid_table, const uint8_t *chunk_level, uint32_t *prefix_end,
-                        uint32_t *prefix_nodes, hipStream_t st);
-
 void launch_node_fill(const WcArgs &a, const uint32_t *node_base, uint8_t *depth, uint64_t *key,
                       uint8_t *mask, hipStream_t st);
 void launch_node_ranges(const uint32_t *sorted_keys, uint64_t n, uint64_t *begin, uint32_t *count,

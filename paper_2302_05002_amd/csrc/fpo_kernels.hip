@@ -1316,7 +1316,7 @@ __device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint
             // is not in index order
             it.each([&](uint32_t pos, uint64_t c, uint32_t &st, uint32_t &, uint32_t &) {
                 if (st != ST_INNER) return;
-                hash_insert_min(ghk, ghv, gmask, (c >> csh) & rel_mask, a.perm[a.wc_src[base + pos]]);
+                hash_insert_min(ghk, ghv, gmask, (c >> csh) & rel_mask, a.wc_orig[base + pos]);
             });
             __syncthreads();
             it.each([&](uint32_t pos, uint64_t c, uint32_t &st, uint32_t &r, uint32_t &f) {
@@ -1324,7 +1324,7 @@ __device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint
                     st = (uint32_t)d;
                     f = r;
                 } else if (st == ST_INNER) {
-                    if (hash_lookup(ghk, ghv, gmask, (c >> csh) & rel_mask) == a.perm[a.wc_src[base + pos]]) {
+                    if (hash_lookup(ghk, ghv, gmask, (c >> csh) & rel_mask) == a.wc_orig[base + pos]) {
                         st = (uint32_t)d;
                         f = r;
                     } else {
@@ -1737,33 +1737,101 @@ __global__ void k_node_counts(WcArgs a, uint32_t *owned)
     }
 }
 
-// Node id of every point, written at its perm position (perm positions of a
-// work chunk lie inside its chunk, so the writes stay local).
-__global__ __launch_bounds__(256) void k_node_ids(WcArgs a, const uint32_t *node_base, uint32_t *nid_perm,
-                                                  uint32_t *err)
+// Node id of every point, written at its original index.  Flat over
+// work-chunk positions in tiles; the blocks of XCD x (blocks are dispatched
+// to the 8 XCDs round robin) take the x-th eighth of the tiles in order, so
+// the scattered writes of one XCD come from one region of space, and points
+// close in space tend to be close in input order: the partial lines merge in
+// that XCD's L2 before they reach HBM.
+constexpr int NI_BLOCK = 256;
+constexpr int NI_ITEMS = 8;
+constexpr uint32_t NI_TILE = NI_BLOCK * NI_ITEMS;
+constexpr uint32_t NI_MAXWC = 32;   // work chunks of a tile with cached ancestor ids
+
+__device__ __forceinline__ uint32_t shared_node_id(const WcArgs &a, const uint32_t *node_base, uint32_t w, int d)
 {
-    __shared__ uint32_t own_id[MAXD];
-    for (uint32_t w = blockIdx.x; w < a.num_wc; w += gridDim.x) {
-        const int lw = a.wc_level[w];
-        const int cut = a.cut[w];
-        if (threadIdx.x < (uint32_t)lw) {
-            const int d = threadIdx.x;
-            own_id[d] = node_base[(uint64_t)d * a.num_wc + owner_of(a, w, d)];
+    return node_base[(uint64_t)d * a.num_wc + owner_of(a, w, d)];
+}
+
+__global__ __launch_bounds__(NI_BLOCK) void k_node_ids(WcArgs a, const uint32_t *node_base, uint32_t *nid_orig,
+                                                        uint32_t *err, uint64_t n)
+{
+    __shared__ uint32_t own[NI_MAXWC][MAXD];
+    __shared__ uint32_t s_begin[NI_MAXWC + 1];
+    __shared__ uint32_t s_w0, s_nw;
+    const uint32_t tiles = (uint32_t)((n + NI_TILE - 1) / NI_TILE);
+    const uint32_t xcd = blockIdx.x & 7u, per = gridDim.x >> 3;
+    const uint32_t t_lo = (uint32_t)((uint64_t)tiles * xcd / 8), t_hi = (uint32_t)((uint64_t)tiles * (xcd + 1) / 8);
+    for (uint32_t tile = t_lo + (blockIdx.x >> 3); tile < t_hi; tile += per) {
+        const uint32_t p0 = tile * NI_TILE;
+        const uint32_t p1 = (uint64_t)p0 + NI_TILE < n ? p0 + NI_TILE : (uint32_t)n;
+        if (threadIdx.x == 0) {
+            uint32_t lo = 0, hi = a.num_wc;   // last work chunk with begin <= p0
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (a.wc_begin[mid] <= p0) lo = mid; else hi = mid;
+            }
+            uint32_t k = 0;
+            while (k < NI_MAXWC && lo + k < a.num_wc && a.wc_begin[lo + k] < p1) {
+                s_begin[k] = a.wc_begin[lo + k];
+                ++k;
+            }
+            // more work chunks than cached: s_begin[NI_MAXWC] is the first
+            // uncached one, and points from there on are looked up one by one
+            const bool more = lo + k < a.num_wc && a.wc_begin[lo + k] < p1;
+            s_begin[k] = more ? a.wc_begin[lo + k] : 0xffffffffu;
+            s_w0 = lo;
+            s_nw = more ? 0xffffffffu : k;
         }
         __syncthreads();
-        const uint32_t base = a.wc_begin[w], n = a.wc_count[w];
-        for (uint32_t pos = threadIdx.x; pos < n; pos += blockDim.x) {
-            int t = a.t[base + pos];
-            uint32_t id;
-            if (t >= MAXD) {  // never placed: an internal error, reported to the host
+        const uint32_t w0 = s_w0, nw = s_nw;
+        const uint32_t ncache = nw == 0xffffffffu ? NI_MAXWC : nw;
+        for (uint32_t idx = threadIdx.x; idx < ncache * MAXD; idx += NI_BLOCK) {
+            const uint32_t k = idx / MAXD;
+            const int d = (int)(idx % MAXD);
+            const uint32_t w = w0 + k;
+            if (d < (int)a.wc_level[w] && d <= (int)a.cut[w]) own[k][d] = shared_node_id(a, node_base, w, d);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NI_ITEMS; ++j) {
+            const uint32_t q = p0 + j * NI_BLOCK + threadIdx.x;
+            if (q >= p1) continue;
+            // the point's work chunk: the last cached begin <= q
+            uint32_t k = 0;
+            if (ncache > 1) {
+                uint32_t lo = 0, hi = ncache;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (s_begin[mid] <= q) lo = mid; else hi = mid;
+                }
+                k = lo;
+            }
+            uint32_t w = w0 + k;
+            bool cached = true;
+            if (nw == 0xffffffffu && k == NI_MAXWC - 1 && s_begin[NI_MAXWC] <= q) {
+                uint32_t lo = w, hi = a.num_wc;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (a.wc_begin[mid] <= q) lo = mid; else hi = mid;
+                }
+                w = lo;
+                cached = false;
+            }
+            int t = a.t[q];
+            const uint32_t dst = a.wc_orig[q];
+            if (t >= MAXD) {   // never placed: an internal error, reported to the host
                 atomicOr(err, 1u);
-                nid_perm[a.wc_src[base + pos]] = 0;
+                nid_orig[dst] = 0;
                 continue;
             }
+            const int lw = a.wc_level[w];
+            const int cut = a.cut[w];
             if (cut < lw && t >= cut) t = cut;
-            if (t < lw) id = own_id[t];
-            else id = node_base[(uint64_t)t * a.num_wc + w] + a.fr[base + pos];
-            nid_perm[a.wc_src[base + pos]] = id;
+            uint32_t id;
+            if (t < lw) id = cached ? own[k][t] : shared_node_id(a, node_base, w, t);
+            else id = node_base[(uint64_t)t * a.num_wc + w] + a.fr[q];
+            nid_orig[dst] = id;
         }
         __syncthreads();
     }
@@ -1816,25 +1884,6 @@ __global__ void k_wc_chunks_nb(const uint32_t *num_chunks_dev, const uint32_t *s
     }
 }
 
-// Nodes whose points lie in more than one chunk: depth below the level of the
-// chunk holding the node's first point (a node at depth >= g lies inside one
-// finest cell, so inside one chunk).
-__global__ void k_above_chunk(uint32_t num_nodes, const uint8_t *node_depth, const uint64_t *node_begin,
-                              const uint32_t *node_count, const uint32_t *node_points, const uint64_t *code, int g,
-                              const uint32_t *cid_table, const uint8_t *chunk_level, uint32_t *prefix_end,
-                              uint32_t *prefix_nodes)
-{
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < num_nodes; k += gridDim.x * blockDim.x) {
-        const int d = node_depth[k];
-        if (d >= g) continue;
-        const uint32_t first = node_points[node_begin[k]];
-        const uint32_t c = cid_table[code[first] >> (3 * (KB - g))];
-        if (chunk_level[c] > d) {
-            atomicMax(prefix_end, (uint32_t)(node_begin[k] + node_count[k]));
-            atomicMax(prefix_nodes, k + 1);
-        }
-    }
-}
 
 // Node table: depth and key of every node, and child masks.  Local nodes
 // carry the masks computed inside their WC; a shared node's mask is the OR of
@@ -2082,10 +2131,15 @@ void launch_node_counts(const WcArgs &a, uint32_t *owned, hipStream_t st)
     hipLaunchKernelGGL(k_node_counts, dim3(grid_for((uint64_t)MAXD * a.num_wc, 256)), dim3(256), 0, st, a, owned);
 }
 
-void launch_node_ids(const WcArgs &a, const uint32_t *node_base, uint32_t *nid_perm, uint32_t *err, hipStream_t st)
+void launch_node_ids(const WcArgs &a, const uint32_t *node_base, uint32_t *nid_orig, uint32_t *err, uint64_t n,
+                     hipStream_t st)
 {
-    const uint32_t grid = a.num_wc < 4096 ? a.num_wc : 4096;
-    hipLaunchKernelGGL(k_node_ids, dim3(grid), dim3(256), 0, st, a, node_base, nid_perm, err);
+    if (n == 0 || a.num_wc == 0) return;
+    // a multiple of 8 blocks (one eighth of the tiles per XCD)
+    uint64_t tiles = (n + NI_TILE - 1) / NI_TILE;
+    uint64_t grid = tiles < 2048 ? tiles : 2048;
+    grid = (grid + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_node_ids, dim3((uint32_t)grid), dim3(NI_BLOCK), 0, st, a, node_base, nid_orig, err, n);
 }
 
 void launch_wc_chunks(const uint32_t *num_wc_dev, uint64_t max_wc, const uint64_t *wc_key, const uint8_t *wc_level,
@@ -2098,16 +2152,6 @@ void launch_wc_chunks(const uint32_t *num_wc_dev, uint64_t max_wc, const uint64_
     hipLaunchKernelGGL(k_wc_segs, dim3(grid_for(max_wc, 256)), dim3(256), 0, st, num_wc_dev, wc_chunk, seg_b0, seg_nb);
     hipLaunchKernelGGL(k_wc_chunks_nb, dim3(grid_for(max_chunks, 256)), dim3(256), 0, st, num_chunks_dev, seg_b0, seg_nb,
                        flags);
-}
-
-void launch_above_chunk(uint32_t num_nodes, const uint8_t *node_depth, const uint64_t *node_begin,
-                        const uint32_t *node_count, const uint32_t *node_points, const uint64_t *code, int g,
-                        const uint32_t *cid_table, const uint8_t *chunk_level, uint32_t *prefix_end,
-                        uint32_t *prefix_nodes, hipStream_t st)
-{
-    if (num_nodes == 0) return;
-    hipLaunchKernelGGL(k_above_chunk, dim3(grid_for(num_nodes, 256)), dim3(256), 0, st, num_nodes, node_depth, node_begin,
-                       node_count, node_points, code, g, cid_table, chunk_level, prefix_end, prefix_nodes);
 }
 
 void launch_node_fill(const WcArgs &a, const uint32_t *node_base, uint8_t *depth, uint64_t *key, uint8_t *mask,

@@ -198,3 +198,26 @@ def test_repeatable(ctx):
     b = gpu_build(ctx, c, 64, 50_000, 32, 2_000, 64)
     for k in KEYS:
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+def spike_cloud(levels=7, dense=5000, seed=3):
+    """A dense cell at the minimum corner of the finest work-chunk level and one
+    point in each of the 7 sibling octants along its path at every level:
+    after the dense work chunk come about 7 * levels one-point work chunks,
+    far more than one 2048-position tile of the node-id pass caches."""
+    rng = np.random.default_rng(seed)
+    pts = [rng.uniform(0.0, 2.0 ** -levels, (dense, 3))]
+    for l in range(1, levels + 1):
+        for o in range(1, 8):
+            org = np.array([(o >> 2) & 1, (o >> 1) & 1, o & 1], float) * 2.0 ** -l
+            pts.append((org + 2.0 ** -(l + 1))[None, :])
+    pts.append(np.array([[1.0, 1.0, 1.0]]))
+    p = np.concatenate(pts).astype(np.float32)
+    return synth.Cloud(p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy())
+
+
+def test_many_tiny_work_chunks(ctx):
+    """Tiles of the node-id pass overlapping more work chunks than they cache."""
+    c = spike_cloud()
+    run_both(ctx, c, 128, 100_000, 128, 10_000, 8)
+    run_both(ctx, c, 128, 1_000, 128, 300, 8)
