@@ -174,6 +174,71 @@ fpo_status fpo_job_result(fpo_job *job, fpo_result *out);
  * workspace). */
 void fpo_job_release(fpo_job *job);
 
+/* Packed host copy of a completed job's arrays, for tests and export: the
+ * arrays of fpo_result in this order, each starting at a multiple of 8 bytes:
+ * count_grid (uint32, G^3), chunk_level (uint8), chunk_key (uint64),
+ * chunk_count (uint32), chunk_begin (uint64) (num_chunks each), perm
+ * (uint32, n), node_depth (uint8), node_key (uint64), node_child_mask
+ * (uint8), node_begin (uint64), node_count (uint32) (num_nodes each),
+ * node_points (uint32, n), preview_index (uint32, preview_count).
+ * fpo_job_export_bytes gives the size; host_dst must hold that many bytes.
+ * Works for every kind of job (the only way to read server results from the
+ * host). */
+fpo_status fpo_job_export_bytes(fpo_job *job, uint64_t *bytes);
+fpo_status fpo_job_copy_to_host(fpo_job *job, void *host_dst, uint64_t bytes);
+
+/* Host steady-clock times (ns) of a completed job: when it was submitted, when
+ * its build started (later than submitted for batch and server jobs that
+ * waited for a worker, a slot or memory) and when a wait or poll first saw it
+ * complete.  FPO_ERR_INVALID_ARG before completion. */
+fpo_status fpo_job_timestamps(fpo_job *job, uint64_t *submitted_ns, uint64_t *started_ns, uint64_t *completed_ns);
+
+/* ---- batched builds ----------------------------------------------------------
+ * Many independent clouds in one call (the paper's import of several clouds,
+ * each with its own preview and tree).  The builds run concurrently on the
+ * context's worker streams (a few, one per hardware queue), largest first,
+ * so that latency-bound small builds overlap; each result is the one a plain
+ * build of that cloud gives. */
+
+/* Workspace bytes of a batch: the worst case of every cloud, each rounded up
+ * to 256 bytes, back to back in the order of the clouds. */
+fpo_status fpo_batch_workspace_size(const fpo_cloud *clouds, const fpo_params *params, uint32_t count,
+                                    uint64_t *bytes);
+
+/* Enqueues count builds: clouds[i] (device arrays) with params[i], results in
+ * slice i of `workspace` (device, >= fpo_batch_workspace_size bytes,
+ * 256-byte aligned, owned by the caller).  The builds start after the work
+ * enqueued on hip_stream so far (NULL: no dependency).  jobs_out[i] receives
+ * the job of cloud i; release every one.  Returns once the builds are queued;
+ * argument errors come back before anything is queued, build errors (a
+ * non-finite coordinate) from that build's job. */
+fpo_status fpo_build_batch(fpo_context *ctx, const fpo_cloud *clouds, const fpo_params *params, uint32_t count,
+                           void *workspace, uint64_t workspace_bytes, void *hip_stream, fpo_job **jobs_out);
+
+/* ---- serving ------------------------------------------------------------------
+ * A request loop with continuous batching: requests are admitted in arrival
+ * order as soon as a slot and enough of the HBM budget are free, and the
+ * builds of admitted requests overlap on the device.  Workspace comes from an
+ * arena of hbm_budget_bytes allocated by the server; a request holds its
+ * share from admission until fpo_job_release. */
+typedef struct fpo_server fpo_server;
+
+/* max_slots (1..64) builds run at once, each on a stream of its own. */
+fpo_status fpo_server_create(fpo_context *ctx, uint64_t hbm_budget_bytes, uint32_t max_slots, fpo_server **out);
+
+/* Queues a build of *cloud (device arrays, valid until the job completes)
+ * and never blocks.  FPO_ERR_REJECTED when its workspace exceeds the whole
+ * budget.  *out receives the job (poll, wait, result, cancel, release). */
+fpo_status fpo_server_submit(fpo_server *srv, const fpo_cloud *cloud, const fpo_params *params, fpo_job **out);
+
+/* Takes a batch or server job that has not started out of its queue; its
+ * wait then returns FPO_ERR_CANCELLED.  FPO_ERR_INVALID_ARG once it started. */
+fpo_status fpo_job_cancel(fpo_job *job);
+
+/* Waits for every queued and running request, then frees the arena.  Release
+ * the jobs of the server first: their results live in the arena. */
+void fpo_server_destroy(fpo_server *srv);
+
 /* ---- kernel timing (for benchmarks) ----------------------------------------
  * With timing enabled on a context, every later submit of it brackets the
  * launches of each timed kernel below with HIP events recorded on the build's

@@ -25,7 +25,9 @@ FPO_BBOX_GIVEN = 1
 #: every symbol include/fpo.h declares
 EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_workspace_size",
            "fpo_build_submit", "fpo_job_preview_ready", "fpo_job_poll", "fpo_job_wait",
-           "fpo_job_result", "fpo_job_release", "fpo_context_set_timing", "fpo_job_timer")
+           "fpo_job_result", "fpo_job_release", "fpo_job_export_bytes", "fpo_job_copy_to_host",
+           "fpo_job_timestamps", "fpo_batch_workspace_size", "fpo_build_batch", "fpo_server_create",
+           "fpo_server_submit", "fpo_job_cancel", "fpo_server_destroy", "fpo_context_set_timing", "fpo_job_timer")
 
 # fpo_timer values (include/fpo.h)
 TIMERS = {"bbox": 0, "quantize": 1, "chunk_scatter": 2, "subsample": 3, "node_ids": 4, "node_points": 5}
@@ -90,6 +92,25 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_job_result.restype = ctypes.c_int
     lib.fpo_job_release.argtypes = [vp]
     lib.fpo_job_release.restype = None
+    u64 = ctypes.c_uint64
+    lib.fpo_job_export_bytes.argtypes = [vp, P(u64)]
+    lib.fpo_job_export_bytes.restype = ctypes.c_int
+    lib.fpo_job_copy_to_host.argtypes = [vp, vp, u64]
+    lib.fpo_job_copy_to_host.restype = ctypes.c_int
+    lib.fpo_job_timestamps.argtypes = [vp, P(u64), P(u64), P(u64)]
+    lib.fpo_job_timestamps.restype = ctypes.c_int
+    lib.fpo_batch_workspace_size.argtypes = [P(_Cloud), P(_Params), ctypes.c_uint32, P(u64)]
+    lib.fpo_batch_workspace_size.restype = ctypes.c_int
+    lib.fpo_build_batch.argtypes = [vp, P(_Cloud), P(_Params), ctypes.c_uint32, vp, u64, vp, P(vp)]
+    lib.fpo_build_batch.restype = ctypes.c_int
+    lib.fpo_server_create.argtypes = [vp, u64, ctypes.c_uint32, P(vp)]
+    lib.fpo_server_create.restype = ctypes.c_int
+    lib.fpo_server_submit.argtypes = [vp, P(_Cloud), P(_Params), P(vp)]
+    lib.fpo_server_submit.restype = ctypes.c_int
+    lib.fpo_job_cancel.argtypes = [vp]
+    lib.fpo_job_cancel.restype = ctypes.c_int
+    lib.fpo_server_destroy.argtypes = [vp]
+    lib.fpo_server_destroy.restype = None
     lib.fpo_context_set_timing.argtypes = [vp, ctypes.c_int]
     lib.fpo_context_set_timing.restype = ctypes.c_int
     lib.fpo_job_timer.argtypes = [vp, ctypes.c_int, P(ctypes.c_float), P(ctypes.c_uint32)]
@@ -184,6 +205,72 @@ class Context:
         job.wait()
         return job.result()
 
+    def build_batch(self, clouds, params, workspace=None, stream=None) -> list:
+        """Enqueue one build per (x, y, z) device-tensor triple in `clouds`,
+        with params[i] (one Params for all, or a list).  Returns the jobs, in
+        the order of the clouds."""
+        import torch
+        count = len(clouds)
+        if isinstance(params, Params):
+            params = [params] * count
+        assert len(params) == count
+        cs = (_Cloud * max(count, 1))()
+        ps = (_Params * max(count, 1))()
+        dev = None
+        for i, (x, y, z) in enumerate(clouds):
+            n = int(x.shape[0])
+            for t in (x, y, z):
+                assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.shape[0] == n
+            cs[i] = _Cloud(n, x.data_ptr(), y.data_ptr(), z.data_ptr())
+            ps[i] = params[i].to_c()
+            dev = x.device
+        need = ctypes.c_uint64()
+        _check(_lib.fpo_batch_workspace_size(cs, ps, count, ctypes.byref(need)))
+        if count == 0:
+            return []
+        if workspace is None:
+            workspace = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        hs = (ctypes.c_void_p * count)()
+        _check(_lib.fpo_build_batch(self._h, cs, ps, count, ctypes.c_void_p(workspace.data_ptr()),
+                                    workspace.numel(), ctypes.c_void_p(stream.cuda_stream), hs))
+        return [Job(ctypes.c_void_p(hs[i]), workspace, params[i], clouds[i]) for i in range(count)]
+
+
+class Server:
+    """Request loop over one device: builds admitted by free slots and an HBM
+    budget (the server's own arena), overlapping on the device."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int = 4):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(_lib.fpo_server_create(ctx._h, int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, x, y, z, params: Params) -> "Job":
+        """Queue a build of the device tensors x, y, z (never blocks).  The
+        result is read with Job.to_numpy(): it lives in the server's arena."""
+        import torch
+        n = int(x.shape[0])
+        for t in (x, y, z):
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.shape[0] == n
+        cloud = _Cloud(n, x.data_ptr(), y.data_ptr(), z.data_ptr())
+        h = ctypes.c_void_p()
+        _check(_lib.fpo_server_submit(self._h, ctypes.byref(cloud), ctypes.byref(params.to_c()), ctypes.byref(h)))
+        return Job(h, None, params, (x, y, z))
+
+    def close(self):
+        if self._h:
+            _lib.fpo_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 class Job:
     def __init__(self, h, workspace, params, inputs):
@@ -213,6 +300,44 @@ class Job:
         r = _Result()
         _check(_lib.fpo_job_result(self._h, ctypes.byref(r)))
         return Result(r, self.workspace, self.params)
+
+    def cancel(self) -> bool:
+        """Take a batch or server job that has not started out of its queue."""
+        return _lib.fpo_job_cancel(self._h) == FPO_OK
+
+    def timestamps(self):
+        """(submitted, started, completed) host steady-clock ns of a completed job."""
+        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_lib.fpo_job_timestamps(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return int(a.value), int(b.value), int(c.value)
+
+    def to_numpy(self) -> dict:
+        """Every output of a completed job as host numpy arrays (through the
+        packed export of the C ABI; works for every kind of job)."""
+        r = _Result()
+        _check(_lib.fpo_job_result(self._h, ctypes.byref(r)))
+        nbytes = ctypes.c_uint64()
+        _check(_lib.fpo_job_export_bytes(self._h, ctypes.byref(nbytes)))
+        buf = np.empty(max(int(nbytes.value), 8), dtype=np.uint8)
+        _check(_lib.fpo_job_copy_to_host(self._h, ctypes.c_void_p(buf.ctypes.data), buf.nbytes))
+        n, nc, nn, pc = int(r.n), int(r.num_chunks), int(r.num_nodes), int(r.preview_count)
+        G = self.params.count_grid
+        layout = [("count_grid", np.uint32, G ** 3), ("chunk_level", np.uint8, nc), ("chunk_key", np.uint64, nc),
+                  ("chunk_count", np.uint32, nc), ("chunk_begin", np.uint64, nc), ("perm", np.uint32, n),
+                  ("node_depth", np.uint8, nn), ("node_key", np.uint64, nn), ("node_child_mask", np.uint8, nn),
+                  ("node_begin", np.uint64, nn), ("node_count", np.uint32, nn), ("node_points", np.uint32, n),
+                  ("preview_index", np.uint32, pc)]
+        out = dict(status=FPO_OK, n=n, bbox_min=np.array(r.bbox_min[:], dtype=np.float32),
+                   bbox_max=np.array(r.bbox_max[:], dtype=np.float32), cube_size=np.float32(r.cube_size),
+                   scale=np.float32(r.scale), n_outside=int(r.n_outside),
+                   chunk_oversized_any=int(r.chunk_oversized_any))
+        off = 0
+        for name, dt, cnt in layout:
+            off = (off + 7) & ~7
+            nb = cnt * np.dtype(dt).itemsize
+            out[name] = buf[off:off + nb].view(dt).copy()
+            off += nb
+        return out
 
     def timer(self, name: str):
         """(summed device ms, launches) of a timer of a completed, timed job."""

@@ -1,5 +1,6 @@
 // Host side of libfpo: argument checks, workspace layout and the launch
 // sequence of one build (C ABI in include/fpo.h).
+#include <chrono>
 #include <mutex>
 #include <stdarg.h>
 #include <stdio.h>
@@ -8,13 +9,16 @@
 #include <vector>
 
 #include "../../include/fpo.h"
+#include "fpo_host.h"
 #include "fpo_internal.h"
 
 using namespace fpo;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace fpo {
 
 fpo_status fail(fpo_status s, const char *fmt, ...)
 {
@@ -26,6 +30,19 @@ fpo_status fail(fpo_status s, const char *fmt, ...)
     g_err = buf;
     return s;
 }
+
+void set_error_text(const std::string &text) { g_err = text; }
+std::string error_text() { return g_err; }
+
+uint64_t now_ns()
+{
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace fpo
+
+namespace {
 
 #define HIPCHK(call)                                                                          \
     do {                                                                                      \
@@ -168,6 +185,10 @@ Plan make_plan(uint64_t n, const fpo_params &p)
     return P;
 }
 
+}  // namespace
+
+namespace fpo {
+
 fpo_status check_params(uint64_t n, const fpo_params *p)
 {
     if (!p) return fail(FPO_ERR_INVALID_ARG, "params is NULL");
@@ -189,28 +210,9 @@ fpo_status check_params(uint64_t n, const fpo_params *p)
     return FPO_OK;
 }
 
-}  // namespace
+uint64_t workspace_bytes(uint64_t n, const fpo_params &p) { return make_plan(n, p).total; }
 
-struct fpo_context {
-    int device;
-    hipStream_t stream;
-    std::mutex mu;
-    std::vector<void *> pinned_free;
-    bool timing = false;
-    std::vector<hipEvent_t> ev_free;   // timing events, reused across jobs
-};
-
-struct fpo_job {
-    fpo_context *ctx;
-    hipStream_t stream;
-    hipEvent_t ev_preview, ev_done;
-    void *pinned;                 // Ctrs + DevBox staging
-    fpo_status status;
-    fpo_result res;
-    bool waited;
-    bool timed;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> tm[FPO_TIMER_COUNT];
-};
+}  // namespace fpo
 
 namespace {
 
@@ -303,6 +305,7 @@ void fpo_context_destroy(fpo_context *c)
 {
     if (!c) return;
     (void)hipSetDevice(c->device);
+    destroy_batch_pool(c);
     for (void *p : c->pinned_free) (void)hipHostFree(p);
     for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(c->stream);
@@ -341,6 +344,9 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     job->status = FPO_OK;
     job->waited = false;
     job->timed = ctx->timing;
+    job->t_submit = now_ns();
+    job->t_done = 0;
+    job->grid_cells = P.G3;
     job->pinned = get_pinned(ctx);
     if (!job->pinned) {
         delete job;
@@ -573,9 +579,22 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
 #undef JCHK
 }
 
+// A batch or server job first waits for its build to be submitted; its
+// calls then act on the submitted build.
+#define FPO_RESOLVE(job, block)                                   \
+    do {                                                          \
+        if ((job)->def) {                                         \
+            fpo_job *inner_ = nullptr;                            \
+            const fpo_status r_ = deferred_resolve(job, block, &inner_); \
+            if (r_ != FPO_OK) return r_;                          \
+            job = inner_;                                         \
+        }                                                         \
+    } while (0)
+
 fpo_status fpo_job_preview_ready(fpo_job *job)
 {
     if (!job) return fail(FPO_ERR_INVALID_ARG, "job is NULL");
+    FPO_RESOLVE(job, false);
     hipError_t e = hipEventQuery(job->ev_preview);
     if (e == hipSuccess) return FPO_OK;
     if (e == hipErrorNotReady) return FPO_NOT_READY;
@@ -586,6 +605,7 @@ static fpo_status finish(fpo_job *job)
 {
     if (!job->waited) {
         job->waited = true;
+        job->t_done = now_ns();
         if (job->status == FPO_OK) {
             const Ctrs *hc = static_cast<const Ctrs *>(job->pinned);
             const DevBox *hb = reinterpret_cast<const DevBox *>(static_cast<const char *>(job->pinned) + 256);
@@ -600,47 +620,112 @@ static fpo_status finish(fpo_job *job)
                 R.n_outside = hb->n_outside;
                 R.preview_count = hc->preview_count;
                 R.chunk_oversized_any = hc->oversized ? 1 : 0;
-                if (hc->internal_error) {
-                    job->status = FPO_ERR_DEVICE;
-                    fail(FPO_ERR_DEVICE, "internal error: a point was left without a node");
-                }
+                if (hc->internal_error) job->status = FPO_ERR_DEVICE;
             }
         }
     }
-    return job->status;
+    if (job->status == FPO_ERR_DEVICE) return fail(FPO_ERR_DEVICE, "internal error: a point was left without a node");
+    return job->status == FPO_OK ? FPO_OK : fail(job->status, "build failed (status %d)", (int)job->status);
 }
 
 fpo_status fpo_job_poll(fpo_job *job)
 {
     if (!job) return fail(FPO_ERR_INVALID_ARG, "job is NULL");
+    FPO_RESOLVE(job, false);
     hipError_t e = hipEventQuery(job->ev_done);
     if (e == hipErrorNotReady) return FPO_NOT_READY;
     if (e != hipSuccess) return fail(FPO_ERR_DEVICE, "hipEventQuery: %s", hipGetErrorString(e));
-    fpo_status s = finish(job);
-    return s == FPO_OK ? s : fail(s, "build failed (status %d)", (int)s);
+    return finish(job);
 }
 
 fpo_status fpo_job_wait(fpo_job *job)
 {
     if (!job) return fail(FPO_ERR_INVALID_ARG, "job is NULL");
+    FPO_RESOLVE(job, true);
     hipError_t e = hipEventSynchronize(job->ev_done);
     if (e != hipSuccess) return fail(FPO_ERR_DEVICE, "hipEventSynchronize: %s", hipGetErrorString(e));
-    fpo_status s = finish(job);
-    return s == FPO_OK ? s : fail(s, "build failed (status %d)", (int)s);
+    return finish(job);
 }
 
 fpo_status fpo_job_result(fpo_job *job, fpo_result *out)
 {
     if (!job || !out) return fail(FPO_ERR_INVALID_ARG, "NULL job or out");
+    FPO_RESOLVE(job, false);
     if (!job->waited) return fail(FPO_ERR_INVALID_ARG, "the job has not been waited for");
     if (job->status != FPO_OK) return fail(job->status, "the build failed");
     *out = job->res;
     return FPO_OK;
 }
 
+// Packed export layout (see include/fpo.h): {pointer, bytes} per array.
+static void export_parts(const fpo_job *job, std::vector<std::pair<const void *, uint64_t>> &parts)
+{
+    const fpo_result &R = job->res;
+    const uint64_t nc = R.num_chunks, nn = R.num_nodes, n = R.n;
+    parts = {{R.count_grid, 4 * job->grid_cells}, {R.chunk_level, nc},     {R.chunk_key, 8 * nc},
+             {R.chunk_count, 4 * nc},             {R.chunk_begin, 8 * nc}, {R.perm, 4 * n},
+             {R.node_depth, nn},                  {R.node_key, 8 * nn},    {R.node_child_mask, nn},
+             {R.node_begin, 8 * nn},              {R.node_count, 4 * nn},  {R.node_points, 4 * n},
+             {R.preview_index, 4 * R.preview_count}};
+}
+
+fpo_status fpo_job_export_bytes(fpo_job *job, uint64_t *bytes)
+{
+    if (!job || !bytes) return fail(FPO_ERR_INVALID_ARG, "NULL job or bytes");
+    FPO_RESOLVE(job, false);
+    if (!job->waited || job->status != FPO_OK) return fail(FPO_ERR_INVALID_ARG, "the job has not completed");
+    std::vector<std::pair<const void *, uint64_t>> parts;
+    export_parts(job, parts);
+    uint64_t off = 0;
+    for (auto &pr : parts) off = ((off + 7) & ~7ull) + pr.second;
+    *bytes = off;
+    return FPO_OK;
+}
+
+fpo_status fpo_job_copy_to_host(fpo_job *job, void *host_dst, uint64_t bytes)
+{
+    if (!job || !host_dst) return fail(FPO_ERR_INVALID_ARG, "NULL job or destination");
+    uint64_t need = 0;
+    fpo_status s = fpo_job_export_bytes(job, &need);
+    if (s != FPO_OK) return s;
+    if (bytes < need) return fail(FPO_ERR_INVALID_ARG, "destination holds %llu bytes, the export needs %llu",
+                                  (unsigned long long)bytes, (unsigned long long)need);
+    FPO_RESOLVE(job, false);
+    HIPCHK(hipSetDevice(job->ctx->device));
+    std::vector<std::pair<const void *, uint64_t>> parts;
+    export_parts(job, parts);
+    uint64_t off = 0;
+    for (auto &pr : parts) {
+        off = (off + 7) & ~7ull;
+        // synchronous copies: the job's stream may already run another build
+        if (pr.second) HIPCHK(hipMemcpy(static_cast<char *>(host_dst) + off, pr.first, pr.second, hipMemcpyDeviceToHost));
+        off += pr.second;
+    }
+    return FPO_OK;
+}
+
+fpo_status fpo_job_timestamps(fpo_job *job, uint64_t *submitted_ns, uint64_t *started_ns, uint64_t *completed_ns)
+{
+    if (!job) return fail(FPO_ERR_INVALID_ARG, "job is NULL");
+    uint64_t sub = job->t_submit, start = job->t_submit;
+    if (job->def) {
+        start = deferred_start_ns(job);
+        FPO_RESOLVE(job, false);
+    }
+    if (!job->waited) return fail(FPO_ERR_INVALID_ARG, "the job has not completed");
+    if (submitted_ns) *submitted_ns = sub;
+    if (started_ns) *started_ns = start;
+    if (completed_ns) *completed_ns = job->t_done;
+    return FPO_OK;
+}
+
 void fpo_job_release(fpo_job *job)
 {
     if (!job) return;
+    if (job->def) {
+        deferred_release(job);
+        return;
+    }
     (void)hipEventSynchronize(job->ev_done);
     (void)hipEventDestroy(job->ev_preview);
     (void)hipEventDestroy(job->ev_done);
@@ -667,6 +752,7 @@ fpo_status fpo_context_set_timing(fpo_context *ctx, int enable)
 fpo_status fpo_job_timer(fpo_job *job, fpo_timer which, float *ms, uint32_t *launches)
 {
     if (!job) return fail(FPO_ERR_INVALID_ARG, "job is NULL");
+    FPO_RESOLVE(job, false);
     if ((int)which < 0 || (int)which >= FPO_TIMER_COUNT) return fail(FPO_ERR_INVALID_ARG, "unknown timer %d", (int)which);
     if (!job->timed) return fail(FPO_ERR_INVALID_ARG, "the job was submitted without timing");
     if (!job->waited || job->status != FPO_OK) return fail(FPO_ERR_INVALID_ARG, "the job has not completed");

@@ -1,0 +1,508 @@
+// Executors of libfpo: worker threads that run plain builds on HIP streams of
+// their own, for batched builds (fpo_build_batch) and for the request server
+// (fpo_server_*), and the server's device memory arena.
+//
+// Small and mid-sized builds are latency bound: a few dozen short kernels
+// and two short host round trips each.  Running several on separate streams
+// keeps the device busy while one build waits for the host, and lets the
+// kernels of different builds share the compute units.  Jobs are handed out
+// before their build starts; every job call first waits for that start.
+#include <algorithm>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "fpo_host.h"
+
+namespace fpo {
+
+struct Server;
+
+struct Deferred {
+    enum State { QUEUED, RUNNING, SUBMITTED, FAILED, CANCELLED };
+    std::mutex m;
+    std::condition_variable cv;
+    State state = QUEUED;
+    fpo_job *inner = nullptr;     // the plain build, once submitted
+    fpo_status status = FPO_OK;
+    std::string err;
+    fpo_cloud cloud{};
+    fpo_params params{};
+    void *ws = nullptr;
+    uint64_t ws_bytes = 0;
+    hipEvent_t after = nullptr;   // the build waits for it (work the caller enqueued before the batch)
+    Pool *pool = nullptr;         // batch pool the job is queued in
+    Server *server = nullptr;
+    uint64_t arena_off = 0;
+    bool has_memory = false;
+    uint64_t t_start = 0;
+};
+
+struct Pool {
+    fpo_context *ctx = nullptr;
+    Server *server = nullptr;     // the server whose slots these workers are, or null (batch)
+    std::mutex m;
+    std::condition_variable cv;
+    std::deque<fpo_job *> q;
+    std::vector<std::thread> threads;
+    std::vector<hipStream_t> streams;
+    bool stop = false;
+};
+
+struct Server {
+    fpo_context *ctx = nullptr;
+    uint64_t budget = 0;
+    uint32_t max_slots = 0;
+    char *arena = nullptr;
+    std::map<uint64_t, uint64_t> free_blocks;   // offset -> bytes, coalesced
+    std::mutex m;
+    std::condition_variable cv;
+    std::deque<fpo_job *> waiting;              // submitted, not yet admitted (FIFO)
+    uint32_t running = 0;
+    Pool *pool = nullptr;
+};
+
+namespace {
+
+constexpr int kBatchWorkers = 4;   // one per hardware queue of a process
+inline uint64_t a256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
+
+void server_finished(Server *S);
+
+void run_job(Pool *P, fpo_job *job, hipStream_t st)
+{
+    Deferred *d = job->def;
+    {
+        std::lock_guard<std::mutex> g(d->m);
+        if (d->state == Deferred::CANCELLED) return;
+        d->state = Deferred::RUNNING;
+        d->t_start = now_ns();
+    }
+    if (d->after) (void)hipStreamWaitEvent(st, d->after, 0);
+    fpo_job *inner = nullptr;
+    const fpo_status s = fpo_build_submit(P->ctx, &d->cloud, &d->params, d->ws, d->ws_bytes, st, &inner);
+    const std::string err = s == FPO_OK ? std::string() : error_text();
+    // a server slot stays taken until its build has ended
+    if (s == FPO_OK && P->server) (void)hipEventSynchronize(inner->ev_done);
+    {
+        // notified under the lock: once a releaser sees the final state, this
+        // thread no longer touches the job
+        std::lock_guard<std::mutex> g(d->m);
+        d->inner = inner;
+        d->status = s;
+        d->err = err;
+        d->state = s == FPO_OK ? Deferred::SUBMITTED : Deferred::FAILED;
+        d->cv.notify_all();
+    }
+    if (P->server) server_finished(P->server);
+}
+
+void worker(Pool *P, int idx)
+{
+    (void)hipSetDevice(P->ctx->device);
+    const hipStream_t st = P->streams[idx];
+    for (;;) {
+        fpo_job *job;
+        {
+            std::unique_lock<std::mutex> lk(P->m);
+            P->cv.wait(lk, [&] { return P->stop || !P->q.empty(); });
+            if (P->q.empty()) return;   // stopping, nothing left
+            job = P->q.front();
+            P->q.pop_front();
+        }
+        run_job(P, job, st);
+    }
+}
+
+Pool *make_pool(fpo_context *ctx, Server *server, int workers)
+{
+    Pool *P = new Pool();
+    P->ctx = ctx;
+    P->server = server;
+    for (int i = 0; i < workers; ++i) {
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) break;
+        P->streams.push_back(st);
+    }
+    if (P->streams.empty()) {
+        delete P;
+        return nullptr;
+    }
+    for (size_t i = 0; i < P->streams.size(); ++i) P->threads.emplace_back(worker, P, (int)i);
+    return P;
+}
+
+void stop_pool(Pool *P)
+{
+    if (!P) return;
+    {
+        std::lock_guard<std::mutex> g(P->m);
+        P->stop = true;
+    }
+    P->cv.notify_all();
+    for (auto &t : P->threads) t.join();
+    for (hipStream_t st : P->streams) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    delete P;
+}
+
+void pool_push(Pool *P, fpo_job *job)
+{
+    {
+        std::lock_guard<std::mutex> g(P->m);
+        P->q.push_back(job);
+    }
+    P->cv.notify_one();
+}
+
+bool pool_remove(Pool *P, fpo_job *job)
+{
+    std::lock_guard<std::mutex> g(P->m);
+    auto it = std::find(P->q.begin(), P->q.end(), job);
+    if (it == P->q.end()) return false;
+    P->q.erase(it);
+    return true;
+}
+
+// ---- server arena: first fit over one allocation, coalescing on free ----
+
+bool arena_alloc(Server *S, uint64_t bytes, uint64_t *off)
+{
+    for (auto it = S->free_blocks.begin(); it != S->free_blocks.end(); ++it) {
+        if (it->second < bytes) continue;
+        *off = it->first;
+        const uint64_t rest = it->second - bytes;
+        const uint64_t at = it->first + bytes;
+        S->free_blocks.erase(it);
+        if (rest) S->free_blocks[at] = rest;
+        return true;
+    }
+    return false;
+}
+
+void arena_free(Server *S, uint64_t off, uint64_t bytes)
+{
+    auto it = S->free_blocks.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != S->free_blocks.end() && it->first + it->second == next->first) {
+        it->second += next->second;
+        S->free_blocks.erase(next);
+    }
+    if (it != S->free_blocks.begin()) {
+        auto prev = std::prev(it);
+        if (prev->first + prev->second == it->first) {
+            prev->second += it->second;
+            S->free_blocks.erase(it);
+        }
+    }
+}
+
+// Admits waiting requests in arrival order while a slot and memory are free
+// (the head waits for memory rather than being overtaken).  S->m held.
+void try_admit(Server *S)
+{
+    while (!S->waiting.empty() && S->running < S->max_slots) {
+        fpo_job *j = S->waiting.front();
+        Deferred *d = j->def;
+        uint64_t off = 0;
+        if (!arena_alloc(S, d->ws_bytes, &off)) break;
+        S->waiting.pop_front();
+        d->arena_off = off;
+        d->ws = S->arena + off;
+        d->has_memory = true;
+        ++S->running;
+        pool_push(S->pool, j);
+    }
+}
+
+void server_finished(Server *S)
+{
+    {
+        std::lock_guard<std::mutex> g(S->m);
+        --S->running;
+        try_admit(S);
+    }
+    S->cv.notify_all();
+}
+
+bool server_remove_waiting(Server *S, fpo_job *job)
+{
+    std::lock_guard<std::mutex> g(S->m);
+    auto it = std::find(S->waiting.begin(), S->waiting.end(), job);
+    if (it == S->waiting.end()) return false;
+    S->waiting.erase(it);
+    S->cv.notify_all();
+    return true;
+}
+
+fpo_job *new_deferred_job(fpo_context *ctx)
+{
+    fpo_job *job = new fpo_job();
+    job->ctx = ctx;
+    job->stream = nullptr;
+    job->ev_preview = job->ev_done = nullptr;
+    job->pinned = nullptr;
+    job->status = FPO_OK;
+    job->waited = false;
+    job->timed = false;
+    job->t_submit = now_ns();
+    job->t_done = 0;
+    job->def = new Deferred();
+    return job;
+}
+
+fpo_status check_cloud(const fpo_cloud *c, const fpo_params *p)
+{
+    if (!c || !p) return fail(FPO_ERR_INVALID_ARG, "NULL cloud or params");
+    const fpo_status s = check_params(c->n, p);
+    if (s != FPO_OK) return s;
+    if (c->n > 0 && (!c->x || !c->y || !c->z)) return fail(FPO_ERR_INVALID_ARG, "NULL coordinate array");
+    return FPO_OK;
+}
+
+// Takes a job that has not started out of its queue; false if it started.
+bool cancel_queued(fpo_job *job)
+{
+    Deferred *d = job->def;
+    bool removed = false;
+    if (d->server) removed = server_remove_waiting(d->server, job);
+    else if (d->pool) removed = pool_remove(d->pool, job);
+    if (!removed) return false;
+    {
+        std::lock_guard<std::mutex> g(d->m);
+        d->state = Deferred::CANCELLED;
+        d->status = FPO_ERR_CANCELLED;
+        d->cv.notify_all();
+    }
+    return true;
+}
+
+}  // namespace
+
+fpo_status deferred_resolve(fpo_job *job, bool block, fpo_job **inner)
+{
+    Deferred *d = job->def;
+    std::unique_lock<std::mutex> lk(d->m);
+    if (block) d->cv.wait(lk, [&] { return d->state != Deferred::QUEUED && d->state != Deferred::RUNNING; });
+    switch (d->state) {
+    case Deferred::QUEUED:
+    case Deferred::RUNNING:
+        return FPO_NOT_READY;
+    case Deferred::SUBMITTED:
+        *inner = d->inner;
+        return FPO_OK;
+    case Deferred::FAILED:
+        set_error_text(d->err);
+        return d->status;
+    case Deferred::CANCELLED:
+    default:
+        set_error_text("the job was cancelled");
+        return FPO_ERR_CANCELLED;
+    }
+}
+
+uint64_t deferred_start_ns(const fpo_job *job)
+{
+    Deferred *d = job->def;
+    std::lock_guard<std::mutex> g(d->m);
+    return d->t_start;
+}
+
+void deferred_release(fpo_job *job)
+{
+    Deferred *d = job->def;
+    (void)cancel_queued(job);   // a job that has not started never will
+    {
+        std::unique_lock<std::mutex> lk(d->m);
+        d->cv.wait(lk, [&] { return d->state != Deferred::QUEUED && d->state != Deferred::RUNNING; });
+    }
+    if (d->inner) fpo_job_release(d->inner);
+    if (d->server && d->has_memory) {
+        Server *S = d->server;
+        {
+            std::lock_guard<std::mutex> g(S->m);
+            arena_free(S, d->arena_off, d->ws_bytes);
+            try_admit(S);
+        }
+        S->cv.notify_all();
+    }
+    if (d->after) (void)hipEventDestroy(d->after);
+    delete d;
+    delete job;
+}
+
+void destroy_batch_pool(fpo_context *ctx)
+{
+    Pool *P = nullptr;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        P = ctx->batch_pool;
+        ctx->batch_pool = nullptr;
+    }
+    stop_pool(P);
+}
+
+}  // namespace fpo
+
+struct fpo_server : fpo::Server {};
+
+using namespace fpo;
+
+extern "C" {
+
+fpo_status fpo_job_cancel(fpo_job *job)
+{
+    if (!job) return fail(FPO_ERR_INVALID_ARG, "job is NULL");
+    if (!job->def) return fail(FPO_ERR_INVALID_ARG, "only batch and server jobs can be cancelled");
+    if (!cancel_queued(job)) return fail(FPO_ERR_INVALID_ARG, "the job has already started (or was cancelled)");
+    return FPO_OK;
+}
+
+fpo_status fpo_batch_workspace_size(const fpo_cloud *clouds, const fpo_params *params, uint32_t count,
+                                    uint64_t *bytes)
+{
+    if (!bytes || (count && (!clouds || !params))) return fail(FPO_ERR_INVALID_ARG, "NULL clouds, params or bytes");
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        const fpo_status s = check_cloud(&clouds[i], &params[i]);
+        if (s != FPO_OK) return s;
+        total += a256(workspace_bytes(clouds[i].n, params[i]));
+    }
+    *bytes = total;
+    return FPO_OK;
+}
+
+fpo_status fpo_build_batch(fpo_context *ctx, const fpo_cloud *clouds, const fpo_params *params, uint32_t count,
+                           void *workspace, uint64_t workspace_bytes_, void *hip_stream, fpo_job **jobs_out)
+{
+    if (!ctx || !jobs_out || (count && (!clouds || !params))) return fail(FPO_ERR_INVALID_ARG, "NULL argument");
+    if (count == 0) return FPO_OK;
+    if (!workspace) return fail(FPO_ERR_INVALID_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(FPO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    std::vector<uint64_t> off(count), sz(count);
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        const fpo_status s = check_cloud(&clouds[i], &params[i]);
+        if (s != FPO_OK) return fail(s, "cloud %u: %s", i, error_text().c_str());
+        sz[i] = workspace_bytes(clouds[i].n, params[i]);
+        off[i] = total;
+        total += a256(sz[i]);
+    }
+    if (workspace_bytes_ < total)
+        return fail(FPO_ERR_OUT_OF_MEMORY, "workspace holds %llu bytes, the batch needs %llu",
+                    (unsigned long long)workspace_bytes_, (unsigned long long)total);
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(FPO_ERR_DEVICE, "hipSetDevice failed");
+    Pool *P;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        if (!ctx->batch_pool) ctx->batch_pool = make_pool(ctx, nullptr, kBatchWorkers);
+        P = ctx->batch_pool;
+    }
+    if (!P) return fail(FPO_ERR_DEVICE, "could not create the worker streams");
+    std::vector<fpo_job *> jobs(count, nullptr);
+    for (uint32_t i = 0; i < count; ++i) {
+        fpo_job *job = new_deferred_job(ctx);
+        jobs[i] = job;
+        Deferred *d = job->def;
+        d->cloud = clouds[i];
+        d->params = params[i];
+        d->ws = static_cast<char *>(workspace) + off[i];
+        d->ws_bytes = sz[i];
+        d->pool = P;
+        bool ok = true;
+        if (hip_stream) {
+            ok = hipEventCreateWithFlags(&d->after, hipEventDisableTiming) == hipSuccess;
+            if (!ok) d->after = nullptr;
+            ok = ok && hipEventRecord(d->after, static_cast<hipStream_t>(hip_stream)) == hipSuccess;
+        }
+        if (!ok) {   // nothing is queued yet: undo
+            for (uint32_t k = 0; k <= i; ++k) {
+                if (jobs[k]->def->after) (void)hipEventDestroy(jobs[k]->def->after);
+                delete jobs[k]->def;
+                delete jobs[k];
+            }
+            return fail(FPO_ERR_DEVICE, "could not record an event on the caller's stream");
+        }
+    }
+    // largest first: the small builds fill in behind the long ones
+    std::vector<uint32_t> order(count);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return clouds[a].n > clouds[b].n; });
+    for (uint32_t i = 0; i < count; ++i) jobs_out[i] = jobs[i];
+    for (uint32_t i : order) pool_push(P, jobs[i]);
+    return FPO_OK;
+}
+
+fpo_status fpo_server_create(fpo_context *ctx, uint64_t hbm_budget_bytes, uint32_t max_slots, fpo_server **out)
+{
+    if (!ctx || !out) return fail(FPO_ERR_INVALID_ARG, "NULL context or out");
+    if (max_slots == 0 || max_slots > 64) return fail(FPO_ERR_INVALID_ARG, "max_slots must be in 1..64 (got %u)", max_slots);
+    const uint64_t budget = hbm_budget_bytes & ~(uint64_t)255;
+    if (budget == 0) return fail(FPO_ERR_INVALID_ARG, "hbm_budget_bytes must be at least 256");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(FPO_ERR_DEVICE, "hipSetDevice failed");
+    fpo_server *S = new fpo_server();
+    S->ctx = ctx;
+    S->budget = budget;
+    S->max_slots = max_slots;
+    void *arena = nullptr;
+    if (hipMalloc(&arena, budget) != hipSuccess) {
+        delete S;
+        return fail(FPO_ERR_OUT_OF_MEMORY, "could not allocate the %llu-byte arena", (unsigned long long)budget);
+    }
+    S->arena = static_cast<char *>(arena);
+    S->free_blocks[0] = budget;
+    S->pool = make_pool(ctx, S, (int)max_slots);
+    if (!S->pool) {
+        (void)hipFree(arena);
+        delete S;
+        return fail(FPO_ERR_DEVICE, "could not create the slot streams");
+    }
+    *out = S;
+    return FPO_OK;
+}
+
+fpo_status fpo_server_submit(fpo_server *S, const fpo_cloud *cloud, const fpo_params *params, fpo_job **out)
+{
+    if (!S || !out) return fail(FPO_ERR_INVALID_ARG, "NULL server or out");
+    const fpo_status s = check_cloud(cloud, params);
+    if (s != FPO_OK) return s;
+    const uint64_t bytes = a256(workspace_bytes(cloud->n, *params));
+    if (bytes > S->budget)
+        return fail(FPO_ERR_REJECTED, "the build needs %llu bytes, more than the server's budget of %llu",
+                    (unsigned long long)bytes, (unsigned long long)S->budget);
+    fpo_job *job = new_deferred_job(S->ctx);
+    Deferred *d = job->def;
+    d->cloud = *cloud;
+    d->params = *params;
+    d->ws_bytes = bytes;
+    d->server = S;
+    *out = job;
+    {
+        std::lock_guard<std::mutex> g(S->m);
+        S->waiting.push_back(job);
+        try_admit(S);
+    }
+    return FPO_OK;
+}
+
+void fpo_server_destroy(fpo_server *S)
+{
+    if (!S) return;
+    {
+        std::unique_lock<std::mutex> lk(S->m);
+        S->cv.wait(lk, [&] { return S->waiting.empty() && S->running == 0; });
+    }
+    stop_pool(S->pool);
+    (void)hipSetDevice(S->ctx->device);
+    (void)hipFree(S->arena);
+    delete S;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Host-side state shared by the sources of libfpo: the context and job
+// objects behind the opaque handles of include/fpo.h, and the helpers the
+// executors (batch, server) use.  Not part of the public C ABI.
+#pragma once
+#include <stdint.h>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/fpo.h"
+
+namespace fpo {
+
+// Sets the calling thread's error text (fpo_last_error) and returns s.
+fpo_status fail(fpo_status s, const char *fmt, ...);
+void set_error_text(const std::string &text);
+std::string error_text();
+fpo_status check_params(uint64_t n, const fpo_params *p);
+uint64_t workspace_bytes(uint64_t n, const fpo_params &p);   // worst case of one build
+uint64_t now_ns();                                           // steady clock
+
+struct Deferred;   // job created before its build starts (batch, server)
+struct Pool;       // worker threads with their own streams
+
+}  // namespace fpo
+
+struct fpo_context {
+    int device;
+    hipStream_t stream;
+    std::mutex mu;
+    std::vector<void *> pinned_free;
+    bool timing = false;
+    std::vector<hipEvent_t> ev_free;   // timing events, reused across jobs
+    fpo::Pool *batch_pool = nullptr;   // created by the first batch
+};
+
+struct fpo_job {
+    fpo_context *ctx;
+    hipStream_t stream;
+    hipEvent_t ev_preview, ev_done;
+    void *pinned;                 // Ctrs + DevBox staging
+    fpo_status status;
+    fpo_result res;
+    bool waited;
+    bool timed;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tm[FPO_TIMER_COUNT];
+    uint64_t t_submit, t_done;    // host steady clock, ns (t_done: when a wait or poll saw it end)
+    uint64_t grid_cells;          // G^3
+    fpo::Deferred *def = nullptr; // set for batch and server jobs (the build runs later)
+};
+
+namespace fpo {
+
+// For a deferred job: FPO_OK with *inner once its build was submitted, the
+// status that ended it otherwise (with the error text set), FPO_NOT_READY
+// while it waits or runs and block is false.
+fpo_status deferred_resolve(fpo_job *job, bool block, fpo_job **inner);
+void deferred_release(fpo_job *job);
+void destroy_batch_pool(fpo_context *ctx);
+uint64_t deferred_start_ns(const fpo_job *job);
+
+}  // namespace fpo
