@@ -92,6 +92,121 @@ def cpu_baseline(cloud, p, seconds: float) -> dict:
                       f"(single-threaded C, host CPU)"}
 
 
+def fpo_params_of(fpo, p):
+    return fpo.Params(p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity, p.preview_modulus)
+
+
+def to_device(torch, c):
+    return tuple(torch.from_numpy(a).to("cuda") for a in (c.x, c.y, c.z))
+
+
+def plain_loop(fpo, torch, ctx, items, ws):
+    """Serial plain builds (submit, wait, release), one workspace reused."""
+    for (x, y, z), p in items:
+        job = ctx.submit(x, y, z, p, workspace=ws)
+        job.wait()
+        job.release()
+
+
+def bench_batched(fpo, torch, ctx, rounds: int = 3) -> dict:
+    """The batched workload at reduced scale: a pool of 32 clouds, sizes
+    log-uniform in [10k, 4M], kinds uniform / planes (5-200) / clusters
+    (10-500), per-size parameters; the batch is the pool repeated `rounds`
+    times.  One fpo_build_batch call against the serial loop of plain builds
+    over the same clouds."""
+    import synth
+    mix = synth.batch_mix(32, seed=4)
+    pool = [(to_device(torch, c), fpo_params_of(fpo, p)) for c, p in mix]
+    items = pool * rounds
+    points = sum(int(x.shape[0]) for (x, _, _), _ in items)
+    ws = torch.empty(max(fpo.workspace_size(int(x.shape[0]), p) for (x, _, _), p in pool), dtype=torch.uint8,
+                     device="cuda")
+    plain_loop(fpo, torch, ctx, pool, ws)   # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain_loop(fpo, torch, ctx, items, ws)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t
+    del ws
+    clouds = [c for c, _ in items]
+    params = [p for _, p in items]
+    jobs = ctx.build_batch(clouds, params)   # warm-up (also sizes the workspace)
+    bws = jobs[0].workspace
+    for j in jobs:
+        j.wait()
+        j.release()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    jobs = ctx.build_batch(clouds, params, workspace=bws)
+    for j in jobs:
+        j.wait()
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t
+    for j in jobs:
+        j.release()
+    return {"workload": f"{len(items)} builds: a pool of 32 clouds (10k-4M points, log-uniform; uniform, planes, "
+                        f"clusters) repeated {rounds} times", "points": points,
+            "plain_points_per_s": points / t_plain, "batched_points_per_s": points / t_batch,
+            "speedup": t_plain / t_batch}
+
+
+def bench_served(fpo, torch, ctx, num_requests: int = 64, load: float = 1.25, slots: int = 4) -> dict:
+    """The served workload at reduced scale: requests drawn from a pool of 12
+    clouds (100k-8M points, log-uniform, mixed kinds), Poisson arrivals at
+    `load` times the measured capacity of the serial plain loop.  Latency =
+    completion - arrival; throughput = points / makespan."""
+    import numpy as np
+    import synth
+    mix = synth.batch_mix(12, seed=5, lo=100_000, hi=8_000_000)
+    pool = [(to_device(torch, c), fpo_params_of(fpo, p)) for c, p in mix]
+    rng = np.random.default_rng(5)
+    reqs = [pool[int(k)] for k in rng.integers(0, len(pool), num_requests)]
+    points = sum(int(x.shape[0]) for (x, _, _), _ in reqs)
+    need = [fpo.workspace_size(int(x.shape[0]), p) for (x, _, _), p in reqs]
+    ws = torch.empty(max(need), dtype=torch.uint8, device="cuda")
+    plain_loop(fpo, torch, ctx, pool, ws)   # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain_loop(fpo, torch, ctx, reqs, ws)
+    torch.cuda.synchronize()
+    t_serial = time.perf_counter() - t
+    del ws
+    serial_pps = points / t_serial
+    rate = load * serial_pps / (points / num_requests)   # requests per second
+    gaps = rng.exponential(1.0 / rate, num_requests)
+    budget = int(min(64 << 30, 8 * sum(sorted(need)[-slots:])))
+    srv = fpo.Server(ctx, budget, slots)
+    for (x, y, z), p in pool[:slots]:            # warm-up of the slot streams
+        j = srv.submit(x, y, z, p)
+        j.wait()
+        j.release()
+    jobs = []
+    t0 = time.monotonic()
+    due = t0
+    for ((x, y, z), p), g in zip(reqs, gaps):
+        due += g
+        while time.monotonic() < due:
+            pass
+        jobs.append(srv.submit(x, y, z, p))
+    lat = []
+    first = last = None
+    for j in jobs:
+        j.wait()
+        sub, _, done = j.timestamps()
+        lat.append((done - sub) / 1e6)
+        first = sub if first is None else min(first, sub)
+        last = done if last is None else max(last, done)
+    for j in jobs:
+        j.release()
+    srv.close()
+    lat = np.array(lat)
+    return {"workload": f"{num_requests} requests from a pool of 12 clouds (100k-8M points, log-uniform; uniform, "
+                        f"planes, clusters), Poisson arrivals at {load}x the serial capacity, {slots} slots",
+            "points": points, "serial_points_per_s": serial_pps, "served_points_per_s": points / ((last - first) / 1e9),
+            "speedup": points / ((last - first) / 1e9) / serial_pps,
+            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +215,7 @@ def main():
     ap.add_argument("--workload", default="planes20m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="CPU work budget of the oracle baseline")
+    ap.add_argument("--no-mix", action="store_true", help="skip the batched and served comparisons")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
@@ -183,6 +299,14 @@ def main():
         "path_hbm_frac": b_alg / (ms / 1000.0) / (HBM_PEAK_GBS * 1e9),
         "roofline": roofline,
     }
+    if not args.no_mix:
+        del ws
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(fpo, torch, ctx)
+        print(f"[bench] batched {out['batched']['speedup']:.2f}x the plain loop", file=sys.stderr, flush=True)
+        out["served"] = bench_served(fpo, torch, ctx)
+        print(f"[bench] served {out['served']['speedup']:.2f}x serial, p99 {out['served']['latency_ms_p99']:.1f} ms",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cloud, p, args.cpu_seconds)
     print(json.dumps(out), flush=True)

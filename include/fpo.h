@@ -189,8 +189,9 @@ fpo_status fpo_job_copy_to_host(fpo_job *job, void *host_dst, uint64_t bytes);
 
 /* Host steady-clock times (ns) of a completed job: when it was submitted, when
  * its build started (later than submitted for batch and server jobs that
- * waited for a worker, a slot or memory) and when a wait or poll first saw it
- * complete.  FPO_ERR_INVALID_ARG before completion. */
+ * waited for a worker, a slot or memory) and when it completed (server jobs:
+ * when their slot saw the build end; others: when a wait or poll first saw
+ * it).  FPO_ERR_INVALID_ARG before a wait or poll has seen the completion. */
 fpo_status fpo_job_timestamps(fpo_job *job, uint64_t *submitted_ns, uint64_t *started_ns, uint64_t *completed_ns);
 
 /* ---- batched builds ----------------------------------------------------------

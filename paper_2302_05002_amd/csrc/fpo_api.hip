@@ -707,15 +707,16 @@ fpo_status fpo_job_copy_to_host(fpo_job *job, void *host_dst, uint64_t bytes)
 fpo_status fpo_job_timestamps(fpo_job *job, uint64_t *submitted_ns, uint64_t *started_ns, uint64_t *completed_ns)
 {
     if (!job) return fail(FPO_ERR_INVALID_ARG, "job is NULL");
-    uint64_t sub = job->t_submit, start = job->t_submit;
+    uint64_t sub = job->t_submit, start = job->t_submit, end = 0;
     if (job->def) {
         start = deferred_start_ns(job);
+        end = deferred_end_ns(job);
         FPO_RESOLVE(job, false);
     }
     if (!job->waited) return fail(FPO_ERR_INVALID_ARG, "the job has not completed");
     if (submitted_ns) *submitted_ns = sub;
     if (started_ns) *started_ns = start;
-    if (completed_ns) *completed_ns = job->t_done;
+    if (completed_ns) *completed_ns = end ? end : job->t_done;
     return FPO_OK;
 }
 

@@ -41,6 +41,7 @@ struct Deferred {
     uint64_t arena_off = 0;
     bool has_memory = false;
     uint64_t t_start = 0;
+    uint64_t t_end = 0;           // server jobs: when the slot saw the build end
 };
 
 struct Pool {
@@ -88,7 +89,11 @@ void run_job(Pool *P, fpo_job *job, hipStream_t st)
     const fpo_status s = fpo_build_submit(P->ctx, &d->cloud, &d->params, d->ws, d->ws_bytes, st, &inner);
     const std::string err = s == FPO_OK ? std::string() : error_text();
     // a server slot stays taken until its build has ended
-    if (s == FPO_OK && P->server) (void)hipEventSynchronize(inner->ev_done);
+    uint64_t t_end = 0;
+    if (s == FPO_OK && P->server) {
+        (void)hipEventSynchronize(inner->ev_done);
+        t_end = now_ns();
+    }
     {
         // notified under the lock: once a releaser sees the final state, this
         // thread no longer touches the job
@@ -96,6 +101,7 @@ void run_job(Pool *P, fpo_job *job, hipStream_t st)
         d->inner = inner;
         d->status = s;
         d->err = err;
+        d->t_end = t_end;
         d->state = s == FPO_OK ? Deferred::SUBMITTED : Deferred::FAILED;
         d->cv.notify_all();
     }
@@ -313,6 +319,13 @@ uint64_t deferred_start_ns(const fpo_job *job)
     Deferred *d = job->def;
     std::lock_guard<std::mutex> g(d->m);
     return d->t_start;
+}
+
+uint64_t deferred_end_ns(const fpo_job *job)
+{
+    Deferred *d = job->def;
+    std::lock_guard<std::mutex> g(d->m);
+    return d->t_end;
 }
 
 void deferred_release(fpo_job *job)

@@ -61,5 +61,6 @@ fpo_status deferred_resolve(fpo_job *job, bool block, fpo_job **inner);
 void deferred_release(fpo_job *job);
 void destroy_batch_pool(fpo_context *ctx);
 uint64_t deferred_start_ns(const fpo_job *job);
+uint64_t deferred_end_ns(const fpo_job *job);   // 0 unless a server slot saw the end
 
 }  // namespace fpo
