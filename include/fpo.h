@@ -88,14 +88,24 @@ typedef struct {
     float bbox_max[3];
 } fpo_params;
 
+#define FPO_DEVICE 0u           /* fpo_cloud.location: arrays in device memory */
+#define FPO_HOST_PINNED 1u      /* arrays in pinned host memory, streamed in batches */
+#define FPO_DEFAULT_STREAM_BATCH 16000000ull
+
 /* A point cloud: n points as three float32 arrays (structure of arrays),
- * device pointers, n <= 2^32 - 1 (indices are 32-bit).  Point i is (x[i],
- * y[i], z[i]); i is its original index. */
+ * n <= 2^32 - 1 (indices are 32-bit).  Point i is (x[i], y[i], z[i]); i is
+ * its original index.  With location FPO_HOST_PINNED the arrays are pinned
+ * host memory (hipHostMalloc): they are copied into the workspace in batches
+ * of stream_batch points (0: FPO_DEFAULT_STREAM_BATCH) on a copy stream of
+ * the context, and the bounding-box pass of each batch (and, with a given
+ * box, its quantise + count pass) starts as soon as the batch has landed. */
 typedef struct {
     uint64_t n;
     const float *x;
     const float *y;
     const float *z;
+    uint32_t location;
+    uint64_t stream_batch;
 } fpo_cloud;
 
 /* Result of a build.  Scalars are host values; arrays are device pointers
@@ -145,8 +155,12 @@ void fpo_context_destroy(fpo_context *ctx);
  * The pointer stays valid until the thread's next fpo call. */
 const char *fpo_last_error(void);
 
-/* Worst-case workspace bytes of one build of n points with *p. */
+/* Worst-case workspace bytes of one build of n device-resident points with *p. */
 fpo_status fpo_workspace_size(uint64_t n, const fpo_params *p, uint64_t *bytes);
+
+/* The same for a given cloud: adds the device staging of pinned host inputs
+ * (12 bytes per point). */
+fpo_status fpo_workspace_size_cloud(const fpo_cloud *cloud, const fpo_params *p, uint64_t *bytes);
 
 /* Enqueues a build of *cloud on hip_stream (a hipStream_t; NULL = the
  * context's own stream) using `workspace` (device, >= fpo_workspace_size

@@ -25,7 +25,7 @@ FPO_BBOX_GIVEN = 1
 #: every symbol include/fpo.h declares
 EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_workspace_size",
            "fpo_build_submit", "fpo_job_preview_ready", "fpo_job_poll", "fpo_job_wait",
-           "fpo_job_result", "fpo_job_release", "fpo_job_export_bytes", "fpo_job_copy_to_host",
+           "fpo_job_result", "fpo_job_release", "fpo_workspace_size_cloud", "fpo_job_export_bytes", "fpo_job_copy_to_host",
            "fpo_job_timestamps", "fpo_batch_workspace_size", "fpo_build_batch", "fpo_server_create",
            "fpo_server_submit", "fpo_job_cancel", "fpo_server_destroy", "fpo_context_set_timing", "fpo_job_timer")
 
@@ -46,8 +46,12 @@ class _Params(ctypes.Structure):
                 ("bbox_min", ctypes.c_float * 3), ("bbox_max", ctypes.c_float * 3)]
 
 
+FPO_DEVICE, FPO_HOST_PINNED = 0, 1
+
+
 class _Cloud(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_uint64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p)]
+    _fields_ = [("n", ctypes.c_uint64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("location", ctypes.c_uint32), ("stream_batch", ctypes.c_uint64)]
 
 
 class _Result(ctypes.Structure):
@@ -83,6 +87,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_last_error.restype = ctypes.c_char_p
     lib.fpo_workspace_size.argtypes = [ctypes.c_uint64, P(_Params), P(ctypes.c_uint64)]
     lib.fpo_workspace_size.restype = ctypes.c_int
+    lib.fpo_workspace_size_cloud.argtypes = [P(_Cloud), P(_Params), P(ctypes.c_uint64)]
+    lib.fpo_workspace_size_cloud.restype = ctypes.c_int
     lib.fpo_build_submit.argtypes = [vp, P(_Cloud), P(_Params), vp, ctypes.c_uint64, vp, P(vp)]
     lib.fpo_build_submit.restype = ctypes.c_int
     for f in ("fpo_job_preview_ready", "fpo_job_poll", "fpo_job_wait"):
@@ -181,19 +187,25 @@ class Context:
         """Bracket the timed kernels of later submits with HIP events."""
         _check(_lib.fpo_context_set_timing(self._h, 1 if enable else 0))
 
-    def submit(self, x, y, z, params: Params, workspace=None, stream=None) -> "Job":
-        """Enqueue a build of the device tensors x, y, z (float32, contiguous).
+    def submit(self, x, y, z, params: Params, workspace=None, stream=None, stream_batch: int = 0) -> "Job":
+        """Enqueue a build of x, y, z (float32, contiguous): device tensors,
+        or pinned host tensors (copied in batches of stream_batch points).
         Allocates the workspace with torch when none is given."""
         import torch
         n = int(x.shape[0])
+        host = not x.is_cuda
         for t in (x, y, z):
-            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.shape[0] == n
-        need = workspace_size(n, params)
+            assert t.dtype == torch.float32 and t.is_contiguous() and t.shape[0] == n and t.is_cuda != host
+            assert not host or t.is_pinned(), "host inputs must be pinned"
+        cloud = _Cloud(n, x.data_ptr(), y.data_ptr(), z.data_ptr(), FPO_HOST_PINNED if host else FPO_DEVICE,
+                       int(stream_batch))
+        need = ctypes.c_uint64()
+        _check(_lib.fpo_workspace_size_cloud(ctypes.byref(cloud), ctypes.byref(params.to_c()), ctypes.byref(need)))
+        dev = torch.device("cuda", self.device)
         if workspace is None:
-            workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
-        cloud = _Cloud(n, x.data_ptr(), y.data_ptr(), z.data_ptr())
+            workspace = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
         if stream is None:
-            stream = torch.cuda.current_stream(x.device)
+            stream = torch.cuda.current_stream(dev)
         h = ctypes.c_void_p()
         _check(_lib.fpo_build_submit(self._h, ctypes.byref(cloud), ctypes.byref(params.to_c()),
                                      ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),

@@ -59,6 +59,9 @@ int ilog2(uint32_t v)
 }
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Smallest host-to-device batch of pinned inputs (keeps the partial count bounded).
+constexpr uint64_t MIN_STREAM_BATCH = 1u << 20;
+
 // Small device counters read back by the host.
 struct Ctrs {
     uint32_t num_chunks;
@@ -81,7 +84,7 @@ struct Plan {
     uint64_t maxC, maxW;
     size_t total;
     // results
-    size_t box, bbox_part, ctrs, grid, c_level, c_key, c_count, c_begin, perm;
+    size_t xyz, box, bbox_part, ctrs, grid, c_level, c_key, c_count, c_begin, perm;
     size_t n_depth, n_key, n_mask, n_begin, n_count, n_points, pv_index;
     // temporaries
     size_t code, pyr, fc, ec, lc, fw, ew, lw_, w_level, w_key, w_count, w_start, w_begin;
@@ -92,7 +95,7 @@ struct Plan {
     uint64_t pv_ntiles;
 };
 
-Plan make_plan(uint64_t n, const fpo_params &p)
+Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
 {
     Plan P{};
     P.n = n;
@@ -112,8 +115,12 @@ Plan make_plan(uint64_t n, const fpo_params &p)
         o += a256(bytes ? bytes : 1);
         return r;
     };
+    // pinned host inputs: device staging of x, y, z (a256-aligned thirds)
+    P.xyz = host_in ? take(3 * a256(4 * nn)) : 0;
     P.box = take(sizeof(DevBox));
-    P.bbox_part = take(8 * 4 * BBOX_MAX_BLOCKS);
+    // bounding-box partials: at most one per 1024 points per batch, plus one
+    // per batch (batches of at least MIN_STREAM_BATCH points)
+    P.bbox_part = take(8 * 4 * (nn / 1024 + nn / MIN_STREAM_BATCH + 1 + BBOX_MAX_BLOCKS));
     P.ctrs = take(sizeof(Ctrs));
     P.grid = take(4 * P.G3);
     P.c_level = take(P.maxC);
@@ -210,7 +217,7 @@ fpo_status check_params(uint64_t n, const fpo_params *p)
     return FPO_OK;
 }
 
-uint64_t workspace_bytes(uint64_t n, const fpo_params &p) { return make_plan(n, p).total; }
+uint64_t workspace_bytes(uint64_t n, const fpo_params &p, bool host_input) { return make_plan(n, p, host_input).total; }
 
 }  // namespace fpo
 
@@ -306,6 +313,7 @@ void fpo_context_destroy(fpo_context *c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     destroy_batch_pool(c);
+    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
     for (void *p : c->pinned_free) (void)hipHostFree(p);
     for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(c->stream);
@@ -321,6 +329,18 @@ fpo_status fpo_workspace_size(uint64_t n, const fpo_params *p, uint64_t *bytes)
     return FPO_OK;
 }
 
+fpo_status fpo_workspace_size_cloud(const fpo_cloud *cloud, const fpo_params *p, uint64_t *bytes)
+{
+    if (!cloud) return fail(FPO_ERR_INVALID_ARG, "cloud is NULL");
+    fpo_status s = check_params(cloud->n, p);
+    if (s != FPO_OK) return s;
+    if (!bytes) return fail(FPO_ERR_INVALID_ARG, "bytes is NULL");
+    if (cloud->location != FPO_DEVICE && cloud->location != FPO_HOST_PINNED)
+        return fail(FPO_ERR_INVALID_ARG, "unknown location %u", cloud->location);
+    *bytes = make_plan(cloud->n, *p, cloud->location == FPO_HOST_PINNED).total;
+    return FPO_OK;
+}
+
 fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
                             uint64_t workspace_bytes, void *hip_stream, fpo_job **out)
 {
@@ -331,7 +351,23 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     if (n > 0 && (!cloud->x || !cloud->y || !cloud->z)) return fail(FPO_ERR_INVALID_ARG, "NULL coordinate array");
     if (!workspace) return fail(FPO_ERR_INVALID_ARG, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(FPO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-    const Plan P = make_plan(n, *p);
+    if (cloud->location != FPO_DEVICE && cloud->location != FPO_HOST_PINNED)
+        return fail(FPO_ERR_INVALID_ARG, "unknown location %u", cloud->location);
+    const bool host_in = cloud->location == FPO_HOST_PINNED && n > 0;
+    if (host_in) {
+        // the copies run asynchronously: the arrays must be pinned host memory
+        for (const float *a : {cloud->x, cloud->y, cloud->z}) {
+            hipPointerAttribute_t attr;
+            if (hipPointerGetAttributes(&attr, a) != hipSuccess || attr.type != hipMemoryTypeHost) {
+                (void)hipGetLastError();
+                return fail(FPO_ERR_INVALID_ARG, "location FPO_HOST_PINNED needs pinned host arrays (hipHostMalloc)");
+            }
+        }
+    }
+    uint64_t sbatch = host_in ? (cloud->stream_batch ? cloud->stream_batch : FPO_DEFAULT_STREAM_BATCH) : n;
+    if (host_in && sbatch < MIN_STREAM_BATCH) sbatch = MIN_STREAM_BATCH;
+    sbatch = (sbatch + 63) / 64 * 64;   // batches start on 256-byte boundaries
+    const Plan P = make_plan(n, *p, host_in);
     if (workspace_bytes < P.total)
         return fail(FPO_ERR_OUT_OF_MEMORY, "workspace holds %llu bytes, the build needs %llu",
                     (unsigned long long)workspace_bytes, (unsigned long long)P.total);
@@ -419,20 +455,76 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
 
     // ---- step 1: bbox, quantise, count ----
     const int given = (p->flags & FPO_BBOX_GIVEN) ? 1 : 0;
-    // the scan runs with a given box too: it also detects non-finite values
-    const uint32_t nparts = bbox_blocks(n);
     JobTimer t_bbox(job, FPO_TIMER_BBOX), t_quant(job, FPO_TIMER_QUANTIZE), t_chunk(job, FPO_TIMER_CHUNK_SCATTER),
         t_sub(job, FPO_TIMER_SUBSAMPLE), t_nid(job, FPO_TIMER_NODE_IDS), t_npts(job, FPO_TIMER_NODE_POINTS);
-    t_bbox.begin(st);
-    launch_bbox(cloud->x, cloud->y, cloud->z, n, U32(P.bbox_part), st);
-    t_bbox.end(st);
-    launch_setup(box, U32(P.bbox_part), nparts, given, p->bbox_min, p->bbox_max, st);
+    const float *X = cloud->x, *Y = cloud->y, *Z = cloud->z;
+    if (host_in) {
+        // pinned host input: batches copied into the workspace on the copy
+        // stream (after the work enqueued on st so far, which may still use
+        // the workspace), one event per batch
+        hipStream_t cs;
+        {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            if (!ctx->copy_stream && hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking) != hipSuccess)
+                ctx->copy_stream = nullptr;
+            cs = ctx->copy_stream;
+        }
+        if (!cs) {
+            fpo_job_release(job);
+            return fail(FPO_ERR_DEVICE, "could not create the copy stream");
+        }
+        float *dx = reinterpret_cast<float *>(ws + P.xyz);
+        float *dy = reinterpret_cast<float *>(ws + P.xyz + a256(4 * n));
+        float *dz = reinterpret_cast<float *>(ws + P.xyz + 2 * a256(4 * n));
+        hipEvent_t before;
+        JCHK(hipEventCreateWithFlags(&before, hipEventDisableTiming));
+        job->stream_events.push_back(before);
+        JCHK(hipEventRecord(before, st));
+        JCHK(hipStreamWaitEvent(cs, before, 0));
+        for (uint64_t o = 0; o < n; o += sbatch) {
+            const uint64_t c = n - o < sbatch ? n - o : sbatch;
+            JCHK(hipMemcpyAsync(dx + o, cloud->x + o, 4 * c, hipMemcpyHostToDevice, cs));
+            JCHK(hipMemcpyAsync(dy + o, cloud->y + o, 4 * c, hipMemcpyHostToDevice, cs));
+            JCHK(hipMemcpyAsync(dz + o, cloud->z + o, 4 * c, hipMemcpyHostToDevice, cs));
+            hipEvent_t e;
+            JCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            job->stream_events.push_back(e);
+            JCHK(hipEventRecord(e, cs));
+        }
+        X = dx;
+        Y = dy;
+        Z = dz;
+    }
     uint32_t *pyr = U32(P.pyr);
     uint32_t *fine = pyr + pyr_off(g);
     launch_fill_u32(fine, 0u, P.G3, st);
-    t_quant.begin(st);
-    launch_quantize(cloud->x, cloud->y, cloud->z, n, box, g, given, U64(P.code), fine, box, st);
-    t_quant.end(st);
+    // with a given box the quantise + count pass of a batch can start as soon
+    // as it has landed; the bounding-box pass (non-finite check) runs either way
+    const bool per_batch_quantize = host_in && given;
+    if (per_batch_quantize) launch_setup(box, U32(P.bbox_part), 0, given, p->bbox_min, p->bbox_max, 0, st);
+    uint32_t nparts = 0;
+    size_t bi = 1;
+    for (uint64_t o = 0; o < n; o += sbatch) {
+        const uint64_t c = n - o < sbatch ? n - o : sbatch;
+        if (host_in) JCHK(hipStreamWaitEvent(st, job->stream_events[bi++], 0));
+        t_bbox.begin(st);
+        launch_bbox(X + o, Y + o, Z + o, c, U32(P.bbox_part) + 8ull * nparts, st);
+        t_bbox.end(st);
+        nparts += bbox_blocks(c);
+        if (per_batch_quantize) {
+            t_quant.begin(st);
+            launch_quantize(X + o, Y + o, Z + o, c, box, g, given, U64(P.code) + o, fine, box, st);
+            t_quant.end(st);
+        }
+    }
+    if (per_batch_quantize) {
+        launch_setup(box, U32(P.bbox_part), nparts, given, p->bbox_min, p->bbox_max, 1, st);   // non-finite flag only
+    } else {
+        launch_setup(box, U32(P.bbox_part), nparts, given, p->bbox_min, p->bbox_max, 0, st);
+        t_quant.begin(st);
+        launch_quantize(X, Y, Z, n, box, g, given, U64(P.code), fine, box, st);
+        t_quant.end(st);
+    }
 
     // ---- step 2: pyramid, chunk cut, work-chunk cut ----
     launch_pyramid(pyr, g, st);
@@ -730,6 +822,7 @@ void fpo_job_release(fpo_job *job)
     (void)hipEventSynchronize(job->ev_done);
     (void)hipEventDestroy(job->ev_preview);
     (void)hipEventDestroy(job->ev_done);
+    for (hipEvent_t e : job->stream_events) (void)hipEventDestroy(e);
     if (job->pinned) put_pinned(job->ctx, job->pinned);
     {
         std::lock_guard<std::mutex> g(job->ctx->mu);

@@ -19,7 +19,7 @@ fpo_status fail(fpo_status s, const char *fmt, ...);
 void set_error_text(const std::string &text);
 std::string error_text();
 fpo_status check_params(uint64_t n, const fpo_params *p);
-uint64_t workspace_bytes(uint64_t n, const fpo_params &p);   // worst case of one build
+uint64_t workspace_bytes(uint64_t n, const fpo_params &p, bool host_input = false);   // worst case of one build
 uint64_t now_ns();                                           // steady clock
 
 struct Deferred;   // job created before its build starts (batch, server)
@@ -35,6 +35,7 @@ struct fpo_context {
     bool timing = false;
     std::vector<hipEvent_t> ev_free;   // timing events, reused across jobs
     fpo::Pool *batch_pool = nullptr;   // created by the first batch
+    hipStream_t copy_stream = nullptr; // host-to-device batches of pinned inputs (created on first use)
 };
 
 struct fpo_job {
@@ -49,6 +50,7 @@ struct fpo_job {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tm[FPO_TIMER_COUNT];
     uint64_t t_submit, t_done;    // host steady clock, ns (t_done: when a wait or poll saw it end)
     uint64_t grid_cells;          // G^3
+    std::vector<hipEvent_t> stream_events;   // one per host-to-device batch
     fpo::Deferred *def = nullptr; // set for batch and server jobs (the build runs later)
 };
 

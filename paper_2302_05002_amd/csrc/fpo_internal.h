@@ -65,8 +65,9 @@ void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t words, hipStream_t st);
 constexpr uint32_t BBOX_MAX_BLOCKS = 4096;
 uint32_t bbox_blocks(uint64_t n);
 void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, uint32_t *part, hipStream_t st);
+// flag_only: only the non-finite flag is reduced (the box was set before).
 void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given, const float *lo, const float *hi,
-                  hipStream_t st);
+                  int flag_only, hipStream_t st);
 void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box,
                      int g, int count_outside, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw,
                      hipStream_t st);

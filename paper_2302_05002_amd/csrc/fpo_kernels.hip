@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ x, const
 // scale = 2^21/side computed in double and rounded once to float (0 for a
 // zero side).
 __global__ __launch_bounds__(256) void k_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given, float gx0,
-                                               float gy0, float gz0, float gx1, float gy1, float gz1)
+                                               float gy0, float gz0, float gx1, float gy1, float gz1, int flag_only)
 {
     __shared__ uint32_t red[7][256];
     uint32_t v[7] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u, 0u};
@@ -248,6 +248,7 @@ __global__ __launch_bounds__(256) void k_setup(DevBox *box, const uint32_t *part
         v[6] |= red[6][t];
     }
     box->nonfinite = v[6];
+    if (flag_only) return;   // the box is set already (and points outside it counted)
     box->n_outside = 0;
     float lo[3], hi[3];
     if (given) {
@@ -2036,10 +2037,10 @@ void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, uin
 }
 
 void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given, const float *lo, const float *hi,
-                  hipStream_t st)
+                  int flag_only, hipStream_t st)
 {
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, box, part, nparts, given, lo[0], lo[1], lo[2], hi[0], hi[1],
-                       hi[2]);
+                       hi[2], flag_only);
 }
 
 void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box, int g,

@@ -109,38 +109,46 @@ def _value_noise_params(rng, octaves, base_wavelength, extent):
 
 
 def _fbm(grids, px, py, gain=0.5):
-    h = np.zeros(px.shape[0], dtype=np.float64)
+    """fBm of value noise at (px, py): octaves of bilinear-smoothstep
+    interpolated lattice values, amplitudes gain^o, normalised to [0, 1]."""
+    h = np.zeros(px.shape[0], dtype=np.float32)
     amp = 1.0
     norm = 0.0
     for lam, g in grids:
-        fx = px / lam
-        fy = py / lam
-        ix = np.floor(fx).astype(np.int64)
-        iy = np.floor(fy).astype(np.int64)
+        cells = g.shape[1]
+        flat = g.astype(np.float32).ravel()
+        fx = px * np.float32(1.0 / lam)
+        fy = py * np.float32(1.0 / lam)
+        ix = fx.astype(np.int32)          # px, py >= 0: truncation is floor
+        iy = fy.astype(np.int32)
         tx = fx - ix
         ty = fy - iy
         tx = tx * tx * (3 - 2 * tx)
         ty = ty * ty * (3 - 2 * ty)
-        v00 = g[ix, iy]
-        v10 = g[ix + 1, iy]
-        v01 = g[ix, iy + 1]
-        v11 = g[ix + 1, iy + 1]
-        h += amp * ((v00 * (1 - tx) + v10 * tx) * (1 - ty) + (v01 * (1 - tx) + v11 * tx) * ty)
+        i00 = ix * cells + iy
+        v00 = flat.take(i00)
+        v01 = flat.take(i00 + 1)
+        v10 = flat.take(i00 + cells)
+        v11 = flat.take(i00 + cells + 1)
+        h += np.float32(amp) * ((v00 + (v10 - v00) * tx) * (1 - ty) + (v01 + (v11 - v01) * tx) * ty)
         norm += amp
         amp *= gain
-    return h / norm
+    return h / np.float32(norm)
 
 
 def terrain_clusters(n: int, seed: int = 3, extent: float = 1000.0, relief: float = 100.0,
                      cluster_fraction: float = 0.2, cluster_size: int = 8000,
                      cluster_sigma: float = 0.5, octaves: int = 8, base_wavelength: float = 250.0,
-                     colors: bool = True, rgba: bool = True) -> Cloud:
+                     colors: bool = True, rgba: bool = True, block: int = 4_000_000, workers: int = 8) -> Cloud:
     """Aerial terrain (an fBm value-noise heightfield over [0, extent)^2 with the
     given relief) plus dense Gaussian clusters (vegetation, buildings) holding
     cluster_fraction of the points, each cluster_size points of standard
     deviation cluster_sigma, centred on the terrain plus U[0, 20] m of height.
-    Terrain points come first, then the clusters one after another."""
-    rng = np.random.Generator(np.random.PCG64(seed))
+    Terrain points come first (blocks of `block` points, block k drawn from
+    PCG64([seed, 1, k]), so the result does not depend on `workers`), then
+    the clusters one after another."""
+    from concurrent.futures import ThreadPoolExecutor
+    rng = np.random.Generator(np.random.PCG64([seed, 0]))
     grids = _value_noise_params(rng, octaves, base_wavelength, extent)
     n_cl_pts = int(round(n * cluster_fraction))
     num_clusters = max(1, int(round(n_cl_pts / cluster_size))) if n_cl_pts > 0 else 0
@@ -148,28 +156,30 @@ def terrain_clusters(n: int, seed: int = 3, extent: float = 1000.0, relief: floa
     x = np.empty(n, dtype=np.float32)
     y = np.empty(n, dtype=np.float32)
     z = np.empty(n, dtype=np.float32)
-    step = 8_000_000
-    pos = 0
-    while pos < n_terrain:
-        b = min(step, n_terrain - pos)
-        px = rng.uniform(0.0, extent, size=b)
-        py = rng.uniform(0.0, extent, size=b)
-        x[pos:pos + b] = px
-        y[pos:pos + b] = py
-        z[pos:pos + b] = _fbm(grids, px, py) * relief
-        pos += b
+
+    def terrain_block(k):
+        lo = k * block
+        b = min(block, n_terrain - lo)
+        r = np.random.Generator(np.random.PCG64([seed, 1, k]))
+        px = r.random(b, dtype=np.float32) * np.float32(extent)
+        py = r.random(b, dtype=np.float32) * np.float32(extent)
+        x[lo:lo + b] = px
+        y[lo:lo + b] = py
+        z[lo:lo + b] = _fbm(grids, px, py) * np.float32(relief)
+
+    nblocks = (n_terrain + block - 1) // block
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        list(ex.map(terrain_block, range(nblocks)))
     if num_clusters:
-        per = _split_exact(np.ones(num_clusters), n_cl_pts)
-        cx = rng.uniform(0.0, extent, size=num_clusters)
-        cy = rng.uniform(0.0, extent, size=num_clusters)
-        cz = _fbm(grids, cx, cy) * relief + rng.uniform(0.0, 20.0, size=num_clusters)
-        for k in range(num_clusters):
-            m = int(per[k])
-            p = rng.normal(scale=cluster_sigma, size=(m, 3))
-            x[pos:pos + m] = cx[k] + p[:, 0]
-            y[pos:pos + m] = cy[k] + p[:, 1]
-            z[pos:pos + m] = cz[k] + p[:, 2]
-            pos += m
+        per = _split_exact(np.ones(num_clusters), n_cl_pts).astype(np.int64)
+        cx = rng.uniform(0.0, extent, size=num_clusters).astype(np.float32)
+        cy = rng.uniform(0.0, extent, size=num_clusters).astype(np.float32)
+        cz = (_fbm(grids, cx, cy) * np.float32(relief)
+              + rng.uniform(0.0, 20.0, size=num_clusters).astype(np.float32))
+        noise = rng.normal(scale=cluster_sigma, size=(n_cl_pts, 3)).astype(np.float32)
+        x[n_terrain:] = np.repeat(cx, per) + noise[:, 0]
+        y[n_terrain:] = np.repeat(cy, per) + noise[:, 1]
+        z[n_terrain:] = np.repeat(cz, per) + noise[:, 2]
     rgb = rng.integers(0, 256, size=(n, 4 if rgba else 3), dtype=np.uint8) if colors else None
     return Cloud(x, y, z, rgb, "terrain_clusters", {"num_clusters": num_clusters})
 
@@ -231,7 +241,7 @@ def config2(n: int = 20_000_000) -> Cloud:
 
 def config3(n: int = 200_000_000) -> Cloud:
     """Out-of-core build: terrain plus clusters (200M points at full size)."""
-    return terrain_clusters(n, seed=3)
+    return terrain_clusters(n, seed=3, colors=False)
 
 
 def batch_mix(num_clouds: int = 256, seed: int = 4, lo: int = 10_000, hi: int = 4_000_000,
