@@ -207,6 +207,56 @@ def bench_served(fpo, torch, ctx, num_requests: int = 64, load: float = 1.25, sl
             "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99))}
 
 
+def bench_streamed(fpo, torch, ctx, steps: int = 3) -> dict:
+    """The out-of-core workload: 200M points of terrain plus clusters in
+    pinned host memory, copied to the device in 16M-point batches with the
+    exact box given as a header (G=512, C=2M, S=128, L=10k, M=64).  Bound by
+    the host link: reported against a plain pinned copy of the same bytes.
+    Also the time until the preview is ready (it depends only on n)."""
+    import synth
+    c = synth.config3()
+    p = synth.CONFIG3
+    box = ((float(c.x.min()), float(c.y.min()), float(c.z.min())),
+           (float(c.x.max()), float(c.y.max()), float(c.z.max())))
+    params = fpo.Params(p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity, p.preview_modulus,
+                        box)
+    host = [torch.from_numpy(a).pin_memory() for a in (c.x, c.y, c.z)]
+    del c
+    n = int(host[0].shape[0])
+    dev = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(3)]
+    for d, h in zip(dev, host):   # warm-up
+        d.copy_(h, non_blocking=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for d, h in zip(dev, host):
+        d.copy_(h, non_blocking=True)
+    torch.cuda.synchronize()
+    link = 12 * n / (time.perf_counter() - t)
+    del dev
+    torch.cuda.empty_cache()
+    job = ctx.submit(*host, params, stream_batch=16_000_000)   # warm-up, sizes the workspace
+    job.wait()
+    ws = job.workspace
+    job.release()
+    times, previews = [], []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        job = ctx.submit(*host, params, workspace=ws, stream_batch=16_000_000)
+        while not job.preview_ready():
+            pass
+        previews.append(time.perf_counter() - t)
+        job.wait()
+        times.append(time.perf_counter() - t)
+        job.release()
+    t_build = sorted(times)[len(times) // 2]
+    return {"workload": "200M points (terrain + 5000 clusters) in pinned host memory, 16M-point batches, box given; "
+                        "G=512, C=2M, S=128, L=10k, M=64",
+            "points_per_s": n / t_build, "ms_per_build": 1000 * t_build,
+            "h2d_GBps": link / 1e9, "link_frac": (12 * n / link) / t_build,
+            "preview_ready_ms": 1000 * sorted(previews)[len(previews) // 2]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +266,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="CPU work budget of the oracle baseline")
     ap.add_argument("--no-mix", action="store_true", help="skip the batched and served comparisons")
+    ap.add_argument("--no-stream", action="store_true", help="skip the streamed 200M-point build")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
@@ -307,6 +358,12 @@ def main():
         out["served"] = bench_served(fpo, torch, ctx)
         print(f"[bench] served {out['served']['speedup']:.2f}x serial, p99 {out['served']['latency_ms_p99']:.1f} ms",
               file=sys.stderr, flush=True)
+    if not args.no_stream:
+        if not args.no_mix:
+            torch.cuda.empty_cache()
+        out["streamed"] = bench_streamed(fpo, torch, ctx)
+        print(f"[bench] streamed {out['streamed']['points_per_s'] / 1e9:.2f} G points/s, "
+              f"{out['streamed']['link_frac']:.2f} of the host link", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cloud, p, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -162,12 +162,16 @@ fpo_status fpo_workspace_size(uint64_t n, const fpo_params *p, uint64_t *bytes);
  * (12 bytes per point). */
 fpo_status fpo_workspace_size_cloud(const fpo_cloud *cloud, const fpo_params *p, uint64_t *bytes);
 
-/* Enqueues a build of *cloud on hip_stream (a hipStream_t; NULL = the
- * context's own stream) using `workspace` (device, >= fpo_workspace_size
- * bytes, 256-byte aligned, owned by the caller).  The preview kernels are
- * enqueued first.  *out receives a job handle; release it with
- * fpo_job_release.  Returns FPO_ERR_NONFINITE when a coordinate is not
- * finite; other errors before any work is enqueued. */
+/* Queues a build of *cloud on hip_stream (a hipStream_t; NULL = the
+ * context's own stream) using `workspace` (device, >= fpo_workspace_size_cloud
+ * bytes, 256-byte aligned, owned by the caller) and returns at once: the
+ * caller is never blocked by the build.  A thread of the context enqueues the
+ * builds in submission order, the preview kernels first, so the preview is
+ * ready (fpo_job_preview_ready) long before the tree; the rest of the build
+ * needs a few host round trips, which that thread takes.  *out receives the
+ * job; release it with fpo_job_release.  Argument errors are returned here,
+ * before anything is queued; a non-finite coordinate (FPO_ERR_NONFINITE) is
+ * reported by fpo_job_poll / fpo_job_wait. */
 fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
                             uint64_t workspace_bytes, void *hip_stream, fpo_job **out);
 

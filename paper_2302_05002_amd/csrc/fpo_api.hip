@@ -1,6 +1,7 @@
 // Host side of libfpo: argument checks, workspace layout and the launch
 // sequence of one build (C ABI in include/fpo.h).
 #include <chrono>
+#include <functional>
 #include <mutex>
 #include <stdarg.h>
 #include <stdio.h>
@@ -341,8 +342,49 @@ fpo_status fpo_workspace_size_cloud(const fpo_cloud *cloud, const fpo_params *p,
     return FPO_OK;
 }
 
-fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
-                            uint64_t workspace_bytes, void *hip_stream, fpo_job **out)
+}  // extern "C"
+
+namespace fpo {
+
+// Checks every argument of a build; fills the stream batch and the plan size.
+static fpo_status check_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
+                              uint64_t workspace_bytes)
+{
+    if (!ctx || !cloud) return fail(FPO_ERR_INVALID_ARG, "NULL context or cloud");
+    fpo_status s = check_params(cloud->n, p);
+    if (s != FPO_OK) return s;
+    const uint64_t n = cloud->n;
+    if (n > 0 && (!cloud->x || !cloud->y || !cloud->z)) return fail(FPO_ERR_INVALID_ARG, "NULL coordinate array");
+    if (!workspace) return fail(FPO_ERR_INVALID_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(FPO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (cloud->location != FPO_DEVICE && cloud->location != FPO_HOST_PINNED)
+        return fail(FPO_ERR_INVALID_ARG, "unknown location %u", cloud->location);
+    const bool host_in = cloud->location == FPO_HOST_PINNED && n > 0;
+    if (host_in) {
+        // the copies run asynchronously: the arrays must be pinned host memory
+        for (const float *a : {cloud->x, cloud->y, cloud->z}) {
+            hipPointerAttribute_t attr;
+            if (hipPointerGetAttributes(&attr, a) != hipSuccess || attr.type != hipMemoryTypeHost) {
+                (void)hipGetLastError();
+                return fail(FPO_ERR_INVALID_ARG, "location FPO_HOST_PINNED needs pinned host arrays (hipHostMalloc)");
+            }
+        }
+    }
+    const uint64_t need = make_plan(n, *p, host_in).total;
+    if (workspace_bytes < need)
+        return fail(FPO_ERR_OUT_OF_MEMORY, "workspace holds %llu bytes, the build needs %llu",
+                    (unsigned long long)workspace_bytes, (unsigned long long)need);
+    return FPO_OK;
+}
+
+// Enqueues one whole build on st, with the host round trips it needs (the
+// counts of chunks, work chunks and nodes size later launches).  on_preview,
+// if given, receives the job as soon as the preview kernels are enqueued;
+// from then on the job is never freed here: an error later ends it with its
+// status set (and its done event recorded) for the caller to release.
+fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
+                       uint64_t workspace_bytes, hipStream_t st, fpo_job **out,
+                       const std::function<void(fpo_job *)> &on_preview)
 {
     if (!ctx || !cloud || !out) return fail(FPO_ERR_INVALID_ARG, "NULL context, cloud or out");
     fpo_status s = check_params(cloud->n, p);
@@ -372,7 +414,6 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
         return fail(FPO_ERR_OUT_OF_MEMORY, "workspace holds %llu bytes, the build needs %llu",
                     (unsigned long long)workspace_bytes, (unsigned long long)P.total);
     HIPCHK(hipSetDevice(ctx->device));
-    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->stream;
 
     fpo_job *job = new fpo_job();
     job->ctx = ctx;
@@ -426,13 +467,24 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     R.node_points = U32(P.n_points);
     R.preview_index = U32(P.pv_index);
 
+    bool published = false;
+    // ends the job with status fs: freed if nobody holds it yet, else left to
+    // its holder with the done event recorded
+    auto end_job = [&](fpo_status fs) {
+        if (!published) {
+            fpo_job_release(job);
+        } else {
+            job->status = fs;
+            (void)hipEventRecord(job->ev_done, st);
+        }
+        return fs;
+    };
 #define JCHK(call)                                                                              \
     do {                                                                                        \
         hipError_t e_ = (call);                                                                 \
         if (e_ != hipSuccess) {                                                                 \
             fpo_status fs_ = fail(FPO_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_));      \
-            fpo_job_release(job);                                                               \
-            return fs_;                                                                         \
+            return end_job(fs_);                                                                \
         }                                                                                       \
     } while (0)
 
@@ -441,6 +493,8 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
         launch_fill_u32(U32(P.grid), 0u, P.G3, st);
         JCHK(hipEventRecord(job->ev_preview, st));
         JCHK(hipEventRecord(job->ev_done, st));
+        published = true;
+        if (on_preview) on_preview(job);
         if (p->flags & FPO_BBOX_GIVEN)
             for (int a = 0; a < 3; ++a) { R.bbox_min[a] = p->bbox_min[a]; R.bbox_max[a] = p->bbox_max[a]; }
         *out = job;
@@ -452,6 +506,8 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     scan_exclusive(U32(P.pv_tiles), U32(P.pv_offs), P.pv_ntiles, &ctrs->preview_count, stemp, st);
     launch_preview_write(n, M, U32(P.pv_offs), U32(P.pv_index), st);
     JCHK(hipEventRecord(job->ev_preview, st));
+    published = true;
+    if (on_preview) on_preview(job);
 
     // ---- step 1: bbox, quantise, count ----
     const int given = (p->flags & FPO_BBOX_GIVEN) ? 1 : 0;
@@ -469,10 +525,7 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
                 ctx->copy_stream = nullptr;
             cs = ctx->copy_stream;
         }
-        if (!cs) {
-            fpo_job_release(job);
-            return fail(FPO_ERR_DEVICE, "could not create the copy stream");
-        }
+        if (!cs) return end_job(fail(FPO_ERR_DEVICE, "could not create the copy stream"));
         float *dx = reinterpret_cast<float *>(ws + P.xyz);
         float *dy = reinterpret_cast<float *>(ws + P.xyz + a256(4 * n));
         float *dz = reinterpret_cast<float *>(ws + P.xyz + 2 * a256(4 * n));
@@ -547,8 +600,7 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
     JCHK(hipMemcpyAsync(hbox, box, sizeof(DevBox), hipMemcpyDeviceToHost, st));
     JCHK(hipStreamSynchronize(st));
     if (hbox->nonfinite) {
-        fpo_job_release(job);
-        return fail(FPO_ERR_NONFINITE, "a coordinate is NaN or infinite");
+        return end_job(fail(FPO_ERR_NONFINITE, "a coordinate is NaN or infinite"));
     }
     const uint32_t num_chunks = hctrs->num_chunks, num_wc = hctrs->num_wc;
 
@@ -671,22 +723,37 @@ fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_
 #undef JCHK
 }
 
+}  // namespace fpo
+
+extern "C" {
+
+fpo_status fpo_build_submit(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
+                            uint64_t workspace_bytes, void *hip_stream, fpo_job **out)
+{
+    if (!out) return fail(FPO_ERR_INVALID_ARG, "out is NULL");
+    const fpo_status s = check_build(ctx, cloud, p, workspace, workspace_bytes);
+    if (s != FPO_OK) return s;
+    return queue_build(ctx, cloud, p, workspace, workspace_bytes,
+                       hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->stream, out);
+}
+
 // A batch or server job first waits for its build to be submitted; its
 // calls then act on the submitted build.
-#define FPO_RESOLVE(job, block)                                   \
+#define FPO_RESOLVE_(job, block, preview)                         \
     do {                                                          \
         if ((job)->def) {                                         \
             fpo_job *inner_ = nullptr;                            \
-            const fpo_status r_ = deferred_resolve(job, block, &inner_); \
+            const fpo_status r_ = deferred_resolve(job, block, preview, &inner_); \
             if (r_ != FPO_OK) return r_;                          \
             job = inner_;                                         \
         }                                                         \
     } while (0)
+#define FPO_RESOLVE(job, block) FPO_RESOLVE_(job, block, false)
 
 fpo_status fpo_job_preview_ready(fpo_job *job)
 {
     if (!job) return fail(FPO_ERR_INVALID_ARG, "job is NULL");
-    FPO_RESOLVE(job, false);
+    FPO_RESOLVE_(job, false, true);
     hipError_t e = hipEventQuery(job->ev_preview);
     if (e == hipSuccess) return FPO_OK;
     if (e == hipErrorNotReady) return FPO_NOT_READY;

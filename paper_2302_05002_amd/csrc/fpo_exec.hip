@@ -24,7 +24,9 @@ namespace fpo {
 struct Server;
 
 struct Deferred {
-    enum State { QUEUED, RUNNING, SUBMITTED, FAILED, CANCELLED };
+    // QUEUED -> RUNNING -> PREVIEW (preview kernels enqueued, inner known)
+    // -> SUBMITTED (whole build enqueued; server jobs: ended) or FAILED
+    enum State { QUEUED, RUNNING, PREVIEW, SUBMITTED, FAILED, CANCELLED };
     std::mutex m;
     std::condition_variable cv;
     State state = QUEUED;
@@ -36,6 +38,7 @@ struct Deferred {
     void *ws = nullptr;
     uint64_t ws_bytes = 0;
     hipEvent_t after = nullptr;   // the build waits for it (work the caller enqueued before the batch)
+    hipStream_t stream = nullptr; // the caller's stream (plain builds); else the worker's
     Pool *pool = nullptr;         // batch pool the job is queued in
     Server *server = nullptr;
     uint64_t arena_off = 0;
@@ -84,9 +87,16 @@ void run_job(Pool *P, fpo_job *job, hipStream_t st)
         d->state = Deferred::RUNNING;
         d->t_start = now_ns();
     }
+    if (d->stream) st = d->stream;
     if (d->after) (void)hipStreamWaitEvent(st, d->after, 0);
     fpo_job *inner = nullptr;
-    const fpo_status s = fpo_build_submit(P->ctx, &d->cloud, &d->params, d->ws, d->ws_bytes, st, &inner);
+    const fpo_status s = issue_build(P->ctx, &d->cloud, &d->params, d->ws, d->ws_bytes, st, &inner,
+                                     [d](fpo_job *j) {
+                                         std::lock_guard<std::mutex> g(d->m);
+                                         d->inner = j;
+                                         d->state = Deferred::PREVIEW;
+                                         d->cv.notify_all();
+                                     });
     const std::string err = s == FPO_OK ? std::string() : error_text();
     // a server slot stays taken until its build has ended
     uint64_t t_end = 0;
@@ -98,7 +108,7 @@ void run_job(Pool *P, fpo_job *job, hipStream_t st)
         // notified under the lock: once a releaser sees the final state, this
         // thread no longer touches the job
         std::lock_guard<std::mutex> g(d->m);
-        d->inner = inner;
+        if (inner) d->inner = inner;   // (a build that failed after its preview keeps the published job)
         d->status = s;
         d->err = err;
         d->t_end = t_end;
@@ -292,15 +302,18 @@ bool cancel_queued(fpo_job *job)
 
 }  // namespace
 
-fpo_status deferred_resolve(fpo_job *job, bool block, fpo_job **inner)
+fpo_status deferred_resolve(fpo_job *job, bool block, bool preview, fpo_job **inner)
 {
     Deferred *d = job->def;
     std::unique_lock<std::mutex> lk(d->m);
-    if (block) d->cv.wait(lk, [&] { return d->state != Deferred::QUEUED && d->state != Deferred::RUNNING; });
+    auto pending = [&] {
+        return d->state == Deferred::QUEUED || d->state == Deferred::RUNNING ||
+               (!preview && d->state == Deferred::PREVIEW);
+    };
+    if (block) d->cv.wait(lk, [&] { return !pending(); });
+    if (pending()) return FPO_NOT_READY;
     switch (d->state) {
-    case Deferred::QUEUED:
-    case Deferred::RUNNING:
-        return FPO_NOT_READY;
+    case Deferred::PREVIEW:
     case Deferred::SUBMITTED:
         *inner = d->inner;
         return FPO_OK;
@@ -334,7 +347,9 @@ void deferred_release(fpo_job *job)
     (void)cancel_queued(job);   // a job that has not started never will
     {
         std::unique_lock<std::mutex> lk(d->m);
-        d->cv.wait(lk, [&] { return d->state != Deferred::QUEUED && d->state != Deferred::RUNNING; });
+        d->cv.wait(lk, [&] {
+            return d->state != Deferred::QUEUED && d->state != Deferred::RUNNING && d->state != Deferred::PREVIEW;
+        });
     }
     if (d->inner) fpo_job_release(d->inner);
     if (d->server && d->has_memory) {
@@ -353,13 +368,38 @@ void deferred_release(fpo_job *job)
 
 void destroy_batch_pool(fpo_context *ctx)
 {
-    Pool *P = nullptr;
+    Pool *P = nullptr, *I = nullptr;
     {
         std::lock_guard<std::mutex> g(ctx->mu);
         P = ctx->batch_pool;
-        ctx->batch_pool = nullptr;
+        I = ctx->issue_pool;
+        ctx->batch_pool = ctx->issue_pool = nullptr;
     }
+    stop_pool(I);
     stop_pool(P);
+}
+
+fpo_status queue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
+                       uint64_t workspace_bytes, hipStream_t st, fpo_job **out)
+{
+    Pool *P;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        if (!ctx->issue_pool) ctx->issue_pool = make_pool(ctx, nullptr, 1);
+        P = ctx->issue_pool;
+    }
+    if (!P) return fail(FPO_ERR_DEVICE, "could not start the issuing thread");
+    fpo_job *job = new_deferred_job(ctx);
+    Deferred *d = job->def;
+    d->cloud = *cloud;
+    d->params = *p;
+    d->ws = workspace;
+    d->ws_bytes = workspace_bytes;
+    d->stream = st;
+    d->pool = P;
+    *out = job;
+    pool_push(P, job);
+    return FPO_OK;
 }
 
 }  // namespace fpo

@@ -3,6 +3,7 @@
 // executors (batch, server) use.  Not part of the public C ABI.
 #pragma once
 #include <stdint.h>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -35,6 +36,7 @@ struct fpo_context {
     bool timing = false;
     std::vector<hipEvent_t> ev_free;   // timing events, reused across jobs
     fpo::Pool *batch_pool = nullptr;   // created by the first batch
+    fpo::Pool *issue_pool = nullptr;   // issues plain builds in submission order (created by the first)
     hipStream_t copy_stream = nullptr; // host-to-device batches of pinned inputs (created on first use)
 };
 
@@ -56,12 +58,21 @@ struct fpo_job {
 
 namespace fpo {
 
-// For a deferred job: FPO_OK with *inner once its build was submitted, the
-// status that ended it otherwise (with the error text set), FPO_NOT_READY
-// while it waits or runs and block is false.
-fpo_status deferred_resolve(fpo_job *job, bool block, fpo_job **inner);
+// For a deferred job: FPO_OK with *inner once its build has been enqueued
+// whole (preview: once its preview kernels have), the status that ended it
+// otherwise (with the error text set), FPO_NOT_READY before that when block
+// is false.
+fpo_status deferred_resolve(fpo_job *job, bool block, bool preview, fpo_job **inner);
 void deferred_release(fpo_job *job);
 void destroy_batch_pool(fpo_context *ctx);
+
+// Enqueues a whole build on st from the calling thread (see fpo_api.hip).
+fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
+                       uint64_t workspace_bytes, hipStream_t st, fpo_job **out,
+                       const std::function<void(fpo_job *)> &on_preview);
+// Hands a checked build to the context's issuing thread; *out at once.
+fpo_status queue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
+                       uint64_t workspace_bytes, hipStream_t st, fpo_job **out);
 uint64_t deferred_start_ns(const fpo_job *job);
 uint64_t deferred_end_ns(const fpo_job *job);   // 0 unless a server slot saw the end
 
