@@ -17,12 +17,12 @@ constexpr int P1_BLOCK = 1024;
 constexpr int P1_ITEMS = 4;
 constexpr uint32_t WC_CAP = P1_BLOCK * P1_ITEMS;   // 4096
 constexpr uint32_t WC_HASH = 2 * WC_CAP;           // 8192 slots, load <= 1/2
-// Size classes of the LDS path.  Classes 0-4: work chunks of at most L points
+// Size classes of the LDS path.  Classes 0-5: work chunks of at most L points
 // (their own root is a leaf, so only the shared ancestors are subsampled),
-// up to 256 / 512 / 1024 / 2048 / 4096 points.  Classes 5-9: the general
-// subtree, same sizes.
-constexpr int WC_CLASSES = 10;
-constexpr int WC_GENERAL = 5;
+// up to 256 / 512 / 1024 / 2048 / 4096 / 8192 points.  Classes 6-10: the
+// general subtree, up to 256 ... 4096 points.
+constexpr int WC_CLASSES = 11;
+constexpr int WC_GENERAL = 6;
 
 constexpr int MS_BLOCK = 256;                // multisplit block (4 waves)
 constexpr int MS_ITEMS = 8;                  // elements per thread

@@ -1435,11 +1435,12 @@ __global__ __launch_bounds__(BLOCK) void k_subsample_lds(WcArgs a, int cls)
 // and class.
 __device__ __forceinline__ uint32_t wc_size_class(uint32_t n)
 {
-    return n <= 256 ? 0u : n <= 512 ? 1u : n <= 1024 ? 2u : n <= 2048 ? 3u : n <= WC_CAP ? 4u : 0xffu;
+    return n <= 256 ? 0u : n <= 512 ? 1u : n <= 1024 ? 2u : n <= 2048 ? 3u : n <= WC_CAP ? 4u : n <= 2 * WC_CAP ? 5u : 0xffu;
 }
 
 // Shared-ancestor pass of a work chunk whose own root is a leaf (at most L
-// points, so no local subtree below it): at every shared depth d < lw each
+// points, so no local subtree below it; up to 8192 points, which only work
+// chunks at the deepest work-chunk level can hold): at every shared depth d < lw each
 // alive point competes for its cell of level d + s (relative to the work
 // chunk: 3(d + s - lw) bits), the lowest position wins and stays at depth d,
 // the others go on; what is left sits in the root at depth lw.  Each point
@@ -1449,7 +1450,7 @@ __device__ __forceinline__ uint32_t wc_size_class(uint32_t n)
 //
 // Cell table, one atomicMin of the position per point and round:
 //  - while the cell key fits the table it is the slot, and the entry is
-//    (31 - d) << 12 | position, so entries of shallower depths are replaced
+//    (31 - d) << 12 (13) | position, so entries of shallower depths are replaced
 //    by the same atomicMin (no clearing per depth);
 //  - longer keys are hashed without probing: every point writes its
 //    position into slot h_r(cell), reads back the winning position and that
@@ -1470,7 +1471,8 @@ __global__ __launch_bounds__(BLOCK) void k_subsample_fast(WcArgs a, int cls)
     constexpr int NW = BLOCK / 64;
     constexpr uint32_t ALIVE = 0xffu << 24;
     constexpr uint32_t EMPTY = 0xffffffffu;
-    static_assert(CAP <= 4096, "positions are packed in 12 bits");
+    constexpr int PB = CAP <= 4096 ? 12 : 13;   // position bits of a direct-mode entry
+    static_assert(CAP <= 8192, "positions are packed in 13 bits");
     static_assert(TSZ >= 2 * CAP, "table of at least two slots per point");
     __shared__ uint4 table4[TSZ / 4];
     uint32_t *table = reinterpret_cast<uint32_t *>(table4);
@@ -1526,7 +1528,7 @@ __global__ __launch_bounds__(BLOCK) void k_subsample_fast(WcArgs a, int cls)
                     clean = true;
                 }
                 __syncthreads();
-                const uint32_t tag = (31u - (uint32_t)d) << 12;
+                const uint32_t tag = (31u - (uint32_t)d) << PB;
 #pragma unroll
                 for (int j = 0; j < ITEMS; ++j)
                     if (it[j] >= ALIVE) atomicMin(&table[(it[j] & 0xffffffu) >> sh], tag | (j * BLOCK + threadIdx.x));
@@ -1620,7 +1622,7 @@ __global__ void k_list_classes(WcArgs a)
             const uint32_t n = a.wc_count[w];
             c = wc_size_class(n);
             if (!a.wc_nested[w]) c = 0xffu;
-            else if (c != 0xffu && !(n <= a.L && a.s <= 7)) c += WC_GENERAL;
+            else if (c != 0xffu && !(n <= a.L && a.s <= 7)) c = c < 5 ? c + WC_GENERAL : 0xffu;
         }
         for (uint32_t k = 0; k <= (uint32_t)WC_CLASSES; ++k) {
             const uint32_t kc = k == (uint32_t)WC_CLASSES ? 0xffu : k;
@@ -2105,6 +2107,8 @@ void launch_subsample_small(const WcArgs &a, hipStream_t st)
     hipLaunchKernelGGL((k_subsample_fast<64, 16, 12>), dim3(gs), dim3(64), 0, st, a, 2);
     hipLaunchKernelGGL((k_subsample_fast<128, 16, 13>), dim3(gs), dim3(128), 0, st, a, 3);
     hipLaunchKernelGGL((k_subsample_fast<256, 16, 13>), dim3(gs), dim3(256), 0, st, a, 4);
+    // oversized work chunks at the deepest work-chunk level (dense clusters)
+    hipLaunchKernelGGL((k_subsample_fast<1024, 8, 14>), dim3(gs < 2048 ? gs : 2048), dim3(1024), 0, st, a, 5);
     // the general subtree: single-wave blocks for the small classes, many per CU
     hipLaunchKernelGGL((k_subsample_lds<64, 4>), dim3(gs), dim3(64), 0, st, a, WC_GENERAL + 0);
     hipLaunchKernelGGL((k_subsample_lds<64, 8>), dim3(gs), dim3(64), 0, st, a, WC_GENERAL + 1);

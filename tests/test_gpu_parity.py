@@ -221,3 +221,13 @@ def test_many_tiny_work_chunks(ctx):
     c = spike_cloud()
     run_both(ctx, c, 128, 100_000, 128, 10_000, 8)
     run_both(ctx, c, 128, 1_000, 128, 300, 8)
+
+
+def test_oversized_work_chunks(ctx):
+    """Dense clusters inside one cell of the deepest work-chunk level: work
+    chunks of 4097-8192 points whose root is a leaf (wide LDS instance), and
+    of more than 8192 points (global-memory path)."""
+    c = synth.clusters(100_000, seed=23, num_clusters=15, sigma_frac=0.0005)   # 14 of 6667 points
+    run_both(ctx, c, 128, 1_000_000, 128, 10_000, 64)
+    c = synth.clusters(120_000, seed=24, num_clusters=12, sigma_frac=0.0004)   # 10 of 10000 points
+    run_both(ctx, c, 128, 1_000_000, 128, 12_000, 64)
