@@ -80,7 +80,7 @@ struct Ctrs {
 // Byte offsets of every region of the workspace for (n, params).
 struct Plan {
     uint64_t n;
-    int g, s, lam_w;
+    int g, s, lam_w, d0;
     uint64_t G3, W3, P;      // finest cells, work-chunk-level cells, pyramid words
     uint64_t maxC, maxW;
     size_t total;
@@ -90,7 +90,7 @@ struct Plan {
     // temporaries
     size_t code, pyr, fc, ec, lc, fw, ew, lw_, w_level, w_key, w_count, w_start, w_begin;
     size_t c_count_scan, code_perm, wc_orig, wc_code, ms_temp, scan_temp, seg_b0, seg_nb, wc_nested, wc_chunk;
-    size_t t, fr, alive, alive_scan, kd, loff, owned, node_base, lnode_key, lnode_mask, cut;
+    size_t gtab, t, fr, alive, alive_scan, kd, loff, owned, node_base, lnode_key, lnode_mask, cut;
     size_t big_list, big_nr, big_node, big_hkey, big_hval, cls_list;
     size_t nid, sorted_nid, pv_tiles, pv_offs;
     uint64_t pv_ntiles;
@@ -102,7 +102,8 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     P.n = n;
     P.g = ilog2(p.count_grid);
     P.s = ilog2(p.subsample_grid);
-    P.lam_w = P.g < P.s ? P.g : P.s;
+    P.lam_w = P.g;                          // work chunks as deep as the count grid
+    P.d0 = P.g > P.s ? P.g - P.s : 0;       // shared depths decided globally
     P.G3 = 1ull << (3 * P.g);
     P.W3 = 1ull << (3 * P.lam_w);
     P.P = pyr_off(P.g + 1);
@@ -167,6 +168,8 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     uint64_t scan_max = P.G3 > (uint64_t)MAXD * P.maxW ? P.G3 : (uint64_t)MAXD * P.maxW;
     if (P.pv_ntiles > scan_max) scan_max = P.pv_ntiles;
     P.scan_temp = take(scan_temp_bytes(scan_max));
+    // cells of the deepest globally decided depth (level d0 - 1 + s)
+    P.gtab = P.d0 > 0 ? take(4ull << (3 * (P.d0 - 1 + P.s))) : 0;
     P.t = take(nn);
     P.fr = take(4 * nn);
     P.alive = take(4 * MAXD * P.maxW);
@@ -582,11 +585,11 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     // ---- step 2: pyramid, chunk cut, work-chunk cut ----
     launch_pyramid(pyr, g, st);
     launch_grid_export(fine, g, U32(P.grid), st);
-    launch_cut_flags(pyr, g, p->max_points_per_chunk, U32(P.fc), U8(P.lc), st);
+    launch_cut_flags(pyr, g, p->max_points_per_chunk, U32(P.fc), U8(P.lc), 0, st);
     scan_exclusive(U32(P.fc), U32(P.ec), P.G3, &ctrs->num_chunks, stemp, st);
     launch_cut_table(pyr, g, U32(P.fc), U32(P.ec), U8(P.lc), U8(P.c_level), U64(P.c_key), U32(P.c_count), nullptr,
                      p->max_points_per_chunk, &ctrs->oversized, st);
-    launch_cut_flags(pyr, P.lam_w, WC_CAP, U32(P.fw), U8(P.lw_), st);
+    launch_cut_flags(pyr, P.lam_w, WC_CAP, U32(P.fw), U8(P.lw_), P.d0, st);
     scan_exclusive(U32(P.fw), U32(P.ew), P.W3, &ctrs->num_wc, stemp, st);
     launch_cut_table(pyr, P.lam_w, U32(P.fw), U32(P.ew), U8(P.lw_), U8(P.w_level), U64(P.w_key), U32(P.w_count),
                      U64(P.w_start), WC_CAP, nullptr, st);
@@ -679,10 +682,15 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     A.big_hkey = U64(P.big_hkey);
     A.big_hval = U32(P.big_hval);
     A.lam_w = P.lam_w;
+    A.d0 = P.d0;
     A.s = s_;
     A.L = p->leaf_capacity;
     A.dmax = KB - s_;
     launch_fill_u32(U32(P.kd), 0u, (uint64_t)MAXD * num_wc, st);
+    // every point alive (0xff) until a depth keeps it; the shared depths above
+    // the work-chunk levels first, over all points
+    launch_fill_u32(reinterpret_cast<uint32_t *>(U8(P.t)), 0xffffffffu, (n + 3) / 4, st);
+    launch_global_depths(A, n, U32(P.gtab), st);
     t_sub.begin(st);
     launch_subsample_small(A, st);
     launch_subsample_big(A, st);

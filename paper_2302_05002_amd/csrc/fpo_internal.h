@@ -73,7 +73,7 @@ void launch_quantize(const float *x, const float *y, const float *z, uint64_t n,
                      hipStream_t st);
 void launch_pyramid(uint32_t *pyr, int g, hipStream_t st);
 void launch_grid_export(const uint32_t *fine_morton, int g, uint32_t *rowmajor, hipStream_t st);
-void launch_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev,
+void launch_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev, int lmin,
                       hipStream_t st);
 void launch_cut_table(const uint32_t *pyr, int lam, const uint32_t *flags, const uint32_t *excl,
                       const uint8_t *lev, uint8_t *t_level, uint64_t *t_key, uint32_t *t_count,
@@ -168,11 +168,16 @@ struct WcArgs {
     uint32_t *big_node;          // 3 words of node scratch per position
     uint64_t *big_hkey;          // 4 table slots per position
     uint32_t *big_hval;
-    int lam_w;
+    int lam_w;                   // deepest work-chunk level (g)
+    int d0;                      // shared depths below it are decided globally: max(0, g - s)
     int s;
     uint32_t L;
     int dmax;
 };
+// Shared depths d < d0 over all points (t filled with 0xff before): winners
+// get t = d, and the reaching-count rows of those depths are written.
+// gtab: 4 * 8^(d0 - 1 + s) bytes.
+void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream_t st);
 void launch_subsample_small(const WcArgs &a, hipStream_t st);
 void launch_subsample_big(const WcArgs &a, hipStream_t st);
 void launch_decide(const WcArgs &a, hipStream_t st);

@@ -438,11 +438,11 @@ __global__ void k_grid_export(const uint32_t *fine, int g, uint32_t *out)
 }
 
 // ---- step 2b: chunk cut ---------------------------------------------------------------
-// A pyramid node (l, a), l <= lam, is a chunk when it is non-empty, holds at
-// most thresh points or l == lam, and l == 0 or its parent holds more than
-// thresh.  flags[m] = 1 at the first level-lam cell m of every chunk; lev[m] =
+// A pyramid node (l, a), lmin <= l <= lam, is a chunk when it is non-empty,
+// holds at most thresh points or l == lam, and l == lmin or its parent holds
+// more than thresh.  flags[m] = 1 at the first level-lam cell m of every chunk; lev[m] =
 // its level.  Chunks are disjoint, so at most one level can start at m.
-__global__ void k_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev)
+__global__ void k_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev, int lmin)
 {
     const uint64_t ncell = 1ull << (3 * lam);
     for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < ncell;
@@ -454,7 +454,7 @@ __global__ void k_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint3
             const uint64_t a = m >> sh;
             const uint32_t cnt = pyr[pyr_off(l) + a];
             if (cnt == 0) break;
-            if (cnt <= thresh || l == lam) {
+            if (l >= lmin && (cnt <= thresh || l == lam)) {
                 // the node at level l containing m is the chunk; it starts here
                 // only if m is its first cell
                 if ((m & ((1ull << sh) - 1ull)) == 0) { f = 1; lv = (uint8_t)l; }
@@ -1024,15 +1024,83 @@ void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, u
 // ---- step 4: per-node grid subsample -----------------------------------------------------------
 //
 // Work chunks (WCs) are the maximal pyramid nodes holding at most WC_CAP
-// points, cut no deeper than level lam_w = min(g, s).  Because lam_w <= s, the
-// subsample cells of every node (lattice level d + s >= s) never straddle two
-// WCs: each cell's lowest-index point is found inside one WC.  The only
+// points, at levels d0 = max(0, g - s) to g.  The subsample cells of a node
+// at depth d lie at lattice level d + s; from depth d0 on (d + s >= g >= lw)
+// they never straddle two WCs, so each cell's lowest-index point is found
+// inside one WC.  The shared depths above d0 (cells spanning several WCs)
+// are decided first by a global pass over all points.  The only other
 // cross-WC question is whether a node above a WC (a "shared" node, depth
 // < lw) is inner or a leaf, which depends on how many points reach it.  Each
-// WC therefore runs its whole subtree assuming its shared ancestors are inner,
+// WC therefore runs its subtree assuming its shared ancestors are inner,
 // posting its reaching count at every shared depth; a top-down pass then
 // finds the first shared leaf of each WC (its "cut"), and points whose
 // tentative depth is at or below the cut belong to that leaf.
+
+// Global shared depths d < d0, in work-chunk order.  Every alive point
+// (state 0xff) offers its original index to its cell of level d + s; a wave
+// whose alive points share one cell (work-chunk order is spatially coherent)
+// offers only its minimum.
+__global__ void k_gdepth_min(const uint64_t *__restrict__ code, const uint32_t *__restrict__ orig,
+                             const uint8_t *__restrict__ t, uint64_t n, int csh, uint32_t *gtab)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t q0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); q0 < n; q0 += stride) {
+        const uint64_t q = q0 + lane_id();
+        const bool alive = q < n && t[q] == 0xffu;
+        const uint64_t cell = alive ? code[q] >> csh : 0ull;
+        const uint32_t o = alive ? orig[q] : 0xffffffffu;
+        const uint64_t am = __ballot(alive);
+        if (!am) continue;
+        const int leader = __ffsll((long long)am) - 1;
+        const uint64_t c0 = __shfl(cell, leader, 64);
+        if (__ballot(alive && cell != c0) == 0) {
+            uint32_t m = o;
+#pragma unroll
+            for (int k = 32; k > 0; k >>= 1) m = min(m, (uint32_t)__shfl_xor(m, k, 64));
+            if (lane_id() == leader) atomicMin(&gtab[c0], m);
+        } else if (alive) {
+            atomicMin(&gtab[cell], o);
+        }
+    }
+}
+
+// The winners of depth d: alive points holding their cell's minimum.
+__global__ void k_gdepth_mark(const uint64_t *__restrict__ code, const uint32_t *__restrict__ orig, uint8_t *t,
+                              uint64_t n, int csh, const uint32_t *gtab, int d)
+{
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (uint64_t)gridDim.x * blockDim.x) {
+        if (t[q] != 0xffu) continue;
+        if (gtab[code[q] >> csh] == orig[q]) t[q] = (uint8_t)d;
+    }
+}
+
+// Rows of the global shared depths: points of each WC alive at depth d < d0
+// (one wave per WC).
+__global__ void k_wc_alive_rows(WcArgs a)
+{
+    const uint32_t waves = gridDim.x * (blockDim.x / 64);
+    for (uint32_t w = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); w < a.num_wc; w += waves) {
+        const uint32_t base = a.wc_begin[w], n = a.wc_count[w];
+        uint32_t placed[MAXD];   // constant indices only (kept in registers)
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d) placed[d] = 0;
+        for (uint32_t p0 = 0; p0 < n; p0 += 64) {
+            const uint32_t p = p0 + lane_id();
+            const uint32_t st = p < n ? a.t[base + p] : 0xffu;
+#pragma unroll
+            for (int d = 0; d < MAXD; ++d)
+                if (d < a.d0) placed[d] += (uint32_t)__popcll(__ballot(st == (uint32_t)d));
+        }
+        if (lane_id() == 0) {
+            uint32_t alive = n;
+#pragma unroll
+            for (int d = 0; d < MAXD; ++d) {
+                if (d < a.d0) a.alive[(uint64_t)d * a.num_wc + w] = alive;
+                alive -= placed[d];
+            }
+        }
+    }
+}
 
 // Global-memory table (full 64-bit keys, separate values) for the work
 // chunks handled outside LDS.
@@ -1110,7 +1178,7 @@ struct Items {
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t pos = j * BLOCK + threadIdx.x;
             code[j] = pos < n ? a.wc_code[base + pos] : 0ull;
-            w[j] = ST_ALIVE;
+            w[j] = pos < n ? a.t[base + pos] : ST_ALIVE;   // alive, or placed at a global depth
         }
     }
     template <class F>
@@ -1152,8 +1220,7 @@ struct Items<BLOCK, ITEMS, true> {
         nr = a.big_nr + base;
         fr = a.fr + base;
         n = n_;
-        for (uint32_t pos = threadIdx.x; pos < n; pos += BLOCK) {
-            t[pos] = ST_ALIVE;
+        for (uint32_t pos = threadIdx.x; pos < n; pos += BLOCK) {   // t: alive, or placed at a global depth
             nr[pos] = 0;
             fr[pos] = 0;
         }
@@ -1212,9 +1279,12 @@ __device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint
     Items<BLOCK, ITEMS, BIG> it;
     it.load(a, base, n);
     __syncthreads();
-    uint32_t A = n;   // alive points at the current depth
+    // alive points at depth d0 (the global depths may have placed some)
+    uint32_t A0 = 0;
+    it.each([&](uint32_t, uint64_t, uint32_t &st, uint32_t &, uint32_t &) { A0 += st == ST_ALIVE ? 1u : 0u; });
+    uint32_t A = block_sum<BLOCK>(A0, red);
     uint32_t Kprev = 0, prev_off = 0, loff = 0;
-    for (int d = 0; d < MAXD; ++d) {
+    for (int d = a.d0; d < MAXD; ++d) {
         if (A == 0) {
             if (d - 1 >= lw)
                 for (uint32_t r = threadIdx.x; r < Kprev; r += BLOCK) a.lnode_mask[base + prev_off + r] = 0;
@@ -1401,7 +1471,7 @@ __device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint
     // depth.  Plain stores, summed per ancestor later: thousands of work
     // chunks share the top ancestors, and atomics on those few addresses
     // would serialise and stall the memory pipeline.
-    if (threadIdx.x < (uint32_t)MAXD) {
+    if (threadIdx.x < (uint32_t)MAXD && (int)threadIdx.x >= a.d0) {   // rows above d0: the global pass
         const int d = threadIdx.x;
         a.alive[(uint64_t)d * a.num_wc + w] = d < lw ? alive_at[d] : 0u;
     }
@@ -1508,15 +1578,21 @@ __global__ __launch_bounds__(BLOCK) void k_subsample_fast(WcArgs a, int cls)
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t pos = j * BLOCK + threadIdx.x;
             const uint64_t c = a.wc_code[base + (pos < n ? pos : n - 1)];
-            it[j] = pos < n ? ((uint32_t)(c >> ksh) & kmask) | ALIVE : 0u;
+            const uint32_t st = a.t[base + (pos < n ? pos : n - 1)];   // alive, or placed at a global depth
+            it[j] = pos < n ? ((uint32_t)(c >> ksh) & kmask) | (st << 24) : 0u;
         }
         if (threadIdx.x < (uint32_t)MAXD) alive_at[threadIdx.x] = 0;
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) keyat[j * BLOCK + threadIdx.x] = it[j] & 0xffffffu;
         for (uint32_t h = threadIdx.x; h < TSZ / 4; h += BLOCK) table4[h] = make_uint4(EMPTY, EMPTY, EMPTY, EMPTY);
-        uint32_t A = n;
+        uint32_t alive0 = 0;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) alive0 += it[j] >= ALIVE ? 1u : 0u;
+        uint32_t A = block_sum2(alive0, par);
+        par ^= 1;
+        __syncthreads();
         bool clean = true;   // the table holds no hashed entries
-        for (int d = 0; d < lw && A > 0; ++d) {
+        for (int d = a.d0; d < lw && A > 0; ++d) {
             if (threadIdx.x == 0) alive_at[d] = A;
             const int rb = 3 * (d + a.s - lw);   // relative key bits at this depth
             const int sh = 3 * (lw - 1 - d);
@@ -1597,7 +1673,7 @@ __global__ __launch_bounds__(BLOCK) void k_subsample_fast(WcArgs a, int cls)
             }
         }
         __syncthreads();
-        if (threadIdx.x < (uint32_t)MAXD) {
+        if (threadIdx.x < (uint32_t)MAXD && (int)threadIdx.x >= a.d0) {   // rows above d0: the global pass
             const int d = threadIdx.x;
             a.alive[(uint64_t)d * a.num_wc + w] = d < lw ? alive_at[d] : 0u;
         }
@@ -2071,10 +2147,26 @@ void launch_grid_export(const uint32_t *fine, int g, uint32_t *out, hipStream_t 
     hipLaunchKernelGGL(k_grid_export, dim3(grid_for(1ull << (3 * g), 256)), dim3(256), 0, st, fine, g, out);
 }
 
-void launch_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev, hipStream_t st)
+void launch_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev, int lmin,
+                      hipStream_t st)
 {
     hipLaunchKernelGGL(k_cut_flags, dim3(grid_for(1ull << (3 * lam), 256)), dim3(256), 0, st, pyr, lam, thresh, flags,
-                       lev);
+                       lev, lmin);
+}
+
+void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream_t st)
+{
+    if (n == 0) return;
+    for (int d = 0; d < a.d0; ++d) {
+        const int csh = 3 * (KB - d - a.s);
+        launch_fill_u32(gtab, 0xffffffffu, 1ull << (3 * (d + a.s)), st);
+        hipLaunchKernelGGL(k_gdepth_min, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, a.wc_code, a.wc_orig, a.t, n,
+                           csh, gtab);
+        hipLaunchKernelGGL(k_gdepth_mark, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, a.wc_code, a.wc_orig, a.t, n,
+                           csh, gtab, d);
+    }
+    if (a.d0 > 0 && a.num_wc > 0)
+        hipLaunchKernelGGL(k_wc_alive_rows, dim3(grid_for(a.num_wc, 4, 4096)), dim3(256), 0, st, a);
 }
 
 void launch_cut_table(const uint32_t *pyr, int lam, const uint32_t *flags, const uint32_t *excl, const uint8_t *lev,
