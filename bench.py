@@ -316,6 +316,25 @@ def main():
 
     for _ in range(args.warmup):
         step(False)
+
+    def bench_gather(reps: int = 10) -> dict:
+        """Node-ordered points of one build (the export step after the tree):
+        read the index 4 B, gather the coordinates 12 B, write 12 B per point."""
+        job = ctx.submit(x, y, z, params, workspace=ws, stream=stream)
+        job.wait()
+        job.gather(x, y, z)   # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            job.gather(x, y, z)
+        torch.cuda.synchronize()
+        ms_g = (time.perf_counter() - t) * 1000.0 / reps
+        job.release()
+        gbs = 28 * n / (ms_g / 1000.0) / 1e9
+        return {"what": "xyz of every point gathered into node order (28 B/pt)", "ms": ms_g, "GBps": gbs,
+                "hbm_frac": gbs / HBM_PEAK_GBS}
+
+    gather_stats = bench_gather()
     # kernel timers: HIP events around the timed kernels, on the build's stream
     ctx.set_timing(True)
     timers = {k: [0.0, 0] for k in KERNEL_BYTES}
@@ -363,6 +382,7 @@ def main():
                    "preview_modulus": p.preview_modulus, "parallelism": "single GPU"},
         "path_hbm_frac": b_alg / (ms / 1000.0) / (HBM_PEAK_GBS * 1e9),
         "roofline": roofline,
+        "node_ordered_points": gather_stats,
     }
     if not args.no_mix:
         del ws

@@ -205,6 +205,34 @@ void fpo_job_release(fpo_job *job);
 fpo_status fpo_job_export_bytes(fpo_job *job, uint64_t *bytes);
 fpo_status fpo_job_copy_to_host(fpo_job *job, void *host_dst, uint64_t bytes);
 
+/* ---- node-ordered points and hierarchy export (after a build) ---------------
+ * The far side of the path in the paper's octree pipeline: the points of the
+ * tree written node by node after the hierarchy ("Octree Construction"). */
+
+/* Gathers the coordinates (and optional per-point colour bytes) of a
+ * completed job into node order, k = 0..n-1:
+ *   out_xyz[3k + a] = coordinate a of point node_points[k]   (float32, xyz interleaved)
+ *   out_color[color_stride * k + c] = color[color_stride * node_points[k] + c]
+ * cloud: the build's input, device arrays (a pinned-host build: pass device
+ * copies).  color: device bytes, color_stride per point (3 rgb, 4 rgba), NULL
+ * with stride 0 for none.  out_xyz: device, 12 n bytes; out_color: device,
+ * color_stride n bytes.  Enqueued on hip_stream (NULL: the context's stream);
+ * complete when that stream reaches it. */
+fpo_status fpo_job_gather(fpo_job *job, const fpo_cloud *cloud, const uint8_t *color, uint32_t color_stride,
+                          float *out_xyz, uint8_t *out_color, void *hip_stream);
+
+/* Writes the hierarchy and the node-ordered points of a completed job to one
+ * file (little endian; blocks back to back):
+ *   header   "FPO1", uint32 version = 1, uint64 n, uint32 num_nodes,
+ *            uint32 color_stride, float32 bbox_min[3], float32 cube_size,
+ *            uint32 count_grid, uint32 subsample_grid (48 bytes)
+ *   nodes    num_nodes records of 24 bytes in (depth, key) order: uint8 depth,
+ *            uint8 child_mask, uint16 0, uint32 count, uint64 key, uint64 begin
+ *   points   n x 3 float32 (xyz) in node order, then n x color_stride bytes
+ * cloud / color as for fpo_job_gather.  Blocks until the file is written. */
+fpo_status fpo_job_write_file(fpo_job *job, const fpo_cloud *cloud, const uint8_t *color, uint32_t color_stride,
+                              const char *path);
+
 /* Host steady-clock times (ns) of a completed job: when it was submitted, when
  * its build started (later than submitted for batch and server jobs that
  * waited for a worker, a slot or memory) and when it completed (server jobs:

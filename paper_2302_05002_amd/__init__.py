@@ -25,7 +25,8 @@ FPO_BBOX_GIVEN = 1
 #: every symbol include/fpo.h declares
 EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_workspace_size",
            "fpo_build_submit", "fpo_job_preview_ready", "fpo_job_poll", "fpo_job_wait",
-           "fpo_job_result", "fpo_job_release", "fpo_workspace_size_cloud", "fpo_job_export_bytes", "fpo_job_copy_to_host",
+           "fpo_job_result", "fpo_job_release", "fpo_workspace_size_cloud", "fpo_job_gather",
+           "fpo_job_write_file", "fpo_job_export_bytes", "fpo_job_copy_to_host",
            "fpo_job_timestamps", "fpo_batch_workspace_size", "fpo_build_batch", "fpo_server_create",
            "fpo_server_submit", "fpo_job_cancel", "fpo_server_destroy", "fpo_context_set_timing", "fpo_job_timer")
 
@@ -99,6 +100,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_job_release.argtypes = [vp]
     lib.fpo_job_release.restype = None
     u64 = ctypes.c_uint64
+    lib.fpo_job_gather.argtypes = [vp, P(_Cloud), vp, ctypes.c_uint32, vp, vp, vp]
+    lib.fpo_job_gather.restype = ctypes.c_int
+    lib.fpo_job_write_file.argtypes = [vp, P(_Cloud), vp, ctypes.c_uint32, ctypes.c_char_p]
+    lib.fpo_job_write_file.restype = ctypes.c_int
     lib.fpo_job_export_bytes.argtypes = [vp, P(u64)]
     lib.fpo_job_export_bytes.restype = ctypes.c_int
     lib.fpo_job_copy_to_host.argtypes = [vp, vp, u64]
@@ -313,6 +318,40 @@ class Job:
         _check(_lib.fpo_job_result(self._h, ctypes.byref(r)))
         return Result(r, self.workspace, self.params)
 
+    @staticmethod
+    def _cloud_and_color(x, y, z, color):
+        import torch
+        n = int(x.shape[0])
+        for t in (x, y, z):
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.shape[0] == n
+        stride = 0
+        if color is not None:
+            assert color.is_cuda and color.dtype == torch.uint8 and color.is_contiguous() and color.shape[0] == n
+            stride = int(color.shape[1]) if color.dim() == 2 else 1
+        return _Cloud(n, x.data_ptr(), y.data_ptr(), z.data_ptr()), stride
+
+    def gather(self, x, y, z, color=None, stream=None):
+        """Points of a completed job in node order: (xyz (n, 3) float32, colour (n, stride) uint8 or None)."""
+        import torch
+        cloud, stride = self._cloud_and_color(x, y, z, color)
+        n = int(cloud.n)
+        out_xyz = torch.empty((n, 3), dtype=torch.float32, device=x.device)
+        out_col = torch.empty((n, stride), dtype=torch.uint8, device=x.device) if stride else None
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        _check(_lib.fpo_job_gather(self._h, ctypes.byref(cloud), ctypes.c_void_p(color.data_ptr() if stride else 0),
+                                   stride, ctypes.c_void_p(out_xyz.data_ptr()),
+                                   ctypes.c_void_p(out_col.data_ptr() if stride else 0),
+                                   ctypes.c_void_p(stream.cuda_stream)))
+        return out_xyz, out_col
+
+    def write_file(self, path: str, x, y, z, color=None):
+        """Hierarchy + node-ordered points of a completed job in one file."""
+        cloud, stride = self._cloud_and_color(x, y, z, color)
+        _check(_lib.fpo_job_write_file(self._h, ctypes.byref(cloud),
+                                       ctypes.c_void_p(color.data_ptr() if stride else 0), stride,
+                                       str(path).encode()))
+
     def cancel(self) -> bool:
         """Take a batch or server job that has not started out of its queue."""
         return _lib.fpo_job_cancel(self._h) == FPO_OK
@@ -423,3 +462,28 @@ class Result:
             node_key=cpu(self.node_key, np.uint64), node_child_mask=cpu(self.node_child_mask, np.uint8),
             node_begin=cpu(self.node_begin, np.uint64), node_count=cpu(self.node_count, np.uint32),
             node_points=cpu(self.node_points, np.uint32), preview_index=cpu(self.preview_index, np.uint32))
+
+
+def read_file(path: str) -> dict:
+    """Parse a file written by Job.write_file (layout in include/fpo.h)."""
+    raw = np.fromfile(path, dtype=np.uint8)
+    assert raw[:4].tobytes() == b"FPO1", "not an FPO1 file"
+    hdr = raw[:48]
+    version, = hdr[4:8].view(np.uint32)
+    n, = hdr[8:16].view(np.uint64)
+    num_nodes, stride = hdr[16:24].view(np.uint32)
+    bbox_min = hdr[24:36].view(np.float32)
+    cube_size, = hdr[36:40].view(np.float32)
+    G, S = hdr[40:48].view(np.uint32)
+    n, num_nodes, stride = int(n), int(num_nodes), int(stride)
+    rec = raw[48:48 + 24 * num_nodes].reshape(num_nodes, 24)
+    nodes = dict(depth=rec[:, 0].copy(), child_mask=rec[:, 1].copy(),
+                 count=rec[:, 4:8].copy().view(np.uint32).ravel(), key=rec[:, 8:16].copy().view(np.uint64).ravel(),
+                 begin=rec[:, 16:24].copy().view(np.uint64).ravel())
+    off = 48 + 24 * num_nodes
+    xyz = raw[off:off + 12 * n].view(np.float32).reshape(n, 3)
+    off += 12 * n
+    color = raw[off:off + stride * n].reshape(n, stride) if stride else None
+    return dict(version=int(version), n=n, num_nodes=num_nodes, color_stride=stride, bbox_min=bbox_min.copy(),
+                cube_size=np.float32(cube_size), count_grid=int(G), subsample_grid=int(S), nodes=nodes,
+                xyz=xyz.copy(), color=None if color is None else color.copy())

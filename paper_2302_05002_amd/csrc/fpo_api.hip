@@ -427,6 +427,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     job->t_submit = now_ns();
     job->t_done = 0;
     job->grid_cells = P.G3;
+    job->params = *p;
     job->pinned = get_pinned(ctx);
     if (!job->pinned) {
         delete job;
@@ -869,6 +870,99 @@ fpo_status fpo_job_copy_to_host(fpo_job *job, void *host_dst, uint64_t bytes)
         off += pr.second;
     }
     return FPO_OK;
+}
+
+fpo_status fpo_job_gather(fpo_job *job, const fpo_cloud *cloud, const uint8_t *color, uint32_t color_stride,
+                          float *out_xyz, uint8_t *out_color, void *hip_stream)
+{
+    if (!job || !cloud || (cloud->n && !out_xyz)) return fail(FPO_ERR_INVALID_ARG, "NULL job, cloud or output");
+    if ((color_stride > 0) != (color != nullptr) || (color_stride > 0 && !out_color) || color_stride > 64)
+        return fail(FPO_ERR_INVALID_ARG, "colour: pass the array, a stride of 1..64 and the output together");
+    fpo_context *ctx = job->ctx;
+    FPO_RESOLVE(job, false);
+    if (!job->waited || job->status != FPO_OK) return fail(FPO_ERR_INVALID_ARG, "the job has not completed");
+    if (cloud->n != job->res.n) return fail(FPO_ERR_INVALID_ARG, "the cloud has %llu points, the build %llu",
+                                            (unsigned long long)cloud->n, (unsigned long long)job->res.n);
+    if (cloud->n && (!cloud->x || !cloud->y || !cloud->z)) return fail(FPO_ERR_INVALID_ARG, "NULL coordinate array");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->stream;
+    launch_gather_points(job->res.node_points, cloud->n, cloud->x, cloud->y, cloud->z, color, color_stride, out_xyz,
+                         out_color, st);
+    HIPCHK(hipGetLastError());
+    return FPO_OK;
+}
+
+fpo_status fpo_job_write_file(fpo_job *job, const fpo_cloud *cloud, const uint8_t *color, uint32_t color_stride,
+                              const char *path)
+{
+    if (!job || !cloud || !path) return fail(FPO_ERR_INVALID_ARG, "NULL job, cloud or path");
+    fpo_job *pub = job;
+    FPO_RESOLVE(job, false);
+    if (!job->waited || job->status != FPO_OK) return fail(FPO_ERR_INVALID_ARG, "the job has not completed");
+    const fpo_result &R = job->res;
+    const uint64_t n = R.n;
+    // node table and points to the host
+    std::vector<uint8_t> depth(R.num_nodes), mask(R.num_nodes);
+    std::vector<uint32_t> count(R.num_nodes);
+    std::vector<uint64_t> key(R.num_nodes), begin(R.num_nodes);
+    HIPCHK(hipSetDevice(job->ctx->device));
+    if (R.num_nodes) {
+        HIPCHK(hipMemcpy(depth.data(), R.node_depth, R.num_nodes, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(mask.data(), R.node_child_mask, R.num_nodes, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(count.data(), R.node_count, 4ull * R.num_nodes, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(key.data(), R.node_key, 8ull * R.num_nodes, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(begin.data(), R.node_begin, 8ull * R.num_nodes, hipMemcpyDeviceToHost));
+    }
+    std::vector<float> xyz(3 * n);
+    std::vector<uint8_t> col((uint64_t)color_stride * n);
+    if (n) {
+        float *d_xyz = nullptr;
+        uint8_t *d_col = nullptr;
+        HIPCHK(hipMalloc(&d_xyz, 12 * n));
+        if (color_stride && hipMalloc(&d_col, (uint64_t)color_stride * n) != hipSuccess) {
+            (void)hipFree(d_xyz);
+            return fail(FPO_ERR_OUT_OF_MEMORY, "device memory for the colours");
+        }
+        fpo_status s = fpo_job_gather(pub, cloud, color, color_stride, d_xyz, d_col, nullptr);
+        hipError_t e = hipSuccess;
+        if (s == FPO_OK) {
+            e = hipStreamSynchronize(job->ctx->stream);
+            if (e == hipSuccess) e = hipMemcpy(xyz.data(), d_xyz, 12 * n, hipMemcpyDeviceToHost);
+            if (e == hipSuccess && color_stride) e = hipMemcpy(col.data(), d_col, col.size(), hipMemcpyDeviceToHost);
+        }
+        (void)hipFree(d_xyz);
+        if (d_col) (void)hipFree(d_col);
+        if (s != FPO_OK) return s;
+        if (e != hipSuccess) return fail(FPO_ERR_DEVICE, "gather: %s", hipGetErrorString(e));
+    }
+    FILE *f = fopen(path, "wb");
+    if (!f) return fail(FPO_ERR_INVALID_ARG, "cannot open %s for writing", path);
+    bool ok = true;
+    auto put = [&](const void *p, size_t b) { ok = ok && (b == 0 || fwrite(p, 1, b, f) == b); };
+    const uint32_t version = 1, nn = R.num_nodes, cs = color_stride;
+    const uint32_t G = job->params.count_grid, S = job->params.subsample_grid;
+    put("FPO1", 4);
+    put(&version, 4);
+    put(&n, 8);
+    put(&nn, 4);
+    put(&cs, 4);
+    put(R.bbox_min, 12);
+    put(&R.cube_size, 4);
+    put(&G, 4);
+    put(&S, 4);
+    for (uint32_t k = 0; k < nn; ++k) {
+        const uint16_t zero = 0;
+        put(&depth[k], 1);
+        put(&mask[k], 1);
+        put(&zero, 2);
+        put(&count[k], 4);
+        put(&key[k], 8);
+        put(&begin[k], 8);
+    }
+    put(xyz.data(), 12 * n);
+    put(col.data(), col.size());
+    if (fclose(f) != 0) ok = false;
+    return ok ? FPO_OK : fail(FPO_ERR_INVALID_ARG, "writing %s failed", path);
 }
 
 fpo_status fpo_job_timestamps(fpo_job *job, uint64_t *submitted_ns, uint64_t *started_ns, uint64_t *completed_ns)

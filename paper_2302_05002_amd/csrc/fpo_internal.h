@@ -198,6 +198,10 @@ void launch_node_fill(const WcArgs &a, const uint32_t *node_base, uint8_t *depth
 void launch_node_ranges(const uint32_t *sorted_keys, uint64_t n, uint64_t *begin, uint32_t *count,
                         uint32_t num_nodes, hipStream_t st);
 
+// Node-ordered gather: out_xyz[3k + a] = coord_a[idx[k]], colour bytes alike.
+void launch_gather_points(const uint32_t *idx, uint64_t n, const float *x, const float *y, const float *z,
+                          const uint8_t *color, uint32_t stride, float *out_xyz, uint8_t *out_color, hipStream_t st);
+
 // Preview.
 void launch_preview_count(uint64_t n, uint64_t m, uint32_t *tile_counts, hipStream_t st);
 void launch_preview_write(uint64_t n, uint64_t m, const uint32_t *tile_offsets, uint32_t *out,

@@ -2281,3 +2281,31 @@ void launch_preview_write(uint64_t n, uint64_t m, const uint32_t *toff, uint32_t
 }
 
 }  // namespace fpo
+
+namespace fpo {
+
+// ---- node-ordered points --------------------------------------------------------------------
+// Gathers in node order: reads are random (one point each), writes coalesced.
+__global__ void k_gather_points(const uint32_t *__restrict__ idx, uint64_t n, const float *__restrict__ x,
+                                const float *__restrict__ y, const float *__restrict__ z,
+                                const uint8_t *__restrict__ color, uint32_t stride, float *__restrict__ out_xyz,
+                                uint8_t *__restrict__ out_color)
+{
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = idx[k];
+        out_xyz[3 * k + 0] = x[i];
+        out_xyz[3 * k + 1] = y[i];
+        out_xyz[3 * k + 2] = z[i];
+        for (uint32_t c = 0; c < stride; ++c) out_color[(uint64_t)stride * k + c] = color[(uint64_t)stride * i + c];
+    }
+}
+
+void launch_gather_points(const uint32_t *idx, uint64_t n, const float *x, const float *y, const float *z,
+                          const uint8_t *color, uint32_t stride, float *out_xyz, uint8_t *out_color, hipStream_t st)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gather_points, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, idx, n, x, y, z,
+                       color, stride, out_xyz, out_color);
+}
+
+}  // namespace fpo

@@ -224,3 +224,24 @@ def test_signed_zero_extremes_reported_as_plus_zero():
         assert r["status"] == oracle.OK
         assert np.signbit(r["bbox_min"][0]) == False and r["bbox_min"][0] == 0.0
         assert np.signbit(r["bbox_max"][1]) == False and r["bbox_max"][1] == 0.0
+
+
+def test_node_ordered_points_inside_their_nodes():
+    """The export order (the oracle's node_points) puts every point inside the
+    cube of the node it is listed under: its fine coordinates shifted to the
+    node's depth equal the node's key (checked on an independent numpy
+    quantisation)."""
+    from checks import morton_keys
+    c = synth.planes(30_000, seed=7, num_planes=6)
+    r = oracle.build_octree(c.x, c.y, c.z, oracle.Params(32, 4_000, 16, 500, 8))
+    lo, hi = bbox_numpy(c.x, c.y, c.z)
+    side = np.float32(max(hi - lo))
+    scale = np.float32(2.0 ** 21 / float(side))
+    u = np.stack([quantize_emulated(a, lo[k], scale) for k, a in enumerate((c.x, c.y, c.z))], 1)
+    for k in range(r["node_depth"].shape[0]):
+        d = int(r["node_depth"][k])
+        b, cnt = int(r["node_begin"][k]), int(r["node_count"][k])
+        pts = r["node_points"][b:b + cnt].astype(np.int64)
+        q = u[pts] >> (21 - d)
+        keys = morton_keys(q[:, 0], q[:, 1], q[:, 2], d)
+        assert np.all(keys == r["node_key"][k]), k
