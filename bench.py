@@ -334,6 +334,44 @@ def main():
         return {"what": "xyz of every point gathered into node order (28 B/pt)", "ms": ms_g, "GBps": gbs,
                 "hbm_frac": gbs / HBM_PEAK_GBS}
 
+    def bench_preview_variants(reps: int = 5) -> dict:
+        """The three previews on the same workload: device time of the preview
+        kernels per build (timer 'preview'), of the quantise pass (which keeps
+        the per-cell hash minima for the grid preview) and of the whole build.
+        Algorithmic bytes of the preview kernels: hash and stride write 4 B per
+        pick (index-only predicates); grid reads the per-cell minima (8 B/cell)
+        and writes 4 B per pick."""
+        res = {}
+        ctx.set_timing(True)
+        for mode in ("hash", "stride", "grid"):
+            pm = fpo.Params(p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity,
+                            p.preview_modulus, None, mode)
+            wsm = torch.empty(fpo.workspace_size(n, pm), dtype=torch.uint8, device=dev)
+            tot = pv = qz = 0.0
+            picks = 0
+            for r in range(reps + 1):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                job = ctx.submit(x, y, z, pm, workspace=wsm, stream=stream)
+                job.wait()
+                el = (time.perf_counter() - t) * 1000.0
+                if r:
+                    tot += el
+                    pv += job.timer("preview")[0]
+                    qz += job.timer("quantize")[0]
+                picks = int(job.result().preview_count)
+                job.release()
+            del wsm
+            pv /= reps
+            alg = 4 * picks + (8 * p.count_grid ** 3 if mode == "grid" else 0)
+            res[mode] = {"preview_ms": pv, "quantize_ms": qz / reps, "build_ms": tot / reps, "picks": picks,
+                         "GBps": alg / (pv / 1000.0) / 1e9, "hbm_frac": alg / (pv / 1000.0) / 1e9 / HBM_PEAK_GBS}
+        ctx.set_timing(False)
+        return res
+
+    preview_stats = bench_preview_variants()
+    print(f"[bench] preview variants: " + ", ".join(f"{k} {v['preview_ms']:.3f} ms ({v['picks']} picks)"
+                                                    for k, v in preview_stats.items()), file=sys.stderr, flush=True)
     gather_stats = bench_gather()
     # kernel timers: HIP events around the timed kernels, on the build's stream
     ctx.set_timing(True)
@@ -383,6 +421,7 @@ def main():
         "path_hbm_frac": b_alg / (ms / 1000.0) / (HBM_PEAK_GBS * 1e9),
         "roofline": roofline,
         "node_ordered_points": gather_stats,
+        "preview_variants": preview_stats,
     }
     if not args.no_mix:
         del ws

@@ -32,7 +32,13 @@
  *     C.
  *   - preview: every index i with H64(i) mod M == 0, ascending, where H64 is
  *     h = i; h ^= h >> 31; h *= 0x9E3779B97F4A7C15; h ^= h >> 29;
- *     h *= 0x9E3779B97F4A7C15; h ^= h >> 32 (all mod 2^64).
+ *     h *= 0x9E3779B97F4A7C15; h ^= h >> 32 (all mod 2^64).  Two variants
+ *     (section "Future Work" proposes a spatially constrained sampler in place
+ *     of the uniform decimation; section "Results" decimates to a fixed target
+ *     count): an exact stride, i mod M == 0; and one pick per occupied count-
+ *     grid cell, the point of least H64 in the cell (H64 is a bijection, so the
+ *     pick is unique).  Hash and stride previews depend on n and M only and are
+ *     ready before the bounding box; the grid preview follows the count pass.
  *
  * Conventions for every entry point:
  *   - Every call returns an fpo_status; fpo_last_error() gives the text of the
@@ -70,12 +76,16 @@ typedef struct fpo_context fpo_context;
 typedef struct fpo_job fpo_job;
 
 #define FPO_BBOX_GIVEN 1u      /* fpo_params.flags: use bbox_min/bbox_max instead of computing it */
+#define FPO_PREVIEW_STRIDE 2u  /* flags: preview = every index with i mod M == 0 */
+#define FPO_PREVIEW_GRID 4u    /* flags: preview = least-H64 point of every occupied count-grid cell (M unused);
+                                  the workspace then holds 8 * G^3 more bytes */
 
 /* Build parameters (names after the paper's "maxPointsPerChunk" style):
  *   count_grid G: power of two, 1..512;  max_points_per_chunk C >= 1;
  *   subsample_grid S: power of two, 1..256;  leaf_capacity L >= 1;
- *   preview_modulus M >= 1.
- * With FPO_BBOX_GIVEN, bbox_min <= bbox_max per axis, all finite; points
+ *   preview_modulus M >= 1 (fpo_preview_modulus gives M for a target count).
+ * At most one of FPO_PREVIEW_STRIDE and FPO_PREVIEW_GRID; neither selects the
+ * H64 predicate.  With FPO_BBOX_GIVEN, bbox_min <= bbox_max per axis, all finite; points
  * outside the box clamp to its faces and are counted in fpo_result.n_outside. */
 typedef struct {
     uint32_t count_grid;
@@ -157,6 +167,12 @@ const char *fpo_last_error(void);
 
 /* Worst-case workspace bytes of one build of n device-resident points with *p. */
 fpo_status fpo_workspace_size(uint64_t n, const fpo_params *p, uint64_t *bytes);
+
+/* Preview modulus for a target preview size: max(1, ceil(n / target)).  With
+ * FPO_PREVIEW_STRIDE the preview then holds ceil(n / M) <= target indices; with
+ * the H64 predicate about n / M.  FPO_ERR_INVALID_ARG if target == 0, n >
+ * 2^32 - 1 or out is NULL. */
+fpo_status fpo_preview_modulus(uint64_t n, uint64_t target, uint32_t *out);
 
 /* The same for a given cloud: adds the device staging of pinned host inputs
  * (12 bytes per point). */
@@ -300,7 +316,8 @@ typedef enum {
     FPO_TIMER_SUBSAMPLE = 3,     /* per-work-chunk subsample kernels, every size class, bracketed together (step 4) */
     FPO_TIMER_NODE_IDS = 4,      /* node id of every point (step 4) */
     FPO_TIMER_NODE_POINTS = 5,   /* scatter kernel of the node_points split, one per digit pass (step 4) */
-    FPO_TIMER_COUNT = 6
+    FPO_TIMER_PREVIEW = 6,       /* preview kernels (grid minimum, count, scan, write), bracketed together (step 5) */
+    FPO_TIMER_COUNT = 7
 } fpo_timer;
 
 /* enable: 1 to time later submits of ctx, 0 to stop. */

@@ -43,8 +43,11 @@ class _Params(ctypes.Structure):
     _fields_ = [("count_grid", ctypes.c_uint32), ("max_points_per_chunk", ctypes.c_uint32),
                 ("subsample_grid", ctypes.c_uint32), ("leaf_capacity", ctypes.c_uint32),
                 ("preview_modulus", ctypes.c_uint32), ("bbox_given", ctypes.c_uint32),
-                ("bbox_min", ctypes.c_float * 3), ("bbox_max", ctypes.c_float * 3)]
+                ("bbox_min", ctypes.c_float * 3), ("bbox_max", ctypes.c_float * 3),
+                ("preview_mode", ctypes.c_uint32)]
 
+
+PREVIEW_MODES = {"hash": 0, "stride": 1, "grid": 2}
 
 _P = ctypes.POINTER
 
@@ -87,13 +90,16 @@ def _load():
 @dataclass
 class Params:
     """Build parameters: G count grid, C max points per chunk, S subsample grid,
-    L leaf capacity, M preview modulus; optional caller-given bounding box."""
+    L leaf capacity, M preview modulus; optional caller-given bounding box;
+    preview variant "hash" (H64(i) mod M == 0), "stride" (i mod M == 0) or
+    "grid" (least H64 of every occupied count-grid cell)."""
     count_grid: int = 64
     max_points_per_chunk: int = 100_000
     subsample_grid: int = 32
     leaf_capacity: int = 10_000
     preview_modulus: int = 64
     bbox: tuple | None = None  # ((xmin, ymin, zmin), (xmax, ymax, zmax))
+    preview: str = "hash"
 
 
 def h64(i: int) -> int:
@@ -118,6 +124,7 @@ def build_octree(x, y, z, params: Params) -> dict:
     assert y.shape[0] == n and z.shape[0] == n
     p = _Params(params.count_grid, params.max_points_per_chunk, params.subsample_grid,
                 params.leaf_capacity, params.preview_modulus, 1 if params.bbox is not None else 0)
+    p.preview_mode = PREVIEW_MODES[params.preview]
     if params.bbox is not None:
         for a in range(3):
             p.bbox_min[a] = params.bbox[0][a]

@@ -51,6 +51,12 @@ static uint64_t morton(uint32_t cx, uint32_t cy, uint32_t cz, uint32_t l)
     return k;
 }
 
+/* Row-major count-grid cell [cx][cy][cz] of fine coordinates u[0..2]. */
+static uint64_t grid_cell(const uint32_t *u, uint32_t G, uint32_t g)
+{
+    return ((uint64_t)(u[0] >> (K_BITS - g)) * G + (u[1] >> (K_BITS - g))) * G + (u[2] >> (K_BITS - g));
+}
+
 /* ---- step 1a: quantization onto the 21-bit lattice ------------------------
  * Reading: the cube is anchored at the box minimum with side = the largest
  * extent; scale = 2^21 / side computed in double and rounded once to float
@@ -252,7 +258,7 @@ int oracle_build(uint64_t n, const float *x, const float *y, const float *z,
 
     if (!p || !is_pow2(p->count_grid) || p->count_grid > 512 || !is_pow2(p->subsample_grid)
         || p->subsample_grid > 256 || p->max_points_per_chunk == 0 || p->leaf_capacity == 0
-        || p->preview_modulus == 0 || n > 0xFFFFFFFFull || (n > 0 && (!x || !y || !z))) {
+        || p->preview_modulus == 0 || p->preview_mode > ORACLE_PREVIEW_GRID || n > 0xFFFFFFFFull || (n > 0 && (!x || !y || !z))) {
         out->status = ORACLE_ERR_INVALID_ARG;
         return out->status;
     }
@@ -441,15 +447,45 @@ int oracle_build(uint64_t n, const float *x, const float *y, const float *z,
         if (oc.oom) { st = ORACLE_ERR_OOM; goto done; }
     }
 
-    /* ---- step 5: preview, every index i with H64(i) mod M == 0, ascending ---- */
+    /* ---- step 5: preview, ascending indices ----
+     * hash:   H64(i) mod M == 0 (section "Immediate Low-Resolution Rendering")
+     * stride: i mod M == 0 (the fixed-target decimation of section "Results")
+     * grid:   H64(i) is the least H64 among the points of i's count-grid cell
+     *         (section "Future Work"); H64 is a bijection, so one point per
+     *         occupied cell qualifies */
     {
+        uint64_t *best = NULL;
+        uint8_t *kept = NULL;
+        CHK(kept = (uint8_t *)malloc((size_t)(n ? n : 1)));
+        if (p->preview_mode == ORACLE_PREVIEW_GRID) {
+            const uint64_t cells = (uint64_t)G * G * G;
+            best = (uint64_t *)malloc((size_t)cells * sizeof(uint64_t));
+            if (!best) { free(kept); st = ORACLE_ERR_OOM; goto done; }
+            for (uint64_t c = 0; c < cells; ++c) best[c] = UINT64_MAX;
+            for (uint64_t i = 0; i < n; ++i) {
+                const uint64_t c = grid_cell(out->u + 3 * i, G, g);
+                const uint64_t h = oracle_h64(i);
+                if (h < best[c]) best[c] = h;
+            }
+        }
         uint64_t cnt = 0;
-        for (uint64_t i = 0; i < n; ++i) cnt += (oracle_h64(i) % M) == 0;
+        for (uint64_t i = 0; i < n; ++i) {
+            if (p->preview_mode == ORACLE_PREVIEW_GRID)
+                kept[i] = oracle_h64(i) == best[grid_cell(out->u + 3 * i, G, g)];
+            else if (p->preview_mode == ORACLE_PREVIEW_STRIDE)
+                kept[i] = i % M == 0;
+            else
+                kept[i] = oracle_h64(i) % M == 0;
+            cnt += kept[i];
+        }
+        free(best);
         out->preview_count = cnt;
-        CHK(out->preview_index = (uint32_t *)malloc((size_t)(cnt ? cnt : 1) * sizeof(uint32_t)));
+        out->preview_index = (uint32_t *)malloc((size_t)(cnt ? cnt : 1) * sizeof(uint32_t));
+        if (!out->preview_index) { free(kept); st = ORACLE_ERR_OOM; goto done; }
         uint64_t w = 0;
         for (uint64_t i = 0; i < n; ++i)
-            if (oracle_h64(i) % M == 0) out->preview_index[w++] = (uint32_t)i;
+            if (kept[i]) out->preview_index[w++] = (uint32_t)i;
+        free(kept);
     }
 
 done:

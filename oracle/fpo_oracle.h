@@ -24,6 +24,11 @@
 extern "C" {
 #endif
 
+/* Preview variants: H64(i) mod M == 0; i mod M == 0; least H64 of every
+ * occupied count-grid cell (section "Future Work": a spatially constrained
+ * sampler instead of uniform decimation). */
+enum { ORACLE_PREVIEW_HASH = 0, ORACLE_PREVIEW_STRIDE = 1, ORACLE_PREVIEW_GRID = 2 };
+
 enum { ORACLE_OK = 0, ORACLE_ERR_INVALID_ARG = 1, ORACLE_ERR_NONFINITE = 2, ORACLE_ERR_OOM = 3 };
 
 typedef struct {
@@ -34,6 +39,7 @@ typedef struct {
     uint32_t preview_modulus;      /* M >= 1 */
     uint32_t bbox_given;           /* 0: computed from the points; 1: use bbox_min/max */
     float bbox_min[3], bbox_max[3];
+    uint32_t preview_mode;         /* ORACLE_PREVIEW_HASH, _STRIDE or _GRID */
 } oracle_params;
 
 typedef struct {

@@ -21,6 +21,9 @@ LIB_PATH = os.path.join(HERE, "libfpo.so")
 FPO_OK, FPO_ERR_INVALID_ARG, FPO_ERR_NONFINITE, FPO_ERR_OUT_OF_MEMORY = 0, 1, 2, 3
 FPO_ERR_DEVICE, FPO_NOT_READY, FPO_ERR_REJECTED, FPO_ERR_CANCELLED = 4, 5, 6, 7
 FPO_BBOX_GIVEN = 1
+FPO_PREVIEW_STRIDE = 2
+FPO_PREVIEW_GRID = 4
+PREVIEW_FLAGS = {"hash": 0, "stride": FPO_PREVIEW_STRIDE, "grid": FPO_PREVIEW_GRID}
 
 #: every symbol include/fpo.h declares
 EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_workspace_size",
@@ -28,10 +31,11 @@ EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_w
            "fpo_job_result", "fpo_job_release", "fpo_workspace_size_cloud", "fpo_job_gather",
            "fpo_job_write_file", "fpo_job_export_bytes", "fpo_job_copy_to_host",
            "fpo_job_timestamps", "fpo_batch_workspace_size", "fpo_build_batch", "fpo_server_create",
-           "fpo_server_submit", "fpo_job_cancel", "fpo_server_destroy", "fpo_context_set_timing", "fpo_job_timer")
+           "fpo_server_submit", "fpo_job_cancel", "fpo_server_destroy", "fpo_context_set_timing", "fpo_job_timer",
+           "fpo_preview_modulus")
 
 # fpo_timer values (include/fpo.h)
-TIMERS = {"bbox": 0, "quantize": 1, "chunk_scatter": 2, "subsample": 3, "node_ids": 4, "node_points": 5}
+TIMERS = {"bbox": 0, "quantize": 1, "chunk_scatter": 2, "subsample": 3, "node_ids": 4, "node_points": 5, "preview": 6}
 
 
 class FpoError(RuntimeError):
@@ -88,6 +92,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_last_error.restype = ctypes.c_char_p
     lib.fpo_workspace_size.argtypes = [ctypes.c_uint64, P(_Params), P(ctypes.c_uint64)]
     lib.fpo_workspace_size.restype = ctypes.c_int
+    lib.fpo_preview_modulus.argtypes = [ctypes.c_uint64, ctypes.c_uint64, P(ctypes.c_uint32)]
+    lib.fpo_preview_modulus.restype = ctypes.c_int
     lib.fpo_workspace_size_cloud.argtypes = [P(_Cloud), P(_Params), P(ctypes.c_uint64)]
     lib.fpo_workspace_size_cloud.restype = ctypes.c_int
     lib.fpo_build_submit.argtypes = [vp, P(_Cloud), P(_Params), vp, ctypes.c_uint64, vp, P(vp)]
@@ -139,17 +145,22 @@ def _check(st: int):
 class Params:
     """G count grid, C max points per chunk, S subsample grid, L leaf capacity,
     M preview modulus; bbox = ((xmin, ymin, zmin), (xmax, ymax, zmax)) to use a
-    caller-given box."""
+    caller-given box; preview = "hash" (H64(i) mod M == 0), "stride"
+    (i mod M == 0) or "grid" (least H64 of every occupied count-grid cell)."""
     count_grid: int = 64
     max_points_per_chunk: int = 100_000
     subsample_grid: int = 32
     leaf_capacity: int = 10_000
     preview_modulus: int = 64
     bbox: tuple | None = None
+    preview: str = "hash"
 
     def to_c(self) -> _Params:
+        if self.preview not in PREVIEW_FLAGS:
+            raise ValueError(f"preview must be one of {sorted(PREVIEW_FLAGS)} (got {self.preview!r})")
+        flags = (FPO_BBOX_GIVEN if self.bbox is not None else 0) | PREVIEW_FLAGS[self.preview]
         p = _Params(self.count_grid, self.max_points_per_chunk, self.subsample_grid, self.leaf_capacity,
-                    self.preview_modulus, FPO_BBOX_GIVEN if self.bbox is not None else 0)
+                    self.preview_modulus, flags)
         if self.bbox is not None:
             for a in range(3):
                 p.bbox_min[a] = self.bbox[0][a]
@@ -161,6 +172,14 @@ def workspace_size(n: int, params: Params) -> int:
     lib = load_library()
     out = ctypes.c_uint64()
     _check(lib.fpo_workspace_size(n, ctypes.byref(params.to_c()), ctypes.byref(out)))
+    return int(out.value)
+
+
+def preview_modulus(n: int, target: int) -> int:
+    """M for a preview of about `target` points (at most `target` with preview="stride")."""
+    lib = load_library()
+    out = ctypes.c_uint32()
+    _check(lib.fpo_preview_modulus(n, target, ctypes.byref(out)))
     return int(out.value)
 
 

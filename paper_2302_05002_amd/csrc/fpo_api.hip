@@ -92,7 +92,7 @@ struct Plan {
     size_t c_count_scan, code_perm, wc_orig, wc_code, ms_temp, scan_temp, seg_b0, seg_nb, wc_nested, wc_chunk;
     size_t gtab, t, fr, alive, alive_scan, kd, loff, owned, node_base, lnode_key, lnode_mask, cut;
     size_t big_list, big_nr, big_node, big_hkey, big_hval, cls_list;
-    size_t nid, sorted_nid, pv_tiles, pv_offs;
+    size_t nid, sorted_nid, pv_tiles, pv_offs, cellmin, pv_bits;
     uint64_t pv_ntiles;
 };
 
@@ -110,7 +110,7 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     const uint64_t nn = n ? n : 1;
     P.maxC = nn < P.G3 ? nn : P.G3;
     P.maxW = nn < P.W3 ? nn : P.W3;
-    P.pv_ntiles = preview_tiles(nn);
+    P.pv_ntiles = bits_tiles(nn);
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t r = o;
@@ -192,6 +192,8 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     P.sorted_nid = take(4 * nn);
     P.pv_tiles = take(4 * P.pv_ntiles);
     P.pv_offs = take(4 * P.pv_ntiles);
+    P.cellmin = (p.flags & FPO_PREVIEW_GRID) ? take(8 * P.G3) : 0;
+    P.pv_bits = take(4 * ((nn + 31) / 32));
     P.total = o;
     return P;
 }
@@ -211,7 +213,10 @@ fpo_status check_params(uint64_t n, const fpo_params *p)
     if (p->leaf_capacity == 0) return fail(FPO_ERR_INVALID_ARG, "leaf_capacity must be >= 1");
     if (p->preview_modulus == 0) return fail(FPO_ERR_INVALID_ARG, "preview_modulus must be >= 1");
     if (n > 0xffffffffull) return fail(FPO_ERR_INVALID_ARG, "n = %llu exceeds 2^32 - 1", (unsigned long long)n);
-    if (p->flags & ~FPO_BBOX_GIVEN) return fail(FPO_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
+    if (p->flags & ~(FPO_BBOX_GIVEN | FPO_PREVIEW_STRIDE | FPO_PREVIEW_GRID))
+        return fail(FPO_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
+    if ((p->flags & FPO_PREVIEW_STRIDE) && (p->flags & FPO_PREVIEW_GRID))
+        return fail(FPO_ERR_INVALID_ARG, "FPO_PREVIEW_STRIDE and FPO_PREVIEW_GRID exclude each other");
     if (p->flags & FPO_BBOX_GIVEN)
         for (int a = 0; a < 3; ++a) {
             const float lo = p->bbox_min[a], hi = p->bbox_max[a];
@@ -330,6 +335,16 @@ fpo_status fpo_workspace_size(uint64_t n, const fpo_params *p, uint64_t *bytes)
     if (s != FPO_OK) return s;
     if (!bytes) return fail(FPO_ERR_INVALID_ARG, "bytes is NULL");
     *bytes = make_plan(n, *p).total;
+    return FPO_OK;
+}
+
+fpo_status fpo_preview_modulus(uint64_t n, uint64_t target, uint32_t *out)
+{
+    if (!out) return fail(FPO_ERR_INVALID_ARG, "out is NULL");
+    if (target == 0) return fail(FPO_ERR_INVALID_ARG, "target must be >= 1");
+    if (n > 0xffffffffull) return fail(FPO_ERR_INVALID_ARG, "n = %llu exceeds 2^32 - 1", (unsigned long long)n);
+    const uint64_t m = (n + target - 1) / target;
+    *out = (uint32_t)(m ? m : 1);
     return FPO_OK;
 }
 
@@ -505,13 +520,39 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         return FPO_OK;
     }
 
-    // ---- step 5 first: the preview depends on n and M only ----
-    launch_preview_count(n, M, U32(P.pv_tiles), st);
-    scan_exclusive(U32(P.pv_tiles), U32(P.pv_offs), P.pv_ntiles, &ctrs->preview_count, stemp, st);
-    launch_preview_write(n, M, U32(P.pv_offs), U32(P.pv_index), st);
-    JCHK(hipEventRecord(job->ev_preview, st));
-    published = true;
-    if (on_preview) on_preview(job);
+    // ---- step 5 first: hash and stride previews depend on n and M only ----
+    PreviewArgs pa{};
+    pa.n = n;
+    pa.m = M;
+    pa.mode = (p->flags & FPO_PREVIEW_GRID) ? PV_GRID : (p->flags & FPO_PREVIEW_STRIDE) ? PV_STRIDE : PV_HASH;
+    pa.code = U64(P.code);
+    pa.cellmin = U64(P.cellmin);
+    pa.shift = 3 * (KB - g);
+    JobTimer t_prev(job, FPO_TIMER_PREVIEW);
+    // ordered compaction of the kept indices, then the preview event (from
+    // here on the job belongs to its holder)
+    auto emit_preview = [&]() {
+        t_prev.begin(st);
+        uint32_t *bits = U32(P.pv_bits);
+        if (pa.mode == PV_GRID && P.G3 <= 2 * n) {
+            // fewer cells than 2n: a pass over the cell minima
+            launch_fill_u32(bits, 0u, (n + 31) / 32, st);
+            launch_grid_picks(pa.cellmin, P.G3, n, bits, st);
+        } else {
+            launch_preview_bits(pa, bits, st);
+        }
+        launch_bits_count(bits, n, U32(P.pv_tiles), st);
+        scan_exclusive(U32(P.pv_tiles), U32(P.pv_offs), bits_tiles(n), &ctrs->preview_count, stemp, st);
+        launch_bits_write(bits, n, U32(P.pv_offs), U32(P.pv_index), st);
+        t_prev.end(st);
+        const hipError_t e = hipEventRecord(job->ev_preview, st);
+        if (e == hipSuccess) {
+            published = true;
+            if (on_preview) on_preview(job);
+        }
+        return e;
+    };
+    if (pa.mode != PV_GRID) JCHK(emit_preview());
 
     // ---- step 1: bbox, quantise, count ----
     const int given = (p->flags & FPO_BBOX_GIVEN) ? 1 : 0;
@@ -555,6 +596,8 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     uint32_t *pyr = U32(P.pyr);
     uint32_t *fine = pyr + pyr_off(g);
     launch_fill_u32(fine, 0u, P.G3, st);
+    uint64_t *cellmin = pa.mode == PV_GRID ? U64(P.cellmin) : nullptr;
+    if (cellmin) launch_fill_u32(U32(P.cellmin), 0xffffffffu, 2 * P.G3, st);
     // with a given box the quantise + count pass of a batch can start as soon
     // as it has landed; the bounding-box pass (non-finite check) runs either way
     const bool per_batch_quantize = host_in && given;
@@ -570,7 +613,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         nparts += bbox_blocks(c);
         if (per_batch_quantize) {
             t_quant.begin(st);
-            launch_quantize(X + o, Y + o, Z + o, c, box, g, given, U64(P.code) + o, fine, box, st);
+            launch_quantize(X + o, Y + o, Z + o, c, box, g, given, U64(P.code) + o, fine, box, o, cellmin, st);
             t_quant.end(st);
         }
     }
@@ -579,9 +622,12 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     } else {
         launch_setup(box, U32(P.bbox_part), nparts, given, p->bbox_min, p->bbox_max, 0, st);
         t_quant.begin(st);
-        launch_quantize(X, Y, Z, n, box, g, given, U64(P.code), fine, box, st);
+        launch_quantize(X, Y, Z, n, box, g, given, U64(P.code), fine, box, 0, cellmin, st);
         t_quant.end(st);
     }
+
+    // grid preview: the least H64 of every occupied cell is known now
+    if (pa.mode == PV_GRID) JCHK(emit_preview());
 
     // ---- step 2: pyramid, chunk cut, work-chunk cut ----
     launch_pyramid(pyr, g, st);

@@ -68,9 +68,11 @@ void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, uin
 // flag_only: only the non-finite flag is reduced (the box was set before).
 void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given, const float *lo, const float *hi,
                   int flag_only, hipStream_t st);
+// base = original index of x[0]; cellmin (grid preview only, else nullptr)
+// receives the least H64 of each count-grid cell.
 void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box,
                      int g, int count_outside, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw,
-                     hipStream_t st);
+                     uint64_t base, uint64_t *cellmin, hipStream_t st);
 void launch_pyramid(uint32_t *pyr, int g, hipStream_t st);
 void launch_grid_export(const uint32_t *fine_morton, int g, uint32_t *rowmajor, hipStream_t st);
 void launch_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev, int lmin,
@@ -203,9 +205,25 @@ void launch_gather_points(const uint32_t *idx, uint64_t n, const float *x, const
                           const uint8_t *color, uint32_t stride, float *out_xyz, uint8_t *out_color, hipStream_t st);
 
 // Preview.
-void launch_preview_count(uint64_t n, uint64_t m, uint32_t *tile_counts, hipStream_t st);
-void launch_preview_write(uint64_t n, uint64_t m, const uint32_t *tile_offsets, uint32_t *out,
-                          hipStream_t st);
-uint64_t preview_tiles(uint64_t n);
+enum { PV_HASH = 0, PV_STRIDE = 1, PV_GRID = 2 };
+struct PreviewArgs {
+    uint64_t n;
+    uint64_t m;                  // modulus (hash, stride)
+    int mode;
+    const uint64_t *code;        // grid: Morton code per original index
+    const uint64_t *cellmin;     // grid: least H64 per count-grid cell
+    int shift;                   // grid: code >> shift = cell
+};
+// bits (ceil(n / 32) words) = the predicate of every index
+void launch_preview_bits(const PreviewArgs &p, uint32_t *bits, hipStream_t st);
+// Grid preview: the quantise pass leaves the least H64 of every count-grid
+// cell in cellmin (G^3 entries, all ones where empty); the picks follow either
+// from the inverse hash (into bits, zeroed before) or from the predicate
+// H64(i) == cellmin[cell(i)] (PV_GRID).  The map is then compacted in order.
+void launch_grid_picks(const uint64_t *cellmin, uint64_t cells, uint64_t n, uint32_t *bits, hipStream_t st);
+uint64_t bits_tiles(uint64_t n);
+void launch_bits_count(const uint32_t *bits, uint64_t n, uint32_t *tile_counts, hipStream_t st);
+void launch_bits_write(const uint32_t *bits, uint64_t n, const uint32_t *tile_offsets, uint32_t *out,
+                       hipStream_t st);
 
 }  // namespace fpo

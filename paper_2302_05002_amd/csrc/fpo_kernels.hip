@@ -281,16 +281,61 @@ __device__ __forceinline__ uint32_t quantize1(float a, float lo, float scale)
     return (uint32_t)floorf(t);
 }
 
+// ---- preview hash H64 and its inverse ----------------------------------------------
+// H64: xorshift-multiply mix with the golden-ratio constant, all mod 2^64.
+// Every step is invertible (an odd multiplier has an inverse mod 2^64; x ^= x
+// >> k is undone by folding the shifts back in), so H64 is a bijection and the
+// index of a hash value is recovered exactly.
+constexpr uint64_t H64_PHI = 0x9E3779B97F4A7C15ull;
+
+__host__ __device__ constexpr uint64_t inverse_odd64(uint64_t a)
+{
+    uint64_t x = a;                      // a * a == 1 mod 8: 3 correct bits
+    for (int k = 0; k < 5; ++k) x *= 2 - a * x;   // Newton: correct bits double each step
+    return x;
+}
+constexpr uint64_t H64_PHI_INV = inverse_odd64(H64_PHI);
+static_assert(H64_PHI * H64_PHI_INV == 1ull, "inverse of the hash multiplier");
+
+__host__ __device__ constexpr uint64_t h64(uint64_t i)
+{
+    uint64_t h = i;
+    h ^= h >> 31;
+    h *= H64_PHI;
+    h ^= h >> 29;
+    h *= H64_PHI;
+    h ^= h >> 32;
+    return h;
+}
+
+__host__ __device__ constexpr uint64_t h64_inverse(uint64_t h)
+{
+    h ^= h >> 32;
+    h *= H64_PHI_INV;
+    h ^= (h >> 29) ^ (h >> 58);
+    h *= H64_PHI_INV;
+    h ^= (h >> 31) ^ (h >> 62);
+    return h;
+}
+static_assert(h64(1) == 0xd8a77e5280806164ull && h64(5) == 0xe1a5a16ee48bea94ull, "hash known answers");
+static_assert(h64_inverse(h64(0)) == 0 && h64_inverse(h64(1)) == 1 && h64_inverse(h64(12345678901ull)) == 12345678901ull &&
+                  h64_inverse(h64(~0ull)) == ~0ull && h64_inverse(h64(0xffffffffull)) == 0xffffffffull,
+              "hash inverse");
+
 // ---- step 1b: quantise + count ---------------------------------------------------
 // One Morton code per point (x the most significant bit of each triple) and a
 // count per finest cell.  Global atomics cost ~40 ns each on this part, so a
 // block first aggregates the cells of its contiguous range of points in an
 // LDS hash table and flushes one atomic per distinct cell: scans emit points
 // surface by surface, so a range touches far fewer cells than it has points.
+// With the grid preview the same table also keeps the least H64 of each cell
+// (fewer slots, 64-bit minima) and flushes it with a 64-bit atomic minimum.
 constexpr int QZ_BLOCK = 1024;
-constexpr int QZ_ITEMS = 4;
-constexpr uint32_t QZ_ROUND = QZ_BLOCK * QZ_ITEMS;
-constexpr uint32_t QZ_HASH = 16384;   // slots (128 KB of LDS with the counts); kept at most half full
+template <bool GRID> struct Qz {
+    static constexpr int ITEMS = GRID ? 2 : 4;
+    static constexpr uint32_t ROUND = QZ_BLOCK * ITEMS;
+    static constexpr uint32_t HASH = GRID ? 8192 : 16384;   // slots, kept at most half full (128 KB of LDS)
+};
 
 __device__ __forceinline__ uint32_t hash32(uint32_t k)
 {
@@ -302,35 +347,47 @@ __device__ __forceinline__ uint32_t hash32(uint32_t k)
     return k;
 }
 
-__device__ void qz_flush(uint32_t *hk, uint32_t *hc, uint32_t *fine)
+template <bool GRID>
+__device__ void qz_flush(uint32_t *hk, uint32_t *hc, unsigned long long *hm, uint32_t *fine,
+                         unsigned long long *cellmin)
 {
-    for (uint32_t h = threadIdx.x; h < QZ_HASH; h += QZ_BLOCK) {
+    for (uint32_t h = threadIdx.x; h < Qz<GRID>::HASH; h += QZ_BLOCK) {
         const uint32_t k = hk[h];
         if (k != 0xffffffffu) {
             atomicAdd(&fine[k], hc[h]);
             hk[h] = 0xffffffffu;
             hc[h] = 0;
+            if constexpr (GRID) {
+                atomicMin(&cellmin[k], hm[h]);
+                hm[h] = ~0ull;
+            }
         }
     }
 }
 
 // One block per compute unit, each over a contiguous range of points.  The
 // coordinates of the next round are loaded before the hash updates of the
-// current one, so the loads stay in flight while the LDS work runs.
+// current one, so the loads stay in flight while the LDS work runs.  `base`
+// is the original index of x[0] (batches of a streamed cloud).
+template <bool GRID>
 __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__ x, const float *__restrict__ y,
                                                        const float *__restrict__ z, uint64_t n, const DevBox *box,
                                                        int g, int count_outside, uint64_t *__restrict__ code,
-                                                       uint32_t *__restrict__ fine, DevBox *box_rw, uint64_t per_block)
+                                                       uint32_t *__restrict__ fine, DevBox *box_rw, uint64_t per_block,
+                                                       uint64_t base, unsigned long long *__restrict__ cellmin)
 {
-    __shared__ uint32_t hk[QZ_HASH];
-    __shared__ uint32_t hc[QZ_HASH];
+    constexpr int ITEMS = Qz<GRID>::ITEMS;
+    constexpr uint32_t ROUND = Qz<GRID>::ROUND, HASH = Qz<GRID>::HASH;
+    __shared__ uint32_t hk[HASH];
+    __shared__ uint32_t hc[HASH];
+    __shared__ unsigned long long hm[GRID ? HASH : 1];
     __shared__ uint32_t used;
     __shared__ uint32_t wsum[QZ_BLOCK / 64];
     const uint64_t lo = (uint64_t)blockIdx.x * per_block;
     const uint64_t hi = lo + per_block < n ? lo + per_block : n;
-    float px[QZ_ITEMS], py[QZ_ITEMS], pz[QZ_ITEMS];
+    float px[ITEMS], py[ITEMS], pz[ITEMS];
 #pragma unroll
-    for (int j = 0; j < QZ_ITEMS; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const uint64_t i = lo + (uint64_t)j * QZ_BLOCK + threadIdx.x;
         px[j] = i < hi ? x[i] : 0.0f;
         py[j] = i < hi ? y[i] : 0.0f;
@@ -339,17 +396,18 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
     const float lx = box->lo[0], ly = box->lo[1], lz = box->lo[2], sc = box->scale;
     const float hx = box->hi[0], hy = box->hi[1], hz = box->hi[2];
     const int sh = 3 * (KB - g);
-    for (uint32_t h = threadIdx.x; h < QZ_HASH; h += QZ_BLOCK) {
+    for (uint32_t h = threadIdx.x; h < HASH; h += QZ_BLOCK) {
         hk[h] = 0xffffffffu;
         hc[h] = 0;
+        if constexpr (GRID) hm[h] = ~0ull;
     }
     if (threadIdx.x == 0) used = 0;
     __syncthreads();
     uint32_t outside = 0;
-    for (uint64_t r0 = lo; r0 < hi; r0 += QZ_ROUND) {
-        uint32_t cell[QZ_ITEMS];
+    for (uint64_t r0 = lo; r0 < hi; r0 += ROUND) {
+        uint32_t cell[ITEMS];
 #pragma unroll
-        for (int j = 0; j < QZ_ITEMS; ++j) {
+        for (int j = 0; j < ITEMS; ++j) {
             const uint64_t i = r0 + (uint64_t)j * QZ_BLOCK + threadIdx.x;
             const uint32_t ux = quantize1(px[j], lx, sc), uy = quantize1(py[j], ly, sc), uz = quantize1(pz[j], lz, sc);
             const uint64_t c = (split3(ux) << 2) | (split3(uy) << 1) | split3(uz);
@@ -360,17 +418,17 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
         }
         // next round's coordinates
 #pragma unroll
-        for (int j = 0; j < QZ_ITEMS; ++j) {
-            const uint64_t i = r0 + QZ_ROUND + (uint64_t)j * QZ_BLOCK + threadIdx.x;
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint64_t i = r0 + ROUND + (uint64_t)j * QZ_BLOCK + threadIdx.x;
             px[j] = i < hi ? x[i] : 0.0f;
             py[j] = i < hi ? y[i] : 0.0f;
             pz[j] = i < hi ? z[i] : 0.0f;
         }
 #pragma unroll
-        for (int j = 0; j < QZ_ITEMS; ++j) {
+        for (int j = 0; j < ITEMS; ++j) {
             const uint32_t cl = cell[j];
             if (cl == 0xffffffffu) continue;
-            uint32_t h = hash32(cl) & (QZ_HASH - 1);
+            uint32_t h = hash32(cl) & (HASH - 1);
             while (true) {
                 uint32_t k = hk[h];
                 if (k == 0xffffffffu) {
@@ -382,23 +440,25 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
                 }
                 if (k == cl) {
                     atomicAdd(&hc[h], 1u);
+                    if constexpr (GRID)
+                        atomicMin(&hm[h], (unsigned long long)h64(base + r0 + (uint64_t)j * QZ_BLOCK + threadIdx.x));
                     break;
                 }
-                h = (h + 1) & (QZ_HASH - 1);
+                h = (h + 1) & (HASH - 1);
             }
         }
         __syncthreads();
-        // at most QZ_ROUND new cells per round: keep the table at most half
+        // at most ROUND new cells per round: keep the table at most half
         // full before the next one
-        if (used > QZ_HASH / 2 - QZ_ROUND) {
-            qz_flush(hk, hc, fine);
+        if (used > HASH / 2 - ROUND) {
+            qz_flush<GRID>(hk, hc, hm, fine, cellmin);
             __syncthreads();
             if (threadIdx.x == 0) used = 0;
             __syncthreads();
         }
     }
     __syncthreads();
-    qz_flush(hk, hc, fine);
+    qz_flush<GRID>(hk, hc, hm, fine, cellmin);
     if (count_outside) {
         // one atomic per block (the same counter for every block)
         outside = wave_sum(outside);
@@ -560,6 +620,36 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(const uint32_t *in, ui
     }
 }
 
+// Short arrays: one block, 4096 elements per round with a running carry (one
+// launch instead of three).
+constexpr uint64_t SCAN_SMALL_MAX = 16384;
+
+__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t *in, uint32_t *out, uint64_t n,
+                                                     const uint32_t *n_dev, uint32_t *total)
+{
+    __shared__ uint32_t lds[1024 / 64 + 1];
+    if (n_dev && *n_dev < n) n = *n_dev;
+    uint32_t carry = 0;
+    for (uint64_t b = 0; b < n; b += 4096) {
+        const uint64_t e0 = b + 4ull * threadIdx.x;
+        uint32_t v[4], s = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = e0 + j < n ? in[e0 + j] : 0u;
+            s += v[j];
+        }
+        uint32_t t;
+        uint32_t run = carry + block_excl_scan<1024>(s, lds, &t);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (e0 + j < n) out[e0 + j] = run;
+            run += v[j];
+        }
+        carry += t;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
 size_t scan_temp_bytes(uint64_t n)
 {
     const uint64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
@@ -570,6 +660,10 @@ void scan_exclusive(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tot
 {
     if (n == 0) {
         if (total) launch_fill_u32(total, 0u, 1, st);
+        return;
+    }
+    if (n <= SCAN_SMALL_MAX) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, in, out, n, nullptr, total);
         return;
     }
     const uint32_t tiles = div_up(n, SCAN_TILE);
@@ -583,6 +677,10 @@ void scan_exclusive_dev(const uint32_t *in, uint32_t *out, const uint32_t *n_dev
                         hipStream_t st)
 {
     if (n_max == 0) return;
+    if (n_max <= SCAN_SMALL_MAX) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, in, out, n_max, n_dev, nullptr);
+        return;
+    }
     const uint32_t tiles = div_up(n_max, SCAN_TILE);
     uint32_t *ts = static_cast<uint32_t *>(temp);
     hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, n_max, n_dev, ts);
@@ -2029,58 +2127,87 @@ __global__ void k_node_count_fix(const uint64_t *begin, uint32_t *count, uint32_
 }
 
 // ---- step 5: preview ---------------------------------------------------------------------------
-// Keep index i iff H64(i) mod M == 0, H64 a xorshift-multiply mix with the
-// golden-ratio constant; ordered compaction (count per tile, scan, write).
+// Modes: keep index i iff H64(i) mod M == 0, iff i mod M == 0 (an exact
+// stride), or iff i is the point of least H64 in its count-grid cell (one pick
+// per occupied cell; H64 is a bijection, so there are no ties).  The kept
+// indices form an n-bit map, compacted in order: count per tile, scan, write.
 
-__device__ __forceinline__ uint64_t h64(uint64_t i)
+__device__ __forceinline__ bool keep(const PreviewArgs &p, uint64_t i)
 {
-    const uint64_t phi = 0x9E3779B97F4A7C15ull;
-    uint64_t h = i;
-    h ^= h >> 31;
-    h *= phi;
-    h ^= h >> 29;
-    h *= phi;
-    h ^= h >> 32;
-    return h;
+    if (p.mode == PV_GRID) return h64(i) == p.cellmin[p.code[i] >> p.shift];
+    const uint64_t v = p.mode == PV_STRIDE ? i : h64(i);
+    return (p.m & (p.m - 1)) == 0 ? (v & (p.m - 1)) == 0 : (v % p.m) == 0;
 }
-__device__ __forceinline__ bool keep(uint64_t i, uint64_t m) { return (m & (m - 1)) == 0 ? (h64(i) & (m - 1)) == 0 : (h64(i) % m) == 0; }
 
+// The predicate of every index into an n-bit map: a wave covers 64
+// consecutive indices per step, and its ballot is two words of the map.
 constexpr int PV_BLOCK = 256, PV_ITEMS = 16;
 constexpr uint64_t PV_TILE = PV_BLOCK * PV_ITEMS;
 
-__global__ __launch_bounds__(PV_BLOCK) void k_preview_count(uint64_t n, uint64_t m, uint32_t *tc)
+__global__ __launch_bounds__(PV_BLOCK) void k_preview_bits(PreviewArgs p, uint32_t *__restrict__ bits)
 {
-    __shared__ uint32_t red[PV_BLOCK / 64 + 1];
-    const uint64_t base = (uint64_t)blockIdx.x * PV_TILE;
-    uint32_t c = 0;
+    const uint64_t words = (p.n + 31) / 32;
+    const uint64_t base = (uint64_t)blockIdx.x * PV_TILE + (uint64_t)(threadIdx.x >> 6) * (64 * PV_ITEMS);
     for (int j = 0; j < PV_ITEMS; ++j) {
-        const uint64_t i = base + (uint64_t)j * PV_BLOCK + threadIdx.x;
-        c += (i < n && keep(i, m)) ? 1u : 0u;
+        const uint64_t i0 = base + (uint64_t)j * 64;
+        const uint64_t i = i0 + lane_id();
+        const uint64_t m = __ballot(i < p.n && keep(p, i));
+        const uint64_t w = i0 / 32;
+        if (lane_id() == 0 && w < words) bits[w] = (uint32_t)m;
+        if (lane_id() == 1 && w + 1 < words) bits[w + 1] = (uint32_t)(m >> 32);
     }
-    c = block_sum<PV_BLOCK>(c, red);
+}
+
+// Grid preview from the per-cell minima (computed by the quantise pass): the
+// pick of an occupied cell is the index whose hash is the cell's minimum, so
+// inverting the hash gives it directly; its bit is set in an n-bit map.
+__global__ void k_grid_picks(const unsigned long long *__restrict__ cellmin, uint64_t cells, uint64_t n,
+                             uint32_t *__restrict__ bits)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += stride) {
+        const unsigned long long h = cellmin[c];
+        if (h == ~0ull) continue;
+        const uint64_t i = h64_inverse(h);
+        if (i < n) atomicOr(&bits[i >> 5], 1u << (i & 31));
+    }
+}
+
+// Ordered compaction of a bit map, a word per thread and round.
+constexpr int BW_BLOCK = 256, BW_ITEMS = 16;
+constexpr uint64_t BW_TILE = (uint64_t)BW_BLOCK * BW_ITEMS;   // words per tile
+
+__global__ __launch_bounds__(BW_BLOCK) void k_bits_count(const uint32_t *__restrict__ bits, uint64_t words,
+                                                         uint32_t *tc)
+{
+    __shared__ uint32_t red[BW_BLOCK / 64 + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * BW_TILE;
+    uint32_t c = 0;
+    for (int j = 0; j < BW_ITEMS; ++j) {
+        const uint64_t w = base + (uint64_t)j * BW_BLOCK + threadIdx.x;
+        c += w < words ? (uint32_t)__popc(bits[w]) : 0u;
+    }
+    c = block_sum<BW_BLOCK>(c, red);
     if (threadIdx.x == 0) tc[blockIdx.x] = c;
 }
 
-__global__ __launch_bounds__(PV_BLOCK) void k_preview_write(uint64_t n, uint64_t m, const uint32_t *toff, uint32_t *out)
+__global__ __launch_bounds__(BW_BLOCK) void k_bits_write(const uint32_t *__restrict__ bits, uint64_t words,
+                                                         const uint32_t *toff, uint32_t *out)
 {
-    __shared__ uint32_t wcnt[PV_BLOCK / 64];
-    const uint64_t base = (uint64_t)blockIdx.x * PV_TILE;
+    __shared__ uint32_t lds[BW_BLOCK / 64 + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * BW_TILE;
     uint32_t run = toff[blockIdx.x];
-    const int w = threadIdx.x >> 6, lane = lane_id();
-    for (int j = 0; j < PV_ITEMS; ++j) {
-        const uint64_t i = base + (uint64_t)j * PV_BLOCK + threadIdx.x;
-        const bool k = i < n && keep(i, m);
-        const uint64_t b = __ballot(k);
-        if (lane == 0) wcnt[w] = (uint32_t)__popcll(b);
-        __syncthreads();
-        uint32_t before = 0, tot = 0;
-        for (int q = 0; q < PV_BLOCK / 64; ++q) {
-            before += q < w ? wcnt[q] : 0u;
-            tot += wcnt[q];
+    for (int j = 0; j < BW_ITEMS; ++j) {
+        const uint64_t w = base + (uint64_t)j * BW_BLOCK + threadIdx.x;
+        uint32_t b = w < words ? bits[w] : 0u;
+        uint32_t tot;
+        uint32_t o = run + block_excl_scan<BW_BLOCK>((uint32_t)__popc(b), lds, &tot);
+        while (b) {
+            const int k = __ffs(b) - 1;
+            out[o++] = (uint32_t)(w * 32 + (uint64_t)k);
+            b &= b - 1;
         }
-        if (k) out[run + before + (uint32_t)__popcll(b & ((1ull << lane) - 1ull))] = (uint32_t)i;
         run += tot;
-        __syncthreads();
     }
 }
 
@@ -2122,7 +2249,8 @@ void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given,
 }
 
 void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box, int g,
-                     int count_outside, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw, hipStream_t st)
+                     int count_outside, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw, uint64_t base,
+                     uint64_t *cellmin, hipStream_t st)
 {
     if (n == 0) return;
     // one contiguous range per block, about one block per compute unit
@@ -2130,8 +2258,13 @@ void launch_quantize(const float *x, const float *y, const float *z, uint64_t n,
     uint64_t per = (n + 255) / 256;
     per = (per + 63) / 64 * 64;
     const uint32_t grid = (uint32_t)((n + per - 1) / per);
-    hipLaunchKernelGGL(k_quantize, dim3(grid), dim3(QZ_BLOCK), 0, st, x, y, z, n, box, g, count_outside, code,
-                       fine_cnt, box_rw, per);
+    auto *cm = reinterpret_cast<unsigned long long *>(cellmin);
+    if (cellmin)
+        hipLaunchKernelGGL(k_quantize<true>, dim3(grid), dim3(QZ_BLOCK), 0, st, x, y, z, n, box, g, count_outside,
+                           code, fine_cnt, box_rw, per, base, cm);
+    else
+        hipLaunchKernelGGL(k_quantize<false>, dim3(grid), dim3(QZ_BLOCK), 0, st, x, y, z, n, box, g, count_outside,
+                           code, fine_cnt, box_rw, per, base, cm);
 }
 
 void launch_pyramid(uint32_t *pyr, int g, hipStream_t st)
@@ -2266,18 +2399,33 @@ void launch_node_ranges(const uint32_t *sorted_keys, uint64_t n, uint64_t *begin
     hipLaunchKernelGGL(k_node_count_fix, dim3(grid_for(num_nodes, 256)), dim3(256), 0, st, begin, count, num_nodes);
 }
 
-uint64_t preview_tiles(uint64_t n) { return (n + PV_TILE - 1) / PV_TILE; }
+static uint64_t preview_tiles(uint64_t n) { return (n + PV_TILE - 1) / PV_TILE; }
 
-void launch_preview_count(uint64_t n, uint64_t m, uint32_t *tc, hipStream_t st)
+void launch_preview_bits(const PreviewArgs &p, uint32_t *bits, hipStream_t st)
 {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_preview_count, dim3((uint32_t)preview_tiles(n)), dim3(PV_BLOCK), 0, st, n, m, tc);
+    if (p.n == 0) return;
+    hipLaunchKernelGGL(k_preview_bits, dim3((uint32_t)preview_tiles(p.n)), dim3(PV_BLOCK), 0, st, p, bits);
 }
 
-void launch_preview_write(uint64_t n, uint64_t m, const uint32_t *toff, uint32_t *out, hipStream_t st)
+uint64_t bits_tiles(uint64_t n) { return ((n + 31) / 32 + BW_TILE - 1) / BW_TILE; }
+
+void launch_grid_picks(const uint64_t *cellmin, uint64_t cells, uint64_t n, uint32_t *bits, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_grid_picks, dim3(grid_for(cells, 256, 8192)), dim3(256), 0, st,
+                       reinterpret_cast<const unsigned long long *>(cellmin), cells, n, bits);
+}
+
+void launch_bits_count(const uint32_t *bits, uint64_t n, uint32_t *tc, hipStream_t st)
 {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_preview_write, dim3((uint32_t)preview_tiles(n)), dim3(PV_BLOCK), 0, st, n, m, toff, out);
+    hipLaunchKernelGGL(k_bits_count, dim3((uint32_t)bits_tiles(n)), dim3(BW_BLOCK), 0, st, bits, (n + 31) / 32, tc);
+}
+
+void launch_bits_write(const uint32_t *bits, uint64_t n, const uint32_t *toff, uint32_t *out, hipStream_t st)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_bits_write, dim3((uint32_t)bits_tiles(n)), dim3(BW_BLOCK), 0, st, bits, (n + 31) / 32, toff,
+                       out);
 }
 
 }  // namespace fpo

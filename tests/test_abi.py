@@ -57,3 +57,44 @@ def test_workspace_grows_with_n(lib):
     a = fpo.workspace_size(10_000, fpo.Params())
     b = fpo.workspace_size(1_000_000, fpo.Params())
     assert b > a
+
+
+def test_preview_modulus_for_a_target(lib):
+    """M = max(1, ceil(n / target)); the stride preview then has ceil(n / M)
+    <= target indices (the paper decimates to a fixed one million points)."""
+    import paper_2302_05002_amd as fpo
+    fpo.load_library(LIB)
+    assert fpo.preview_modulus(100_000_000, 1_000_000) == 100
+    assert fpo.preview_modulus(1_000_001, 1_000_000) == 2
+    assert fpo.preview_modulus(5, 10) == 1
+    assert fpo.preview_modulus(0, 1) == 1
+    assert fpo.preview_modulus(0xFFFFFFFF, 1) == 0xFFFFFFFF
+    rng = __import__("random").Random(4)
+    for _ in range(2000):
+        n, t = rng.randrange(0, 1 << 32), rng.randrange(1, 1 << 33)
+        m = fpo.preview_modulus(n, t)
+        assert m >= 1 and -(-n // m) <= t
+        assert m == 1 or -(-n // (m - 1)) > t   # the least such M
+    for n, t in ((10, 0), (1 << 32, 5)):
+        with pytest.raises(fpo.FpoError) as e:
+            fpo.preview_modulus(n, t)
+        assert e.value.status == fpo.FPO_ERR_INVALID_ARG
+
+
+def test_preview_flags(lib):
+    import paper_2302_05002_amd as fpo
+    fpo.load_library(LIB)
+    both = fpo.Params()
+    c = both.to_c()
+    c.flags = fpo.FPO_PREVIEW_STRIDE | fpo.FPO_PREVIEW_GRID
+    out = ctypes.c_uint64()
+    assert fpo.load_library().fpo_workspace_size(100, ctypes.byref(c), ctypes.byref(out)) == fpo.FPO_ERR_INVALID_ARG
+    c.flags = 8
+    assert fpo.load_library().fpo_workspace_size(100, ctypes.byref(c), ctypes.byref(out)) == fpo.FPO_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        fpo.Params(preview="voxel").to_c()
+    # the grid preview adds its per-cell minima (8 bytes per count-grid cell)
+    for G in (1, 64, 512):
+        h = fpo.workspace_size(1000, fpo.Params(count_grid=G))
+        assert fpo.workspace_size(1000, fpo.Params(count_grid=G, preview="stride")) == h
+        assert fpo.workspace_size(1000, fpo.Params(count_grid=G, preview="grid")) >= h + 8 * G ** 3
