@@ -2174,7 +2174,7 @@ __global__ void k_grid_picks(const unsigned long long *__restrict__ cellmin, uin
 }
 
 // Ordered compaction of a bit map, a word per thread and round.
-constexpr int BW_BLOCK = 256, BW_ITEMS = 16;
+constexpr int BW_BLOCK = 256, BW_ITEMS = 2;
 constexpr uint64_t BW_TILE = (uint64_t)BW_BLOCK * BW_ITEMS;   // words per tile
 
 __global__ __launch_bounds__(BW_BLOCK) void k_bits_count(const uint32_t *__restrict__ bits, uint64_t words,
