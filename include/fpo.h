@@ -328,6 +328,51 @@ fpo_status fpo_context_set_timing(fpo_context *ctx, int enable);
  * unknown timer, a job that was not timed or is not complete. */
 fpo_status fpo_job_timer(fpo_job *job, fpo_timer which, float *ms, uint32_t *launches);
 
+/* ---- LAS point records --------------------------------------------------------
+ * Section "File Importing": clouds arrive as LAS files.  A LAS file (ASPRS LAS
+ * 1.0-1.4) holds a public header block, variable-length records, then n
+ * fixed-size little-endian point records whose first twelve bytes are the
+ * int32 coordinates X, Y, Z (point data record formats 0-10; LAZ-compressed
+ * records are not supported).  The decode turns records into the float32
+ * structure of arrays a build takes, per axis:
+ *     x = (float)((X * scale_x + offset_x) - origin_x)
+ * with IEEE double arithmetic rounded to nearest after each operation (no
+ * fused multiply-add) and one rounding to float32.  The caller picks the
+ * origin (the header's minimum, say) so that float32 keeps the file's
+ * precision near the data. */
+typedef struct {
+    uint8_t version_major, version_minor;
+    uint8_t point_format;      /* 0..10 */
+    uint8_t has_rgb;           /* 1 if the format stores R, G, B */
+    uint16_t record_length;    /* bytes per point record (>= the format's minimum: 20 28 26 34 57 63 30 36 38 59 67) */
+    uint16_t rgb_offset;       /* byte offset of R, G, B (uint16 each) in a record when has_rgb */
+    uint32_t offset_to_points; /* file offset of the first point record */
+    uint64_t num_points;       /* LAS 1.4: the 64-bit count; earlier versions: the 32-bit one */
+    double scale[3], offset[3];
+    double min[3], max[3];     /* the header's box, x y z */
+} fpo_las_header;
+
+/* Parses the public header block in bytes[0..len) (host memory).
+ * FPO_ERR_INVALID_ARG if it is not a LAS header, is shorter than its version
+ * requires, has an unknown or compressed record format, a record length
+ * below the format's minimum, points that start inside the header, or a
+ * non-finite scale or offset. */
+fpo_status fpo_las_parse_header(const void *bytes, uint64_t len, fpo_las_header *out);
+
+/* The header's box in the decoded frame: lo = (float)(min - origin), hi =
+ * (float)(max - origin), per axis (for FPO_BBOX_GIVEN). */
+fpo_status fpo_las_header_box(const fpo_las_header *h, const double origin[3], float lo[3], float hi[3]);
+
+/* Enqueues the decode of the n records at `records` (device, record_length
+ * bytes each, any alignment) on hip_stream (NULL = the context's stream):
+ * x, y, z (device float32[n]) as above and, if rgb is not NULL, R, G, B
+ * (device uint16[3n], interleaved per point; the format must have them).
+ * Returns once enqueued; the outputs are ready when the stream reaches the
+ * decode.  FPO_ERR_INVALID_ARG for NULL arguments, n > 2^32 - 1, an
+ * inconsistent header or a non-finite origin. */
+fpo_status fpo_las_decode(fpo_context *ctx, const fpo_las_header *h, const void *records, uint64_t n,
+                          const double origin[3], float *x, float *y, float *z, uint16_t *rgb, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,7 @@ EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_w
            "fpo_job_write_file", "fpo_job_export_bytes", "fpo_job_copy_to_host",
            "fpo_job_timestamps", "fpo_batch_workspace_size", "fpo_build_batch", "fpo_server_create",
            "fpo_server_submit", "fpo_job_cancel", "fpo_server_destroy", "fpo_context_set_timing", "fpo_job_timer",
-           "fpo_preview_modulus")
+           "fpo_preview_modulus", "fpo_las_parse_header", "fpo_las_header_box", "fpo_las_decode")
 
 # fpo_timer values (include/fpo.h)
 TIMERS = {"bbox": 0, "quantize": 1, "chunk_scatter": 2, "subsample": 3, "node_ids": 4, "node_points": 5, "preview": 6}
@@ -52,6 +52,15 @@ class _Params(ctypes.Structure):
 
 
 FPO_DEVICE, FPO_HOST_PINNED = 0, 1
+
+
+class _LasHeader(ctypes.Structure):
+    _fields_ = [("version_major", ctypes.c_uint8), ("version_minor", ctypes.c_uint8),
+                ("point_format", ctypes.c_uint8), ("has_rgb", ctypes.c_uint8),
+                ("record_length", ctypes.c_uint16), ("rgb_offset", ctypes.c_uint16),
+                ("offset_to_points", ctypes.c_uint32), ("num_points", ctypes.c_uint64),
+                ("scale", ctypes.c_double * 3), ("offset", ctypes.c_double * 3),
+                ("min", ctypes.c_double * 3), ("max", ctypes.c_double * 3)]
 
 
 class _Cloud(ctypes.Structure):
@@ -92,6 +101,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_last_error.restype = ctypes.c_char_p
     lib.fpo_workspace_size.argtypes = [ctypes.c_uint64, P(_Params), P(ctypes.c_uint64)]
     lib.fpo_workspace_size.restype = ctypes.c_int
+    lib.fpo_las_parse_header.argtypes = [vp, ctypes.c_uint64, P(_LasHeader)]
+    lib.fpo_las_parse_header.restype = ctypes.c_int
+    lib.fpo_las_header_box.argtypes = [P(_LasHeader), P(ctypes.c_double), P(ctypes.c_float), P(ctypes.c_float)]
+    lib.fpo_las_header_box.restype = ctypes.c_int
+    lib.fpo_las_decode.argtypes = [vp, P(_LasHeader), vp, ctypes.c_uint64, P(ctypes.c_double), vp, vp, vp, vp, vp]
+    lib.fpo_las_decode.restype = ctypes.c_int
     lib.fpo_preview_modulus.argtypes = [ctypes.c_uint64, ctypes.c_uint64, P(ctypes.c_uint32)]
     lib.fpo_preview_modulus.restype = ctypes.c_int
     lib.fpo_workspace_size_cloud.argtypes = [P(_Cloud), P(_Params), P(ctypes.c_uint64)]
@@ -183,6 +198,44 @@ def preview_modulus(n: int, target: int) -> int:
     return int(out.value)
 
 
+_SIDE_STREAMS = {}
+
+
+def _ordered_stream(dev, stream):
+    """(stream to enqueue on, stream that must wait for it afterwards or None).
+    The library maps a NULL stream to the context's own non-blocking stream,
+    which is not ordered with torch's default (null) stream; work meant for
+    that stream goes to a side stream that first waits for it instead."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    if stream.cuda_stream != 0:
+        return stream, None
+    side = _SIDE_STREAMS.get(dev.index)
+    if side is None:
+        side = _SIDE_STREAMS[dev.index] = torch.cuda.Stream(dev)
+    side.wait_stream(stream)
+    return side, stream
+
+
+def las_parse_header(data: bytes) -> _LasHeader:
+    """The public header block of a LAS file (fpo_las_parse_header)."""
+    lib = load_library()
+    h = _LasHeader()
+    buf = ctypes.create_string_buffer(bytes(data[:4096]), min(len(data), 4096))
+    _check(lib.fpo_las_parse_header(buf, min(len(data), 4096), ctypes.byref(h)))
+    return h
+
+
+def las_header_box(h: _LasHeader, origin=(0.0, 0.0, 0.0)):
+    """((lo), (hi)) of the header's box in the decoded frame, float32 values."""
+    lib = load_library()
+    o = (ctypes.c_double * 3)(*origin)
+    lo, hi = (ctypes.c_float * 3)(), (ctypes.c_float * 3)()
+    _check(lib.fpo_las_header_box(ctypes.byref(h), o, lo, hi))
+    return tuple(lo), tuple(hi)
+
+
 class Context:
     """One device: its own stream and pinned staging."""
 
@@ -228,13 +281,36 @@ class Context:
         dev = torch.device("cuda", self.device)
         if workspace is None:
             workspace = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
-        if stream is None:
-            stream = torch.cuda.current_stream(dev)
+        stream, _ = _ordered_stream(dev, stream)   # inputs ready; results are read after wait()
         h = ctypes.c_void_p()
         _check(_lib.fpo_build_submit(self._h, ctypes.byref(cloud), ctypes.byref(params.to_c()),
                                      ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                      ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
         return Job(h, workspace, params, (x, y, z))
+
+    def las_decode(self, records, header: _LasHeader, origin=(0.0, 0.0, 0.0), rgb: bool = False, n=None,
+                   stream=None):
+        """Decode LAS point records (a uint8 device tensor, any alignment) into
+        float32 x, y, z device tensors (and uint16 [n, 3] colours when rgb).
+        Enqueued on `stream` (default: torch's current stream)."""
+        import torch
+        assert records.is_cuda and records.dtype == torch.uint8 and records.is_contiguous()
+        if n is None:
+            n = records.numel() // header.record_length
+        assert n * header.record_length <= records.numel()
+        dev = records.device
+        x, y, z = (torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3))
+        col = torch.empty((n, 3), dtype=torch.int16, device=dev) if rgb else None
+        stream, back = _ordered_stream(dev, stream)
+        o = (ctypes.c_double * 3)(*origin)
+        _check(_lib.fpo_las_decode(self._h, ctypes.byref(header), ctypes.c_void_p(records.data_ptr()), n, o,
+                                   ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                   ctypes.c_void_p(z.data_ptr()),
+                                   ctypes.c_void_p(col.data_ptr()) if rgb else None,
+                                   ctypes.c_void_p(stream.cuda_stream)))
+        if back is not None:
+            back.wait_stream(stream)
+        return x, y, z, col
 
     def build(self, x, y, z, params: Params, workspace=None, stream=None) -> "Result":
         job = self.submit(x, y, z, params, workspace, stream)
@@ -266,8 +342,7 @@ class Context:
             return []
         if workspace is None:
             workspace = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev)
-        if stream is None:
-            stream = torch.cuda.current_stream(dev)
+        stream, _ = _ordered_stream(dev, stream)
         hs = (ctypes.c_void_p * count)()
         _check(_lib.fpo_build_batch(self._h, cs, ps, count, ctypes.c_void_p(workspace.data_ptr()),
                                     workspace.numel(), ctypes.c_void_p(stream.cuda_stream), hs))
@@ -356,12 +431,13 @@ class Job:
         n = int(cloud.n)
         out_xyz = torch.empty((n, 3), dtype=torch.float32, device=x.device)
         out_col = torch.empty((n, stride), dtype=torch.uint8, device=x.device) if stride else None
-        if stream is None:
-            stream = torch.cuda.current_stream(x.device)
+        stream, back = _ordered_stream(x.device, stream)
         _check(_lib.fpo_job_gather(self._h, ctypes.byref(cloud), ctypes.c_void_p(color.data_ptr() if stride else 0),
                                    stride, ctypes.c_void_p(out_xyz.data_ptr()),
                                    ctypes.c_void_p(out_col.data_ptr() if stride else 0),
                                    ctypes.c_void_p(stream.cuda_stream)))
+        if back is not None:
+            back.wait_stream(stream)
         return out_xyz, out_col
 
     def write_file(self, path: str, x, y, z, color=None):
