@@ -404,6 +404,46 @@ def main():
     print(f"[bench] preview variants: " + ", ".join(f"{k} {v['preview_ms']:.3f} ms ({v['picks']} picks)"
                                                     for k, v in preview_stats.items()), file=sys.stderr, flush=True)
     gather_stats = bench_gather()
+
+    def bench_select(reps: int = 20) -> dict:
+        """Node selection for one perspective view of the built tree (eye outside
+        the cloud, 60 degree field of view, 1080-pixel viewport, nodes refined
+        above 100 pixels): time per view from the host (launches, compaction
+        and the read-back of the two totals)."""
+        job = ctx.submit(x, y, z, params, workspace=ws, stream=stream)
+        job.wait()
+        res = job.result()
+        lo = [float(v) for v in res.bbox_min]
+        side = float(res.cube_size)
+        eye = (lo[0] - 0.5 * side, lo[1] - 0.5 * side, lo[2] + 1.5 * side)
+        tgt = tuple(lo[a] + 0.5 * side for a in range(3))
+        f = [tgt[a] - eye[a] for a in range(3)]
+        fl = sum(v * v for v in f) ** 0.5
+        f = [v / fl for v in f]
+        up = (0.0, 0.0, 1.0)
+        r = [f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]]
+        rl = sum(v * v for v in r) ** 0.5
+        r = [v / rl for v in r]
+        u = [r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]]
+        th = 0.5773502691896257   # tan(30 degrees)
+        tw = th * 16 / 9
+        planes = []
+        for nrm, pt in (([tw * f[a] + r[a] for a in range(3)], eye), ([tw * f[a] - r[a] for a in range(3)], eye),
+                        ([th * f[a] + u[a] for a in range(3)], eye), ([th * f[a] - u[a] for a in range(3)], eye),
+                        (f, eye), ([-v for v in f], [eye[a] + 10 * side * f[a] for a in range(3)])):
+            planes.append((*nrm, -sum(nrm[a] * pt[a] for a in range(3))))
+        view = fpo.make_view(eye, planes, 1080.0 / (2 * th), 100.0)
+        sel = ctx.select_nodes(res.node_depth, res.node_key, res.node_count, res.bbox_min, res.cube_size, view)
+        t = time.perf_counter()
+        for _ in range(reps):
+            sel = ctx.select_nodes(res.node_depth, res.node_key, res.node_count, res.bbox_min, res.cube_size, view)
+        ms_s = (time.perf_counter() - t) * 1000.0 / reps
+        out = {"what": "drawn nodes of one perspective view (frustum + 100-pixel refinement)", "ms": ms_s,
+               "nodes": res.num_nodes, "drawn_nodes": int(sel[0].shape[0]), "drawn_points": int(sel[1])}
+        job.release()
+        return out
+
+    select_stats = bench_select()
     # kernel timers: HIP events around the timed kernels, on the build's stream
     ctx.set_timing(True)
     timers = {k: [0.0, 0] for k in KERNEL_BYTES}
@@ -454,6 +494,7 @@ def main():
         "node_ordered_points": gather_stats,
         "preview_variants": preview_stats,
         "las_decode": las_stats,
+        "node_selection": select_stats,
     }
     if not args.no_mix:
         del ws

@@ -373,6 +373,51 @@ fpo_status fpo_las_header_box(const fpo_las_header *h, const double origin[3], f
 fpo_status fpo_las_decode(fpo_context *ctx, const fpo_las_header *h, const void *records, uint64_t n,
                           const double origin[3], float *x, float *y, float *z, uint16_t *rgb, void *hip_stream);
 
+/* ---- view-dependent node selection -----------------------------------------------
+ * Section "Octree Rendering": a traversal thread walks the octree with the
+ * camera's position and frustum, checks every node's visibility and queues the
+ * nodes to draw.  Here one data-parallel pass decides every node at once.
+ * Readings (all IEEE double, one rounding per operation, no fused
+ * multiply-add; m = the cloud's box minimum and side its cube side, both
+ * float32 values taken as doubles):
+ *   - a node at depth d with cell c (its key de-interleaved, x the most
+ *     significant bit of each triple) spans m + c*s .. m + (c+1)*s per axis,
+ *     s = side / 2^d; centre m + (2c+1)*(s/2); radius (s/2) * 1.7320508075688772;
+ *   - a plane (a, b, c, e) keeps a*x + b*y + c*z + e >= 0; a node is visible
+ *     unless for some plane ((a*px + b*py) + c*pz) + e < 0 at its corner
+ *     farthest along the normal (hi where a component is >= 0, else lo);
+ *   - its size on screen is proj_factor * (radius / dist) pixels, dist =
+ *     sqrt((dx*dx + dy*dy) + dz*dz) from the eye to the centre, and infinite
+ *     when dist <= radius;
+ *   - a node is drawn iff it and all its ancestors are visible and every
+ *     ancestor's size is >= min_size (a node is refined into its children when
+ *     it covers at least min_size pixels); this is the top-down traversal's
+ *     result.  Nodes deeper than 21 are never drawn. */
+typedef struct {
+    double eye[3];          /* camera position */
+    double planes[6][4];    /* frustum planes (a, b, c, e) */
+    double proj_factor;     /* viewport height / (2 tan(fov_y / 2)), > 0 */
+    double min_size;        /* pixels, >= 0 (+inf: draw visible roots only) */
+} fpo_view;
+
+/* Device scratch bytes of fpo_select_nodes for num_nodes nodes. */
+fpo_status fpo_select_workspace_size(uint64_t num_nodes, uint64_t *bytes);
+
+/* Enqueues the selection of the nodes of one view on hip_stream (NULL = the
+ * context's stream).  node_depth, node_key, node_count: device arrays of a
+ * node table (fpo_result's, or one read from a file and copied back);
+ * bbox_min, cube_size: its cloud's box minimum and cube side.  Writes the
+ * drawn nodes' indices, ascending, to out_nodes (device, num_nodes entries
+ * at most) and out_totals[0] = their number, out_totals[1] = their points
+ * (device uint32[2]).  workspace: device, fpo_select_workspace_size bytes,
+ * 256-byte aligned; calls that share a workspace must not overlap.
+ * FPO_ERR_INVALID_ARG for NULL arrays, a too small workspace, num_nodes >
+ * 2^32 - 1, or non-finite view values (min_size may be +inf). */
+fpo_status fpo_select_nodes(fpo_context *ctx, uint64_t num_nodes, const uint8_t *node_depth, const uint64_t *node_key,
+                            const uint32_t *node_count, const float bbox_min[3], float cube_size,
+                            const fpo_view *view, void *workspace, uint64_t workspace_bytes, uint32_t *out_nodes,
+                            uint32_t *out_totals, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

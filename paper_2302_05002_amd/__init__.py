@@ -32,7 +32,8 @@ EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_w
            "fpo_job_write_file", "fpo_job_export_bytes", "fpo_job_copy_to_host",
            "fpo_job_timestamps", "fpo_batch_workspace_size", "fpo_build_batch", "fpo_server_create",
            "fpo_server_submit", "fpo_job_cancel", "fpo_server_destroy", "fpo_context_set_timing", "fpo_job_timer",
-           "fpo_preview_modulus", "fpo_las_parse_header", "fpo_las_header_box", "fpo_las_decode")
+           "fpo_preview_modulus", "fpo_las_parse_header", "fpo_las_header_box", "fpo_las_decode",
+           "fpo_select_workspace_size", "fpo_select_nodes")
 
 # fpo_timer values (include/fpo.h)
 TIMERS = {"bbox": 0, "quantize": 1, "chunk_scatter": 2, "subsample": 3, "node_ids": 4, "node_points": 5, "preview": 6}
@@ -52,6 +53,27 @@ class _Params(ctypes.Structure):
 
 
 FPO_DEVICE, FPO_HOST_PINNED = 0, 1
+
+
+class _View(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_double * 3), ("planes", (ctypes.c_double * 4) * 6),
+                ("proj_factor", ctypes.c_double), ("min_size", ctypes.c_double)]
+
+
+def make_view(eye, planes, proj_factor: float, min_size: float) -> _View:
+    """An fpo_view: camera position, six planes (a, b, c, e) keeping
+    a*x + b*y + c*z + e >= 0, pixels per unit of radius / distance, and the
+    size in pixels above which a node is refined."""
+    v = _View()
+    for a in range(3):
+        v.eye[a] = eye[a]
+    assert len(planes) == 6
+    for p, q in enumerate(planes):
+        for k in range(4):
+            v.planes[p][k] = q[k]
+    v.proj_factor = proj_factor
+    v.min_size = min_size
+    return v
 
 
 class _LasHeader(ctypes.Structure):
@@ -107,6 +129,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_las_header_box.restype = ctypes.c_int
     lib.fpo_las_decode.argtypes = [vp, P(_LasHeader), vp, ctypes.c_uint64, P(ctypes.c_double), vp, vp, vp, vp, vp]
     lib.fpo_las_decode.restype = ctypes.c_int
+    lib.fpo_select_workspace_size.argtypes = [ctypes.c_uint64, P(ctypes.c_uint64)]
+    lib.fpo_select_workspace_size.restype = ctypes.c_int
+    lib.fpo_select_nodes.argtypes = [vp, ctypes.c_uint64, vp, vp, vp, P(ctypes.c_float), ctypes.c_float, P(_View),
+                                     vp, ctypes.c_uint64, vp, vp, vp]
+    lib.fpo_select_nodes.restype = ctypes.c_int
     lib.fpo_preview_modulus.argtypes = [ctypes.c_uint64, ctypes.c_uint64, P(ctypes.c_uint32)]
     lib.fpo_preview_modulus.restype = ctypes.c_int
     lib.fpo_workspace_size_cloud.argtypes = [P(_Cloud), P(_Params), P(ctypes.c_uint64)]
@@ -311,6 +338,34 @@ class Context:
         if back is not None:
             back.wait_stream(stream)
         return x, y, z, col
+
+    def select_nodes(self, node_depth, node_key, node_count, bbox_min, cube_size, view: _View, workspace=None,
+                     stream=None):
+        """Drawn nodes of one view (fpo_select_nodes) from device node arrays
+        (uint8 depth, int64 key, int32 count tensors): (ascending int32 index
+        tensor, number of drawn points).  Synchronises the stream it runs on."""
+        import torch
+        n = int(node_depth.shape[0])
+        assert node_key.shape[0] == n and node_count.shape[0] == n
+        dev = node_depth.device if n else torch.device("cuda", self.device)
+        need = ctypes.c_uint64()
+        _check(_lib.fpo_select_workspace_size(n, ctypes.byref(need)))
+        if workspace is None:
+            workspace = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        totals = torch.zeros(2, dtype=torch.int32, device=dev)
+        stream, back = _ordered_stream(dev, stream)
+        lo = (ctypes.c_float * 3)(*[float(v) for v in bbox_min])
+        ptr = (lambda t: ctypes.c_void_p(t.data_ptr() if n else 0))
+        _check(_lib.fpo_select_nodes(self._h, n, ptr(node_depth), ptr(node_key), ptr(node_count), lo,
+                                     float(cube_size), ctypes.byref(view), ctypes.c_void_p(workspace.data_ptr()),
+                                     workspace.numel(), ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(totals.data_ptr()), ctypes.c_void_p(stream.cuda_stream)))
+        if back is not None:
+            back.wait_stream(stream)
+        stream.synchronize()
+        t = totals.cpu().tolist()
+        return out[:t[0]], t[1]
 
     def build(self, x, y, z, params: Params, workspace=None, stream=None) -> "Result":
         job = self.submit(x, y, z, params, workspace, stream)

@@ -70,3 +70,15 @@ def test_decode_argument_errors(fpo):
     buf = ctypes.create_string_buffer(64)
     # no context
     assert lib.fpo_las_decode(None, ctypes.byref(h), buf, 1, o, buf, buf, buf, None, None) == fpo.FPO_ERR_INVALID_ARG
+
+
+def test_select_argument_errors(fpo):
+    lib = fpo.load_library()
+    out = ctypes.c_uint64()
+    assert lib.fpo_select_workspace_size(1000, ctypes.byref(out)) == fpo.FPO_OK and out.value > 0
+    assert lib.fpo_select_workspace_size(1 << 33, ctypes.byref(out)) == fpo.FPO_ERR_INVALID_ARG
+    v = fpo.make_view((0, 0, 0), ((0, 0, 0, 1),) * 6, 1.0, 0.0)
+    lo = (ctypes.c_float * 3)(0, 0, 0)
+    # no context
+    assert lib.fpo_select_nodes(None, 0, None, None, None, lo, 1.0, ctypes.byref(v), None, 0, None, None,
+                                None) == fpo.FPO_ERR_INVALID_ARG
