@@ -281,6 +281,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="CPU work budget of the oracle baseline")
     ap.add_argument("--no-mix", action="store_true", help="skip the batched and served comparisons")
     ap.add_argument("--no-stream", action="store_true", help="skip the streamed 200M-point build")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the LAS decode, preview variant, gather and node selection legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
@@ -397,13 +399,16 @@ def main():
                 "points_per_s": n / (ms_d / 1000.0), "GBps": b / (ms_d / 1000.0) / 1e9,
                 "hbm_frac": b / (ms_d / 1000.0) / 1e9 / HBM_PEAK_GBS}
 
-    las_stats = bench_las_decode()
-    print(f"[bench] LAS decode {las_stats['ms']:.3f} ms, {las_stats['hbm_frac']:.2f} of HBM peak",
-          file=sys.stderr, flush=True)
-    preview_stats = bench_preview_variants()
-    print(f"[bench] preview variants: " + ", ".join(f"{k} {v['preview_ms']:.3f} ms ({v['picks']} picks)"
-                                                    for k, v in preview_stats.items()), file=sys.stderr, flush=True)
-    gather_stats = bench_gather()
+    extras = {}
+    if not args.no_extras:
+        extras["las_decode"] = las_stats = bench_las_decode()
+        print(f"[bench] LAS decode {las_stats['ms']:.3f} ms, {las_stats['hbm_frac']:.2f} of HBM peak",
+              file=sys.stderr, flush=True)
+        extras["preview_variants"] = preview_stats = bench_preview_variants()
+        print(f"[bench] preview variants: " + ", ".join(f"{k} {v['preview_ms']:.3f} ms ({v['picks']} picks)"
+                                                        for k, v in preview_stats.items()),
+              file=sys.stderr, flush=True)
+        extras["node_ordered_points"] = bench_gather()
 
     def bench_select(reps: int = 20) -> dict:
         """Node selection for one perspective view of the built tree (eye outside
@@ -443,7 +448,8 @@ def main():
         job.release()
         return out
 
-    select_stats = bench_select()
+    if not args.no_extras:
+        extras["node_selection"] = bench_select()
     # kernel timers: HIP events around the timed kernels, on the build's stream
     ctx.set_timing(True)
     timers = {k: [0.0, 0] for k in KERNEL_BYTES}
@@ -491,10 +497,7 @@ def main():
                    "preview_modulus": p.preview_modulus, "parallelism": "single GPU"},
         "path_hbm_frac": b_alg / (ms / 1000.0) / (HBM_PEAK_GBS * 1e9),
         "roofline": roofline,
-        "node_ordered_points": gather_stats,
-        "preview_variants": preview_stats,
-        "las_decode": las_stats,
-        "node_selection": select_stats,
+        **extras,
     }
     if not args.no_mix:
         del ws
