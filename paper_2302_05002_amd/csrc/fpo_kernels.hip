@@ -2327,11 +2327,15 @@ void launch_subsample_small(const WcArgs &a, hipStream_t st)
     hipLaunchKernelGGL(k_list_classes, dim3(grid_for(a.num_wc, 256)), dim3(256), 0, st, a);
     const uint32_t gs = a.num_wc < 8192 ? a.num_wc : 8192;
     // work chunks whose own root is a leaf: shared ancestors only
+    // (few points per thread: a work chunk's depths run one after another, so
+    // its latency bounds these kernels.  Measured on the 20M-point planes:
+    // four points per thread up to 2048 points, eight above, where LDS
+    // limits the blocks per CU)
     hipLaunchKernelGGL((k_subsample_fast<64, 4, 10>), dim3(gs), dim3(64), 0, st, a, 0);
-    hipLaunchKernelGGL((k_subsample_fast<64, 8, 11>), dim3(gs), dim3(64), 0, st, a, 1);
-    hipLaunchKernelGGL((k_subsample_fast<64, 16, 12>), dim3(gs), dim3(64), 0, st, a, 2);
-    hipLaunchKernelGGL((k_subsample_fast<128, 16, 13>), dim3(gs), dim3(128), 0, st, a, 3);
-    hipLaunchKernelGGL((k_subsample_fast<256, 16, 13>), dim3(gs), dim3(256), 0, st, a, 4);
+    hipLaunchKernelGGL((k_subsample_fast<128, 4, 11>), dim3(gs), dim3(128), 0, st, a, 1);
+    hipLaunchKernelGGL((k_subsample_fast<256, 4, 12>), dim3(gs), dim3(256), 0, st, a, 2);
+    hipLaunchKernelGGL((k_subsample_fast<512, 4, 13>), dim3(gs), dim3(512), 0, st, a, 3);
+    hipLaunchKernelGGL((k_subsample_fast<512, 8, 13>), dim3(gs), dim3(512), 0, st, a, 4);
     // oversized work chunks at the deepest work-chunk level (dense clusters)
     hipLaunchKernelGGL((k_subsample_fast<1024, 8, 14>), dim3(gs < 2048 ? gs : 2048), dim3(1024), 0, st, a, 5);
     // the general subtree: single-wave blocks for the small classes, many per CU
