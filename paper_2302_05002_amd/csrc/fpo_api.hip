@@ -76,6 +76,7 @@ struct Ctrs {
     uint32_t wc_flags[2];      // [0] a work chunk spans several chunks, [1] a chunk holds too many
     uint32_t cls_cnt[WC_CLASSES];   // work chunks per LDS size class
 };
+static_assert(sizeof(Ctrs) <= 256, "the box follows the counters 256 bytes later");
 
 // Byte offsets of every region of the workspace for (n, params).
 struct Plan {
@@ -119,11 +120,13 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     };
     // pinned host inputs: device staging of x, y, z (a256-aligned thirds)
     P.xyz = host_in ? take(3 * a256(4 * nn)) : 0;
+    // counters, then the box 256 bytes later: the host reads both with one
+    // copy into the same layout of its pinned staging
+    P.ctrs = take(sizeof(Ctrs));
     P.box = take(sizeof(DevBox));
     // bounding-box partials: at most one per 1024 points per batch, plus one
     // per batch (batches of at least MIN_STREAM_BATCH points)
     P.bbox_part = take(8 * 4 * (nn / 1024 + nn / MIN_STREAM_BATCH + 1 + BBOX_MAX_BLOCKS));
-    P.ctrs = take(sizeof(Ctrs));
     P.grid = take(4 * P.G3);
     P.c_level = take(P.maxC);
     P.c_key = take(8 * P.maxC);
@@ -646,8 +649,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     launch_wc_chunks(&ctrs->num_wc, P.maxW, U64(P.w_key), U8(P.w_level), g, pyr, U32(P.ec), U8(P.c_level),
                      &ctrs->num_chunks, P.maxC, U32(P.wc_chunk), U32(P.seg_b0), U32(P.seg_nb), U8(P.wc_nested),
                      ctrs->wc_flags, st);
-    JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
-    JCHK(hipMemcpyAsync(hbox, box, sizeof(DevBox), hipMemcpyDeviceToHost, st));
+    JCHK(hipMemcpyAsync(hctrs, ctrs, 256 + sizeof(DevBox), hipMemcpyDeviceToHost, st));   // counters and box
     JCHK(hipStreamSynchronize(st));
     if (hbox->nonfinite) {
         return end_job(fail(FPO_ERR_NONFINITE, "a coordinate is NaN or infinite"));
@@ -767,8 +769,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     }
     launch_node_ranges(U32(P.sorted_nid), n, U64(P.n_begin), U32(P.n_count), num_nodes, st);
 
-    JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
-    JCHK(hipMemcpyAsync(hbox, box, sizeof(DevBox), hipMemcpyDeviceToHost, st));
+    JCHK(hipMemcpyAsync(hctrs, ctrs, 256 + sizeof(DevBox), hipMemcpyDeviceToHost, st));   // counters and box
     JCHK(hipEventRecord(job->ev_done, st));
     JCHK(hipGetLastError());
     R.num_chunks = num_chunks;

@@ -474,6 +474,22 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
 
 // ---- step 2a: count pyramid ---------------------------------------------------------
 // Level l-1 cell k = sum of level-l cells 8k..8k+7 (Morton order).
+// The top levels (at most 4096 cells at level `top`) in one block: one launch
+// instead of one per level.
+__global__ __launch_bounds__(1024) void k_pyr_top(uint32_t *pyr, int top)
+{
+    for (int l = top; l >= 1; --l) {
+        const uint32_t ncell = 1u << (3 * (l - 1));
+        const uint32_t *src = pyr + pyr_off(l);
+        uint32_t *dst = pyr + pyr_off(l - 1);
+        for (uint32_t k = threadIdx.x; k < ncell; k += blockDim.x) {
+            const uint32_t *c = src + 8 * k;
+            dst[k] = c[0] + c[1] + c[2] + c[3] + c[4] + c[5] + c[6] + c[7];
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_pyr_level(uint32_t *pyr, int l)
 {
     const uint64_t ncell = 1ull << (3 * (l - 1));
@@ -586,11 +602,27 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *tile_sum, uint32_t 
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
+// With TOP, tile_off holds the raw tile sums and every block adds up those
+// before its own (at most SCAN_FUSED_TILES of them, read from L2), and the
+// last block writes the total: the separate top pass is not launched.
+constexpr uint32_t SCAN_FUSED_TILES = 4096;
+
+template <bool TOP>
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(const uint32_t *in, uint32_t *out, uint64_t n,
-                                                          const uint32_t *n_dev, const uint32_t *tile_off)
+                                                          const uint32_t *n_dev, const uint32_t *tile_off,
+                                                          uint32_t *total)
 {
     __shared__ uint32_t lds[SCAN_BLOCK / 64 + 1];
     __shared__ uint32_t buf[SCAN_TILE];
+    uint32_t prior = 0;
+    if constexpr (TOP) {
+        uint32_t v = 0;
+        for (uint32_t t = threadIdx.x; t < blockIdx.x; t += SCAN_BLOCK) v += tile_off[t];
+        prior = block_sum<SCAN_BLOCK>(v, lds);
+        if (blockIdx.x == gridDim.x - 1 && total && threadIdx.x == 0) *total = prior + tile_off[blockIdx.x];
+    } else {
+        prior = tile_off[blockIdx.x];
+    }
     if (n_dev && *n_dev < n) n = *n_dev;
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
     if (base >= n) return;
@@ -607,7 +639,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(const uint32_t *in, ui
         s += v[j];
     }
     uint32_t t;
-    uint32_t run = block_excl_scan<SCAN_BLOCK>(s, lds, &t) + tile_off[blockIdx.x];
+    uint32_t run = block_excl_scan<SCAN_BLOCK>(s, lds, &t) + prior;
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; ++j) {
         buf[threadIdx.x * SCAN_ITEMS + j] = run;
@@ -669,8 +701,12 @@ void scan_exclusive(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tot
     const uint32_t tiles = div_up(n, SCAN_TILE);
     uint32_t *ts = static_cast<uint32_t *>(temp);
     hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, n, nullptr, ts);
+    if (tiles <= SCAN_FUSED_TILES) {
+        hipLaunchKernelGGL(k_scan_down<true>, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, out, n, nullptr, ts, total);
+        return;
+    }
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, ts, tiles, total);
-    hipLaunchKernelGGL(k_scan_down, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, out, n, nullptr, ts);
+    hipLaunchKernelGGL(k_scan_down<false>, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, out, n, nullptr, ts, nullptr);
 }
 
 void scan_exclusive_dev(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t n_max, void *temp,
@@ -684,8 +720,13 @@ void scan_exclusive_dev(const uint32_t *in, uint32_t *out, const uint32_t *n_dev
     const uint32_t tiles = div_up(n_max, SCAN_TILE);
     uint32_t *ts = static_cast<uint32_t *>(temp);
     hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, n_max, n_dev, ts);
+    if (tiles <= SCAN_FUSED_TILES) {
+        hipLaunchKernelGGL(k_scan_down<true>, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, out, n_max, n_dev, ts,
+                           nullptr);
+        return;
+    }
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, ts, tiles, nullptr);
-    hipLaunchKernelGGL(k_scan_down, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, out, n_max, n_dev, ts);
+    hipLaunchKernelGGL(k_scan_down<false>, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, out, n_max, n_dev, ts, nullptr);
 }
 
 __global__ void k_cell_ids(const uint32_t *flags, uint32_t *ids, uint64_t ncell)
@@ -2269,10 +2310,13 @@ void launch_quantize(const float *x, const float *y, const float *z, uint64_t n,
 
 void launch_pyramid(uint32_t *pyr, int g, hipStream_t st)
 {
-    for (int l = g; l >= 1; --l) {
+    // levels above 4 one launch each, the rest (level 4 = 4096 cells and up) in one block
+    int l = g;
+    for (; l >= 1 && l > 4; --l) {
         const uint64_t ncell = 1ull << (3 * (l - 1));
         hipLaunchKernelGGL(k_pyr_level, dim3(grid_for(ncell, 256)), dim3(256), 0, st, pyr, l);
     }
+    if (l >= 1) hipLaunchKernelGGL(k_pyr_top, dim3(1), dim3(1024), 0, st, pyr, l);
 }
 
 void launch_grid_export(const uint32_t *fine, int g, uint32_t *out, hipStream_t st)
@@ -2338,7 +2382,10 @@ void launch_subsample_small(const WcArgs &a, hipStream_t st)
     hipLaunchKernelGGL((k_subsample_fast<512, 8, 13>), dim3(gs), dim3(512), 0, st, a, 4);
     // oversized work chunks at the deepest work-chunk level (dense clusters)
     hipLaunchKernelGGL((k_subsample_fast<1024, 8, 14>), dim3(gs < 2048 ? gs : 2048), dim3(1024), 0, st, a, 5);
-    // the general subtree: single-wave blocks for the small classes, many per CU
+    // the general subtree: single-wave blocks for the small classes, many per
+    // CU.  Only work chunks with more than L points or subsample grids above
+    // 2^7 go there, so with L >= WC_CAP and s <= 7 these classes stay empty
+    if (a.L >= WC_CAP && a.s <= 7) return;
     hipLaunchKernelGGL((k_subsample_lds<64, 4>), dim3(gs), dim3(64), 0, st, a, WC_GENERAL + 0);
     hipLaunchKernelGGL((k_subsample_lds<64, 8>), dim3(gs), dim3(64), 0, st, a, WC_GENERAL + 1);
     hipLaunchKernelGGL((k_subsample_lds<64, 16>), dim3(gs), dim3(64), 0, st, a, WC_GENERAL + 2);
