@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ x, const
 __global__ __launch_bounds__(256) void k_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given, float gx0,
                                                float gy0, float gz0, float gx1, float gy1, float gz1, int flag_only)
 {
-    __shared__ uint32_t red[7][256];
+    __shared__ uint32_t red[7][4];
     uint32_t v[7] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u, 0u};
     for (uint32_t b = threadIdx.x; b < nparts; b += 256) {
         for (int a = 0; a < 3; ++a) {
@@ -237,10 +237,20 @@ __global__ __launch_bounds__(256) void k_setup(DevBox *box, const uint32_t *part
         }
         v[6] |= part[(uint64_t)b * 8 + 6];
     }
-    for (int a = 0; a < 7; ++a) red[a][threadIdx.x] = v[a];
+    // wave reductions, then the four wave results
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        for (int a = 0; a < 3; ++a) {
+            v[a] = min(v[a], (uint32_t)__shfl_xor(v[a], o, 64));
+            v[3 + a] = max(v[3 + a], (uint32_t)__shfl_xor(v[3 + a], o, 64));
+        }
+        v[6] |= (uint32_t)__shfl_xor(v[6], o, 64);
+    }
+    if (lane_id() == 0)
+        for (int a = 0; a < 7; ++a) red[a][threadIdx.x >> 6] = v[a];
     __syncthreads();
     if (threadIdx.x != 0) return;
-    for (uint32_t t = 1; t < 256; ++t) {
+    for (uint32_t t = 1; t < 4; ++t) {
         for (int a = 0; a < 3; ++a) {
             v[a] = min(v[a], red[a][t]);
             v[3 + a] = max(v[3 + a], red[3 + a][t]);
@@ -1826,11 +1836,17 @@ __global__ __launch_bounds__(BLOCK) void k_subsample_fast(WcArgs a, int cls)
     }
 }
 
-__global__ void k_list_classes(WcArgs a)
+// One pass over the work chunks in blocks of 256: each wave counts its work
+// chunks per class with ballots into the block's LDS counters, one global
+// atomic per block and class reserves the block's run, then the waves write.
+__global__ __launch_bounds__(256) void k_list_classes(WcArgs a)
 {
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t w0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); w0 < a.num_wc; w0 += stride) {
-        const uint32_t w = w0 + lane_id();
+    constexpr uint32_t NC = WC_CLASSES + 1;   // the last one: the global-memory list
+    __shared__ uint32_t bcnt[NC], bbase[NC];
+    for (uint32_t b0 = blockIdx.x * 256u; b0 < a.num_wc; b0 += gridDim.x * 256u) {
+        if (threadIdx.x < NC) bcnt[threadIdx.x] = 0;
+        __syncthreads();
+        const uint32_t w = b0 + threadIdx.x;
         const bool valid = w < a.num_wc;
         uint32_t c = 0xfeu;
         if (valid) {
@@ -1839,21 +1855,28 @@ __global__ void k_list_classes(WcArgs a)
             if (!a.wc_nested[w]) c = 0xffu;
             else if (c != 0xffu && !(n <= a.L && a.s <= 7)) c = c < 5 ? c + WC_GENERAL : 0xffu;
         }
-        for (uint32_t k = 0; k <= (uint32_t)WC_CLASSES; ++k) {
-            const uint32_t kc = k == (uint32_t)WC_CLASSES ? 0xffu : k;
-            const uint64_t m = __ballot(c == kc);
+        const uint32_t ci = c == 0xffu ? (uint32_t)WC_CLASSES : c;   // counter index (0xfe: none)
+        uint32_t rank = 0;
+        for (uint32_t k = 0; k < NC; ++k) {
+            const uint64_t m = __ballot(ci == k);
             if (!m) continue;
-            uint32_t base = 0;
             const int leader = __ffsll((long long)m) - 1;
-            if (lane_id() == leader)
-                base = atomicAdd(kc == 0xffu ? a.num_big_dev : &a.cls_cnt[kc], (uint32_t)__popcll(m));
-            base = __shfl(base, leader, 64);
-            if (c == kc) {
-                const uint32_t r = base + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
-                if (kc == 0xffu) a.big_list[r] = w;
-                else a.cls_list[(uint64_t)kc * a.num_wc + r] = w;
-            }
+            uint32_t wb = 0;
+            if ((int)lane_id() == leader) wb = atomicAdd(&bcnt[k], (uint32_t)__popcll(m));
+            wb = __shfl(wb, leader, 64);
+            if (ci == k) rank = wb + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
         }
+        __syncthreads();
+        if (threadIdx.x < NC && bcnt[threadIdx.x])
+            bbase[threadIdx.x] = atomicAdd(threadIdx.x == (uint32_t)WC_CLASSES ? a.num_big_dev : &a.cls_cnt[threadIdx.x],
+                                           bcnt[threadIdx.x]);
+        __syncthreads();
+        if (ci < NC) {
+            const uint32_t r = bbase[ci] + rank;
+            if (ci == (uint32_t)WC_CLASSES) a.big_list[r] = w;
+            else a.cls_list[(uint64_t)ci * a.num_wc + r] = w;
+        }
+        __syncthreads();
     }
 }
 
