@@ -164,3 +164,33 @@ def test_server_cancel(ctx):
         j.release()
     jobs[3].release()
     srv.close()
+
+
+def test_batch_and_server_with_preview_variants(ctx):
+    """Preview variants inside batches and served requests: the grid variant
+    adds its per-cell minima to a build's workspace, which the batch
+    workspace and the server's arena account for."""
+    import paper_2302_05002_amd as fpo
+    modes = ["grid", "stride", "hash", "grid", "grid", "stride", "hash", "grid"]
+    clouds = [make(k, n, s) for (k, n, s, *_rest) in MIX]
+    dev = [device_cloud(c) for c in clouds]
+    params = [fpo.Params(G, C, S, L, M, None, mode) for (_, _, _, G, C, S, L, M), mode in zip(MIX, modes)]
+    exp = []
+    for c, (_, _, _, G, C, S, L, M), mode in zip(clouds, MIX, modes):
+        r = oracle.build_octree(c.x, c.y, c.z, oracle.Params(G, C, S, L, M, None, mode))
+        assert r["status"] == oracle.OK
+        exp.append(r)
+    print(f"[batch] {len(dev)} clouds with preview variants", flush=True)
+    jobs = ctx.build_batch(dev, params)
+    for j, e, case in zip(jobs, exp, MIX):
+        j.wait()
+        compare(j.result().to_numpy(), e, label=f"batch variants {case}: ")
+        j.release()
+    srv = fpo.Server(ctx, hbm_budget_bytes=6 << 30, max_slots=3)   # G=512 with grid minima: 4.7 GB
+    print(f"[server] {len(dev)} requests with preview variants", flush=True)
+    jobs = [srv.submit(*d, p) for d, p in zip(dev, params)]
+    for j, e, case in zip(jobs, exp, MIX):
+        j.wait()
+        compare(j.to_numpy(), e, label=f"served variants {case}: ")
+        j.release()
+    srv.close()
