@@ -1671,13 +1671,16 @@ __device__ __forceinline__ uint32_t wc_size_class(uint32_t n)
 //  - while the cell key fits the table it is the slot, and the entry is
 //    (31 - d) << 12 (13) | position, so entries of shallower depths are replaced
 //    by the same atomicMin (no clearing per depth);
-//  - longer keys are hashed without probing: every point writes its
-//    position into slot h_r(cell), reads back the winning position and that
-//    position's key; points whose cell owns the slot are decided, the cells
-//    that collided try again with the next multiplier.  With at most a
-//    quarter of the slots used, few cells collide per round, and a round
-//    costs two dependent LDS reads, where linear probing costs as many load
-//    and CAS round trips as the longest probe chain of the block.
+//  - longer keys are hashed without probing: every point writes its cell key
+//    and position, key << 12 (13) | position, into slot h_r(cell) with an
+//    atomicMin, and reads the slot back: the smallest key among the cells
+//    that met there owns the slot, and its entry holds the lowest position of
+//    that cell; points whose cell owns the slot are decided, the cells that
+//    collided try again with the next multiplier.  (Keys have at most 18
+//    bits, positions 13.)  With at most a quarter of the slots used, few
+//    cells collide per round, and a round costs one LDS read, where linear
+//    probing costs as many load and CAS round trips as the longest probe
+//    chain of the block.
 // LDS operations of all items are issued together and waited for once.
 __constant__ uint32_t kFastMul[8] = {0x9E3779B1u, 0x85EBCA77u, 0xC2B2AE3Du, 0x27D4EB2Fu,
                                      0x165667B1u, 0xD3A2646Du, 0xFD7046C5u, 0xB55A4F09u};
@@ -1690,12 +1693,11 @@ __global__ __launch_bounds__(BLOCK) void k_subsample_fast(WcArgs a, int cls)
     constexpr int NW = BLOCK / 64;
     constexpr uint32_t ALIVE = 0xffu << 24;
     constexpr uint32_t EMPTY = 0xffffffffu;
-    constexpr int PB = CAP <= 4096 ? 12 : 13;   // position bits of a direct-mode entry
+    constexpr int PB = CAP <= 4096 ? 12 : 13;   // position bits of a table entry
     static_assert(CAP <= 8192, "positions are packed in 13 bits");
     static_assert(TSZ >= 2 * CAP, "table of at least two slots per point");
     __shared__ uint4 table4[TSZ / 4];
     uint32_t *table = reinterpret_cast<uint32_t *>(table4);
-    __shared__ uint32_t keyat[CAP];
     __shared__ uint32_t wsum[2][NW];
     __shared__ uint32_t alive_at[MAXD];
     const uint32_t cnt = a.cls_cnt[cls];
@@ -1731,8 +1733,6 @@ __global__ __launch_bounds__(BLOCK) void k_subsample_fast(WcArgs a, int cls)
             it[j] = pos < n ? ((uint32_t)(c >> ksh) & kmask) | (st << 24) : 0u;
         }
         if (threadIdx.x < (uint32_t)MAXD) alive_at[threadIdx.x] = 0;
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) keyat[j * BLOCK + threadIdx.x] = it[j] & 0xffffffu;
         for (uint32_t h = threadIdx.x; h < TSZ / 4; h += BLOCK) table4[h] = make_uint4(EMPTY, EMPTY, EMPTY, EMPTY);
         uint32_t alive0 = 0;
 #pragma unroll
@@ -1780,21 +1780,20 @@ __global__ __launch_bounds__(BLOCK) void k_subsample_fast(WcArgs a, int cls)
                     uint32_t slot[ITEMS];
 #pragma unroll
                     for (int j = 0; j < ITEMS; ++j) {
-                        slot[j] = (((it[j] & 0xffffffu) >> sh) * mul) >> (32 - hb);
-                        if ((pend >> j) & 1u) atomicMin(&table[slot[j]], j * BLOCK + threadIdx.x);
+                        const uint32_t key = (it[j] & 0xffffffu) >> sh;
+                        slot[j] = (key * mul) >> (32 - hb);
+                        if ((pend >> j) & 1u) atomicMin(&table[slot[j]], (key << PB) | (j * BLOCK + threadIdx.x));
                     }
                     __syncthreads();
-                    uint32_t cur[ITEMS], ck[ITEMS];
+                    uint32_t cur[ITEMS];
 #pragma unroll
-                    for (int j = 0; j < ITEMS; ++j) cur[j] = table[slot[j]] & (CAP - 1);
-#pragma unroll
-                    for (int j = 0; j < ITEMS; ++j) ck[j] = keyat[cur[j]];
+                    for (int j = 0; j < ITEMS; ++j) cur[j] = table[slot[j]];
 #pragma unroll
                     for (int j = 0; j < ITEMS; ++j) {
                         if (!((pend >> j) & 1u)) continue;
-                        if ((ck[j] >> sh) == ((it[j] & 0xffffffu) >> sh)) {   // the slot is this cell's
+                        if ((cur[j] >> PB) == ((it[j] & 0xffffffu) >> sh)) {   // the slot is this cell's
                             pend &= ~(1u << j);
-                            if (cur[j] == j * BLOCK + threadIdx.x) won |= 1u << j;
+                            if ((cur[j] & ((1u << PB) - 1u)) == j * BLOCK + threadIdx.x) won |= 1u << j;
                         }
                     }
                     clean = false;
