@@ -399,8 +399,53 @@ def main():
                 "points_per_s": n / (ms_d / 1000.0), "GBps": b / (ms_d / 1000.0) / 1e9,
                 "hbm_frac": b / (ms_d / 1000.0) / 1e9 / HBM_PEAK_GBS}
 
+    def bench_copy(reps: int = 20) -> dict:
+        """A plain device-to-device copy of 1 GiB (read + write), the practical
+        HBM ceiling the kernels are compared against."""
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms_c = e0.elapsed_time(e1) / reps
+        del src, dst
+        gbs = 2 * (1 << 30) / (ms_c / 1000.0) / 1e9
+        return {"what": "torch copy of 1 GiB on the device (2 GiB moved)", "ms": ms_c, "GBps": gbs,
+                "frac_of_peak": gbs / HBM_PEAK_GBS}
+
+    def bench_atomics(reps: int = 5) -> dict:
+        """Device atomic throughput, the secondary ceiling of the histogram and
+        winner passes: int32 scatter-add (global atomics) of 64M updates into
+        a 1M-entry table, uniform random and sorted (neighbouring lanes on
+        neighbouring words) targets."""
+        m = 1 << 26
+        g = torch.Generator(device=dev)
+        g.manual_seed(9)
+        idx = torch.randint(0, 1 << 20, (m,), device=dev, generator=g)
+        one = torch.ones(m, dtype=torch.int32, device=dev)
+        res = {}
+        for name, ix in (("random", idx), ("sorted", torch.sort(idx).values)):
+            tab = torch.zeros(1 << 20, dtype=torch.int32, device=dev)
+            tab.scatter_add_(0, ix, one)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                tab.scatter_add_(0, ix, one)
+            e1.record()
+            e1.synchronize()
+            res[name + "_per_s"] = m * reps / (e0.elapsed_time(e1) / 1000.0)
+        del idx, one
+        res["what"] = "torch scatter_add_ of 64M int32 updates into 1M counters (global atomics)"
+        return res
+
     extras = {}
     if not args.no_extras:
+        extras["hbm_copy"] = bench_copy()
+        extras["atomics"] = bench_atomics()
         extras["las_decode"] = las_stats = bench_las_decode()
         print(f"[bench] LAS decode {las_stats['ms']:.3f} ms, {las_stats['hbm_frac']:.2f} of HBM peak",
               file=sys.stderr, flush=True)
@@ -507,6 +552,10 @@ def main():
         out["served"] = bench_served(fpo, torch, ctx)
         print(f"[bench] served {out['served']['speedup']:.2f}x serial, p99 {out['served']['latency_ms_p99']:.1f} ms",
               file=sys.stderr, flush=True)
+        # the same trace at half the serial capacity: latency without queueing
+        out["served_half_load"] = bench_served(fpo, torch, ctx, load=0.5)
+        print(f"[bench] served at 0.5x load: p50 {out['served_half_load']['latency_ms_p50']:.1f} ms, "
+              f"p99 {out['served_half_load']['latency_ms_p99']:.1f} ms", file=sys.stderr, flush=True)
     if not args.no_stream:
         if not args.no_mix:
             torch.cuda.empty_cache()
