@@ -364,14 +364,16 @@ fpo_status fpo_las_parse_header(const void *bytes, uint64_t len, fpo_las_header 
 fpo_status fpo_las_header_box(const fpo_las_header *h, const double origin[3], float lo[3], float hi[3]);
 
 /* Enqueues the decode of the n records at `records` (device, record_length
- * bytes each, any alignment) on hip_stream (NULL = the context's stream):
+ * bytes each, any alignment, records_bytes >= n * record_length readable
+ * bytes) on hip_stream (NULL = the context's stream):
  * x, y, z (device float32[n]) as above and, if rgb is not NULL, R, G, B
  * (device uint16[3n], interleaved per point; the format must have them).
  * Returns once enqueued; the outputs are ready when the stream reaches the
- * decode.  FPO_ERR_INVALID_ARG for NULL arguments, n > 2^32 - 1, an
- * inconsistent header or a non-finite origin. */
-fpo_status fpo_las_decode(fpo_context *ctx, const fpo_las_header *h, const void *records, uint64_t n,
-                          const double origin[3], float *x, float *y, float *z, uint16_t *rgb, void *hip_stream);
+ * decode.  FPO_ERR_INVALID_ARG for NULL arguments, n > 2^32 - 1, records_bytes
+ * below n * record_length, an inconsistent header or a non-finite origin. */
+fpo_status fpo_las_decode(fpo_context *ctx, const fpo_las_header *h, const void *records, uint64_t records_bytes,
+                          uint64_t n, const double origin[3], float *x, float *y, float *z, uint16_t *rgb,
+                          void *hip_stream);
 
 /* ---- view-dependent node selection -----------------------------------------------
  * Section "Octree Rendering": a traversal thread walks the octree with the

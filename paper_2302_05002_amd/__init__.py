@@ -127,7 +127,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_las_parse_header.restype = ctypes.c_int
     lib.fpo_las_header_box.argtypes = [P(_LasHeader), P(ctypes.c_double), P(ctypes.c_float), P(ctypes.c_float)]
     lib.fpo_las_header_box.restype = ctypes.c_int
-    lib.fpo_las_decode.argtypes = [vp, P(_LasHeader), vp, ctypes.c_uint64, P(ctypes.c_double), vp, vp, vp, vp, vp]
+    lib.fpo_las_decode.argtypes = [vp, P(_LasHeader), vp, ctypes.c_uint64, ctypes.c_uint64, P(ctypes.c_double), vp,
+                                   vp, vp, vp, vp]
     lib.fpo_las_decode.restype = ctypes.c_int
     lib.fpo_select_workspace_size.argtypes = [ctypes.c_uint64, P(ctypes.c_uint64)]
     lib.fpo_select_workspace_size.restype = ctypes.c_int
@@ -324,13 +325,13 @@ class Context:
         assert records.is_cuda and records.dtype == torch.uint8 and records.is_contiguous()
         if n is None:
             n = records.numel() // header.record_length
-        assert n * header.record_length <= records.numel()
         dev = records.device
         x, y, z = (torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3))
         col = torch.empty((n, 3), dtype=torch.int16, device=dev) if rgb else None
         stream, back = _ordered_stream(dev, stream)
         o = (ctypes.c_double * 3)(*origin)
-        _check(_lib.fpo_las_decode(self._h, ctypes.byref(header), ctypes.c_void_p(records.data_ptr()), n, o,
+        _check(_lib.fpo_las_decode(self._h, ctypes.byref(header), ctypes.c_void_p(records.data_ptr()),
+                                   records.numel(), n, o,
                                    ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                    ctypes.c_void_p(z.data_ptr()),
                                    ctypes.c_void_p(col.data_ptr()) if rgb else None,

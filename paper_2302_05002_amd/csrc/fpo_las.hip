@@ -188,14 +188,18 @@ fpo_status fpo_las_header_box(const fpo_las_header *h, const double origin[3], f
     return FPO_OK;
 }
 
-fpo_status fpo_las_decode(fpo_context *ctx, const fpo_las_header *h, const void *records, uint64_t n,
-                          const double origin[3], float *x, float *y, float *z, uint16_t *rgb, void *hip_stream)
+fpo_status fpo_las_decode(fpo_context *ctx, const fpo_las_header *h, const void *records, uint64_t records_bytes,
+                          uint64_t n, const double origin[3], float *x, float *y, float *z, uint16_t *rgb,
+                          void *hip_stream)
 {
     if (!ctx || !origin) return fail(FPO_ERR_INVALID_ARG, "NULL context or origin");
     fpo_status s = check_header(h);
     if (s != FPO_OK) return s;
     if (n > 0xffffffffull) return fail(FPO_ERR_INVALID_ARG, "n = %llu exceeds 2^32 - 1", (unsigned long long)n);
     if (n && (!records || !x || !y || !z)) return fail(FPO_ERR_INVALID_ARG, "NULL records or output");
+    if (n * h->record_length > records_bytes)
+        return fail(FPO_ERR_INVALID_ARG, "%llu records of %u bytes exceed the %llu bytes given", (unsigned long long)n,
+                    h->record_length, (unsigned long long)records_bytes);
     if (rgb && !h->has_rgb) return fail(FPO_ERR_INVALID_ARG, "point format %u has no colour", h->point_format);
     for (int a = 0; a < 3; ++a)
         if (!isfinite(origin[a])) return fail(FPO_ERR_INVALID_ARG, "origin must be finite");

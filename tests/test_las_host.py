@@ -69,7 +69,8 @@ def test_decode_argument_errors(fpo):
     o = (ctypes.c_double * 3)(0, 0, 0)
     buf = ctypes.create_string_buffer(64)
     # no context
-    assert lib.fpo_las_decode(None, ctypes.byref(h), buf, 1, o, buf, buf, buf, None, None) == fpo.FPO_ERR_INVALID_ARG
+    assert lib.fpo_las_decode(None, ctypes.byref(h), buf, 64, 1, o, buf, buf, buf, None,
+                              None) == fpo.FPO_ERR_INVALID_ARG
 
 
 def test_select_argument_errors(fpo):
