@@ -749,12 +749,14 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     launch_decide(A, st);
     launch_node_counts(A, U32(P.owned), st);
     scan_exclusive(U32(P.owned), U32(P.node_base), (uint64_t)MAXD * num_wc, &ctrs->num_nodes, stemp, st);
-    JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
-    JCHK(hipStreamSynchronize(st));
-    const uint32_t num_nodes = hctrs->num_nodes;
+    // node ids need no count: enqueued before the read-back, they keep the
+    // device busy while the host waits for the number of nodes
     t_nid.begin(st);
     launch_node_ids(A, U32(P.node_base), U32(P.nid), &ctrs->internal_error, n, st);
     t_nid.end(st);
+    JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
+    JCHK(hipStreamSynchronize(st));
+    const uint32_t num_nodes = hctrs->num_nodes;
     launch_fill_u32(U32(P.n_mask), 0u, (num_nodes + 3) / 4, st);
     launch_node_fill(A, U32(P.node_base), U8(P.n_depth), U64(P.n_key), U8(P.n_mask), st);
     // node_points: the original indices 0..n-1 split stably by node id, so
