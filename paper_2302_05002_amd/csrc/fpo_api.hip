@@ -601,31 +601,35 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     launch_fill_u32(fine, 0u, P.G3, st);
     uint64_t *cellmin = pa.mode == PV_GRID ? U64(P.cellmin) : nullptr;
     if (cellmin) launch_fill_u32(U32(P.cellmin), 0xffffffffu, 2 * P.G3, st);
-    // with a given box the quantise + count pass of a batch can start as soon
-    // as it has landed; the bounding-box pass (non-finite check) runs either way
-    const bool per_batch_quantize = host_in && given;
-    if (per_batch_quantize) launch_setup(box, U32(P.bbox_part), 0, given, p->bbox_min, p->bbox_max, 0, st);
-    uint32_t nparts = 0;
-    size_t bi = 1;
-    for (uint64_t o = 0; o < n; o += sbatch) {
-        const uint64_t c = n - o < sbatch ? n - o : sbatch;
-        if (host_in) JCHK(hipStreamWaitEvent(st, job->stream_events[bi++], 0));
-        t_bbox.begin(st);
-        launch_bbox(X + o, Y + o, Z + o, c, U32(P.bbox_part) + 8ull * nparts, st);
-        t_bbox.end(st);
-        nparts += bbox_blocks(c);
-        if (per_batch_quantize) {
+    if (given) {
+        // a given box: no bounding-box pass.  The quantise + count pass of a
+        // batch starts as soon as it has landed and also flags non-finite
+        // coordinates and counts points outside the box
+        launch_setup(box, U32(P.bbox_part), 0, given, p->bbox_min, p->bbox_max, 0, st);
+        size_t bi = 1;
+        for (uint64_t o = 0; o < n; o += sbatch) {
+            const uint64_t c = n - o < sbatch ? n - o : sbatch;
+            if (host_in) JCHK(hipStreamWaitEvent(st, job->stream_events[bi++], 0));
             t_quant.begin(st);
-            launch_quantize(X + o, Y + o, Z + o, c, box, g, given, U64(P.code) + o, fine, box, o, cellmin, st);
+            launch_quantize(X + o, Y + o, Z + o, c, box, g, 1, U64(P.code) + o, fine, box, o, cellmin, st);
             t_quant.end(st);
         }
-    }
-    if (per_batch_quantize) {
-        launch_setup(box, U32(P.bbox_part), nparts, given, p->bbox_min, p->bbox_max, 1, st);   // non-finite flag only
     } else {
-        launch_setup(box, U32(P.bbox_part), nparts, given, p->bbox_min, p->bbox_max, 0, st);
+        // bounding box of each batch as it lands, then the box and one
+        // quantise + count pass over all points
+        uint32_t nparts = 0;
+        size_t bi = 1;
+        for (uint64_t o = 0; o < n; o += sbatch) {
+            const uint64_t c = n - o < sbatch ? n - o : sbatch;
+            if (host_in) JCHK(hipStreamWaitEvent(st, job->stream_events[bi++], 0));
+            t_bbox.begin(st);
+            launch_bbox(X + o, Y + o, Z + o, c, U32(P.bbox_part) + 8ull * nparts, st);
+            t_bbox.end(st);
+            nparts += bbox_blocks(c);
+        }
+        launch_setup(box, U32(P.bbox_part), nparts, 0, p->bbox_min, p->bbox_max, 0, st);
         t_quant.begin(st);
-        launch_quantize(X, Y, Z, n, box, g, given, U64(P.code), fine, box, 0, cellmin, st);
+        launch_quantize(X, Y, Z, n, box, g, 0, U64(P.code), fine, box, 0, cellmin, st);
         t_quant.end(st);
     }
 

@@ -71,7 +71,7 @@ void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given,
 // base = original index of x[0]; cellmin (grid preview only, else nullptr)
 // receives the least H64 of each count-grid cell.
 void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box,
-                     int g, int count_outside, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw,
+                     int g, int given, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw,
                      uint64_t base, uint64_t *cellmin, hipStream_t st);
 void launch_pyramid(uint32_t *pyr, int g, hipStream_t st);
 void launch_grid_export(const uint32_t *fine_morton, int g, uint32_t *rowmajor, hipStream_t st);

@@ -12,6 +12,8 @@
 //   5. hash-of-index preview with an ordered compaction
 // Nothing here is a dense contraction, so no MFMA: the bounds are HBM
 // bandwidth, LDS/global atomics and scan latency.
+#include <float.h>
+
 #include "fpo_internal.h"
 
 namespace fpo {
@@ -382,7 +384,7 @@ __device__ void qz_flush(uint32_t *hk, uint32_t *hc, unsigned long long *hm, uin
 template <bool GRID>
 __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__ x, const float *__restrict__ y,
                                                        const float *__restrict__ z, uint64_t n, const DevBox *box,
-                                                       int g, int count_outside, uint64_t *__restrict__ code,
+                                                       int g, int given, uint64_t *__restrict__ code,
                                                        uint32_t *__restrict__ fine, DevBox *box_rw, uint64_t per_block,
                                                        uint64_t base, unsigned long long *__restrict__ cellmin)
 {
@@ -414,6 +416,7 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
     if (threadIdx.x == 0) used = 0;
     __syncthreads();
     uint32_t outside = 0;
+    bool bad = false;
     for (uint64_t r0 = lo; r0 < hi; r0 += ROUND) {
         uint32_t cell[ITEMS];
 #pragma unroll
@@ -423,8 +426,11 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
             const uint64_t c = (split3(ux) << 2) | (split3(uy) << 1) | split3(uz);
             cell[j] = i < hi ? (uint32_t)(c >> sh) : 0xffffffffu;
             if (i < hi) code[i] = c;
-            if (count_outside && i < hi)
+            if (given && i < hi) {
                 outside += (px[j] < lx || px[j] > hx || py[j] < ly || py[j] > hy || pz[j] < lz || pz[j] > hz) ? 1u : 0u;
+                // NaN fails every comparison, an infinity exceeds the largest float
+                bad |= !(fabsf(px[j]) <= FLT_MAX && fabsf(py[j]) <= FLT_MAX && fabsf(pz[j]) <= FLT_MAX);
+            }
         }
         // next round's coordinates
 #pragma unroll
@@ -469,15 +475,20 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
     }
     __syncthreads();
     qz_flush<GRID>(hk, hc, hm, fine, cellmin);
-    if (count_outside) {
-        // one atomic per block (the same counter for every block)
+    if (given) {
+        // one atomic per block (the same counters for every block)
         outside = wave_sum(outside);
-        if (lane_id() == 0) wsum[threadIdx.x >> 6] = outside;
+        const bool wbad = __ballot(bad) != 0;
+        if (lane_id() == 0) wsum[threadIdx.x >> 6] = outside | (wbad ? 0x80000000u : 0u);
         __syncthreads();
         if (threadIdx.x == 0) {
-            uint32_t t = 0;
-            for (int w = 0; w < QZ_BLOCK / 64; ++w) t += wsum[w];
+            uint32_t t = 0, b = 0;
+            for (int w = 0; w < QZ_BLOCK / 64; ++w) {
+                t += wsum[w] & 0x7fffffffu;
+                b |= wsum[w] >> 31;
+            }
             if (t) atomicAdd(&box_rw->n_outside, (unsigned long long)t);
+            if (b) atomicOr(&box_rw->nonfinite, 1u);
         }
     }
 }
@@ -2312,7 +2323,7 @@ void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given,
 }
 
 void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box, int g,
-                     int count_outside, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw, uint64_t base,
+                     int given, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw, uint64_t base,
                      uint64_t *cellmin, hipStream_t st)
 {
     if (n == 0) return;
@@ -2323,10 +2334,10 @@ void launch_quantize(const float *x, const float *y, const float *z, uint64_t n,
     const uint32_t grid = (uint32_t)((n + per - 1) / per);
     auto *cm = reinterpret_cast<unsigned long long *>(cellmin);
     if (cellmin)
-        hipLaunchKernelGGL(k_quantize<true>, dim3(grid), dim3(QZ_BLOCK), 0, st, x, y, z, n, box, g, count_outside,
+        hipLaunchKernelGGL(k_quantize<true>, dim3(grid), dim3(QZ_BLOCK), 0, st, x, y, z, n, box, g, given,
                            code, fine_cnt, box_rw, per, base, cm);
     else
-        hipLaunchKernelGGL(k_quantize<false>, dim3(grid), dim3(QZ_BLOCK), 0, st, x, y, z, n, box, g, count_outside,
+        hipLaunchKernelGGL(k_quantize<false>, dim3(grid), dim3(QZ_BLOCK), 0, st, x, y, z, n, box, g, given,
                            code, fine_cnt, box_rw, per, base, cm);
 }
 

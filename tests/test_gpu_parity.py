@@ -162,6 +162,28 @@ def test_nonfinite_rejected(ctx):
     assert e.value.status == fpo.FPO_ERR_NONFINITE
 
 
+def test_nonfinite_rejected_with_given_box(ctx):
+    """With a given box there is no bounding-box pass: the quantise pass flags
+    NaN and infinities, in any coordinate and anywhere in the input."""
+    import torch
+    import paper_2302_05002_amd as fpo
+    box = ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    c = synth.uniform(300_000, seed=77)
+    for bad in (float("nan"), float("inf"), float("-inf")):
+        for axis in range(3):
+            for at in (0, 123_457, c.n - 1):
+                a = [np.ascontiguousarray(v).copy() for v in (c.x, c.y, c.z)]
+                a[axis][at] = bad
+                x, y, z = (torch.from_numpy(v).cuda() for v in a)
+                with pytest.raises(fpo.FpoError) as e:
+                    ctx.build(x, y, z, fpo.Params(16, 10_000, 8, 100, 4, box))
+                assert e.value.status == fpo.FPO_ERR_NONFINITE, (bad, axis, at)
+    # finite points outside the given box are fine (counted, clamped)
+    a = [np.ascontiguousarray(v).copy() for v in (c.x, c.y, c.z)]
+    a[1][5] = 7.0
+    run_both(ctx, synth.Cloud(*a), 16, 10_000, 8, 100, 4, box, label="outside: ")
+
+
 def test_config1_full(ctx):
     """The uniform 1M-point workload, every output compared."""
     c = synth.config1()

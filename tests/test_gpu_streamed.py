@@ -82,3 +82,18 @@ def test_config3_full(ctx):
     c = synth.config3()
     streamed_vs_oracle(ctx, c, p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity,
                        p.preview_modulus, exact_box(c), 16_000_000, "config3: ")
+
+
+def test_streamed_nonfinite_with_given_box(ctx):
+    """A NaN in the last batch of a streamed build with a given box."""
+    import paper_2302_05002_amd as fpo
+    c = synth.uniform(1_000_000, seed=92)
+    x = c.x.copy()
+    x[-3] = float("nan")
+    box = ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    hx, hy, hz = pinned(synth.Cloud(x, c.y, c.z))
+    job = ctx.submit(hx, hy, hz, fpo.Params(16, 100_000, 8, 1_000, 4, box), stream_batch=300_000)
+    with pytest.raises(fpo.FpoError) as e:
+        job.wait()
+    assert e.value.status == fpo.FPO_ERR_NONFINITE
+    job.release()
