@@ -2184,13 +2184,29 @@ __global__ void k_node_fill(WcArgs a, const uint32_t *node_base, uint8_t *depth,
     }
 }
 
-// Begin and count of every node from the node-sorted keys.
+// Begin and count of every node from the node-sorted keys (16-byte aligned):
+// four keys per thread and step, with the neighbours across the group edges.
 __global__ void k_node_ranges(const uint32_t *sk, uint64_t n, uint64_t *begin, uint32_t *count, uint32_t nn)
 {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t k = sk[i];
-        if (i == 0 || sk[i - 1] != k) begin[k] = i;
-        if (i + 1 == n || sk[i + 1] != k) count[k] = (uint32_t)(i + 1);  // end, fixed below
+    const uint64_t n4 = (n + 3) / 4;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n4; g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i0 = 4 * g;
+        uint32_t k[6];
+        if (i0 + 4 <= n) {
+            const uint4 v = reinterpret_cast<const uint4 *>(sk)[g];
+            k[1] = v.x; k[2] = v.y; k[3] = v.z; k[4] = v.w;
+        } else {
+            for (int j = 0; j < 4; ++j) k[1 + j] = i0 + j < n ? sk[i0 + j] : 0u;
+        }
+        k[0] = i0 > 0 ? sk[i0 - 1] : ~k[1];
+        k[5] = i0 + 4 < n ? sk[i0 + 4] : ~k[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t i = i0 + j;
+            if (i >= n) break;
+            if (k[j] != k[j + 1]) begin[k[j + 1]] = i;
+            if (i + 1 == n || k[j + 2] != k[j + 1]) count[k[j + 1]] = (uint32_t)(i + 1);   // end, fixed below
+        }
     }
 }
 __global__ void k_node_count_fix(const uint64_t *begin, uint32_t *count, uint32_t nn)
@@ -2479,7 +2495,8 @@ void launch_node_ranges(const uint32_t *sorted_keys, uint64_t n, uint64_t *begin
                         hipStream_t st)
 {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_node_ranges, dim3(grid_for(n, 256)), dim3(256), 0, st, sorted_keys, n, begin, count, num_nodes);
+    hipLaunchKernelGGL(k_node_ranges, dim3(grid_for((n + 3) / 4, 256)), dim3(256), 0, st, sorted_keys, n, begin, count,
+                       num_nodes);
     hipLaunchKernelGGL(k_node_count_fix, dim3(grid_for(num_nodes, 256)), dim3(256), 0, st, begin, count, num_nodes);
 }
 
