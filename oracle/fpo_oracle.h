@@ -14,8 +14,8 @@
  *   visits every point once.
  * The paper gives no constants, rounding rules or orderings for either; the
  * readings used here (21-bit lattice, min-corner cube, lowest index wins a
- * subsample cell, hash-of-index preview, ...) are listed in the design doc and in
- * the comments of fpo_oracle.c at the step they govern.
+ * subsample cell, hash-of-index preview, ...) are stated in the comments of
+ * fpo_oracle.c at the step they govern.
  */
 #ifndef FPO_ORACLE_H
 #define FPO_ORACLE_H
