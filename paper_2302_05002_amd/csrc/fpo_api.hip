@@ -697,7 +697,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
             sg.max_cells = n + num_wc;
             in.vals = U32(P.perm);   // original indices ride along
             o.vals = U32(P.wc_orig);
-            multisplit_segmented(in, n, sg, (n + MS_TILE - 1) / MS_TILE + num_chunks, o, ws + P.ms_temp, st);
+            multisplit_segmented(in, n, sg, (n + MS_SEG_TILE - 1) / MS_SEG_TILE + num_chunks, o, ws + P.ms_temp, st);
         } else {
             in.vals = U32(P.perm);
             o.vals = U32(P.wc_orig);

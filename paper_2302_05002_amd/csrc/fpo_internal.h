@@ -27,6 +27,10 @@ constexpr int WC_GENERAL = 6;
 constexpr int MS_BLOCK = 256;                // multisplit block (4 waves)
 constexpr int MS_ITEMS = 8;                  // elements per thread
 constexpr uint32_t MS_TILE = MS_BLOCK * MS_ITEMS;  // 2048
+// Segmented splits (many small buckets per segment) take longer tiles, so a
+// bucket's run inside a tile is long enough to write whole lines.
+constexpr int MS_SEG_ITEMS = 12;
+constexpr uint32_t MS_SEG_TILE = MS_BLOCK * MS_SEG_ITEMS;  // 3072
 constexpr uint32_t MS_MAX_BINS = 2048;       // buckets a tile can hold (segments)
 constexpr uint32_t MS_ONE_PASS_BINS = 1024;  // beyond this, sort by digits (keeps the count matrix small)
 constexpr uint32_t MS_DIGIT_BITS = 10;

@@ -801,13 +801,14 @@ struct MsTile {
     bool ok;
 };
 
-template <bool SEG>
+template <bool SEG, int IT>
 __device__ __forceinline__ MsTile ms_tile(const MsArgs &A, uint32_t t)
 {
+    constexpr uint32_t TILE = MS_BLOCK * IT;
     MsTile T{};
     if (!SEG) {
-        T.lo = (uint64_t)t * MS_TILE;
-        T.hi = T.lo + MS_TILE < A.n ? T.lo + MS_TILE : A.n;
+        T.lo = (uint64_t)t * TILE;
+        T.hi = T.lo + TILE < A.n ? T.lo + TILE : A.n;
         T.b0 = 0;
         T.nb = A.nbins;
         T.mat = 0;
@@ -826,8 +827,8 @@ __device__ __forceinline__ MsTile ms_tile(const MsArgs &A, uint32_t t)
     const uint32_t sgm = lo;
     T.tis = t - A.seg_tile_first[sgm];
     const uint64_t sb = A.seg_begin[sgm], se = A.seg_begin[sgm] + A.seg_len[sgm];
-    T.lo = sb + (uint64_t)T.tis * MS_TILE;
-    T.hi = T.lo + MS_TILE < se ? T.lo + MS_TILE : se;
+    T.lo = sb + (uint64_t)T.tis * TILE;
+    T.hi = T.lo + TILE < se ? T.lo + TILE : se;
     T.b0 = A.seg_b0[sgm];
     T.nb = A.seg_nb[sgm];
     T.mat = A.seg_mat[sgm];
@@ -838,24 +839,24 @@ __device__ __forceinline__ MsTile ms_tile(const MsArgs &A, uint32_t t)
 // Count pass: equal keys of a wave round are grouped by a ballot match and
 // added once (consecutive points usually share their chunk), so LDS atomics
 // do not pile up on one counter.
-template <bool SEG>
+template <bool SEG, int IT = MS_ITEMS>
 __global__ __launch_bounds__(MS_BLOCK) void k_ms_count(MsArgs A)
 {
-    constexpr int PER_WAVE = MS_ITEMS * 64;
+    constexpr int PER_WAVE = IT * 64;
     __shared__ uint32_t hist[MS_MAX_BINS];
-    const MsTile T = ms_tile<SEG>(A, blockIdx.x);
+    const MsTile T = ms_tile<SEG, IT>(A, blockIdx.x);
     if (!T.ok) return;
     const int w = threadIdx.x >> 6, lane = lane_id();
     const uint64_t wlo = T.lo + (uint64_t)w * PER_WAVE;
     // all loads of the tile first, so their latencies overlap
-    uint32_t full[MS_ITEMS];
+    uint32_t full[IT];
     ms_load_keys(A, wlo, T.hi, lane, full);
     for (uint32_t b = threadIdx.x; b < T.nb; b += MS_BLOCK) hist[b] = 0;
     __syncthreads();
     const uint32_t dmask = (1u << A.dbits) - 1u;
     const int nbits = (int)ceil_log2_dev(T.nb);
 #pragma unroll
-    for (int r = 0; r < MS_ITEMS; ++r) {
+    for (int r = 0; r < IT; ++r) {
         const uint64_t e = wlo + (uint64_t)r * 64 + lane;
         const bool valid = e < T.hi;
         const uint32_t key = valid ? ((full[r] >> A.shift) & dmask) - T.b0 : 0u;
@@ -867,18 +868,19 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_count(MsArgs A)
         A.counts[(uint64_t)T.mat + (uint64_t)b * T.ntile + T.tis] = hist[b];
 }
 
-template <bool SEG>
+template <bool SEG, int IT = MS_ITEMS>
 __global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
 {
+    constexpr uint32_t TILE = MS_BLOCK * IT;
     constexpr int W = MS_BLOCK / 64;
-    constexpr int PER_WAVE = MS_ITEMS * 64;
+    constexpr int PER_WAVE = IT * 64;
     __shared__ uint16_t pre[W][MS_MAX_BINS];
     __shared__ uint32_t gbase[MS_MAX_BINS];   // global position of local slot 0 of a bucket (mod 2^32)
-    __shared__ unsigned long long stage[MS_TILE];   // (key, value) pairs, then payloads
+    __shared__ unsigned long long stage[TILE];   // (key, value) pairs, then payloads
     // scan scratch, in the stage (unused until phase 3): 40 KB in all, four
     // blocks per compute unit
     uint32_t *red = reinterpret_cast<uint32_t *>(stage);
-    const MsTile T = ms_tile<SEG>(A, blockIdx.x);
+    const MsTile T = ms_tile<SEG, IT>(A, blockIdx.x);
     if (!T.ok) return;
     const int w = threadIdx.x >> 6, lane = lane_id();
     const uint32_t dmask = (1u << A.dbits) - 1u;
@@ -886,36 +888,36 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
     // all loads of the tile first (keys, values, payloads), so their
     // latencies overlap
     const uint64_t wlo = T.lo + (uint64_t)w * PER_WAVE;
-    uint32_t full[MS_ITEMS], val[MS_ITEMS];
-    unsigned long long pay[MS_ITEMS];
+    uint32_t full[IT], val[IT];
+    unsigned long long pay[IT];
     ms_load_keys(A, wlo, T.hi, lane, full);
     if (A.vals) {
 #pragma unroll
-        for (int r = 0; r < MS_ITEMS; ++r) {
+        for (int r = 0; r < IT; ++r) {
             const uint64_t e = wlo + (uint64_t)r * 64 + lane;
             val[r] = A.vals[e < T.hi ? e : T.hi - 1];
         }
     } else {
 #pragma unroll
-        for (int r = 0; r < MS_ITEMS; ++r) val[r] = (uint32_t)(wlo + (uint64_t)r * 64 + lane);
+        for (int r = 0; r < IT; ++r) val[r] = (uint32_t)(wlo + (uint64_t)r * 64 + lane);
     }
     if (A.pay) {
 #pragma unroll
-        for (int r = 0; r < MS_ITEMS; ++r) {
+        for (int r = 0; r < IT; ++r) {
             const uint64_t e = wlo + (uint64_t)r * 64 + lane;
             pay[r] = A.pay[e < T.hi ? e : T.hi - 1];
         }
     } else {
 #pragma unroll
-        for (int r = 0; r < MS_ITEMS; ++r) pay[r] = wlo + (uint64_t)r * 64 + lane;
+        for (int r = 0; r < IT; ++r) pay[r] = wlo + (uint64_t)r * 64 + lane;
     }
     for (uint32_t b = threadIdx.x; b < T.nb; b += MS_BLOCK)
         for (int k = 0; k < W; ++k) pre[k][b] = 0;
     __syncthreads();
     // phase 1: per-wave running counts; each lane keeps its offset inside its wave
-    uint16_t wof[MS_ITEMS];
+    uint16_t wof[IT];
 #pragma unroll
-    for (int r = 0; r < MS_ITEMS; ++r) {
+    for (int r = 0; r < IT; ++r) {
         const uint64_t e = wlo + (uint64_t)r * 64 + lane;
         const bool valid = e < T.hi;
         const uint32_t key = valid ? ((full[r] >> A.shift) & dmask) - T.b0 : 0u;
@@ -949,7 +951,7 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
     __syncthreads();
     // phase 3: stage (key, value) in bucket order
 #pragma unroll
-    for (int r = 0; r < MS_ITEMS; ++r) {
+    for (int r = 0; r < IT; ++r) {
         const uint64_t e = wlo + (uint64_t)r * 64 + lane;
         if (e >= T.hi) continue;
         const uint32_t key = ((full[r] >> A.shift) & dmask) - T.b0;
@@ -960,9 +962,9 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
     __syncthreads();
     // phase 4: write bucket runs
     const uint32_t cnt = (uint32_t)(T.hi - T.lo);
-    uint32_t gp[MS_ITEMS];
+    uint32_t gp[IT];
 #pragma unroll
-    for (int i = 0; i < MS_ITEMS; ++i) {
+    for (int i = 0; i < IT; ++i) {
         const uint32_t k = i * MS_BLOCK + threadIdx.x;
         if (k >= cnt) continue;
         const unsigned long long kv = stage[k];
@@ -977,14 +979,14 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
         // the input position (and payload) of every slot, through the same stage
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < MS_ITEMS; ++r) {
+        for (int r = 0; r < IT; ++r) {
             const uint64_t e = wlo + (uint64_t)r * 64 + lane;
             if (e >= T.hi) continue;
             stage[wof[r]] = pay[r];
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < MS_ITEMS; ++i) {
+        for (int i = 0; i < IT; ++i) {
             const uint32_t k = i * MS_BLOCK + threadIdx.x;
             if (k >= cnt) continue;
             if (A.pay_out) A.pay_out[gp[i]] = stage[k];
@@ -992,7 +994,7 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
         if (A.src_out && A.pay_out) {
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < MS_ITEMS; ++r) {
+            for (int r = 0; r < IT; ++r) {
                 const uint64_t e = wlo + (uint64_t)r * 64 + lane;
                 if (e >= T.hi) continue;
                 stage[wof[r]] = e;
@@ -1001,7 +1003,7 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
         }
         if (A.src_out) {
 #pragma unroll
-            for (int i = 0; i < MS_ITEMS; ++i) {
+            for (int i = 0; i < IT; ++i) {
                 const uint32_t k = i * MS_BLOCK + threadIdx.x;
                 if (k >= cnt) continue;
                 A.src_out[gp[i]] = (uint32_t)stage[k];
@@ -1011,11 +1013,12 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
 }
 
 // Segment preparation: tiles per segment and count-matrix cells per segment.
-__global__ void k_ms_seg_prep(uint32_t nseg, const uint32_t *len, const uint32_t *nb, uint32_t *ntile, uint32_t *cells)
+__global__ void k_ms_seg_prep(uint32_t nseg, const uint32_t *len, const uint32_t *nb, uint32_t *ntile, uint32_t *cells,
+                              uint32_t tile)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) ntile[nseg] = 0;
     for (uint32_t sg = blockIdx.x * blockDim.x + threadIdx.x; sg < nseg; sg += gridDim.x * blockDim.x) {
-        const uint32_t t = (len[sg] + MS_TILE - 1) / MS_TILE;
+        const uint32_t t = (len[sg] + tile - 1) / tile;
         ntile[sg] = t;
         cells[sg] = t * nb[sg];
     }
@@ -1148,7 +1151,8 @@ void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, u
     uint32_t *counts = reinterpret_cast<uint32_t *>(p); p += align256(4 * sg.max_cells);
     uint32_t *offs = reinterpret_cast<uint32_t *>(p); p += align256(4 * sg.max_cells);
     void *stemp = p;
-    hipLaunchKernelGGL(k_ms_seg_prep, dim3(div_up(sg.nseg, 256)), dim3(256), 0, st, sg.nseg, sg.len, sg.nb, ntile, cells);
+    hipLaunchKernelGGL(k_ms_seg_prep, dim3(div_up(sg.nseg, 256)), dim3(256), 0, st, sg.nseg, sg.len, sg.nb, ntile, cells,
+                       MS_SEG_TILE);
     // tile_first has nseg + 1 entries (the last one = total tiles)
     scan_exclusive(ntile, tile_first, sg.nseg + 1, tot, stemp, st);
     scan_exclusive(cells, mat, sg.nseg, tot + 1, stemp, st);
@@ -1176,9 +1180,9 @@ void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, u
     A.keys_out = out.keys;
     A.pay_out = out.pay;
     A.src_out = out.src;
-    hipLaunchKernelGGL(k_ms_count<true>, dim3((uint32_t)max_tiles), dim3(MS_BLOCK), 0, st, A);
+    hipLaunchKernelGGL((k_ms_count<true, MS_SEG_ITEMS>), dim3((uint32_t)max_tiles), dim3(MS_BLOCK), 0, st, A);
     scan_exclusive_dev(counts, offs, tot + 1, sg.max_cells, stemp, st);
-    hipLaunchKernelGGL(k_ms_scatter<true>, dim3((uint32_t)max_tiles), dim3(MS_BLOCK), 0, st, A);
+    hipLaunchKernelGGL((k_ms_scatter<true, MS_SEG_ITEMS>), dim3((uint32_t)max_tiles), dim3(MS_BLOCK), 0, st, A);
 }
 
 // ---- step 4: per-node grid subsample -----------------------------------------------------------
