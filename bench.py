@@ -50,10 +50,10 @@ KERNEL_BYTES = {
 KERNEL_NAMES = {
     "bbox": "fpo::k_bbox",
     "quantize": "fpo::k_quantize",
-    "chunk_scatter": "fpo::k_ms_scatter<false> (split into chunks)",
+    "chunk_scatter": "fpo::k_ms_scatter<false, 8> (split into chunks)",
     "subsample": "fpo::k_subsample_* (all size classes)",
     "node_ids": "fpo::k_node_ids",
-    "node_points": "fpo::k_ms_scatter<false> (node_points split)",
+    "node_points": "fpo::k_ms_scatter<false, 8> (node_points split)",
 }
 
 

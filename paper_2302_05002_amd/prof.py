@@ -94,7 +94,7 @@ def groups_per_build(path: str, counter: str, chunk_passes: int = 1, node_passes
             elif "k_node_ids" in k:
                 sums["node_ids"] += v
                 after_ids = True
-            elif "k_ms_scatter<false>" in k:
+            elif "k_ms_scatter<false" in k:
                 if after_ids and node_left > 0:
                     sums["node_points"] += v
                     node_left -= 1
