@@ -43,8 +43,8 @@ KERNEL_BYTES = {
     "quantize": (lambda n, G, M: 12 * n + 4 * G ** 3, "read x, y, z again: 12 B/pt; write the count grid: 4 B/cell"),
     "chunk_scatter": (lambda n, G, M: 16 * n, "re-read the points 12 B/pt, write perm 4 B/pt"),
     "subsample": (lambda n, G, M: 16 * n, "read perm 4 B/pt, gather the coordinates once 12 B/pt"),
-    "node_ids": (lambda n, G, M: 4 * n, "one 4-byte id per point"),
-    "node_points": (lambda n, G, M: 4 * n, "write node_points 4 B/pt"),
+    "node_counts": (lambda n, G, M: 5 * n, "read each point's depth 1 B and own-node rank 4 B"),
+    "node_points": (lambda n, G, M: 8 * n, "read the original indices in work-chunk order 4 B/pt, write node_points 4 B/pt"),
 }
 
 KERNEL_NAMES = {
@@ -52,8 +52,8 @@ KERNEL_NAMES = {
     "quantize": "fpo::k_quantize",
     "chunk_scatter": "fpo::k_ms_scatter<false, 8> (split into chunks)",
     "subsample": "fpo::k_subsample_* (all size classes)",
-    "node_ids": "fpo::k_node_ids",
-    "node_points": "fpo::k_ms_scatter<false, 8> (node_points split)",
+    "node_counts": "fpo::k_np_count + scan + fpo::k_np_shared",
+    "node_points": "fpo::k_np_place + fpo::k_np_sort + fpo::k_np_merge",
 }
 
 

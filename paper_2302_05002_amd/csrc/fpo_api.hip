@@ -75,6 +75,9 @@ struct Ctrs {
     uint32_t internal_error;
     uint32_t wc_flags[2];      // [0] a work chunk spans several chunks, [1] a chunk holds too many
     uint32_t cls_cnt[WC_CLASSES];   // work chunks per LDS size class
+    uint32_t np_max;                // points of the largest node
+    uint32_t np_lists[5];           // node_points sort: tile lists of four sizes, merge jobs
+    uint32_t np_general;            // work chunks with own nodes below their root
 };
 static_assert(sizeof(Ctrs) <= 256, "the box follows the counters 256 bytes later");
 
@@ -93,7 +96,7 @@ struct Plan {
     size_t c_count_scan, code_perm, wc_orig, wc_code, ms_temp, scan_temp, seg_b0, seg_nb, wc_nested, wc_chunk;
     size_t gtab, t, fr, alive, alive_scan, kd, loff, owned, node_base, lnode_key, lnode_mask, cut;
     size_t big_list, big_nr, big_node, big_hkey, big_hval, cls_list;
-    size_t nid, sorted_nid, pv_tiles, pv_offs, cellmin, pv_bits;
+    size_t np_tmp, np_glist, np_cnt, np_scan, np_nb, np_l0, np_l1, np_l2, np_l3, np_jobs, pv_tiles, pv_offs, cellmin, pv_bits;
     uint64_t pv_ntiles;
 };
 
@@ -170,6 +173,7 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     }
     uint64_t scan_max = P.G3 > (uint64_t)MAXD * P.maxW ? P.G3 : (uint64_t)MAXD * P.maxW;
     if (P.pv_ntiles > scan_max) scan_max = P.pv_ntiles;
+    if (nn > scan_max) scan_max = nn;   // node sizes (nodes number at most n)
     P.scan_temp = take(scan_temp_bytes(scan_max));
     // cells of the deepest globally decided depth (level d0 - 1 + s)
     P.gtab = P.d0 > 0 ? take(4ull << (3 * (P.d0 - 1 + P.s))) : 0;
@@ -191,8 +195,16 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     // hash slots for work chunks above the LDS capacity: at most 4n in total
     P.big_hkey = take(8 * 4 * nn);
     P.big_hval = take(4 * 4 * nn);
-    P.nid = take(4 * nn);
-    P.sorted_nid = take(4 * nn);
+    P.np_tmp = take(4 * nn);
+    P.np_cnt = take(4 * MAXD * P.maxW);
+    P.np_glist = take(4 * P.maxW);
+    P.np_scan = take(4 * (MAXD * P.maxW + 1));
+    P.np_nb = take(4 * (nn + 1));
+    P.np_l0 = take(4 * np_list_entries(nn, 0));
+    P.np_l1 = take(4 * np_list_entries(nn, 1));
+    P.np_l2 = take(4 * np_list_entries(nn, 2));
+    P.np_l3 = take(8 * np_list_entries(nn, 3));
+    P.np_jobs = take(8 * np_job_entries(nn));
     P.pv_tiles = take(4 * P.pv_ntiles);
     P.pv_offs = take(4 * P.pv_ntiles);
     P.cellmin = (p.flags & FPO_PREVIEW_GRID) ? take(8 * P.G3) : 0;
@@ -560,7 +572,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     // ---- step 1: bbox, quantise, count ----
     const int given = (p->flags & FPO_BBOX_GIVEN) ? 1 : 0;
     JobTimer t_bbox(job, FPO_TIMER_BBOX), t_quant(job, FPO_TIMER_QUANTIZE), t_chunk(job, FPO_TIMER_CHUNK_SCATTER),
-        t_sub(job, FPO_TIMER_SUBSAMPLE), t_nid(job, FPO_TIMER_NODE_IDS), t_npts(job, FPO_TIMER_NODE_POINTS);
+        t_sub(job, FPO_TIMER_SUBSAMPLE), t_ncnt(job, FPO_TIMER_NODE_COUNTS), t_npts(job, FPO_TIMER_NODE_POINTS);
     const float *X = cloud->x, *Y = cloud->y, *Z = cloud->z;
     if (host_in) {
         // pinned host input: batches copied into the workspace on the copy
@@ -753,27 +765,40 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     launch_decide(A, st);
     launch_node_counts(A, U32(P.owned), st);
     scan_exclusive(U32(P.owned), U32(P.node_base), (uint64_t)MAXD * num_wc, &ctrs->num_nodes, stemp, st);
-    // node ids need no count: enqueued before the read-back, they keep the
-    // device busy while the host waits for the number of nodes
-    t_nid.begin(st);
-    launch_node_ids(A, U32(P.node_base), U32(P.nid), &ctrs->internal_error, n, st);
-    t_nid.end(st);
+    // points per node (node_count) need no host count: enqueued before the
+    // read-back, they keep the device busy while the host waits for it
+    t_ncnt.begin(st);
+    launch_np_counts(A, U32(P.node_base), U32(P.np_cnt), U32(P.np_scan), U32(P.n_count), U32(P.owned),
+                     U32(P.np_glist), &ctrs->np_general, &ctrs->np_max, stemp, st);
+    t_ncnt.end(st);
     JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
     JCHK(hipStreamSynchronize(st));
     const uint32_t num_nodes = hctrs->num_nodes;
+    if (num_nodes > NP_MAX_NODES) return end_job(fail(FPO_ERR_INVALID_ARG, "%u nodes: at most 2^31 - 1", num_nodes));
     launch_fill_u32(U32(P.n_mask), 0u, (num_nodes + 3) / 4, st);
     launch_node_fill(A, U32(P.node_base), U8(P.n_depth), U64(P.n_key), U8(P.n_mask), st);
-    // node_points: the original indices 0..n-1 split stably by node id, so
-    // every node lists its points in ascending original index
+    // node_points: every point placed in its node's range, then each range
+    // sorted by original index
     {
-        MsInput in;
-        in.keys = U32(P.nid);
-        MsOutput o;
-        o.vals = U32(P.n_points);
-        o.keys = U32(P.sorted_nid);
-        multisplit(in, n, num_nodes, o, ws + P.ms_temp, st, &t_npts);
+        NpWork w{};
+        w.nb = U32(P.np_nb);
+        w.tmp = U32(P.np_tmp);
+        w.fill = U32(P.big_nr);
+        w.general = hctrs->np_general > 0;
+        w.err = &ctrs->internal_error;
+        w.out = U32(P.n_points);
+        w.lists.c0 = U32(P.np_l0);
+        w.lists.c1 = U32(P.np_l1);
+        w.lists.c2 = U32(P.np_l2);
+        w.lists.c3 = U64(P.np_l3);
+        w.lists.jobs = U64(P.np_jobs);
+        w.lists.counts = ctrs->np_lists;
+        w.scan_temp = stemp;
+        w.timer = &t_npts;
+        launch_np_points(A, U32(P.node_base), U32(P.owned), U32(P.np_cnt), U32(P.n_count), num_nodes, hctrs->np_max, n,
+                         w, st);
     }
-    launch_node_ranges(U32(P.sorted_nid), n, U64(P.n_begin), U32(P.n_count), num_nodes, st);
+    launch_u32_to_u64(U32(P.np_nb), U64(P.n_begin), num_nodes, st);
 
     JCHK(hipMemcpyAsync(hctrs, ctrs, 256 + sizeof(DevBox), hipMemcpyDeviceToHost, st));   // counters and box
     JCHK(hipEventRecord(job->ev_done, st));

@@ -155,7 +155,8 @@ struct WcArgs {
     uint8_t *t;                  // tentative depth per position
     uint32_t *fr;                // local node rank per position
     uint32_t *alive;             // [MAXD][num_wc] points reaching each shared ancestor from a work
-                                 // chunk; after k_decide, the ancestor's whole reaching count (d <= cut)
+                                 // chunk (row lw: reaching its own root); after k_decide, rows d <= cut
+                                 // hold the ancestor's whole reaching count
     const uint32_t *alive_scan;  // exclusive scan of alive over the flattened matrix (MAXD * num_wc + 1)
     uint32_t *kd;                // [num_wc][MAXD] local node count per depth
     uint32_t *loff;              // [num_wc][MAXD] offset of a depth's local nodes
@@ -188,8 +189,40 @@ void launch_subsample_small(const WcArgs &a, hipStream_t st);
 void launch_subsample_big(const WcArgs &a, hipStream_t st);
 void launch_decide(const WcArgs &a, hipStream_t st);
 void launch_node_counts(const WcArgs &a, uint32_t *owned, hipStream_t st);
-void launch_node_ids(const WcArgs &a, const uint32_t *node_base, uint32_t *nid_perm, uint32_t *err, uint64_t n,
-                     hipStream_t st);
+// node_points, sizes first: cnt_dw[d * W + w] = points of work chunk w in the
+// shared node of depth d (from the reaching counts), S its exclusive scan
+// (MAXD * W + 1 entries), cnt_node[id] = points of every node; per (d, w) the
+// node whose range one offset places w's depth-d points in (pnode, all ones
+// for none) and that offset (in place of cnt_dw); work chunks with own nodes
+// below their root in glist (*gcount, zeroed before).  *maxc = the largest
+// node (zeroed before).
+void launch_np_counts(const WcArgs &a, const uint32_t *node_base, uint32_t *cnt_dw, uint32_t *S, uint32_t *cnt_node,
+                      uint32_t *pnode, uint32_t *glist, uint32_t *gcount, uint32_t *maxc, void *scan_temp,
+                      hipStream_t st);
+constexpr uint32_t NP_MAX_NODES = 0x7fffffffu;   // the tile lists flag groups of nodes in bit 31
+struct NpLists {
+    uint32_t *c0, *c1, *c2;   // tiles of up to 1024, 4096, 8192 values: a node, or a group of small nodes
+    uint64_t *c3;             // parts of up to 16384 values of longer nodes
+    uint64_t *jobs;           // merge jobs of the nodes above 16384 values
+    uint32_t *counts;         // 5 list lengths, zeroed before
+};
+struct NpWork {
+    uint32_t *nb;         // node begins (num_nodes + 1)
+    uint32_t *tmp;        // n: points placed in node order; then the merges' other buffer
+    uint32_t *fill;       // per node id: fill counters of own nodes below subdivided roots
+    bool general;         // some work chunk has such nodes (fill is zeroed then)
+    uint32_t *err;        // set when a point was never placed
+    uint32_t *out;        // n: node_points
+    NpLists lists;
+    void *scan_temp;
+    LaunchTimer *timer;   // brackets placement, sorts and merges
+};
+// Then the points of every node in ascending original index, at the begins nb.
+void launch_np_points(const WcArgs &a, const uint32_t *node_base, const uint32_t *pnode, const uint32_t *poff,
+                      const uint32_t *cnt_node, uint32_t num_nodes, uint32_t max_count, uint64_t n, const NpWork &w,
+                      hipStream_t st);
+uint64_t np_list_entries(uint64_t n, int cls);   // entries of tile list cls (0..3) for n points
+uint64_t np_job_entries(uint64_t n);
 // Chunk of every work chunk (the chunk holding its first occupied finest
 // cell), per chunk the range of its work chunks [b0, b0 + nb), per work chunk
 // whether it lies inside that chunk; flags[0] is set when some work chunk
@@ -201,8 +234,6 @@ void launch_wc_chunks(const uint32_t *num_wc_dev, uint64_t max_wc, const uint64_
                       uint32_t *seg_nb, uint8_t *wc_nested, uint32_t *flags, hipStream_t st);
 void launch_node_fill(const WcArgs &a, const uint32_t *node_base, uint8_t *depth, uint64_t *key,
                       uint8_t *mask, hipStream_t st);
-void launch_node_ranges(const uint32_t *sorted_keys, uint64_t n, uint64_t *begin, uint32_t *count,
-                        uint32_t num_nodes, hipStream_t st);
 
 // Node-ordered gather: out_xyz[3k + a] = coord_a[idx[k]], colour bytes alike.
 void launch_gather_points(const uint32_t *idx, uint64_t n, const float *x, const float *y, const float *z,

@@ -1462,6 +1462,7 @@ __device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint
             if (threadIdx.x == 0) alive_at[d] = A;
             single_inner = true;
         } else if (d == lw) {
+            if (threadIdx.x == 0) alive_at[d] = A;
             Kd = 1;
             single_inner = !deepest && A > a.L;
             it.each([&](uint32_t, uint64_t, uint32_t &st, uint32_t &r, uint32_t &) { if (st == ST_ALIVE) r = 0; });
@@ -1632,12 +1633,12 @@ __device__ bool subsample_wc(const WcArgs &a, uint32_t w, uint32_t *region, uint
         }
     }
     // points reaching each shared ancestor from this work chunk, one row per
-    // depth.  Plain stores, summed per ancestor later: thousands of work
+    // depth, and at depth lw the points reaching its own root.  Plain stores, summed per ancestor later: thousands of work
     // chunks share the top ancestors, and atomics on those few addresses
     // would serialise and stall the memory pipeline.
     if (threadIdx.x < (uint32_t)MAXD && (int)threadIdx.x >= a.d0) {   // rows above d0: the global pass
         const int d = threadIdx.x;
-        a.alive[(uint64_t)d * a.num_wc + w] = d < lw ? alive_at[d] : 0u;
+        a.alive[(uint64_t)d * a.num_wc + w] = d <= lw ? alive_at[d] : 0u;
     }
     it.store(a, base);
     __syncthreads();
@@ -1838,7 +1839,7 @@ __global__ __launch_bounds__(BLOCK) void k_subsample_fast(WcArgs a, int cls)
         __syncthreads();
         if (threadIdx.x < (uint32_t)MAXD && (int)threadIdx.x >= a.d0) {   // rows above d0: the global pass
             const int d = threadIdx.x;
-            a.alive[(uint64_t)d * a.num_wc + w] = d < lw ? alive_at[d] : 0u;
+            a.alive[(uint64_t)d * a.num_wc + w] = d < lw ? alive_at[d] : d == lw ? A : 0u;
         }
         if (threadIdx.x == 0 && A > 0) {
             a.kd[(uint64_t)w * MAXD + lw] = 1;
@@ -1992,102 +1993,677 @@ __global__ void k_node_counts(WcArgs a, uint32_t *owned)
     }
 }
 
-// Node id of every point, written at its original index.  Flat over
-// work-chunk positions in tiles; the blocks of XCD x (blocks are dispatched
-// to the 8 XCDs round robin) take the x-th eighth of the tiles in order, so
-// the scattered writes of one XCD come from one region of space, and points
-// close in space tend to be close in input order: the partial lines merge in
-// that XCD's L2 before they reach HBM.
-constexpr int NI_BLOCK = 256;
-constexpr int NI_ITEMS = 8;
-constexpr uint32_t NI_TILE = NI_BLOCK * NI_ITEMS;
-constexpr uint32_t NI_MAXWC = 32;   // work chunks of a tile with cached ancestor ids
+// ---- node_points: the points of every node in ascending original index ------------------------
+//
+// A point's node is fixed by its final depth t: a shared ancestor above its
+// work chunk when t < lw, else one of the work chunk's own nodes (rank fr
+// among those of depth t).  The points of work chunk w in the shared node of
+// depth d form one piece; the depth-major exclusive scan S of the piece sizes
+// gives every shared node's size (a difference of S over its work chunks,
+// which are consecutive) and every piece's offset inside its node.  Own nodes
+// are counted directly.  With the node begins (scan of the node sizes in node
+// order) every point is put inside its node's range, in no particular order,
+// and each node's range is then sorted by original index: an LDS radix sort
+// per tile (tiles sized to the node), merge rounds for nodes above one tile.
 
-__device__ __forceinline__ uint32_t shared_node_id(const WcArgs &a, const uint32_t *node_base, uint32_t w, int d)
+constexpr int NP_BLOCK = 256;
+constexpr int NP_ITEMS = 16;          // positions per thread and step (one step covers a work chunk)
+constexpr uint32_t NP_LCAP = 4096;    // own nodes of a work chunk counted in LDS
+constexpr uint32_t NP_GROUP = 32;     // consecutive small nodes sorted as one tile
+constexpr uint32_t NP_GROUP_FLAG = 0x80000000u;
+constexpr uint32_t NP_NONE = 0xffffffffu;
+
+__device__ __forceinline__ int np_final_depth(int t, int lw, int cut) { return (cut < lw && t >= cut) ? cut : t; }
+
+// One LDS atomic per distinct key of the wave: adds the number of active
+// lanes holding each key to cnt[key]; with RANK, returns the count before the
+// lane's own one (lanes of a key in lane order).
+template <bool RANK>
+__device__ __forceinline__ uint32_t wave_lds_count(uint32_t *cnt, uint32_t key, bool active)
 {
-    return node_base[(uint64_t)d * a.num_wc + owner_of(a, w, d)];
+    uint64_t todo = __ballot(active);
+    uint32_t r = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
+        const uint64_t m = __ballot(active && key == k);
+        if constexpr (RANK) {
+            uint32_t b = 0;
+            if ((int)lane_id() == leader) b = atomicAdd(&cnt[k], (uint32_t)__popcll(m));
+            b = (uint32_t)__builtin_amdgcn_readlane((int)b, leader);
+            if (active && key == k) r = b + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
+        } else {
+            if ((int)lane_id() == leader) atomicAdd(&cnt[k], (uint32_t)__popcll(m));
+        }
+        todo &= ~m;
+    }
+    return r;
 }
 
-__global__ __launch_bounds__(NI_BLOCK) void k_node_ids(WcArgs a, const uint32_t *node_base, uint32_t *nid_orig,
-                                                        uint32_t *err, uint64_t n)
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
 {
-    __shared__ uint32_t own[NI_MAXWC][MAXD];
-    __shared__ uint32_t s_begin[NI_MAXWC + 1];
-    __shared__ uint32_t s_w0, s_nw;
-    const uint32_t tiles = (uint32_t)((n + NI_TILE - 1) / NI_TILE);
-    const uint32_t xcd = blockIdx.x & 7u, per = gridDim.x >> 3;
-    const uint32_t t_lo = (uint32_t)((uint64_t)tiles * xcd / 8), t_hi = (uint32_t)((uint64_t)tiles * (xcd + 1) / 8);
-    for (uint32_t tile = t_lo + (blockIdx.x >> 3); tile < t_hi; tile += per) {
-        const uint32_t p0 = tile * NI_TILE;
-        const uint32_t p1 = (uint64_t)p0 + NI_TILE < n ? p0 + NI_TILE : (uint32_t)n;
-        if (threadIdx.x == 0) {
-            uint32_t lo = 0, hi = a.num_wc;   // last work chunk with begin <= p0
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (a.wc_begin[mid] <= p0) lo = mid; else hi = mid;
-            }
-            uint32_t k = 0;
-            while (k < NI_MAXWC && lo + k < a.num_wc && a.wc_begin[lo + k] < p1) {
-                s_begin[k] = a.wc_begin[lo + k];
-                ++k;
-            }
-            // more work chunks than cached: s_begin[NI_MAXWC] is the first
-            // uncached one, and points from there on are looked up one by one
-            const bool more = lo + k < a.num_wc && a.wc_begin[lo + k] < p1;
-            s_begin[k] = more ? a.wc_begin[lo + k] : 0xffffffffu;
-            s_w0 = lo;
-            s_nw = more ? 0xffffffffu : k;
-        }
-        __syncthreads();
-        const uint32_t w0 = s_w0, nw = s_nw;
-        const uint32_t ncache = nw == 0xffffffffu ? NI_MAXWC : nw;
-        for (uint32_t idx = threadIdx.x; idx < ncache * MAXD; idx += NI_BLOCK) {
-            const uint32_t k = idx / MAXD;
-            const int d = (int)(idx % MAXD);
-            const uint32_t w = w0 + k;
-            if (d < (int)a.wc_level[w] && d <= (int)a.cut[w]) own[k][d] = shared_node_id(a, node_base, w, d);
-        }
-        __syncthreads();
 #pragma unroll
-        for (int j = 0; j < NI_ITEMS; ++j) {
-            const uint32_t q = p0 + j * NI_BLOCK + threadIdx.x;
-            if (q >= p1) continue;
-            // the point's work chunk: the last cached begin <= q
-            uint32_t k = 0;
-            if (ncache > 1) {
-                uint32_t lo = 0, hi = ncache;
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (s_begin[mid] <= q) lo = mid; else hi = mid;
-                }
-                k = lo;
-            }
-            uint32_t w = w0 + k;
-            bool cached = true;
-            if (nw == 0xffffffffu && k == NI_MAXWC - 1 && s_begin[NI_MAXWC] <= q) {
-                uint32_t lo = w, hi = a.num_wc;
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (a.wc_begin[mid] <= q) lo = mid; else hi = mid;
-                }
-                w = lo;
-                cached = false;
-            }
-            int t = a.t[q];
-            const uint32_t dst = a.wc_orig[q];
-            if (t >= MAXD) {   // never placed: an internal error, reported to the host
-                atomicOr(err, 1u);
-                nid_orig[dst] = 0;
-                continue;
-            }
-            const int lw = a.wc_level[w];
-            const int cut = a.cut[w];
-            if (cut < lw && t >= cut) t = cut;
-            uint32_t id;
-            if (t < lw) id = cached ? own[k][t] : shared_node_id(a, node_base, w, t);
-            else id = node_base[(uint64_t)t * a.num_wc + w] + a.fr[q];
-            nid_orig[dst] = id;
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o, 64));
+    return v;
+}
+
+// The own nodes of a work chunk, per depth: how many (kd), the slot of the
+// first one among all its own nodes (loff) and its node id (first).
+struct NpOwn {
+    uint32_t kd[MAXD], loff[MAXD], first[MAXD];
+    __device__ void load(const WcArgs &a, const uint32_t *node_base, uint32_t w, int lw, int cut)
+    {
+        if (threadIdx.x < (uint32_t)MAXD) {
+            const int d = threadIdx.x;
+            const bool own = cut == lw && d >= lw;
+            kd[d] = own ? a.kd[(uint64_t)w * MAXD + d] : 0u;
+            loff[d] = own ? a.loff[(uint64_t)w * MAXD + d] : 0u;
+            first[d] = own ? node_base[(uint64_t)d * a.num_wc + w] : 0u;
         }
+    }
+    __device__ uint32_t total(int lw) const
+    {
+        uint32_t t = 0;
+        for (int d = lw; d < MAXD; ++d)
+            if (kd[d]) t = loff[d] + kd[d];
+        return t;
+    }
+    __device__ uint32_t id_of_slot(uint32_t slot, int lw) const
+    {
+        int d = lw;
+        while (d < MAXD - 1 && !(kd[d] && slot < loff[d] + kd[d])) ++d;
+        return first[d] + slot - loff[d];
+    }
+};
+
+// The LDS key of an own-node point (its slot among the work chunk's own
+// nodes), NP_NONE when beyond the LDS counters; gid = the node id.
+__device__ __forceinline__ uint32_t np_own_key(const NpOwn &own, int t, uint32_t f, uint32_t &gid)
+{
+    gid = own.first[t] + f;
+    const uint32_t slot = own.loff[t] + f;
+    return slot < NP_LCAP ? slot : NP_NONE;
+}
+
+// Piece sizes from the reaching counts of the work chunks (their scan, taken
+// before k_decide replaced rows): at a shared depth d above its cut a work
+// chunk leaves a(d) - a(d+1) of its points (row lw: those reaching its own
+// root), at the cut all a(cut).
+__global__ void k_np_pieces(WcArgs a, uint32_t *cnt_dw)
+{
+    const uint32_t W = a.num_wc;
+    const uint64_t total = (uint64_t)MAXD * W;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const int d = (int)(i / W);
+        const uint32_t w = (uint32_t)(i % W);
+        const int lw = a.wc_level[w], cut = a.cut[w];
+        uint32_t v = 0;
+        if (d < lw && d <= cut) {
+            v = a.alive_scan[i + 1] - a.alive_scan[i];
+            if (d < cut) v -= a.alive_scan[i + W + 1] - a.alive_scan[i + W];
+        }
+        cnt_dw[i] = v;
+    }
+}
+
+// Per (depth d, work chunk w): the node holding w's points of depth d when
+// one offset places them (pnode, NP_NONE otherwise) and that offset (poff):
+// a piece of a shared node (d < lw), or w's own root when it is its only own
+// node (d = lw).  Sizes: of each shared node at its first work chunk (a
+// difference of S over its work chunks, found by binary search on their first
+// cells), of such roots (the points reaching them).  Work chunks with own
+// nodes below their root are listed for k_np_count.
+__global__ void k_np_shared(WcArgs a, const uint32_t *node_base, const uint32_t *S, uint32_t *cnt_node,
+                            uint32_t *pnode, uint32_t *poff, uint32_t *glist, uint32_t *gcount, uint32_t *maxc)
+{
+    const uint32_t W = a.num_wc;
+    const uint64_t total = (uint64_t)MAXD * W;
+    uint32_t mymax = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const int d = (int)(i / W);
+        const uint32_t w = (uint32_t)(i % W);
+        const int lw = a.wc_level[w], cut = a.cut[w];
+        uint32_t node = NP_NONE, off = 0;
+        if (d < lw && d <= cut) {
+            const uint64_t wkey = a.wc_key[w];
+            bool first = true;
+            if (w > 0) {
+                const int lp = a.wc_level[w - 1];
+                if (lp > d && (a.wc_key[w - 1] >> (3 * (lp - d))) == (wkey >> (3 * (lw - d)))) first = false;
+            }
+            if (first && (d < cut || a.alive[i] > 0)) {
+                const int sh = 3 * (a.lam_w - d);
+                const uint64_t node_start = (wkey >> (3 * (lw - d))) << sh;
+                const uint32_t we = wc_lower_bound(a.wc_start, w + 1, W, node_start + (1ull << sh));
+                const uint32_t c = S[(uint64_t)d * W + we] - S[i];
+                cnt_node[node_base[i]] = c;
+                mymax = max(mymax, c);
+            }
+            if (S[i + 1] > S[i]) {
+                const uint32_t o = first ? w : owner_of(a, w, d);
+                node = node_base[(uint64_t)d * W + o];
+                off = S[i] - S[(uint64_t)d * W + o];
+            }
+        } else if (d == lw && cut == lw) {
+            const uint32_t reach = a.alive_scan[i + 1] - a.alive_scan[i];
+            if (reach > 0) {
+                if (a.kd[(uint64_t)w * MAXD + lw + 1] == 0) {   // a leaf root, or every point kept there
+                    node = node_base[i];
+                    cnt_node[node] = reach;
+                    mymax = max(mymax, reach);
+                } else {
+                    glist[atomicAdd(gcount, 1u)] = w;
+                }
+            }
+        }
+        pnode[i] = node;
+        poff[i] = off;
+    }
+    mymax = wave_max(mymax);
+    if (lane_id() == 0 && mymax) atomicMax(maxc, mymax);
+}
+
+// Per listed work chunk (one block each): the size of each of its own nodes
+// into cnt_node[id].
+__global__ __launch_bounds__(NP_BLOCK) void k_np_count(WcArgs a, const uint32_t *node_base, const uint32_t *glist,
+                                                       const uint32_t *gcount, uint32_t *cnt_node, uint32_t *maxc)
+{
+    __shared__ uint32_t cnt[NP_LCAP];
+    __shared__ NpOwn own;
+    const uint32_t G = *gcount;
+    uint32_t mymax = 0;
+    for (uint32_t gi = blockIdx.x; gi < G; gi += gridDim.x) {
+        const uint32_t w = glist[gi];
+        const int lw = a.wc_level[w], cut = a.cut[w];
+        const uint32_t base = a.wc_begin[w], n = a.wc_count[w];
+        own.load(a, node_base, w, lw, cut);
+        __syncthreads();
+        const uint32_t nown = own.total(lw), nl = nown < NP_LCAP ? nown : NP_LCAP;
+        for (uint32_t i = threadIdx.x; i < nl; i += NP_BLOCK) cnt[i] = 0;
+        // own nodes beyond the LDS counters count in global memory
+        for (uint32_t i = NP_LCAP + threadIdx.x; i < nown; i += NP_BLOCK) cnt_node[own.id_of_slot(i, lw)] = 0;
+        __syncthreads();
+        for (uint32_t c0 = 0; c0 < n; c0 += NP_BLOCK * NP_ITEMS) {
+            uint32_t t8[NP_ITEMS], f[NP_ITEMS];
+#pragma unroll
+            for (int j = 0; j < NP_ITEMS; ++j) {
+                const uint32_t p = c0 + j * NP_BLOCK + threadIdx.x;
+                t8[j] = p < n ? a.t[base + p] : (uint32_t)MAXD;
+                f[j] = p < n ? a.fr[base + p] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < NP_ITEMS; ++j) {
+                const int t = (int)t8[j];
+                const bool mine = t < MAXD && t >= lw;   // the cut is lw here
+                uint32_t gid = 0;
+                const uint32_t key = mine ? np_own_key(own, t, f[j], gid) : 0u;
+                wave_lds_count<false>(cnt, key, mine && key != NP_NONE);
+                if (mine && key == NP_NONE) atomicAdd(&cnt_node[gid], 1u);
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < nl; i += NP_BLOCK) {
+            const uint32_t c = cnt[i];
+            cnt_node[own.id_of_slot(i, lw)] = c;
+            mymax = max(mymax, c);
+        }
+        for (uint32_t i = NP_LCAP + threadIdx.x; i < nown; i += NP_BLOCK)   // settled by the barrier above
+            mymax = max(mymax, atomicAdd(&cnt_node[own.id_of_slot(i, lw)], 0u));
+        __syncthreads();
+    }
+    mymax = wave_max(mymax);
+    if (lane_id() == 0 && mymax) atomicMax(maxc, mymax);
+}
+
+// Sort tile classes: values per tile (threads x values per thread).
+constexpr uint32_t NP_T0 = 64 * 16, NP_T1 = 256 * 16, NP_T2 = 256 * 32, NP_T3 = 512 * 32;
+constexpr uint32_t NPM_OUT = 4096;   // outputs per merge job; divides NP_T3
+
+// Work lists of the sort (one thread per node): groups of NP_GROUP
+// consecutive nodes holding at most NP_T1 points together (entry
+// g | NP_GROUP_FLAG, class 0 or 1 by size); other nodes by size into classes
+// 0..2 (entry: the node), or class 3 for longer ones (entries node << 32 |
+// part, plus merge jobs of NPM_OUT outputs, node << 32 | job, above one tile).
+// One atomic per wave and list reserves the entries.
+__global__ void k_np_lists(const uint32_t *nb, uint32_t nn, NpLists L)
+{
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t x0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); x0 < nn; x0 += stride) {
+        const uint32_t x = x0 + lane_id();
+        const bool valid = x < nn;
+        uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0, nj = 0, g = 0;
+        bool grouped = false;
+        if (valid) {
+            g = x / NP_GROUP;
+            const uint32_t gx0 = g * NP_GROUP, gx1 = min(gx0 + NP_GROUP, nn);
+            const uint32_t gt = nb[gx1] - nb[gx0];
+            const uint32_t c = nb[x + 1] - nb[x];
+            grouped = gx1 - gx0 > 1 && gt <= NP_T1;
+            if (grouped) {
+                if (x == gx0) {
+                    n0 = gt <= NP_T0 ? 1u : 0u;
+                    n1 = 1u - n0;
+                }
+            } else if (c <= NP_T0) {
+                n0 = 1;
+            } else if (c <= NP_T1) {
+                n1 = 1;
+            } else if (c <= NP_T2) {
+                n2 = 1;
+            } else {
+                n3 = (c + NP_T3 - 1) / NP_T3;
+                if (c > NP_T3) nj = (c + NPM_OUT - 1) / NPM_OUT;
+            }
+        }
+        auto reserve = [&](uint32_t v, uint32_t *counter) -> uint32_t {
+            const uint32_t inc = wave_incl_sum(v);
+            uint32_t b = 0;
+            if (lane_id() == 63 && inc) b = atomicAdd(counter, inc);
+            return (uint32_t)__builtin_amdgcn_readlane((int)b, 63) + inc - v;
+        };
+        const uint32_t o0 = reserve(n0, &L.counts[0]), o1 = reserve(n1, &L.counts[1]);
+        const uint32_t o2 = reserve(n2, &L.counts[2]), o3 = reserve(n3, &L.counts[3]);
+        const uint32_t oj = reserve(nj, &L.counts[4]);
+        const uint32_t entry = grouped ? (g | NP_GROUP_FLAG) : x;
+        if (n0) L.c0[o0] = entry;
+        if (n1) L.c1[o1] = entry;
+        if (n2) L.c2[o2] = entry;
+        for (uint32_t k = 0; k < n3; ++k) L.c3[o3 + k] = ((uint64_t)x << 32) | k;
+        for (uint32_t k = 0; k < nj; ++k) L.jobs[oj + k] = ((uint64_t)x << 32) | k;
+    }
+}
+
+// One wave per work chunk: every point into its node's range.  Where one
+// offset places a depth's points (a piece of a shared node, or the own root),
+// positions are handed out from it in registers: lane d holds depth d's next
+// position, and each distinct depth of a row of 64 points is one ballot.
+// Points of own nodes below a subdivided root take theirs from global fill
+// counters (zeroed before).
+constexpr int NPP_ITEMS = 16;
+constexpr int NPP_WAVES = 4;
+
+__global__ __launch_bounds__(64 * NPP_WAVES) void k_np_place(WcArgs a, const uint32_t *node_base, const uint32_t *pnode,
+                                                             const uint32_t *poff, const uint32_t *nb, uint32_t *fill,
+                                                             uint32_t *out, uint32_t n_total, uint32_t *err)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint32_t W = a.num_wc;
+    for (uint32_t w = blockIdx.x * NPP_WAVES + (threadIdx.x >> 6); w < W; w += gridDim.x * NPP_WAVES) {
+        const int lw = a.wc_level[w], cut = a.cut[w];
+        const uint32_t base = a.wc_begin[w], n = a.wc_count[w];
+        uint32_t next = NP_NONE;   // lane d < MAXD: next position of depth d
+        if (lane < (uint32_t)MAXD) {
+            const uint64_t i = (uint64_t)lane * W + w;
+            const uint32_t node = pnode[i];
+            if (node != NP_NONE) next = nb[node] + poff[i];
+        }
+        // own nodes below a subdivided root (their points find no offset)
+        const bool general = cut == lw && (uint32_t)__builtin_amdgcn_readlane((int)next, lw) == NP_NONE;
+        bool bad = false;
+        for (uint32_t c0 = 0; c0 < n; c0 += 64 * NPP_ITEMS) {
+            uint32_t t8[NPP_ITEMS], o[NPP_ITEMS];
+#pragma unroll
+            for (int j = 0; j < NPP_ITEMS; ++j) {
+                const uint32_t p = c0 + j * 64 + lane;
+                t8[j] = p < n ? a.t[base + p] : 0xffu;
+                o[j] = p < n ? a.wc_orig[base + p] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < NPP_ITEMS; ++j) {
+                const uint32_t p = c0 + j * 64 + lane;
+                int t = (int)t8[j];
+                bad |= p < n && t >= MAXD;   // never placed: an internal error
+                const bool ok = p < n && t < MAXD;
+                t = np_final_depth(ok ? t : 0, lw, cut);
+                uint32_t dst = NP_NONE;
+                uint64_t todo = __ballot(ok);
+                while (todo) {
+                    const int leader = __ffsll((long long)todo) - 1;
+                    const int k = __builtin_amdgcn_readlane(t, leader);
+                    const uint64_t m = __ballot(ok && t == k);
+                    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)next, k);
+                    if (b != NP_NONE) {
+                        dst = (ok && t == k) ? b + (uint32_t)__popcll(m & below) : dst;
+                        next += (int)lane == k ? (uint32_t)__popcll(m) : 0u;
+                    }
+                    todo &= ~m;
+                }
+                if (general && ok && dst == NP_NONE && t >= lw) {
+                    const uint32_t id = node_base[(uint64_t)t * W + w] + a.fr[base + p];
+                    dst = nb[id] + atomicAdd(&fill[id], 1u);
+                }
+                if (dst < n_total) out[dst] = o[j];
+                else bad |= ok;
+            }
+        }
+        if (__ballot(bad) && lane == 0) atomicOr(err, 1u);
+    }
+}
+
+// Inclusive sum over the wave with DPP row shifts and row broadcasts.
+__device__ __forceinline__ uint32_t wave_incl_sum_dpp(uint32_t v)
+{
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+    return (uint32_t)x;
+}
+
+// Exclusive scan of one value per thread across the block (DPP within waves);
+// *total = sum.  lds: BLOCK / 64 + 1 words.  Ends with a barrier.
+template <int BLOCK>
+__device__ __forceinline__ uint32_t np_block_scan(uint32_t v, uint32_t *lds, uint32_t *total)
+{
+    constexpr int NW = BLOCK / 64;
+    const uint32_t inc = wave_incl_sum_dpp(v);
+    if constexpr (NW == 1) {
+        *total = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+        return inc - v;
+    } else {
+        const int w = threadIdx.x >> 6;
+        if (lane_id() == 63) lds[w] = inc;
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const uint32_t x = lds[k];
+            before += k < w ? x : 0u;
+            all += x;
+        }
+        *total = all;
+        __syncthreads();
+        return before + inc - v;
+    }
+}
+
+// LDS radix sort of the block's keys (KPT per thread, blocked: thread i holds
+// elements i * KPT ..), 5 bits per pass from bit 0 up to `bits`; stable, so
+// the passes compose.  Each thread counts its own keys per digit in 16-bit
+// halves (digit d in word d & 15, half d >> 4; words [d & 15][thread], one
+// padding word per 16), the words are scanned in that order (both halves at
+// once; the high half then adds the low total), and keys move through LDS.
+// A thread's counter words are its own outside the scan, so it clears them
+// right after reading its offsets.  The sorted keys are left in keys[]
+// (element e at e + e / KPT).  cnt must be zero on entry; it is zero on exit.
+template <int BLOCK, int KPT>
+__device__ void np_radix(uint32_t (&k)[KPT], int bits, uint32_t *keys, uint32_t *cnt, uint32_t *red)
+{
+    static_assert(BLOCK * KPT <= 65535, "16-bit counters");
+    constexpr uint32_t ROW = BLOCK + BLOCK / 16;   // counter words per digit row, padding included
+    constexpr int KSH = ilog2_c(KPT);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t col = tid + (tid >> 4);         // the thread's column
+    for (int sh = 0; sh < bits; sh += 5) {
+        // the thread's rank among its own keys of the same digit (16 bits each)
+        uint32_t loc[KPT / 2];
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+            const uint32_t d = k[j] >> sh;
+            const uint32_t h = d & 16u;
+            const uint32_t l = (atomicAdd(&cnt[(d & 15u) * ROW + col], 1u << h) >> h) & 0xffffu;
+            if (j % 2 == 0) loc[j / 2] = l;
+            else loc[j / 2] |= l << 16;
+        }
+        __syncthreads();
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) s += cnt[tid * 17 + i];
+        uint32_t tot;
+        uint32_t ex = np_block_scan<BLOCK>(s, red, &tot);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const uint32_t v = cnt[tid * 17 + i];
+            cnt[tid * 17 + i] = ex;
+            ex += v;
+        }
+        const uint32_t low_total = tot & 0xffffu;
+        __syncthreads();
+        uint32_t dst[KPT];
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+            const uint32_t d = k[j] >> sh;
+            const uint32_t h = d & 16u;
+            const uint32_t pre = cnt[(d & 15u) * ROW + col];
+            dst[j] = ((pre >> h) & 0xffffu) + (h ? low_total : 0u) + ((loc[j / 2] >> (16 * (j % 2))) & 0xffffu);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) cnt[i * ROW + col] = 0;
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) keys[dst[j] + (dst[j] >> KSH)] = k[j];
+        __syncthreads();
+        if (sh + 5 < bits) {
+#pragma unroll
+            for (int j = 0; j < KPT; ++j) k[j] = keys[tid * (KPT + 1) + j];
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t bits_for(uint32_t span) { return span ? 32u - (uint32_t)__clz(span) : 0u; }
+
+// Sorts src[r0, r0 + len) (len <= BLOCK * KPT) into dst[r0, ..): by segment
+// (nseg > 1: segment s starts at segb[s], relative) and then by value.
+template <int BLOCK, int KPT>
+__device__ void np_sort_range(const uint32_t *src, uint32_t *dst, uint32_t r0, uint32_t len, uint32_t nseg,
+                              const uint32_t *segb, uint32_t *keys, uint32_t *cnt, uint32_t *red)
+{
+    const uint32_t tid = threadIdx.x;
+#pragma unroll 4
+    for (int j = 0; j < KPT; ++j) {
+        const uint32_t e = j * BLOCK + tid;
+        keys[e + e / KPT] = e < len ? src[r0 + e] : 0u;
+    }
+    __syncthreads();
+    uint32_t k[KPT];
+    uint32_t mn = 0xffffffffu, mx = 0;
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        k[j] = keys[tid * (KPT + 1) + j];
+        if (tid * KPT + j < len) {
+            mn = min(mn, k[j]);
+            mx = max(mx, k[j]);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = min(mn, (uint32_t)__shfl_xor(mn, o, 64));
+        mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
+    }
+    if constexpr (BLOCK > 64) {
+        if (lane_id() == 0) {
+            red[2 * (tid >> 6)] = mn;
+            red[2 * (tid >> 6) + 1] = mx;
+        }
+        __syncthreads();
+        mn = 0xffffffffu;
+        mx = 0;
+        for (int w = 0; w < BLOCK / 64; ++w) {
+            mn = min(mn, red[2 * w]);
+            mx = max(mx, red[2 * w + 1]);
+        }
+        __syncthreads();
+    }
+    const uint32_t kb = bits_for(mx - mn);
+    const uint32_t kmask = kb >= 32 ? 0xffffffffu : (1u << kb) - 1u;
+    uint32_t bits = kb;
+    if (nseg > 1) {
+        // segment index above the value bits (at most 32 segments: 5 bits)
+        bits = kb + 5;
+        uint32_t e = tid * KPT, s = 0;
+#pragma unroll
+        for (int j = 0; j < KPT; ++j, ++e) {
+            while (s + 1 < nseg && segb[s + 1] <= e) ++s;
+            k[j] = e < len ? (s << kb) | (k[j] - mn) : 0xffffffffu;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) k[j] = tid * KPT + j < len ? k[j] - mn : 0xffffffffu;
+    }
+    // padding keys are all ones: every digit maximal, and they start after
+    // the real keys, so a stable sort leaves them last
+    np_radix<BLOCK, KPT>(k, (int)bits, keys, cnt, red);
+#pragma unroll 4
+    for (int j = 0; j < KPT; ++j) {
+        const uint32_t e = j * BLOCK + tid;
+        if (e < len) dst[r0 + e] = bits ? (keys[e + e / KPT] & kmask) + mn : keys[e + e / KPT];
+    }
+    __syncthreads();
+}
+
+// One tile per list entry.  Classes 0..2 (LONG = false): a group of small
+// nodes (sorted by node, then value) or one node.  Class 3 (LONG): one part of
+// NP_T3 values of a node; a node of R merge rounds leaves its sorted parts
+// where round 0 reads them: dst when R is even, alt when odd (the rounds
+// alternate, the last one writes dst).
+// waves per SIMD each tile size is compiled for (registers held to it, no spills)
+constexpr int np_sort_waves(int block, int kpt) { return block * kpt <= 4096 ? 3 : 2; }
+
+template <int BLOCK, int KPT, bool LONG>
+__global__ __launch_bounds__(BLOCK, np_sort_waves(BLOCK, KPT)) void k_np_sort(const void *list, const uint32_t *list_cnt, const uint32_t *nb,
+                                                   uint32_t nn, const uint32_t *src, uint32_t *dst, uint32_t *alt)
+{
+    constexpr uint32_t T = BLOCK * KPT;
+    __shared__ uint32_t keys[T + BLOCK];
+    __shared__ uint32_t cnt[17 * BLOCK];
+    __shared__ uint32_t red[2 * (BLOCK / 64) + 2];
+    __shared__ uint32_t segb[NP_GROUP + 1];
+    const uint32_t count = *list_cnt;
+    for (uint32_t i = threadIdx.x; i < 17 * BLOCK; i += BLOCK) cnt[i] = 0;   // the radix passes keep it zero
+    __syncthreads();
+    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        uint32_t r0, len, nseg = 0, nsub = 1;
+        uint32_t *out = dst;
+        if constexpr (LONG) {
+            const uint64_t e = static_cast<const uint64_t *>(list)[i];
+            const uint32_t x = (uint32_t)(e >> 32), part = (uint32_t)e;
+            const uint32_t b = nb[x], c = nb[x + 1] - b;
+            const uint32_t R = ceil_log2_dev((c + T - 1) / T);
+            r0 = b + part * T;
+            len = min(T, c - part * T);
+            if (R & 1u) out = alt;
+        } else {
+            const uint32_t e = static_cast<const uint32_t *>(list)[i];
+            if (e & NP_GROUP_FLAG) {
+                const uint32_t x0 = (e & ~NP_GROUP_FLAG) * NP_GROUP, x1 = min(x0 + NP_GROUP, nn);
+                nseg = x1 - x0;
+                r0 = nb[x0];
+                len = nb[x1] - r0;
+                if (threadIdx.x <= nseg) segb[threadIdx.x] = nb[x0 + threadIdx.x] - r0;
+                // the segment index fits above the values when their span
+                // needs at most 27 bits; else the nodes go one by one
+                uint32_t mn = 0xffffffffu, mx = 0;
+                for (uint32_t j = threadIdx.x; j < len; j += BLOCK) {
+                    const uint32_t v = src[r0 + j];
+                    mn = min(mn, v);
+                    mx = max(mx, v);
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    mn = min(mn, (uint32_t)__shfl_xor(mn, o, 64));
+                    mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
+                }
+                if (!__syncthreads_and(len == 0 || bits_for(mx - mn) <= 27)) {
+                    nsub = nseg;
+                    nseg = 0;
+                }
+            } else {
+                r0 = nb[e];
+                len = nb[e + 1] - r0;
+            }
+        }
+        for (uint32_t sub = 0; sub < nsub; ++sub) {
+            uint32_t rr = r0, ll = len;
+            if (nsub > 1) {
+                rr = r0 + segb[sub];
+                ll = segb[sub + 1] - segb[sub];
+            }
+            np_sort_range<BLOCK, KPT>(src, out, rr, ll, nseg, segb, keys, cnt, red);
+        }
+    }
+}
+
+// Merge path: how many of the first k outputs of merging sorted A and B
+// (distinct values) come from A.  Wave-wide: 64 probes per step.
+__device__ uint32_t merge_split_wave(const uint32_t *A, uint32_t la, const uint32_t *B, uint32_t lb, uint32_t k)
+{
+    uint32_t lo = k > lb ? k - lb : 0, hi = k < la ? k : la;
+    // P(i): A[i] < B[k - 1 - i], true exactly for i below the answer
+    while (lo < hi) {
+        const uint32_t step = (hi - lo + 63) / 64;
+        const uint32_t i = lo + lane_id() * step;
+        const bool p = i < hi && A[i] < B[k - 1 - i];
+        const uint32_t t = (uint32_t)__popcll(__ballot(p));
+        const uint32_t nlo = t == 0 ? lo : lo + (t - 1) * step + 1;
+        const uint32_t nhi = lo + t * step < hi ? lo + t * step : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    return lo;
+}
+
+// Merge round r of the long nodes: runs of NP_T3 << r sorted values, merged in
+// pairs, NPM_OUT outputs per job; nodes needing fewer rounds are done.
+constexpr int NPM_BLOCK = 256;
+constexpr int NPM_KPT = NPM_OUT / NPM_BLOCK;
+
+__global__ __launch_bounds__(NPM_BLOCK) void k_np_merge(const uint64_t *jobs, const uint32_t *njobs, const uint32_t *nb,
+                                                        int r, uint32_t *dst_final, uint32_t *alt)
+{
+    __shared__ uint32_t in[NPM_OUT];
+    __shared__ uint32_t out[NPM_OUT + NPM_OUT / NPM_KPT];
+    __shared__ uint32_t split[2];
+    const uint32_t nj = *njobs;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t q = blockIdx.x; q < nj; q += gridDim.x) {
+        const uint64_t e = jobs[q];
+        const uint32_t x = (uint32_t)(e >> 32), j = (uint32_t)e;
+        const uint32_t b = nb[x], c = nb[x + 1] - b;
+        const uint32_t R = ceil_log2_dev((c + NP_T3 - 1) / NP_T3);
+        if ((uint32_t)r >= R) continue;
+        // after k rounds a node's values sit in dst_final when R - k is even
+        const uint32_t *S = (((R - r) & 1u) == 0 ? dst_final : alt) + b;
+        uint32_t *D = (((R - r) & 1u) == 0 ? alt : dst_final) + b;
+        const uint64_t L = (uint64_t)NP_T3 << r;
+        const uint32_t o0 = j * NPM_OUT, o1 = min(o0 + NPM_OUT, c);
+        const uint32_t a0 = (uint32_t)(o0 / (2 * L) * (2 * L));
+        const uint32_t a1 = (uint32_t)min((uint64_t)a0 + L, (uint64_t)c);
+        const uint32_t b1 = (uint32_t)min((uint64_t)a0 + 2 * L, (uint64_t)c);
+        if (a1 >= b1) {   // an unpaired last run: already sorted
+            for (uint32_t i = o0 + tid; i < o1; i += NPM_BLOCK) D[i] = S[i];
+            continue;
+        }
+        const uint32_t la = a1 - a0, lb = b1 - a1, k0 = o0 - a0, k1 = o1 - a0;
+        if (tid < 128) {
+            const uint32_t s = merge_split_wave(S + a0, la, S + a1, lb, tid < 64 ? k0 : k1);
+            if (lane_id() == 0) split[tid >> 6] = s;
+        }
+        __syncthreads();
+        const uint32_t i0 = split[0], i1 = split[1];
+        const uint32_t na = i1 - i0, nbv = (k1 - i1) - (k0 - i0), tot = k1 - k0;
+        for (uint32_t i = tid; i < na; i += NPM_BLOCK) in[i] = S[a0 + i0 + i];
+        for (uint32_t i = tid; i < nbv; i += NPM_BLOCK) in[na + i] = S[a1 + (k0 - i0) + i];
+        __syncthreads();
+        const uint32_t d0 = tid * NPM_KPT;
+        if (d0 < tot) {
+            uint32_t lo = d0 > nbv ? d0 - nbv : 0, hi = d0 < na ? d0 : na;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (in[mid] < in[na + d0 - 1 - mid]) lo = mid + 1; else hi = mid;
+            }
+            uint32_t ia = lo, ib = d0 - lo;
+            for (int s = 0; s < NPM_KPT && d0 + s < tot; ++s) {
+                const bool takeA = ib >= nbv || (ia < na && in[ia] < in[na + ib]);
+                const uint32_t v = takeA ? in[ia++] : in[na + ib++];
+                const uint32_t o = d0 + s;
+                out[o + o / NPM_KPT] = v;
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < tot; i += NPM_BLOCK) D[o0 + i] = out[i + i / NPM_KPT];
         __syncthreads();
     }
 }
@@ -2186,38 +2762,6 @@ __global__ void k_node_fill(WcArgs a, const uint32_t *node_base, uint8_t *depth,
             }
         }
     }
-}
-
-// Begin and count of every node from the node-sorted keys (16-byte aligned):
-// four keys per thread and step, with the neighbours across the group edges.
-__global__ void k_node_ranges(const uint32_t *sk, uint64_t n, uint64_t *begin, uint32_t *count, uint32_t nn)
-{
-    const uint64_t n4 = (n + 3) / 4;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n4; g += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t i0 = 4 * g;
-        uint32_t k[6];
-        if (i0 + 4 <= n) {
-            const uint4 v = reinterpret_cast<const uint4 *>(sk)[g];
-            k[1] = v.x; k[2] = v.y; k[3] = v.z; k[4] = v.w;
-        } else {
-            for (int j = 0; j < 4; ++j) k[1 + j] = i0 + j < n ? sk[i0 + j] : 0u;
-        }
-        k[0] = i0 > 0 ? sk[i0 - 1] : ~k[1];
-        k[5] = i0 + 4 < n ? sk[i0 + 4] : ~k[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint64_t i = i0 + j;
-            if (i >= n) break;
-            if (k[j] != k[j + 1]) begin[k[j + 1]] = i;
-            if (i + 1 == n || k[j + 2] != k[j + 1]) count[k[j + 1]] = (uint32_t)(i + 1);   // end, fixed below
-        }
-    }
-}
-__global__ void k_node_count_fix(const uint64_t *begin, uint32_t *count, uint32_t nn)
-{
-    // count[k] currently holds the end (exclusive) of node k
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x)
-        count[k] = count[k] - (uint32_t)begin[k];
 }
 
 // ---- step 5: preview ---------------------------------------------------------------------------
@@ -2465,17 +3009,6 @@ void launch_node_counts(const WcArgs &a, uint32_t *owned, hipStream_t st)
     hipLaunchKernelGGL(k_node_counts, dim3(grid_for((uint64_t)MAXD * a.num_wc, 256)), dim3(256), 0, st, a, owned);
 }
 
-void launch_node_ids(const WcArgs &a, const uint32_t *node_base, uint32_t *nid_orig, uint32_t *err, uint64_t n,
-                     hipStream_t st)
-{
-    if (n == 0 || a.num_wc == 0) return;
-    // a multiple of 8 blocks (one eighth of the tiles per XCD)
-    uint64_t tiles = (n + NI_TILE - 1) / NI_TILE;
-    uint64_t grid = tiles < 2048 ? tiles : 2048;
-    grid = (grid + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_node_ids, dim3((uint32_t)grid), dim3(NI_BLOCK), 0, st, a, node_base, nid_orig, err, n);
-}
-
 void launch_wc_chunks(const uint32_t *num_wc_dev, uint64_t max_wc, const uint64_t *wc_key, const uint8_t *wc_level,
                       int g, const uint32_t *pyr, const uint32_t *cid_table, const uint8_t *chunk_level,
                       const uint32_t *num_chunks_dev, uint64_t max_chunks, uint32_t *wc_chunk, uint32_t *seg_b0,
@@ -2495,14 +3028,63 @@ void launch_node_fill(const WcArgs &a, const uint32_t *node_base, uint8_t *depth
                        depth, key, mask);
 }
 
-void launch_node_ranges(const uint32_t *sorted_keys, uint64_t n, uint64_t *begin, uint32_t *count, uint32_t num_nodes,
-                        hipStream_t st)
+void launch_np_counts(const WcArgs &a, const uint32_t *node_base, uint32_t *cnt_dw, uint32_t *S, uint32_t *cnt_node,
+                      uint32_t *pnode, uint32_t *glist, uint32_t *gcount, uint32_t *maxc, void *scan_temp,
+                      hipStream_t st)
 {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_node_ranges, dim3(grid_for((n + 3) / 4, 256)), dim3(256), 0, st, sorted_keys, n, begin, count,
-                       num_nodes);
-    hipLaunchKernelGGL(k_node_count_fix, dim3(grid_for(num_nodes, 256)), dim3(256), 0, st, begin, count, num_nodes);
+    if (a.num_wc == 0) return;
+    const uint64_t rows = (uint64_t)MAXD * a.num_wc;
+    hipLaunchKernelGGL(k_np_pieces, dim3(grid_for(rows, 256)), dim3(256), 0, st, a, cnt_dw);
+    scan_exclusive(cnt_dw, S, rows, S + rows, scan_temp, st);
+    // the piece offsets replace the piece sizes (scanned into S already)
+    hipLaunchKernelGGL(k_np_shared, dim3(grid_for(rows, 256)), dim3(256), 0, st, a, node_base, S, cnt_node, pnode,
+                       cnt_dw, glist, gcount, maxc);
+    hipLaunchKernelGGL(k_np_count, dim3(a.num_wc < 2048 ? a.num_wc : 2048), dim3(NP_BLOCK), 0, st, a, node_base, glist,
+                       gcount, cnt_node, maxc);
 }
+
+void launch_np_points(const WcArgs &a, const uint32_t *node_base, const uint32_t *pnode, const uint32_t *poff,
+                      const uint32_t *cnt_node, uint32_t num_nodes, uint32_t max_count, uint64_t n, const NpWork &w,
+                      hipStream_t st)
+{
+    if (n == 0 || num_nodes == 0) return;
+    scan_exclusive(cnt_node, w.nb, num_nodes, w.nb + num_nodes, w.scan_temp, st);
+    hipLaunchKernelGGL(k_np_lists, dim3(grid_for(num_nodes, 256, 1024)), dim3(256), 0, st, w.nb, num_nodes, w.lists);
+    if (w.general) launch_fill_u32(w.fill, 0u, num_nodes, st);
+    if (w.timer) w.timer->begin(st);
+    const uint32_t pg = (a.num_wc + NPP_WAVES - 1) / NPP_WAVES;
+    hipLaunchKernelGGL(k_np_place, dim3(pg < 4096 ? pg : 4096), dim3(64 * NPP_WAVES), 0, st, a, node_base, pnode, poff,
+                       w.nb, w.fill, w.tmp, (uint32_t)n, w.err);
+    const uint32_t g0 = num_nodes < 8192 ? num_nodes : 8192;
+    const uint64_t n1 = n / 1024 + num_nodes / NP_GROUP + 1, n2 = n / 4096 + 1, n3 = n / 8192 + n / NP_T3 + 1;
+    hipLaunchKernelGGL((k_np_sort<64, 16, false>), dim3(g0), dim3(64), 0, st, w.lists.c0, w.lists.counts, w.nb,
+                       num_nodes, w.tmp, w.out, w.tmp);
+    hipLaunchKernelGGL((k_np_sort<256, 16, false>), dim3(n1 < 4096 ? (uint32_t)n1 : 4096), dim3(256), 0, st, w.lists.c1,
+                       w.lists.counts + 1, w.nb, num_nodes, w.tmp, w.out, w.tmp);
+    hipLaunchKernelGGL((k_np_sort<256, 32, false>), dim3(n2 < 2048 ? (uint32_t)n2 : 2048), dim3(256), 0, st, w.lists.c2,
+                       w.lists.counts + 2, w.nb, num_nodes, w.tmp, w.out, w.tmp);
+    hipLaunchKernelGGL((k_np_sort<512, 32, true>), dim3(n3 < 1024 ? (uint32_t)n3 : 1024), dim3(512), 0, st, w.lists.c3,
+                       w.lists.counts + 3, w.nb, num_nodes, w.tmp, w.out, w.tmp);
+    const uint32_t rounds = ceil_log2((max_count + NP_T3 - 1) / NP_T3);
+    const uint64_t njobs = np_job_entries(n);
+    for (uint32_t r = 0; r < rounds; ++r)
+        hipLaunchKernelGGL(k_np_merge, dim3(njobs < 4096 ? (uint32_t)njobs : 4096), dim3(NPM_BLOCK), 0, st,
+                           w.lists.jobs, w.lists.counts + 4, w.nb, (int)r, w.out, w.tmp);
+    if (w.timer) w.timer->end(st);
+}
+
+uint64_t np_list_entries(uint64_t n, int cls)
+{
+    // nodes number at most n; class 1 holds nodes above NP_T0 values and
+    // groups, class 2 nodes above NP_T1, class 3 parts of nodes above NP_T2
+    switch (cls) {
+    case 0: return n + 1;
+    case 1: return n / NP_T0 + n / NP_GROUP + 2;
+    case 2: return n / NP_T1 + 1;
+    default: return n / NP_T2 + n / NP_T3 + 2;
+    }
+}
+uint64_t np_job_entries(uint64_t n) { return n / NPM_OUT + n / NP_T3 + 2; }
 
 static uint64_t preview_tiles(uint64_t n) { return (n + PV_TILE - 1) / PV_TILE; }
 

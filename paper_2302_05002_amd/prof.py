@@ -4,7 +4,7 @@
         per-kernel device time per build (from a --kernel-trace --stats run)
     python3 -m paper_2302_05002_amd.prof pmc    <counter_collection.csv> <counter>
         per-build sum of one counter for each timed kernel group
-    python3 -m paper_2302_05002_amd.prof traffic <fetch.csv> <write.csv> <workload> <out.json> [chunk_passes node_passes]
+    python3 -m paper_2302_05002_amd.prof traffic <fetch.csv> <write.csv> <workload> <out.json> [chunk_passes]
         FETCH_SIZE and WRITE_SIZE per build of every timed kernel group, with
         the digest of the HIP sources they were taken on, merged into out.json
 
@@ -70,7 +70,7 @@ def _dispatches(path: str, counter: str):
     return [(d, names[d], acc[d]) for d in sorted(acc)]
 
 
-def groups_per_build(path: str, counter: str, chunk_passes: int = 1, node_passes: int = 2):
+def groups_per_build(path: str, counter: str, chunk_passes: int = 1):
     """Per build, the counter summed over each timed kernel group (averaged over builds)."""
     seq = _dispatches(path, counter)
     starts = [i for i, (_, k, _) in enumerate(seq) if "k_bbox" in k]
@@ -81,8 +81,8 @@ def groups_per_build(path: str, counter: str, chunk_passes: int = 1, node_passes
         # the build's preview kernels come before its bounding box
         b = seq[s0:s1]
         nb += 1
-        after_quant = after_ids = False
-        chunk_left, node_left = chunk_passes, node_passes
+        after_quant = in_counts = False
+        chunk_left = chunk_passes
         for _, k, v in b:
             if "k_bbox" in k:
                 sums["bbox"] += v
@@ -91,23 +91,26 @@ def groups_per_build(path: str, counter: str, chunk_passes: int = 1, node_passes
                 after_quant = True
             elif "k_subsample" in k or "k_list_classes" in k:
                 sums["subsample"] += v
-            elif "k_node_ids" in k:
-                sums["node_ids"] += v
-                after_ids = True
+            elif "k_np_count" in k:
+                sums["node_counts"] += v
+                in_counts = True
+            elif "k_np_shared" in k:
+                sums["node_counts"] += v
+                in_counts = False
+            elif in_counts and "k_scan" in k:
+                sums["node_counts"] += v
+            elif "k_np_place" in k or "k_np_sort" in k or "k_np_merge" in k:
+                sums["node_points"] += v
             elif "k_ms_scatter<false" in k:
-                if after_ids and node_left > 0:
-                    sums["node_points"] += v
-                    node_left -= 1
-                elif after_quant and chunk_left > 0 and not after_ids:
+                if after_quant and chunk_left > 0:
                     sums["chunk_scatter"] += v
                     chunk_left -= 1
     return {k: v / nb for k, v in sums.items()}, nb
 
 
-def traffic(fetch_csv: str, write_csv: str, workload: str, out_json: str, chunk_passes: int = 1,
-            node_passes: int = 2):
-    f, nf = groups_per_build(fetch_csv, "FETCH_SIZE", chunk_passes, node_passes)
-    w, nw = groups_per_build(write_csv, "WRITE_SIZE", chunk_passes, node_passes)
+def traffic(fetch_csv: str, write_csv: str, workload: str, out_json: str, chunk_passes: int = 1):
+    f, nf = groups_per_build(fetch_csv, "FETCH_SIZE", chunk_passes)
+    w, nw = groups_per_build(write_csv, "WRITE_SIZE", chunk_passes)
     data = {"read_factor": READ_FACTOR, "write_factor": WRITE_FACTOR, "unit": "KiB per build", "kernels": {}}
     if os.path.exists(out_json):
         with open(out_json) as fh:
@@ -130,7 +133,7 @@ def main(argv):
         for k, v in sorted(g.items()):
             print(f"  {k:14s} {v:14.1f}")
     elif argv[0] == "traffic":
-        extra = [int(a) for a in argv[5:7]]
+        extra = [int(a) for a in argv[5:6]]
         d = traffic(argv[1], argv[2], argv[3], argv[4], *extra)
         for k, v in sorted(d["kernels"].items()):
             hbm = (v["fetch_kib"] * d["read_factor"] + v["write_kib"] * d["write_factor"]) / 1024
