@@ -43,8 +43,9 @@ KERNEL_BYTES = {
     "quantize": (lambda n, G, M: 12 * n + 4 * G ** 3, "read x, y, z again: 12 B/pt; write the count grid: 4 B/cell"),
     "chunk_scatter": (lambda n, G, M: 16 * n, "re-read the points 12 B/pt, write perm 4 B/pt"),
     "subsample": (lambda n, G, M: 16 * n, "read perm 4 B/pt, gather the coordinates once 12 B/pt"),
-    "node_counts": (lambda n, G, M: 5 * n, "read each point's depth 1 B and own-node rank 4 B"),
-    "node_points": (lambda n, G, M: 8 * n, "read the original indices in work-chunk order 4 B/pt, write node_points 4 B/pt"),
+    "node_counts": (None, "rows per (depth, work chunk), not per point"),
+    "node_place": (lambda n, G, M: 9 * n, "read each point's depth 1 B and original index 4 B, write it 4 B"),
+    "node_sort": (lambda n, G, M: 8 * n, "read and write every node's points once: 8 B/pt"),
 }
 
 KERNEL_NAMES = {
@@ -52,8 +53,9 @@ KERNEL_NAMES = {
     "quantize": "fpo::k_quantize",
     "chunk_scatter": "fpo::k_ms_scatter<false, 8> (split into chunks)",
     "subsample": "fpo::k_subsample_* (all size classes)",
-    "node_counts": "fpo::k_np_count + scan + fpo::k_np_shared",
-    "node_points": "fpo::k_np_place + fpo::k_np_sort + fpo::k_np_merge",
+    "node_counts": "fpo::k_np_pieces + scan + fpo::k_np_shared + fpo::k_np_count",
+    "node_place": "fpo::k_np_place",
+    "node_sort": "fpo::k_np_sort (four tile sizes) + fpo::k_np_merge",
 }
 
 
@@ -515,11 +517,12 @@ def main():
     dom = max(timers, key=lambda k: timers[k][0])
     dom_ms = timers[dom][0] / args.steps
     dom_launches = timers[dom][1] / args.steps
-    dom_bytes = KERNEL_BYTES[dom][0](n, p.count_grid, p.preview_modulus)
-    achieved = dom_bytes / (dom_ms / 1000.0) / 1e9
+    fn = KERNEL_BYTES[dom][0]
+    dom_bytes = fn(n, p.count_grid, p.preview_modulus) if fn else None
+    achieved = dom_bytes / (dom_ms / 1000.0) / 1e9 if dom_bytes else None
     traffic = measured_traffic(dom, args.workload)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
                 "kernel": KERNEL_NAMES[dom], "algorithmic_bytes": dom_bytes, "bytes_rule": KERNEL_BYTES[dom][1],
                 "ms_per_build": dom_ms, "launches_per_build": dom_launches,
                 "kernels_ms_per_build": {k: v[0] / args.steps for k, v in timers.items()}}

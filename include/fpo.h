@@ -314,10 +314,11 @@ typedef enum {
     FPO_TIMER_QUANTIZE = 1,      /* quantise + count, one launch (step 1) */
     FPO_TIMER_CHUNK_SCATTER = 2, /* scatter kernel of the stable split into chunks, one per digit pass (step 3) */
     FPO_TIMER_SUBSAMPLE = 3,     /* per-work-chunk subsample kernels, every size class, bracketed together (step 4) */
-    FPO_TIMER_NODE_COUNTS = 4,   /* points per node: per-work-chunk counts, their scan, shared-node sums (step 4) */
-    FPO_TIMER_NODE_POINTS = 5,   /* node_points: placement, per-node sorts and merges, bracketed together (step 4) */
+    FPO_TIMER_NODE_COUNTS = 4,   /* points per node: piece sizes, their scan, node sizes, bracketed together (step 4) */
+    FPO_TIMER_NODE_PLACE = 5,    /* every point into its node's range, one launch (step 4) */
     FPO_TIMER_PREVIEW = 6,       /* preview kernels (grid minimum, count, scan, write), bracketed together (step 5) */
-    FPO_TIMER_COUNT = 7
+    FPO_TIMER_NODE_SORT = 7,     /* node ranges sorted by original index: tile sorts and merge rounds (step 4) */
+    FPO_TIMER_COUNT = 8
 } fpo_timer;
 
 /* enable: 1 to time later submits of ctx, 0 to stop. */

@@ -36,7 +36,8 @@ EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_w
            "fpo_select_workspace_size", "fpo_select_nodes")
 
 # fpo_timer values (include/fpo.h)
-TIMERS = {"bbox": 0, "quantize": 1, "chunk_scatter": 2, "subsample": 3, "node_counts": 4, "node_points": 5, "preview": 6}
+TIMERS = {"bbox": 0, "quantize": 1, "chunk_scatter": 2, "subsample": 3, "node_counts": 4, "node_place": 5,
+          "preview": 6, "node_sort": 7}
 
 
 class FpoError(RuntimeError):

@@ -114,6 +114,14 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     const uint64_t nn = n ? n : 1;
     P.maxC = nn < P.G3 ? nn : P.G3;
     P.maxW = nn < P.W3 ? nn : P.W3;
+    {
+        // a work chunk deeper than level d0 has a parent with more than
+        // WC_CAP points; such parents are disjoint within a level and have at most
+        // eight children each, and level d0 holds at most 8^d0 work chunks
+        const uint64_t heavy = nn / (WC_CAP + 1);
+        const uint64_t bound = (1ull << (3 * P.d0)) + 8ull * (uint64_t)(P.lam_w - P.d0) * heavy;
+        if (bound < P.maxW) P.maxW = bound;
+    }
     P.pv_ntiles = bits_tiles(nn);
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -572,7 +580,8 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     // ---- step 1: bbox, quantise, count ----
     const int given = (p->flags & FPO_BBOX_GIVEN) ? 1 : 0;
     JobTimer t_bbox(job, FPO_TIMER_BBOX), t_quant(job, FPO_TIMER_QUANTIZE), t_chunk(job, FPO_TIMER_CHUNK_SCATTER),
-        t_sub(job, FPO_TIMER_SUBSAMPLE), t_ncnt(job, FPO_TIMER_NODE_COUNTS), t_npts(job, FPO_TIMER_NODE_POINTS);
+        t_sub(job, FPO_TIMER_SUBSAMPLE), t_ncnt(job, FPO_TIMER_NODE_COUNTS), t_place(job, FPO_TIMER_NODE_PLACE),
+        t_nsort(job, FPO_TIMER_NODE_SORT);
     const float *X = cloud->x, *Y = cloud->y, *Z = cloud->z;
     if (host_in) {
         // pinned host input: batches copied into the workspace on the copy
@@ -654,11 +663,11 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     launch_cut_flags(pyr, g, p->max_points_per_chunk, U32(P.fc), U8(P.lc), 0, st);
     scan_exclusive(U32(P.fc), U32(P.ec), P.G3, &ctrs->num_chunks, stemp, st);
     launch_cut_table(pyr, g, U32(P.fc), U32(P.ec), U8(P.lc), U8(P.c_level), U64(P.c_key), U32(P.c_count), nullptr,
-                     p->max_points_per_chunk, &ctrs->oversized, st);
+                     p->max_points_per_chunk, &ctrs->oversized, P.maxC, &ctrs->internal_error, st);
     launch_cut_flags(pyr, P.lam_w, WC_CAP, U32(P.fw), U8(P.lw_), P.d0, st);
     scan_exclusive(U32(P.fw), U32(P.ew), P.W3, &ctrs->num_wc, stemp, st);
     launch_cut_table(pyr, P.lam_w, U32(P.fw), U32(P.ew), U8(P.lw_), U8(P.w_level), U64(P.w_key), U32(P.w_count),
-                     U64(P.w_start), WC_CAP, nullptr, st);
+                     U64(P.w_start), WC_CAP, nullptr, P.maxW, &ctrs->internal_error, st);
     // cell -> chunk id and cell -> work-chunk id tables (in place of the scans)
     launch_cell_ids(U32(P.fc), U32(P.ec), P.G3, st);
     launch_cell_ids(U32(P.fw), U32(P.ew), P.W3, st);
@@ -671,6 +680,8 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         return end_job(fail(FPO_ERR_NONFINITE, "a coordinate is NaN or infinite"));
     }
     const uint32_t num_chunks = hctrs->num_chunks, num_wc = hctrs->num_wc;
+    if (hctrs->internal_error || num_wc > P.maxW || num_chunks > P.maxC)
+        return end_job(fail(FPO_ERR_DEVICE, "internal: %u chunks, %u work chunks exceed the plan", num_chunks, num_wc));
 
     // chunk begins (u64) and work-chunk begins
     scan_exclusive(U32(P.c_count), U32(P.c_count_scan), num_chunks, nullptr, stemp, st);
@@ -794,7 +805,8 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         w.lists.jobs = U64(P.np_jobs);
         w.lists.counts = ctrs->np_lists;
         w.scan_temp = stemp;
-        w.timer = &t_npts;
+        w.place_timer = &t_place;
+        w.sort_timer = &t_nsort;
         launch_np_points(A, U32(P.node_base), U32(P.owned), U32(P.np_cnt), U32(P.n_count), num_nodes, hctrs->np_max, n,
                          w, st);
     }

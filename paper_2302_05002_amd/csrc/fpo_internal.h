@@ -81,9 +81,12 @@ void launch_pyramid(uint32_t *pyr, int g, hipStream_t st);
 void launch_grid_export(const uint32_t *fine_morton, int g, uint32_t *rowmajor, hipStream_t st);
 void launch_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev, int lmin,
                       hipStream_t st);
+// Table of the cut (entries at excl[m] for flagged cells m); entries at or
+// beyond max_out are not written and set *cap_flag.
 void launch_cut_table(const uint32_t *pyr, int lam, const uint32_t *flags, const uint32_t *excl,
                       const uint8_t *lev, uint8_t *t_level, uint64_t *t_key, uint32_t *t_count,
-                      uint64_t *t_start, uint32_t thresh, uint32_t *over_flag, hipStream_t st);
+                      uint64_t *t_start, uint32_t thresh, uint32_t *over_flag, uint64_t max_out,
+                      uint32_t *cap_flag, hipStream_t st);
 void launch_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t st);
 // Device-wide exclusive scan of n u32 values; *total (device) gets the sum.
 size_t scan_temp_bytes(uint64_t n);
@@ -215,7 +218,7 @@ struct NpWork {
     uint32_t *out;        // n: node_points
     NpLists lists;
     void *scan_temp;
-    LaunchTimer *timer;   // brackets placement, sorts and merges
+    LaunchTimer *place_timer, *sort_timer;   // the placement; the sorts and merges
 };
 // Then the points of every node in ascending original index, at the begins nb.
 void launch_np_points(const WcArgs &a, const uint32_t *node_base, const uint32_t *pnode, const uint32_t *poff,

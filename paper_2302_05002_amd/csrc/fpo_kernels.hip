@@ -565,13 +565,18 @@ __global__ void k_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint3
 
 __global__ void k_cut_table(const uint32_t *pyr, int lam, const uint32_t *flags, const uint32_t *excl,
                             const uint8_t *lev, uint8_t *t_level, uint64_t *t_key, uint32_t *t_count,
-                            uint64_t *t_start, uint32_t thresh, uint32_t *over_flag)
+                            uint64_t *t_start, uint32_t thresh, uint32_t *over_flag, uint64_t max_out,
+                            uint32_t *cap_flag)
 {
     const uint64_t ncell = 1ull << (3 * lam);
     for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < ncell;
          m += (uint64_t)gridDim.x * blockDim.x) {
         if (!flags[m]) continue;
         const uint32_t id = excl[m];
+        if (id >= max_out) {   // beyond the planned table: reported, never written
+            atomicOr(cap_flag, 1u);
+            continue;
+        }
         const int l = lev[m];
         const uint64_t key = m >> (3 * (lam - l));
         t_level[id] = (uint8_t)l;
@@ -2671,11 +2676,11 @@ __global__ __launch_bounds__(NPM_BLOCK) void k_np_merge(const uint64_t *jobs, co
 // Chunk of every work chunk: the chunk holding the first occupied finest cell
 // of the work chunk (found by descending the count pyramid; an occupied cell
 // always lies inside a chunk).
-__global__ void k_wc_chunks(const uint32_t *num_wc_dev, const uint64_t *wc_key, const uint8_t *wc_level, int g,
+__global__ void k_wc_chunks(const uint32_t *num_wc_dev, uint32_t max_wc, const uint64_t *wc_key, const uint8_t *wc_level, int g,
                             const uint32_t *pyr, const uint32_t *cid_table, const uint8_t *chunk_level,
                             uint32_t *wc_chunk, uint8_t *wc_nested, uint32_t *flags)
 {
-    const uint32_t num_wc = *num_wc_dev;
+    const uint32_t num_wc = min(*num_wc_dev, max_wc);
     for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < num_wc; w += gridDim.x * blockDim.x) {
         uint64_t m = wc_key[w];
         for (int l = wc_level[w]; l < g; ++l) {
@@ -2694,9 +2699,10 @@ __global__ void k_wc_chunks(const uint32_t *num_wc_dev, const uint64_t *wc_key, 
 
 // Work-chunk range of every chunk (work chunks inside one chunk are
 // consecutive in Morton order).
-__global__ void k_wc_segs(const uint32_t *num_wc_dev, const uint32_t *wc_chunk, uint32_t *seg_b0, uint32_t *seg_end)
+__global__ void k_wc_segs(const uint32_t *num_wc_dev, uint32_t max_wc, const uint32_t *wc_chunk, uint32_t *seg_b0,
+                          uint32_t *seg_end)
 {
-    const uint32_t num_wc = *num_wc_dev;
+    const uint32_t num_wc = min(*num_wc_dev, max_wc);
     for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < num_wc; w += gridDim.x * blockDim.x) {
         const uint32_t c = wc_chunk[w];
         if (w == 0 || wc_chunk[w - 1] != c) seg_b0[c] = w;
@@ -2945,10 +2951,10 @@ void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream
 
 void launch_cut_table(const uint32_t *pyr, int lam, const uint32_t *flags, const uint32_t *excl, const uint8_t *lev,
                       uint8_t *t_level, uint64_t *t_key, uint32_t *t_count, uint64_t *t_start, uint32_t thresh,
-                      uint32_t *over_flag, hipStream_t st)
+                      uint32_t *over_flag, uint64_t max_out, uint32_t *cap_flag, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cut_table, dim3(grid_for(1ull << (3 * lam), 256)), dim3(256), 0, st, pyr, lam, flags, excl,
-                       lev, t_level, t_key, t_count, t_start, thresh, over_flag);
+                       lev, t_level, t_key, t_count, t_start, thresh, over_flag, max_out, cap_flag);
 }
 
 void launch_cell_ids(const uint32_t *flags, uint32_t *excl_to_ids, uint64_t ncell, hipStream_t st)
@@ -3014,9 +3020,11 @@ void launch_wc_chunks(const uint32_t *num_wc_dev, uint64_t max_wc, const uint64_
                       const uint32_t *num_chunks_dev, uint64_t max_chunks, uint32_t *wc_chunk, uint32_t *seg_b0,
                       uint32_t *seg_nb, uint8_t *wc_nested, uint32_t *flags, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_wc_chunks, dim3(grid_for(max_wc, 256)), dim3(256), 0, st, num_wc_dev, wc_key, wc_level, g, pyr,
+    hipLaunchKernelGGL(k_wc_chunks, dim3(grid_for(max_wc, 256)), dim3(256), 0, st, num_wc_dev, (uint32_t)max_wc, wc_key,
+                       wc_level, g, pyr,
                        cid_table, chunk_level, wc_chunk, wc_nested, flags);
-    hipLaunchKernelGGL(k_wc_segs, dim3(grid_for(max_wc, 256)), dim3(256), 0, st, num_wc_dev, wc_chunk, seg_b0, seg_nb);
+    hipLaunchKernelGGL(k_wc_segs, dim3(grid_for(max_wc, 256)), dim3(256), 0, st, num_wc_dev, (uint32_t)max_wc, wc_chunk,
+                       seg_b0, seg_nb);
     hipLaunchKernelGGL(k_wc_chunks_nb, dim3(grid_for(max_chunks, 256)), dim3(256), 0, st, num_chunks_dev, seg_b0, seg_nb,
                        flags);
 }
@@ -3051,10 +3059,12 @@ void launch_np_points(const WcArgs &a, const uint32_t *node_base, const uint32_t
     scan_exclusive(cnt_node, w.nb, num_nodes, w.nb + num_nodes, w.scan_temp, st);
     hipLaunchKernelGGL(k_np_lists, dim3(grid_for(num_nodes, 256, 1024)), dim3(256), 0, st, w.nb, num_nodes, w.lists);
     if (w.general) launch_fill_u32(w.fill, 0u, num_nodes, st);
-    if (w.timer) w.timer->begin(st);
+    if (w.place_timer) w.place_timer->begin(st);
     const uint32_t pg = (a.num_wc + NPP_WAVES - 1) / NPP_WAVES;
     hipLaunchKernelGGL(k_np_place, dim3(pg < 4096 ? pg : 4096), dim3(64 * NPP_WAVES), 0, st, a, node_base, pnode, poff,
                        w.nb, w.fill, w.tmp, (uint32_t)n, w.err);
+    if (w.place_timer) w.place_timer->end(st);
+    if (w.sort_timer) w.sort_timer->begin(st);
     const uint32_t g0 = num_nodes < 8192 ? num_nodes : 8192;
     const uint64_t n1 = n / 1024 + num_nodes / NP_GROUP + 1, n2 = n / 4096 + 1, n3 = n / 8192 + n / NP_T3 + 1;
     hipLaunchKernelGGL((k_np_sort<64, 16, false>), dim3(g0), dim3(64), 0, st, w.lists.c0, w.lists.counts, w.nb,
@@ -3070,7 +3080,7 @@ void launch_np_points(const WcArgs &a, const uint32_t *node_base, const uint32_t
     for (uint32_t r = 0; r < rounds; ++r)
         hipLaunchKernelGGL(k_np_merge, dim3(njobs < 4096 ? (uint32_t)njobs : 4096), dim3(NPM_BLOCK), 0, st,
                            w.lists.jobs, w.lists.counts + 4, w.nb, (int)r, w.out, w.tmp);
-    if (w.timer) w.timer->end(st);
+    if (w.sort_timer) w.sort_timer->end(st);
 }
 
 uint64_t np_list_entries(uint64_t n, int cls)

@@ -91,16 +91,20 @@ def groups_per_build(path: str, counter: str, chunk_passes: int = 1):
                 after_quant = True
             elif "k_subsample" in k or "k_list_classes" in k:
                 sums["subsample"] += v
-            elif "k_np_count" in k:
+            elif "k_np_pieces" in k:
                 sums["node_counts"] += v
                 in_counts = True
             elif "k_np_shared" in k:
                 sums["node_counts"] += v
+            elif "k_np_count" in k:
+                sums["node_counts"] += v
                 in_counts = False
             elif in_counts and "k_scan" in k:
                 sums["node_counts"] += v
-            elif "k_np_place" in k or "k_np_sort" in k or "k_np_merge" in k:
-                sums["node_points"] += v
+            elif "k_np_place" in k:
+                sums["node_place"] += v
+            elif "k_np_sort" in k or "k_np_merge" in k:
+                sums["node_sort"] += v
             elif "k_ms_scatter<false" in k:
                 if after_quant and chunk_left > 0:
                     sums["chunk_scatter"] += v
