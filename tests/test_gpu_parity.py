@@ -253,3 +253,23 @@ def test_oversized_work_chunks(ctx):
     run_both(ctx, c, 128, 1_000_000, 128, 10_000, 64)
     c = synth.clusters(120_000, seed=24, num_clusters=12, sigma_frac=0.0004)   # 10 of 10000 points
     run_both(ctx, c, 128, 1_000_000, 128, 12_000, 64)
+
+
+def test_node_points_odd_tile_count(ctx):
+    """A root above two sort tiles of 16384 values (41,307 points: three
+    tiles, so two merge rounds, the first with an unpaired run)."""
+    c = synth.uniform(45_000, seed=41)
+    got, exp = run_both(ctx, c, 16, 1_000_000, 64, 10_000, 7)
+    assert int(exp["node_count"][0]) > 2 * 16384
+
+
+def test_node_points_many_own_nodes(ctx):
+    """A dense blob inside one count-grid cell (a single work chunk of 30,000
+    points taking the global-memory path) with L = 1: more than 4096 own nodes,
+    beyond the per-work-chunk LDS counters of the node sizes and placement."""
+    rng = np.random.default_rng(42)
+    p = rng.random((30_000, 3), dtype=np.float32)
+    p = np.concatenate([p, np.array([[1000.0, 1000.0, 1000.0]], np.float32)])
+    c = synth.Cloud(p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy())
+    got, exp = run_both(ctx, c, 4, 1_000_000, 2, 1, 5)
+    assert exp["node_depth"].shape[0] > 4096 + 1000
