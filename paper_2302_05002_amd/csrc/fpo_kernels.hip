@@ -2222,7 +2222,7 @@ __global__ __launch_bounds__(NP_BLOCK) void k_np_count(WcArgs a, const uint32_t 
 
 // Sort tile classes: values per tile (threads x values per thread).
 constexpr uint32_t NP_T0 = 64 * 16, NP_T1 = 256 * 16, NP_T2 = 256 * 32, NP_T3 = 512 * 32;
-constexpr uint32_t NPM_OUT = 4096;   // outputs per merge job; divides NP_T3
+constexpr uint32_t NPM_OUT = 2048;   // outputs per merge job (measured: 4096 and 1024 slower); divides NP_T3
 
 // Work lists of the sort (one thread per node): groups of NP_GROUP
 // consecutive nodes holding at most NP_T1 points together (entry
