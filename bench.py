@@ -287,7 +287,7 @@ def main():
                     help="skip the LAS decode, preview variant, gather and node selection legs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library builds on one GPU (no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
