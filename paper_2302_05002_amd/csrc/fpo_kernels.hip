@@ -2021,28 +2021,17 @@ constexpr uint32_t NP_NONE = 0xffffffffu;
 __device__ __forceinline__ int np_final_depth(int t, int lw, int cut) { return (cut < lw && t >= cut) ? cut : t; }
 
 // One LDS atomic per distinct key of the wave: adds the number of active
-// lanes holding each key to cnt[key]; with RANK, returns the count before the
-// lane's own one (lanes of a key in lane order).
-template <bool RANK>
-__device__ __forceinline__ uint32_t wave_lds_count(uint32_t *cnt, uint32_t key, bool active)
+// lanes holding each key to cnt[key].
+__device__ __forceinline__ void wave_lds_count(uint32_t *cnt, uint32_t key, bool active)
 {
     uint64_t todo = __ballot(active);
-    uint32_t r = 0;
     while (todo) {
         const int leader = __ffsll((long long)todo) - 1;
         const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
         const uint64_t m = __ballot(active && key == k);
-        if constexpr (RANK) {
-            uint32_t b = 0;
-            if ((int)lane_id() == leader) b = atomicAdd(&cnt[k], (uint32_t)__popcll(m));
-            b = (uint32_t)__builtin_amdgcn_readlane((int)b, leader);
-            if (active && key == k) r = b + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
-        } else {
-            if ((int)lane_id() == leader) atomicAdd(&cnt[k], (uint32_t)__popcll(m));
-        }
+        if ((int)lane_id() == leader) atomicAdd(&cnt[k], (uint32_t)__popcll(m));
         todo &= ~m;
     }
-    return r;
 }
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t v)
@@ -2202,7 +2191,7 @@ __global__ __launch_bounds__(NP_BLOCK) void k_np_count(WcArgs a, const uint32_t 
                 const bool mine = t < MAXD && t >= lw;   // the cut is lw here
                 uint32_t gid = 0;
                 const uint32_t key = mine ? np_own_key(own, t, f[j], gid) : 0u;
-                wave_lds_count<false>(cnt, key, mine && key != NP_NONE);
+                wave_lds_count(cnt, key, mine && key != NP_NONE);
                 if (mine && key == NP_NONE) atomicAdd(&cnt_node[gid], 1u);
             }
         }
@@ -2284,7 +2273,7 @@ __global__ void k_np_lists(const uint32_t *nb, uint32_t nn, NpLists L)
 // position, and each distinct depth of a row of 64 points is one ballot.
 // Points of own nodes below a subdivided root take theirs from global fill
 // counters (zeroed before).
-constexpr int NPP_ITEMS = 16;
+constexpr int NPP_ITEMS = 8;    // positions per lane and step (measured: 4, 16 and 32 slower)
 constexpr int NPP_WAVES = 4;
 
 __global__ __launch_bounds__(64 * NPP_WAVES) void k_np_place(WcArgs a, const uint32_t *node_base, const uint32_t *pnode,
