@@ -321,8 +321,14 @@ typedef enum {
     FPO_TIMER_COUNT = 8
 } fpo_timer;
 
-/* enable: 1 to time later submits of ctx, 0 to stop. */
+/* enable: 1 to time later submits of ctx (every timer), 0 to stop. */
 fpo_status fpo_context_set_timing(fpo_context *ctx, int enable);
+
+/* Times later submits of ctx with the timers whose bits are set in mask
+ * (bit t for fpo_timer t; 0 stops timing): fewer events, less perturbation of
+ * the build.  The others report 0 launches.  FPO_ERR_INVALID_ARG for bits at
+ * or above FPO_TIMER_COUNT. */
+fpo_status fpo_context_set_timers(fpo_context *ctx, uint32_t mask);
 
 /* *ms = summed elapsed time of the timer's launches in the job, *launches =
  * their number (either pointer may be NULL).  FPO_ERR_INVALID_ARG for an

@@ -31,7 +31,7 @@ EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_w
            "fpo_job_result", "fpo_job_release", "fpo_workspace_size_cloud", "fpo_job_gather",
            "fpo_job_write_file", "fpo_job_export_bytes", "fpo_job_copy_to_host",
            "fpo_job_timestamps", "fpo_batch_workspace_size", "fpo_build_batch", "fpo_server_create",
-           "fpo_server_submit", "fpo_job_cancel", "fpo_server_destroy", "fpo_context_set_timing", "fpo_job_timer",
+           "fpo_server_submit", "fpo_job_cancel", "fpo_server_destroy", "fpo_context_set_timing", "fpo_context_set_timers", "fpo_job_timer",
            "fpo_preview_modulus", "fpo_las_parse_header", "fpo_las_header_box", "fpo_las_decode",
            "fpo_select_workspace_size", "fpo_select_nodes")
 
@@ -174,6 +174,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_server_destroy.restype = None
     lib.fpo_context_set_timing.argtypes = [vp, ctypes.c_int]
     lib.fpo_context_set_timing.restype = ctypes.c_int
+    lib.fpo_context_set_timers.argtypes = [vp, ctypes.c_uint32]
+    lib.fpo_context_set_timers.restype = ctypes.c_int
     lib.fpo_job_timer.argtypes = [vp, ctypes.c_int, P(ctypes.c_float), P(ctypes.c_uint32)]
     lib.fpo_job_timer.restype = ctypes.c_int
     _lib = lib
@@ -289,9 +291,16 @@ class Context:
         except Exception:
             pass
 
-    def set_timing(self, enable: bool):
-        """Bracket the timed kernels of later submits with HIP events."""
-        _check(_lib.fpo_context_set_timing(self._h, 1 if enable else 0))
+    def set_timing(self, enable: bool, only=None):
+        """Bracket the timed kernels of later submits with HIP events: every
+        timer, or only the named ones (keys of TIMERS)."""
+        if only is None:
+            _check(_lib.fpo_context_set_timing(self._h, 1 if enable else 0))
+        else:
+            mask = 0
+            for name in only:
+                mask |= 1 << TIMERS[name]
+            _check(_lib.fpo_context_set_timers(self._h, mask if enable else 0))
 
     def submit(self, x, y, z, params: Params, workspace=None, stream=None, stream_batch: int = 0) -> "Job":
         """Enqueue a build of x, y, z (float32, contiguous): device tensors,

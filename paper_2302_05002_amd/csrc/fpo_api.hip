@@ -303,7 +303,7 @@ struct JobTimer final : LaunchTimer {
 
 void JobTimer::begin(hipStream_t st)
 {
-    first = job->timed ? get_event(job->ctx) : nullptr;
+    first = job->timed && ((job->timer_mask >> which) & 1u) ? get_event(job->ctx) : nullptr;
     if (first) (void)hipEventRecord(first, st);
 }
 
@@ -462,6 +462,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     job->status = FPO_OK;
     job->waited = false;
     job->timed = ctx->timing;
+    job->timer_mask = ctx->timer_mask;
     job->t_submit = now_ns();
     job->t_done = 0;
     job->grid_cells = P.G3;
@@ -1096,9 +1097,16 @@ void fpo_job_release(fpo_job *job)
 
 fpo_status fpo_context_set_timing(fpo_context *ctx, int enable)
 {
+    return fpo_context_set_timers(ctx, enable ? (1u << FPO_TIMER_COUNT) - 1u : 0u);
+}
+
+fpo_status fpo_context_set_timers(fpo_context *ctx, uint32_t mask)
+{
     if (!ctx) return fail(FPO_ERR_INVALID_ARG, "context is NULL");
+    if (mask >> FPO_TIMER_COUNT) return fail(FPO_ERR_INVALID_ARG, "unknown timers in mask 0x%x", mask);
     std::lock_guard<std::mutex> g(ctx->mu);
-    ctx->timing = enable != 0;
+    ctx->timing = mask != 0;
+    ctx->timer_mask = mask;
     return FPO_OK;
 }
 

@@ -34,6 +34,7 @@ struct fpo_context {
     std::mutex mu;
     std::vector<void *> pinned_free;
     bool timing = false;
+    uint32_t timer_mask = 0;           // bit t: timer t is recorded (when timing)
     std::vector<hipEvent_t> ev_free;   // timing events, reused across jobs
     fpo::Pool *batch_pool = nullptr;   // created by the first batch
     fpo::Pool *issue_pool = nullptr;   // issues plain builds in submission order (created by the first)
@@ -49,6 +50,7 @@ struct fpo_job {
     fpo_result res;
     bool waited;
     bool timed;
+    uint32_t timer_mask = 0;      // the context's timers when it was submitted
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tm[FPO_TIMER_COUNT];
     uint64_t t_submit, t_done;    // host steady clock, ns (t_done: when a wait or poll saw it end)
     uint64_t grid_cells;          // G^3

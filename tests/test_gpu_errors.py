@@ -105,3 +105,29 @@ def test_las_decode_errors(ctx):
     x, y, z, _ = ctx.las_decode(recs, h)
     torch.cuda.synchronize()
     assert x.shape[0] == 1000
+
+
+def test_timer_mask(ctx):
+    """Timers of a mask: the selected group records its launches, the others
+    none; a bit beyond the last timer is rejected."""
+    import torch
+    import paper_2302_05002_amd as fpo
+    lib = fpo.load_library()
+    assert lib.fpo_context_set_timers(ctx._h, 1 << fpo.TIMERS["node_sort"] | 1 << 20) == fpo.FPO_ERR_INVALID_ARG
+    c = synth.planes(200_000, seed=8, num_planes=20)
+    x, y, z = (torch.from_numpy(a).cuda() for a in (c.x, c.y, c.z))
+    p = fpo.Params(64, 100_000, 32, 10_000, 64)
+    ctx.set_timing(True, ["subsample", "node_sort"])
+    job = ctx.submit(x, y, z, p)
+    job.wait()
+    got = {k: job.timer(k) for k in fpo.TIMERS}
+    job.release()
+    ctx.set_timing(False)
+    assert got["subsample"][1] >= 1 and got["node_sort"][1] >= 1 and got["subsample"][0] > 0
+    assert all(got[k] == (0.0, 0) for k in fpo.TIMERS if k not in ("subsample", "node_sort"))
+    ctx.set_timing(True)
+    job = ctx.submit(x, y, z, p)
+    job.wait()
+    assert all(job.timer(k)[1] >= 1 for k in ("bbox", "quantize", "subsample", "node_place", "node_sort", "preview"))
+    job.release()
+    ctx.set_timing(False)
