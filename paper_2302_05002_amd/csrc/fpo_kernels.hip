@@ -2003,13 +2003,16 @@ __global__ void k_node_counts(WcArgs a, uint32_t *owned)
 // A point's node is fixed by its final depth t: a shared ancestor above its
 // work chunk when t < lw, else one of the work chunk's own nodes (rank fr
 // among those of depth t).  The points of work chunk w in the shared node of
-// depth d form one piece; the depth-major exclusive scan S of the piece sizes
-// gives every shared node's size (a difference of S over its work chunks,
-// which are consecutive) and every piece's offset inside its node.  Own nodes
-// are counted directly.  With the node begins (scan of the node sizes in node
-// order) every point is put inside its node's range, in no particular order,
-// and each node's range is then sorted by original index: an LDS radix sort
-// per tile (tiles sized to the node), merge rounds for nodes above one tile.
+// depth d form one piece.  Piece sizes are differences of the reaching counts
+// the subsample pass posts, and the depth-major exclusive scan S of the piece
+// sizes gives every shared node's size (a difference of S over its work
+// chunks, which are consecutive) and every piece's offset inside its node.  A
+// root that is its work chunk's only own node holds every point reaching it;
+// only work chunks with own nodes below their root count their points.  With
+// the node begins (scan of the node sizes in node order) every point is put
+// inside its node's range, and each range is then sorted by original index:
+// an LDS radix sort per tile (tiles sized to the node), merge rounds for
+// nodes above one tile.
 
 constexpr int NP_BLOCK = 256;
 constexpr int NP_ITEMS = 16;          // positions per thread and step (one step covers a work chunk)
@@ -2375,34 +2378,79 @@ __device__ __forceinline__ uint32_t np_block_scan(uint32_t v, uint32_t *lds, uin
     }
 }
 
-// LDS radix sort of the block's keys (KPT per thread, blocked: thread i holds
-// elements i * KPT ..), 5 bits per pass from bit 0 up to `bits`; stable, so
-// the passes compose.  Each thread counts its own keys per digit in 16-bit
-// halves (digit d in word d & 15, half d >> 4; words [d & 15][thread], one
-// padding word per 16), the words are scanned in that order (both halves at
-// once; the high half then adds the low total), and keys move through LDS.
-// A thread's counter words are its own outside the scan, so it clears them
-// right after reading its offsets.  The sorted keys are left in keys[]
-// (element e at e + e / KPT).  cnt must be zero on entry; it is zero on exit.
-template <int BLOCK, int KPT>
-__device__ void np_radix(uint32_t (&k)[KPT], int bits, uint32_t *keys, uint32_t *cnt, uint32_t *red)
+template <int BLOCK, int KPT, bool CHECK>
+__device__ __forceinline__ void np_radix_count(const uint32_t (&k)[KPT], uint32_t (&loc)[KPT / 2], int sh,
+                                               uint32_t *cnt, uint32_t col, uint32_t first, uint32_t len)
+{
+    constexpr uint32_t ROW = BLOCK + BLOCK / 16;
+    // every atomic is issued before any result is used, so they overlap
+    uint32_t r[KPT];
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        r[j] = 0;
+        if (!CHECK || first + j < len) {
+            const uint32_t d = k[j] >> sh;
+            r[j] = atomicAdd(&cnt[(d & 15u) * ROW + col], 1u << (d & 16u));
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        const uint32_t l = (r[j] >> ((k[j] >> sh) & 16u)) & 0xffffu;
+        if (j % 2 == 0) loc[j / 2] = l;
+        else loc[j / 2] |= l << 16;
+    }
+}
+
+template <int BLOCK, int KPT, bool CHECK>
+__device__ __forceinline__ void np_radix_scatter(const uint32_t (&k)[KPT], const uint32_t (&loc)[KPT / 2], int sh,
+                                                 const uint32_t *cnt, uint32_t *keys, uint32_t col, uint32_t low_total,
+                                                 uint32_t first, uint32_t len)
+{
+    constexpr uint32_t ROW = BLOCK + BLOCK / 16;
+    constexpr int KSH = ilog2_c(KPT);
+    uint32_t dst[KPT];
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        const uint32_t d = k[j] >> sh;
+        const uint32_t h = d & 16u;
+        const uint32_t pre = cnt[(d & 15u) * ROW + col];
+        dst[j] = ((pre >> h) & 0xffffu) + (h ? low_total : 0u) + ((loc[j / 2] >> (16 * (j % 2))) & 0xffffu);
+    }
+#pragma unroll
+    for (int j = 0; j < KPT; ++j)
+        if (!CHECK || first + j < len) keys[dst[j] + (dst[j] >> KSH)] = k[j];
+}
+
+// LDS radix sort of the block's first len keys (KPT per thread, blocked:
+// thread i holds elements i * KPT ..; the rest is padding), 5 bits per pass
+// from bit 0 up to `bits`; stable, so the passes compose.  Each thread counts
+// its own keys per digit in 16-bit halves (digit d in word d & 15, half
+// d >> 4; words [d & 15][thread], one padding word per 16), the words are
+// scanned in that order (both halves at once; the high half then adds the low
+// total), and keys move through LDS.  A thread's counter words are its own
+// outside the scan, so it clears them right after reading its offsets.  Waves
+// holding only padding skip the passes; only the wave at the end of the keys
+// checks each key (with SKIP: measured faster for 8192-value tiles only; the
+// larger code is slower for the others).  The sorted keys are left in keys[]
+// (element e < len at e + e / KPT).  cnt must be zero on entry; it is zero on
+// exit.
+template <int BLOCK, int KPT, bool SKIP>
+__device__ void np_radix(uint32_t (&k)[KPT], uint32_t len, int bits, uint32_t *keys, uint32_t *cnt, uint32_t *red)
 {
     static_assert(BLOCK * KPT <= 65535, "16-bit counters");
     constexpr uint32_t ROW = BLOCK + BLOCK / 16;   // counter words per digit row, padding included
-    constexpr int KSH = ilog2_c(KPT);
     const uint32_t tid = threadIdx.x;
     const uint32_t col = tid + (tid >> 4);         // the thread's column
+    const uint32_t first = tid * KPT;
+    const uint32_t wave_first = (tid & ~63u) * KPT;
+    // full, partly, no keys (without SKIP every wave counts as full: the
+    // padding then sorts last, its keys being all ones)
+    const int mode = !SKIP || wave_first + 64 * KPT <= len ? 2 : wave_first < len ? 1 : 0;
     for (int sh = 0; sh < bits; sh += 5) {
         // the thread's rank among its own keys of the same digit (16 bits each)
         uint32_t loc[KPT / 2];
-#pragma unroll
-        for (int j = 0; j < KPT; ++j) {
-            const uint32_t d = k[j] >> sh;
-            const uint32_t h = d & 16u;
-            const uint32_t l = (atomicAdd(&cnt[(d & 15u) * ROW + col], 1u << h) >> h) & 0xffffu;
-            if (j % 2 == 0) loc[j / 2] = l;
-            else loc[j / 2] |= l << 16;
-        }
+        if (mode == 2) np_radix_count<BLOCK, KPT, false>(k, loc, sh, cnt, col, first, len);
+        else if (mode == 1) np_radix_count<BLOCK, KPT, true>(k, loc, sh, cnt, col, first, len);
         __syncthreads();
         uint32_t s = 0;
 #pragma unroll
@@ -2417,20 +2465,12 @@ __device__ void np_radix(uint32_t (&k)[KPT], int bits, uint32_t *keys, uint32_t 
         }
         const uint32_t low_total = tot & 0xffffu;
         __syncthreads();
-        uint32_t dst[KPT];
-#pragma unroll
-        for (int j = 0; j < KPT; ++j) {
-            const uint32_t d = k[j] >> sh;
-            const uint32_t h = d & 16u;
-            const uint32_t pre = cnt[(d & 15u) * ROW + col];
-            dst[j] = ((pre >> h) & 0xffffu) + (h ? low_total : 0u) + ((loc[j / 2] >> (16 * (j % 2))) & 0xffffu);
-        }
+        if (mode == 2) np_radix_scatter<BLOCK, KPT, false>(k, loc, sh, cnt, keys, col, low_total, first, len);
+        else if (mode == 1) np_radix_scatter<BLOCK, KPT, true>(k, loc, sh, cnt, keys, col, low_total, first, len);
 #pragma unroll
         for (int i = 0; i < 16; ++i) cnt[i * ROW + col] = 0;
-#pragma unroll
-        for (int j = 0; j < KPT; ++j) keys[dst[j] + (dst[j] >> KSH)] = k[j];
         __syncthreads();
-        if (sh + 5 < bits) {
+        if (sh + 5 < bits && mode != 0) {
 #pragma unroll
             for (int j = 0; j < KPT; ++j) k[j] = keys[tid * (KPT + 1) + j];
         }
@@ -2441,7 +2481,7 @@ __device__ __forceinline__ uint32_t bits_for(uint32_t span) { return span ? 32u 
 
 // Sorts src[r0, r0 + len) (len <= BLOCK * KPT) into dst[r0, ..): by segment
 // (nseg > 1: segment s starts at segb[s], relative) and then by value.
-template <int BLOCK, int KPT>
+template <int BLOCK, int KPT, bool SKIP>
 __device__ void np_sort_range(const uint32_t *src, uint32_t *dst, uint32_t r0, uint32_t len, uint32_t nseg,
                               const uint32_t *segb, uint32_t *keys, uint32_t *cnt, uint32_t *red)
 {
@@ -2499,7 +2539,7 @@ __device__ void np_sort_range(const uint32_t *src, uint32_t *dst, uint32_t r0, u
     }
     // padding keys are all ones: every digit maximal, and they start after
     // the real keys, so a stable sort leaves them last
-    np_radix<BLOCK, KPT>(k, (int)bits, keys, cnt, red);
+    np_radix<BLOCK, KPT, SKIP>(k, len, (int)bits, keys, cnt, red);
 #pragma unroll 4
     for (int j = 0; j < KPT; ++j) {
         const uint32_t e = j * BLOCK + tid;
@@ -2516,7 +2556,7 @@ __device__ void np_sort_range(const uint32_t *src, uint32_t *dst, uint32_t r0, u
 // waves per SIMD each tile size is compiled for (registers held to it, no spills)
 constexpr int np_sort_waves(int block, int kpt) { return block * kpt <= 4096 ? 3 : 2; }
 
-template <int BLOCK, int KPT, bool LONG>
+template <int BLOCK, int KPT, bool LONG, bool SKIP = false>
 __global__ __launch_bounds__(BLOCK, np_sort_waves(BLOCK, KPT)) void k_np_sort(const void *list, const uint32_t *list_cnt, const uint32_t *nb,
                                                    uint32_t nn, const uint32_t *src, uint32_t *dst, uint32_t *alt)
 {
@@ -2575,7 +2615,7 @@ __global__ __launch_bounds__(BLOCK, np_sort_waves(BLOCK, KPT)) void k_np_sort(co
                 rr = r0 + segb[sub];
                 ll = segb[sub + 1] - segb[sub];
             }
-            np_sort_range<BLOCK, KPT>(src, out, rr, ll, nseg, segb, keys, cnt, red);
+            np_sort_range<BLOCK, KPT, SKIP>(src, out, rr, ll, nseg, segb, keys, cnt, red);
         }
     }
 }
@@ -3060,7 +3100,8 @@ void launch_np_points(const WcArgs &a, const uint32_t *node_base, const uint32_t
                        num_nodes, w.tmp, w.out, w.tmp);
     hipLaunchKernelGGL((k_np_sort<256, 16, false>), dim3(n1 < 4096 ? (uint32_t)n1 : 4096), dim3(256), 0, st, w.lists.c1,
                        w.lists.counts + 1, w.nb, num_nodes, w.tmp, w.out, w.tmp);
-    hipLaunchKernelGGL((k_np_sort<256, 32, false>), dim3(n2 < 2048 ? (uint32_t)n2 : 2048), dim3(256), 0, st, w.lists.c2,
+    hipLaunchKernelGGL((k_np_sort<256, 32, false, true>), dim3(n2 < 2048 ? (uint32_t)n2 : 2048), dim3(256), 0, st,
+                       w.lists.c2,
                        w.lists.counts + 2, w.nb, num_nodes, w.tmp, w.out, w.tmp);
     hipLaunchKernelGGL((k_np_sort<512, 32, true>), dim3(n3 < 1024 ? (uint32_t)n3 : 1024), dim3(512), 0, st, w.lists.c3,
                        w.lists.counts + 3, w.nb, num_nodes, w.tmp, w.out, w.tmp);
