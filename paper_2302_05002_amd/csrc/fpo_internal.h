@@ -66,7 +66,7 @@ struct LaunchTimer {
 void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t words, hipStream_t st);
 // Bounding box: per-block partials (8 words each: 3 min, 3 max in an
 // order-preserving integer encoding, a non-finite flag), reduced by k_setup.
-constexpr uint32_t BBOX_MAX_BLOCKS = 4096;
+constexpr uint32_t BBOX_MAX_BLOCKS = 2048;
 uint32_t bbox_blocks(uint64_t n);
 void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, uint32_t *part, hipStream_t st);
 // flag_only: only the non-finite flag is reduced (the box was set before).

@@ -169,21 +169,24 @@ __global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ x, const
     const float4 *px = reinterpret_cast<const float4 *>(x), *py = reinterpret_cast<const float4 *>(y),
                  *pz = reinterpret_cast<const float4 *>(z);
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + stride < n4; i += 2 * stride) {
-        const float4 a0 = px[i], b0 = py[i], c0 = pz[i];
-        const float4 a1 = px[i + stride], b1 = py[i + stride], c1 = pz[i + stride];
-        bbox_acc(mn[0], mx[0], bad, a0.x); bbox_acc(mn[0], mx[0], bad, a0.y);
-        bbox_acc(mn[0], mx[0], bad, a0.z); bbox_acc(mn[0], mx[0], bad, a0.w);
-        bbox_acc(mn[1], mx[1], bad, b0.x); bbox_acc(mn[1], mx[1], bad, b0.y);
-        bbox_acc(mn[1], mx[1], bad, b0.z); bbox_acc(mn[1], mx[1], bad, b0.w);
-        bbox_acc(mn[2], mx[2], bad, c0.x); bbox_acc(mn[2], mx[2], bad, c0.y);
-        bbox_acc(mn[2], mx[2], bad, c0.z); bbox_acc(mn[2], mx[2], bad, c0.w);
-        bbox_acc(mn[0], mx[0], bad, a1.x); bbox_acc(mn[0], mx[0], bad, a1.y);
-        bbox_acc(mn[0], mx[0], bad, a1.z); bbox_acc(mn[0], mx[0], bad, a1.w);
-        bbox_acc(mn[1], mx[1], bad, b1.x); bbox_acc(mn[1], mx[1], bad, b1.y);
-        bbox_acc(mn[1], mx[1], bad, b1.z); bbox_acc(mn[1], mx[1], bad, b1.w);
-        bbox_acc(mn[2], mx[2], bad, c1.x); bbox_acc(mn[2], mx[2], bad, c1.y);
-        bbox_acc(mn[2], mx[2], bad, c1.z); bbox_acc(mn[2], mx[2], bad, c1.w);
+    // four float4 per axis in flight per thread
+    for (; i + 3 * stride < n4; i += 4 * stride) {
+        float4 a[4], b[4], c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = px[i + u * stride];
+            b[u] = py[i + u * stride];
+            c[u] = pz[i + u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            bbox_acc(mn[0], mx[0], bad, a[u].x); bbox_acc(mn[0], mx[0], bad, a[u].y);
+            bbox_acc(mn[0], mx[0], bad, a[u].z); bbox_acc(mn[0], mx[0], bad, a[u].w);
+            bbox_acc(mn[1], mx[1], bad, b[u].x); bbox_acc(mn[1], mx[1], bad, b[u].y);
+            bbox_acc(mn[1], mx[1], bad, b[u].z); bbox_acc(mn[1], mx[1], bad, b[u].w);
+            bbox_acc(mn[2], mx[2], bad, c[u].x); bbox_acc(mn[2], mx[2], bad, c[u].y);
+            bbox_acc(mn[2], mx[2], bad, c[u].z); bbox_acc(mn[2], mx[2], bad, c[u].w);
+        }
     }
     for (; i < n4; i += stride) {
         const float4 a0 = px[i], b0 = py[i], c0 = pz[i];
@@ -285,12 +288,12 @@ __global__ __launch_bounds__(256) void k_setup(DevBox *box, const uint32_t *part
     box->scale = side > 0.0f ? (float)(2097152.0 / (double)side) : 0.0f;
 }
 
+// Clamped to [0, UMAX] before the conversion (NaN and t <= 0 give 0, t >=
+// UMAX gives UMAX), so no branch: on t >= 0 truncation is the floor.
 __device__ __forceinline__ uint32_t quantize1(float a, float lo, float scale)
 {
     const float t = __fmul_rn(__fsub_rn(a, lo), scale);
-    if (!(t > 0.0f)) return 0u;
-    if (t >= 2097151.0f) return UMAX;
-    return (uint32_t)floorf(t);
+    return (uint32_t)fminf(fmaxf(t, 0.0f), 2097151.0f);
 }
 
 // ---- preview hash H64 and its inverse ----------------------------------------------
@@ -344,9 +347,12 @@ static_assert(h64_inverse(h64(0)) == 0 && h64_inverse(h64(1)) == 1 && h64_invers
 // (fewer slots, 64-bit minima) and flushes it with a 64-bit atomic minimum.
 constexpr int QZ_BLOCK = 1024;
 template <bool GRID> struct Qz {
-    static constexpr int ITEMS = GRID ? 2 : 4;
+    static constexpr int ITEMS = GRID ? 2 : 8;
     static constexpr uint32_t ROUND = QZ_BLOCK * ITEMS;
-    static constexpr uint32_t HASH = GRID ? 8192 : 16384;   // slots, kept at most half full (128 KB of LDS)
+    static constexpr uint32_t HASH = GRID ? 8192 : 16384;   // slots (128 KB of LDS)
+    // flushed when a round could fill the table past half (grid preview)
+    // or three quarters of its slots
+    static constexpr uint32_t FLUSH_AT = (GRID ? HASH / 2 : HASH - HASH / 4) - ROUND;
 };
 
 __device__ __forceinline__ uint32_t hash32(uint32_t k)
@@ -377,10 +383,42 @@ __device__ void qz_flush(uint32_t *hk, uint32_t *hc, unsigned long long *hm, uin
     }
 }
 
+// Claims or finds the slot of cell `cl`, starting at slot h whose key was
+// read as k (linear probing; entries stay until the next flush).
+template <uint32_t HASH>
+__device__ __forceinline__ uint32_t qz_slot(uint32_t *hk, uint32_t *used, uint32_t cl, uint32_t h, uint32_t k)
+{
+    while (true) {
+        if (k == 0xffffffffu) {
+            k = atomicCAS(&hk[h], 0xffffffffu, cl);
+            if (k == 0xffffffffu) {
+                atomicAdd(used, 1u);
+                return h;
+            }
+        }
+        if (k == cl) return h;
+        h = (h + 1) & (HASH - 1);
+        k = hk[h];
+    }
+}
+
+// 32-bit byte offsets from a block's own base pointers (a block covers at
+// most 2^32 / 256 points), so the loads and stores take a scalar base.
+template <typename T> __device__ __forceinline__ const T &at_byte(const T *p, uint32_t off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + off);
+}
+template <typename T> __device__ __forceinline__ T &at_byte(T *p, uint32_t off)
+{
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(p) + off);
+}
+
 // One block per compute unit, each over a contiguous range of points.  The
 // coordinates of the next round are loaded before the hash updates of the
-// current one, so the loads stay in flight while the LDS work runs.  `base`
-// is the original index of x[0] (batches of a streamed cloud).
+// current one, so the loads stay in flight while the LDS work runs.  The
+// first probe of every item is read before any is used: a cell already in
+// the table (the usual case) then costs one read and one atomic.  `base` is
+// the original index of x[0] (batches of a streamed cloud).
 template <bool GRID>
 __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__ x, const float *__restrict__ y,
                                                        const float *__restrict__ z, uint64_t n, const DevBox *box,
@@ -396,14 +434,16 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
     __shared__ uint32_t used;
     __shared__ uint32_t wsum[QZ_BLOCK / 64];
     const uint64_t lo = (uint64_t)blockIdx.x * per_block;
-    const uint64_t hi = lo + per_block < n ? lo + per_block : n;
+    const uint32_t cnt = (uint32_t)((lo + per_block < n ? lo + per_block : n) - lo);
+    const float *bx = x + lo, *by = y + lo, *bz = z + lo;
+    uint64_t *bcode = code + lo;
     float px[ITEMS], py[ITEMS], pz[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        const uint64_t i = lo + (uint64_t)j * QZ_BLOCK + threadIdx.x;
-        px[j] = i < hi ? x[i] : 0.0f;
-        py[j] = i < hi ? y[i] : 0.0f;
-        pz[j] = i < hi ? z[i] : 0.0f;
+        const uint32_t o = (uint32_t)j * QZ_BLOCK + threadIdx.x;
+        px[j] = o < cnt ? at_byte(bx, 4 * o) : 0.0f;
+        py[j] = o < cnt ? at_byte(by, 4 * o) : 0.0f;
+        pz[j] = o < cnt ? at_byte(bz, 4 * o) : 0.0f;
     }
     const float lx = box->lo[0], ly = box->lo[1], lz = box->lo[2], sc = box->scale;
     const float hx = box->hi[0], hy = box->hi[1], hz = box->hi[2];
@@ -417,16 +457,16 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
     __syncthreads();
     uint32_t outside = 0;
     bool bad = false;
-    for (uint64_t r0 = lo; r0 < hi; r0 += ROUND) {
+    for (uint32_t r0 = 0; r0 < cnt; r0 += ROUND) {
         uint32_t cell[ITEMS];
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
-            const uint64_t i = r0 + (uint64_t)j * QZ_BLOCK + threadIdx.x;
+            const uint32_t o = r0 + (uint32_t)j * QZ_BLOCK + threadIdx.x;
             const uint32_t ux = quantize1(px[j], lx, sc), uy = quantize1(py[j], ly, sc), uz = quantize1(pz[j], lz, sc);
             const uint64_t c = (split3(ux) << 2) | (split3(uy) << 1) | split3(uz);
-            cell[j] = i < hi ? (uint32_t)(c >> sh) : 0xffffffffu;
-            if (i < hi) code[i] = c;
-            if (given && i < hi) {
+            cell[j] = o < cnt ? (uint32_t)(c >> sh) : 0xffffffffu;
+            if (o < cnt) at_byte(bcode, 8 * o) = c;
+            if (given && o < cnt) {
                 outside += (px[j] < lx || px[j] > hx || py[j] < ly || py[j] > hy || pz[j] < lz || pz[j] > hz) ? 1u : 0u;
                 // NaN fails every comparison, an infinity exceeds the largest float
                 bad |= !(fabsf(px[j]) <= FLT_MAX && fabsf(py[j]) <= FLT_MAX && fabsf(pz[j]) <= FLT_MAX);
@@ -435,38 +475,29 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
         // next round's coordinates
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
-            const uint64_t i = r0 + ROUND + (uint64_t)j * QZ_BLOCK + threadIdx.x;
-            px[j] = i < hi ? x[i] : 0.0f;
-            py[j] = i < hi ? y[i] : 0.0f;
-            pz[j] = i < hi ? z[i] : 0.0f;
+            const uint32_t o = r0 + ROUND + (uint32_t)j * QZ_BLOCK + threadIdx.x;
+            px[j] = o < cnt ? at_byte(bx, 4 * o) : 0.0f;
+            py[j] = o < cnt ? at_byte(by, 4 * o) : 0.0f;
+            pz[j] = o < cnt ? at_byte(bz, 4 * o) : 0.0f;
+        }
+        uint32_t slot[ITEMS], seen[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            slot[j] = hash32(cell[j]) & (HASH - 1);
+            seen[j] = hk[slot[j]];
         }
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t cl = cell[j];
             if (cl == 0xffffffffu) continue;
-            uint32_t h = hash32(cl) & (HASH - 1);
-            while (true) {
-                uint32_t k = hk[h];
-                if (k == 0xffffffffu) {
-                    k = atomicCAS(&hk[h], 0xffffffffu, cl);
-                    if (k == 0xffffffffu) {
-                        atomicAdd(&used, 1u);
-                        k = cl;
-                    }
-                }
-                if (k == cl) {
-                    atomicAdd(&hc[h], 1u);
-                    if constexpr (GRID)
-                        atomicMin(&hm[h], (unsigned long long)h64(base + r0 + (uint64_t)j * QZ_BLOCK + threadIdx.x));
-                    break;
-                }
-                h = (h + 1) & (HASH - 1);
-            }
+            const uint32_t h = seen[j] == cl ? slot[j] : qz_slot<HASH>(hk, &used, cl, slot[j], seen[j]);
+            atomicAdd(&hc[h], 1u);
+            if constexpr (GRID)
+                atomicMin(&hm[h], (unsigned long long)h64(base + lo + r0 + (uint64_t)j * QZ_BLOCK + threadIdx.x));
         }
         __syncthreads();
-        // at most ROUND new cells per round: keep the table at most half
-        // full before the next one
-        if (used > HASH / 2 - ROUND) {
+        // at most ROUND new cells per round
+        if (used > Qz<GRID>::FLUSH_AT) {
             qz_flush<GRID>(hk, hc, hm, fine, cellmin);
             __syncthreads();
             if (threadIdx.x == 0) used = 0;
@@ -2906,6 +2937,7 @@ void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t words, hipStream_t st)
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(words, 256, 2048)), dim3(256), 0, st, p, v, words);
 }
 
+// at most 2048 blocks of four waves: one resident wave of blocks on 256 compute units
 uint32_t bbox_blocks(uint64_t n) { return grid_for((n + 3) / 4, 256, BBOX_MAX_BLOCKS); }
 
 void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, uint32_t *part, hipStream_t st)
