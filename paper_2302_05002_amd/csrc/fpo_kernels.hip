@@ -1737,8 +1737,12 @@ __device__ __forceinline__ uint32_t wc_size_class(uint32_t n)
 __constant__ uint32_t kFastMul[8] = {0x9E3779B1u, 0x85EBCA77u, 0xC2B2AE3Du, 0x27D4EB2Fu,
                                      0x165667B1u, 0xD3A2646Du, 0xFD7046C5u, 0xB55A4F09u};
 
+// The 512 x 8 class is held to six waves per SIMD (80 registers, a few
+// per-chunk constants spilled): three blocks per CU instead of two, 119 ->
+// 97 us on the 20M-point planes.  Eight waves spill in the depth loop.
 template <int BLOCK, int ITEMS, int TLOG>
-__global__ __launch_bounds__(BLOCK) void k_subsample_fast(WcArgs a, int cls)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 512 && ITEMS == 8 ? 6 : 1)))
+void k_subsample_fast(WcArgs a, int cls)
 {
     constexpr uint32_t CAP = BLOCK * ITEMS;
     constexpr uint32_t TSZ = 1u << TLOG;        // table entries
@@ -1789,9 +1793,8 @@ __global__ __launch_bounds__(BLOCK) void k_subsample_fast(WcArgs a, int cls)
         uint32_t alive0 = 0;
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) alive0 += it[j] >= ALIVE ? 1u : 0u;
-        uint32_t A = block_sum2(alive0, par);
+        uint32_t A = block_sum2(alive0, par);   // its barrier also ends the clearing (one wave: program order)
         par ^= 1;
-        __syncthreads();
         bool clean = true;   // the table holds no hashed entries
         for (int d = a.d0; d < lw && A > 0; ++d) {
             if (threadIdx.x == 0) alive_at[d] = A;
@@ -1799,12 +1802,12 @@ __global__ __launch_bounds__(BLOCK) void k_subsample_fast(WcArgs a, int cls)
             const int sh = 3 * (lw - 1 - d);
             uint32_t won = 0;                    // bit j: item j stays at depth d
             if (rb <= TLOG) {
-                if (!clean) {
+                if (!clean) {   // block-uniform
                     for (uint32_t h = threadIdx.x; h < TSZ / 4; h += BLOCK)
                         table4[h] = make_uint4(EMPTY, EMPTY, EMPTY, EMPTY);
                     clean = true;
+                    __syncthreads();
                 }
-                __syncthreads();
                 const uint32_t tag = (31u - (uint32_t)d) << PB;
 #pragma unroll
                 for (int j = 0; j < ITEMS; ++j)
@@ -1859,9 +1862,11 @@ __global__ __launch_bounds__(BLOCK) void k_subsample_fast(WcArgs a, int cls)
                 if ((won >> j) & 1u) it[j] = (it[j] & 0xffffffu) | ((uint32_t)d << 24);
                 else ++surv;
             }
+            // every table read of this depth has completed before the sum's
+            // barrier (one wave: in program order), so the next depth may
+            // write the table
             A = block_sum2(surv, par);
             par ^= 1;
-            __syncthreads();   // the table is reused next
         }
         // the rest sits in the root (a leaf) at depth lw
 #pragma unroll
