@@ -1737,11 +1737,14 @@ __device__ __forceinline__ uint32_t wc_size_class(uint32_t n)
 __constant__ uint32_t kFastMul[8] = {0x9E3779B1u, 0x85EBCA77u, 0xC2B2AE3Du, 0x27D4EB2Fu,
                                      0x165667B1u, 0xD3A2646Du, 0xFD7046C5u, 0xB55A4F09u};
 
-// The 512 x 8 class is held to six waves per SIMD (80 registers, a few
-// per-chunk constants spilled): three blocks per CU instead of two, 119 ->
-// 97 us on the 20M-point planes.  Eight waves spill in the depth loop.
+// Eight items per thread are held to six waves per SIMD (80 registers, a
+// few per-chunk constants spilled): on the 20M-point planes the 512 x 8
+// class then runs three blocks per CU instead of two (119 -> 97 us), and
+// 256 x 8 for the 2048-point class six blocks of four waves instead of four
+// blocks of eight at 512 x 4 (106 -> 84 us).  Eight waves per SIMD spill in
+// the depth loop.
 template <int BLOCK, int ITEMS, int TLOG>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 512 && ITEMS == 8 ? 6 : 1)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK <= 512 && ITEMS == 8 ? 6 : 1)))
 void k_subsample_fast(WcArgs a, int cls)
 {
     constexpr uint32_t CAP = BLOCK * ITEMS;
@@ -3041,13 +3044,13 @@ void launch_subsample_small(const WcArgs &a, hipStream_t st)
     const uint32_t gs = a.num_wc < 8192 ? a.num_wc : 8192;
     // work chunks whose own root is a leaf: shared ancestors only
     // (few points per thread: a work chunk's depths run one after another, so
-    // its latency bounds these kernels.  Measured on the 20M-point planes:
-    // four points per thread up to 2048 points, eight above, where LDS
-    // limits the blocks per CU)
+    // its latency bounds these kernels and the blocks resident per CU set
+    // their speed.  Measured on the 20M-point planes: four points per thread
+    // up to 1024 points, eight above)
     hipLaunchKernelGGL((k_subsample_fast<64, 4, 10>), dim3(gs), dim3(64), 0, st, a, 0);
     hipLaunchKernelGGL((k_subsample_fast<128, 4, 11>), dim3(gs), dim3(128), 0, st, a, 1);
     hipLaunchKernelGGL((k_subsample_fast<256, 4, 12>), dim3(gs), dim3(256), 0, st, a, 2);
-    hipLaunchKernelGGL((k_subsample_fast<512, 4, 13>), dim3(gs), dim3(512), 0, st, a, 3);
+    hipLaunchKernelGGL((k_subsample_fast<256, 8, 12>), dim3(gs), dim3(256), 0, st, a, 3);
     hipLaunchKernelGGL((k_subsample_fast<512, 8, 13>), dim3(gs), dim3(512), 0, st, a, 4);
     // oversized work chunks at the deepest work-chunk level (dense clusters)
     hipLaunchKernelGGL((k_subsample_fast<1024, 8, 14>), dim3(gs < 2048 ? gs : 2048), dim3(1024), 0, st, a, 5);
