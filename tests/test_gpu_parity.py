@@ -194,6 +194,15 @@ def test_config1_full(ctx):
     assert np.bincount(got["node_depth"]).tolist() == [1, 8, 64, 512]
 
 
+def test_quantize_table_flushes(ctx):
+    """3M uniform points over a 128^3 count grid: each block of the quantise
+    pass meets about 8,000 new cells in its first round of 8,192 points,
+    more than its LDS cell table keeps between rounds, so the table is
+    flushed to the global histogram between rounds."""
+    c = synth.uniform(3_000_000, seed=91)
+    run_both(ctx, c, 128, 1_000_000, 32, 10_000, 64)
+
+
 def test_config2_reduced_with_invariants(ctx):
     """The 200-plane workload at 2M points: full comparison plus invariants."""
     c = synth.planes(2_000_000, seed=2)

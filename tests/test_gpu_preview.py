@@ -82,6 +82,15 @@ def test_parity(ctx, case, mode):
     both(ctx, c, G, max(n // 8, 1), 32, 1_000, M, mode, label=str(case))
 
 
+def test_grid_table_flushes(ctx):
+    """3M uniform points over a 128^3 count grid: the grid preview's cell
+    table (per-cell hash minima) is flushed between the quantise rounds of
+    every block, since each round of 2,048 points meets about 2,000 new
+    cells."""
+    c = synth.uniform(3_000_000, seed=91)
+    both(ctx, c, 128, 1_000_000, 32, 10_000, 64, "grid", label="flushes")
+
+
 def test_empty_single_and_identical(ctx):
     e = synth.Cloud(np.zeros(0, np.float32), np.zeros(0, np.float32), np.zeros(0, np.float32))
     one = np.array([3.5], np.float32)
