@@ -78,6 +78,7 @@ struct Ctrs {
     uint32_t np_max;                // points of the largest node
     uint32_t np_lists[5];           // node_points sort: tile lists of four sizes, merge jobs
     uint32_t np_general;            // work chunks with own nodes below their root
+    uint32_t wc_over;               // a work chunk holds more than WC_CAP points (one finest cell)
 };
 static_assert(sizeof(Ctrs) <= 256, "the box follows the counters 256 bytes later");
 
@@ -668,7 +669,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     launch_cut_flags(pyr, P.lam_w, WC_CAP, U32(P.fw), U8(P.lw_), P.d0, st);
     scan_exclusive(U32(P.fw), U32(P.ew), P.W3, &ctrs->num_wc, stemp, st);
     launch_cut_table(pyr, P.lam_w, U32(P.fw), U32(P.ew), U8(P.lw_), U8(P.w_level), U64(P.w_key), U32(P.w_count),
-                     U64(P.w_start), WC_CAP, nullptr, P.maxW, &ctrs->internal_error, st);
+                     U64(P.w_start), WC_CAP, &ctrs->wc_over, P.maxW, &ctrs->internal_error, st);
     // cell -> chunk id and cell -> work-chunk id tables (in place of the scans)
     launch_cell_ids(U32(P.fc), U32(P.ec), P.G3, st);
     launch_cell_ids(U32(P.fw), U32(P.ew), P.W3, st);
@@ -769,8 +770,10 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     launch_fill_u32(reinterpret_cast<uint32_t *>(U8(P.t)), 0xffffffffu, (n + 3) / 4, st);
     launch_global_depths(A, n, U32(P.gtab), st);
     t_sub.begin(st);
-    launch_subsample_small(A, st);
-    launch_subsample_big(A, st);
+    // the class above WC_CAP points and the global-memory list are launched
+    // only when the counters read back show they can hold work chunks
+    launch_subsample_small(A, hctrs->wc_over != 0, st);
+    if (hctrs->wc_over || hctrs->wc_flags[0] || !subsample_fast_only(A)) launch_subsample_big(A, st);
     t_sub.end(st);
     scan_exclusive(U32(P.alive), U32(P.alive_scan), (uint64_t)MAXD * num_wc, U32(P.alive_scan) + (uint64_t)MAXD * num_wc,
                    stemp, st);

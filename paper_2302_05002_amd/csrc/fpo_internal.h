@@ -188,7 +188,10 @@ struct WcArgs {
 // get t = d, and the reaching-count rows of those depths are written.
 // gtab: 4 * 8^(d0 - 1 + s) bytes.
 void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream_t st);
-void launch_subsample_small(const WcArgs &a, hipStream_t st);
+// Work chunks above WC_CAP points (class 5) exist only when any_over.
+void launch_subsample_small(const WcArgs &a, bool any_over, hipStream_t st);
+// Every work chunk takes a fast class (own root a leaf): no general subtree.
+inline bool subsample_fast_only(const WcArgs &a) { return a.L >= WC_CAP && a.s <= 7; }
 void launch_subsample_big(const WcArgs &a, hipStream_t st);
 void launch_decide(const WcArgs &a, hipStream_t st);
 void launch_node_counts(const WcArgs &a, uint32_t *owned, hipStream_t st);

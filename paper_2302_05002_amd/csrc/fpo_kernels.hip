@@ -3037,7 +3037,7 @@ void launch_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_
     hipLaunchKernelGGL(k_u32_to_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, in, out, n);
 }
 
-void launch_subsample_small(const WcArgs &a, hipStream_t st)
+void launch_subsample_small(const WcArgs &a, bool any_over, hipStream_t st)
 {
     if (a.num_wc == 0) return;
     hipLaunchKernelGGL(k_list_classes, dim3(grid_for(a.num_wc, 256)), dim3(256), 0, st, a);
@@ -3053,11 +3053,12 @@ void launch_subsample_small(const WcArgs &a, hipStream_t st)
     hipLaunchKernelGGL((k_subsample_fast<256, 8, 12>), dim3(gs), dim3(256), 0, st, a, 3);
     hipLaunchKernelGGL((k_subsample_fast<512, 8, 13>), dim3(gs), dim3(512), 0, st, a, 4);
     // oversized work chunks at the deepest work-chunk level (dense clusters)
-    hipLaunchKernelGGL((k_subsample_fast<1024, 8, 14>), dim3(gs < 2048 ? gs : 2048), dim3(1024), 0, st, a, 5);
+    if (any_over)
+        hipLaunchKernelGGL((k_subsample_fast<1024, 8, 14>), dim3(gs < 2048 ? gs : 2048), dim3(1024), 0, st, a, 5);
     // the general subtree: single-wave blocks for the small classes, many per
     // CU.  Only work chunks with more than L points or subsample grids above
     // 2^7 go there, so with L >= WC_CAP and s <= 7 these classes stay empty
-    if (a.L >= WC_CAP && a.s <= 7) return;
+    if (subsample_fast_only(a)) return;
     hipLaunchKernelGGL((k_subsample_lds<64, 4>), dim3(gs), dim3(64), 0, st, a, WC_GENERAL + 0);
     hipLaunchKernelGGL((k_subsample_lds<64, 8>), dim3(gs), dim3(64), 0, st, a, WC_GENERAL + 1);
     hipLaunchKernelGGL((k_subsample_lds<64, 16>), dim3(gs), dim3(64), 0, st, a, WC_GENERAL + 2);
