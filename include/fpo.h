@@ -68,8 +68,10 @@ typedef enum {
     FPO_ERR_OUT_OF_MEMORY = 3, /* workspace too small, or a host/device allocation failed */
     FPO_ERR_DEVICE = 4,        /* a HIP runtime call failed */
     FPO_NOT_READY = 5,         /* poll: the build is still running */
-    FPO_ERR_REJECTED = 6,      /* reserved for admission control */
-    FPO_ERR_CANCELLED = 7      /* reserved */
+    FPO_ERR_REJECTED = 6,      /* fpo_server_submit: the build needs more than the server's whole budget */
+    FPO_ERR_CANCELLED = 7,     /* wait/poll of a batch or server job taken out of its queue by fpo_job_cancel */
+    FPO_ERR_TIMEOUT = 8        /* a wait on another host thread of the library (a job not yet started, a build
+                                  still being enqueued) exceeded FPO_WAIT_LIMIT_MS (environment; default 300000) */
 } fpo_status;
 
 typedef struct fpo_context fpo_context;
@@ -156,8 +158,16 @@ typedef struct {
 } fpo_result;
 
 /* Creates a context on HIP device `device` (its streams, events and pinned
- * host staging).  *out receives the handle; destroy it with
- * fpo_context_destroy after every job of it has been released. */
+ * host staging).  *out receives the handle.  With FPO_FAULT=alloc:<k> in the
+ * environment at creation, the k-th allocation the context makes (pinned
+ * staging, events, streams, server arenas; counted from 1) fails as if the
+ * memory were exhausted, for failure tests: the call that needed it returns
+ * FPO_ERR_OUT_OF_MEMORY and the context stays usable.
+ *
+ * fpo_context_destroy drops the caller's handle and never blocks.  Every job
+ * and server holds its context, so jobs may still be waited for, read and
+ * released afterwards; the streams, threads and staging are freed when the
+ * last of them is released. */
 fpo_status fpo_context_create(int device, fpo_context **out);
 void fpo_context_destroy(fpo_context *ctx);
 
@@ -198,14 +208,21 @@ fpo_status fpo_job_preview_ready(fpo_job *job);
  * the error that ended it.  Never blocks. */
 fpo_status fpo_job_poll(fpo_job *job);
 
-/* Blocks until the build is complete; returns its status. */
+/* Blocks until the build is complete; returns its status.  A batch or
+ * server job that does not start within FPO_WAIT_LIMIT_MS (default 300 s)
+ * returns FPO_ERR_TIMEOUT instead (the job stays valid; wait again or
+ * release it). */
 fpo_status fpo_job_wait(fpo_job *job);
 
 /* Fills *out for a completed job (call after fpo_job_wait returned FPO_OK). */
 fpo_status fpo_job_result(fpo_job *job, fpo_result *out);
 
 /* Waits for the job if it still runs, then frees the handle (not the
- * workspace). */
+ * workspace; a server job's share of the arena returns to the server).  A job
+ * that has not started is taken out of its queue first.  If a batch or
+ * server job is still being enqueued after FPO_WAIT_LIMIT_MS, the handle is
+ * left allocated rather than freed under its worker, and fpo_last_error says
+ * so. */
 void fpo_job_release(fpo_job *job);
 
 /* Packed host copy of a completed job's arrays, for tests and export: the
@@ -298,8 +315,10 @@ fpo_status fpo_server_submit(fpo_server *srv, const fpo_cloud *cloud, const fpo_
  * wait then returns FPO_ERR_CANCELLED.  FPO_ERR_INVALID_ARG once it started. */
 fpo_status fpo_job_cancel(fpo_job *job);
 
-/* Waits for every queued and running request, then frees the arena.  Release
- * the jobs of the server first: their results live in the arena. */
+/* Drops the caller's handle and never blocks.  Queued and running requests
+ * go on; every served job holds its server, whose arena (where the job's
+ * results live) and slot streams are freed when the last job has been
+ * released.  No further fpo_server_submit may use the handle. */
 void fpo_server_destroy(fpo_server *srv);
 
 /* ---- kernel timing (for benchmarks) ----------------------------------------

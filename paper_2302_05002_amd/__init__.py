@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libfpo.so")
 
 FPO_OK, FPO_ERR_INVALID_ARG, FPO_ERR_NONFINITE, FPO_ERR_OUT_OF_MEMORY = 0, 1, 2, 3
 FPO_ERR_DEVICE, FPO_NOT_READY, FPO_ERR_REJECTED, FPO_ERR_CANCELLED = 4, 5, 6, 7
+FPO_ERR_TIMEOUT = 8
 FPO_BBOX_GIVEN = 1
 FPO_PREVIEW_STRIDE = 2
 FPO_PREVIEW_GRID = 4
@@ -324,7 +325,7 @@ class Context:
         _check(_lib.fpo_build_submit(self._h, ctypes.byref(cloud), ctypes.byref(params.to_c()),
                                      ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                      ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
-        return Job(h, workspace, params, (x, y, z))
+        return Job(h, workspace, params, (x, y, z), self)
 
     def las_decode(self, records, header: _LasHeader, origin=(0.0, 0.0, 0.0), rgb: bool = False, n=None,
                    stream=None):
@@ -380,8 +381,11 @@ class Context:
 
     def build(self, x, y, z, params: Params, workspace=None, stream=None) -> "Result":
         job = self.submit(x, y, z, params, workspace, stream)
-        job.wait()
-        return job.result()
+        try:
+            job.wait()
+            return job.result()
+        finally:
+            job.release()   # the result views the workspace, not the job
 
     def build_batch(self, clouds, params, workspace=None, stream=None) -> list:
         """Enqueue one build per (x, y, z) device-tensor triple in `clouds`,
@@ -412,7 +416,7 @@ class Context:
         hs = (ctypes.c_void_p * count)()
         _check(_lib.fpo_build_batch(self._h, cs, ps, count, ctypes.c_void_p(workspace.data_ptr()),
                                     workspace.numel(), ctypes.c_void_p(stream.cuda_stream), hs))
-        return [Job(ctypes.c_void_p(hs[i]), workspace, params[i], clouds[i]) for i in range(count)]
+        return [Job(ctypes.c_void_p(hs[i]), workspace, params[i], clouds[i], self) for i in range(count)]
 
 
 class Server:
@@ -435,7 +439,7 @@ class Server:
         cloud = _Cloud(n, x.data_ptr(), y.data_ptr(), z.data_ptr())
         h = ctypes.c_void_p()
         _check(_lib.fpo_server_submit(self._h, ctypes.byref(cloud), ctypes.byref(params.to_c()), ctypes.byref(h)))
-        return Job(h, None, params, (x, y, z))
+        return Job(h, None, params, (x, y, z), self)
 
     def close(self):
         if self._h:
@@ -450,11 +454,16 @@ class Server:
 
 
 class Job:
-    def __init__(self, h, workspace, params, inputs):
+    """One build.  It keeps its owner (the Context or Server that made it)
+    alive, so whatever order handles are dropped in, a job is released before
+    its owner is destroyed (the library also counts these references)."""
+
+    def __init__(self, h, workspace, params, inputs, owner):
         self._h = h
         self.workspace = workspace
         self.params = params
         self._inputs = inputs
+        self._owner = owner
 
     def preview_ready(self) -> bool:
         st = _lib.fpo_job_preview_ready(self._h)

@@ -5,6 +5,7 @@
 #include <mutex>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 #include <string>
 #include <vector>
@@ -39,6 +40,37 @@ uint64_t now_ns()
 {
     return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
                std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+std::chrono::milliseconds wait_limit()
+{
+    static const long long ms = [] {
+        const char *v = getenv("FPO_WAIT_LIMIT_MS");
+        const long long t = v ? strtoll(v, nullptr, 10) : 0;
+        return t > 0 ? t : 300000ll;
+    }();
+    return std::chrono::milliseconds(ms);
+}
+
+bool alloc_fault(fpo_context *c)
+{
+    if (!c || !c->fault_at) return false;
+    return c->allocs.fetch_add(1) + 1 == c->fault_at;
+}
+
+void ctx_retain(fpo_context *c) { c->refs.fetch_add(1); }
+
+void ctx_release(fpo_context *c)
+{
+    if (c->refs.fetch_sub(1) != 1) return;
+    // last reference: no job, batch or server of the context is left
+    (void)hipSetDevice(c->device);
+    destroy_batch_pool(c);
+    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+    for (void *p : c->pinned_free) (void)hipHostFree(p);
+    for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(c->stream);
+    delete c;
 }
 
 }  // namespace fpo
@@ -267,7 +299,7 @@ void *get_pinned(fpo_context *c)
         return p;
     }
     void *p = nullptr;
-    if (hipHostMalloc(&p, PINNED_BYTES, hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (alloc_fault(c) || hipHostMalloc(&p, PINNED_BYTES, hipHostMallocDefault) != hipSuccess) return nullptr;
     return p;
 }
 
@@ -288,7 +320,7 @@ hipEvent_t get_event(fpo_context *c)
         }
     }
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (alloc_fault(c) || hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
 
@@ -333,9 +365,11 @@ fpo_status fpo_context_create(int device, fpo_context **out)
     HIPCHK(hipSetDevice(device));
     fpo_context *c = new fpo_context();
     c->device = device;
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    if (const char *f = getenv("FPO_FAULT"))
+        if (strncmp(f, "alloc:", 6) == 0) c->fault_at = strtoull(f + 6, nullptr, 10);
+    if (alloc_fault(c) || hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
-        return fail(FPO_ERR_DEVICE, "hipStreamCreate failed");
+        return fail(FPO_ERR_OUT_OF_MEMORY, "could not create the context's stream");
     }
     *out = c;
     return FPO_OK;
@@ -343,14 +377,7 @@ fpo_status fpo_context_create(int device, fpo_context **out)
 
 void fpo_context_destroy(fpo_context *c)
 {
-    if (!c) return;
-    (void)hipSetDevice(c->device);
-    destroy_batch_pool(c);
-    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
-    for (void *p : c->pinned_free) (void)hipHostFree(p);
-    for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
-    (void)hipStreamDestroy(c->stream);
-    delete c;
+    if (c) ctx_release(c);
 }
 
 fpo_status fpo_workspace_size(uint64_t n, const fpo_params *p, uint64_t *bytes)
@@ -468,16 +495,18 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     job->t_done = 0;
     job->grid_cells = P.G3;
     job->params = *p;
+    job->ev_preview = job->ev_done = nullptr;
     job->pinned = get_pinned(ctx);
     if (!job->pinned) {
         delete job;
         return fail(FPO_ERR_OUT_OF_MEMORY, "pinned host staging allocation failed");
     }
-    if (hipEventCreateWithFlags(&job->ev_preview, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&job->ev_done, hipEventDisableTiming) != hipSuccess) {
+    if (alloc_fault(ctx) || hipEventCreateWithFlags(&job->ev_preview, hipEventDisableTiming) != hipSuccess ||
+        alloc_fault(ctx) || hipEventCreateWithFlags(&job->ev_done, hipEventDisableTiming) != hipSuccess) {
+        if (job->ev_preview) (void)hipEventDestroy(job->ev_preview);
         put_pinned(ctx, job->pinned);
         delete job;
-        return fail(FPO_ERR_DEVICE, "hipEventCreate failed");
+        return fail(FPO_ERR_OUT_OF_MEMORY, "could not create the job's events");
     }
 
     char *ws = static_cast<char *>(workspace);
@@ -592,11 +621,12 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         hipStream_t cs;
         {
             std::lock_guard<std::mutex> g(ctx->mu);
-            if (!ctx->copy_stream && hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking) != hipSuccess)
+            if (!ctx->copy_stream &&
+                (alloc_fault(ctx) || hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking) != hipSuccess))
                 ctx->copy_stream = nullptr;
             cs = ctx->copy_stream;
         }
-        if (!cs) return end_job(fail(FPO_ERR_DEVICE, "could not create the copy stream"));
+        if (!cs) return end_job(fail(FPO_ERR_OUT_OF_MEMORY, "could not create the copy stream"));
         float *dx = reinterpret_cast<float *>(ws + P.xyz);
         float *dy = reinterpret_cast<float *>(ws + P.xyz + a256(4 * n));
         float *dz = reinterpret_cast<float *>(ws + P.xyz + 2 * a256(4 * n));

@@ -2,12 +2,19 @@
 // their own, for batched builds (fpo_build_batch) and for the request server
 // (fpo_server_*), and the server's device memory arena.
 //
+// Lifetimes: every job holds a reference to its context (and a served job one
+// to its server), so handles may be released in any order; destroying a
+// context or a server only drops the owner's reference and never blocks.  The
+// last release tears the object down.  Waits on other host threads are
+// bounded by wait_limit() and end with FPO_ERR_TIMEOUT.
+//
 // Small and mid-sized builds are latency bound: a few dozen short kernels
 // and two short host round trips each.  Running several on separate streams
 // keeps the device busy while one build waits for the host, and lets the
 // kernels of different builds share the compute units.  Jobs are handed out
 // before their build starts; every job call first waits for that start.
 #include <algorithm>
+#include <atomic>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -59,6 +66,7 @@ struct Pool {
 };
 
 struct Server {
+    std::atomic<int> refs{1};   // the owner's plus one per job submitted
     fpo_context *ctx = nullptr;
     uint64_t budget = 0;
     uint32_t max_slots = 0;
@@ -70,6 +78,12 @@ struct Server {
     uint32_t running = 0;
     Pool *pool = nullptr;
 };
+
+}  // namespace fpo
+
+struct fpo_server : fpo::Server {};
+
+namespace fpo {
 
 namespace {
 
@@ -142,10 +156,11 @@ Pool *make_pool(fpo_context *ctx, Server *server, int workers)
     P->server = server;
     for (int i = 0; i < workers; ++i) {
         hipStream_t st = nullptr;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) break;
+        if (alloc_fault(ctx) || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) break;
         P->streams.push_back(st);
     }
-    if (P->streams.empty()) {
+    if ((int)P->streams.size() < workers) {
+        for (hipStream_t st : P->streams) (void)hipStreamDestroy(st);
         delete P;
         return nullptr;
     }
@@ -260,6 +275,7 @@ bool server_remove_waiting(Server *S, fpo_job *job)
 
 fpo_job *new_deferred_job(fpo_context *ctx)
 {
+    ctx_retain(ctx);   // dropped by deferred_release (or free_unqueued)
     fpo_job *job = new fpo_job();
     job->ctx = ctx;
     job->stream = nullptr;
@@ -272,6 +288,29 @@ fpo_job *new_deferred_job(fpo_context *ctx)
     job->t_done = 0;
     job->def = new Deferred();
     return job;
+}
+
+// A job that was never queued (an error before the batch was handed over).
+void free_unqueued(fpo_job *job)
+{
+    fpo_context *ctx = job->ctx;
+    if (job->def->after) (void)hipEventDestroy(job->def->after);
+    delete job->def;
+    delete job;
+    ctx_release(ctx);
+}
+
+void server_release(Server *S)
+{
+    if (S->refs.fetch_sub(1) != 1) return;
+    // last reference: the owner destroyed the server and every job of it has
+    // been released, so nothing waits, runs or holds arena memory
+    fpo_context *ctx = S->ctx;
+    stop_pool(S->pool);
+    (void)hipSetDevice(ctx->device);
+    (void)hipFree(S->arena);
+    delete static_cast<fpo_server *>(S);
+    ctx_release(ctx);
 }
 
 fpo_status check_cloud(const fpo_cloud *c, const fpo_params *p)
@@ -310,7 +349,9 @@ fpo_status deferred_resolve(fpo_job *job, bool block, bool preview, fpo_job **in
         return d->state == Deferred::QUEUED || d->state == Deferred::RUNNING ||
                (!preview && d->state == Deferred::PREVIEW);
     };
-    if (block) d->cv.wait(lk, [&] { return !pending(); });
+    if (block && !d->cv.wait_for(lk, wait_limit(), [&] { return !pending(); }))
+        return fail(FPO_ERR_TIMEOUT, "gave up after %lld ms waiting for the build to be enqueued",
+                    (long long)wait_limit().count());
     if (pending()) return FPO_NOT_READY;
     switch (d->state) {
     case Deferred::PREVIEW:
@@ -347,9 +388,15 @@ void deferred_release(fpo_job *job)
     (void)cancel_queued(job);   // a job that has not started never will
     {
         std::unique_lock<std::mutex> lk(d->m);
-        d->cv.wait(lk, [&] {
-            return d->state != Deferred::QUEUED && d->state != Deferred::RUNNING && d->state != Deferred::PREVIEW;
-        });
+        if (!d->cv.wait_for(lk, wait_limit(), [&] {
+                return d->state != Deferred::QUEUED && d->state != Deferred::RUNNING && d->state != Deferred::PREVIEW;
+            })) {
+            // its build is still being enqueued: leave the job (and its
+            // references) alive rather than free what the worker still uses
+            (void)fail(FPO_ERR_TIMEOUT, "release gave up after %lld ms; the job was left allocated",
+                 (long long)wait_limit().count());
+            return;
+        }
     }
     if (d->inner) fpo_job_release(d->inner);
     if (d->server && d->has_memory) {
@@ -362,8 +409,12 @@ void deferred_release(fpo_job *job)
         S->cv.notify_all();
     }
     if (d->after) (void)hipEventDestroy(d->after);
+    Server *S = d->server;
+    fpo_context *ctx = job->ctx;
     delete d;
     delete job;
+    if (S) server_release(S);
+    ctx_release(ctx);
 }
 
 void destroy_batch_pool(fpo_context *ctx)
@@ -403,8 +454,6 @@ fpo_status queue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
 }
 
 }  // namespace fpo
-
-struct fpo_server : fpo::Server {};
 
 using namespace fpo;
 
@@ -471,17 +520,13 @@ fpo_status fpo_build_batch(fpo_context *ctx, const fpo_cloud *clouds, const fpo_
         d->pool = P;
         bool ok = true;
         if (hip_stream) {
-            ok = hipEventCreateWithFlags(&d->after, hipEventDisableTiming) == hipSuccess;
+            ok = !alloc_fault(ctx) && hipEventCreateWithFlags(&d->after, hipEventDisableTiming) == hipSuccess;
             if (!ok) d->after = nullptr;
             ok = ok && hipEventRecord(d->after, static_cast<hipStream_t>(hip_stream)) == hipSuccess;
         }
         if (!ok) {   // nothing is queued yet: undo
-            for (uint32_t k = 0; k <= i; ++k) {
-                if (jobs[k]->def->after) (void)hipEventDestroy(jobs[k]->def->after);
-                delete jobs[k]->def;
-                delete jobs[k];
-            }
-            return fail(FPO_ERR_DEVICE, "could not record an event on the caller's stream");
+            for (uint32_t k = 0; k <= i; ++k) free_unqueued(jobs[k]);
+            return fail(FPO_ERR_OUT_OF_MEMORY, "could not record an event on the caller's stream");
         }
     }
     // largest first: the small builds fill in behind the long ones
@@ -505,7 +550,7 @@ fpo_status fpo_server_create(fpo_context *ctx, uint64_t hbm_budget_bytes, uint32
     S->budget = budget;
     S->max_slots = max_slots;
     void *arena = nullptr;
-    if (hipMalloc(&arena, budget) != hipSuccess) {
+    if (alloc_fault(ctx) || hipMalloc(&arena, budget) != hipSuccess) {
         delete S;
         return fail(FPO_ERR_OUT_OF_MEMORY, "could not allocate the %llu-byte arena", (unsigned long long)budget);
     }
@@ -515,8 +560,9 @@ fpo_status fpo_server_create(fpo_context *ctx, uint64_t hbm_budget_bytes, uint32
     if (!S->pool) {
         (void)hipFree(arena);
         delete S;
-        return fail(FPO_ERR_DEVICE, "could not create the slot streams");
+        return fail(FPO_ERR_OUT_OF_MEMORY, "could not create the slot streams");
     }
+    ctx_retain(ctx);   // dropped when the server is torn down
     *out = S;
     return FPO_OK;
 }
@@ -536,6 +582,7 @@ fpo_status fpo_server_submit(fpo_server *S, const fpo_cloud *cloud, const fpo_pa
     d->params = *params;
     d->ws_bytes = bytes;
     d->server = S;
+    S->refs.fetch_add(1);   // dropped by the job's release
     *out = job;
     {
         std::lock_guard<std::mutex> g(S->m);
@@ -547,15 +594,9 @@ fpo_status fpo_server_submit(fpo_server *S, const fpo_cloud *cloud, const fpo_pa
 
 void fpo_server_destroy(fpo_server *S)
 {
-    if (!S) return;
-    {
-        std::unique_lock<std::mutex> lk(S->m);
-        S->cv.wait(lk, [&] { return S->waiting.empty() && S->running == 0; });
-    }
-    stop_pool(S->pool);
-    (void)hipSetDevice(S->ctx->device);
-    (void)hipFree(S->arena);
-    delete S;
+    // queued and running requests go on; the arena is freed when the last
+    // job of the server has been released
+    if (S) server_release(S);
 }
 
 }  // extern "C"

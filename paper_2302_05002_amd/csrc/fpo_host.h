@@ -3,6 +3,8 @@
 // executors (batch, server) use.  Not part of the public C ABI.
 #pragma once
 #include <stdint.h>
+#include <atomic>
+#include <chrono>
 #include <functional>
 #include <mutex>
 #include <string>
@@ -22,6 +24,10 @@ std::string error_text();
 fpo_status check_params(uint64_t n, const fpo_params *p);
 uint64_t workspace_bytes(uint64_t n, const fpo_params &p, bool host_input = false);   // worst case of one build
 uint64_t now_ns();                                           // steady clock
+// Longest time a library call waits on another host thread (a job that has
+// not started, a build still being enqueued) before it gives up with
+// FPO_ERR_TIMEOUT: FPO_WAIT_LIMIT_MS from the environment, else 300 s.
+std::chrono::milliseconds wait_limit();
 
 struct Deferred;   // job created before its build starts (batch, server)
 struct Pool;       // worker threads with their own streams
@@ -29,6 +35,14 @@ struct Pool;       // worker threads with their own streams
 }  // namespace fpo
 
 struct fpo_context {
+    // The owner's reference plus one per live batch, server or plain job and
+    // one per server: the context is torn down when the last one is dropped,
+    // so a job released after fpo_context_destroy still finds its context.
+    std::atomic<int> refs{1};
+    // FPO_FAULT=alloc:<k> at creation: the k-th allocation the context makes
+    // (pinned staging, events, streams, server arenas) fails, counted from 1.
+    uint64_t fault_at = 0;
+    std::atomic<uint64_t> allocs{0};
     int device;
     hipStream_t stream;
     std::mutex mu;
@@ -60,6 +74,11 @@ struct fpo_job {
 };
 
 namespace fpo {
+
+void ctx_retain(fpo_context *c);
+void ctx_release(fpo_context *c);   // tears the context down at zero references
+// True when the allocation about to be made is the one FPO_FAULT names.
+bool alloc_fault(fpo_context *c);
 
 // For a deferred job: FPO_OK with *inner once its build has been enqueued
 // whole (preview: once its preview kernels have), the status that ended it
