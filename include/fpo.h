@@ -446,6 +446,26 @@ fpo_status fpo_select_nodes(fpo_context *ctx, uint64_t num_nodes, const uint8_t 
                             const fpo_view *view, void *workspace, uint64_t workspace_bytes, uint32_t *out_nodes,
                             uint32_t *out_totals, void *hip_stream);
 
+/* ---- node selection without allocation ------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, render or serving loops that forbid hipMalloc): fpo_select_nodes
+ * with the library's own static scratch in place of a workspace.  That
+ * scratch is FPO_SELECT_STATIC_BYTES of device memory per device, held from
+ * the first fpo_context_create on that device until the process ends; it
+ * serves tables of at most FPO_SELECT_STATIC_MAX_NODES nodes.  Arguments,
+ * outputs and results are those of fpo_select_nodes; the call makes no
+ * hipMalloc, hipFree or other allocating call.  FPO_ERR_INVALID_ARG for more
+ * than FPO_SELECT_STATIC_MAX_NODES nodes, before anything is enqueued.
+ * Every call on a device shares that device's scratch: calls that overlap on
+ * one device (two streams, or two threads) race and give wrong results;
+ * calls in order on one stream are safe. */
+#define FPO_SELECT_STATIC_MAX_NODES 4194304u
+#define FPO_SELECT_STATIC_BYTES 655360u
+fpo_status fpo_select_nodes_static(fpo_context *ctx, uint64_t num_nodes, const uint8_t *node_depth,
+                                   const uint64_t *node_key, const uint32_t *node_count, const float bbox_min[3],
+                                   float cube_size, const fpo_view *view, uint32_t *out_nodes, uint32_t *out_totals,
+                                   void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,7 +34,10 @@ EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_w
            "fpo_job_timestamps", "fpo_batch_workspace_size", "fpo_build_batch", "fpo_server_create",
            "fpo_server_submit", "fpo_job_cancel", "fpo_server_destroy", "fpo_context_set_timing", "fpo_context_set_timers", "fpo_job_timer",
            "fpo_preview_modulus", "fpo_las_parse_header", "fpo_las_header_box", "fpo_las_decode",
-           "fpo_select_workspace_size", "fpo_select_nodes")
+           "fpo_select_workspace_size", "fpo_select_nodes", "fpo_select_nodes_static")
+#: fpo_select_nodes_static's limits (include/fpo.h)
+SELECT_STATIC_MAX_NODES = 4194304
+SELECT_STATIC_BYTES = 655360
 
 # fpo_timer values (include/fpo.h)
 TIMERS = {"bbox": 0, "quantize": 1, "chunk_scatter": 2, "subsample": 3, "node_counts": 4, "node_place": 5,
@@ -137,6 +140,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_select_nodes.argtypes = [vp, ctypes.c_uint64, vp, vp, vp, P(ctypes.c_float), ctypes.c_float, P(_View),
                                      vp, ctypes.c_uint64, vp, vp, vp]
     lib.fpo_select_nodes.restype = ctypes.c_int
+    lib.fpo_select_nodes_static.argtypes = [vp, ctypes.c_uint64, vp, vp, vp, P(ctypes.c_float), ctypes.c_float,
+                                            P(_View), vp, vp, vp]
+    lib.fpo_select_nodes_static.restype = ctypes.c_int
     lib.fpo_preview_modulus.argtypes = [ctypes.c_uint64, ctypes.c_uint64, P(ctypes.c_uint32)]
     lib.fpo_preview_modulus.restype = ctypes.c_int
     lib.fpo_workspace_size_cloud.argtypes = [P(_Cloud), P(_Params), P(ctypes.c_uint64)]
@@ -378,6 +384,30 @@ class Context:
         stream.synchronize()
         t = totals.cpu().tolist()
         return out[:t[0]], t[1]
+
+    def select_nodes_static(self, node_depth, node_key, node_count, bbox_min, cube_size, view: _View, out=None,
+                            totals=None, stream=None):
+        """select_nodes without a workspace (fpo_select_nodes_static: the
+        library's static scratch, at most SELECT_STATIC_MAX_NODES nodes).
+        Enqueues on `stream` and returns (out, totals) device tensors without
+        synchronising: out[:totals[0]] are the drawn nodes, totals[1] their
+        points.  Pass preallocated out / totals to allocate nothing here."""
+        import torch
+        n = int(node_depth.shape[0])
+        dev = node_depth.device if n else torch.device("cuda", self.device)
+        if out is None:
+            out = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        if totals is None:
+            totals = torch.empty(2, dtype=torch.int32, device=dev)
+        stream, back = _ordered_stream(dev, stream)
+        lo = (ctypes.c_float * 3)(*[float(v) for v in bbox_min])
+        ptr = (lambda t: ctypes.c_void_p(t.data_ptr() if n else 0))
+        _check(_lib.fpo_select_nodes_static(self._h, n, ptr(node_depth), ptr(node_key), ptr(node_count), lo,
+                                            float(cube_size), ctypes.byref(view), ctypes.c_void_p(out.data_ptr()),
+                                            ctypes.c_void_p(totals.data_ptr()), ctypes.c_void_p(stream.cuda_stream)))
+        if back is not None:
+            back.wait_stream(stream)
+        return out, totals
 
     def build(self, x, y, z, params: Params, workspace=None, stream=None) -> "Result":
         job = self.submit(x, y, z, params, workspace, stream)

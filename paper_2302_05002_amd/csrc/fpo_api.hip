@@ -363,6 +363,10 @@ fpo_status fpo_context_create(int device, fpo_context **out)
     HIPCHK(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) return fail(FPO_ERR_INVALID_ARG, "device %d out of range (%d devices)", device, count);
     HIPCHK(hipSetDevice(device));
+    {
+        const fpo_status si = select_static_init(device);
+        if (si != FPO_OK) return si;
+    }
     fpo_context *c = new fpo_context();
     c->device = device;
     if (const char *f = getenv("FPO_FAULT"))

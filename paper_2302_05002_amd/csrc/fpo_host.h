@@ -75,6 +75,10 @@ struct fpo_job {
 
 namespace fpo {
 
+// Records the device address of fpo_select_nodes_static's scratch for the
+// current device (once per device; fpo_context_create calls it).
+fpo_status select_static_init(int device);
+
 void ctx_retain(fpo_context *c);
 void ctx_release(fpo_context *c);   // tears the context down at zero references
 // True when the allocation about to be made is the one FPO_FAULT names.

@@ -7,6 +7,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include <hip/hip_runtime.h>
 
 #include "fpo_host.h"
@@ -125,31 +127,23 @@ SelPlan sel_plan(uint64_t n)
     return p;
 }
 
-}  // namespace
+// Scratch of fpo_select_nodes_static, for callers that cannot allocate: one
+// selection's bit map, tile counts, tile offsets and scan partials.  Each
+// device holds its own copy for the life of the process.  Every word a call
+// reads was written earlier in the same call, so nothing needs clearing.
+static_assert(FPO_SELECT_STATIC_BYTES % 256 == 0, "whole 256-byte blocks");
+__device__ __align__(256) unsigned char scratch[FPO_SELECT_STATIC_BYTES];
 
-extern "C" {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices];   // device address of `scratch`, per device
 
-fpo_status fpo_select_workspace_size(uint64_t num_nodes, uint64_t *bytes)
+// Validates a selection and enqueues it with the workspace at ws.
+fpo_status select_nodes(fpo_context *ctx, uint64_t num_nodes, const uint8_t *node_depth, const uint64_t *node_key,
+                        const uint32_t *node_count, const float bbox_min[3], float cube_size, const fpo_view *view,
+                        char *ws, uint32_t *out_nodes, uint32_t *out_totals, void *hip_stream)
 {
-    if (!bytes) return fail(FPO_ERR_INVALID_ARG, "bytes is NULL");
-    if (num_nodes > 0xffffffffull) return fail(FPO_ERR_INVALID_ARG, "num_nodes exceeds 2^32 - 1");
-    *bytes = sel_plan(num_nodes).total;
-    return FPO_OK;
-}
-
-fpo_status fpo_select_nodes(fpo_context *ctx, uint64_t num_nodes, const uint8_t *node_depth, const uint64_t *node_key,
-                            const uint32_t *node_count, const float bbox_min[3], float cube_size,
-                            const fpo_view *view, void *workspace, uint64_t workspace_bytes, uint32_t *out_nodes,
-                            uint32_t *out_totals, void *hip_stream)
-{
-    if (!ctx || !bbox_min || !view || !out_totals) return fail(FPO_ERR_INVALID_ARG, "NULL context, box, view or totals");
-    if (num_nodes > 0xffffffffull) return fail(FPO_ERR_INVALID_ARG, "num_nodes exceeds 2^32 - 1");
-    if (num_nodes && (!node_depth || !node_key || !node_count || !out_nodes))
-        return fail(FPO_ERR_INVALID_ARG, "NULL node array or output");
     const SelPlan P = sel_plan(num_nodes);
-    if (!workspace || workspace_bytes < P.total || (reinterpret_cast<uintptr_t>(workspace) & 255))
-        return fail(FPO_ERR_INVALID_ARG, "workspace must be 256-byte aligned with %llu bytes",
-                    (unsigned long long)P.total);
     bool finite = isfinite(cube_size) && isfinite(view->proj_factor) && view->proj_factor > 0.0 &&
                   !isnan(view->min_size) && view->min_size >= 0.0;
     for (int k = 0; k < 3; ++k) finite = finite && isfinite(bbox_min[k]) && isfinite(view->eye[k]);
@@ -160,7 +154,6 @@ fpo_status fpo_select_nodes(fpo_context *ctx, uint64_t num_nodes, const uint8_t 
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return fail(FPO_ERR_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
     hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->stream;
-    char *ws = static_cast<char *>(workspace);
     fpo::launch_fill_u32(out_totals, 0u, 2, st);
     if (num_nodes) {
         SelArgs a;
@@ -189,6 +182,85 @@ fpo_status fpo_select_nodes(fpo_context *ctx, uint64_t num_nodes, const uint8_t 
     e = hipGetLastError();
     if (e != hipSuccess) return fail(FPO_ERR_DEVICE, "node selection launch: %s", hipGetErrorString(e));
     return FPO_OK;
+}
+
+fpo_status check_select_args(fpo_context *ctx, uint64_t num_nodes, const uint8_t *node_depth, const uint64_t *node_key,
+                             const uint32_t *node_count, const float bbox_min[3], const fpo_view *view,
+                             uint32_t *out_nodes, uint32_t *out_totals)
+{
+    if (!ctx || !bbox_min || !view || !out_totals) return fail(FPO_ERR_INVALID_ARG, "NULL context, box, view or totals");
+    if (num_nodes > 0xffffffffull) return fail(FPO_ERR_INVALID_ARG, "num_nodes exceeds 2^32 - 1");
+    if (num_nodes && (!node_depth || !node_key || !node_count || !out_nodes))
+        return fail(FPO_ERR_INVALID_ARG, "NULL node array or output");
+    return FPO_OK;
+}
+
+}  // namespace
+
+namespace fpo {
+
+// Called by fpo_context_create with `device` current: records the device
+// address of the static scratch once per device.
+fpo_status select_static_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(FPO_ERR_DEVICE, "device %d beyond %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch[device]) return FPO_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(FPO_ERR_DEVICE, "hipGetSymbolAddress of the selection scratch: %s", hipGetErrorString(e));
+    g_scratch[device] = ptr;
+    return FPO_OK;
+}
+
+}  // namespace fpo
+
+extern "C" {
+
+fpo_status fpo_select_workspace_size(uint64_t num_nodes, uint64_t *bytes)
+{
+    if (!bytes) return fail(FPO_ERR_INVALID_ARG, "bytes is NULL");
+    if (num_nodes > 0xffffffffull) return fail(FPO_ERR_INVALID_ARG, "num_nodes exceeds 2^32 - 1");
+    *bytes = sel_plan(num_nodes).total;
+    return FPO_OK;
+}
+
+fpo_status fpo_select_nodes(fpo_context *ctx, uint64_t num_nodes, const uint8_t *node_depth, const uint64_t *node_key,
+                            const uint32_t *node_count, const float bbox_min[3], float cube_size,
+                            const fpo_view *view, void *workspace, uint64_t workspace_bytes, uint32_t *out_nodes,
+                            uint32_t *out_totals, void *hip_stream)
+{
+    const fpo_status s =
+        check_select_args(ctx, num_nodes, node_depth, node_key, node_count, bbox_min, view, out_nodes, out_totals);
+    if (s != FPO_OK) return s;
+    const SelPlan P = sel_plan(num_nodes);
+    if (!workspace || workspace_bytes < P.total || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return fail(FPO_ERR_INVALID_ARG, "workspace must be 256-byte aligned with %llu bytes",
+                    (unsigned long long)P.total);
+    return select_nodes(ctx, num_nodes, node_depth, node_key, node_count, bbox_min, cube_size, view,
+                        static_cast<char *>(workspace), out_nodes, out_totals, hip_stream);
+}
+
+fpo_status fpo_select_nodes_static(fpo_context *ctx, uint64_t num_nodes, const uint8_t *node_depth,
+                                   const uint64_t *node_key, const uint32_t *node_count, const float bbox_min[3],
+                                   float cube_size, const fpo_view *view, uint32_t *out_nodes, uint32_t *out_totals,
+                                   void *hip_stream)
+{
+    const fpo_status s =
+        check_select_args(ctx, num_nodes, node_depth, node_key, node_count, bbox_min, view, out_nodes, out_totals);
+    if (s != FPO_OK) return s;
+    if (num_nodes > FPO_SELECT_STATIC_MAX_NODES || sel_plan(num_nodes).total > FPO_SELECT_STATIC_BYTES)
+        return fail(FPO_ERR_INVALID_ARG, "%llu nodes: the static scratch holds at most %u",
+                    (unsigned long long)num_nodes, (unsigned)FPO_SELECT_STATIC_MAX_NODES);
+    char *ws = nullptr;
+    if (ctx->device >= 0 && ctx->device < kMaxDevices) {
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        ws = static_cast<char *>(g_scratch[ctx->device]);
+    }
+    if (!ws) return fail(FPO_ERR_DEVICE, "the static scratch of device %d has no address", ctx->device);
+    return select_nodes(ctx, num_nodes, node_depth, node_key, node_count, bbox_min, cube_size, view, ws, out_nodes,
+                        out_totals, hip_stream);
 }
 
 }  // extern "C"

@@ -98,3 +98,19 @@ def test_preview_flags(lib):
         h = fpo.workspace_size(1000, fpo.Params(count_grid=G))
         assert fpo.workspace_size(1000, fpo.Params(count_grid=G, preview="stride")) == h
         assert fpo.workspace_size(1000, fpo.Params(count_grid=G, preview="grid")) >= h + 8 * G ** 3
+
+
+def test_static_selection_scratch_covers_its_maximum(lib):
+    """fpo_select_nodes_static's fixed scratch holds the workspace of its
+    largest allowed node table (and the header and binding agree on both)."""
+    import paper_2302_05002_amd as fpo
+    fpo.load_library(LIB)
+    src = open(HDR).read()
+    max_nodes = int(re.search(r"#define FPO_SELECT_STATIC_MAX_NODES (\d+)u", src).group(1))
+    nbytes = int(re.search(r"#define FPO_SELECT_STATIC_BYTES (\d+)u", src).group(1))
+    assert (max_nodes, nbytes) == (fpo.SELECT_STATIC_MAX_NODES, fpo.SELECT_STATIC_BYTES)
+    need = ctypes.c_uint64()
+    for n in (0, 1, 4097, max_nodes - 1, max_nodes):
+        assert fpo.load_library().fpo_select_workspace_size(n, ctypes.byref(need)) == fpo.FPO_OK
+        assert need.value <= nbytes, n
+    assert nbytes <= 1 << 20   # a modest, fixed amount per device
