@@ -6,7 +6,10 @@ count, pyramid + chunk cut, stable scatter, node subsample, preview) of one
 synthetic cloud whose coordinates are already resident in HBM.  Default
 workload: 20,000,000 points on 200 random planes (count grid 128^3, chunks of
 at most 1,000,000 points, subsample grid 128^3, leaf capacity 10,000, preview
-modulus 64).  Prints one JSON line.
+modulus 64).  The same line reports the plain 1M-point build, the 256-cloud
+batch against the plain loop, the 2,000-request served trace against serial
+plain builds, the streamed 200M-point build, and the CPU oracle on the host's
+cores.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -28,58 +31,103 @@ WORKLOADS = {
 }
 
 
-def algorithmic_bytes(n: int, G: int, M: int) -> int:
-    """Bytes the whole path must move: bbox read 12/pt, quantise+count read
-    12/pt, scatter read 12 + write 4 /pt, subsample read perm 4 + gather 12 +
-    write node_points 4 /pt, histogram written and read once (8 G^3), preview
-    4 N/M."""
-    return 60 * n + 8 * G ** 3 + 4 * n // M
+def algorithmic_bytes(n: int, G: int, M: int, given: bool = False) -> int:
+    """Bytes the whole path must move: bbox read 12/pt (none with a given
+    box), quantise+count read 12/pt, scatter read 12 + write 4 /pt, subsample
+    read perm 4 + gather 12 + write node_points 4 /pt, histogram written and
+    read once (8 G^3), preview 4 per kept index (about n/M)."""
+    return (48 if given else 60) * n + 8 * G ** 3 + 4 * -(-n // M)
 
 
-# Algorithmic bytes of each timed kernel per build, from the per-step figures
-# above: (bytes(n, G, M), what they are).
-KERNEL_BYTES = {
-    "bbox": (lambda n, G, M: 12 * n, "read x, y, z once: 12 B/pt"),
-    "quantize": (lambda n, G, M: 12 * n + 4 * G ** 3, "read x, y, z again: 12 B/pt; write the count grid: 4 B/cell"),
-    "chunk_scatter": (lambda n, G, M: 16 * n, "re-read the points 12 B/pt, write perm 4 B/pt"),
-    "subsample": (lambda n, G, M: 16 * n, "read perm 4 B/pt, gather the coordinates once 12 B/pt"),
-    "node_counts": (None, "rows per (depth, work chunk), not per point"),
-    "node_place": (lambda n, G, M: 9 * n, "read each point's depth 1 B and original index 4 B, write it 4 B"),
-    "node_sort": (lambda n, G, M: 8 * n, "read and write every node's points once: 8 B/pt"),
+# The path's steps as groups of the library's timed regions (fpo_timer), each
+# with its share of the algorithmic bytes above, so that the groups add up to
+# the whole path: (regions, bytes(n, G, M, given), what the bytes are).
+GROUPS = {
+    "a1 bbox": (("bbox",), lambda n, G, M, gv: 0 if gv else 12 * n, "read x, y, z once: 12 B/pt"),
+    "a1 quantize + count": (("quantize",), lambda n, G, M, gv: 12 * n + 4 * G ** 3,
+                            "read x, y, z again 12 B/pt; write the count grid 4 B/cell"),
+    "a2 pyramid + chunk cut": (("cut",), lambda n, G, M, gv: 4 * G ** 3, "read the count grid once: 4 B/cell"),
+    "a3 stable scatter": (("chunk_split",), lambda n, G, M, gv: 16 * n,
+                          "re-read the points 12 B/pt; write perm 4 B/pt"),
+    "a4 node subsample": (("subsample",), lambda n, G, M, gv: 16 * n,
+                          "read perm 4 B/pt; gather the coordinates once 12 B/pt"),
+    "a4 node_points": (("node_counts", "node_place", "node_sort"), lambda n, G, M, gv: 4 * n,
+                       "write node_points once: 4 B/pt"),
+    "a5 preview": (("preview",), lambda n, G, M, gv: 4 * -(-n // M), "write every kept index: 4 B each"),
 }
 
-KERNEL_NAMES = {
-    "bbox": "fpo::k_bbox",
-    "quantize": "fpo::k_quantize",
-    "chunk_scatter": "fpo::k_ms_scatter<false, 8> (split into chunks)",
-    "subsample": "fpo::k_subsample_* (all size classes)",
-    "node_counts": "fpo::k_np_pieces + scan + fpo::k_np_shared + fpo::k_np_count",
-    "node_place": "fpo::k_np_place",
-    "node_sort": "fpo::k_np_sort (four tile sizes) + fpo::k_np_merge",
+GROUP_KERNELS = {
+    "a1 bbox": "fpo::k_fill_u32 (count grid), fpo::k_bbox, fpo::k_setup",
+    "a1 quantize + count": "fpo::k_quantize<false>",
+    "a2 pyramid + chunk cut": "fpo::k_pyr_*, k_grid_export, k_cut_flags, scans, k_cut_table, k_cell_ids, k_wc_chunks*",
+    "a3 stable scatter": "chunk begins (scans, k_u32_to_u64), fpo::k_ms_count<false, 8>, scan, fpo::k_ms_scatter<false, 8>",
+    "a4 node subsample": "work-chunk split (fpo::k_ms_*<true, 12>), fpo::k_gdepth_*, fpo::k_wc_alive_rows, "
+                         "fpo::k_list_classes, fpo::k_subsample_*, fpo::k_decide, fpo::k_node_counts, scans",
+    "a4 node_points": "fpo::k_np_pieces/k_np_shared/k_np_count, fpo::k_node_fill, fpo::k_np_lists, fpo::k_np_place, "
+                      "fpo::k_np_sort, fpo::k_np_merge",
+    "a5 preview": "fpo::k_preview_bits, fpo::k_bits_count, scan, fpo::k_bits_write",
 }
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per build of `kernel` from the committed FETCH_SIZE /
-    WRITE_SIZE readings (profiles/traffic.json), scaled by the plain-copy
-    calibration factors; None when there is no reading for this kernel and
-    workload or the sources changed since it was taken."""
+def measured_traffic(group: str, workload: str):
+    """HBM bytes per build of a group from the committed FETCH_SIZE /
+    WRITE_SIZE readings of its regions (profiles/traffic.json), scaled by the
+    plain-copy calibration factors; None when a region has no reading for
+    this workload or the sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
     from paper_2302_05002_amd.prof import source_digest
-    e = t.get("kernels", {}).get(f"{workload}/{kernel}")
-    if not e or e.get("source_digest") != source_digest():
-        return None
-    kib = e["fetch_kib"] * t["read_factor"] + e["write_kib"] * t["write_factor"]
-    return kib * 1024.0
+    dig = source_digest()
+    total = 0.0
+    for reg in GROUPS[group][0]:
+        e = t.get("kernels", {}).get(f"{workload}/{reg}")
+        if not e or e.get("source_digest") != dig:
+            return None
+        total += e["fetch_kib"] * t["read_factor"] + e["write_kib"] * t["write_factor"]
+    return total * 1024.0
 
 
-def cpu_baseline(cloud, p, seconds: float) -> dict:
-    """The CPU oracle as it stands (single thread) on the same workload,
-    repeated until `seconds` of work are done."""
+def host_cpu() -> dict:
+    """The host's CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count()}
+
+
+def _oracle_worker(args):
+    """One all-cores worker: builds its own copy of the workload `builds`
+    times with the oracle; returns (points built, seconds)."""
+    gen, pname, builds, barrier_at = args
+    import synth
+    import oracle
+    c = getattr(synth, gen)()
+    p = getattr(synth, pname)
+    op = oracle.Params(p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity, p.preview_modulus)
+    while time.time() < barrier_at:   # start together
+        time.sleep(0.001)
+    t = time.perf_counter()
+    for _ in range(builds):
+        r = oracle.build_octree(c.x, c.y, c.z, op)
+        assert r["status"] == oracle.OK
+    return c.n * builds, time.perf_counter() - t
+
+
+def cpu_baseline(cloud, p, seconds: float, gen: str, pname: str) -> dict:
+    """The CPU oracle as it stands on the same workload: one thread, repeated
+    until `seconds` of work are done; then all cores, as independent
+    single-threaded oracle processes (one per core this process may use, at
+    most 16), each building its own copy of the workload twice.  The oracle
+    itself is unchanged: all-cores is throughput over concurrent builds."""
     import oracle
     op = oracle.Params(p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity, p.preview_modulus)
     runs, t_total = 0, 0.0
@@ -89,9 +137,22 @@ def cpu_baseline(cloud, p, seconds: float) -> dict:
         t_total += time.perf_counter() - t
         assert r["status"] == oracle.OK
         runs += 1
-    return {"value": runs * cloud.n / t_total, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"the whole {cloud.n}-point workload, built {runs} times in {t_total:.1f} s "
-                      f"(single-threaded C, host CPU)"}
+    single = runs * cloud.n / t_total
+    cpu = host_cpu()
+    procs = max(1, min(16, cpu["nproc"]))
+    import multiprocessing as mp
+    builds = 2
+    with mp.get_context("spawn").Pool(procs) as pool:
+        start = time.time() + 4.0 + 0.05 * procs   # time for every worker to generate its copy
+        res = pool.map(_oracle_worker, [(gen, pname, builds, start)] * procs)
+    pts = sum(a for a, _ in res)
+    wall = max(b for _, b in res)
+    return {"value": pts / wall, "unit": "points/s", "cores": procs, "kind": "oracle",
+            "sample": f"{procs} concurrent single-threaded oracle builds of the whole {cloud.n}-point workload, "
+                      f"{builds} each ({procs * builds} builds in {wall:.1f} s of wall time)",
+            "cpu": cpu,
+            "single_thread": {"value": single, "unit": "points/s", "cores": 1,
+                              "sample": f"the whole workload built {runs} times in {t_total:.1f} s"}}
 
 
 def fpo_params_of(fpo, p):
@@ -110,26 +171,28 @@ def plain_loop(fpo, torch, ctx, items, ws):
         job.release()
 
 
-def bench_batched(fpo, torch, ctx, rounds: int = 3) -> dict:
-    """The batched workload at reduced scale: a pool of 32 clouds, sizes
-    log-uniform in [10k, 4M], kinds uniform / planes (5-200) / clusters
-    (10-500), per-size parameters; the batch is the pool repeated `rounds`
-    times.  One fpo_build_batch call against the serial loop of plain builds
-    over the same clouds."""
+def bench_batched(fpo, torch, ctx) -> dict:
+    """The batched workload: 256 clouds, sizes log-uniform in [10k, 4M],
+    kinds uniform / planes (5-200) / clusters (10-500), per-size parameters
+    (about 150M points).  One fpo_build_batch call against the serial loop of
+    plain builds (submit, wait, release) over the same clouds."""
     import synth
-    mix = synth.batch_mix(32, seed=4)
-    pool = [(to_device(torch, c), fpo_params_of(fpo, p)) for c, p in mix]
-    items = pool * rounds
+    t = time.perf_counter()
+    mix = synth.batch_mix(256, seed=4)
+    items = [(to_device(torch, c), fpo_params_of(fpo, p)) for c, p in mix]
+    del mix
+    print(f"[bench] batched workload ready in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
     points = sum(int(x.shape[0]) for (x, _, _), _ in items)
-    ws = torch.empty(max(fpo.workspace_size(int(x.shape[0]), p) for (x, _, _), p in pool), dtype=torch.uint8,
+    ws = torch.empty(max(fpo.workspace_size(int(x.shape[0]), p) for (x, _, _), p in items), dtype=torch.uint8,
                      device="cuda")
-    plain_loop(fpo, torch, ctx, pool, ws)   # warm-up
+    plain_loop(fpo, torch, ctx, items, ws)   # warm-up
     torch.cuda.synchronize()
     t = time.perf_counter()
     plain_loop(fpo, torch, ctx, items, ws)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t
     del ws
+    torch.cuda.empty_cache()
     clouds = [c for c, _ in items]
     params = [p for _, p in items]
     jobs = ctx.build_batch(clouds, params)   # warm-up (also sizes the workspace)
@@ -138,61 +201,90 @@ def bench_batched(fpo, torch, ctx, rounds: int = 3) -> dict:
         j.wait()
         j.release()
     torch.cuda.synchronize()
-    t = time.perf_counter()
-    jobs = ctx.build_batch(clouds, params, workspace=bws)
-    for j in jobs:
-        j.wait()
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t
-    for j in jobs:
-        j.release()
-    return {"workload": f"{len(items)} builds: a pool of 32 clouds (10k-4M points, log-uniform; uniform, planes, "
-                        f"clusters) repeated {rounds} times", "points": points,
-            "plain_points_per_s": points / t_plain, "batched_points_per_s": points / t_batch,
-            "speedup": t_plain / t_batch}
+    reps = 3
+    t_batch = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        jobs = ctx.build_batch(clouds, params, workspace=bws)
+        for j in jobs:
+            j.wait()
+        torch.cuda.synchronize()
+        t_batch.append(time.perf_counter() - t)
+        for j in jobs:
+            j.release()
+    tb = sorted(t_batch)[reps // 2]
+    return {"workload": "256 clouds (10k-4M points, log-uniform; uniform, planes, clusters; per-size G, C, S)",
+            "clouds": len(items), "points": points, "batch_workspace_bytes": int(bws.numel()),
+            "plain_points_per_s": points / t_plain, "batched_points_per_s": points / tb,
+            "plain_ms": 1000 * t_plain, "batched_ms": 1000 * tb, "speedup": t_plain / tb}
 
 
-def bench_served(fpo, torch, ctx, num_requests: int = 64, load: float = 1.25, slots: int = 4) -> dict:
-    """The served workload at reduced scale: requests drawn from a pool of 12
-    clouds (100k-8M points, log-uniform, mixed kinds), Poisson arrivals at
-    `load` times the measured capacity of the serial plain loop.  Latency =
-    completion - arrival; throughput = points / makespan."""
+class ServedTrace:
+    """The served workload, generated once: 2,000 requests with sizes
+    log-uniform in [100k, 50M] (about 16G points), each the first n points of
+    one of three 50M-point pool clouds (uniform, planes, clusters) resident on
+    the device, per-size parameters."""
+
+    def __init__(self, fpo, torch):
+        import synth
+        t = time.perf_counter()
+        pool, self.reqs = synth.serve_trace(2000, seed=5)
+        self.dev = [to_device(torch, c) for c in pool]
+        del pool
+        self.params = [fpo_params_of(fpo, synth.params_for_size(r.n)) for r in self.reqs]
+        self.points = sum(r.n for r in self.reqs)
+        self.need = [fpo.workspace_size(r.n, p) for r, p in zip(self.reqs, self.params)]
+        print(f"[bench] served trace ready in {time.perf_counter() - t:.1f}s ({self.points} points)",
+              file=sys.stderr, flush=True)
+
+    def cloud(self, i):
+        r = self.reqs[i]
+        return tuple(a[:r.n] for a in self.dev[r.kind])
+
+    def serial(self, fpo, torch, ctx) -> float:
+        """Points/s of the serial plain loop over the whole trace (one
+        workspace, sized for the largest request)."""
+        ws = torch.empty(max(self.need), dtype=torch.uint8, device="cuda")
+        items = [(self.cloud(i), p) for i, p in enumerate(self.params)]
+        plain_loop(fpo, torch, ctx, items[:50], ws)   # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        plain_loop(fpo, torch, ctx, items, ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        del ws
+        torch.cuda.empty_cache()
+        return self.points / dt
+
+
+def bench_served(fpo, torch, ctx, trace: ServedTrace, serial_pps: float, load: float, slots: int = 4,
+                 budget: int = 200 * 10 ** 9) -> dict:
+    """Requests submitted on their Poisson schedule, rescaled so that the
+    offered load is `load` times the serial plain loop's capacity, into a
+    server with `slots` slots and an HBM budget of `budget` bytes.  A client
+    thread collects results in arrival order and releases each at once (a
+    request holds its share of the budget until then).  Latency = completion
+    - arrival; throughput = points / makespan."""
     import numpy as np
-    import synth
-    mix = synth.batch_mix(12, seed=5, lo=100_000, hi=8_000_000)
-    pool = [(to_device(torch, c), fpo_params_of(fpo, p)) for c, p in mix]
-    rng = np.random.default_rng(5)
-    reqs = [pool[int(k)] for k in rng.integers(0, len(pool), num_requests)]
-    points = sum(int(x.shape[0]) for (x, _, _), _ in reqs)
-    need = [fpo.workspace_size(int(x.shape[0]), p) for (x, _, _), p in reqs]
-    ws = torch.empty(max(need), dtype=torch.uint8, device="cuda")
-    plain_loop(fpo, torch, ctx, pool, ws)   # warm-up
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    plain_loop(fpo, torch, ctx, reqs, ws)
-    torch.cuda.synchronize()
-    t_serial = time.perf_counter() - t
-    del ws
-    serial_pps = points / t_serial
-    rate = load * serial_pps / (points / num_requests)   # requests per second
-    gaps = rng.exponential(1.0 / rate, num_requests)
-    budget = int(min(64 << 30, 8 * sum(sorted(need)[-slots:])))
-    srv = fpo.Server(ctx, budget, slots)
-    for (x, y, z), p in pool[:slots]:            # warm-up of the slot streams
-        j = srv.submit(x, y, z, p)
-        j.wait()
-        j.release()
-    # a client thread collects the results in arrival order and releases them
-    # at once (a request holds its share of the budget until then), while
-    # this thread submits on the arrival schedule
     import queue
     import threading
+    reqs = trace.reqs
+    num = len(reqs)
+    rate = load * serial_pps / (trace.points / num)   # requests per second
+    mean_gap = reqs[-1].arrival / max(num - 1, 1)
+    scale = (1.0 / rate) / mean_gap
+    srv = fpo.Server(ctx, budget, slots)
+    for i in range(slots):   # warm-up of the slot streams
+        j = srv.submit(*trace.cloud(i), trace.params[i])
+        j.wait()
+        j.release()
     pending = queue.Queue()
     lat = []
     span = [None, None]
 
     def collect():
-        for _ in range(num_requests):
+        for _ in range(num):
             j = pending.get()
             j.wait()
             sub, _, done = j.timestamps()
@@ -203,23 +295,25 @@ def bench_served(fpo, torch, ctx, num_requests: int = 64, load: float = 1.25, sl
 
     client = threading.Thread(target=collect)
     client.start()
-    due = time.monotonic()
-    for ((x, y, z), p), g in zip(reqs, gaps):
-        due += g
+    t0 = time.monotonic()
+    for i, r in enumerate(reqs):
+        due = t0 + r.arrival * scale
         rest = due - time.monotonic()
         if rest > 1e-3:
             time.sleep(rest - 5e-4)   # (sleeping lets the client thread run)
         while time.monotonic() < due:
             pass
-        pending.put(srv.submit(x, y, z, p))
+        pending.put(srv.submit(*trace.cloud(i), trace.params[i]))
     client.join()
-    first, last = span
     srv.close()
+    first, last = span
     lat = np.array(lat)
-    return {"workload": f"{num_requests} requests from a pool of 12 clouds (100k-8M points, log-uniform; uniform, "
-                        f"planes, clusters), Poisson arrivals at {load}x the serial capacity, {slots} slots",
-            "points": points, "serial_points_per_s": serial_pps, "served_points_per_s": points / ((last - first) / 1e9),
-            "speedup": points / ((last - first) / 1e9) / serial_pps,
+    served = trace.points / ((last - first) / 1e9)
+    return {"workload": f"{num} requests (100k-50M points, log-uniform; uniform, planes, clusters), Poisson "
+                        f"arrivals at {load}x the serial capacity, {slots} slots, {budget / 1e9:.0f} GB budget",
+            "requests": num, "points": trace.points, "serial_points_per_s": serial_pps,
+            "served_points_per_s": served, "speedup": served / serial_pps,
+            "makespan_s": (last - first) / 1e9,
             "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99))}
 
 
@@ -271,6 +365,92 @@ def bench_streamed(fpo, torch, ctx, steps: int = 3) -> dict:
             "points_per_s": n / t_build, "ms_per_build": 1000 * t_build,
             "h2d_GBps": link / 1e9, "link_frac": (12 * n / link) / t_build,
             "preview_ready_ms": 1000 * sorted(previews)[len(previews) // 2]}
+
+
+def measure(fpo, torch, ctx, xyz, params, ws, stream, steps: int, workload: str, p, given: bool = False) -> dict:
+    """Timed plain builds of one workload.
+
+    A few builds with every region timed give the split per group and the
+    dominant group (most device time per build).  Then `steps` builds are
+    submitted back to back on one stream and workspace and waited for
+    together (a build's host round trips overlap the device work of the one
+    before), with HIP events around the dominant group's regions only, so
+    its duration is measured live over the timed region."""
+    x, y, z = xyz
+    n = int(x.shape[0])
+    G, M = p.count_grid, p.preview_modulus
+
+    def timed_builds(k: int, only):
+        ctx.set_timing(True, only)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        jobs = [ctx.submit(x, y, z, params, workspace=ws, stream=stream) for _ in range(k)]
+        for job in jobs:
+            job.wait()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        acc = {name: [0.0, 0] for name in fpo.TIMERS}
+        for job in jobs:
+            for name in only:
+                ms_k, nl = job.timer(name)
+                acc[name][0] += ms_k
+                acc[name][1] += nl
+            job.release()
+        ctx.set_timing(False)
+        return tb - ta, acc
+
+    split_builds = max(2, min(steps, 5))
+    _, split = timed_builds(split_builds, list(fpo.TIMERS))
+    group_ms = {g: sum(split[r][0] for r in regs) / split_builds for g, (regs, _, _) in GROUPS.items()}
+    dom = max(group_ms, key=group_ms.get)
+    secs, timers = timed_builds(steps, list(GROUPS[dom][0]))
+    ms = secs * 1000.0 / steps
+    b_alg = algorithmic_bytes(n, G, M, given)
+    dom_ms = sum(timers[r][0] for r in GROUPS[dom][0]) / steps
+    dom_brackets = sum(timers[r][1] for r in GROUPS[dom][0]) / steps
+    dom_bytes = GROUPS[dom][1](n, G, M, given)
+    achieved = dom_bytes / (dom_ms / 1000.0) / 1e9
+    groups = {}
+    for g, (regs, fn, rule) in GROUPS.items():
+        b = fn(n, G, M, given)
+        t = group_ms[g]
+        groups[g] = {"ms": t, "algorithmic_bytes": b, "GBps": b / (t / 1000.0) / 1e9 if t > 0 else None,
+                     "frac": b / (t / 1000.0) / 1e9 / HBM_PEAK_GBS if t > 0 else None, "bytes_rule": rule,
+                     "regions": list(regs)}
+    device_ms = sum(group_ms.values())
+    assert sum(fn(n, G, M, given) for _, fn, _ in GROUPS.values()) == b_alg
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, workload),
+                "kernel": f"{dom}: {GROUP_KERNELS[dom]}", "algorithmic_bytes": dom_bytes,
+                "bytes_rule": GROUPS[dom][2], "ms_per_build": dom_ms, "brackets_per_build": dom_brackets,
+                "groups": groups, "split_builds": split_builds}
+    path = {"algorithmic_bytes": b_alg, "bytes_rule": "60 B/pt + 8 B per count-grid cell + 4 B per kept index "
+                                                      "(48 B/pt with a given box)",
+            "device_ms_per_build": device_ms, "achieved_device_GBps": b_alg / (device_ms / 1000.0) / 1e9,
+            "frac_of_device_time": b_alg / (device_ms / 1000.0) / 1e9 / HBM_PEAK_GBS,
+            "ms_per_build": ms, "frac_of_step": b_alg / (ms / 1000.0) / 1e9 / HBM_PEAK_GBS}
+    return {"ms_per_build": ms, "roofline": roofline, "path": path}
+
+
+def bench_config1(fpo, torch, ctx, steps: int) -> dict:
+    """The plain 1M-point build (uniform cube, G=64, C=100k, S=32, L=10k,
+    M=64): ms per build and the fraction of HBM peak for the whole path."""
+    import synth
+    p = synth.CONFIG1
+    c = synth.config1()
+    xyz = to_device(torch, c)
+    params = fpo_params_of(fpo, p)
+    ws = torch.empty(fpo.workspace_size(c.n, params), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        job = ctx.submit(*xyz, params, workspace=ws, stream=stream)
+        job.wait()
+        job.release()
+    res = measure(fpo, torch, ctx, xyz, params, ws, stream, max(steps, 50), "uniform1m", p)
+    return {"workload": "1M uniform points, G=64, C=100k, S=32, L=10k, M=64", "n": c.n,
+            "ms_per_build": res["ms_per_build"], "points_per_s": c.n / (res["ms_per_build"] / 1000.0),
+            "path": res["path"], "roofline": res["roofline"],
+            "target": "<= 15.5 us per build (50% of HBM peak for the path's algorithmic bytes)"}
 
 
 def main():
@@ -492,55 +672,9 @@ def main():
 
     if not args.no_extras:
         extras["node_selection"] = bench_select()
-    def timed_builds(k: int, only=None):
-        """k builds submitted back to back (same stream and workspace, so they
-        run one after another on the device) and waited for together: the host
-        work of a build (its two read-backs and launches) overlaps the end of
-        the one before, as for any caller with more than one cloud to build.
-        Returns (seconds, {timer: [ms summed over the builds, launches]})."""
-        ctx.set_timing(True, only)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        jobs = [ctx.submit(x, y, z, params, workspace=ws, stream=stream) for _ in range(k)]
-        for job in jobs:
-            job.wait()
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        acc = {name: [0.0, 0] for name in KERNEL_BYTES}
-        for job in jobs:
-            for name in KERNEL_BYTES:
-                ms_k, nl = job.timer(name)
-                acc[name][0] += ms_k
-                acc[name][1] += nl
-            job.release()
-        ctx.set_timing(False)
-        return tb - ta, acc
-
-    # kernel timers (HIP events on the build's stream): every group on a few
-    # builds to find the dominant one and the split, then the timed region
-    # with events around the dominant group only (fewer events, less
-    # perturbation), its duration measured live there
-    split_builds = max(2, min(args.steps, 5))
-    _, split = timed_builds(split_builds)
-    dom = max(split, key=lambda k: split[k][0])
-    secs, timers = timed_builds(args.steps, [dom])
-    ms = secs * 1000.0 / args.steps
+    res = measure(fpo, torch, ctx, (x, y, z), params, ws, stream, args.steps, args.workload, p)
+    ms = res["ms_per_build"]
     value = n / (ms / 1000.0)
-    b_alg = algorithmic_bytes(n, p.count_grid, p.preview_modulus)
-
-    # dominant kernel: the most device time per build (from the split builds)
-    dom_ms = timers[dom][0] / args.steps
-    dom_launches = timers[dom][1] / args.steps
-    fn = KERNEL_BYTES[dom][0]
-    dom_bytes = fn(n, p.count_grid, p.preview_modulus) if fn else None
-    achieved = dom_bytes / (dom_ms / 1000.0) / 1e9 if dom_bytes else None
-    traffic = measured_traffic(dom, args.workload)
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
-                "kernel": KERNEL_NAMES[dom], "algorithmic_bytes": dom_bytes, "bytes_rule": KERNEL_BYTES[dom][1],
-                "ms_per_build": dom_ms, "launches_per_build": dom_launches,
-                "kernels_ms_per_build": {k: v[0] / split_builds for k, v in split.items()},
-                "split_builds": split_builds}
 
     out = {
         "metric": "octree-build points/s (bit-exact) + %HBM peak; batched/served vs plain",
@@ -558,22 +692,34 @@ def main():
         "config": {"workload": desc, "n": n, "count_grid": p.count_grid, "max_points_per_chunk": p.max_points_per_chunk,
                    "subsample_grid": p.subsample_grid, "leaf_capacity": p.leaf_capacity,
                    "preview_modulus": p.preview_modulus, "parallelism": "single GPU"},
-        "path_hbm_frac": b_alg / (ms / 1000.0) / (HBM_PEAK_GBS * 1e9),
-        "roofline": roofline,
+        "path_hbm_frac": res["path"]["frac_of_step"],
+        "roofline": res["roofline"],
+        "path": res["path"],
         **extras,
     }
+    if args.workload != "uniform1m":
+        out["config1"] = bench_config1(fpo, torch, ctx, args.steps)
+        print(f"[bench] 1M uniform: {out['config1']['ms_per_build']:.3f} ms per build, "
+              f"{out['config1']['path']['frac_of_step']:.4f} of HBM peak", file=sys.stderr, flush=True)
     if not args.no_mix:
         del ws
         torch.cuda.empty_cache()
         out["batched"] = bench_batched(fpo, torch, ctx)
         print(f"[bench] batched {out['batched']['speedup']:.2f}x the plain loop", file=sys.stderr, flush=True)
-        out["served"] = bench_served(fpo, torch, ctx)
+        torch.cuda.empty_cache()
+        trace = ServedTrace(fpo, torch)
+        serial_pps = trace.serial(fpo, torch, ctx)
+        print(f"[bench] serial plain loop over the trace: {serial_pps / 1e9:.2f} G points/s", file=sys.stderr,
+              flush=True)
+        out["served"] = bench_served(fpo, torch, ctx, trace, serial_pps, 1.25)
         print(f"[bench] served {out['served']['speedup']:.2f}x serial, p99 {out['served']['latency_ms_p99']:.1f} ms",
               file=sys.stderr, flush=True)
         # the same trace at half the serial capacity: latency without queueing
-        out["served_half_load"] = bench_served(fpo, torch, ctx, load=0.5)
+        out["served_half_load"] = bench_served(fpo, torch, ctx, trace, serial_pps, 0.5)
         print(f"[bench] served at 0.5x load: p50 {out['served_half_load']['latency_ms_p50']:.1f} ms, "
               f"p99 {out['served_half_load']['latency_ms_p99']:.1f} ms", file=sys.stderr, flush=True)
+        del trace
+        torch.cuda.empty_cache()
     if not args.no_stream:
         if not args.no_mix:
             torch.cuda.empty_cache()
@@ -581,7 +727,7 @@ def main():
         print(f"[bench] streamed {out['streamed']['points_per_s'] / 1e9:.2f} G points/s, "
               f"{out['streamed']['link_frac']:.2f} of the host link", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cloud, p, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(cloud, p, args.cpu_seconds, gen, pname)
     print(json.dumps(out), flush=True)
 
 

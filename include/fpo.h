@@ -322,22 +322,25 @@ fpo_status fpo_job_cancel(fpo_job *job);
 void fpo_server_destroy(fpo_server *srv);
 
 /* ---- kernel timing (for benchmarks) ----------------------------------------
- * With timing enabled on a context, every later submit of it brackets the
- * launches of each timed kernel below with HIP events recorded on the build's
- * stream (a few microseconds of host time per event; off by default).  After
- * fpo_job_wait returned FPO_OK, fpo_job_timer gives the summed device time of
- * a timer's launches and their number (0 launches when the kernel did not run
- * in this build). */
+ * With timing enabled on a context, every later submit of it brackets each
+ * region below with a pair of HIP events recorded on the build's stream (a
+ * few microseconds of host time per event; off by default).  The regions are
+ * contiguous runs of launches that together hold every kernel of a build; only
+ * the build's host round trips fall between them.  After fpo_job_wait
+ * returned FPO_OK, fpo_job_timer gives a region's summed device time and its
+ * number of brackets (0 when the region did not run in this build). */
 typedef enum {
-    FPO_TIMER_BBOX = 0,          /* bounding-box scan, one launch (step 1) */
-    FPO_TIMER_QUANTIZE = 1,      /* quantise + count, one launch (step 1) */
-    FPO_TIMER_CHUNK_SCATTER = 2, /* scatter kernel of the stable split into chunks, one per digit pass (step 3) */
-    FPO_TIMER_SUBSAMPLE = 3,     /* per-work-chunk subsample kernels, every size class, bracketed together (step 4) */
-    FPO_TIMER_NODE_COUNTS = 4,   /* points per node: piece sizes, their scan, node sizes, bracketed together (step 4) */
-    FPO_TIMER_NODE_PLACE = 5,    /* every point into its node's range, one launch (step 4) */
-    FPO_TIMER_PREVIEW = 6,       /* preview kernels (grid minimum, count, scan, write), bracketed together (step 5) */
-    FPO_TIMER_NODE_SORT = 7,     /* node ranges sorted by original index: tile sorts and merge rounds (step 4) */
-    FPO_TIMER_COUNT = 8
+    FPO_TIMER_BBOX = 0,          /* step 1: grid fills, bounding-box passes, box reduction (empty with a given box) */
+    FPO_TIMER_QUANTIZE = 1,      /* step 1: quantise + count (one bracket per streamed batch) */
+    FPO_TIMER_CHUNK_SPLIT = 2,   /* step 3: chunk begins and the stable split into chunks (count, scan, scatter) */
+    FPO_TIMER_SUBSAMPLE = 3,     /* step 4: work-chunk split, shared depths, subsample classes, leaf decision,
+                                    node numbering */
+    FPO_TIMER_NODE_COUNTS = 4,   /* step 4: points per node */
+    FPO_TIMER_NODE_PLACE = 5,    /* step 4: node table, node begins, every point into its node's range */
+    FPO_TIMER_PREVIEW = 6,       /* step 5: counters' fill and the preview kernels */
+    FPO_TIMER_NODE_SORT = 7,     /* step 4: node ranges sorted by original index, merges, 64-bit begins */
+    FPO_TIMER_CUT = 8,           /* step 2: pyramid, count-grid export, chunk and work-chunk cuts */
+    FPO_TIMER_COUNT = 9
 } fpo_timer;
 
 /* enable: 1 to time later submits of ctx (every timer), 0 to stop. */

@@ -40,8 +40,8 @@ SELECT_STATIC_MAX_NODES = 4194304
 SELECT_STATIC_BYTES = 655360
 
 # fpo_timer values (include/fpo.h)
-TIMERS = {"bbox": 0, "quantize": 1, "chunk_scatter": 2, "subsample": 3, "node_counts": 4, "node_place": 5,
-          "preview": 6, "node_sort": 7}
+TIMERS = {"bbox": 0, "quantize": 1, "chunk_split": 2, "subsample": 3, "node_counts": 4, "node_place": 5,
+          "preview": 6, "node_sort": 7, "cut": 8}
 
 
 class FpoError(RuntimeError):

@@ -565,8 +565,15 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         }                                                                                       \
     } while (0)
 
-    launch_fill_u32(reinterpret_cast<uint32_t *>(ctrs), 0u, sizeof(Ctrs) / 4, st);
+    JobTimer t_prev(job, FPO_TIMER_PREVIEW);
+    if (p->flags & (FPO_PREVIEW_GRID)) {
+        launch_fill_u32(reinterpret_cast<uint32_t *>(ctrs), 0u, sizeof(Ctrs) / 4, st);
+    } else {
+        t_prev.begin(st);   // (the preview region opens with the counters' fill)
+        launch_fill_u32(reinterpret_cast<uint32_t *>(ctrs), 0u, sizeof(Ctrs) / 4, st);
+    }
     if (n == 0) {
+        t_prev.end(st);
         launch_fill_u32(U32(P.grid), 0u, P.G3, st);
         JCHK(hipEventRecord(job->ev_preview, st));
         JCHK(hipEventRecord(job->ev_done, st));
@@ -586,11 +593,10 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     pa.code = U64(P.code);
     pa.cellmin = U64(P.cellmin);
     pa.shift = 3 * (KB - g);
-    JobTimer t_prev(job, FPO_TIMER_PREVIEW);
     // ordered compaction of the kept indices, then the preview event (from
     // here on the job belongs to its holder)
     auto emit_preview = [&]() {
-        t_prev.begin(st);
+        if (pa.mode == PV_GRID) t_prev.begin(st);
         uint32_t *bits = U32(P.pv_bits);
         if (pa.mode == PV_GRID && P.G3 <= 2 * n) {
             // fewer cells than 2n: a pass over the cell minima
@@ -614,9 +620,12 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
 
     // ---- step 1: bbox, quantise, count ----
     const int given = (p->flags & FPO_BBOX_GIVEN) ? 1 : 0;
-    JobTimer t_bbox(job, FPO_TIMER_BBOX), t_quant(job, FPO_TIMER_QUANTIZE), t_chunk(job, FPO_TIMER_CHUNK_SCATTER),
-        t_sub(job, FPO_TIMER_SUBSAMPLE), t_ncnt(job, FPO_TIMER_NODE_COUNTS), t_place(job, FPO_TIMER_NODE_PLACE),
-        t_nsort(job, FPO_TIMER_NODE_SORT);
+    // Timed regions (when timing): contiguous runs of launches that together
+    // cover every kernel of the build; only the host round trips fall between
+    // them.
+    JobTimer t_bbox(job, FPO_TIMER_BBOX), t_quant(job, FPO_TIMER_QUANTIZE), t_cut(job, FPO_TIMER_CUT),
+        t_chunk(job, FPO_TIMER_CHUNK_SPLIT), t_sub(job, FPO_TIMER_SUBSAMPLE), t_ncnt(job, FPO_TIMER_NODE_COUNTS),
+        t_place(job, FPO_TIMER_NODE_PLACE), t_nsort(job, FPO_TIMER_NODE_SORT);
     const float *X = cloud->x, *Y = cloud->y, *Z = cloud->z;
     if (host_in) {
         // pinned host input: batches copied into the workspace on the copy
@@ -655,14 +664,19 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     }
     uint32_t *pyr = U32(P.pyr);
     uint32_t *fine = pyr + pyr_off(g);
+    const bool box_region = !given;   // a given box has no bounding-box pass: its fills go with quantise
+    (box_region ? t_bbox : t_quant).begin(st);
     launch_fill_u32(fine, 0u, P.G3, st);
     uint64_t *cellmin = pa.mode == PV_GRID ? U64(P.cellmin) : nullptr;
     if (cellmin) launch_fill_u32(U32(P.cellmin), 0xffffffffu, 2 * P.G3, st);
+    (box_region ? t_bbox : t_quant).end(st);
     if (given) {
         // a given box: no bounding-box pass.  The quantise + count pass of a
         // batch starts as soon as it has landed and also flags non-finite
         // coordinates and counts points outside the box
+        t_quant.begin(st);
         launch_setup(box, U32(P.bbox_part), 0, given, p->bbox_min, p->bbox_max, 0, st);
+        t_quant.end(st);
         size_t bi = 1;
         for (uint64_t o = 0; o < n; o += sbatch) {
             const uint64_t c = n - o < sbatch ? n - o : sbatch;
@@ -684,7 +698,9 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
             t_bbox.end(st);
             nparts += bbox_blocks(c);
         }
+        t_bbox.begin(st);
         launch_setup(box, U32(P.bbox_part), nparts, 0, p->bbox_min, p->bbox_max, 0, st);
+        t_bbox.end(st);
         t_quant.begin(st);
         launch_quantize(X, Y, Z, n, box, g, 0, U64(P.code), fine, box, 0, cellmin, st);
         t_quant.end(st);
@@ -694,6 +710,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     if (pa.mode == PV_GRID) JCHK(emit_preview());
 
     // ---- step 2: pyramid, chunk cut, work-chunk cut ----
+    t_cut.begin(st);
     launch_pyramid(pyr, g, st);
     launch_grid_export(fine, g, U32(P.grid), st);
     launch_cut_flags(pyr, g, p->max_points_per_chunk, U32(P.fc), U8(P.lc), 0, st);
@@ -710,6 +727,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     launch_wc_chunks(&ctrs->num_wc, P.maxW, U64(P.w_key), U8(P.w_level), g, pyr, U32(P.ec), U8(P.c_level),
                      &ctrs->num_chunks, P.maxC, U32(P.wc_chunk), U32(P.seg_b0), U32(P.seg_nb), U8(P.wc_nested),
                      ctrs->wc_flags, st);
+    t_cut.end(st);
     JCHK(hipMemcpyAsync(hctrs, ctrs, 256 + sizeof(DevBox), hipMemcpyDeviceToHost, st));   // counters and box
     JCHK(hipStreamSynchronize(st));
     if (hbox->nonfinite) {
@@ -720,6 +738,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         return end_job(fail(FPO_ERR_DEVICE, "internal: %u chunks, %u work chunks exceed the plan", num_chunks, num_wc));
 
     // chunk begins (u64) and work-chunk begins
+    t_chunk.begin(st);
     scan_exclusive(U32(P.c_count), U32(P.c_count_scan), num_chunks, nullptr, stemp, st);
     launch_u32_to_u64(U32(P.c_count_scan), U64(P.c_begin), num_chunks, st);
     scan_exclusive(U32(P.w_count), U32(P.w_begin), num_wc, nullptr, stemp, st);
@@ -734,10 +753,12 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         MsOutput o;
         o.vals = U32(P.perm);
         o.pay = U64(P.code_perm);
-        multisplit(in, n, num_chunks, o, ws + P.ms_temp, st, &t_chunk);
+        multisplit(in, n, num_chunks, o, ws + P.ms_temp, st);
     }
+    t_chunk.end(st);
     // work-chunk order from perm order: chunk by chunk when every work chunk
     // lies inside one chunk (one pass, few buckets per chunk), else globally
+    t_sub.begin(st);
     {
         MsInput in;
         in.code = U64(P.code_perm);
@@ -803,17 +824,16 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     // the work-chunk levels first, over all points
     launch_fill_u32(reinterpret_cast<uint32_t *>(U8(P.t)), 0xffffffffu, (n + 3) / 4, st);
     launch_global_depths(A, n, U32(P.gtab), st);
-    t_sub.begin(st);
     // the class above WC_CAP points and the global-memory list are launched
     // only when the counters read back show they can hold work chunks
     launch_subsample_small(A, hctrs->wc_over != 0, st);
     if (hctrs->wc_over || hctrs->wc_flags[0] || !subsample_fast_only(A)) launch_subsample_big(A, st);
-    t_sub.end(st);
     scan_exclusive(U32(P.alive), U32(P.alive_scan), (uint64_t)MAXD * num_wc, U32(P.alive_scan) + (uint64_t)MAXD * num_wc,
                    stemp, st);
     launch_decide(A, st);
     launch_node_counts(A, U32(P.owned), st);
     scan_exclusive(U32(P.owned), U32(P.node_base), (uint64_t)MAXD * num_wc, &ctrs->num_nodes, stemp, st);
+    t_sub.end(st);
     // points per node (node_count) need no host count: enqueued before the
     // read-back, they keep the device busy while the host waits for it
     t_ncnt.begin(st);
@@ -824,6 +844,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     JCHK(hipStreamSynchronize(st));
     const uint32_t num_nodes = hctrs->num_nodes;
     if (num_nodes > NP_MAX_NODES) return end_job(fail(FPO_ERR_INVALID_ARG, "%u nodes: at most 2^31 - 1", num_nodes));
+    t_place.begin(st);
     launch_fill_u32(U32(P.n_mask), 0u, (num_nodes + 3) / 4, st);
     launch_node_fill(A, U32(P.node_base), U8(P.n_depth), U64(P.n_key), U8(P.n_mask), st);
     // node_points: every point placed in its node's range, then each range
@@ -849,6 +870,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
                          w, st);
     }
     launch_u32_to_u64(U32(P.np_nb), U64(P.n_begin), num_nodes, st);
+    t_nsort.end(st);
 
     JCHK(hipMemcpyAsync(hctrs, ctrs, 256 + sizeof(DevBox), hipMemcpyDeviceToHost, st));   // counters and box
     JCHK(hipEventRecord(job->ev_done, st));

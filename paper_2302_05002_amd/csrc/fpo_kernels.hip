@@ -3129,7 +3129,6 @@ void launch_np_points(const WcArgs &a, const uint32_t *node_base, const uint32_t
     scan_exclusive(cnt_node, w.nb, num_nodes, w.nb + num_nodes, w.scan_temp, st);
     hipLaunchKernelGGL(k_np_lists, dim3(grid_for(num_nodes, 256, 1024)), dim3(256), 0, st, w.nb, num_nodes, w.lists);
     if (w.general) launch_fill_u32(w.fill, 0u, num_nodes, st);
-    if (w.place_timer) w.place_timer->begin(st);
     const uint32_t pg = (a.num_wc + NPP_WAVES - 1) / NPP_WAVES;
     hipLaunchKernelGGL(k_np_place, dim3(pg < 4096 ? pg : 4096), dim3(64 * NPP_WAVES), 0, st, a, node_base, pnode, poff,
                        w.nb, w.fill, w.tmp, (uint32_t)n, w.err);
@@ -3151,7 +3150,6 @@ void launch_np_points(const WcArgs &a, const uint32_t *node_base, const uint32_t
     for (uint32_t r = 0; r < rounds; ++r)
         hipLaunchKernelGGL(k_np_merge, dim3(njobs < 4096 ? (uint32_t)njobs : 4096), dim3(NPM_BLOCK), 0, st,
                            w.lists.jobs, w.lists.counts + 4, w.nb, (int)r, w.out, w.tmp);
-    if (w.sort_timer) w.sort_timer->end(st);
 }
 
 uint64_t np_list_entries(uint64_t n, int cls)

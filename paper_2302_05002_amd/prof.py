@@ -1,16 +1,21 @@
 """Summaries of rocprofv3 output for the benchmark's kernels.
 
-    python3 -m paper_2302_05002_amd.prof stats  <kernel_stats.csv> <builds>
+    python3 -m paper_2302_05002_amd.prof stats   <kernel_stats.csv> <builds>
         per-kernel device time per build (from a --kernel-trace --stats run)
-    python3 -m paper_2302_05002_amd.prof pmc    <counter_collection.csv> <counter>
-        per-build sum of one counter for each timed kernel group
+    python3 -m paper_2302_05002_amd.prof groups  <kernel_trace.csv> [chunk_passes]
+        device time per build of every timed region (the groups bench.py
+        reports), from the dispatch timestamps
     python3 -m paper_2302_05002_amd.prof traffic <fetch.csv> <write.csv> <workload> <out.json> [chunk_passes]
-        FETCH_SIZE and WRITE_SIZE per build of every timed kernel group, with
-        the digest of the HIP sources they were taken on, merged into out.json
+        FETCH_SIZE and WRITE_SIZE per build of every region, with the digest of
+        the HIP sources they were taken on, merged into out.json
 
-Counter files come from runs of bench.py under ``rocprofv3 --pmc FETCH_SIZE``
-(then ``WRITE_SIZE``); builds are delimited by the bounding-box kernel, which
-every non-empty build launches exactly once.
+Every dispatch of a build is attributed to the region the library's timers
+bracket (include/fpo.h, fpo_timer): preview, bbox, quantize, cut,
+chunk_split, subsample, node_counts, node_place, node_sort.  The attribution
+follows the launch order of a build with the hash or stride preview; builds
+are delimited by the preview kernel, which every non-empty build launches
+once.  Host-to-device and device-to-host copies (runtime blit kernels) belong
+to no region.
 """
 from __future__ import annotations
 
@@ -29,6 +34,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 READ_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 
+REGIONS = ("preview", "bbox", "quantize", "cut", "chunk_split", "subsample", "node_counts", "node_place",
+           "node_sort")
+
 
 def source_digest() -> str:
     """Hash of the HIP sources (counter readings apply only to the code they were taken on)."""
@@ -44,6 +52,45 @@ def _short(name: str) -> str:
     return name.split("(")[0].replace("void ", "").strip()
 
 
+def attribute(names, chunk_passes: int = 1):
+    """Region of every dispatch in `names` (kernel names in dispatch order),
+    or None for runtime copies.  Transitions follow a build's launch order:
+    preview (counters' fill, preview kernels) -> bbox -> quantize -> cut
+    (through k_wc_chunks_nb) -> chunk_split (chunk_passes split passes) ->
+    subsample -> node_counts (k_np_pieces .. k_np_count) -> node_place ->
+    node_sort (from the first k_np_sort)."""
+    out = []
+    state, prev, left = None, "", 0
+    for i, k in enumerate(names):
+        if "__amd_rocclr" in k:
+            out.append(None)
+            continue
+        nxt = next((m for m in names[i + 1:] if "__amd_rocclr" not in m), "")
+        if "k_preview_bits" in k or ("k_fill_u32" in k and "k_preview_bits" in nxt):
+            state = "preview"
+        elif state == "preview" and "k_bits_write" in prev:
+            state = "bbox"
+        elif "k_quantize" in k:
+            state = "quantize"
+        elif state == "quantize":
+            state = "cut"
+        elif state == "cut" and "k_wc_chunks_nb" in prev:
+            state, left = "chunk_split", chunk_passes
+        elif state == "chunk_split" and left == 0:
+            state = "subsample"
+        elif "k_np_pieces" in k:
+            state = "node_counts"
+        elif state == "node_counts" and "k_np_count" in prev:
+            state = "node_place"
+        elif "k_np_sort" in k and state != "node_sort":
+            state = "node_sort"
+        out.append(state)
+        if state == "chunk_split" and "k_ms_scatter<false" in k:
+            left -= 1
+        prev = k
+    return out
+
+
 def stats(path: str, builds: int) -> str:
     rows = list(csv.DictReader(open(path)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
@@ -57,8 +104,29 @@ def stats(path: str, builds: int) -> str:
     return "\n".join(out)
 
 
+def _builds(names) -> int:
+    return sum(1 for k in names if "k_preview_bits" in k)
+
+
+def trace_groups(path: str, chunk_passes: int = 1):
+    """(region -> (ms per build, kernels per build)), builds, from a kernel trace."""
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    names = [r["Kernel_Name"] for r in rows]
+    regs = attribute(names, chunk_passes)
+    nb = _builds(names)
+    ms = defaultdict(float)
+    cnt = defaultdict(int)
+    for r, g in zip(rows, regs):
+        if g is None:
+            continue
+        ms[g] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+        cnt[g] += 1
+    return {g: (ms[g] / nb, cnt[g] / nb) for g in ms}, nb
+
+
 def _dispatches(path: str, counter: str):
-    """[(dispatch_id, kernel, value)] in dispatch order, summed over the counter's instances."""
+    """[(kernel, value)] in dispatch order, summed over the counter's instances."""
     acc = defaultdict(float)
     names = {}
     for r in csv.DictReader(open(path)):
@@ -67,48 +135,19 @@ def _dispatches(path: str, counter: str):
         d = int(r["Dispatch_Id"])
         acc[d] += float(r["Counter_Value"])
         names[d] = r["Kernel_Name"]
-    return [(d, names[d], acc[d]) for d in sorted(acc)]
+    return [(names[d], acc[d]) for d in sorted(acc)]
 
 
 def groups_per_build(path: str, counter: str, chunk_passes: int = 1):
-    """Per build, the counter summed over each timed kernel group (averaged over builds)."""
+    """Per build, the counter summed over each region (averaged over builds)."""
     seq = _dispatches(path, counter)
-    starts = [i for i, (_, k, _) in enumerate(seq) if "k_bbox" in k]
+    names = [k for k, _ in seq]
+    regs = attribute(names, chunk_passes)
+    nb = _builds(names)
     sums = defaultdict(float)
-    nb = 0
-    for bi, s0 in enumerate(starts):
-        s1 = starts[bi + 1] if bi + 1 < len(starts) else len(seq)
-        # the build's preview kernels come before its bounding box
-        b = seq[s0:s1]
-        nb += 1
-        after_quant = in_counts = False
-        chunk_left = chunk_passes
-        for _, k, v in b:
-            if "k_bbox" in k:
-                sums["bbox"] += v
-            elif "k_quantize" in k:
-                sums["quantize"] += v
-                after_quant = True
-            elif "k_subsample" in k or "k_list_classes" in k:
-                sums["subsample"] += v
-            elif "k_np_pieces" in k:
-                sums["node_counts"] += v
-                in_counts = True
-            elif "k_np_shared" in k:
-                sums["node_counts"] += v
-            elif "k_np_count" in k:
-                sums["node_counts"] += v
-                in_counts = False
-            elif in_counts and "k_scan" in k:
-                sums["node_counts"] += v
-            elif "k_np_place" in k:
-                sums["node_place"] += v
-            elif "k_np_sort" in k or "k_np_merge" in k:
-                sums["node_sort"] += v
-            elif "k_ms_scatter<false" in k:
-                if after_quant and chunk_left > 0:
-                    sums["chunk_scatter"] += v
-                    chunk_left -= 1
+    for (_, v), g in zip(seq, regs):
+        if g is not None:
+            sums[g] += v
     return {k: v / nb for k, v in sums.items()}, nb
 
 
@@ -131,11 +170,15 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, out_json: str, chunk_
 def main(argv):
     if argv[0] == "stats":
         print(stats(argv[1], int(argv[2])))
-    elif argv[0] == "pmc":
-        g, nb = groups_per_build(argv[1], argv[2])
-        print(f"{nb} builds; {argv[2]} per build (KiB):")
-        for k, v in sorted(g.items()):
-            print(f"  {k:14s} {v:14.1f}")
+    elif argv[0] == "groups":
+        g, nb = trace_groups(argv[1], *[int(a) for a in argv[2:3]])
+        print(f"{nb} builds; device time per build of every region:")
+        print("| region | kernels/build | ms/build |")
+        print("|---|---:|---:|")
+        for k in REGIONS:
+            if k in g:
+                print(f"| {k} | {g[k][1]:g} | {g[k][0]:.4f} |")
+        print(f"| **all regions** | {sum(v[1] for v in g.values()):g} | {sum(v[0] for v in g.values()):.4f} |")
     elif argv[0] == "traffic":
         extra = [int(a) for a in argv[5:6]]
         d = traffic(argv[1], argv[2], argv[3], argv[4], *extra)

@@ -264,3 +264,35 @@ def batch_mix(num_clouds: int = 256, seed: int = 4, lo: int = 10_000, hi: int = 
             c = clusters(n, seed=sub, num_clusters=int(rng.integers(10, 501)))
         out.append((c, params_for_size(int(round(sizes[k])))))
     return out
+
+
+@dataclass(frozen=True)
+class Request:
+    """One served build request: the first n points of pool cloud `kind`,
+    arriving `arrival` seconds after the first request (before scaling by the
+    offered load)."""
+    kind: int
+    n: int
+    arrival: float
+
+
+def serve_trace(num_requests: int = 2000, seed: int = 5, lo: int = 100_000, hi: int = 50_000_000,
+                pool_size: int = 0, mean_gap: float = 1.0):
+    """The served workload: request sizes log-uniform in [lo, hi], generator
+    kind uniform over {uniform cube, planes, clusters}, Poisson arrivals with
+    mean gap `mean_gap` (rescaled by the caller to the offered load).  To keep
+    host generation bounded, every request is a prefix (its first n points)
+    of one pool cloud per kind of pool_size points (default hi); a prefix of
+    a seeded cloud is itself a valid cloud.  Returns (pool, requests)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = pool_size or hi
+    pool = [uniform(m, seed=seed * 10 + 1, lo=0.0, hi=80.0, colors=False),
+            planes(m, seed=seed * 10 + 2, num_planes=120, colors=False),
+            clusters(m, seed=seed * 10 + 3, num_clusters=300, colors=False)]
+    sizes = np.exp(rng.uniform(math.log(lo), math.log(hi), size=num_requests))
+    kinds = rng.integers(0, 3, size=num_requests)
+    gaps = rng.exponential(mean_gap, size=num_requests)
+    t = np.cumsum(gaps) - gaps[0]
+    reqs = [Request(int(k), min(m, max(1, int(round(v)))), float(a)) for k, v, a in zip(kinds, sizes, t)]
+    return pool, reqs
+
