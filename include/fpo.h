@@ -273,6 +273,25 @@ fpo_status fpo_job_write_file(fpo_job *job, const fpo_cloud *cloud, const uint8_
  * it).  FPO_ERR_INVALID_ARG before a wait or poll has seen the completion. */
 fpo_status fpo_job_timestamps(fpo_job *job, uint64_t *submitted_ns, uint64_t *started_ns, uint64_t *completed_ns);
 
+/* Statistics of a completed job (for logs and monitoring). */
+typedef struct {
+    uint64_t n;                   /* points */
+    uint32_t num_chunks;
+    uint32_t num_nodes;
+    uint32_t max_depth;           /* depth of the deepest node (0 for an empty cloud) */
+    uint32_t chunk_oversized_any; /* 1 when a finest count-grid cell holds more than C points */
+    uint64_t n_outside;           /* points clamped to a given box */
+    uint64_t preview_count;
+    uint64_t workspace_bytes;     /* the build's worst-case plan (what fpo_workspace_size_cloud returns) */
+    uint64_t submitted_ns, started_ns, completed_ns;   /* as fpo_job_timestamps */
+    float region_ms[16];          /* device ms of each fpo_timer region when the job was timed, else -1 */
+} fpo_job_stats;
+
+/* Fills *out for a completed job (after fpo_job_wait returned FPO_OK); reads
+ * one byte of the node table back from the device.  FPO_ERR_INVALID_ARG
+ * before completion. */
+fpo_status fpo_job_get_stats(fpo_job *job, fpo_job_stats *out);
+
 /* ---- batched builds ----------------------------------------------------------
  * Many independent clouds in one call (the paper's import of several clouds,
  * each with its own preview and tree).  The builds run concurrently on the

@@ -34,7 +34,8 @@ EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_w
            "fpo_job_timestamps", "fpo_batch_workspace_size", "fpo_build_batch", "fpo_server_create",
            "fpo_server_submit", "fpo_job_cancel", "fpo_server_destroy", "fpo_context_set_timing", "fpo_context_set_timers", "fpo_job_timer",
            "fpo_preview_modulus", "fpo_las_parse_header", "fpo_las_header_box", "fpo_las_decode",
-           "fpo_select_workspace_size", "fpo_select_nodes", "fpo_select_nodes_static")
+           "fpo_select_workspace_size", "fpo_select_nodes", "fpo_select_nodes_static",
+           "fpo_job_get_stats")
 #: fpo_select_nodes_static's limits (include/fpo.h)
 SELECT_STATIC_MAX_NODES = 4194304
 SELECT_STATIC_BYTES = 655360
@@ -93,6 +94,15 @@ class _LasHeader(ctypes.Structure):
 class _Cloud(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
                 ("location", ctypes.c_uint32), ("stream_batch", ctypes.c_uint64)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("num_chunks", ctypes.c_uint32), ("num_nodes", ctypes.c_uint32),
+                ("max_depth", ctypes.c_uint32), ("chunk_oversized_any", ctypes.c_uint32),
+                ("n_outside", ctypes.c_uint64), ("preview_count", ctypes.c_uint64),
+                ("workspace_bytes", ctypes.c_uint64), ("submitted_ns", ctypes.c_uint64),
+                ("started_ns", ctypes.c_uint64), ("completed_ns", ctypes.c_uint64),
+                ("region_ms", ctypes.c_float * 16)]
 
 
 class _Result(ctypes.Structure):
@@ -185,6 +195,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_context_set_timers.restype = ctypes.c_int
     lib.fpo_job_timer.argtypes = [vp, ctypes.c_int, P(ctypes.c_float), P(ctypes.c_uint32)]
     lib.fpo_job_timer.restype = ctypes.c_int
+    lib.fpo_job_get_stats.argtypes = [vp, P(_Stats)]
+    lib.fpo_job_get_stats.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -588,6 +600,15 @@ class Job:
             nb = cnt * np.dtype(dt).itemsize
             out[name] = buf[off:off + nb].view(dt).copy()
             off += nb
+        return out
+
+    def stats(self) -> dict:
+        """fpo_job_get_stats of a completed job, as a dict (region_ms by timer
+        name, only the timed regions)."""
+        st = _Stats()
+        _check(_lib.fpo_job_get_stats(self._h, ctypes.byref(st)))
+        out = {k: getattr(st, k) for k, _ in _Stats._fields_ if k != "region_ms"}
+        out["region_ms"] = {name: float(st.region_ms[t]) for name, t in TIMERS.items() if st.region_ms[t] >= 0}
         return out
 
     def timer(self, name: str):

@@ -498,6 +498,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     job->t_submit = now_ns();
     job->t_done = 0;
     job->grid_cells = P.G3;
+    job->plan_bytes = P.total;
     job->params = *p;
     job->ev_preview = job->ev_done = nullptr;
     job->pinned = get_pinned(ctx);
@@ -1128,6 +1129,47 @@ fpo_status fpo_job_timestamps(fpo_job *job, uint64_t *submitted_ns, uint64_t *st
     if (submitted_ns) *submitted_ns = sub;
     if (started_ns) *started_ns = start;
     if (completed_ns) *completed_ns = end ? end : job->t_done;
+    return FPO_OK;
+}
+
+fpo_status fpo_job_get_stats(fpo_job *job, fpo_job_stats *out)
+{
+    if (!job || !out) return fail(FPO_ERR_INVALID_ARG, "NULL job or out");
+    fpo_job_stats st;
+    memset(&st, 0, sizeof(st));
+    const fpo_status ts = fpo_job_timestamps(job, &st.submitted_ns, &st.started_ns, &st.completed_ns);
+    if (ts != FPO_OK) return ts;
+    FPO_RESOLVE(job, false);
+    if (!job->waited || job->status != FPO_OK) return fail(FPO_ERR_INVALID_ARG, "the job has not completed");
+    const fpo_result &R = job->res;
+    st.n = R.n;
+    st.num_chunks = R.num_chunks;
+    st.num_nodes = R.num_nodes;
+    st.chunk_oversized_any = R.chunk_oversized_any;
+    st.n_outside = R.n_outside;
+    st.preview_count = R.preview_count;
+    st.workspace_bytes = job->plan_bytes;
+    if (R.num_nodes) {
+        // nodes are listed by depth: the last one is the deepest
+        uint8_t d = 0;
+        HIPCHK(hipSetDevice(job->ctx->device));
+        HIPCHK(hipMemcpy(&d, R.node_depth + (R.num_nodes - 1), 1, hipMemcpyDeviceToHost));
+        st.max_depth = d;
+    }
+    static_assert(FPO_TIMER_COUNT <= 16, "region_ms holds every timer");
+    for (int t = 0; t < 16; ++t) st.region_ms[t] = -1.0f;
+    if (job->timed)
+        for (int t = 0; t < FPO_TIMER_COUNT; ++t) {
+            if (!((job->timer_mask >> t) & 1u)) continue;
+            float total = 0.0f;
+            for (auto &pr : job->tm[t]) {
+                float v = 0.0f;
+                HIPCHK(hipEventElapsedTime(&v, pr.first, pr.second));
+                total += v;
+            }
+            st.region_ms[t] = total;
+        }
+    *out = st;
     return FPO_OK;
 }
 

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "fpo_host.h"
+#include "fpo_sched.h"
 
 namespace fpo {
 
@@ -66,22 +67,22 @@ struct Pool {
 };
 
 struct Server {
+    Server(uint64_t budget_, uint32_t slots) : budget(budget_), adm(budget_, slots) {}
     std::atomic<int> refs{1};   // the owner's plus one per job submitted
     fpo_context *ctx = nullptr;
     uint64_t budget = 0;
-    uint32_t max_slots = 0;
     char *arena = nullptr;
-    std::map<uint64_t, uint64_t> free_blocks;   // offset -> bytes, coalesced
     std::mutex m;
     std::condition_variable cv;
-    std::deque<fpo_job *> waiting;              // submitted, not yet admitted (FIFO)
-    uint32_t running = 0;
+    Admission<fpo_job *> adm;   // arena, waiting requests (FIFO), running builds (under m)
     Pool *pool = nullptr;
 };
 
 }  // namespace fpo
 
-struct fpo_server : fpo::Server {};
+struct fpo_server : fpo::Server {
+    using fpo::Server::Server;
+};
 
 namespace fpo {
 
@@ -202,62 +203,24 @@ bool pool_remove(Pool *P, fpo_job *job)
     return true;
 }
 
-// ---- server arena: first fit over one allocation, coalescing on free ----
-
-bool arena_alloc(Server *S, uint64_t bytes, uint64_t *off)
-{
-    for (auto it = S->free_blocks.begin(); it != S->free_blocks.end(); ++it) {
-        if (it->second < bytes) continue;
-        *off = it->first;
-        const uint64_t rest = it->second - bytes;
-        const uint64_t at = it->first + bytes;
-        S->free_blocks.erase(it);
-        if (rest) S->free_blocks[at] = rest;
-        return true;
-    }
-    return false;
-}
-
-void arena_free(Server *S, uint64_t off, uint64_t bytes)
-{
-    auto it = S->free_blocks.emplace(off, bytes).first;
-    auto next = std::next(it);
-    if (next != S->free_blocks.end() && it->first + it->second == next->first) {
-        it->second += next->second;
-        S->free_blocks.erase(next);
-    }
-    if (it != S->free_blocks.begin()) {
-        auto prev = std::prev(it);
-        if (prev->first + prev->second == it->first) {
-            prev->second += it->second;
-            S->free_blocks.erase(it);
-        }
-    }
-}
-
 // Admits waiting requests in arrival order while a slot and memory are free
 // (the head waits for memory rather than being overtaken).  S->m held.
 void try_admit(Server *S)
 {
-    while (!S->waiting.empty() && S->running < S->max_slots) {
-        fpo_job *j = S->waiting.front();
+    S->adm.admit([S](fpo_job *j, uint64_t off) {
         Deferred *d = j->def;
-        uint64_t off = 0;
-        if (!arena_alloc(S, d->ws_bytes, &off)) break;
-        S->waiting.pop_front();
         d->arena_off = off;
         d->ws = S->arena + off;
         d->has_memory = true;
-        ++S->running;
         pool_push(S->pool, j);
-    }
+    });
 }
 
 void server_finished(Server *S)
 {
     {
         std::lock_guard<std::mutex> g(S->m);
-        --S->running;
+        S->adm.finished();
         try_admit(S);
     }
     S->cv.notify_all();
@@ -266,9 +229,7 @@ void server_finished(Server *S)
 bool server_remove_waiting(Server *S, fpo_job *job)
 {
     std::lock_guard<std::mutex> g(S->m);
-    auto it = std::find(S->waiting.begin(), S->waiting.end(), job);
-    if (it == S->waiting.end()) return false;
-    S->waiting.erase(it);
+    if (!S->adm.remove_waiting(job)) return false;
     S->cv.notify_all();
     return true;
 }
@@ -403,7 +364,7 @@ void deferred_release(fpo_job *job)
         Server *S = d->server;
         {
             std::lock_guard<std::mutex> g(S->m);
-            arena_free(S, d->arena_off, d->ws_bytes);
+            S->adm.release(d->arena_off, d->ws_bytes);
             try_admit(S);
         }
         S->cv.notify_all();
@@ -439,7 +400,7 @@ fpo_status queue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         if (!ctx->issue_pool) ctx->issue_pool = make_pool(ctx, nullptr, 1);
         P = ctx->issue_pool;
     }
-    if (!P) return fail(FPO_ERR_DEVICE, "could not start the issuing thread");
+    if (!P) return fail(FPO_ERR_OUT_OF_MEMORY, "could not create the issuing thread's stream");
     fpo_job *job = new_deferred_job(ctx);
     Deferred *d = job->def;
     d->cloud = *cloud;
@@ -507,7 +468,7 @@ fpo_status fpo_build_batch(fpo_context *ctx, const fpo_cloud *clouds, const fpo_
         if (!ctx->batch_pool) ctx->batch_pool = make_pool(ctx, nullptr, kBatchWorkers);
         P = ctx->batch_pool;
     }
-    if (!P) return fail(FPO_ERR_DEVICE, "could not create the worker streams");
+    if (!P) return fail(FPO_ERR_OUT_OF_MEMORY, "could not create the worker streams");
     std::vector<fpo_job *> jobs(count, nullptr);
     for (uint32_t i = 0; i < count; ++i) {
         fpo_job *job = new_deferred_job(ctx);
@@ -545,17 +506,14 @@ fpo_status fpo_server_create(fpo_context *ctx, uint64_t hbm_budget_bytes, uint32
     const uint64_t budget = hbm_budget_bytes & ~(uint64_t)255;
     if (budget == 0) return fail(FPO_ERR_INVALID_ARG, "hbm_budget_bytes must be at least 256");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(FPO_ERR_DEVICE, "hipSetDevice failed");
-    fpo_server *S = new fpo_server();
+    fpo_server *S = new fpo_server(budget, max_slots);
     S->ctx = ctx;
-    S->budget = budget;
-    S->max_slots = max_slots;
     void *arena = nullptr;
     if (alloc_fault(ctx) || hipMalloc(&arena, budget) != hipSuccess) {
         delete S;
         return fail(FPO_ERR_OUT_OF_MEMORY, "could not allocate the %llu-byte arena", (unsigned long long)budget);
     }
     S->arena = static_cast<char *>(arena);
-    S->free_blocks[0] = budget;
     S->pool = make_pool(ctx, S, (int)max_slots);
     if (!S->pool) {
         (void)hipFree(arena);
@@ -586,7 +544,7 @@ fpo_status fpo_server_submit(fpo_server *S, const fpo_cloud *cloud, const fpo_pa
     *out = job;
     {
         std::lock_guard<std::mutex> g(S->m);
-        S->waiting.push_back(job);
+        S->adm.submit(job, bytes);
         try_admit(S);
     }
     return FPO_OK;

@@ -68,6 +68,7 @@ struct fpo_job {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tm[FPO_TIMER_COUNT];
     uint64_t t_submit, t_done;    // host steady clock, ns (t_done: when a wait or poll saw it end)
     uint64_t grid_cells;          // G^3
+    uint64_t plan_bytes = 0;      // the build's worst-case workspace plan
     fpo_params params;            // of the build
     std::vector<hipEvent_t> stream_events;   // one per host-to-device batch
     fpo::Deferred *def = nullptr; // set for batch and server jobs (the build runs later)

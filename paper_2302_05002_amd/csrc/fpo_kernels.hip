@@ -110,6 +110,8 @@ __device__ __forceinline__ uint32_t compact3(uint64_t x)
     return (uint32_t)x;
 }
 
+// Slot hash of the global-memory cell tables: the 64-bit finaliser of
+// MurmurHash3 (fmix64, Austin Appleby, public domain), used as published.
 __device__ __forceinline__ uint64_t mix64(uint64_t k)
 {
     k ^= k >> 33;
@@ -355,6 +357,8 @@ template <bool GRID> struct Qz {
     static constexpr uint32_t FLUSH_AT = (GRID ? HASH / 2 : HASH - HASH / 4) - ROUND;
 };
 
+// Slot hash of the quantise pass's LDS cell table: the "lowbias32" integer
+// hash of Chris Wellons' hash-prospector (public domain), used as published.
 __device__ __forceinline__ uint32_t hash32(uint32_t k)
 {
     k ^= k >> 16;
