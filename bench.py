@@ -171,6 +171,20 @@ def plain_loop(fpo, torch, ctx, items, ws):
         job.release()
 
 
+def tune_classes(fpo, ctx, items, reps: int = 2) -> dict:
+    """The quantise shape of every (size class, count grid) in `items`
+    ([((x, y, z), Params)]), tuned on the first cloud of each."""
+    seen = {}
+    for (x, y, z), p in items:
+        n = int(x.shape[0])
+        key = (n.bit_length() - 1, p.count_grid)
+        if key in seen or n < 1:
+            continue
+        t = ctx.autotune(x, y, z, p, reps=reps)
+        seen[key] = t["quantize_variant"]
+    return {f"2^{k}:G{g}": v for (k, g), v in sorted(seen.items())}
+
+
 def bench_batched(fpo, torch, ctx) -> dict:
     """The batched workload: 256 clouds, sizes log-uniform in [10k, 4M],
     kinds uniform / planes (5-200) / clusters (10-500), per-size parameters
@@ -183,6 +197,9 @@ def bench_batched(fpo, torch, ctx) -> dict:
     del mix
     print(f"[bench] batched workload ready in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
     points = sum(int(x.shape[0]) for (x, _, _), _ in items)
+    t = time.perf_counter()
+    tuned = tune_classes(fpo, ctx, items)
+    print(f"[bench] tuned {len(tuned)} size classes in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
     ws = torch.empty(max(fpo.workspace_size(int(x.shape[0]), p) for (x, _, _), p in items), dtype=torch.uint8,
                      device="cuda")
     plain_loop(fpo, torch, ctx, items, ws)   # warm-up
@@ -200,6 +217,7 @@ def bench_batched(fpo, torch, ctx) -> dict:
     for j in jobs:
         j.wait()
         j.release()
+    workers = ctx.autotune_batch(clouds, params, workspace=bws, reps=2)
     torch.cuda.synchronize()
     reps = 3
     t_batch = []
@@ -217,7 +235,9 @@ def bench_batched(fpo, torch, ctx) -> dict:
     return {"workload": "256 clouds (10k-4M points, log-uniform; uniform, planes, clusters; per-size G, C, S)",
             "clouds": len(items), "points": points, "batch_workspace_bytes": int(bws.numel()),
             "plain_points_per_s": points / t_plain, "batched_points_per_s": points / tb,
-            "plain_ms": 1000 * t_plain, "batched_ms": 1000 * tb, "speedup": t_plain / tb}
+            "plain_ms": 1000 * t_plain, "batched_ms": 1000 * tb, "speedup": t_plain / tb,
+            "autotuned": {"quantize_shape_by_class": tuned, "batch_workers": workers["workers"],
+                          "batch_ms_by_workers": workers["batch_ms"]}}
 
 
 class ServedTrace:
@@ -442,6 +462,7 @@ def bench_config1(fpo, torch, ctx, steps: int) -> dict:
     params = fpo_params_of(fpo, p)
     ws = torch.empty(fpo.workspace_size(c.n, params), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
+    tuned = ctx.autotune(*xyz, params, workspace=ws, reps=5)
     for _ in range(3):
         job = ctx.submit(*xyz, params, workspace=ws, stream=stream)
         job.wait()
@@ -449,7 +470,7 @@ def bench_config1(fpo, torch, ctx, steps: int) -> dict:
     res = measure(fpo, torch, ctx, xyz, params, ws, stream, max(steps, 50), "uniform1m", p)
     return {"workload": "1M uniform points, G=64, C=100k, S=32, L=10k, M=64", "n": c.n,
             "ms_per_build": res["ms_per_build"], "points_per_s": c.n / (res["ms_per_build"] / 1000.0),
-            "path": res["path"], "roofline": res["roofline"],
+            "path": res["path"], "roofline": res["roofline"], "autotuned": tuned,
             "target": "<= 15.5 us per build (50% of HBM peak for the path's algorithmic bytes)"}
 
 
@@ -491,6 +512,9 @@ def main():
     ws = torch.empty(fpo.workspace_size(n, params), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
 
+    tuned = ctx.autotune(x, y, z, params, workspace=ws, reps=3)
+    print(f"[bench] autotuned quantise shape {tuned['quantize_variant']} "
+          f"(ms per shape {['%.3f' % v for v in tuned['quantize_ms']]})", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         job = ctx.submit(x, y, z, params, workspace=ws, stream=stream)
         job.wait()
@@ -695,6 +719,7 @@ def main():
         "path_hbm_frac": res["path"]["frac_of_step"],
         "roofline": res["roofline"],
         "path": res["path"],
+        "autotuned": tuned,
         **extras,
     }
     if args.workload != "uniform1m":

@@ -299,6 +299,11 @@ fpo_status fpo_job_get_stats(fpo_job *job, fpo_job_stats *out);
  * so that latency-bound small builds overlap; each result is the one a plain
  * build of that cloud gives. */
 
+/* Number of worker streams (and issuing threads) of later fpo_build_batch
+ * calls on ctx: 1..16, default 4 (one per hardware queue of a process).  Each
+ * count has its own workers, kept until the context is torn down. */
+fpo_status fpo_context_set_batch_workers(fpo_context *ctx, uint32_t workers);
+
 /* Workspace bytes of a batch: the worst case of every cloud, each rounded up
  * to 256 bytes, back to back in the order of the clouds. */
 fpo_status fpo_batch_workspace_size(const fpo_cloud *clouds, const fpo_params *params, uint32_t count,
@@ -339,6 +344,46 @@ fpo_status fpo_job_cancel(fpo_job *job);
  * results live) and slot streams are freed when the last job has been
  * released.  No further fpo_server_submit may use the handle. */
 void fpo_server_destroy(fpo_server *srv);
+
+/* ---- autotuning ----------------------------------------------------------------
+ * Choices that change only how fast a build runs, never its result, picked by
+ * timing every candidate on the caller's own cloud.  The tuner checks that
+ * every candidate gives a result with the same fingerprint (a hash of every
+ * output array) as the first and reports FPO_ERR_DEVICE otherwise.  Choices
+ * are kept in the context; with FPO_AUTOTUNE_CACHE=<path> in the environment
+ * they are read when a context is created and written after every tuning
+ * call.  Tuning a context while other builds run on it changes only their
+ * speed. */
+typedef struct {
+    uint32_t quantize_variant;  /* the chosen shape of the quantise + count pass (0, 1, 2) */
+    uint32_t size_class;        /* floor(log2 n): the choice applies to clouds of this size class ... */
+    uint32_t count_grid_log2;   /* ... built with this count grid */
+    uint32_t candidates;        /* number of shapes timed */
+    float quantize_ms[4];       /* median device time of the pass per shape */
+} fpo_tuning;
+
+/* Times the quantise + count pass of `reps` builds (after one warm-up) of
+ * *cloud with every candidate shape: one 1024-thread block per compute unit
+ * with a 16K-slot LDS table, two 512-thread blocks with 8K slots, or four
+ * 256-thread blocks with 4K slots, each over a contiguous range of points.
+ * Later builds of the size class and count grid use the fastest.  workspace
+ * as for fpo_build_submit; reps 1..100.  Blocks until done.  Not for the
+ * grid preview (FPO_ERR_INVALID_ARG), which has one shape. */
+fpo_status fpo_autotune(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
+                        uint64_t workspace_bytes, uint32_t reps, fpo_tuning *out);
+
+/* Times `reps` whole batches (after one warm-up) with 2, 4 and 8 worker
+ * streams and keeps the fastest for later batches of ctx (*workers_out);
+ * ms_out (3 floats, may be NULL) receives the median batch time per
+ * candidate.  Arguments as for fpo_build_batch (no stream dependency).
+ * Blocks until done. */
+fpo_status fpo_autotune_batch(fpo_context *ctx, const fpo_cloud *clouds, const fpo_params *params, uint32_t count,
+                              void *workspace, uint64_t workspace_bytes, uint32_t reps, uint32_t *workers_out,
+                              float *ms_out);
+
+/* Forces the quantise shape of later builds of ctx (0..2), or -1 to use the
+ * tuned choices again (for tests: every shape gives the same result). */
+fpo_status fpo_context_force_quantize_variant(fpo_context *ctx, int variant);
 
 /* ---- kernel timing (for benchmarks) ----------------------------------------
  * With timing enabled on a context, every later submit of it brackets each

@@ -35,7 +35,8 @@ EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_w
            "fpo_server_submit", "fpo_job_cancel", "fpo_server_destroy", "fpo_context_set_timing", "fpo_context_set_timers", "fpo_job_timer",
            "fpo_preview_modulus", "fpo_las_parse_header", "fpo_las_header_box", "fpo_las_decode",
            "fpo_select_workspace_size", "fpo_select_nodes", "fpo_select_nodes_static",
-           "fpo_job_get_stats")
+           "fpo_job_get_stats", "fpo_context_set_batch_workers", "fpo_autotune", "fpo_autotune_batch",
+           "fpo_context_force_quantize_variant")
 #: fpo_select_nodes_static's limits (include/fpo.h)
 SELECT_STATIC_MAX_NODES = 4194304
 SELECT_STATIC_BYTES = 655360
@@ -103,6 +104,12 @@ class _Stats(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_uint64), ("submitted_ns", ctypes.c_uint64),
                 ("started_ns", ctypes.c_uint64), ("completed_ns", ctypes.c_uint64),
                 ("region_ms", ctypes.c_float * 16)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("quantize_variant", ctypes.c_uint32), ("size_class", ctypes.c_uint32),
+                ("count_grid_log2", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
+                ("quantize_ms", ctypes.c_float * 4)]
 
 
 class _Result(ctypes.Structure):
@@ -197,6 +204,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_job_timer.restype = ctypes.c_int
     lib.fpo_job_get_stats.argtypes = [vp, P(_Stats)]
     lib.fpo_job_get_stats.restype = ctypes.c_int
+    lib.fpo_context_set_batch_workers.argtypes = [vp, ctypes.c_uint32]
+    lib.fpo_context_set_batch_workers.restype = ctypes.c_int
+    lib.fpo_autotune.argtypes = [vp, P(_Cloud), P(_Params), vp, u64, ctypes.c_uint32, P(_Tuning)]
+    lib.fpo_autotune.restype = ctypes.c_int
+    lib.fpo_autotune_batch.argtypes = [vp, P(_Cloud), P(_Params), ctypes.c_uint32, vp, u64, ctypes.c_uint32,
+                                       P(ctypes.c_uint32), P(ctypes.c_float)]
+    lib.fpo_autotune_batch.restype = ctypes.c_int
+    lib.fpo_context_force_quantize_variant.argtypes = [vp, ctypes.c_int]
+    lib.fpo_context_force_quantize_variant.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -428,6 +444,55 @@ class Context:
             return job.result()
         finally:
             job.release()   # the result views the workspace, not the job
+
+    def autotune(self, x, y, z, params: Params, workspace=None, reps: int = 5) -> dict:
+        """fpo_autotune on device tensors x, y, z: the fastest quantise shape
+        for clouds of this size class and count grid (kept in the context)."""
+        import torch
+        n = int(x.shape[0])
+        for t in (x, y, z):
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.shape[0] == n
+        cloud = _Cloud(n, x.data_ptr(), y.data_ptr(), z.data_ptr())
+        if workspace is None:
+            workspace = torch.empty(workspace_size(n, params), dtype=torch.uint8, device=x.device)
+        torch.cuda.synchronize(x.device)   # inputs written on torch's streams are complete
+        t = _Tuning()
+        _check(_lib.fpo_autotune(self._h, ctypes.byref(cloud), ctypes.byref(params.to_c()),
+                                 ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), int(reps),
+                                 ctypes.byref(t)))
+        return {"quantize_variant": int(t.quantize_variant), "size_class": int(t.size_class),
+                "count_grid_log2": int(t.count_grid_log2),
+                "quantize_ms": [float(t.quantize_ms[i]) for i in range(int(t.candidates))]}
+
+    def autotune_batch(self, clouds, params, workspace=None, reps: int = 3) -> dict:
+        """fpo_autotune_batch: the fastest number of batch worker streams."""
+        import torch
+        count = len(clouds)
+        if isinstance(params, Params):
+            params = [params] * count
+        cs = (_Cloud * count)()
+        ps = (_Params * count)()
+        for i, (x, y, z) in enumerate(clouds):
+            cs[i] = _Cloud(int(x.shape[0]), x.data_ptr(), y.data_ptr(), z.data_ptr())
+            ps[i] = params[i].to_c()
+        need = ctypes.c_uint64()
+        _check(_lib.fpo_batch_workspace_size(cs, ps, count, ctypes.byref(need)))
+        if workspace is None:
+            workspace = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=clouds[0][0].device)
+        torch.cuda.synchronize()
+        w = ctypes.c_uint32()
+        ms = (ctypes.c_float * 3)()
+        _check(_lib.fpo_autotune_batch(self._h, cs, ps, count, ctypes.c_void_p(workspace.data_ptr()),
+                                       workspace.numel(), int(reps), ctypes.byref(w), ms))
+        return {"workers": int(w.value), "batch_ms": {c: float(ms[i]) for i, c in enumerate((2, 4, 8))}}
+
+    def force_quantize_variant(self, variant: int):
+        """Force the quantise shape of later builds (0..2), -1 for the tuned one."""
+        _check(_lib.fpo_context_force_quantize_variant(self._h, int(variant)))
+
+    def set_batch_workers(self, workers: int):
+        """Worker streams of later build_batch calls (1..16, default 4)."""
+        _check(_lib.fpo_context_set_batch_workers(self._h, int(workers)))
 
     def build_batch(self, clouds, params, workspace=None, stream=None) -> list:
         """Enqueue one build per (x, y, z) device-tensor triple in `clouds`,

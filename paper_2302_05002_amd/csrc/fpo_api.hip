@@ -371,6 +371,8 @@ fpo_status fpo_context_create(int device, fpo_context **out)
     c->device = device;
     if (const char *f = getenv("FPO_FAULT"))
         if (strncmp(f, "alloc:", 6) == 0) c->fault_at = strtoull(f + 6, nullptr, 10);
+    memset(c->qz_variant, 0xff, sizeof(c->qz_variant));
+    tune_cache_load(c);
     if (alloc_fault(c) || hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return fail(FPO_ERR_OUT_OF_MEMORY, "could not create the context's stream");
@@ -621,6 +623,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
 
     // ---- step 1: bbox, quantise, count ----
     const int given = (p->flags & FPO_BBOX_GIVEN) ? 1 : 0;
+    const int qv = quantize_variant(ctx, n, P.g);
     // Timed regions (when timing): contiguous runs of launches that together
     // cover every kernel of the build; only the host round trips fall between
     // them.
@@ -683,7 +686,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
             const uint64_t c = n - o < sbatch ? n - o : sbatch;
             if (host_in) JCHK(hipStreamWaitEvent(st, job->stream_events[bi++], 0));
             t_quant.begin(st);
-            launch_quantize(X + o, Y + o, Z + o, c, box, g, 1, U64(P.code) + o, fine, box, o, cellmin, st);
+            launch_quantize(X + o, Y + o, Z + o, c, box, g, 1, U64(P.code) + o, fine, box, o, cellmin, st, qv);
             t_quant.end(st);
         }
     } else {
@@ -703,7 +706,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         launch_setup(box, U32(P.bbox_part), nparts, 0, p->bbox_min, p->bbox_max, 0, st);
         t_bbox.end(st);
         t_quant.begin(st);
-        launch_quantize(X, Y, Z, n, box, g, 0, U64(P.code), fine, box, 0, cellmin, st);
+        launch_quantize(X, Y, Z, n, box, g, 0, U64(P.code), fine, box, 0, cellmin, st, qv);
         t_quant.end(st);
     }
 
@@ -987,6 +990,47 @@ static void export_parts(const fpo_job *job, std::vector<std::pair<const void *,
              {R.node_begin, 8 * nn},              {R.node_count, 4 * nn},  {R.node_points, 4 * n},
              {R.preview_index, 4 * R.preview_count}};
 }
+
+}  // extern "C"
+
+namespace fpo {
+
+// Fingerprint of every array of a completed job (and of its scalars): equal
+// for equal results.  Synchronous; allocates 8 bytes of device memory.
+fpo_status job_fingerprint(fpo_job *job, uint64_t *out)
+{
+    FPO_RESOLVE(job, false);
+    if (!job->waited || job->status != FPO_OK) return fail(FPO_ERR_INVALID_ARG, "the job has not completed");
+    HIPCHK(hipSetDevice(job->ctx->device));
+    std::vector<std::pair<const void *, uint64_t>> parts;
+    export_parts(job, parts);
+    uint64_t *acc = nullptr;
+    HIPCHK(hipMalloc(&acc, sizeof(uint64_t)));
+    hipStream_t st = job->ctx->stream;
+    launch_fill_u32(reinterpret_cast<uint32_t *>(acc), 0u, 2, st);
+    uint64_t salt = 0;
+    for (auto &pr : parts) launch_fingerprint(pr.first, pr.second, (salt += 0x9E3779B97F4A7C15ull), acc, st);
+    uint64_t h = 0;
+    hipError_t e = hipMemcpyAsync(&h, acc, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(acc);
+    if (e != hipSuccess) return fail(FPO_ERR_DEVICE, "fingerprint: %s", hipGetErrorString(e));
+    const fpo_result &R = job->res;
+    uint32_t sc[8];
+    memcpy(sc, R.bbox_min, 12);
+    memcpy(sc + 3, R.bbox_max, 12);
+    memcpy(sc + 6, &R.cube_size, 4);
+    memcpy(sc + 7, &R.scale, 4);
+    for (int i = 0; i < 8; ++i) h = (h ^ sc[i]) * 0x100000001B3ull;
+    h = (h ^ R.num_chunks ^ ((uint64_t)R.num_nodes << 32)) * 0x100000001B3ull;
+    h = (h ^ R.preview_count ^ (R.n_outside << 20)) * 0x100000001B3ull;
+    *out = h;
+    return FPO_OK;
+}
+
+}  // namespace fpo
+
+extern "C" {
 
 fpo_status fpo_job_export_bytes(fpo_job *job, uint64_t *bytes)
 {

@@ -88,7 +88,6 @@ namespace fpo {
 
 namespace {
 
-constexpr int kBatchWorkers = 4;   // one per hardware queue of a process
 inline uint64_t a256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
 
 void server_finished(Server *S);
@@ -380,15 +379,19 @@ void deferred_release(fpo_job *job)
 
 void destroy_batch_pool(fpo_context *ctx)
 {
-    Pool *P = nullptr, *I = nullptr;
+    Pool *I = nullptr;
+    std::vector<Pool *> B;
     {
         std::lock_guard<std::mutex> g(ctx->mu);
-        P = ctx->batch_pool;
         I = ctx->issue_pool;
-        ctx->batch_pool = ctx->issue_pool = nullptr;
+        ctx->issue_pool = nullptr;
+        for (Pool *&P : ctx->batch_pools) {
+            if (P) B.push_back(P);
+            P = nullptr;
+        }
     }
     stop_pool(I);
-    stop_pool(P);
+    for (Pool *P : B) stop_pool(P);
 }
 
 fpo_status queue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
@@ -425,6 +428,15 @@ fpo_status fpo_job_cancel(fpo_job *job)
     if (!job) return fail(FPO_ERR_INVALID_ARG, "job is NULL");
     if (!job->def) return fail(FPO_ERR_INVALID_ARG, "only batch and server jobs can be cancelled");
     if (!cancel_queued(job)) return fail(FPO_ERR_INVALID_ARG, "the job has already started (or was cancelled)");
+    return FPO_OK;
+}
+
+fpo_status fpo_context_set_batch_workers(fpo_context *ctx, uint32_t workers)
+{
+    if (!ctx) return fail(FPO_ERR_INVALID_ARG, "context is NULL");
+    if (workers < 1 || workers > 16) return fail(FPO_ERR_INVALID_ARG, "workers must be in 1..16 (got %u)", workers);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->batch_workers = (int)workers;
     return FPO_OK;
 }
 
@@ -465,8 +477,11 @@ fpo_status fpo_build_batch(fpo_context *ctx, const fpo_cloud *clouds, const fpo_
     Pool *P;
     {
         std::lock_guard<std::mutex> g(ctx->mu);
-        if (!ctx->batch_pool) ctx->batch_pool = make_pool(ctx, nullptr, kBatchWorkers);
-        P = ctx->batch_pool;
+        // one pool per worker count, kept until the context is torn down
+        // (queued jobs refer to theirs)
+        Pool *&slot = ctx->batch_pools[ctx->batch_workers];
+        if (!slot) slot = make_pool(ctx, nullptr, ctx->batch_workers);
+        P = slot;
     }
     if (!P) return fail(FPO_ERR_OUT_OF_MEMORY, "could not create the worker streams");
     std::vector<fpo_job *> jobs(count, nullptr);

@@ -50,7 +50,11 @@ struct fpo_context {
     bool timing = false;
     uint32_t timer_mask = 0;           // bit t: timer t is recorded (when timing)
     std::vector<hipEvent_t> ev_free;   // timing events, reused across jobs
-    fpo::Pool *batch_pool = nullptr;   // created by the first batch
+    fpo::Pool *batch_pools[17] = {};   // worker pools of batches, by worker count (created on first use)
+    int batch_workers = 4;             // workers of the next batch (fpo_context_set_batch_workers)
+    // autotuned quantise variant per (log2 n, log2 G); 0xff = not tuned (variant 0)
+    uint8_t qz_variant[33][10];
+    int qz_force = -1;                 // fpo_context_force_quantize_variant, else -1
     fpo::Pool *issue_pool = nullptr;   // issues plain builds in submission order (created by the first)
     hipStream_t copy_stream = nullptr; // host-to-device batches of pinned inputs (created on first use)
 };
@@ -82,6 +86,14 @@ fpo_status select_static_init(int device);
 
 void ctx_retain(fpo_context *c);
 void ctx_release(fpo_context *c);   // tears the context down at zero references
+// Fingerprint of a completed job's result (equal for equal results).
+fpo_status job_fingerprint(fpo_job *job, uint64_t *out);
+
+// Quantise variant of a build of n points with count grid 2^g.
+int quantize_variant(fpo_context *c, uint64_t n, int g);
+// Loads FPO_AUTOTUNE_CACHE into a new context's table (missing file: nothing).
+void tune_cache_load(fpo_context *c);
+
 // True when the allocation about to be made is the one FPO_FAULT names.
 bool alloc_fault(fpo_context *c);
 

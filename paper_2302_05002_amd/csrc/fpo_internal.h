@@ -74,9 +74,12 @@ void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given,
                   int flag_only, hipStream_t st);
 // base = original index of x[0]; cellmin (grid preview only, else nullptr)
 // receives the least H64 of each count-grid cell.
+// variant: the pass's block and LDS-table shape, 0..QZ_VARIANTS-1 (autotuned;
+// every variant gives the same codes and counts).
+constexpr int QZ_VARIANTS = 3;
 void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box,
                      int g, int given, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw,
-                     uint64_t base, uint64_t *cellmin, hipStream_t st);
+                     uint64_t base, uint64_t *cellmin, hipStream_t st, int variant);
 void launch_pyramid(uint32_t *pyr, int g, hipStream_t st);
 void launch_grid_export(const uint32_t *fine_morton, int g, uint32_t *rowmajor, hipStream_t st);
 void launch_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev, int lmin,
@@ -240,6 +243,10 @@ void launch_wc_chunks(const uint32_t *num_wc_dev, uint64_t max_wc, const uint64_
                       uint32_t *seg_nb, uint8_t *wc_nested, uint32_t *flags, hipStream_t st);
 void launch_node_fill(const WcArgs &a, const uint32_t *node_base, uint8_t *depth, uint64_t *key,
                       uint8_t *mask, hipStream_t st);
+
+// *out += fingerprint of bytes [p, p + bytes) (order-independent sum; out
+// zeroed by the caller): equal for equal ranges.
+void launch_fingerprint(const void *p, uint64_t bytes, uint64_t salt, uint64_t *out, hipStream_t st);
 
 // Node-ordered gather: out_xyz[3k + a] = coord_a[idx[k]], colour bytes alike.
 void launch_gather_points(const uint32_t *idx, uint64_t n, const float *x, const float *y, const float *z,

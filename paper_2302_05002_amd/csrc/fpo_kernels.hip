@@ -49,6 +49,12 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
 
 // Exclusive scan of one value per thread across the block; *total = sum.
 // lds must hold BLOCK/64 + 1 words.  Ends with a barrier so lds can be reused.
@@ -347,14 +353,21 @@ static_assert(h64_inverse(h64(0)) == 0 && h64_inverse(h64(1)) == 1 && h64_invers
 // surface by surface, so a range touches far fewer cells than it has points.
 // With the grid preview the same table also keeps the least H64 of each cell
 // (fewer slots, 64-bit minima) and flushes it with a 64-bit atomic minimum.
-constexpr int QZ_BLOCK = 1024;
-template <bool GRID> struct Qz {
+// Shapes of the pass (autotuned per size class, result-identical: the counts
+// do not depend on which block aggregates which points): a block of BLOCK
+// threads with a table of 2^HLOG slots.  Variant 0 is one 1024-thread block
+// per compute unit with 16K slots (128 KB); variants 1 and 2 are two 512-
+// thread blocks with 8K slots and four 256-thread blocks with 4K slots per
+// compute unit, over shorter ranges of points.  The grid preview always
+// takes variant 0's shape with 8K slots of 64-bit minima.
+template <bool GRID, int BLOCK = 1024, int HLOG = 14> struct Qz {
     static constexpr int ITEMS = GRID ? 2 : 8;
-    static constexpr uint32_t ROUND = QZ_BLOCK * ITEMS;
-    static constexpr uint32_t HASH = GRID ? 8192 : 16384;   // slots (128 KB of LDS)
+    static constexpr uint32_t ROUND = BLOCK * ITEMS;
+    static constexpr uint32_t HASH = GRID ? 8192 : (1u << HLOG);   // slots
     // flushed when a round could fill the table past half (grid preview)
     // or three quarters of its slots
     static constexpr uint32_t FLUSH_AT = (GRID ? HASH / 2 : HASH - HASH / 4) - ROUND;
+    static_assert(HASH - HASH / 4 > ROUND, "a round fits the table");
 };
 
 // Slot hash of the quantise pass's LDS cell table: the "lowbias32" integer
@@ -369,11 +382,11 @@ __device__ __forceinline__ uint32_t hash32(uint32_t k)
     return k;
 }
 
-template <bool GRID>
+template <bool GRID, int BLOCK, uint32_t HASH>
 __device__ void qz_flush(uint32_t *hk, uint32_t *hc, unsigned long long *hm, uint32_t *fine,
                          unsigned long long *cellmin)
 {
-    for (uint32_t h = threadIdx.x; h < Qz<GRID>::HASH; h += QZ_BLOCK) {
+    for (uint32_t h = threadIdx.x; h < HASH; h += BLOCK) {
         const uint32_t k = hk[h];
         if (k != 0xffffffffu) {
             atomicAdd(&fine[k], hc[h]);
@@ -423,15 +436,16 @@ template <typename T> __device__ __forceinline__ T &at_byte(T *p, uint32_t off)
 // first probe of every item is read before any is used: a cell already in
 // the table (the usual case) then costs one read and one atomic.  `base` is
 // the original index of x[0] (batches of a streamed cloud).
-template <bool GRID>
+template <bool GRID, int QZ_BLOCK = 1024, int HLOG = 14>
 __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__ x, const float *__restrict__ y,
                                                        const float *__restrict__ z, uint64_t n, const DevBox *box,
                                                        int g, int given, uint64_t *__restrict__ code,
                                                        uint32_t *__restrict__ fine, DevBox *box_rw, uint64_t per_block,
                                                        uint64_t base, unsigned long long *__restrict__ cellmin)
 {
-    constexpr int ITEMS = Qz<GRID>::ITEMS;
-    constexpr uint32_t ROUND = Qz<GRID>::ROUND, HASH = Qz<GRID>::HASH;
+    using C = Qz<GRID, QZ_BLOCK, HLOG>;
+    constexpr int ITEMS = C::ITEMS;
+    constexpr uint32_t ROUND = C::ROUND, HASH = C::HASH;
     __shared__ uint32_t hk[HASH];
     __shared__ uint32_t hc[HASH];
     __shared__ unsigned long long hm[GRID ? HASH : 1];
@@ -501,15 +515,15 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
         }
         __syncthreads();
         // at most ROUND new cells per round
-        if (used > Qz<GRID>::FLUSH_AT) {
-            qz_flush<GRID>(hk, hc, hm, fine, cellmin);
+        if (used > C::FLUSH_AT) {
+            qz_flush<GRID, QZ_BLOCK, HASH>(hk, hc, hm, fine, cellmin);
             __syncthreads();
             if (threadIdx.x == 0) used = 0;
             __syncthreads();
         }
     }
     __syncthreads();
-    qz_flush<GRID>(hk, hc, hm, fine, cellmin);
+    qz_flush<GRID, QZ_BLOCK, HASH>(hk, hc, hm, fine, cellmin);
     if (given) {
         // one atomic per block (the same counters for every block)
         outside = wave_sum(outside);
@@ -2967,21 +2981,29 @@ void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given,
 
 void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box, int g,
                      int given, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw, uint64_t base,
-                     uint64_t *cellmin, hipStream_t st)
+                     uint64_t *cellmin, hipStream_t st, int variant)
 {
     if (n == 0) return;
-    // one contiguous range per block, about one block per compute unit
-    // (each block holds 128 KB of LDS)
-    uint64_t per = (n + 255) / 256;
+    // one contiguous range per block: 256 blocks (one per compute unit) for
+    // variant 0 and the grid preview, 512 for variant 1, 1024 for variant 2
+    if (cellmin) variant = 0;
+    const uint64_t blocks = variant == 2 ? 1024 : variant == 1 ? 512 : 256;
+    uint64_t per = (n + blocks - 1) / blocks;
     per = (per + 63) / 64 * 64;
     const uint32_t grid = (uint32_t)((n + per - 1) / per);
     auto *cm = reinterpret_cast<unsigned long long *>(cellmin);
     if (cellmin)
-        hipLaunchKernelGGL(k_quantize<true>, dim3(grid), dim3(QZ_BLOCK), 0, st, x, y, z, n, box, g, given,
+        hipLaunchKernelGGL((k_quantize<true>), dim3(grid), dim3(1024), 0, st, x, y, z, n, box, g, given, code,
+                           fine_cnt, box_rw, per, base, cm);
+    else if (variant == 2)
+        hipLaunchKernelGGL((k_quantize<false, 256, 12>), dim3(grid), dim3(256), 0, st, x, y, z, n, box, g, given,
+                           code, fine_cnt, box_rw, per, base, cm);
+    else if (variant == 1)
+        hipLaunchKernelGGL((k_quantize<false, 512, 13>), dim3(grid), dim3(512), 0, st, x, y, z, n, box, g, given,
                            code, fine_cnt, box_rw, per, base, cm);
     else
-        hipLaunchKernelGGL(k_quantize<false>, dim3(grid), dim3(QZ_BLOCK), 0, st, x, y, z, n, box, g, given,
-                           code, fine_cnt, box_rw, per, base, cm);
+        hipLaunchKernelGGL((k_quantize<false>), dim3(grid), dim3(1024), 0, st, x, y, z, n, box, g, given, code,
+                           fine_cnt, box_rw, per, base, cm);
 }
 
 void launch_pyramid(uint32_t *pyr, int g, hipStream_t st)
@@ -3216,6 +3238,27 @@ __global__ void k_gather_points(const uint32_t *__restrict__ idx, uint64_t n, co
         out_xyz[3 * k + 2] = z[i];
         for (uint32_t c = 0; c < stride; ++c) out_color[(uint64_t)stride * k + c] = color[(uint64_t)stride * i + c];
     }
+}
+
+// Fingerprint of a byte range: the wrapping sum over its bytes b at offsets i
+// of mix64((i << 8) | b + salt), so equal ranges give equal sums whatever the
+// order of the additions, and a changed byte or a moved value changes the sum
+// with high probability.  For comparing results of equivalent builds.
+__global__ void k_fingerprint(const uint8_t *p, uint64_t bytes, uint64_t salt, unsigned long long *out)
+{
+    uint64_t acc = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < bytes;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        acc += mix64(((i << 8) | p[i]) + salt);
+    acc = wave_sum64(acc);
+    if (lane_id() == 0 && acc) atomicAdd(out, (unsigned long long)acc);
+}
+
+void launch_fingerprint(const void *p, uint64_t bytes, uint64_t salt, uint64_t *out, hipStream_t st)
+{
+    if (bytes == 0) return;
+    hipLaunchKernelGGL(k_fingerprint, dim3(grid_for(bytes, 256, 4096)), dim3(256), 0, st,
+                       static_cast<const uint8_t *>(p), bytes, salt, reinterpret_cast<unsigned long long *>(out));
 }
 
 void launch_gather_points(const uint32_t *idx, uint64_t n, const float *x, const float *y, const float *z,
