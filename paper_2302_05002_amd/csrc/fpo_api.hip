@@ -14,6 +14,8 @@
 #include "fpo_host.h"
 #include "fpo_internal.h"
 
+#include <algorithm>
+
 using namespace fpo;
 
 namespace {
@@ -114,10 +116,41 @@ struct Ctrs {
 };
 static_assert(sizeof(Ctrs) <= 256, "the box follows the counters 256 bytes later");
 
+// Capacities of one cut's lists (CutArgs) for n points: heavy nodes of a
+// level number at most min(8^l, n) above lmin and min(8^l, n / (thresh + 1))
+// from lmin on (disjoint nodes holding more than thresh points), and never
+// more than eight per heavy node above; entries of a level number at most
+// eight per heavy node above (and 8^l, and n).
+struct CutPlan {
+    uint64_t open_cap = 1;
+    uint64_t ent_off[MAXD + 1] = {};
+    uint64_t st_off[MAXD + 1] = {};
+};
+
+CutPlan cut_plan(uint64_t n, int lam, uint32_t thresh, int lmin)
+{
+    CutPlan c;
+    uint64_t prev = 1;   // level 0: the root
+    c.ent_off[0] = 0;
+    c.ent_off[1] = lmin == 0 ? 1 : 0;
+    for (int l = 1; l <= lam; ++l) {
+        const uint64_t cells = 1ull << (3 * l);
+        uint64_t ent = l < lmin ? 0 : std::min(std::min(cells, 8 * prev), n);
+        c.ent_off[l + 1] = c.ent_off[l] + ent;
+        uint64_t open = 0;
+        if (l < lam) open = std::min(std::min(cells, l < lmin ? n : n / ((uint64_t)thresh + 1)), 8 * prev);
+        c.open_cap = std::max(c.open_cap, open);
+        prev = open;
+    }
+    const uint64_t tiles = (c.open_cap + FR_BLOCK - 1) / FR_BLOCK;
+    for (int l = 0; l <= lam + 1; ++l) c.st_off[l] = l >= 1 ? (uint64_t)(l - 1) * tiles : 0;
+    return c;
+}
+
 // Byte offsets of every region of the workspace for (n, params).
 struct Plan {
     uint64_t n;
-    int g, s, lam_w, d0;
+    int g, s, lam_w, d0, lt;
     uint64_t G3, W3, P;      // finest cells, work-chunk-level cells, pyramid words
     uint64_t maxC, maxW;
     size_t total;
@@ -125,7 +158,9 @@ struct Plan {
     size_t xyz, box, bbox_part, ctrs, grid, c_level, c_key, c_count, c_begin, perm;
     size_t n_depth, n_key, n_mask, n_begin, n_count, n_points, pv_index;
     // temporaries
-    size_t code, pyr, fc, ec, lc, fw, ew, lw_, w_level, w_key, w_count, w_start, w_begin;
+    size_t code, pyr, w_level, w_key, w_count, w_start, w_begin, c_start;
+    CutPlan cp[2];   // chunk cut, work-chunk cut
+    size_t cut_open[2], cut_ent[2], cut_st[2], cut_ctr[2], cut_idx[2];
     size_t c_count_scan, code_perm, wc_orig, wc_code, ms_temp, scan_temp, seg_b0, seg_nb, wc_nested, wc_chunk;
     size_t gtab, t, fr, alive, alive_scan, kd, loff, owned, node_base, lnode_key, lnode_mask, cut;
     size_t big_list, big_nr, big_node, big_hkey, big_hval, cls_list;
@@ -144,6 +179,7 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     P.G3 = 1ull << (3 * P.g);
     P.W3 = 1ull << (3 * P.lam_w);
     P.P = pyr_off(P.g + 1);
+    P.lt = P.g < 7 ? P.g : 7;
     const uint64_t nn = n ? n : 1;
     P.maxC = nn < P.G3 ? nn : P.G3;
     P.maxW = nn < P.W3 ? nn : P.W3;
@@ -186,12 +222,16 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     P.pv_index = take(4 * nn);
     P.code = take(8 * nn);
     P.pyr = take(4 * P.P);
-    P.fc = take(4 * P.G3);
-    P.ec = take(4 * P.G3);
-    P.lc = take(P.G3);
-    P.fw = take(4 * P.W3);
-    P.ew = take(4 * P.W3);
-    P.lw_ = take(P.W3);
+    P.c_start = take(8 * P.maxC);
+    P.cp[0] = cut_plan(nn, P.g, p.max_points_per_chunk, 0);
+    P.cp[1] = cut_plan(nn, P.lam_w, WC_CAP, P.d0);
+    for (int k = 0; k < 2; ++k) {
+        P.cut_open[k] = take(2 * 8 * P.cp[k].open_cap);
+        P.cut_ent[k] = take(8 * P.cp[k].ent_off[P.g + 1]);
+        P.cut_st[k] = take(8 * P.cp[k].st_off[P.g + 1]);
+        P.cut_ctr[k] = take(4 * 3 * MAXD);
+        P.cut_idx[k] = take(4 * ((1ull << (3 * P.lt)) + 1));
+    }
     P.w_level = take(P.maxW);
     P.w_key = take(8 * P.maxW);
     P.w_count = take(4 * P.maxW);
@@ -212,7 +252,7 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
         const size_t b = multisplit_seg_temp_bytes(nn, (uint32_t)P.maxC, nn + P.maxW);
         P.ms_temp = take(a > b ? a : b);
     }
-    uint64_t scan_max = P.G3 > (uint64_t)MAXD * P.maxW ? P.G3 : (uint64_t)MAXD * P.maxW;
+    uint64_t scan_max = (uint64_t)MAXD * P.maxW;
     if (P.pv_ntiles > scan_max) scan_max = P.pv_ntiles;
     if (nn > scan_max) scan_max = nn;   // node sizes (nodes number at most n)
     P.scan_temp = take(scan_temp_bytes(scan_max));
@@ -717,18 +757,40 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     t_cut.begin(st);
     launch_pyramid(pyr, g, st);
     launch_grid_export(fine, g, U32(P.grid), st);
-    launch_cut_flags(pyr, g, p->max_points_per_chunk, U32(P.fc), U8(P.lc), 0, st);
-    scan_exclusive(U32(P.fc), U32(P.ec), P.G3, &ctrs->num_chunks, stemp, st);
-    launch_cut_table(pyr, g, U32(P.fc), U32(P.ec), U8(P.lc), U8(P.c_level), U64(P.c_key), U32(P.c_count), nullptr,
-                     p->max_points_per_chunk, &ctrs->oversized, P.maxC, &ctrs->internal_error, st);
-    launch_cut_flags(pyr, P.lam_w, WC_CAP, U32(P.fw), U8(P.lw_), P.d0, st);
-    scan_exclusive(U32(P.fw), U32(P.ew), P.W3, &ctrs->num_wc, stemp, st);
-    launch_cut_table(pyr, P.lam_w, U32(P.fw), U32(P.ew), U8(P.lw_), U8(P.w_level), U64(P.w_key), U32(P.w_count),
-                     U64(P.w_start), WC_CAP, &ctrs->wc_over, P.maxW, &ctrs->internal_error, st);
-    // cell -> chunk id and cell -> work-chunk id tables (in place of the scans)
-    launch_cell_ids(U32(P.fc), U32(P.ec), P.G3, st);
-    launch_cell_ids(U32(P.fw), U32(P.ew), P.W3, st);
-    launch_wc_chunks(&ctrs->num_wc, P.maxW, U64(P.w_key), U8(P.w_level), g, pyr, U32(P.ec), U8(P.c_level),
+    CutArgs cut[2];
+    for (int k = 0; k < 2; ++k) {
+        CutArgs &c = cut[k];
+        const CutPlan &cp = P.cp[k];
+        c.thresh = k == 0 ? p->max_points_per_chunk : WC_CAP;
+        c.lmin = k == 0 ? 0 : P.d0;
+        c.lam = g;
+        c.lt = P.lt;
+        c.open[0] = U64(P.cut_open[k]);
+        c.open[1] = U64(P.cut_open[k]) + cp.open_cap;
+        c.open_cap = (uint32_t)cp.open_cap;
+        c.n_open = U32(P.cut_ctr[k]);
+        c.n_ent = c.n_open + MAXD;
+        c.tile_ctr = c.n_open + 2 * MAXD;
+        c.ent = U64(P.cut_ent[k]);
+        c.status = reinterpret_cast<unsigned long long *>(ws + P.cut_st[k]);
+        for (int l = 0; l <= MAXD; ++l) {
+            c.ent_off[l] = l <= g + 1 ? cp.ent_off[l] : cp.ent_off[g + 1];
+            c.st_off[l] = l <= g + 1 ? cp.st_off[l] : cp.st_off[g + 1];
+        }
+        c.over = k == 0 ? &ctrs->oversized : &ctrs->wc_over;
+        c.err = &ctrs->internal_error;
+        c.num_out = k == 0 ? &ctrs->num_chunks : &ctrs->num_wc;
+        c.max_out = (uint32_t)(k == 0 ? P.maxC : P.maxW);
+        c.out_level = k == 0 ? U8(P.c_level) : U8(P.w_level);
+        c.out_key = k == 0 ? U64(P.c_key) : U64(P.w_key);
+        c.out_count = k == 0 ? U32(P.c_count) : U32(P.w_count);
+        c.out_start = k == 0 ? U64(P.c_start) : U64(P.w_start);
+        c.idx = U32(P.cut_idx[k]);
+    }
+    launch_cut(pyr, cut[0], cut[1], st);
+    CutIndex chunk_index{U64(P.c_start), U32(P.cut_idx[0]), 3 * (g - P.lt)};
+    CutIndex wc_index{U64(P.w_start), U32(P.cut_idx[1]), 3 * (g - P.lt)};
+    launch_wc_chunks(&ctrs->num_wc, P.maxW, U64(P.w_key), U8(P.w_level), g, pyr, chunk_index, U8(P.c_level),
                      &ctrs->num_chunks, P.maxC, U32(P.wc_chunk), U32(P.seg_b0), U32(P.seg_nb), U8(P.wc_nested),
                      ctrs->wc_flags, st);
     t_cut.end(st);
@@ -751,7 +813,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     {
         MsInput in;
         in.code = U64(P.code);
-        in.table = U32(P.ec);
+        in.cut = chunk_index;
         in.code_shift = 3 * (KB - g);
         in.pay = U64(P.code);
         MsOutput o;
@@ -766,7 +828,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     {
         MsInput in;
         in.code = U64(P.code_perm);
-        in.table = U32(P.ew);
+        in.cut = wc_index;
         in.code_shift = 3 * (KB - P.lam_w);
         in.pay = U64(P.code_perm);
         MsOutput o;

@@ -82,14 +82,57 @@ void launch_quantize(const float *x, const float *y, const float *z, uint64_t n,
                      uint64_t base, uint64_t *cellmin, hipStream_t st, int variant);
 void launch_pyramid(uint32_t *pyr, int g, hipStream_t st);
 void launch_grid_export(const uint32_t *fine_morton, int g, uint32_t *rowmajor, hipStream_t st);
-void launch_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev, int lmin,
-                      hipStream_t st);
-// Table of the cut (entries at excl[m] for flagged cells m); entries at or
-// beyond max_out are not written and set *cap_flag.
-void launch_cut_table(const uint32_t *pyr, int lam, const uint32_t *flags, const uint32_t *excl,
-                      const uint8_t *lev, uint8_t *t_level, uint64_t *t_key, uint32_t *t_count,
-                      uint64_t *t_start, uint32_t thresh, uint32_t *over_flag, uint64_t max_out,
-                      uint32_t *cap_flag, hipStream_t st);
+constexpr int FR_BLOCK = 256;   // parents per tile of a frontier launch
+
+// The chunk cut and the work-chunk cut (entries = maximal nodes at or below a
+// threshold, oversized finest cells), found top-down over the heavy nodes.
+// One per cut; the host sizes every list from n (see cut_plan in fpo_api.hip).
+struct CutArgs {
+    uint32_t thresh;             // light: count <= thresh
+    int lmin;                    // entries only at levels >= lmin
+    int lam;                     // finest level (log2 G)
+    int lt;                      // level of the coarse index (min(lam, 7))
+    uint64_t *open[2];           // heavy nodes of a level (ping-pong by level parity), open_cap each
+    uint32_t open_cap;
+    uint32_t *n_open;            // [MAXD] heavy nodes per level
+    uint64_t *ent;               // entry keys; level l's at ent + ent_off[l], capacity ent_off[l + 1] - ent_off[l]
+    uint64_t ent_off[MAXD + 1];
+    uint32_t *n_ent;             // [MAXD] entries per level
+    unsigned long long *status;  // chained-scan words; level l's tiles at status + st_off[l]
+    uint64_t st_off[MAXD + 1];
+    uint32_t *tile_ctr;          // [MAXD]
+    uint32_t *over;              // set when an entry holds more than thresh points (oversized)
+    uint32_t *err;               // set when a list exceeds its capacity
+    uint32_t *num_out;           // number of entries
+    uint32_t max_out;            // capacity of the outputs below
+    uint8_t *out_level;          // entries in Morton pre-order: level, key, count, first finest cell
+    uint64_t *out_key;
+    uint32_t *out_count;
+    uint64_t *out_start;
+    uint32_t *idx;               // 8^lt + 1 words: entries starting before each coarse cell
+};
+// cut init, one frontier launch per level, rank, coarse index
+void launch_cut(const uint32_t *pyr, const CutArgs &chunks, const CutArgs &wcs, hipStream_t st);
+
+// Entry containing finest cell m (a cell holding points): the last entry
+// starting at or before m, searched among those starting inside m's coarse
+// cell (indices idx[c] .. idx[c + 1]) and else the one before them.
+struct CutIndex {
+    const uint64_t *starts;      // first finest cell of every entry, ascending
+    const uint32_t *idx;         // CutArgs::idx
+    int tsh;                     // 3 * (lam - lt)
+};
+__device__ __forceinline__ uint32_t cut_find(const CutIndex &X, uint64_t m)
+{
+    const uint64_t c = m >> X.tsh;
+    uint32_t lo = X.idx[c], hi = X.idx[c + 1];
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (X.starts[mid] <= m) lo = mid + 1; else hi = mid;
+    }
+    return lo ? lo - 1 : 0u;
+}
+
 void launch_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t st);
 // Device-wide exclusive scan of n u32 values; *total (device) gets the sum.
 size_t scan_temp_bytes(uint64_t n);
@@ -99,8 +142,8 @@ void scan_exclusive(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tot
 // Stable multisplit (counting sort) by u32 keys.
 struct MsInput {
     const uint32_t *keys = nullptr;    // explicit keys, or
-    const uint64_t *code = nullptr;    // key = table[code[e] >> code_shift]
-    const uint32_t *table = nullptr;
+    const uint64_t *code = nullptr;    // key = the cut entry holding cell code[e] >> code_shift
+    CutIndex cut{};
     int code_shift = 0;
     const uint32_t *vals = nullptr;    // values (null: the input position)
     const uint64_t *pay = nullptr;     // optional payload carried along
@@ -122,7 +165,7 @@ struct MsArgs {
     uint64_t n;
     const uint32_t *keys;
     const uint64_t *code;
-    const uint32_t *table;
+    CutIndex cut;
     int code_shift;
     const uint32_t *vals;
     const uint64_t *pay;
@@ -144,7 +187,6 @@ void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, u
 // Exclusive scan whose length is read on the device (*n_dev <= n_max).
 void scan_exclusive_dev(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t n_max, void *temp,
                         hipStream_t st);
-void launch_cell_ids(const uint32_t *flags, uint32_t *excl_to_ids, uint64_t ncell, hipStream_t st);
 
 // Subsample step.
 struct WcArgs {
@@ -238,7 +280,7 @@ uint64_t np_job_entries(uint64_t n);
 // spans several chunks, flags[1] when a chunk holds more than MS_MAX_BINS work
 // chunks.  Counts are read on the device; grids cover max_wc / max_chunks.
 void launch_wc_chunks(const uint32_t *num_wc_dev, uint64_t max_wc, const uint64_t *wc_key, const uint8_t *wc_level,
-                      int g, const uint32_t *pyr, const uint32_t *cid_table, const uint8_t *chunk_level,
+                      int g, const uint32_t *pyr, const CutIndex &chunks, const uint8_t *chunk_level,
                       const uint32_t *num_chunks_dev, uint64_t max_chunks, uint32_t *wc_chunk, uint32_t *seg_b0,
                       uint32_t *seg_nb, uint8_t *wc_nested, uint32_t *flags, hipStream_t st);
 void launch_node_fill(const WcArgs &a, const uint32_t *node_base, uint8_t *depth, uint64_t *key,

@@ -588,53 +588,211 @@ __global__ void k_grid_export(const uint32_t *fine, int g, uint32_t *out)
 // holds at most thresh points or l == lam, and l == lmin or its parent holds
 // more than thresh.  flags[m] = 1 at the first level-lam cell m of every chunk; lev[m] =
 // its level.  Chunks are disjoint, so at most one level can start at m.
-__global__ void k_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev, int lmin)
+// ---- step 2b: chunk and work-chunk cuts ---------------------------------------------------
+// A node of a cut is heavy when it lies above the cut's first level lmin, or
+// holds more than the cut's threshold (C for chunks, WC_CAP for work chunks)
+// and is not a finest cell.  The cut's entries are the non-empty children of
+// heavy nodes that are not heavy themselves (the maximal nodes at or below
+// threshold; oversized finest cells), and the root when it is not heavy.
+// They are found top-down from the heavy nodes alone, one launch per level:
+// a launch classifies the eight children of every heavy node of the level
+// above and compacts the heavy children and the entries, each in key order,
+// with a single-pass chained scan over tiles of parents.  Work is
+// proportional to the heavy nodes (at most n / (threshold + 1) per level), not
+// to the G^3 cells of the finest level.  k_cut_rank then merges the per-level
+// lists into Morton pre-order, and k_cut_index builds the coarse index that
+// maps a finest cell to its entry.
+constexpr uint64_t FR_SPIN_LIMIT = 1ull << 22;   // look-back polls before giving up (internal error)
+
+__device__ __forceinline__ uint64_t fr_load(const unsigned long long *p)
 {
-    const uint64_t ncell = 1ull << (3 * lam);
-    for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < ncell;
-         m += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t f = 0;
-        uint8_t lv = 0;
-        for (int l = 0; l <= lam; ++l) {
-            const int sh = 3 * (lam - l);
-            const uint64_t a = m >> sh;
-            const uint32_t cnt = pyr[pyr_off(l) + a];
-            if (cnt == 0) break;
-            if (l >= lmin && (cnt <= thresh || l == lam)) {
-                // the node at level l containing m is the chunk; it starts here
-                // only if m is its first cell
-                if ((m & ((1ull << sh) - 1ull)) == 0) { f = 1; lv = (uint8_t)l; }
-                break;
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fr_store(unsigned long long *p, uint64_t v)
+{
+    __hip_atomic_store(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// status word of a tile: flag (1 aggregate, 2 inclusive prefix) << 62 |
+// heavy count << 31 | entry count
+__device__ __forceinline__ uint64_t fr_word(uint64_t flag, uint64_t o, uint64_t e) { return flag << 62 | o << 31 | e; }
+
+__global__ void k_cut_init(const uint32_t *pyr, CutArgs c0, CutArgs c1)
+{
+    for (int which = 0; which < 2; ++which) {
+        const CutArgs &a = which ? c1 : c0;
+        const uint64_t ns = a.st_off[a.lam + 1];
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns;
+             i += (uint64_t)gridDim.x * blockDim.x)
+            a.status[i] = 0ull;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            for (int l = 0; l < MAXD; ++l) a.n_open[l] = a.n_ent[l] = a.tile_ctr[l] = 0u;
+            const uint32_t n = pyr[0];
+            if (n == 0) continue;
+            if (a.lmin == 0 && (n <= a.thresh || a.lam == 0)) {
+                a.ent[a.ent_off[0]] = 0ull;   // the root is the only entry
+                a.n_ent[0] = 1u;
+                if (n > a.thresh) atomicOr(a.over, 1u);
+            } else {
+                a.open[0][0] = 0ull;
+                a.n_open[0] = 1u;
             }
         }
-        flags[m] = f;
-        lev[m] = lv;
     }
 }
 
-__global__ void k_cut_table(const uint32_t *pyr, int lam, const uint32_t *flags, const uint32_t *excl,
-                            const uint8_t *lev, uint8_t *t_level, uint64_t *t_key, uint32_t *t_count,
-                            uint64_t *t_start, uint32_t thresh, uint32_t *over_flag, uint64_t max_out,
-                            uint32_t *cap_flag)
+// Children (level l) of the heavy nodes of level l - 1; blockIdx.y = cut.
+__global__ __launch_bounds__(FR_BLOCK) void k_frontier(const uint32_t *pyr, int l, CutArgs c0, CutArgs c1)
 {
-    const uint64_t ncell = 1ull << (3 * lam);
-    for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < ncell;
-         m += (uint64_t)gridDim.x * blockDim.x) {
-        if (!flags[m]) continue;
-        const uint32_t id = excl[m];
-        if (id >= max_out) {   // beyond the planned table: reported, never written
-            atomicOr(cap_flag, 1u);
-            continue;
+    const CutArgs &a = blockIdx.y ? c1 : c0;
+    __shared__ uint32_t lds[FR_BLOCK / 64 + 1];
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_po, s_pe;
+    const uint32_t n_in = min(a.n_open[l - 1], a.open_cap);
+    const uint32_t live = (n_in + FR_BLOCK - 1) / FR_BLOCK;
+    if (blockIdx.x >= live) return;   // exactly `live` blocks take tiles
+    if (threadIdx.x == 0) s_tile = atomicAdd(&a.tile_ctr[l], 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t i = tile * FR_BLOCK + threadIdx.x;
+    const uint64_t *in = a.open[(l - 1) & 1];
+    uint64_t pk = 0;
+    uint32_t om = 0, em = 0;
+    bool over = false;
+    if (i < n_in) {
+        pk = in[i];
+        const uint32_t *ch = pyr + pyr_off(l) + (pk << 3);
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const uint32_t c = ch[o];
+            if (c == 0) continue;
+            if (l < a.lmin || (c > a.thresh && l < a.lam)) {
+                om |= 1u << o;
+            } else {
+                em |= 1u << o;
+                over |= c > a.thresh;
+            }
         }
-        const int l = lev[m];
-        const uint64_t key = m >> (3 * (lam - l));
-        t_level[id] = (uint8_t)l;
-        t_key[id] = key;
-        const uint32_t cnt = pyr[pyr_off(l) + key];
-        t_count[id] = cnt;
-        if (t_start) t_start[id] = m;
-        if (over_flag && cnt > thresh) atomicOr(over_flag, 1u);
     }
+    const uint32_t no = __popc(om), ne = __popc(em);
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<FR_BLOCK>(no | ne << 16, lds, &tot);   // at most 8 * FR_BLOCK each
+    const uint64_t bo = tot & 0xffffu, be = tot >> 16;
+    unsigned long long *st = a.status + a.st_off[l];
+    if (threadIdx.x == 0) {
+        uint64_t po = 0, pe = 0;
+        if (tile == 0) {
+            fr_store(&st[0], fr_word(2, bo, be));
+        } else {
+            fr_store(&st[tile], fr_word(1, bo, be));
+            uint32_t j = tile - 1;
+            uint64_t spins = 0;
+            for (;;) {
+                const uint64_t w = fr_load(&st[j]);
+                const uint64_t f = w >> 62;
+                if (f == 0) {
+                    if (++spins > FR_SPIN_LIMIT) {   // never expected: report, and end the wait
+                        atomicOr(a.err, 1u);
+                        break;
+                    }
+                    continue;
+                }
+                po += (w >> 31) & 0x7fffffffull;
+                pe += w & 0x7fffffffull;
+                if (f == 2 || j == 0) break;
+                --j;
+            }
+            fr_store(&st[tile], fr_word(2, po + bo, pe + be));
+        }
+        if (tile == live - 1) {   // the last tile knows the level's totals
+            a.n_open[l] = (uint32_t)(po + bo);
+            a.n_ent[l] = (uint32_t)(pe + be);
+        }
+        s_po = po;
+        s_pe = pe;
+    }
+    __syncthreads();
+    uint64_t oo = s_po + (ex & 0xffffu), oe = s_pe + (ex >> 16);
+    const uint64_t ecap = a.ent_off[l + 1] - a.ent_off[l];
+    uint64_t *out = a.open[l & 1];
+    bool full = false;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        if (om >> o & 1u) {
+            if (oo < a.open_cap) out[oo] = pk << 3 | (uint64_t)o; else full = true;
+            ++oo;
+        }
+        if (em >> o & 1u) {
+            if (oe < ecap) a.ent[a.ent_off[l] + oe] = pk << 3 | (uint64_t)o; else full = true;
+            ++oe;
+        }
+    }
+    if (full) atomicOr(a.err, 1u);
+    if (over) atomicOr(a.over, 1u);
+}
+
+// First index of keys[0..n) not below v (keys ascending).
+__device__ __forceinline__ uint32_t fr_lower_bound(const uint64_t *keys, uint32_t n, uint64_t v)
+{
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (keys[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Every entry's place in Morton pre-order (by first finest cell): its index in
+// its level's list plus, for every other level, how many of that level's
+// entries start before it (entries are disjoint, so a coarser one starts
+// before it iff its key is below the entry's ancestor key there, a finer one
+// iff its ancestor at the entry's level is below the entry's key).
+__global__ void k_cut_rank(const uint32_t *pyr, CutArgs c0, CutArgs c1)
+{
+    const CutArgs &a = blockIdx.y ? c1 : c0;
+    uint32_t ne[MAXD];
+    uint32_t total = 0;
+#pragma unroll
+    for (int l = 0; l < MAXD; ++l) {
+        const uint64_t cap = l <= a.lam ? a.ent_off[l + 1] - a.ent_off[l] : 0;
+        ne[l] = l <= a.lam ? (uint32_t)min((uint64_t)a.n_ent[l], cap) : 0u;
+        total += ne[l];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *a.num_out = total;
+        if (total > a.max_out) atomicOr(a.err, 1u);
+    }
+    const uint64_t slots = a.ent_off[a.lam + 1];
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
+         s += (uint64_t)gridDim.x * blockDim.x) {
+        int l = 0;
+        while (a.ent_off[l + 1] <= s) ++l;
+        const uint32_t i = (uint32_t)(s - a.ent_off[l]);
+        if (i >= ne[l]) continue;
+        const uint64_t key = a.ent[s];
+        uint64_t rank = i;
+        for (int m = 0; m <= a.lam; ++m) {
+            if (m == l || ne[m] == 0) continue;
+            const uint64_t v = m < l ? key >> (3 * (l - m)) : key << (3 * (m - l));
+            rank += fr_lower_bound(a.ent + a.ent_off[m], ne[m], v);
+        }
+        if (rank >= a.max_out) continue;   // reported above
+        a.out_level[rank] = (uint8_t)l;
+        a.out_key[rank] = key;
+        a.out_count[rank] = pyr[pyr_off(l) + key];
+        a.out_start[rank] = key << (3 * (a.lam - l));
+    }
+}
+
+// idx[c] = number of entries whose first finest cell lies before coarse cell
+// c of level lt (c = 0 .. 8^lt).
+__global__ void k_cut_index(CutArgs c0, CutArgs c1)
+{
+    const CutArgs &a = blockIdx.y ? c1 : c0;
+    const uint32_t num = min(*a.num_out, a.max_out);
+    const uint64_t cells = 1ull << (3 * a.lt);
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= cells;
+         c += (uint64_t)gridDim.x * blockDim.x)
+        a.idx[c] = fr_lower_bound(a.out_start, num, c << (3 * (a.lam - a.lt)));
 }
 
 __global__ void k_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n)
@@ -804,11 +962,6 @@ void scan_exclusive_dev(const uint32_t *in, uint32_t *out, const uint32_t *n_dev
     hipLaunchKernelGGL(k_scan_down<false>, dim3(tiles), dim3(SCAN_BLOCK), 0, st, in, out, n_max, n_dev, ts, nullptr);
 }
 
-__global__ void k_cell_ids(const uint32_t *flags, uint32_t *ids, uint64_t ncell)
-{
-    for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < ncell; m += (uint64_t)gridDim.x * blockDim.x)
-        ids[m] = ids[m] + flags[m] - 1u;
-}
 
 // ---- stable multisplit ------------------------------------------------------------------------
 // Counting sort of n elements by a key with at most MS_MAX_BINS buckets per
@@ -844,7 +997,7 @@ __device__ __forceinline__ void ms_load_keys(const MsArgs &A, uint64_t wlo, uint
             c[r] = A.code[e < hi ? e : hi - 1];
         }
 #pragma unroll
-        for (int r = 0; r < N; ++r) full[r] = A.table[c[r] >> A.code_shift];
+        for (int r = 0; r < N; ++r) full[r] = cut_find(A.cut, c[r] >> A.code_shift);
     }
 }
 
@@ -1159,7 +1312,7 @@ void multisplit(const MsInput &in, uint64_t n, uint32_t nbins, const MsOutput &o
     A.n = n;
     A.keys = in.keys;
     A.code = in.code;
-    A.table = in.table;
+    A.cut = in.cut;
     A.code_shift = in.code_shift;
     A.vals = in.vals;
     A.pay = in.pay;
@@ -1214,7 +1367,7 @@ void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, u
     A.n = n;
     A.keys = in.keys;
     A.code = in.code;
-    A.table = in.table;
+    A.cut = in.cut;
     A.code_shift = in.code_shift;
     A.vals = in.vals;
     A.pay = in.pay;
@@ -2763,7 +2916,7 @@ __global__ __launch_bounds__(NPM_BLOCK) void k_np_merge(const uint64_t *jobs, co
 // of the work chunk (found by descending the count pyramid; an occupied cell
 // always lies inside a chunk).
 __global__ void k_wc_chunks(const uint32_t *num_wc_dev, uint32_t max_wc, const uint64_t *wc_key, const uint8_t *wc_level, int g,
-                            const uint32_t *pyr, const uint32_t *cid_table, const uint8_t *chunk_level,
+                            const uint32_t *pyr, CutIndex chunks, const uint8_t *chunk_level,
                             uint32_t *wc_chunk, uint8_t *wc_nested, uint32_t *flags)
 {
     const uint32_t num_wc = min(*num_wc_dev, max_wc);
@@ -2775,7 +2928,7 @@ __global__ void k_wc_chunks(const uint32_t *num_wc_dev, uint32_t max_wc, const u
             while (o < 7 && ch[o] == 0) ++o;   // the work chunk holds a point, so some child does
             m = (m << 3) | o;
         }
-        const uint32_t c = cid_table[m];
+        const uint32_t c = cut_find(chunks, m);
         wc_chunk[w] = c;
         const bool nested = chunk_level[c] <= wc_level[w];
         wc_nested[w] = nested ? 1 : 0;
@@ -3022,12 +3175,6 @@ void launch_grid_export(const uint32_t *fine, int g, uint32_t *out, hipStream_t 
     hipLaunchKernelGGL(k_grid_export, dim3(grid_for(1ull << (3 * g), 256)), dim3(256), 0, st, fine, g, out);
 }
 
-void launch_cut_flags(const uint32_t *pyr, int lam, uint32_t thresh, uint32_t *flags, uint8_t *lev, int lmin,
-                      hipStream_t st)
-{
-    hipLaunchKernelGGL(k_cut_flags, dim3(grid_for(1ull << (3 * lam), 256)), dim3(256), 0, st, pyr, lam, thresh, flags,
-                       lev, lmin);
-}
 
 void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream_t st)
 {
@@ -3044,18 +3191,23 @@ void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream
         hipLaunchKernelGGL(k_wc_alive_rows, dim3(grid_for(a.num_wc, 4, 4096)), dim3(256), 0, st, a);
 }
 
-void launch_cut_table(const uint32_t *pyr, int lam, const uint32_t *flags, const uint32_t *excl, const uint8_t *lev,
-                      uint8_t *t_level, uint64_t *t_key, uint32_t *t_count, uint64_t *t_start, uint32_t thresh,
-                      uint32_t *over_flag, uint64_t max_out, uint32_t *cap_flag, hipStream_t st)
+void launch_cut(const uint32_t *pyr, const CutArgs &chunks, const CutArgs &wcs, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cut_table, dim3(grid_for(1ull << (3 * lam), 256)), dim3(256), 0, st, pyr, lam, flags, excl,
-                       lev, t_level, t_key, t_count, t_start, thresh, over_flag, max_out, cap_flag);
+    const uint64_t ns = chunks.st_off[chunks.lam + 1] > wcs.st_off[wcs.lam + 1] ? chunks.st_off[chunks.lam + 1]
+                                                                                  : wcs.st_off[wcs.lam + 1];
+    hipLaunchKernelGGL(k_cut_init, dim3(grid_for(ns, 256, 1024)), dim3(256), 0, st, pyr, chunks, wcs);
+    for (int l = 1; l <= chunks.lam; ++l) {
+        const uint64_t t0 = chunks.st_off[l + 1] - chunks.st_off[l], t1 = wcs.st_off[l + 1] - wcs.st_off[l];
+        const uint64_t tiles = t0 > t1 ? t0 : t1;
+        if (tiles) hipLaunchKernelGGL(k_frontier, dim3((uint32_t)tiles, 2), dim3(FR_BLOCK), 0, st, pyr, l, chunks, wcs);
+    }
+    const uint64_t slots = chunks.ent_off[chunks.lam + 1] > wcs.ent_off[wcs.lam + 1] ? chunks.ent_off[chunks.lam + 1]
+                                                                                      : wcs.ent_off[wcs.lam + 1];
+    hipLaunchKernelGGL(k_cut_rank, dim3(grid_for(slots, 256, 2048), 2), dim3(256), 0, st, pyr, chunks, wcs);
+    const uint64_t cells = (1ull << (3 * chunks.lt)) + 1;
+    hipLaunchKernelGGL(k_cut_index, dim3(grid_for(cells, 256, 2048), 2), dim3(256), 0, st, chunks, wcs);
 }
 
-void launch_cell_ids(const uint32_t *flags, uint32_t *excl_to_ids, uint64_t ncell, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_cell_ids, dim3(grid_for(ncell, 256)), dim3(256), 0, st, flags, excl_to_ids, ncell);
-}
 
 void launch_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t st)
 {
@@ -3112,13 +3264,13 @@ void launch_node_counts(const WcArgs &a, uint32_t *owned, hipStream_t st)
 }
 
 void launch_wc_chunks(const uint32_t *num_wc_dev, uint64_t max_wc, const uint64_t *wc_key, const uint8_t *wc_level,
-                      int g, const uint32_t *pyr, const uint32_t *cid_table, const uint8_t *chunk_level,
+                      int g, const uint32_t *pyr, const CutIndex &chunks, const uint8_t *chunk_level,
                       const uint32_t *num_chunks_dev, uint64_t max_chunks, uint32_t *wc_chunk, uint32_t *seg_b0,
                       uint32_t *seg_nb, uint8_t *wc_nested, uint32_t *flags, hipStream_t st)
 {
     hipLaunchKernelGGL(k_wc_chunks, dim3(grid_for(max_wc, 256)), dim3(256), 0, st, num_wc_dev, (uint32_t)max_wc, wc_key,
                        wc_level, g, pyr,
-                       cid_table, chunk_level, wc_chunk, wc_nested, flags);
+                       chunks, chunk_level, wc_chunk, wc_nested, flags);
     hipLaunchKernelGGL(k_wc_segs, dim3(grid_for(max_wc, 256)), dim3(256), 0, st, num_wc_dev, (uint32_t)max_wc, wc_chunk,
                        seg_b0, seg_nb);
     hipLaunchKernelGGL(k_wc_chunks_nb, dim3(grid_for(max_chunks, 256)), dim3(256), 0, st, num_chunks_dev, seg_b0, seg_nb,
