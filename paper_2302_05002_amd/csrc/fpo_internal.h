@@ -124,6 +124,10 @@ struct CutIndex {
 };
 __device__ __forceinline__ uint32_t cut_find(const CutIndex &X, uint64_t m)
 {
+    if (X.tsh == 0) {   // the index is at the finest level: entries starting at or before m
+        const uint32_t v = X.idx[m + 1];
+        return v ? v - 1 : 0u;
+    }
     const uint64_t c = m >> X.tsh;
     uint32_t lo = X.idx[c], hi = X.idx[c + 1];
     while (lo < hi) {

@@ -1408,30 +1408,32 @@ void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, u
 // tentative depth is at or below the cut belong to that leaf.
 
 // Global shared depths d < d0, in work-chunk order.  Every alive point
-// (state 0xff) offers its original index to its cell of level d + s; a wave
-// whose alive points share one cell (work-chunk order is spatially coherent)
-// offers only its minimum.
+// (state 0xff) offers its original index to its cell of level d + s.  The
+// order is spatially coherent, so a wave's alive points usually fall in a few
+// cells: up to four of them are reduced inside the wave (one atomic each, a
+// ballot and a butterfly minimum per cell), the rest offer their own index.
 __global__ void k_gdepth_min(const uint64_t *__restrict__ code, const uint32_t *__restrict__ orig,
                              const uint8_t *__restrict__ t, uint64_t n, int csh, uint32_t *gtab)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint32_t lane = lane_id();
     for (uint64_t q0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); q0 < n; q0 += stride) {
-        const uint64_t q = q0 + lane_id();
+        const uint64_t q = q0 + lane;
         const bool alive = q < n && t[q] == 0xffu;
         const uint64_t cell = alive ? code[q] >> csh : 0ull;
         const uint32_t o = alive ? orig[q] : 0xffffffffu;
-        const uint64_t am = __ballot(alive);
-        if (!am) continue;
-        const int leader = __ffsll((long long)am) - 1;
-        const uint64_t c0 = __shfl(cell, leader, 64);
-        if (__ballot(alive && cell != c0) == 0) {
-            uint32_t m = o;
+        uint64_t pending = __ballot(alive);
+        for (int round = 0; round < 4 && pending; ++round) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const uint64_t c0 = __shfl(cell, leader, 64);
+            const bool mine = ((pending >> lane) & 1ull) && cell == c0;
+            uint32_t m = mine ? o : 0xffffffffu;
 #pragma unroll
             for (int k = 32; k > 0; k >>= 1) m = min(m, (uint32_t)__shfl_xor(m, k, 64));
-            if (lane_id() == leader) atomicMin(&gtab[c0], m);
-        } else if (alive) {
-            atomicMin(&gtab[cell], o);
+            if ((int)lane == leader) atomicMin(&gtab[c0], m);
+            pending &= ~__ballot(mine);
         }
+        if ((pending >> lane) & 1ull) atomicMin(&gtab[cell], o);
     }
 }
 
