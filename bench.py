@@ -484,6 +484,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="CPU work budget of the oracle baseline")
     ap.add_argument("--no-mix", action="store_true", help="skip the batched and served comparisons")
     ap.add_argument("--no-stream", action="store_true", help="skip the streamed 200M-point build")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default kernel shapes (profiling runs)")
+    ap.add_argument("--no-config1", action="store_true", help="skip the 1M-point leg (profiling runs)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the LAS decode, preview variant, gather and node selection legs")
     args = ap.parse_args()
@@ -512,9 +514,11 @@ def main():
     ws = torch.empty(fpo.workspace_size(n, params), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
 
-    tuned = ctx.autotune(x, y, z, params, workspace=ws, reps=3)
-    print(f"[bench] autotuned quantise shape {tuned['quantize_variant']} "
-          f"(ms per shape {['%.3f' % v for v in tuned['quantize_ms']]})", file=sys.stderr, flush=True)
+    tuned = None
+    if not args.no_tune:
+        tuned = ctx.autotune(x, y, z, params, workspace=ws, reps=3)
+        print(f"[bench] autotuned quantise shape {tuned['quantize_variant']} "
+              f"(ms per shape {['%.3f' % v for v in tuned['quantize_ms']]})", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         job = ctx.submit(x, y, z, params, workspace=ws, stream=stream)
         job.wait()
@@ -722,7 +726,7 @@ def main():
         "autotuned": tuned,
         **extras,
     }
-    if args.workload != "uniform1m":
+    if args.workload != "uniform1m" and not args.no_config1:
         out["config1"] = bench_config1(fpo, torch, ctx, args.steps)
         print(f"[bench] 1M uniform: {out['config1']['ms_per_build']:.3f} ms per build, "
               f"{out['config1']['path']['frac_of_step']:.4f} of HBM peak", file=sys.stderr, flush=True)
