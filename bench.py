@@ -278,10 +278,11 @@ class ServedTrace:
         return self.points / dt
 
 
-def bench_served(fpo, torch, ctx, trace: ServedTrace, serial_pps: float, load: float, slots: int = 4,
+def bench_served(fpo, torch, ctx, trace: ServedTrace, serial_pps: float, load, slots: int = 4,
                  budget: int = 200 * 10 ** 9) -> dict:
     """Requests submitted on their Poisson schedule, rescaled so that the
-    offered load is `load` times the serial plain loop's capacity, into a
+    offered load is `load` times the serial plain loop's capacity (None: all
+    at once, the server's capacity), into a
     server with `slots` slots and an HBM budget of `budget` bytes.  A client
     thread collects results in arrival order and releases each at once (a
     request holds its share of the budget until then).  Latency = completion
@@ -291,9 +292,12 @@ def bench_served(fpo, torch, ctx, trace: ServedTrace, serial_pps: float, load: f
     import threading
     reqs = trace.reqs
     num = len(reqs)
-    rate = load * serial_pps / (trace.points / num)   # requests per second
-    mean_gap = reqs[-1].arrival / max(num - 1, 1)
-    scale = (1.0 / rate) / mean_gap
+    if load is None:
+        scale = 0.0
+    else:
+        rate = load * serial_pps / (trace.points / num)   # requests per second
+        mean_gap = reqs[-1].arrival / max(num - 1, 1)
+        scale = (1.0 / rate) / mean_gap
     srv = fpo.Server(ctx, budget, slots)
     for i in range(slots):   # warm-up of the slot streams
         j = srv.submit(*trace.cloud(i), trace.params[i])
@@ -329,8 +333,9 @@ def bench_served(fpo, torch, ctx, trace: ServedTrace, serial_pps: float, load: f
     first, last = span
     lat = np.array(lat)
     served = trace.points / ((last - first) / 1e9)
-    return {"workload": f"{num} requests (100k-50M points, log-uniform; uniform, planes, clusters), Poisson "
-                        f"arrivals at {load}x the serial capacity, {slots} slots, {budget / 1e9:.0f} GB budget",
+    arrivals = "all submitted at once" if load is None else f"Poisson arrivals at {load}x the serial capacity"
+    return {"workload": f"{num} requests (100k-50M points, log-uniform; uniform, planes, clusters), {arrivals}, "
+                        f"{slots} slots, {budget / 1e9:.0f} GB budget",
             "requests": num, "points": trace.points, "serial_points_per_s": serial_pps,
             "served_points_per_s": served, "speedup": served / serial_pps,
             "makespan_s": (last - first) / 1e9,
@@ -742,6 +747,10 @@ def main():
               flush=True)
         out["served"] = bench_served(fpo, torch, ctx, trace, serial_pps, 1.25)
         print(f"[bench] served {out['served']['speedup']:.2f}x serial, p99 {out['served']['latency_ms_p99']:.1f} ms",
+              file=sys.stderr, flush=True)
+        # every request at once: the server's capacity against the serial loop
+        out["served_saturated"] = bench_served(fpo, torch, ctx, trace, serial_pps, None)
+        print(f"[bench] served, all requests at once: {out['served_saturated']['speedup']:.2f}x serial",
               file=sys.stderr, flush=True)
         # the same trace at half the serial capacity: latency without queueing
         out["served_half_load"] = bench_served(fpo, torch, ctx, trace, serial_pps, 0.5)
