@@ -110,7 +110,7 @@ struct Ctrs {
     uint32_t wc_flags[2];      // [0] a work chunk spans several chunks, [1] a chunk holds too many
     uint32_t cls_cnt[WC_CLASSES];   // work chunks per LDS size class
     uint32_t np_max;                // points of the largest node
-    uint32_t np_lists[5];           // node_points sort: tile lists of four sizes, merge jobs
+    uint32_t np_lists[6];           // node_points: tile lists of four sizes, merge jobs, copies
     uint32_t np_general;            // work chunks with own nodes below their root
     uint32_t wc_over;               // a work chunk holds more than WC_CAP points (one finest cell)
 };
@@ -164,7 +164,8 @@ struct Plan {
     size_t c_count_scan, code_perm, wc_orig, wc_code, ms_temp, scan_temp, seg_b0, seg_nb, wc_nested, wc_chunk;
     size_t gtab, t, fr, alive, alive_scan, kd, loff, owned, node_base, lnode_key, lnode_mask, cut;
     size_t big_list, big_nr, big_node, big_hkey, big_hval, cls_list;
-    size_t np_tmp, np_glist, np_cnt, np_scan, np_nb, np_l0, np_l1, np_l2, np_l3, np_jobs, pv_tiles, pv_offs, cellmin, pv_bits;
+    size_t np_tmp, np_glist, np_cnt, np_scan, np_nb, np_l0, np_l1, np_l2, np_l3, np_jobs, np_cp, np_single, pv_tiles, pv_offs,
+        cellmin, pv_bits;
     uint64_t pv_ntiles;
 };
 
@@ -286,6 +287,8 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     P.np_l2 = take(4 * np_list_entries(nn, 2));
     P.np_l3 = take(8 * np_list_entries(nn, 3));
     P.np_jobs = take(8 * np_job_entries(nn));
+    P.np_cp = take(8 * np_copy_entries(nn));
+    P.np_single = take(nn);
     P.pv_tiles = take(4 * P.pv_ntiles);
     P.pv_offs = take(4 * P.pv_ntiles);
     P.cellmin = (p.flags & FPO_PREVIEW_GRID) ? take(8 * P.G3) : 0;
@@ -904,7 +907,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     // read-back, they keep the device busy while the host waits for it
     t_ncnt.begin(st);
     launch_np_counts(A, U32(P.node_base), U32(P.np_cnt), U32(P.np_scan), U32(P.n_count), U32(P.owned),
-                     U32(P.np_glist), &ctrs->np_general, &ctrs->np_max, stemp, st);
+                     U32(P.np_glist), &ctrs->np_general, &ctrs->np_max, U8(P.np_single), stemp, st);
     t_ncnt.end(st);
     JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
     JCHK(hipStreamSynchronize(st));
@@ -928,6 +931,8 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         w.lists.c2 = U32(P.np_l2);
         w.lists.c3 = U64(P.np_l3);
         w.lists.jobs = U64(P.np_jobs);
+        w.lists.cp = U64(P.np_cp);
+        w.lists.single = U8(P.np_single);
         w.lists.counts = ctrs->np_lists;
         w.scan_temp = stemp;
         w.place_timer = &t_place;

@@ -251,15 +251,20 @@ void launch_node_counts(const WcArgs &a, uint32_t *owned, hipStream_t st);
 // for none) and that offset (in place of cnt_dw); work chunks with own nodes
 // below their root in glist (*gcount, zeroed before).  *maxc = the largest
 // node (zeroed before).
+// single[id] = 1 for every node filled by one piece in work-chunk order
+// (one work chunk contributes to it, not through the fill counters), so its
+// placed range already ascends; 0 for the others.
 void launch_np_counts(const WcArgs &a, const uint32_t *node_base, uint32_t *cnt_dw, uint32_t *S, uint32_t *cnt_node,
-                      uint32_t *pnode, uint32_t *glist, uint32_t *gcount, uint32_t *maxc, void *scan_temp,
-                      hipStream_t st);
+                      uint32_t *pnode, uint32_t *glist, uint32_t *gcount, uint32_t *maxc, uint8_t *single,
+                      void *scan_temp, hipStream_t st);
 constexpr uint32_t NP_MAX_NODES = 0x7fffffffu;   // the tile lists flag groups of nodes in bit 31
 struct NpLists {
     uint32_t *c0, *c1, *c2;   // tiles of up to 1024, 4096, 8192 values: a node, or a group of small nodes
     uint64_t *c3;             // parts of up to 16384 values of longer nodes
     uint64_t *jobs;           // merge jobs of the nodes above 16384 values
-    uint32_t *counts;         // 5 list lengths, zeroed before
+    uint64_t *cp;             // parts of up to 16384 values of nodes (or groups) already in order: copied
+    const uint8_t *single;    // per node: 1 when one piece in work-chunk order fills it (already ascending)
+    uint32_t *counts;         // 6 list lengths (c0..c3, jobs, cp), zeroed before
 };
 struct NpWork {
     uint32_t *nb;         // node begins (num_nodes + 1)
@@ -278,6 +283,7 @@ void launch_np_points(const WcArgs &a, const uint32_t *node_base, const uint32_t
                       hipStream_t st);
 uint64_t np_list_entries(uint64_t n, int cls);   // entries of tile list cls (0..3) for n points
 uint64_t np_job_entries(uint64_t n);
+uint64_t np_copy_entries(uint64_t n);
 // Chunk of every work chunk (the chunk holding its first occupied finest
 // cell), per chunk the range of its work chunks [b0, b0 + nb), per work chunk
 // whether it lies inside that chunk; flags[0] is set when some work chunk

@@ -2323,7 +2323,8 @@ __global__ void k_np_pieces(WcArgs a, uint32_t *cnt_dw)
 // cells), of such roots (the points reaching them).  Work chunks with own
 // nodes below their root are listed for k_np_count.
 __global__ void k_np_shared(WcArgs a, const uint32_t *node_base, const uint32_t *S, uint32_t *cnt_node,
-                            uint32_t *pnode, uint32_t *poff, uint32_t *glist, uint32_t *gcount, uint32_t *maxc)
+                            uint32_t *pnode, uint32_t *poff, uint32_t *glist, uint32_t *gcount, uint32_t *maxc,
+                            uint8_t *single)
 {
     const uint32_t W = a.num_wc;
     const uint64_t total = (uint64_t)MAXD * W;
@@ -2347,6 +2348,16 @@ __global__ void k_np_shared(WcArgs a, const uint32_t *node_base, const uint32_t 
                 const uint32_t c = S[(uint64_t)d * W + we] - S[i];
                 cnt_node[node_base[i]] = c;
                 mymax = max(mymax, c);
+                // one piece: the first non-empty piece of w .. we - 1 holds all c
+                // points, and its work chunk lies inside one chunk (so work-chunk
+                // order is index order there)
+                uint32_t lo = w, hi = we;   // first w' with a non-empty piece (S rises after it)
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (S[(uint64_t)d * W + mid + 1] > S[i]) hi = mid; else lo = mid + 1;
+                }
+                single[node_base[i]] =
+                    lo < we && S[(uint64_t)d * W + lo + 1] == S[(uint64_t)d * W + we] && a.wc_nested[lo] ? 1 : 0;
             }
             if (S[i + 1] > S[i]) {
                 const uint32_t o = first ? w : owner_of(a, w, d);
@@ -2359,6 +2370,7 @@ __global__ void k_np_shared(WcArgs a, const uint32_t *node_base, const uint32_t 
                 if (a.kd[(uint64_t)w * MAXD + lw + 1] == 0) {   // a leaf root, or every point kept there
                     node = node_base[i];
                     cnt_node[node] = reach;
+                    single[node] = a.wc_nested[w];   // placed from this work chunk alone, in index order if nested
                     mymax = max(mymax, reach);
                 } else {
                     glist[atomicAdd(gcount, 1u)] = w;
@@ -2375,7 +2387,8 @@ __global__ void k_np_shared(WcArgs a, const uint32_t *node_base, const uint32_t 
 // Per listed work chunk (one block each): the size of each of its own nodes
 // into cnt_node[id].
 __global__ __launch_bounds__(NP_BLOCK) void k_np_count(WcArgs a, const uint32_t *node_base, const uint32_t *glist,
-                                                       const uint32_t *gcount, uint32_t *cnt_node, uint32_t *maxc)
+                                                       const uint32_t *gcount, uint32_t *cnt_node, uint32_t *maxc,
+                                                       uint8_t *single)
 {
     __shared__ uint32_t cnt[NP_LCAP];
     __shared__ NpOwn own;
@@ -2411,13 +2424,20 @@ __global__ __launch_bounds__(NP_BLOCK) void k_np_count(WcArgs a, const uint32_t 
             }
         }
         __syncthreads();
+        // own nodes below a subdivided root are filled through counters (any
+        // order within a wave): sorted
         for (uint32_t i = threadIdx.x; i < nl; i += NP_BLOCK) {
             const uint32_t c = cnt[i];
-            cnt_node[own.id_of_slot(i, lw)] = c;
+            const uint32_t id = own.id_of_slot(i, lw);
+            cnt_node[id] = c;
+            single[id] = 0;
             mymax = max(mymax, c);
         }
-        for (uint32_t i = NP_LCAP + threadIdx.x; i < nown; i += NP_BLOCK)   // settled by the barrier above
-            mymax = max(mymax, atomicAdd(&cnt_node[own.id_of_slot(i, lw)], 0u));
+        for (uint32_t i = NP_LCAP + threadIdx.x; i < nown; i += NP_BLOCK) {   // settled by the barrier above
+            const uint32_t id = own.id_of_slot(i, lw);
+            single[id] = 0;
+            mymax = max(mymax, atomicAdd(&cnt_node[id], 0u));
+        }
         __syncthreads();
     }
     mymax = wave_max(mymax);
@@ -2440,7 +2460,7 @@ __global__ void k_np_lists(const uint32_t *nb, uint32_t nn, NpLists L)
     for (uint32_t x0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); x0 < nn; x0 += stride) {
         const uint32_t x = x0 + lane_id();
         const bool valid = x < nn;
-        uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0, nj = 0, g = 0;
+        uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0, nj = 0, ncp = 0, g = 0;
         bool grouped = false;
         if (valid) {
             g = x / NP_GROUP;
@@ -2450,9 +2470,17 @@ __global__ void k_np_lists(const uint32_t *nb, uint32_t nn, NpLists L)
             grouped = gx1 - gx0 > 1 && gt <= NP_T1;
             if (grouped) {
                 if (x == gx0) {
-                    n0 = gt <= NP_T0 ? 1u : 0u;
-                    n1 = 1u - n0;
+                    bool all = true;   // every node of the group already ascends: copied
+                    for (uint32_t y = gx0; y < gx1 && all; ++y) all = L.single[y] != 0;
+                    if (all) {
+                        ncp = 1;
+                    } else {
+                        n0 = gt <= NP_T0 ? 1u : 0u;
+                        n1 = 1u - n0;
+                    }
                 }
+            } else if (L.single[x]) {
+                ncp = c ? (c + NP_T3 - 1) / NP_T3 : 0u;
             } else if (c <= NP_T0) {
                 n0 = 1;
             } else if (c <= NP_T1) {
@@ -2473,12 +2501,37 @@ __global__ void k_np_lists(const uint32_t *nb, uint32_t nn, NpLists L)
         const uint32_t o0 = reserve(n0, &L.counts[0]), o1 = reserve(n1, &L.counts[1]);
         const uint32_t o2 = reserve(n2, &L.counts[2]), o3 = reserve(n3, &L.counts[3]);
         const uint32_t oj = reserve(nj, &L.counts[4]);
+        const uint32_t oc = reserve(ncp, &L.counts[5]);
         const uint32_t entry = grouped ? (g | NP_GROUP_FLAG) : x;
         if (n0) L.c0[o0] = entry;
         if (n1) L.c1[o1] = entry;
         if (n2) L.c2[o2] = entry;
         for (uint32_t k = 0; k < n3; ++k) L.c3[o3 + k] = ((uint64_t)x << 32) | k;
         for (uint32_t k = 0; k < nj; ++k) L.jobs[oj + k] = ((uint64_t)x << 32) | k;
+        for (uint32_t k = 0; k < ncp; ++k) L.cp[oc + k] = ((uint64_t)entry << 32) | k;
+    }
+}
+
+// Ranges already in ascending order, copied from the placement buffer to
+// node_points in parts of NP_T3 values (an entry: node or group << 32 | part).
+__global__ void k_np_copy(const uint64_t *list, const uint32_t *list_cnt, const uint32_t *nb, uint32_t nn,
+                          const uint32_t *src, uint32_t *dst)
+{
+    const uint32_t cnt = *list_cnt;
+    for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
+        const uint64_t v = list[e];
+        const uint32_t x = (uint32_t)(v >> 32), part = (uint32_t)v;
+        uint32_t lo, hi;
+        if (x & NP_GROUP_FLAG) {
+            const uint32_t g = x & ~NP_GROUP_FLAG;
+            lo = nb[g * NP_GROUP];
+            hi = nb[min(g * NP_GROUP + NP_GROUP, nn)];
+        } else {
+            lo = nb[x];
+            hi = nb[x + 1];
+        }
+        const uint32_t b = lo + part * NP_T3, end = min(hi, b + NP_T3);
+        for (uint32_t i = b + threadIdx.x; i < end; i += blockDim.x) dst[i] = src[i];
     }
 }
 
@@ -3287,8 +3340,8 @@ void launch_node_fill(const WcArgs &a, const uint32_t *node_base, uint8_t *depth
 }
 
 void launch_np_counts(const WcArgs &a, const uint32_t *node_base, uint32_t *cnt_dw, uint32_t *S, uint32_t *cnt_node,
-                      uint32_t *pnode, uint32_t *glist, uint32_t *gcount, uint32_t *maxc, void *scan_temp,
-                      hipStream_t st)
+                      uint32_t *pnode, uint32_t *glist, uint32_t *gcount, uint32_t *maxc, uint8_t *single,
+                      void *scan_temp, hipStream_t st)
 {
     if (a.num_wc == 0) return;
     const uint64_t rows = (uint64_t)MAXD * a.num_wc;
@@ -3296,9 +3349,9 @@ void launch_np_counts(const WcArgs &a, const uint32_t *node_base, uint32_t *cnt_
     scan_exclusive(cnt_dw, S, rows, S + rows, scan_temp, st);
     // the piece offsets replace the piece sizes (scanned into S already)
     hipLaunchKernelGGL(k_np_shared, dim3(grid_for(rows, 256)), dim3(256), 0, st, a, node_base, S, cnt_node, pnode,
-                       cnt_dw, glist, gcount, maxc);
+                       cnt_dw, glist, gcount, maxc, single);
     hipLaunchKernelGGL(k_np_count, dim3(a.num_wc < 2048 ? a.num_wc : 2048), dim3(NP_BLOCK), 0, st, a, node_base, glist,
-                       gcount, cnt_node, maxc);
+                       gcount, cnt_node, maxc, single);
 }
 
 void launch_np_points(const WcArgs &a, const uint32_t *node_base, const uint32_t *pnode, const uint32_t *poff,
@@ -3312,6 +3365,9 @@ void launch_np_points(const WcArgs &a, const uint32_t *node_base, const uint32_t
     const uint32_t pg = (a.num_wc + NPP_WAVES - 1) / NPP_WAVES;
     hipLaunchKernelGGL(k_np_place, dim3(pg < 4096 ? pg : 4096), dim3(64 * NPP_WAVES), 0, st, a, node_base, pnode, poff,
                        w.nb, w.fill, w.tmp, (uint32_t)n, w.err);
+    const uint64_t ncp = n / NP_T3 + num_nodes / NP_GROUP + 1;
+    hipLaunchKernelGGL(k_np_copy, dim3(ncp < 4096 ? (uint32_t)ncp : 4096), dim3(256), 0, st, w.lists.cp, w.lists.counts + 5,
+                       w.nb, num_nodes, w.tmp, w.out);
     if (w.place_timer) w.place_timer->end(st);
     if (w.sort_timer) w.sort_timer->begin(st);
     const uint32_t g0 = num_nodes < 8192 ? num_nodes : 8192;
@@ -3344,6 +3400,7 @@ uint64_t np_list_entries(uint64_t n, int cls)
     }
 }
 uint64_t np_job_entries(uint64_t n) { return n / NPM_OUT + n / NP_T3 + 2; }
+uint64_t np_copy_entries(uint64_t n) { return n + n / NP_T3 + 2; }
 
 static uint64_t preview_tiles(uint64_t n) { return (n + PV_TILE - 1) / PV_TILE; }
 
