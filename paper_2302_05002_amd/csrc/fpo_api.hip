@@ -612,12 +612,11 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     } while (0)
 
     JobTimer t_prev(job, FPO_TIMER_PREVIEW);
-    if (p->flags & (FPO_PREVIEW_GRID)) {
-        launch_fill_u32(reinterpret_cast<uint32_t *>(ctrs), 0u, sizeof(Ctrs) / 4, st);
-    } else {
-        t_prev.begin(st);   // (the preview region opens with the counters' fill)
-        launch_fill_u32(reinterpret_cast<uint32_t *>(ctrs), 0u, sizeof(Ctrs) / 4, st);
-    }
+    // the counters start at zero: cleared here, or by the first preview kernel
+    // when that is the build's first launch (hash and stride previews)
+    const bool early_preview = !(p->flags & FPO_PREVIEW_GRID) && n > 0;
+    if (!(p->flags & FPO_PREVIEW_GRID)) t_prev.begin(st);
+    if (!early_preview) launch_fill_u32(reinterpret_cast<uint32_t *>(ctrs), 0u, sizeof(Ctrs) / 4, st);
     if (n == 0) {
         t_prev.end(st);
         launch_fill_u32(U32(P.grid), 0u, P.G3, st);
@@ -639,6 +638,10 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     pa.code = U64(P.code);
     pa.cellmin = U64(P.cellmin);
     pa.shift = 3 * (KB - g);
+    if (early_preview) {
+        pa.zero = reinterpret_cast<uint32_t *>(ctrs);
+        pa.zero_words = sizeof(Ctrs) / 4;
+    }
     // ordered compaction of the kept indices, then the preview event (from
     // here on the job belongs to its holder)
     auto emit_preview = [&]() {
@@ -808,9 +811,14 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
 
     // chunk begins (u64) and work-chunk begins
     t_chunk.begin(st);
-    scan_exclusive(U32(P.c_count), U32(P.c_count_scan), num_chunks, nullptr, stemp, st);
-    launch_u32_to_u64(U32(P.c_count_scan), U64(P.c_begin), num_chunks, st);
-    scan_exclusive(U32(P.w_count), U32(P.w_begin), num_wc, nullptr, stemp, st);
+    if (num_chunks <= SCAN_PAIR_MAX && num_wc <= SCAN_PAIR_MAX) {
+        scan_exclusive_pair(U32(P.c_count), U32(P.c_count_scan), U64(P.c_begin), num_chunks, U32(P.w_count),
+                            U32(P.w_begin), num_wc, st);
+    } else {
+        scan_exclusive(U32(P.c_count), U32(P.c_count_scan), num_chunks, nullptr, stemp, st);
+        launch_u32_to_u64(U32(P.c_count_scan), U64(P.c_begin), num_chunks, st);
+        scan_exclusive(U32(P.w_count), U32(P.w_begin), num_wc, nullptr, stemp, st);
+    }
 
     // ---- step 3: stable scatter by chunk (perm) and by work chunk ----
     {
@@ -888,11 +896,17 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     A.s = s_;
     A.L = p->leaf_capacity;
     A.dmax = KB - s_;
-    launch_fill_u32(U32(P.kd), 0u, (uint64_t)MAXD * num_wc, st);
     // every point alive (0xff) until a depth keeps it; the shared depths above
-    // the work-chunk levels first, over all points
-    launch_fill_u32(reinterpret_cast<uint32_t *>(U8(P.t)), 0xffffffffu, (n + 3) / 4, st);
-    launch_global_depths(A, n, U32(P.gtab), st);
+    // the work-chunk levels first, over all points (their first table is
+    // cleared with the other two)
+    {
+        FillSpec f[4];
+        f[0] = {U32(P.kd), 0u, (uint64_t)MAXD * num_wc};
+        f[1] = {reinterpret_cast<uint32_t *>(U8(P.t)), 0xffffffffu, (n + 3) / 4};
+        if (P.d0 > 0) f[2] = {U32(P.gtab), 0xffffffffu, 1ull << (3 * P.s)};
+        launch_fill_many(f, st);
+    }
+    launch_global_depths(A, n, U32(P.gtab), st, true);
     // the class above WC_CAP points and the global-memory list are launched
     // only when the counters read back show they can hold work chunks
     launch_subsample_small(A, hctrs->wc_over != 0, st);

@@ -64,6 +64,13 @@ struct LaunchTimer {
 // Fill kernel (in place of hipMemsetAsync, which costs far more host time per
 // call and is not safe to record in a graph).
 void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t words, hipStream_t st);
+// Up to four fills in one launch (null or empty ones skipped).
+struct FillSpec {
+    uint32_t *p = nullptr;
+    uint32_t v = 0;
+    uint64_t words = 0;
+};
+void launch_fill_many(const FillSpec (&f)[4], hipStream_t st);
 // Bounding box: per-block partials (8 words each: 3 min, 3 max in an
 // order-preserving integer encoding, a non-finite flag), reduced by k_setup.
 constexpr uint32_t BBOX_MAX_BLOCKS = 2048;
@@ -138,6 +145,11 @@ __device__ __forceinline__ uint32_t cut_find(const CutIndex &X, uint64_t m)
 }
 
 void launch_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t st);
+// Two independent exclusive scans of at most SCAN_PAIR_MAX values each in one
+// launch (one block each); out0_wide (optional) gets the first as u64.
+constexpr uint64_t SCAN_PAIR_MAX = 16384;
+void scan_exclusive_pair(const uint32_t *in0, uint32_t *out0, uint64_t *out0_wide, uint64_t n0, const uint32_t *in1,
+                         uint32_t *out1, uint64_t n1, hipStream_t st);
 // Device-wide exclusive scan of n u32 values; *total (device) gets the sum.
 size_t scan_temp_bytes(uint64_t n);
 void scan_exclusive(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total, void *temp,
@@ -236,7 +248,8 @@ struct WcArgs {
 // Shared depths d < d0 over all points (t filled with 0xff before): winners
 // get t = d, and the reaching-count rows of those depths are written.
 // gtab: 4 * 8^(d0 - 1 + s) bytes.
-void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream_t st);
+// first_filled: the table of depth 0 was cleared to all ones already.
+void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream_t st, bool first_filled = false);
 // Work chunks above WC_CAP points (class 5) exist only when any_over.
 void launch_subsample_small(const WcArgs &a, bool any_over, hipStream_t st);
 // Every work chunk takes a fast class (own root a leaf): no general subtree.
@@ -313,6 +326,8 @@ struct PreviewArgs {
     const uint64_t *code;        // grid: Morton code per original index
     const uint64_t *cellmin;     // grid: least H64 per count-grid cell
     int shift;                   // grid: code >> shift = cell
+    uint32_t *zero = nullptr;    // words cleared by the first block (the build's counters), or null
+    uint32_t zero_words = 0;
 };
 // bits (ceil(n / 32) words) = the predicate of every index
 void launch_preview_bits(const PreviewArgs &p, uint32_t *bits, hipStream_t st);

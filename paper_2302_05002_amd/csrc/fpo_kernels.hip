@@ -915,6 +915,46 @@ __global__ __launch_bounds__(1024) void k_scan_small(const uint32_t *in, uint32_
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
+// Block b scans its own array (b = 0: in0 into out0 and out0_wide; b = 1:
+// in1 into out1), 4096 values per round with a running carry.
+__global__ __launch_bounds__(1024) void k_scan_pair(const uint32_t *in0, uint32_t *out0, uint64_t *out0_wide,
+                                                    uint64_t n0, const uint32_t *in1, uint32_t *out1, uint64_t n1)
+{
+    __shared__ uint32_t lds[1024 / 64 + 1];
+    const uint32_t *in = blockIdx.x ? in1 : in0;
+    uint32_t *out = blockIdx.x ? out1 : out0;
+    uint64_t *wide = blockIdx.x ? nullptr : out0_wide;
+    const uint64_t n = blockIdx.x ? n1 : n0;
+    uint32_t carry = 0;
+    for (uint64_t b = 0; b < n; b += 4096) {
+        const uint64_t e0 = b + 4ull * threadIdx.x;
+        uint32_t v[4], s = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = e0 + j < n ? in[e0 + j] : 0u;
+            s += v[j];
+        }
+        uint32_t t;
+        uint32_t run = carry + block_excl_scan<1024>(s, lds, &t);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (e0 + j < n) {
+                out[e0 + j] = run;
+                if (wide) wide[e0 + j] = run;
+            }
+            run += v[j];
+        }
+        carry += t;
+    }
+}
+
+void scan_exclusive_pair(const uint32_t *in0, uint32_t *out0, uint64_t *out0_wide, uint64_t n0, const uint32_t *in1,
+                         uint32_t *out1, uint64_t n1, hipStream_t st)
+{
+    if (n0 == 0 && n1 == 0) return;
+    hipLaunchKernelGGL(k_scan_pair, dim3(2), dim3(1024), 0, st, in0, out0, out0_wide, n0, in1, out1, n1);
+}
+
 size_t scan_temp_bytes(uint64_t n)
 {
     const uint64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
@@ -1448,30 +1488,41 @@ __global__ void k_gdepth_mark(const uint64_t *__restrict__ code, const uint32_t 
 }
 
 // Rows of the global shared depths: points of each WC alive at depth d < d0
-// (one wave per WC).
-__global__ void k_wc_alive_rows(WcArgs a)
+// (d0 = g - s <= 9), one block per WC: every thread counts its points placed
+// at each global depth, the block sums them in LDS.
+constexpr int AR_BLOCK = 256;
+constexpr int AR_MAXD0 = 10;   // global depths d < d0 <= 9
+__global__ __launch_bounds__(AR_BLOCK) void k_wc_alive_rows(WcArgs a)
 {
-    const uint32_t waves = gridDim.x * (blockDim.x / 64);
-    for (uint32_t w = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); w < a.num_wc; w += waves) {
+    __shared__ uint32_t placed[AR_MAXD0];
+    const int d0 = a.d0 < AR_MAXD0 ? a.d0 : AR_MAXD0;
+    for (uint32_t w = blockIdx.x; w < a.num_wc; w += gridDim.x) {
+        if (threadIdx.x < AR_MAXD0) placed[threadIdx.x] = 0;
+        __syncthreads();
         const uint32_t base = a.wc_begin[w], n = a.wc_count[w];
-        uint32_t placed[MAXD];   // constant indices only (kept in registers)
+        uint32_t c[AR_MAXD0];
 #pragma unroll
-        for (int d = 0; d < MAXD; ++d) placed[d] = 0;
-        for (uint32_t p0 = 0; p0 < n; p0 += 64) {
-            const uint32_t p = p0 + lane_id();
-            const uint32_t st = p < n ? a.t[base + p] : 0xffu;
+        for (int d = 0; d < AR_MAXD0; ++d) c[d] = 0;
+        for (uint32_t p = threadIdx.x; p < n; p += AR_BLOCK) {
+            const uint32_t t = a.t[base + p];
 #pragma unroll
-            for (int d = 0; d < MAXD; ++d)
-                if (d < a.d0) placed[d] += (uint32_t)__popcll(__ballot(st == (uint32_t)d));
+            for (int d = 0; d < AR_MAXD0; ++d) c[d] += t == (uint32_t)d ? 1u : 0u;
         }
-        if (lane_id() == 0) {
-            uint32_t alive = n;
 #pragma unroll
-            for (int d = 0; d < MAXD; ++d) {
-                if (d < a.d0) a.alive[(uint64_t)d * a.num_wc + w] = alive;
+        for (int d = 0; d < AR_MAXD0; ++d) {
+            if (d >= d0) break;
+            const uint32_t s = wave_sum(c[d]);
+            if (lane_id() == 0 && s) atomicAdd(&placed[d], s);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t alive = n;
+            for (int d = 0; d < d0; ++d) {
+                a.alive[(uint64_t)d * a.num_wc + w] = alive;
                 alive -= placed[d];
             }
         }
+        __syncthreads();   // placed is cleared for the next WC after every read
     }
 }
 
@@ -3084,6 +3135,8 @@ constexpr uint64_t PV_TILE = PV_BLOCK * PV_ITEMS;
 
 __global__ __launch_bounds__(PV_BLOCK) void k_preview_bits(PreviewArgs p, uint32_t *__restrict__ bits)
 {
+    if (p.zero && blockIdx.x == 0)
+        for (uint32_t i = threadIdx.x; i < p.zero_words; i += PV_BLOCK) p.zero[i] = 0u;
     const uint64_t words = (p.n + 31) / 32;
     const uint64_t base = (uint64_t)blockIdx.x * PV_TILE + (uint64_t)(threadIdx.x >> 6) * (64 * PV_ITEMS);
     for (int j = 0; j < PV_ITEMS; ++j) {
@@ -3165,6 +3218,33 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t words)
         p[i] = v;
 }
 
+struct FillSpecs {
+    FillSpec f[4];
+};
+__global__ void k_fill_many(FillSpecs s)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint32_t *p = s.f[k].p;
+        const uint32_t v = s.f[k].v;
+        const uint64_t words = p ? s.f[k].words : 0;
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = v;
+    }
+}
+
+void launch_fill_many(const FillSpec (&f)[4], hipStream_t st)
+{
+    FillSpecs s;
+    uint64_t most = 0;
+    for (int k = 0; k < 4; ++k) {
+        s.f[k] = f[k];
+        if (f[k].p && f[k].words > most) most = f[k].words;
+    }
+    if (most == 0) return;
+    hipLaunchKernelGGL(k_fill_many, dim3(grid_for(most, 256, 2048)), dim3(256), 0, st, s);
+}
+
 void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t words, hipStream_t st)
 {
     if (words == 0) return;
@@ -3231,19 +3311,19 @@ void launch_grid_export(const uint32_t *fine, int g, uint32_t *out, hipStream_t 
 }
 
 
-void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream_t st)
+void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream_t st, bool first_filled)
 {
     if (n == 0) return;
     for (int d = 0; d < a.d0; ++d) {
         const int csh = 3 * (KB - d - a.s);
-        launch_fill_u32(gtab, 0xffffffffu, 1ull << (3 * (d + a.s)), st);
+        if (d > 0 || !first_filled) launch_fill_u32(gtab, 0xffffffffu, 1ull << (3 * (d + a.s)), st);
         hipLaunchKernelGGL(k_gdepth_min, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, a.wc_code, a.wc_orig, a.t, n,
                            csh, gtab);
         hipLaunchKernelGGL(k_gdepth_mark, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, a.wc_code, a.wc_orig, a.t, n,
                            csh, gtab, d);
     }
     if (a.d0 > 0 && a.num_wc > 0)
-        hipLaunchKernelGGL(k_wc_alive_rows, dim3(grid_for(a.num_wc, 4, 4096)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_wc_alive_rows, dim3(a.num_wc < 8192 ? a.num_wc : 8192), dim3(AR_BLOCK), 0, st, a);
 }
 
 void launch_cut(const uint32_t *pyr, const CutArgs &chunks, const CutArgs &wcs, hipStream_t st)
