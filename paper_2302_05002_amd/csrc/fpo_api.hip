@@ -113,6 +113,7 @@ struct Ctrs {
     uint32_t np_lists[6];           // node_points: tile lists of four sizes, merge jobs, copies
     uint32_t np_general;            // work chunks with own nodes below their root
     uint32_t wc_over;               // a work chunk holds more than WC_CAP points (one finest cell)
+    uint32_t lists_pre[WC_CLASSES + 1];   // work chunks per subsample list (and the global-memory path)
 };
 static_assert(sizeof(Ctrs) <= 256, "the box follows the counters 256 bytes later");
 
@@ -798,7 +799,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     CutIndex wc_index{U64(P.w_start), U32(P.cut_idx[1]), 3 * (g - P.lt)};
     launch_wc_chunks(&ctrs->num_wc, P.maxW, U64(P.w_key), U8(P.w_level), g, pyr, chunk_index, U8(P.c_level),
                      &ctrs->num_chunks, P.maxC, U32(P.wc_chunk), U32(P.seg_b0), U32(P.seg_nb), U8(P.wc_nested),
-                     ctrs->wc_flags, st);
+                     ctrs->wc_flags, U32(P.w_count), p->leaf_capacity, s_, ctrs->lists_pre, st);
     t_cut.end(st);
     JCHK(hipMemcpyAsync(hctrs, ctrs, 256 + sizeof(DevBox), hipMemcpyDeviceToHost, st));   // counters and box
     JCHK(hipStreamSynchronize(st));
@@ -907,10 +908,13 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         launch_fill_many(f, st);
     }
     launch_global_depths(A, n, U32(P.gtab), st, true);
-    // the class above WC_CAP points and the global-memory list are launched
-    // only when the counters read back show they can hold work chunks
-    launch_subsample_small(A, hctrs->wc_over != 0, st);
-    if (hctrs->wc_over || hctrs->wc_flags[0] || !subsample_fast_only(A)) launch_subsample_big(A, st);
+    // only the lists the counters read back show non-empty are launched; a
+    // general-class work chunk whose table overflows LDS joins the
+    // global-memory list, so that list runs whenever a general class does
+    launch_subsample_small(A, hctrs->lists_pre, st);
+    bool big = hctrs->lists_pre[WC_CLASSES] != 0;
+    for (int k = WC_GENERAL; k < WC_CLASSES; ++k) big = big || hctrs->lists_pre[k] != 0;
+    if (big) launch_subsample_big(A, st);
     scan_exclusive(U32(P.alive), U32(P.alive_scan), (uint64_t)MAXD * num_wc, U32(P.alive_scan) + (uint64_t)MAXD * num_wc,
                    stemp, st);
     launch_decide(A, st);

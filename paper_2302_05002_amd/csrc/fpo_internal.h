@@ -250,10 +250,9 @@ struct WcArgs {
 // gtab: 4 * 8^(d0 - 1 + s) bytes.
 // first_filled: the table of depth 0 was cleared to all ones already.
 void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream_t st, bool first_filled = false);
-// Work chunks above WC_CAP points (class 5) exist only when any_over.
-void launch_subsample_small(const WcArgs &a, bool any_over, hipStream_t st);
-// Every work chunk takes a fast class (own root a leaf): no general subtree.
-inline bool subsample_fast_only(const WcArgs &a) { return a.L >= WC_CAP && a.s <= 7; }
+// lists[c] (host): number of work chunks in list c, 0 .. WC_CLASSES (the last:
+// the global-memory path), as counted by the cut; empty lists are skipped.
+void launch_subsample_small(const WcArgs &a, const uint32_t *lists, hipStream_t st);
 void launch_subsample_big(const WcArgs &a, hipStream_t st);
 void launch_decide(const WcArgs &a, hipStream_t st);
 void launch_node_counts(const WcArgs &a, uint32_t *owned, hipStream_t st);
@@ -305,7 +304,8 @@ uint64_t np_copy_entries(uint64_t n);
 void launch_wc_chunks(const uint32_t *num_wc_dev, uint64_t max_wc, const uint64_t *wc_key, const uint8_t *wc_level,
                       int g, const uint32_t *pyr, const CutIndex &chunks, const uint8_t *chunk_level,
                       const uint32_t *num_chunks_dev, uint64_t max_chunks, uint32_t *wc_chunk, uint32_t *seg_b0,
-                      uint32_t *seg_nb, uint8_t *wc_nested, uint32_t *flags, hipStream_t st);
+                      uint32_t *seg_nb, uint8_t *wc_nested, uint32_t *flags, const uint32_t *wc_count, uint32_t L,
+                      int s, uint32_t *class_counts, hipStream_t st);
 void launch_node_fill(const WcArgs &a, const uint32_t *node_base, uint8_t *depth, uint64_t *key,
                       uint8_t *mask, hipStream_t st);
 

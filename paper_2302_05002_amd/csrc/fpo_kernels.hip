@@ -2122,6 +2122,17 @@ void k_subsample_fast(WcArgs a, int cls)
 // One pass over the work chunks in blocks of 256: each wave counts its work
 // chunks per class with ballots into the block's LDS counters, one global
 // atomic per block and class reserves the block's run, then the waves write.
+// List of a work chunk of n points: a fast class (its own root a leaf), a
+// general class, or WC_CLASSES for the global-memory path (work chunks across
+// chunks, or too large for LDS).
+__device__ __forceinline__ uint32_t wc_list_class(uint32_t n, bool nested, uint32_t L, int s)
+{
+    uint32_t c = wc_size_class(n);
+    if (!nested) c = 0xffu;
+    else if (c != 0xffu && !(n <= L && s <= 7)) c = c < 5 ? c + WC_GENERAL : 0xffu;
+    return c == 0xffu ? (uint32_t)WC_CLASSES : c;
+}
+
 __global__ __launch_bounds__(256) void k_list_classes(WcArgs a)
 {
     constexpr uint32_t NC = WC_CLASSES + 1;   // the last one: the global-memory list
@@ -2131,14 +2142,8 @@ __global__ __launch_bounds__(256) void k_list_classes(WcArgs a)
         __syncthreads();
         const uint32_t w = b0 + threadIdx.x;
         const bool valid = w < a.num_wc;
-        uint32_t c = 0xfeu;
-        if (valid) {
-            const uint32_t n = a.wc_count[w];
-            c = wc_size_class(n);
-            if (!a.wc_nested[w]) c = 0xffu;
-            else if (c != 0xffu && !(n <= a.L && a.s <= 7)) c = c < 5 ? c + WC_GENERAL : 0xffu;
-        }
-        const uint32_t ci = c == 0xffu ? (uint32_t)WC_CLASSES : c;   // counter index (0xfe: none)
+        // counter index (0xfe: none)
+        const uint32_t ci = valid ? wc_list_class(a.wc_count[w], a.wc_nested[w] != 0, a.L, a.s) : 0xfeu;
         uint32_t rank = 0;
         for (uint32_t k = 0; k < NC; ++k) {
             const uint64_t m = __ballot(ci == k);
@@ -3023,22 +3028,33 @@ __global__ __launch_bounds__(NPM_BLOCK) void k_np_merge(const uint64_t *jobs, co
 // always lies inside a chunk).
 __global__ void k_wc_chunks(const uint32_t *num_wc_dev, uint32_t max_wc, const uint64_t *wc_key, const uint8_t *wc_level, int g,
                             const uint32_t *pyr, CutIndex chunks, const uint8_t *chunk_level,
-                            uint32_t *wc_chunk, uint8_t *wc_nested, uint32_t *flags)
+                            uint32_t *wc_chunk, uint8_t *wc_nested, uint32_t *flags, const uint32_t *wc_count,
+                            uint32_t L, int s, uint32_t *class_counts)
 {
     const uint32_t num_wc = min(*num_wc_dev, max_wc);
-    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < num_wc; w += gridDim.x * blockDim.x) {
-        uint64_t m = wc_key[w];
-        for (int l = wc_level[w]; l < g; ++l) {
-            const uint32_t *ch = pyr + pyr_off(l + 1) + (m << 3);
-            uint32_t o = 0;
-            while (o < 7 && ch[o] == 0) ++o;   // the work chunk holds a point, so some child does
-            m = (m << 3) | o;
+    for (uint32_t w0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); w0 < num_wc; w0 += gridDim.x * blockDim.x) {
+        // per-list counts of the work chunks, for the host to skip empty launches
+        const uint32_t w = w0 + lane_id();
+        uint32_t ci = 0xffffffffu;
+        if (w < num_wc) {
+            uint64_t m = wc_key[w];
+            for (int l = wc_level[w]; l < g; ++l) {
+                const uint32_t *ch = pyr + pyr_off(l + 1) + (m << 3);
+                uint32_t o = 0;
+                while (o < 7 && ch[o] == 0) ++o;   // the work chunk holds a point, so some child does
+                m = (m << 3) | o;
+            }
+            const uint32_t c = cut_find(chunks, m);
+            wc_chunk[w] = c;
+            const bool nested = chunk_level[c] <= wc_level[w];
+            wc_nested[w] = nested ? 1 : 0;
+            if (!nested) atomicOr(&flags[0], 1u);
+            ci = wc_list_class(wc_count[w], nested, L, s);
         }
-        const uint32_t c = cut_find(chunks, m);
-        wc_chunk[w] = c;
-        const bool nested = chunk_level[c] <= wc_level[w];
-        wc_nested[w] = nested ? 1 : 0;
-        if (!nested) atomicOr(&flags[0], 1u);
+        for (uint32_t k = 0; k <= (uint32_t)WC_CLASSES; ++k) {
+            const uint64_t b = __ballot(ci == k);
+            if (b && lane_id() == (uint32_t)(__ffsll((long long)b) - 1)) atomicAdd(&class_counts[k], (uint32_t)__popcll(b));
+        }
     }
 }
 
@@ -3350,35 +3366,39 @@ void launch_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_
     hipLaunchKernelGGL(k_u32_to_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, in, out, n);
 }
 
-void launch_subsample_small(const WcArgs &a, bool any_over, hipStream_t st)
+void launch_subsample_small(const WcArgs &a, const uint32_t *lists, hipStream_t st)
 {
     if (a.num_wc == 0) return;
     hipLaunchKernelGGL(k_list_classes, dim3(grid_for(a.num_wc, 256)), dim3(256), 0, st, a);
-    const uint32_t gs = a.num_wc < 8192 ? a.num_wc : 8192;
+    // lists[c]: work chunks of class c (counted before the read-back); an
+    // empty class is not launched, the others get at most one block per work
+    // chunk.
+    auto grid = [&](int c, uint32_t cap) { return lists[c] < cap ? lists[c] : cap; };
     // work chunks whose own root is a leaf: shared ancestors only
     // (few points per thread: a work chunk's depths run one after another, so
     // its latency bounds these kernels and the blocks resident per CU set
     // their speed.  Measured on the 20M-point planes: four points per thread
     // up to 1024 points, eight above)
-    hipLaunchKernelGGL((k_subsample_fast<64, 4, 10>), dim3(gs), dim3(64), 0, st, a, 0);
-    hipLaunchKernelGGL((k_subsample_fast<128, 4, 11>), dim3(gs), dim3(128), 0, st, a, 1);
-    hipLaunchKernelGGL((k_subsample_fast<256, 4, 12>), dim3(gs), dim3(256), 0, st, a, 2);
-    hipLaunchKernelGGL((k_subsample_fast<256, 8, 12>), dim3(gs), dim3(256), 0, st, a, 3);
-    hipLaunchKernelGGL((k_subsample_fast<512, 8, 13>), dim3(gs), dim3(512), 0, st, a, 4);
+    if (lists[0]) hipLaunchKernelGGL((k_subsample_fast<64, 4, 10>), dim3(grid(0, 8192)), dim3(64), 0, st, a, 0);
+    if (lists[1]) hipLaunchKernelGGL((k_subsample_fast<128, 4, 11>), dim3(grid(1, 8192)), dim3(128), 0, st, a, 1);
+    if (lists[2]) hipLaunchKernelGGL((k_subsample_fast<256, 4, 12>), dim3(grid(2, 8192)), dim3(256), 0, st, a, 2);
+    if (lists[3]) hipLaunchKernelGGL((k_subsample_fast<256, 8, 12>), dim3(grid(3, 8192)), dim3(256), 0, st, a, 3);
+    if (lists[4]) hipLaunchKernelGGL((k_subsample_fast<512, 8, 13>), dim3(grid(4, 8192)), dim3(512), 0, st, a, 4);
     // oversized work chunks at the deepest work-chunk level (dense clusters)
-    if (any_over)
-        hipLaunchKernelGGL((k_subsample_fast<1024, 8, 14>), dim3(gs < 2048 ? gs : 2048), dim3(1024), 0, st, a, 5);
+    if (lists[5]) hipLaunchKernelGGL((k_subsample_fast<1024, 8, 14>), dim3(grid(5, 2048)), dim3(1024), 0, st, a, 5);
     // the general subtree: single-wave blocks for the small classes, many per
     // CU.  Only work chunks with more than L points or subsample grids above
-    // 2^7 go there, so with L >= WC_CAP and s <= 7 these classes stay empty
-    if (subsample_fast_only(a)) return;
-    hipLaunchKernelGGL((k_subsample_lds<64, 4>), dim3(gs), dim3(64), 0, st, a, WC_GENERAL + 0);
-    hipLaunchKernelGGL((k_subsample_lds<64, 8>), dim3(gs), dim3(64), 0, st, a, WC_GENERAL + 1);
-    hipLaunchKernelGGL((k_subsample_lds<64, 16>), dim3(gs), dim3(64), 0, st, a, WC_GENERAL + 2);
-    const uint32_t g1 = a.num_wc < 2048 ? a.num_wc : 2048;
-    hipLaunchKernelGGL((k_subsample_lds<256, 8>), dim3(g1), dim3(256), 0, st, a, WC_GENERAL + 3);
-    const uint32_t g2 = a.num_wc < 1024 ? a.num_wc : 1024;
-    hipLaunchKernelGGL((k_subsample_lds<512, 8>), dim3(g2), dim3(512), 0, st, a, WC_GENERAL + 4);
+    // 2^7 go there
+    if (lists[WC_GENERAL + 0])
+        hipLaunchKernelGGL((k_subsample_lds<64, 4>), dim3(grid(WC_GENERAL + 0, 8192)), dim3(64), 0, st, a, WC_GENERAL + 0);
+    if (lists[WC_GENERAL + 1])
+        hipLaunchKernelGGL((k_subsample_lds<64, 8>), dim3(grid(WC_GENERAL + 1, 8192)), dim3(64), 0, st, a, WC_GENERAL + 1);
+    if (lists[WC_GENERAL + 2])
+        hipLaunchKernelGGL((k_subsample_lds<64, 16>), dim3(grid(WC_GENERAL + 2, 8192)), dim3(64), 0, st, a, WC_GENERAL + 2);
+    if (lists[WC_GENERAL + 3])
+        hipLaunchKernelGGL((k_subsample_lds<256, 8>), dim3(grid(WC_GENERAL + 3, 2048)), dim3(256), 0, st, a, WC_GENERAL + 3);
+    if (lists[WC_GENERAL + 4])
+        hipLaunchKernelGGL((k_subsample_lds<512, 8>), dim3(grid(WC_GENERAL + 4, 1024)), dim3(512), 0, st, a, WC_GENERAL + 4);
 }
 
 void launch_subsample_big(const WcArgs &a, hipStream_t st)
@@ -3401,11 +3421,12 @@ void launch_node_counts(const WcArgs &a, uint32_t *owned, hipStream_t st)
 void launch_wc_chunks(const uint32_t *num_wc_dev, uint64_t max_wc, const uint64_t *wc_key, const uint8_t *wc_level,
                       int g, const uint32_t *pyr, const CutIndex &chunks, const uint8_t *chunk_level,
                       const uint32_t *num_chunks_dev, uint64_t max_chunks, uint32_t *wc_chunk, uint32_t *seg_b0,
-                      uint32_t *seg_nb, uint8_t *wc_nested, uint32_t *flags, hipStream_t st)
+                      uint32_t *seg_nb, uint8_t *wc_nested, uint32_t *flags, const uint32_t *wc_count, uint32_t L,
+                      int s, uint32_t *class_counts, hipStream_t st)
 {
     hipLaunchKernelGGL(k_wc_chunks, dim3(grid_for(max_wc, 256)), dim3(256), 0, st, num_wc_dev, (uint32_t)max_wc, wc_key,
                        wc_level, g, pyr,
-                       chunks, chunk_level, wc_chunk, wc_nested, flags);
+                       chunks, chunk_level, wc_chunk, wc_nested, flags, wc_count, L, s, class_counts);
     hipLaunchKernelGGL(k_wc_segs, dim3(grid_for(max_wc, 256)), dim3(256), 0, st, num_wc_dev, (uint32_t)max_wc, wc_chunk,
                        seg_b0, seg_nb);
     hipLaunchKernelGGL(k_wc_chunks_nb, dim3(grid_for(max_chunks, 256)), dim3(256), 0, st, num_chunks_dev, seg_b0, seg_nb,
