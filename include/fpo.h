@@ -385,6 +385,19 @@ fpo_status fpo_autotune_batch(fpo_context *ctx, const fpo_cloud *clouds, const f
  * tuned choices again (for tests: every shape gives the same result). */
 fpo_status fpo_context_force_quantize_variant(fpo_context *ctx, int variant);
 
+/* ---- single-workgroup builds ------------------------------------------------
+ * A small cloud is built whole by one workgroup in one launch (box, quantise
+ * and count, chunk, preview and the tree level by level), instead of a few
+ * dozen launches and two host round trips.  A build takes this path when its
+ * cloud is in device memory, 1 <= n <= max_points (default 65536, at most
+ * 262143), n <= C (the root is the only chunk), G <= 64, S <= 32, the preview
+ * is the hash or stride one, and n / (L + 1) <= 64 (at most 64 nodes above L
+ * points per depth).  The results are those of the multi-kernel path, in the
+ * same workspace; fpo_build_batch puts up to 32 such clouds in one launch, one
+ * workgroup each (their jobs start with that launch and cannot be cancelled).
+ * max_points = 0 turns the path off for later builds of ctx. */
+fpo_status fpo_context_set_single_block_max(fpo_context *ctx, uint32_t max_points);
+
 /* ---- kernel timing (for benchmarks) ----------------------------------------
  * With timing enabled on a context, every later submit of it brackets each
  * region below with a pair of HIP events recorded on the build's stream (a
@@ -404,7 +417,9 @@ typedef enum {
     FPO_TIMER_PREVIEW = 6,       /* step 5: counters' fill and the preview kernels */
     FPO_TIMER_NODE_SORT = 7,     /* step 4: node ranges sorted by original index, merges, 64-bit begins */
     FPO_TIMER_CUT = 8,           /* step 2: pyramid, count-grid export, chunk and work-chunk cuts */
-    FPO_TIMER_COUNT = 9
+    FPO_TIMER_FUSED = 9,         /* steps 1-5 of a single-workgroup build (fpo_context_set_single_block_max):
+                                    the one launch; such a build has no other region */
+    FPO_TIMER_COUNT = 10
 } fpo_timer;
 
 /* enable: 1 to time later submits of ctx (every timer), 0 to stop. */

@@ -36,14 +36,16 @@ EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_w
            "fpo_preview_modulus", "fpo_las_parse_header", "fpo_las_header_box", "fpo_las_decode",
            "fpo_select_workspace_size", "fpo_select_nodes", "fpo_select_nodes_static",
            "fpo_job_get_stats", "fpo_context_set_batch_workers", "fpo_autotune", "fpo_autotune_batch",
-           "fpo_context_force_quantize_variant")
+           "fpo_context_force_quantize_variant", "fpo_context_set_single_block_max")
 #: fpo_select_nodes_static's limits (include/fpo.h)
 SELECT_STATIC_MAX_NODES = 4194304
 SELECT_STATIC_BYTES = 655360
 
 # fpo_timer values (include/fpo.h)
 TIMERS = {"bbox": 0, "quantize": 1, "chunk_split": 2, "subsample": 3, "node_counts": 4, "node_place": 5,
-          "preview": 6, "node_sort": 7, "cut": 8}
+          "preview": 6, "node_sort": 7, "cut": 8, "fused": 9}
+#: largest n fpo_context_set_single_block_max accepts (include/fpo.h)
+SINGLE_BLOCK_MAX_POINTS = 262143
 
 
 class FpoError(RuntimeError):
@@ -206,6 +208,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_job_get_stats.restype = ctypes.c_int
     lib.fpo_context_set_batch_workers.argtypes = [vp, ctypes.c_uint32]
     lib.fpo_context_set_batch_workers.restype = ctypes.c_int
+    lib.fpo_context_set_single_block_max.argtypes = [vp, ctypes.c_uint32]
+    lib.fpo_context_set_single_block_max.restype = ctypes.c_int
     lib.fpo_autotune.argtypes = [vp, P(_Cloud), P(_Params), vp, u64, ctypes.c_uint32, P(_Tuning)]
     lib.fpo_autotune.restype = ctypes.c_int
     lib.fpo_autotune_batch.argtypes = [vp, P(_Cloud), P(_Params), ctypes.c_uint32, vp, u64, ctypes.c_uint32,
@@ -493,6 +497,11 @@ class Context:
     def set_batch_workers(self, workers: int):
         """Worker streams of later build_batch calls (1..16, default 4)."""
         _check(_lib.fpo_context_set_batch_workers(self._h, int(workers)))
+
+    def set_single_block_max(self, max_points: int):
+        """Clouds up to max_points points (and within the path's other limits)
+        are built by one workgroup in one launch; 0 turns that off."""
+        _check(_lib.fpo_context_set_single_block_max(self._h, int(max_points)))
 
     def build_batch(self, clouds, params, workspace=None, stream=None) -> list:
         """Enqueue one build per (x, y, z) device-tensor triple in `clouds`,

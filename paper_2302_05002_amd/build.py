@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["fpo_kernels.hip", "fpo_api.hip", "fpo_exec.hip", "fpo_tune.hip", "fpo_las.hip", "fpo_view.hip"]
+SOURCES = ["fpo_kernels.hip", "fpo_api.hip", "fpo_exec.hip", "fpo_tune.hip", "fpo_las.hip", "fpo_view.hip", "fpo_small.hip"]
 LIB = os.path.join(HERE, "libfpo.so")
 ARCH = os.environ.get("FPO_OFFLOAD_ARCH", "gfx950")
 

@@ -97,26 +97,6 @@ size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 // Smallest host-to-device batch of pinned inputs (keeps the partial count bounded).
 constexpr uint64_t MIN_STREAM_BATCH = 1u << 20;
 
-// Small device counters read back by the host.
-struct Ctrs {
-    uint32_t num_chunks;
-    uint32_t num_wc;
-    uint32_t num_big;
-    uint32_t max_big;
-    uint32_t num_nodes;
-    uint32_t preview_count;
-    uint32_t oversized;
-    uint32_t internal_error;
-    uint32_t wc_flags[2];      // [0] a work chunk spans several chunks, [1] a chunk holds too many
-    uint32_t cls_cnt[WC_CLASSES];   // work chunks per LDS size class
-    uint32_t np_max;                // points of the largest node
-    uint32_t np_lists[6];           // node_points: tile lists of four sizes, merge jobs, copies
-    uint32_t np_general;            // work chunks with own nodes below their root
-    uint32_t wc_over;               // a work chunk holds more than WC_CAP points (one finest cell)
-    uint32_t lists_pre[WC_CLASSES + 1];   // work chunks per subsample list (and the global-memory path)
-};
-static_assert(sizeof(Ctrs) <= 256, "the box follows the counters 256 bytes later");
-
 // Capacities of one cut's lists (CutArgs) for n points: heavy nodes of a
 // level number at most min(8^l, n) above lmin and min(8^l, n / (thresh + 1))
 // from lmin on (disjoint nodes holding more than thresh points), and never
@@ -496,6 +476,142 @@ static fpo_status check_build(fpo_context *ctx, const fpo_cloud *cloud, const fp
     return FPO_OK;
 }
 
+// A job for a build on st (its events and pinned staging).
+static fpo_status new_job(fpo_context *ctx, hipStream_t st, const fpo_params *p, uint64_t grid_cells,
+                          uint64_t plan_bytes, fpo_job **out)
+{
+    fpo_job *job = new fpo_job();
+    job->ctx = ctx;
+    job->stream = st;
+    job->status = FPO_OK;
+    job->waited = false;
+    job->timed = ctx->timing;
+    job->timer_mask = ctx->timer_mask;
+    job->t_submit = now_ns();
+    job->t_done = 0;
+    job->grid_cells = grid_cells;
+    job->plan_bytes = plan_bytes;
+    job->params = *p;
+    job->ev_preview = job->ev_done = nullptr;
+    job->pinned = get_pinned(ctx);
+    if (!job->pinned) {
+        delete job;
+        return fail(FPO_ERR_OUT_OF_MEMORY, "pinned host staging allocation failed");
+    }
+    if (alloc_fault(ctx) || hipEventCreateWithFlags(&job->ev_preview, hipEventDisableTiming) != hipSuccess ||
+        alloc_fault(ctx) || hipEventCreateWithFlags(&job->ev_done, hipEventDisableTiming) != hipSuccess) {
+        if (job->ev_preview) (void)hipEventDestroy(job->ev_preview);
+        put_pinned(ctx, job->pinned);
+        delete job;
+        return fail(FPO_ERR_OUT_OF_MEMORY, "could not create the job's events");
+    }
+    *out = job;
+    return FPO_OK;
+}
+
+bool small_eligible(const fpo_context *ctx, uint64_t n, const fpo_params &p, bool host_in)
+{
+    return !host_in && n >= 1 && n <= ctx->small_max.load() && n <= SB_MAX_N && n <= p.max_points_per_chunk &&
+           p.count_grid <= SB_MAX_G && p.subsample_grid <= SB_MAX_S && !(p.flags & FPO_PREVIEW_GRID) &&
+           n / ((uint64_t)p.leaf_capacity + 1) <= SB_MAX_INNER;
+}
+
+fpo_status issue_small_group(fpo_context *ctx, uint32_t count, const fpo_cloud *const *clouds,
+                             const fpo_params *const *params, void *const *workspaces, hipStream_t st,
+                             fpo_job **jobs_out)
+{
+    if (count == 0 || count > SB_GROUP) return fail(FPO_ERR_INVALID_ARG, "internal: %u clouds in one group", count);
+    HIPCHK(hipSetDevice(ctx->device));
+    SmallGroup grp{};
+    std::vector<fpo_job *> jobs(count, nullptr);
+    std::vector<SmallLayout> lay(count);
+    auto drop = [&]() {   // nothing was enqueued: the jobs were never handed out
+        for (fpo_job *j : jobs)
+            if (j) fpo_job_release(j);
+    };
+    for (uint32_t i = 0; i < count; ++i) {
+        const fpo_cloud &c = *clouds[i];
+        const fpo_params &p = *params[i];
+        const uint64_t n = c.n;
+        const int g = (int)ilog2(p.count_grid);
+        const Plan P = make_plan(n, p);
+        lay[i] = small_layout(n, g);
+        if (!small_eligible(ctx, n, p, c.location == FPO_HOST_PINNED) || lay[i].total > P.total) {
+            drop();
+            return fail(FPO_ERR_INVALID_ARG, "internal: cloud %u does not take the single-workgroup path", i);
+        }
+        const fpo_status js = new_job(ctx, st, &p, P.G3, P.total, &jobs[i]);
+        if (js != FPO_OK) {
+            drop();
+            return js;
+        }
+        fpo_job *job = jobs[i];
+        job->small = true;
+        char *ws = static_cast<char *>(workspaces[i]);
+        const SmallLayout &Lo = lay[i];
+        fpo_result &R = job->res;
+        memset(&R, 0, sizeof(R));
+        R.n = n;
+        R.count_grid = reinterpret_cast<const uint32_t *>(ws + Lo.grid);
+        R.chunk_level = reinterpret_cast<const uint8_t *>(ws + Lo.c_level);
+        R.chunk_key = reinterpret_cast<const uint64_t *>(ws + Lo.c_key);
+        R.chunk_count = reinterpret_cast<const uint32_t *>(ws + Lo.c_count);
+        R.chunk_begin = reinterpret_cast<const uint64_t *>(ws + Lo.c_begin);
+        R.perm = reinterpret_cast<const uint32_t *>(ws + Lo.perm);
+        R.node_depth = reinterpret_cast<const uint8_t *>(ws + Lo.n_depth);
+        R.node_key = reinterpret_cast<const uint64_t *>(ws + Lo.n_key);
+        R.node_child_mask = reinterpret_cast<const uint8_t *>(ws + Lo.n_mask);
+        R.node_begin = reinterpret_cast<const uint64_t *>(ws + Lo.n_begin);
+        R.node_count = reinterpret_cast<const uint32_t *>(ws + Lo.n_count);
+        R.node_points = reinterpret_cast<const uint32_t *>(ws + Lo.n_points);
+        R.preview_index = reinterpret_cast<const uint32_t *>(ws + Lo.pv_index);
+        SmallDesc &d = grp.d[i];
+        d.x = c.x;
+        d.y = c.y;
+        d.z = c.z;
+        d.ws = ws;
+        d.n = (uint32_t)n;
+        d.g = (uint32_t)g;
+        d.s = ilog2(p.subsample_grid);
+        d.L = p.leaf_capacity;
+        d.M = p.preview_modulus;
+        d.given = (p.flags & FPO_BBOX_GIVEN) ? 1u : 0u;
+        d.stride = (p.flags & FPO_PREVIEW_STRIDE) ? 1u : 0u;
+        for (int a = 0; a < 3; ++a) {
+            d.glo[a] = p.bbox_min[a];
+            d.ghi[a] = p.bbox_max[a];
+        }
+    }
+    std::vector<JobTimer> tmr;
+    tmr.reserve(count);
+    for (uint32_t i = 0; i < count; ++i) {
+        tmr.emplace_back(jobs[i], FPO_TIMER_FUSED);
+        tmr[i].begin(st);
+    }
+    launch_small_build(grp, count, st);
+    for (uint32_t i = 0; i < count; ++i) tmr[i].end(st);
+    hipError_t e = hipGetLastError();
+    for (uint32_t i = 0; i < count && e == hipSuccess; ++i) e = hipEventRecord(jobs[i]->ev_preview, st);
+    // counters and box of every build (the counts of chunks and nodes come
+    // with them)
+    for (uint32_t i = 0; i < count && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(jobs[i]->pinned, static_cast<char *>(workspaces[i]) + lay[i].ctrs, 256 + sizeof(DevBox),
+                           hipMemcpyDeviceToHost, st);
+    for (uint32_t i = 0; i < count && e == hipSuccess; ++i) e = hipEventRecord(jobs[i]->ev_done, st);
+    if (e != hipSuccess) {
+        // the launch may be in flight: the jobs end with the error, their
+        // done events recorded where possible
+        for (fpo_job *j : jobs) {
+            j->status = FPO_ERR_DEVICE;
+            (void)hipEventRecord(j->ev_done, st);
+        }
+        for (uint32_t i = 0; i < count; ++i) jobs_out[i] = jobs[i];
+        return FPO_OK;
+    }
+    for (uint32_t i = 0; i < count; ++i) jobs_out[i] = jobs[i];
+    return FPO_OK;
+}
+
 // Enqueues one whole build on st, with the host round trips it needs (the
 // counts of chunks, work chunks and nodes size later launches).  on_preview,
 // if given, receives the job as soon as the preview kernels are enqueued;
@@ -534,30 +650,20 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
                     (unsigned long long)workspace_bytes, (unsigned long long)P.total);
     HIPCHK(hipSetDevice(ctx->device));
 
-    fpo_job *job = new fpo_job();
-    job->ctx = ctx;
-    job->stream = st;
-    job->status = FPO_OK;
-    job->waited = false;
-    job->timed = ctx->timing;
-    job->timer_mask = ctx->timer_mask;
-    job->t_submit = now_ns();
-    job->t_done = 0;
-    job->grid_cells = P.G3;
-    job->plan_bytes = P.total;
-    job->params = *p;
-    job->ev_preview = job->ev_done = nullptr;
-    job->pinned = get_pinned(ctx);
-    if (!job->pinned) {
-        delete job;
-        return fail(FPO_ERR_OUT_OF_MEMORY, "pinned host staging allocation failed");
+    if (small_eligible(ctx, n, *p, host_in)) {
+        // the whole build in one workgroup
+        void *w = workspace;
+        fpo_job *job = nullptr;
+        const fpo_status ss = issue_small_group(ctx, 1, &cloud, &p, &w, st, &job);
+        if (ss != FPO_OK) return ss;
+        if (on_preview) on_preview(job);
+        *out = job;
+        return FPO_OK;
     }
-    if (alloc_fault(ctx) || hipEventCreateWithFlags(&job->ev_preview, hipEventDisableTiming) != hipSuccess ||
-        alloc_fault(ctx) || hipEventCreateWithFlags(&job->ev_done, hipEventDisableTiming) != hipSuccess) {
-        if (job->ev_preview) (void)hipEventDestroy(job->ev_preview);
-        put_pinned(ctx, job->pinned);
-        delete job;
-        return fail(FPO_ERR_OUT_OF_MEMORY, "could not create the job's events");
+    fpo_job *job = nullptr;
+    {
+        const fpo_status js = new_job(ctx, st, p, P.G3, P.total, &job);
+        if (js != FPO_OK) return js;
     }
 
     char *ws = static_cast<char *>(workspace);
@@ -1027,11 +1133,18 @@ static fpo_status finish(fpo_job *job)
                 R.n_outside = hb->n_outside;
                 R.preview_count = hc->preview_count;
                 R.chunk_oversized_any = hc->oversized ? 1 : 0;
-                if (hc->internal_error) job->status = FPO_ERR_DEVICE;
+                if (job->small) {
+                    // counted by the device: the host never saw them mid-build
+                    R.num_chunks = hc->num_chunks;
+                    R.num_nodes = hc->num_nodes;
+                    if (hb->nonfinite) job->status = FPO_ERR_NONFINITE;
+                }
+                if (hc->internal_error && job->status == FPO_OK) job->status = FPO_ERR_DEVICE;
             }
         }
     }
     if (job->status == FPO_ERR_DEVICE) return fail(FPO_ERR_DEVICE, "internal error: a point was left without a node");
+    if (job->status == FPO_ERR_NONFINITE) return fail(FPO_ERR_NONFINITE, "a coordinate is NaN or infinite");
     return job->status == FPO_OK ? FPO_OK : fail(job->status, "build failed (status %d)", (int)job->status);
 }
 
@@ -1323,6 +1436,15 @@ void fpo_job_release(fpo_job *job)
             }
     }
     delete job;
+}
+
+fpo_status fpo_context_set_single_block_max(fpo_context *ctx, uint32_t max_points)
+{
+    if (!ctx) return fail(FPO_ERR_INVALID_ARG, "context is NULL");
+    if (max_points > SB_MAX_N)
+        return fail(FPO_ERR_INVALID_ARG, "max_points must be at most %u (got %u)", SB_MAX_N, max_points);
+    ctx->small_max.store(max_points);
+    return FPO_OK;
 }
 
 fpo_status fpo_context_set_timing(fpo_context *ctx, int enable)

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "fpo_host.h"
+#include "fpo_internal.h"
 #include "fpo_sched.h"
 
 namespace fpo {
@@ -53,6 +54,10 @@ struct Deferred {
     bool has_memory = false;
     uint64_t t_start = 0;
     uint64_t t_end = 0;           // server jobs: when the slot saw the build end
+    // a queue entry for single-workgroup builds launched together: the jobs
+    // of those clouds (not queued themselves); the entry is internal and
+    // deleted once it ran
+    std::vector<fpo_job *> group;
 };
 
 struct Pool {
@@ -92,9 +97,53 @@ inline uint64_t a256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
 
 void server_finished(Server *S);
 
+// Runs a group entry: every member's build in one launch.  A member is
+// never queued itself, so it cannot be cancelled, and its release waits
+// until this has set its final state.
+void run_group(Pool *P, fpo_job *entry, hipStream_t st)
+{
+    std::vector<fpo_job *> mem;
+    mem.swap(entry->def->group);
+    delete entry->def;
+    delete entry;
+    const uint64_t t0 = now_ns();
+    std::vector<const fpo_cloud *> clouds;
+    std::vector<const fpo_params *> params;
+    std::vector<void *> ws;
+    for (fpo_job *j : mem) {
+        Deferred *d = j->def;
+        {
+            std::lock_guard<std::mutex> g(d->m);
+            d->state = Deferred::RUNNING;
+            d->t_start = t0;
+        }
+        if (d->after) (void)hipStreamWaitEvent(st, d->after, 0);
+        clouds.push_back(&d->cloud);
+        params.push_back(&d->params);
+        ws.push_back(d->ws);
+    }
+    std::vector<fpo_job *> inner(mem.size(), nullptr);
+    const fpo_status s = issue_small_group(P->ctx, (uint32_t)mem.size(), clouds.data(), params.data(), ws.data(), st,
+                                           inner.data());
+    const std::string err = s == FPO_OK ? std::string() : error_text();
+    for (size_t k = 0; k < mem.size(); ++k) {
+        Deferred *d = mem[k]->def;
+        std::lock_guard<std::mutex> g(d->m);
+        d->inner = inner[k];
+        d->status = s;
+        d->err = err;
+        d->state = s == FPO_OK ? Deferred::SUBMITTED : Deferred::FAILED;
+        d->cv.notify_all();
+    }
+}
+
 void run_job(Pool *P, fpo_job *job, hipStream_t st)
 {
     Deferred *d = job->def;
+    if (!d->group.empty()) {
+        run_group(P, job, st);
+        return;
+    }
     {
         std::lock_guard<std::mutex> g(d->m);
         if (d->state == Deferred::CANCELLED) return;
@@ -505,12 +554,28 @@ fpo_status fpo_build_batch(fpo_context *ctx, const fpo_cloud *clouds, const fpo_
             return fail(FPO_ERR_OUT_OF_MEMORY, "could not record an event on the caller's stream");
         }
     }
-    // largest first: the small builds fill in behind the long ones
+    // largest first: the small builds fill in behind the long ones.  Clouds
+    // of the single-workgroup path go in groups of up to SB_GROUP per
+    // launch, queued first so that their workgroups share the device with
+    // the long builds
     std::vector<uint32_t> order(count);
     std::iota(order.begin(), order.end(), 0u);
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return clouds[a].n > clouds[b].n; });
+    std::vector<uint32_t> small, rest;
+    for (uint32_t i : order)
+        (small_eligible(ctx, clouds[i].n, params[i], clouds[i].location == FPO_HOST_PINNED) ? small : rest).push_back(i);
+    std::vector<fpo_job *> entries;
+    for (size_t k = 0; k < small.size(); k += SB_GROUP) {
+        fpo_job *e = new fpo_job();
+        e->ctx = ctx;
+        e->def = new Deferred();
+        e->def->pool = P;
+        for (size_t m = k; m < small.size() && m < k + SB_GROUP; ++m) e->def->group.push_back(jobs[small[m]]);
+        entries.push_back(e);
+    }
     for (uint32_t i = 0; i < count; ++i) jobs_out[i] = jobs[i];
-    for (uint32_t i : order) pool_push(P, jobs[i]);
+    for (fpo_job *e : entries) pool_push(P, e);
+    for (uint32_t i : rest) pool_push(P, jobs[i]);
     return FPO_OK;
 }
 

@@ -57,6 +57,7 @@ struct fpo_context {
     int qz_force = -1;                 // fpo_context_force_quantize_variant, else -1
     fpo::Pool *issue_pool = nullptr;   // issues plain builds in submission order (created by the first)
     hipStream_t copy_stream = nullptr; // host-to-device batches of pinned inputs (created on first use)
+    std::atomic<uint32_t> small_max{65536};   // single-workgroup builds up to this many points (0: off)
 };
 
 struct fpo_job {
@@ -76,6 +77,7 @@ struct fpo_job {
     fpo_params params;            // of the build
     std::vector<hipEvent_t> stream_events;   // one per host-to-device batch
     fpo::Deferred *def = nullptr; // set for batch and server jobs (the build runs later)
+    bool small = false;           // a single-workgroup build (counts come with the final read-back)
 };
 
 namespace fpo {
@@ -105,6 +107,14 @@ fpo_status deferred_resolve(fpo_job *job, bool block, bool preview, fpo_job **in
 void deferred_release(fpo_job *job);
 void destroy_batch_pool(fpo_context *ctx);
 
+// True when a build of n points with p runs as one workgroup.
+bool small_eligible(const fpo_context *ctx, uint64_t n, const fpo_params &p, bool host_in);
+// Enqueues count single-workgroup builds (each small_eligible) as one launch
+// on st; jobs_out[i] receives the job of clouds[i].  On an error no job is
+// left.
+fpo_status issue_small_group(fpo_context *ctx, uint32_t count, const fpo_cloud *const *clouds,
+                             const fpo_params *const *params, void *const *workspaces, hipStream_t st,
+                             fpo_job **jobs_out);
 // Enqueues a whole build on st from the calling thread (see fpo_api.hip).
 fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
                        uint64_t workspace_bytes, hipStream_t st, fpo_job **out,

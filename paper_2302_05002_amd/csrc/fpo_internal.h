@@ -50,6 +50,27 @@ struct DevBox {
     unsigned long long n_outside;
 };
 
+// Device counters of a build, read back by the host (with the box 256 bytes
+// after them).
+struct Ctrs {
+    uint32_t num_chunks;
+    uint32_t num_wc;
+    uint32_t num_big;
+    uint32_t max_big;
+    uint32_t num_nodes;
+    uint32_t preview_count;
+    uint32_t oversized;
+    uint32_t internal_error;
+    uint32_t wc_flags[2];      // [0] a work chunk spans several chunks, [1] a chunk holds too many
+    uint32_t cls_cnt[WC_CLASSES];   // work chunks per LDS size class
+    uint32_t np_max;                // points of the largest node
+    uint32_t np_lists[6];           // node_points: tile lists of four sizes, merge jobs, copies
+    uint32_t np_general;            // work chunks with own nodes below their root
+    uint32_t wc_over;               // a work chunk holds more than WC_CAP points (one finest cell)
+    uint32_t lists_pre[WC_CLASSES + 1];   // work chunks per subsample list (and the global-memory path)
+};
+static_assert(sizeof(Ctrs) <= 256, "the box follows the counters 256 bytes later");
+
 // Offsets of level l in a pyramid array holding levels 0..g back to back.
 __host__ __device__ inline uint64_t pyr_off(int l) { return ((1ull << (3 * l)) - 1ull) / 7ull; }
 
@@ -340,5 +361,72 @@ uint64_t bits_tiles(uint64_t n);
 void launch_bits_count(const uint32_t *bits, uint64_t n, uint32_t *tile_counts, hipStream_t st);
 void launch_bits_write(const uint32_t *bits, uint64_t n, const uint32_t *tile_offsets, uint32_t *out,
                        hipStream_t st);
+
+// ---- single-workgroup builds of small clouds ----
+// A cloud whose root is its only chunk (n <= C), with at most SB_MAX_N
+// points, S <= SB_MAX_S, G <= SB_MAX_G and at most SB_MAX_INNER nodes above L
+// points per level (there are at most n / (L + 1) of them), is built whole by
+// one workgroup: box, quantise and count, the chunk, the preview, and the tree
+// level by level with a node's subsample grid as a table in LDS.  Up to
+// SB_GROUP clouds go in one launch, one workgroup each.
+constexpr uint32_t SB_MAX_N = (1u << 18) - 1;   // a position inside a node fits 18 bits
+constexpr uint32_t SB_MAX_S = 32;               // the S^3 table: 128 KB of LDS
+constexpr uint32_t SB_MAX_G = 64;               // the count grid: at most 1 MB to clear
+constexpr uint32_t SB_MAX_INNER = 64;
+constexpr uint32_t SB_GROUP = 32;
+
+struct SmallDesc {
+    const float *x, *y, *z;
+    char *ws;                  // the cloud's workspace, laid out by small_layout
+    uint32_t n, g, s, L, M;    // points, log2 G, log2 S, leaf capacity, preview modulus
+    uint32_t given, stride;    // box given; stride preview (else the hash preview)
+    float glo[3], ghi[3];      // the given box
+};
+struct SmallGroup {
+    SmallDesc d[SB_GROUP];
+};
+
+// Byte offsets of a single-workgroup build's arrays in its workspace (the
+// counters first, the box 256 bytes after them).
+struct SmallLayout {
+    uint64_t ctrs, box, grid, c_level, c_key, c_count, c_begin, perm;
+    uint64_t n_depth, n_key, n_mask, n_begin, n_count, n_points, pv_index;
+    uint64_t code, ia, ib, ca, cb, total;
+};
+__host__ __device__ inline uint64_t sb_take(uint64_t &at, uint64_t bytes)
+{
+    const uint64_t r = at;
+    at += bytes ? (bytes + 255) & ~(uint64_t)255 : 256;
+    return r;
+}
+__host__ __device__ inline SmallLayout small_layout(uint64_t n, int g)
+{
+    SmallLayout o{};
+    uint64_t at = 0;
+    o.ctrs = sb_take(at, 256);
+    o.box = sb_take(at, sizeof(DevBox));
+    o.grid = sb_take(at, 4ull << (3 * g));
+    o.c_level = sb_take(at, 1);
+    o.c_key = sb_take(at, 8);
+    o.c_count = sb_take(at, 4);
+    o.c_begin = sb_take(at, 8);
+    o.perm = sb_take(at, 4 * n);
+    o.n_depth = sb_take(at, n);
+    o.n_key = sb_take(at, 8 * n);
+    o.n_mask = sb_take(at, n);
+    o.n_begin = sb_take(at, 8 * n);
+    o.n_count = sb_take(at, 4 * n);
+    o.n_points = sb_take(at, 4 * n);
+    o.pv_index = sb_take(at, 4 * n);
+    o.code = sb_take(at, 8 * n);
+    o.ia = sb_take(at, 4 * n);
+    o.ib = sb_take(at, 4 * n);
+    o.ca = sb_take(at, 8 * n);
+    o.cb = sb_take(at, 8 * n);
+    o.total = at;
+    return o;
+}
+// One workgroup per cloud: g.d[0 .. count).
+void launch_small_build(const SmallGroup &g, uint32_t count, hipStream_t st);
 
 }  // namespace fpo

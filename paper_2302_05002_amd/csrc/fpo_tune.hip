@@ -74,11 +74,13 @@ struct TimingGuard {   // the context's own timing settings, restored on exit
     fpo_context *c;
     bool timing;
     uint32_t mask;
+    uint32_t small_max;
     explicit TimingGuard(fpo_context *ctx) : c(ctx)
     {
         std::lock_guard<std::mutex> g(c->mu);
         timing = c->timing;
         mask = c->timer_mask;
+        small_max = c->small_max.load();
     }
     ~TimingGuard()
     {
@@ -86,6 +88,7 @@ struct TimingGuard {   // the context's own timing settings, restored on exit
         c->timing = timing;
         c->timer_mask = mask;
         c->qz_force = -1;
+        c->small_max.store(small_max);
     }
 };
 
@@ -143,6 +146,9 @@ fpo_status fpo_autotune(fpo_context *ctx, const fpo_cloud *cloud, const fpo_para
     if (chk != FPO_OK) return chk;
     if (cloud->n == 0) return fail(FPO_ERR_INVALID_ARG, "nothing to tune on an empty cloud");
     TimingGuard guard(ctx);
+    // the shapes are those of the multi-kernel path, also for a cloud that
+    // would take the single-workgroup one
+    ctx->small_max.store(0);
     memset(out, 0, sizeof(*out));
     uint64_t ref = 0;
     for (int v = 0; v < QZ_VARIANTS; ++v) {
