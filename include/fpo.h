@@ -389,14 +389,17 @@ fpo_status fpo_context_force_quantize_variant(fpo_context *ctx, int variant);
  * A small cloud is built whole by one workgroup in one launch (box, quantise
  * and count, chunk, preview and the tree level by level), instead of a few
  * dozen launches and two host round trips.  A build takes this path when its
- * cloud is in device memory, 1 <= n <= max_points (default 65536, at most
- * 262143), n <= C (the root is the only chunk), G <= 64, S <= 32, the preview
- * is the hash or stride one, and n / (L + 1) <= 64 (at most 64 nodes above L
- * points per depth).  The results are those of the multi-kernel path, in the
- * same workspace; fpo_build_batch puts up to 32 such clouds in one launch, one
- * workgroup each (their jobs start with that launch and cannot be cancelled).
- * max_points = 0 turns the path off for later builds of ctx. */
-fpo_status fpo_context_set_single_block_max(fpo_context *ctx, uint32_t max_points);
+ * cloud is in device memory, n >= 1, n <= C (the root is the only chunk),
+ * G <= 64, S <= 32, the preview is the hash or stride one, n / (L + 1) <= 64
+ * (at most 64 nodes above L points per depth), and n is at most the
+ * context's limit: plain_max for plain and served builds (default 65536,
+ * where one workgroup stops being faster than the whole device), batch_max in
+ * fpo_build_batch (default 262143), which puts up to 32 such clouds in one
+ * launch, one workgroup each, beside the other builds (those jobs start with
+ * their launch and cannot be cancelled).  Both limits are at most 262143; 0
+ * turns the path off.  The results are those of the multi-kernel path, in
+ * the same workspace. */
+fpo_status fpo_context_set_single_block_max(fpo_context *ctx, uint32_t plain_max, uint32_t batch_max);
 
 /* ---- kernel timing (for benchmarks) ----------------------------------------
  * With timing enabled on a context, every later submit of it brackets each

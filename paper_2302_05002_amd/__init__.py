@@ -208,7 +208,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_job_get_stats.restype = ctypes.c_int
     lib.fpo_context_set_batch_workers.argtypes = [vp, ctypes.c_uint32]
     lib.fpo_context_set_batch_workers.restype = ctypes.c_int
-    lib.fpo_context_set_single_block_max.argtypes = [vp, ctypes.c_uint32]
+    lib.fpo_context_set_single_block_max.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32]
     lib.fpo_context_set_single_block_max.restype = ctypes.c_int
     lib.fpo_autotune.argtypes = [vp, P(_Cloud), P(_Params), vp, u64, ctypes.c_uint32, P(_Tuning)]
     lib.fpo_autotune.restype = ctypes.c_int
@@ -498,10 +498,12 @@ class Context:
         """Worker streams of later build_batch calls (1..16, default 4)."""
         _check(_lib.fpo_context_set_batch_workers(self._h, int(workers)))
 
-    def set_single_block_max(self, max_points: int):
-        """Clouds up to max_points points (and within the path's other limits)
-        are built by one workgroup in one launch; 0 turns that off."""
-        _check(_lib.fpo_context_set_single_block_max(self._h, int(max_points)))
+    def set_single_block_max(self, plain_max: int, batch_max: int | None = None):
+        """Clouds up to plain_max points (plain and served builds) or batch_max
+        points (build_batch; default: plain_max), within the path's other
+        limits, are built by one workgroup in one launch; 0 turns that off."""
+        bm = plain_max if batch_max is None else batch_max
+        _check(_lib.fpo_context_set_single_block_max(self._h, int(plain_max), int(bm)))
 
     def build_batch(self, clouds, params, workspace=None, stream=None) -> list:
         """Enqueue one build per (x, y, z) device-tensor triple in `clouds`,

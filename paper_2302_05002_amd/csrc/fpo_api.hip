@@ -509,9 +509,9 @@ static fpo_status new_job(fpo_context *ctx, hipStream_t st, const fpo_params *p,
     return FPO_OK;
 }
 
-bool small_eligible(const fpo_context *ctx, uint64_t n, const fpo_params &p, bool host_in)
+bool small_eligible(uint64_t limit, uint64_t n, const fpo_params &p, bool host_in)
 {
-    return !host_in && n >= 1 && n <= ctx->small_max.load() && n <= SB_MAX_N && n <= p.max_points_per_chunk &&
+    return !host_in && n >= 1 && n <= limit && n <= SB_MAX_N && n <= p.max_points_per_chunk &&
            p.count_grid <= SB_MAX_G && p.subsample_grid <= SB_MAX_S && !(p.flags & FPO_PREVIEW_GRID) &&
            n / ((uint64_t)p.leaf_capacity + 1) <= SB_MAX_INNER;
 }
@@ -536,7 +536,7 @@ fpo_status issue_small_group(fpo_context *ctx, uint32_t count, const fpo_cloud *
         const int g = (int)ilog2(p.count_grid);
         const Plan P = make_plan(n, p);
         lay[i] = small_layout(n, g);
-        if (!small_eligible(ctx, n, p, c.location == FPO_HOST_PINNED) || lay[i].total > P.total) {
+        if (!small_eligible(SB_MAX_N, n, p, c.location == FPO_HOST_PINNED) || lay[i].total > P.total) {
             drop();
             return fail(FPO_ERR_INVALID_ARG, "internal: cloud %u does not take the single-workgroup path", i);
         }
@@ -650,7 +650,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
                     (unsigned long long)workspace_bytes, (unsigned long long)P.total);
     HIPCHK(hipSetDevice(ctx->device));
 
-    if (small_eligible(ctx, n, *p, host_in)) {
+    if (small_eligible(ctx->small_max.load(), n, *p, host_in)) {
         // the whole build in one workgroup
         void *w = workspace;
         fpo_job *job = nullptr;
@@ -1438,12 +1438,13 @@ void fpo_job_release(fpo_job *job)
     delete job;
 }
 
-fpo_status fpo_context_set_single_block_max(fpo_context *ctx, uint32_t max_points)
+fpo_status fpo_context_set_single_block_max(fpo_context *ctx, uint32_t plain_max, uint32_t batch_max)
 {
     if (!ctx) return fail(FPO_ERR_INVALID_ARG, "context is NULL");
-    if (max_points > SB_MAX_N)
-        return fail(FPO_ERR_INVALID_ARG, "max_points must be at most %u (got %u)", SB_MAX_N, max_points);
-    ctx->small_max.store(max_points);
+    if (plain_max > SB_MAX_N || batch_max > SB_MAX_N)
+        return fail(FPO_ERR_INVALID_ARG, "limits must be at most %u (got %u, %u)", SB_MAX_N, plain_max, batch_max);
+    ctx->small_max.store(plain_max);
+    ctx->small_max_batch.store(batch_max);
     return FPO_OK;
 }
 

@@ -563,7 +563,10 @@ fpo_status fpo_build_batch(fpo_context *ctx, const fpo_cloud *clouds, const fpo_
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return clouds[a].n > clouds[b].n; });
     std::vector<uint32_t> small, rest;
     for (uint32_t i : order)
-        (small_eligible(ctx, clouds[i].n, params[i], clouds[i].location == FPO_HOST_PINNED) ? small : rest).push_back(i);
+        (small_eligible(ctx->small_max_batch.load(), clouds[i].n, params[i], clouds[i].location == FPO_HOST_PINNED)
+             ? small
+             : rest)
+            .push_back(i);
     std::vector<fpo_job *> entries;
     for (size_t k = 0; k < small.size(); k += SB_GROUP) {
         fpo_job *e = new fpo_job();

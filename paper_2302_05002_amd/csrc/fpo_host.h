@@ -57,7 +57,10 @@ struct fpo_context {
     int qz_force = -1;                 // fpo_context_force_quantize_variant, else -1
     fpo::Pool *issue_pool = nullptr;   // issues plain builds in submission order (created by the first)
     hipStream_t copy_stream = nullptr; // host-to-device batches of pinned inputs (created on first use)
-    std::atomic<uint32_t> small_max{65536};   // single-workgroup builds up to this many points (0: off)
+    // single-workgroup builds up to this many points (0: off): plain and
+    // served builds, batches
+    std::atomic<uint32_t> small_max{65536};
+    std::atomic<uint32_t> small_max_batch{262143};
 };
 
 struct fpo_job {
@@ -107,8 +110,9 @@ fpo_status deferred_resolve(fpo_job *job, bool block, bool preview, fpo_job **in
 void deferred_release(fpo_job *job);
 void destroy_batch_pool(fpo_context *ctx);
 
-// True when a build of n points with p runs as one workgroup.
-bool small_eligible(const fpo_context *ctx, uint64_t n, const fpo_params &p, bool host_in);
+// True when a build of n points with p runs as one workgroup (limit: the
+// context's size limit for the kind of build).
+bool small_eligible(uint64_t limit, uint64_t n, const fpo_params &p, bool host_in);
 // Enqueues count single-workgroup builds (each small_eligible) as one launch
 // on st; jobs_out[i] receives the job of clouds[i].  On an error no job is
 // left.

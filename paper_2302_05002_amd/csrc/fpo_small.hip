@@ -34,6 +34,7 @@ constexpr uint32_t SB_TAB = SB_MAX_S * SB_MAX_S * SB_MAX_S;
 constexpr uint32_t SB_NODES = 8 * SB_MAX_INNER;       // nodes of one depth
 constexpr uint32_t SB_POS_BITS = 18;
 constexpr uint32_t SB_TAG_MAX = (1u << (32 - SB_POS_BITS)) - 1u;
+constexpr int SB_U = 4;   // loads in flight per thread in the passes over points
 static_assert(SB_MAX_N < (1u << SB_POS_BITS), "positions fit their field");
 
 __device__ __forceinline__ bool sb_keep(uint32_t i, uint32_t m, bool stride)
@@ -80,10 +81,22 @@ __global__ __launch_bounds__(SB_BLOCK) void k_small_build(SmallGroup grp)
     // ---- 1. box ----
     if (!given) {
         uint32_t mn[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[3] = {0u, 0u, 0u}, bad = 0;
-        for (uint32_t i = tid; i < n; i += SB_BLOCK) {
-            bbox_acc(mn[0], mx[0], bad, X[i]);
-            bbox_acc(mn[1], mx[1], bad, Y[i]);
-            bbox_acc(mn[2], mx[2], bad, Z[i]);
+        // SB_U points per thread and round, every load issued first
+        for (uint32_t i0 = tid; i0 < n; i0 += SB_U * SB_BLOCK) {
+            float px[SB_U], py[SB_U], pz[SB_U];
+#pragma unroll
+            for (int u = 0; u < SB_U; ++u) {
+                const uint32_t i = min(i0 + u * SB_BLOCK, n - 1u);   // a repeat of the last point changes no extreme
+                px[u] = X[i];
+                py[u] = Y[i];
+                pz[u] = Z[i];
+            }
+#pragma unroll
+            for (int u = 0; u < SB_U; ++u) {
+                bbox_acc(mn[0], mx[0], bad, px[u]);
+                bbox_acc(mn[1], mx[1], bad, py[u]);
+                bbox_acc(mn[2], mx[2], bad, pz[u]);
+            }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -130,25 +143,48 @@ __global__ __launch_bounds__(SB_BLOCK) void k_small_build(SmallGroup grp)
     if (s_u[0]) return;   // a non-finite coordinate: the host reports it
 
     // ---- 1. quantise + count ----
+    // The count grid is either cleared and counted with global atomics (few
+    // points per cell), or, from n >= G^3 / 16 on, counted in LDS one range
+    // of SB_TAB cells at a time from each point's cell id (kept in the ia
+    // array until the tree needs it) and written once: a single workgroup
+    // issues global atomics far more slowly than LDS ones.
     uint32_t *grid = reinterpret_cast<uint32_t *>(ws + Lo.grid);
     const uint32_t G = 1u << D.g, G3 = 1u << (3 * D.g);
-    for (uint32_t c = tid; c < G3; c += SB_BLOCK) grid[c] = 0u;
-    __syncthreads();
+    const bool lds_count = n >= (G3 >> 4);
+    uint32_t *cell_id = reinterpret_cast<uint32_t *>(ws + Lo.ia);
+    if (!lds_count) {
+        for (uint32_t c = tid; c < G3; c += SB_BLOCK) grid[c] = 0u;
+        __syncthreads();
+    }
     uint64_t *code = reinterpret_cast<uint64_t *>(ws + Lo.code);
     {
         const float lx = s_box[0], ly = s_box[1], lz = s_box[2], hx = s_box[3], hy = s_box[4], hz = s_box[5];
         const float sc = s_box[6];
         const int gsh = KB - (int)D.g;
         uint32_t outside = 0, bad = 0;
-        for (uint32_t i = tid; i < n; i += SB_BLOCK) {
-            const float px = X[i], py = Y[i], pz = Z[i];
-            const uint32_t ux = quantize1(px, lx, sc), uy = quantize1(py, ly, sc), uz = quantize1(pz, lz, sc);
-            code[i] = (split3(ux) << 2) | (split3(uy) << 1) | split3(uz);
-            atomicAdd(&grid[((ux >> gsh) * G + (uy >> gsh)) * G + (uz >> gsh)], 1u);
-            if (given) {
-                outside += (px < lx || px > hx || py < ly || py > hy || pz < lz || pz > hz) ? 1u : 0u;
-                // NaN fails every comparison, an infinity exceeds the largest float
-                bad |= !(fabsf(px) <= FLT_MAX && fabsf(py) <= FLT_MAX && fabsf(pz) <= FLT_MAX) ? 1u : 0u;
+        for (uint32_t i0 = tid; i0 < n; i0 += SB_U * SB_BLOCK) {
+            float px[SB_U], py[SB_U], pz[SB_U];
+#pragma unroll
+            for (int u = 0; u < SB_U; ++u) {
+                const uint32_t i = min(i0 + u * SB_BLOCK, n - 1u);
+                px[u] = X[i];
+                py[u] = Y[i];
+                pz[u] = Z[i];
+            }
+#pragma unroll
+            for (int u = 0; u < SB_U; ++u) {
+                const uint32_t i = i0 + u * SB_BLOCK;
+                if (i >= n) break;
+                const uint32_t ux = quantize1(px[u], lx, sc), uy = quantize1(py[u], ly, sc), uz = quantize1(pz[u], lz, sc);
+                code[i] = (split3(ux) << 2) | (split3(uy) << 1) | split3(uz);
+                const uint32_t cell = ((ux >> gsh) * G + (uy >> gsh)) * G + (uz >> gsh);
+                if (lds_count) cell_id[i] = cell;
+                else atomicAdd(&grid[cell], 1u);
+                if (given) {
+                    outside += (px[u] < lx || px[u] > hx || py[u] < ly || py[u] > hy || pz[u] < lz || pz[u] > hz) ? 1u : 0u;
+                    // NaN fails every comparison, an infinity exceeds the largest float
+                    bad |= !(fabsf(px[u]) <= FLT_MAX && fabsf(py[u]) <= FLT_MAX && fabsf(pz[u]) <= FLT_MAX) ? 1u : 0u;
+                }
             }
         }
         if (given) {
@@ -173,6 +209,24 @@ __global__ __launch_bounds__(SB_BLOCK) void k_small_build(SmallGroup grp)
     }
     __syncthreads();
     if (s_u[0]) return;
+    if (lds_count) {
+        for (uint32_t r0 = 0; r0 < G3; r0 += SB_TAB) {
+            const uint32_t span = min(SB_TAB, G3 - r0);
+            for (uint32_t c = tid; c < span; c += SB_BLOCK) tab[c] = 0u;
+            __syncthreads();
+            for (uint32_t i0 = tid; i0 < n; i0 += SB_U * SB_BLOCK) {
+                uint32_t cl[SB_U];
+#pragma unroll
+                for (int u = 0; u < SB_U; ++u) cl[u] = cell_id[min(i0 + u * SB_BLOCK, n - 1u)];
+#pragma unroll
+                for (int u = 0; u < SB_U; ++u)
+                    if (i0 + u * SB_BLOCK < n && cl[u] - r0 < span) atomicAdd(&tab[cl[u] - r0], 1u);
+            }
+            __syncthreads();
+            for (uint32_t c = tid; c < span; c += SB_BLOCK) grid[r0 + c] = tab[c];
+            __syncthreads();
+        }
+    }
 
     // ---- 2. the one chunk ----
     if (tid == 0) {
@@ -276,18 +330,32 @@ __global__ __launch_bounds__(SB_BLOCK) void k_small_build(SmallGroup grp)
             // an inner node: cells of level d + s, children at level d + 1
             const int csh = 3 * (KB - d - (int)D.s), osh = 3 * (KB - d - 1);
             const uint32_t tg = tag << SB_POS_BITS;
-            for (uint32_t j = b + tid; j < b + c; j += SB_BLOCK)
-                atomicMin(&tab[(uint32_t)(ccode[j] >> csh) & cmask], tg | (j - b));
+            for (uint32_t j0 = b + tid; j0 < b + c; j0 += SB_U * SB_BLOCK) {
+                uint64_t cc[SB_U];
+#pragma unroll
+                for (int u = 0; u < SB_U; ++u) cc[u] = ccode[min(j0 + u * SB_BLOCK, b + c - 1u)];
+#pragma unroll
+                for (int u = 0; u < SB_U; ++u) {
+                    const uint32_t j = j0 + u * SB_BLOCK;
+                    if (j < b + c) atomicMin(&tab[(uint32_t)(cc[u] >> csh) & cmask], tg | (j - b));
+                }
+            }
             __syncthreads();
             // each wave classifies a contiguous run of the node's points
             const uint32_t seg = (c + SB_BLOCK - 1) / SB_BLOCK * 64;
             const uint32_t lo = b + min(c, w * seg), hi = b + min(c, w * seg + seg);
             uint32_t cnt[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            for (uint32_t j0 = lo; j0 < hi; j0 += 64) {
-                const uint32_t j = j0 + lane;
-                const uint32_t cat = j < hi ? sb_category(tab, ccode[j], tg | (j - b), csh, cmask, osh) : 9u;
+            for (uint32_t j0 = lo; j0 < hi; j0 += 64 * SB_U) {
+                uint64_t cc[SB_U];
 #pragma unroll
-                for (int q = 0; q < 9; ++q) cnt[q] += (uint32_t)__popcll(__ballot(cat == (uint32_t)q));
+                for (int u = 0; u < SB_U; ++u) cc[u] = ccode[min(j0 + u * 64 + lane, hi - 1u)];
+#pragma unroll
+                for (int u = 0; u < SB_U; ++u) {
+                    const uint32_t j = j0 + u * 64 + lane;
+                    const uint32_t cat = j < hi ? sb_category(tab, cc[u], tg | (j - b), csh, cmask, osh) : 9u;
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) cnt[q] += (uint32_t)__popcll(__ballot(cat == (uint32_t)q));
+                }
             }
 #pragma unroll
             for (int q = 0; q < 9; ++q)
@@ -341,30 +409,35 @@ __global__ __launch_bounds__(SB_BLOCK) void k_small_build(SmallGroup grp)
             uint32_t off[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) off[q] = cat_base[q] + wcat[w][q];
-            for (uint32_t j0 = lo; j0 < hi; j0 += 64) {
-                const uint32_t j = j0 + lane;
-                uint64_t cc = 0;
-                uint32_t cat = 9u;
-                if (j < hi) {
-                    cc = ccode[j];
-                    cat = sb_category(tab, cc, tg | (j - b), csh, cmask, osh);
-                }
-                uint32_t pos = 0;
+            for (uint32_t j0 = lo; j0 < hi; j0 += 64 * SB_U) {
+                uint64_t cc[SB_U];
+                uint32_t ix[SB_U];
 #pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    const uint64_t bq = __ballot(cat == (uint32_t)q);
-                    if (cat == (uint32_t)q) pos = off[q] + (uint32_t)__popcll(bq & lanes_below());
-                    off[q] += (uint32_t)__popcll(bq);
+                for (int u = 0; u < SB_U; ++u) {
+                    const uint32_t j = min(j0 + u * 64 + lane, hi - 1u);
+                    cc[u] = ccode[j];
+                    ix[u] = cidx ? cidx[j] : j;
                 }
-                // (every position is below n by construction; the bound keeps a
-                // broken count from writing past the arrays)
-                if (cat < 9u && pos < n) {
-                    const uint32_t idx = cidx ? cidx[j] : j;
-                    if (cat == 8u) {
-                        n_points[pos] = idx;
-                    } else {
-                        nidx[pos] = idx;
-                        ncode[pos] = cc;
+#pragma unroll
+                for (int u = 0; u < SB_U; ++u) {
+                    const uint32_t j = j0 + u * 64 + lane;
+                    const uint32_t cat = j < hi ? sb_category(tab, cc[u], tg | (j - b), csh, cmask, osh) : 9u;
+                    uint32_t pos = 0;
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) {
+                        const uint64_t bq = __ballot(cat == (uint32_t)q);
+                        if (cat == (uint32_t)q) pos = off[q] + (uint32_t)__popcll(bq & lanes_below());
+                        off[q] += (uint32_t)__popcll(bq);
+                    }
+                    // (every position is below n by construction; the bound
+                    // keeps a broken count from writing past the arrays)
+                    if (cat < 9u && pos < n) {
+                        if (cat == 8u) {
+                            n_points[pos] = ix[u];
+                        } else {
+                            nidx[pos] = ix[u];
+                            ncode[pos] = cc[u];
+                        }
                     }
                 }
             }

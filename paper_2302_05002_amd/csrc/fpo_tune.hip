@@ -74,13 +74,14 @@ struct TimingGuard {   // the context's own timing settings, restored on exit
     fpo_context *c;
     bool timing;
     uint32_t mask;
-    uint32_t small_max;
+    uint32_t small_max, small_max_batch;
     explicit TimingGuard(fpo_context *ctx) : c(ctx)
     {
         std::lock_guard<std::mutex> g(c->mu);
         timing = c->timing;
         mask = c->timer_mask;
         small_max = c->small_max.load();
+        small_max_batch = c->small_max_batch.load();
     }
     ~TimingGuard()
     {
@@ -89,6 +90,7 @@ struct TimingGuard {   // the context's own timing settings, restored on exit
         c->timer_mask = mask;
         c->qz_force = -1;
         c->small_max.store(small_max);
+        c->small_max_batch.store(small_max_batch);
     }
 };
 

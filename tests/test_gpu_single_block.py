@@ -213,3 +213,30 @@ def test_batch_groups_many_small_clouds(ctxs):
                                                                p.subsample_grid, p.leaf_capacity, p.preview_modulus))
         compare(j.result().to_numpy(), exp, label=f"cloud {i} (n={c.n}): ")
         j.release()
+
+
+def test_plain_and_batch_limits_are_separate():
+    """With the plain limit at 0 and the batch limit at its maximum, a plain
+    build takes the multi-kernel path and the same clouds in a batch take the
+    single-workgroup one (one launch, a fused timer bracket per job)."""
+    import paper_2302_05002_amd as fpo
+    ctx = fpo.Context(0)
+    try:
+        ctx.set_single_block_max(0, fpo.SINGLE_BLOCK_MAX_POINTS)
+        ctx.set_timing(True, only=["fused"])
+        clouds = [_cloud(k, n, seed=n) for k, n in (("uniform", 9_000), ("planes", 150_000), ("few", 3))]
+        p = fpo.Params(64, 200_000, 32, 10_000, 16)
+        dev = [_dev(c) for c in clouds]
+        job = ctx.submit(*dev[0], p)
+        job.wait()
+        assert job.timer("fused")[1] == 0
+        job.release()
+        jobs = ctx.build_batch(dev, p)
+        for c, j in zip(clouds, jobs):
+            j.wait()
+            assert j.timer("fused")[1] == 1
+            exp = oracle.build_octree(c.x, c.y, c.z, oracle.Params(64, 200_000, 32, 10_000, 16))
+            compare(j.result().to_numpy(), exp, label=f"batch n={c.n}: ")
+            j.release()
+    finally:
+        ctx.close()
