@@ -934,6 +934,8 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         in.cut = chunk_index;
         in.code_shift = 3 * (KB - g);
         in.pay = U64(P.code);
+        in.bucket_begin = U64(P.c_begin);   // the chunk begins: one pass, no counting pass
+        in.err = &ctrs->internal_error;
         MsOutput o;
         o.vals = U32(P.perm);
         o.pay = U64(P.code_perm);

@@ -184,6 +184,13 @@ struct MsInput {
     int code_shift = 0;
     const uint32_t *vals = nullptr;    // values (null: the input position)
     const uint64_t *pay = nullptr;     // optional payload carried along
+    // Known start of every bucket in the output (the exclusive scan of the
+    // bucket sizes): a split of few tiles then runs in one pass, each tile
+    // finding its offsets by a look-back over its predecessors' per-bucket
+    // counts instead of a counting pass and a scan.  err receives 1 if a
+    // look-back ever gives up waiting (never expected).
+    const uint64_t *bucket_begin = nullptr;
+    uint32_t *err = nullptr;
 };
 struct MsOutput {
     uint32_t *vals = nullptr;          // values in sorted order (optional)
@@ -212,6 +219,11 @@ struct MsArgs {
     uint64_t *pay_out;
     uint32_t nseg;
     const uint32_t *seg_begin, *seg_len, *seg_b0, *seg_nb, *seg_mat, *seg_tile_first, *seg_total_tiles;
+    // one-pass split: bucket starts, per-(tile, bucket) status words, the
+    // tile ticket counter, the error flag
+    const uint64_t *bucket_begin;
+    unsigned long long *status;
+    uint32_t *tile_ctr, *err;
 };
 size_t multisplit_temp_bytes(uint64_t n, uint32_t nbins);
 size_t multisplit_temp_bound(uint64_t n, uint64_t max_bins);   // for any nbins <= max_bins

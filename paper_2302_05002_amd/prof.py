@@ -8,6 +8,11 @@
     python3 -m paper_2302_05002_amd.prof traffic <fetch.csv> <write.csv> <workload> <out.json> [chunk_passes]
         FETCH_SIZE and WRITE_SIZE per build of every region, with the digest of
         the HIP sources they were taken on, merged into out.json
+    python3 -m paper_2302_05002_amd.prof calibrate
+        three plain device copies of 256 MiB, to be run under rocprofv3 --pmc
+        (the counters' calibration: bytes moved per FETCH_SIZE / WRITE_SIZE unit)
+    python3 -m paper_2302_05002_amd.prof calibration <fetch.csv> <write.csv>
+        the factors from such a run
 
 Every dispatch of a build is attributed to the region the library's timers
 bracket (include/fpo.h, fpo_timer): preview, bbox, quantize, cut,
@@ -167,7 +172,39 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, out_json: str, chunk_
     return data
 
 
+def calibrate():
+    """Three device-to-device copies of 256 MiB (the copy kernel of the HIP runtime)."""
+    import torch
+    src = torch.empty(1 << 26, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print("copied 3 x 256 MiB", flush=True)
+
+
+def calibration(fetch_csv: str, write_csv: str):
+    """(read factor, write factor): bytes a 256 MiB copy moves each way per counter unit (KiB)."""
+    out = []
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        vals = [v for k, v in _dispatches(path, counter) if "copyBuffer" in k]
+        if not vals:
+            raise SystemExit(f"no copy kernel in {path}")
+        per = sorted(vals)[len(vals) // 2]   # median copy, KiB
+        out.append(256 * 1024 / per)
+    return tuple(out)
+
+
 def main(argv):
+    if not argv:
+        raise SystemExit(__doc__)
+    if argv[0] == "calibrate":
+        calibrate()
+        return
+    if argv[0] == "calibration":
+        r, w = calibration(argv[1], argv[2])
+        print(f"read factor {r:.3f}, write factor {w:.3f} (bytes = FETCH_SIZE KiB x {r:.3f} + WRITE_SIZE KiB x {w:.3f}, in KiB)")
+        return
     if argv[0] == "stats":
         print(stats(argv[1], int(argv[2])))
     elif argv[0] == "groups":
