@@ -758,10 +758,10 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
             // fewer cells than 2n: a pass over the cell minima
             launch_fill_u32(bits, 0u, (n + 31) / 32, st);
             launch_grid_picks(pa.cellmin, P.G3, n, bits, st);
+            launch_bits_count(bits, n, U32(P.pv_tiles), st);
         } else {
-            launch_preview_bits(pa, bits, st);
+            launch_preview_bits(pa, bits, U32(P.pv_tiles), st);   // the predicate and the tile counts
         }
-        launch_bits_count(bits, n, U32(P.pv_tiles), st);
         scan_exclusive(U32(P.pv_tiles), U32(P.pv_offs), bits_tiles(n), &ctrs->preview_count, stemp, st);
         launch_bits_write(bits, n, U32(P.pv_offs), U32(P.pv_index), st);
         t_prev.end(st);
@@ -822,8 +822,11 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     uint32_t *pyr = U32(P.pyr);
     uint32_t *fine = pyr + pyr_off(g);
     const bool box_region = !given;   // a given box has no bounding-box pass: its fills go with quantise
+    // the count grid is cleared by the bounding-box pass of a one-batch build
+    // (device input), else here
+    const bool zero_in_bbox = !given && !host_in;
     (box_region ? t_bbox : t_quant).begin(st);
-    launch_fill_u32(fine, 0u, P.G3, st);
+    if (!zero_in_bbox) launch_fill_u32(fine, 0u, P.G3, st);
     uint64_t *cellmin = pa.mode == PV_GRID ? U64(P.cellmin) : nullptr;
     if (cellmin) launch_fill_u32(U32(P.cellmin), 0xffffffffu, 2 * P.G3, st);
     (box_region ? t_bbox : t_quant).end(st);
@@ -851,7 +854,8 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
             const uint64_t c = n - o < sbatch ? n - o : sbatch;
             if (host_in) JCHK(hipStreamWaitEvent(st, job->stream_events[bi++], 0));
             t_bbox.begin(st);
-            launch_bbox(X + o, Y + o, Z + o, c, U32(P.bbox_part) + 8ull * nparts, st);
+            launch_bbox(X + o, Y + o, Z + o, c, U32(P.bbox_part) + 8ull * nparts, st, zero_in_bbox ? fine : nullptr,
+                        zero_in_bbox ? P.G3 : 0);
             t_bbox.end(st);
             nparts += bbox_blocks(c);
         }
@@ -868,8 +872,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
 
     // ---- step 2: pyramid, chunk cut, work-chunk cut ----
     t_cut.begin(st);
-    launch_pyramid(pyr, g, st);
-    launch_grid_export(fine, g, U32(P.grid), st);
+    launch_pyramid(pyr, g, U32(P.grid), st);   // with the row-major count grid
     CutArgs cut[2];
     for (int k = 0; k < 2; ++k) {
         CutArgs &c = cut[k];

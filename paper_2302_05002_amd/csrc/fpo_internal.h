@@ -96,7 +96,9 @@ void launch_fill_many(const FillSpec (&f)[4], hipStream_t st);
 // order-preserving integer encoding, a non-finite flag), reduced by k_setup.
 constexpr uint32_t BBOX_MAX_BLOCKS = 2048;
 uint32_t bbox_blocks(uint64_t n);
-void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, uint32_t *part, hipStream_t st);
+// zero (or null): zero_words words cleared by the same launch.
+void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, uint32_t *part, hipStream_t st,
+                 uint32_t *zero = nullptr, uint64_t zero_words = 0);
 // flag_only: only the non-finite flag is reduced (the box was set before).
 void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given, const float *lo, const float *hi,
                   int flag_only, hipStream_t st);
@@ -108,7 +110,9 @@ constexpr int QZ_VARIANTS = 3;
 void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box,
                      int g, int given, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw,
                      uint64_t base, uint64_t *cellmin, hipStream_t st, int variant);
-void launch_pyramid(uint32_t *pyr, int g, hipStream_t st);
+// exp_out (or null): the finest level's row-major export, written by the
+// launch that reads it.
+void launch_pyramid(uint32_t *pyr, int g, uint32_t *exp_out, hipStream_t st);
 void launch_grid_export(const uint32_t *fine_morton, int g, uint32_t *rowmajor, hipStream_t st);
 constexpr int FR_BLOCK = 256;   // parents per tile of a frontier launch
 
@@ -363,7 +367,9 @@ struct PreviewArgs {
     uint32_t zero_words = 0;
 };
 // bits (ceil(n / 32) words) = the predicate of every index
-void launch_preview_bits(const PreviewArgs &p, uint32_t *bits, hipStream_t st);
+// tile_counts (or null): the kept indices of every compaction tile (what
+// launch_bits_count gives), counted by the same launch.
+void launch_preview_bits(const PreviewArgs &p, uint32_t *bits, uint32_t *tile_counts, hipStream_t st);
 // Grid preview: the quantise pass leaves the least H64 of every count-grid
 // cell in cellmin (G^3 entries, all ones where empty); the picks follow either
 // from the inverse hash (into bits, zeroed before) or from the predicate

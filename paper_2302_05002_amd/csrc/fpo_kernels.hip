@@ -57,9 +57,15 @@ static inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b
 // ---- step 1a: bounding box ------------------------------------------------------
 
 
+// zero (or null): zero_words words cleared on the way (the count grid).
 __global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ x, const float *__restrict__ y,
-                                              const float *__restrict__ z, uint64_t n, int vec4, uint32_t *part)
+                                              const float *__restrict__ z, uint64_t n, int vec4, uint32_t *part,
+                                              uint32_t *zero, uint64_t zero_words)
 {
+    if (zero)   // (a pyramid level: 4-byte aligned only)
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < zero_words;
+             i += (uint64_t)gridDim.x * blockDim.x)
+            zero[i] = 0u;
     uint32_t mn[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[3] = {0u, 0u, 0u};
     uint32_t bad = 0;
     const uint64_t n4 = vec4 ? n / 4 : 0;   // float4 loads only on 16-byte aligned inputs
@@ -367,7 +373,22 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
 // Level l-1 cell k = sum of level-l cells 8k..8k+7 (Morton order).
 // The top levels (at most 4096 cells at level `top`) in one block: one launch
 // instead of one per level.
-__global__ __launch_bounds__(1024) void k_pyr_top(uint32_t *pyr, int top)
+// The eight level-l cells 8k..8k+7 (Morton order) into the row-major export
+// of the finest level (l = g).
+__device__ __forceinline__ void pyr_export(const uint32_t *c, uint64_t k, int l, uint32_t *out)
+{
+    const uint64_t G = 1ull << l;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        const uint64_t m = 8 * k + (uint64_t)o;
+        const uint32_t cx = compact3(m >> 2), cy = compact3(m >> 1), cz = compact3(m);
+        out[((uint64_t)cx * G + cy) * G + cz] = c[o];
+    }
+}
+
+// exp_out (or null): the finest level is level `top`, exported row-major on
+// the way.
+__global__ __launch_bounds__(1024) void k_pyr_top(uint32_t *pyr, int top, uint32_t *exp_out)
 {
     for (int l = top; l >= 1; --l) {
         const uint32_t ncell = 1u << (3 * (l - 1));
@@ -376,12 +397,14 @@ __global__ __launch_bounds__(1024) void k_pyr_top(uint32_t *pyr, int top)
         for (uint32_t k = threadIdx.x; k < ncell; k += blockDim.x) {
             const uint32_t *c = src + 8 * k;
             dst[k] = c[0] + c[1] + c[2] + c[3] + c[4] + c[5] + c[6] + c[7];
+            if (exp_out && l == top) pyr_export(c, k, l, exp_out);
         }
         __syncthreads();
     }
 }
 
-__global__ void k_pyr_level(uint32_t *pyr, int l)
+// exp_out (or null): level l is the finest, exported row-major on the way.
+__global__ void k_pyr_level(uint32_t *pyr, int l, uint32_t *exp_out)
 {
     const uint64_t ncell = 1ull << (3 * (l - 1));
     const uint32_t *src = pyr + pyr_off(l);
@@ -390,6 +413,7 @@ __global__ void k_pyr_level(uint32_t *pyr, int l)
          k += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t *c = src + 8 * k;
         dst[k] = c[0] + c[1] + c[2] + c[3] + c[4] + c[5] + c[6] + c[7];
+        if (exp_out) pyr_export(c, k, l, exp_out);
     }
 }
 
@@ -3063,22 +3087,37 @@ __device__ __forceinline__ bool keep(const PreviewArgs &p, uint64_t i)
 
 // The predicate of every index into an n-bit map: a wave covers 64
 // consecutive indices per step, and its ballot is two words of the map.
+// A block covers one tile of the compaction (4096 indices, 128 words) and
+// also writes the tile's count.
 constexpr int PV_BLOCK = 256, PV_ITEMS = 16;
 constexpr uint64_t PV_TILE = PV_BLOCK * PV_ITEMS;
 
-__global__ __launch_bounds__(PV_BLOCK) void k_preview_bits(PreviewArgs p, uint32_t *__restrict__ bits)
+__global__ __launch_bounds__(PV_BLOCK) void k_preview_bits(PreviewArgs p, uint32_t *__restrict__ bits,
+                                                           uint32_t *__restrict__ tile_counts)
 {
+    __shared__ uint32_t wsum[PV_BLOCK / 64];
     if (p.zero && blockIdx.x == 0)
         for (uint32_t i = threadIdx.x; i < p.zero_words; i += PV_BLOCK) p.zero[i] = 0u;
     const uint64_t words = (p.n + 31) / 32;
     const uint64_t base = (uint64_t)blockIdx.x * PV_TILE + (uint64_t)(threadIdx.x >> 6) * (64 * PV_ITEMS);
+    uint32_t cnt = 0;
     for (int j = 0; j < PV_ITEMS; ++j) {
         const uint64_t i0 = base + (uint64_t)j * 64;
         const uint64_t i = i0 + lane_id();
         const uint64_t m = __ballot(i < p.n && keep(p, i));
+        cnt += (uint32_t)__popcll(m);
         const uint64_t w = i0 / 32;
         if (lane_id() == 0 && w < words) bits[w] = (uint32_t)m;
         if (lane_id() == 1 && w + 1 < words) bits[w + 1] = (uint32_t)(m >> 32);
+    }
+    if (tile_counts) {
+        if (lane_id() == 0) wsum[threadIdx.x >> 6] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int k = 0; k < PV_BLOCK / 64; ++k) t += wsum[k];
+            tile_counts[blockIdx.x] = t;
+        }
     }
 }
 
@@ -3097,8 +3136,8 @@ __global__ void k_grid_picks(const unsigned long long *__restrict__ cellmin, uin
     }
 }
 
-// Ordered compaction of a bit map, a word per thread and round.
-constexpr int BW_BLOCK = 256, BW_ITEMS = 2;
+// Ordered compaction of a bit map, a word per thread.
+constexpr int BW_BLOCK = 128, BW_ITEMS = 1;
 constexpr uint64_t BW_TILE = (uint64_t)BW_BLOCK * BW_ITEMS;   // words per tile
 
 __global__ __launch_bounds__(BW_BLOCK) void k_bits_count(const uint32_t *__restrict__ bits, uint64_t words,
@@ -3187,10 +3226,11 @@ void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t words, hipStream_t st)
 // at most 2048 blocks of four waves: one resident wave of blocks on 256 compute units
 uint32_t bbox_blocks(uint64_t n) { return grid_for((n + 3) / 4, 256, BBOX_MAX_BLOCKS); }
 
-void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, uint32_t *part, hipStream_t st)
+void launch_bbox(const float *x, const float *y, const float *z, uint64_t n, uint32_t *part, hipStream_t st,
+                 uint32_t *zero, uint64_t zero_words)
 {
     const int vec4 = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(z)) & 15) == 0;
-    hipLaunchKernelGGL(k_bbox, dim3(bbox_blocks(n)), dim3(256), 0, st, x, y, z, n, vec4, part);
+    hipLaunchKernelGGL(k_bbox, dim3(bbox_blocks(n)), dim3(256), 0, st, x, y, z, n, vec4, part, zero, zero_words);
 }
 
 void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given, const float *lo, const float *hi,
@@ -3227,15 +3267,18 @@ void launch_quantize(const float *x, const float *y, const float *z, uint64_t n,
                            fine_cnt, box_rw, per, base, cm);
 }
 
-void launch_pyramid(uint32_t *pyr, int g, hipStream_t st)
+void launch_pyramid(uint32_t *pyr, int g, uint32_t *exp_out, hipStream_t st)
 {
-    // levels above 4 one launch each, the rest (level 4 = 4096 cells and up) in one block
+    // levels above 4 one launch each, the rest (level 4 = 4096 cells and up)
+    // in one block; the first launch reads the finest level and exports it
     int l = g;
     for (; l >= 1 && l > 4; --l) {
         const uint64_t ncell = 1ull << (3 * (l - 1));
-        hipLaunchKernelGGL(k_pyr_level, dim3(grid_for(ncell, 256)), dim3(256), 0, st, pyr, l);
+        hipLaunchKernelGGL(k_pyr_level, dim3(grid_for(ncell, 256)), dim3(256), 0, st, pyr, l,
+                           l == g ? exp_out : nullptr);
     }
-    if (l >= 1) hipLaunchKernelGGL(k_pyr_top, dim3(1), dim3(1024), 0, st, pyr, l);
+    if (l >= 1) hipLaunchKernelGGL(k_pyr_top, dim3(1), dim3(1024), 0, st, pyr, l, l == g ? exp_out : nullptr);
+    else if (exp_out) launch_grid_export(pyr, 0, exp_out, st);   // G = 1: the root is the finest level
 }
 
 void launch_grid_export(const uint32_t *fine, int g, uint32_t *out, hipStream_t st)
@@ -3422,10 +3465,13 @@ uint64_t np_copy_entries(uint64_t n) { return n + n / NP_T3 + 2; }
 
 static uint64_t preview_tiles(uint64_t n) { return (n + PV_TILE - 1) / PV_TILE; }
 
-void launch_preview_bits(const PreviewArgs &p, uint32_t *bits, hipStream_t st)
+static_assert(PV_TILE == BW_TILE * 32, "a preview block covers one compaction tile");
+
+void launch_preview_bits(const PreviewArgs &p, uint32_t *bits, uint32_t *tile_counts, hipStream_t st)
 {
     if (p.n == 0) return;
-    hipLaunchKernelGGL(k_preview_bits, dim3((uint32_t)preview_tiles(p.n)), dim3(PV_BLOCK), 0, st, p, bits);
+    hipLaunchKernelGGL(k_preview_bits, dim3((uint32_t)preview_tiles(p.n)), dim3(PV_BLOCK), 0, st, p, bits,
+                       tile_counts);
 }
 
 uint64_t bits_tiles(uint64_t n) { return ((n + 31) / 32 + BW_TILE - 1) / BW_TILE; }
