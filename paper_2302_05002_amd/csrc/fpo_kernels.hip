@@ -1390,31 +1390,48 @@ void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, u
 
 // Global shared depths d < d0, in work-chunk order.  Every alive point
 // (state 0xff) offers its original index to its cell of level d + s.  The
-// order is spatially coherent, so a wave's alive points usually fall in a few
-// cells: up to four of them are reduced inside the wave (one atomic each, a
-// ballot and a butterfly minimum per cell), the rest offer their own index.
-__global__ void k_gdepth_min(const uint64_t *__restrict__ code, const uint32_t *__restrict__ orig,
-                             const uint8_t *__restrict__ t, uint64_t n, int csh, uint32_t *gtab)
+// order is spatially coherent, so a tile of GD_TILE consecutive points falls
+// in few cells: the tile keeps the minimum of each of its cells in an LDS
+// hash table (at least twice as many slots as points, so it never fills) and
+// flushes one global atomic per distinct cell.
+constexpr int GD_BLOCK = 256, GD_ITEMS = 8;
+constexpr uint32_t GD_TILE = GD_BLOCK * GD_ITEMS;   // 2048 points
+constexpr uint32_t GD_HASH = 2 * GD_TILE;           // slots
+__global__ __launch_bounds__(GD_BLOCK) void k_gdepth_min(const uint64_t *__restrict__ code,
+                                                         const uint32_t *__restrict__ orig,
+                                                         const uint8_t *__restrict__ t, uint64_t n, int csh,
+                                                         uint32_t *gtab)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint32_t lane = lane_id();
-    for (uint64_t q0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); q0 < n; q0 += stride) {
-        const uint64_t q = q0 + lane;
-        const bool alive = q < n && t[q] == 0xffu;
-        const uint64_t cell = alive ? code[q] >> csh : 0ull;
-        const uint32_t o = alive ? orig[q] : 0xffffffffu;
-        uint64_t pending = __ballot(alive);
-        for (int round = 0; round < 4 && pending; ++round) {
-            const int leader = __ffsll((long long)pending) - 1;
-            const uint64_t c0 = __shfl(cell, leader, 64);
-            const bool mine = ((pending >> lane) & 1ull) && cell == c0;
-            uint32_t m = mine ? o : 0xffffffffu;
-#pragma unroll
-            for (int k = 32; k > 0; k >>= 1) m = min(m, (uint32_t)__shfl_xor(m, k, 64));
-            if ((int)lane == leader) atomicMin(&gtab[c0], m);
-            pending &= ~__ballot(mine);
+    __shared__ uint32_t hk[GD_HASH], hv[GD_HASH];
+    __shared__ uint32_t used;
+    const uint64_t tiles = (n + GD_TILE - 1) / GD_TILE;
+    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        for (uint32_t h = threadIdx.x; h < GD_HASH; h += GD_BLOCK) {
+            hk[h] = 0xffffffffu;
+            hv[h] = 0xffffffffu;
         }
-        if ((pending >> lane) & 1ull) atomicMin(&gtab[cell], o);
+        if (threadIdx.x == 0) used = 0;
+        __syncthreads();
+        // cells of level d + s < g number at most 8^8, so a cell id fits 32 bits
+        uint32_t cell[GD_ITEMS], o[GD_ITEMS];
+#pragma unroll
+        for (int j = 0; j < GD_ITEMS; ++j) {
+            const uint64_t q = tile * GD_TILE + (uint64_t)j * GD_BLOCK + threadIdx.x;
+            const bool alive = q < n && t[q] == 0xffu;
+            cell[j] = alive ? (uint32_t)(code[q] >> csh) : 0xffffffffu;
+            o[j] = alive ? orig[q] : 0xffffffffu;
+        }
+#pragma unroll
+        for (int j = 0; j < GD_ITEMS; ++j) {
+            if (cell[j] == 0xffffffffu) continue;
+            const uint32_t slot = hash32(cell[j]) & (GD_HASH - 1);
+            const uint32_t h = qz_slot<GD_HASH>(hk, &used, cell[j], slot, hk[slot]);
+            atomicMin(&hv[h], o[j]);
+        }
+        __syncthreads();
+        for (uint32_t h = threadIdx.x; h < GD_HASH; h += GD_BLOCK)
+            if (hk[h] != 0xffffffffu) atomicMin(&gtab[hk[h]], hv[h]);
+        __syncthreads();
     }
 }
 
@@ -3293,8 +3310,8 @@ void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream
     for (int d = 0; d < a.d0; ++d) {
         const int csh = 3 * (KB - d - a.s);
         if (d > 0 || !first_filled) launch_fill_u32(gtab, 0xffffffffu, 1ull << (3 * (d + a.s)), st);
-        hipLaunchKernelGGL(k_gdepth_min, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, a.wc_code, a.wc_orig, a.t, n,
-                           csh, gtab);
+        hipLaunchKernelGGL(k_gdepth_min, dim3(grid_for(n, GD_TILE, 8192)), dim3(GD_BLOCK), 0, st, a.wc_code, a.wc_orig,
+                           a.t, n, csh, gtab);
         hipLaunchKernelGGL(k_gdepth_mark, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, a.wc_code, a.wc_orig, a.t, n,
                            csh, gtab, d);
     }
