@@ -403,17 +403,68 @@ __global__ __launch_bounds__(1024) void k_pyr_top(uint32_t *pyr, int top, uint32
     }
 }
 
-// exp_out (or null): level l is the finest, exported row-major on the way.
-__global__ void k_pyr_level(uint32_t *pyr, int l, uint32_t *exp_out)
+// Level l - 1 from level l: a thread per child, loads coalesced, the eight
+// children of a parent summed across eight lanes (a parent's children are
+// consecutive, and the stride is a multiple of 8, so its lanes are active
+// together).
+__global__ void k_pyr_level(uint32_t *pyr, int l)
 {
-    const uint64_t ncell = 1ull << (3 * (l - 1));
+    const uint64_t nchild = 1ull << (3 * l);
     const uint32_t *src = pyr + pyr_off(l);
     uint32_t *dst = pyr + pyr_off(l - 1);
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ncell;
-         k += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t *c = src + 8 * k;
-        dst[k] = c[0] + c[1] + c[2] + c[3] + c[4] + c[5] + c[6] + c[7];
-        if (exp_out) pyr_export(c, k, l, exp_out);
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchild;
+         c += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t s = src[c];
+        s += (uint32_t)__shfl_xor(s, 1, 64);
+        s += (uint32_t)__shfl_xor(s, 2, 64);
+        s += (uint32_t)__shfl_xor(s, 4, 64);
+        if ((c & 7) == 0) dst[c >> 3] = s;
+    }
+}
+
+// The finest level g >= 5: level g - 1 and the row-major export in one pass.
+// A block takes 2^14 Morton-contiguous cells (a 16 x 32 x 32 box: x, y, z),
+// reads them coalesced (all loads first), sums the parents across lanes, and
+// stages the box in LDS in row-major order (z XOR-swizzled by x and y against
+// bank conflicts), so that the export is written in whole 128-byte rows of
+// 32 cells.  64 KB of LDS: two blocks per compute unit.
+constexpr uint32_t PE_CELLS = 1u << 14;
+constexpr int PE_BLOCK = 1024, PE_ITEMS = PE_CELLS / PE_BLOCK;
+__device__ __forceinline__ uint32_t pe_slot(uint32_t x, uint32_t y, uint32_t z)
+{
+    return (x * 32u + y) * 32u + (z ^ (((y & 7u) << 2) | (x & 3u)));
+}
+__global__ __launch_bounds__(PE_BLOCK) void k_pyr_export(uint32_t *pyr, int g, uint32_t *exp_out)
+{
+    __shared__ uint32_t box[PE_CELLS];
+    const uint64_t G = 1ull << g;
+    const uint32_t *src = pyr + pyr_off(g);
+    uint32_t *dst = pyr + pyr_off(g - 1);
+    const uint64_t nboxes = (1ull << (3 * g)) / PE_CELLS;
+    for (uint64_t bx = blockIdx.x; bx < nboxes; bx += gridDim.x) {
+        const uint64_t m0 = bx * PE_CELLS;
+        uint32_t v[PE_ITEMS];
+#pragma unroll
+        for (int j = 0; j < PE_ITEMS; ++j) v[j] = src[m0 + (uint32_t)j * PE_BLOCK + threadIdx.x];
+#pragma unroll
+        for (int j = 0; j < PE_ITEMS; ++j) {
+            const uint32_t lm = (uint32_t)j * PE_BLOCK + threadIdx.x;   // Morton index inside the box
+            box[pe_slot(compact3(lm >> 2), compact3(lm >> 1), compact3(lm))] = v[j];
+            uint32_t s = v[j];
+            s += (uint32_t)__shfl_xor(s, 1, 64);
+            s += (uint32_t)__shfl_xor(s, 2, 64);
+            s += (uint32_t)__shfl_xor(s, 4, 64);
+            if ((lm & 7) == 0) dst[(m0 + lm) >> 3] = s;
+        }
+        __syncthreads();
+        const uint64_t ox = compact3(m0 >> 2), oy = compact3(m0 >> 1), oz = compact3(m0);   // the box's corner
+#pragma unroll
+        for (int j = 0; j < PE_ITEMS; ++j) {
+            const uint32_t r = (uint32_t)j * PE_BLOCK + threadIdx.x;
+            const uint32_t x = r >> 10, y = (r >> 5) & 31u, z = r & 31u;
+            exp_out[((ox + x) * G + (oy + y)) * G + (oz + z)] = box[pe_slot(x, y, z)];
+        }
+        __syncthreads();
     }
 }
 
@@ -3286,16 +3337,21 @@ void launch_quantize(const float *x, const float *y, const float *z, uint64_t n,
 
 void launch_pyramid(uint32_t *pyr, int g, uint32_t *exp_out, hipStream_t st)
 {
-    // levels above 4 one launch each, the rest (level 4 = 4096 cells and up)
-    // in one block; the first launch reads the finest level and exports it
+    // the finest level (g >= 5) with its export, levels above 4 one launch
+    // each, the rest (level 4 = 4096 cells and up) in one block
     int l = g;
+    if (g >= 5 && exp_out) {
+        const uint64_t nboxes = (1ull << (3 * g)) / PE_CELLS;
+        hipLaunchKernelGGL(k_pyr_export, dim3((uint32_t)(nboxes < 8192 ? nboxes : 8192)), dim3(PE_BLOCK), 0, st,
+                           pyr, g, exp_out);
+        --l;
+    }
     for (; l >= 1 && l > 4; --l) {
-        const uint64_t ncell = 1ull << (3 * (l - 1));
-        hipLaunchKernelGGL(k_pyr_level, dim3(grid_for(ncell, 256)), dim3(256), 0, st, pyr, l,
-                           l == g ? exp_out : nullptr);
+        const uint64_t nchild = 1ull << (3 * l);
+        hipLaunchKernelGGL(k_pyr_level, dim3(grid_for(nchild, 256)), dim3(256), 0, st, pyr, l);
     }
     if (l >= 1) hipLaunchKernelGGL(k_pyr_top, dim3(1), dim3(1024), 0, st, pyr, l, l == g ? exp_out : nullptr);
-    else if (exp_out) launch_grid_export(pyr, 0, exp_out, st);   // G = 1: the root is the finest level
+    else if (exp_out && g == 0) launch_grid_export(pyr, 0, exp_out, st);   // G = 1: the root is the finest level
 }
 
 void launch_grid_export(const uint32_t *fine, int g, uint32_t *out, hipStream_t st)
