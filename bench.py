@@ -742,10 +742,18 @@ def main():
         print(f"[bench] batched {out['batched']['speedup']:.2f}x the plain loop", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         trace = ServedTrace(fpo, torch)
+        tuned = {}
+        if not args.no_tune:
+            t = time.perf_counter()
+            tuned = tune_classes(fpo, ctx, [(trace.cloud(i), p) for i, p in enumerate(trace.params)])
+            torch.cuda.empty_cache()
+            print(f"[bench] tuned {len(tuned)} size classes of the trace in {time.perf_counter() - t:.1f}s",
+                  file=sys.stderr, flush=True)
         serial_pps = trace.serial(fpo, torch, ctx)
         print(f"[bench] serial plain loop over the trace: {serial_pps / 1e9:.2f} G points/s", file=sys.stderr,
               flush=True)
         out["served"] = bench_served(fpo, torch, ctx, trace, serial_pps, 1.25)
+        out["served"]["autotuned"] = {"quantize_shape_by_class": tuned}
         print(f"[bench] served {out['served']['speedup']:.2f}x serial, p99 {out['served']['latency_ms_p99']:.1f} ms",
               file=sys.stderr, flush=True)
         # every request at once: the server's capacity against the serial loop

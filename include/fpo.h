@@ -355,7 +355,7 @@ void fpo_server_destroy(fpo_server *srv);
  * call.  Tuning a context while other builds run on it changes only their
  * speed. */
 typedef struct {
-    uint32_t quantize_variant;  /* the chosen shape of the quantise + count pass (0, 1, 2) */
+    uint32_t quantize_variant;  /* the chosen shape of the quantise + count pass (0 .. 3) */
     uint32_t size_class;        /* floor(log2 n): the choice applies to clouds of this size class ... */
     uint32_t count_grid_log2;   /* ... built with this count grid */
     uint32_t candidates;        /* number of shapes timed */
@@ -364,8 +364,11 @@ typedef struct {
 
 /* Times the quantise + count pass of `reps` builds (after one warm-up) of
  * *cloud with every candidate shape: one 1024-thread block per compute unit
- * with a 16K-slot LDS table, two 512-thread blocks with 8K slots, or four
- * 256-thread blocks with 4K slots, each over a contiguous range of points.
+ * with a 16K-slot LDS table, two 512-thread blocks with 8K slots, four
+ * 256-thread blocks with 4K slots, each over a contiguous range of points and
+ * taking eight points per thread between table flushes, or the first shape
+ * taking two points per thread between flushes (the table then keeps up to
+ * 10K cells between flushes: for count grids with few points per cell).
  * Later builds of the size class and count grid use the fastest.  workspace
  * as for fpo_build_submit; reps 1..100.  Blocks until done.  Not for the
  * grid preview (FPO_ERR_INVALID_ARG), which has one shape. */
@@ -381,7 +384,7 @@ fpo_status fpo_autotune_batch(fpo_context *ctx, const fpo_cloud *clouds, const f
                               void *workspace, uint64_t workspace_bytes, uint32_t reps, uint32_t *workers_out,
                               float *ms_out);
 
-/* Forces the quantise shape of later builds of ctx (0..2), or -1 to use the
+/* Forces the quantise shape of later builds of ctx (0..3), or -1 to use the
  * tuned choices again (for tests: every shape gives the same result). */
 fpo_status fpo_context_force_quantize_variant(fpo_context *ctx, int variant);
 

@@ -44,6 +44,8 @@ SELECT_STATIC_BYTES = 655360
 # fpo_timer values (include/fpo.h)
 TIMERS = {"bbox": 0, "quantize": 1, "chunk_split": 2, "subsample": 3, "node_counts": 4, "node_place": 5,
           "preview": 6, "node_sort": 7, "cut": 8, "fused": 9}
+#: quantise-pass shapes the autotuner chooses among (include/fpo.h, fpo_tuning)
+QUANTIZE_VARIANTS = 4
 #: largest n fpo_context_set_single_block_max accepts (include/fpo.h)
 SINGLE_BLOCK_MAX_POINTS = 262143
 

@@ -106,7 +106,7 @@ void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given,
 // receives the least H64 of each count-grid cell.
 // variant: the pass's block and LDS-table shape, 0..QZ_VARIANTS-1 (autotuned;
 // every variant gives the same codes and counts).
-constexpr int QZ_VARIANTS = 3;
+constexpr int QZ_VARIANTS = 4;
 void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box,
                      int g, int given, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw,
                      uint64_t base, uint64_t *cellmin, hipStream_t st, int variant);

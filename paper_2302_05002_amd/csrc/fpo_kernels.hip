@@ -185,10 +185,15 @@ __global__ __launch_bounds__(256) void k_setup(DevBox *box, const uint32_t *part
 // threads with a table of 2^HLOG slots.  Variant 0 is one 1024-thread block
 // per compute unit with 16K slots (128 KB); variants 1 and 2 are two 512-
 // thread blocks with 8K slots and four 256-thread blocks with 4K slots per
-// compute unit, over shorter ranges of points.  The grid preview always
-// takes variant 0's shape with 8K slots of 64-bit minima.
-template <bool GRID, int BLOCK = 1024, int HLOG = 14> struct Qz {
-    static constexpr int ITEMS = GRID ? 2 : 8;
+// compute unit, over shorter ranges of points.  All three take IT = 8 points
+// per thread between flushes, so the table keeps at most 3/4 of its slots
+// minus a round (4K cells for variant 0).  Variant 3 is variant 0 with two
+// points per thread: up to 10K cells between flushes, for count grids with
+// few points per cell, where a flush per round costs one atomic for nearly
+// every point.  The grid preview always takes variant 0's shape with 8K slots
+// of 64-bit minima.
+template <bool GRID, int BLOCK = 1024, int HLOG = 14, int IT = 8> struct Qz {
+    static constexpr int ITEMS = GRID ? 2 : IT;
     static constexpr uint32_t ROUND = BLOCK * ITEMS;
     static constexpr uint32_t HASH = GRID ? 8192 : (1u << HLOG);   // slots
     // flushed when a round could fill the table past half (grid preview)
@@ -263,14 +268,14 @@ template <typename T> __device__ __forceinline__ T &at_byte(T *p, uint32_t off)
 // first probe of every item is read before any is used: a cell already in
 // the table (the usual case) then costs one read and one atomic.  `base` is
 // the original index of x[0] (batches of a streamed cloud).
-template <bool GRID, int QZ_BLOCK = 1024, int HLOG = 14>
+template <bool GRID, int QZ_BLOCK = 1024, int HLOG = 14, int IT = 8>
 __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__ x, const float *__restrict__ y,
                                                        const float *__restrict__ z, uint64_t n, const DevBox *box,
                                                        int g, int given, uint64_t *__restrict__ code,
                                                        uint32_t *__restrict__ fine, DevBox *box_rw, uint64_t per_block,
                                                        uint64_t base, unsigned long long *__restrict__ cellmin)
 {
-    using C = Qz<GRID, QZ_BLOCK, HLOG>;
+    using C = Qz<GRID, QZ_BLOCK, HLOG, IT>;
     constexpr int ITEMS = C::ITEMS;
     constexpr uint32_t ROUND = C::ROUND, HASH = C::HASH;
     __shared__ uint32_t hk[HASH];
@@ -1443,8 +1448,9 @@ void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, u
 // (state 0xff) offers its original index to its cell of level d + s.  The
 // order is spatially coherent, so a tile of GD_TILE consecutive points falls
 // in few cells: the tile keeps the minimum of each of its cells in an LDS
-// hash table (at least twice as many slots as points, so it never fills) and
-// flushes one global atomic per distinct cell.
+// hash table (at least twice as many slots as points, so it never fills),
+// lists the slots it takes, and flushes one global atomic per distinct cell,
+// clearing just those slots for the next tile.
 constexpr int GD_BLOCK = 256, GD_ITEMS = 8;
 constexpr uint32_t GD_TILE = GD_BLOCK * GD_ITEMS;   // 2048 points
 constexpr uint32_t GD_HASH = 2 * GD_TILE;           // slots
@@ -1454,15 +1460,16 @@ __global__ __launch_bounds__(GD_BLOCK) void k_gdepth_min(const uint64_t *__restr
                                                          uint32_t *gtab)
 {
     __shared__ uint32_t hk[GD_HASH], hv[GD_HASH];
+    __shared__ uint16_t taken[GD_TILE];   // slots in use (at most one per point of the tile)
     __shared__ uint32_t used;
+    for (uint32_t h = threadIdx.x; h < GD_HASH; h += GD_BLOCK) {
+        hk[h] = 0xffffffffu;
+        hv[h] = 0xffffffffu;
+    }
+    if (threadIdx.x == 0) used = 0;
+    __syncthreads();
     const uint64_t tiles = (n + GD_TILE - 1) / GD_TILE;
     for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        for (uint32_t h = threadIdx.x; h < GD_HASH; h += GD_BLOCK) {
-            hk[h] = 0xffffffffu;
-            hv[h] = 0xffffffffu;
-        }
-        if (threadIdx.x == 0) used = 0;
-        __syncthreads();
         // cells of level d + s < g number at most 8^8, so a cell id fits 32 bits
         uint32_t cell[GD_ITEMS], o[GD_ITEMS];
 #pragma unroll
@@ -1475,13 +1482,31 @@ __global__ __launch_bounds__(GD_BLOCK) void k_gdepth_min(const uint64_t *__restr
 #pragma unroll
         for (int j = 0; j < GD_ITEMS; ++j) {
             if (cell[j] == 0xffffffffu) continue;
-            const uint32_t slot = hash32(cell[j]) & (GD_HASH - 1);
-            const uint32_t h = qz_slot<GD_HASH>(hk, &used, cell[j], slot, hk[slot]);
+            uint32_t h = hash32(cell[j]) & (GD_HASH - 1);
+            for (;;) {   // linear probing; the table is at most half full
+                uint32_t k = hk[h];
+                if (k == 0xffffffffu) {
+                    k = atomicCAS(&hk[h], 0xffffffffu, cell[j]);
+                    if (k == 0xffffffffu) {
+                        taken[atomicAdd(&used, 1u)] = (uint16_t)h;
+                        break;
+                    }
+                }
+                if (k == cell[j]) break;
+                h = (h + 1) & (GD_HASH - 1);
+            }
             atomicMin(&hv[h], o[j]);
         }
         __syncthreads();
-        for (uint32_t h = threadIdx.x; h < GD_HASH; h += GD_BLOCK)
-            if (hk[h] != 0xffffffffu) atomicMin(&gtab[hk[h]], hv[h]);
+        const uint32_t nu = used;
+        for (uint32_t i = threadIdx.x; i < nu; i += GD_BLOCK) {
+            const uint32_t h = taken[i];
+            atomicMin(&gtab[hk[h]], hv[h]);
+            hk[h] = 0xffffffffu;
+            hv[h] = 0xffffffffu;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) used = 0;
         __syncthreads();
     }
 }
@@ -3314,7 +3339,8 @@ void launch_quantize(const float *x, const float *y, const float *z, uint64_t n,
 {
     if (n == 0) return;
     // one contiguous range per block: 256 blocks (one per compute unit) for
-    // variant 0 and the grid preview, 512 for variant 1, 1024 for variant 2
+    // variants 0 and 3 and the grid preview, 512 for variant 1, 1024 for
+    // variant 2
     if (cellmin) variant = 0;
     const uint64_t blocks = variant == 2 ? 1024 : variant == 1 ? 512 : 256;
     uint64_t per = (n + blocks - 1) / blocks;
@@ -3330,6 +3356,9 @@ void launch_quantize(const float *x, const float *y, const float *z, uint64_t n,
     else if (variant == 1)
         hipLaunchKernelGGL((k_quantize<false, 512, 13>), dim3(grid), dim3(512), 0, st, x, y, z, n, box, g, given,
                            code, fine_cnt, box_rw, per, base, cm);
+    else if (variant == 3)
+        hipLaunchKernelGGL((k_quantize<false, 1024, 14, 2>), dim3(grid), dim3(1024), 0, st, x, y, z, n, box, g,
+                           given, code, fine_cnt, box_rw, per, base, cm);
     else
         hipLaunchKernelGGL((k_quantize<false>), dim3(grid), dim3(1024), 0, st, x, y, z, n, box, g, given, code,
                            fine_cnt, box_rw, per, base, cm);

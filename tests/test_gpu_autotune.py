@@ -23,7 +23,9 @@ def _oracle(c, G, C, S, L, M, bbox=None):
 
 CLOUDS = [("uniform", lambda: synth.uniform(300_000, seed=31), (64, 20_000, 32, 1_000, 64)),
           ("planes", lambda: synth.planes(500_000, seed=32, num_planes=30), (128, 50_000, 64, 2_000, 16)),
-          ("clusters", lambda: synth.clusters(200_000, seed=33, num_clusters=12), (32, 5_000, 16, 300, 7))]
+          ("clusters", lambda: synth.clusters(200_000, seed=33, num_clusters=12), (32, 5_000, 16, 300, 7)),
+          # G = 512: few points per cell, the regime of the two-points-per-thread shape
+          ("sparse", lambda: synth.planes(1_000_000, seed=34, num_planes=40), (512, 1_000_000, 128, 10_000, 64))]
 
 
 @pytest.mark.parametrize("name,make,case", CLOUDS, ids=[c[0] for c in CLOUDS])
@@ -39,7 +41,7 @@ def test_every_quantize_shape_gives_the_same_result(name, make, case):
     try:
         dev = [torch.from_numpy(a).cuda() for a in (c.x, c.y, c.z)]
         pinned = [torch.from_numpy(a).pin_memory() for a in (c.x, c.y, c.z)]
-        for v in range(3):
+        for v in range(fpo.QUANTIZE_VARIANTS):
             ctx.force_quantize_variant(v)
             compare(ctx.build(*dev, fpo.Params(*case)).to_numpy(), exp, label=f"{name} shape {v}: ")
             compare(ctx.build(*dev, fpo.Params(*case, box)).to_numpy(), exp_box, label=f"{name} shape {v} box: ")
@@ -65,7 +67,8 @@ def test_autotune_keeps_and_stores_its_choice(tmp_path):
         try:
             dev = [torch.from_numpy(a).cuda() for a in (c.x, c.y, c.z)]
             t = ctx.autotune(*dev, fpo.Params(*case), reps=2)
-            assert t["quantize_variant"] in (0, 1, 2) and len(t["quantize_ms"]) == 3
+            assert t["quantize_variant"] in range(fpo.QUANTIZE_VARIANTS)
+            assert len(t["quantize_ms"]) == fpo.QUANTIZE_VARIANTS
             assert all(ms > 0 for ms in t["quantize_ms"])
             assert t["size_class"] == 18 and t["count_grid_log2"] == 6   # 2^18 <= 400k < 2^19
             assert t["quantize_ms"][t["quantize_variant"]] == min(t["quantize_ms"])
