@@ -1451,7 +1451,7 @@ void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, u
 // hash table (at least twice as many slots as points, so it never fills),
 // lists the slots it takes, and flushes one global atomic per distinct cell,
 // clearing just those slots for the next tile.
-constexpr int GD_BLOCK = 256, GD_ITEMS = 8;
+constexpr int GD_BLOCK = 256, GD_ITEMS = 8;   // (item j of a wave: 64 consecutive points)
 constexpr uint32_t GD_TILE = GD_BLOCK * GD_ITEMS;   // 2048 points
 constexpr uint32_t GD_HASH = 2 * GD_TILE;           // slots
 __global__ __launch_bounds__(GD_BLOCK) void k_gdepth_min(const uint64_t *__restrict__ code,
@@ -1481,7 +1481,12 @@ __global__ __launch_bounds__(GD_BLOCK) void k_gdepth_min(const uint64_t *__restr
         }
 #pragma unroll
         for (int j = 0; j < GD_ITEMS; ++j) {
-            if (cell[j] == 0xffffffffu) continue;
+            // a point whose left neighbour (the previous point, one lane down)
+            // offers the same cell a smaller index cannot be the minimum:
+            // inside a work chunk the indices ascend, so a run of one cell
+            // sends one offer
+            const uint32_t pc = (uint32_t)__shfl_up((int)cell[j], 1, 64), po = (uint32_t)__shfl_up((int)o[j], 1, 64);
+            if (cell[j] == 0xffffffffu || (lane_id() > 0 && pc == cell[j] && po < o[j])) continue;
             uint32_t h = hash32(cell[j]) & (GD_HASH - 1);
             for (;;) {   // linear probing; the table is at most half full
                 uint32_t k = hk[h];
