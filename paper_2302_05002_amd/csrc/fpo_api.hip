@@ -942,6 +942,11 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         MsOutput o;
         o.vals = U32(P.perm);
         o.pay = U64(P.code_perm);
+        // every point's work chunk, in chunk order, for the work-chunk split
+        // (the subsample's node list buffer is free until then)
+        o.cut2_keys = U32(P.big_nr);
+        o.cut2 = wc_index;
+        o.cut2_shift = 3 * (KB - P.lam_w);
         multisplit(in, n, num_chunks, o, ws + P.ms_temp, st);
     }
     t_chunk.end(st);
@@ -950,9 +955,7 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     t_sub.begin(st);
     {
         MsInput in;
-        in.code = U64(P.code_perm);
-        in.cut = wc_index;
-        in.code_shift = 3 * (KB - P.lam_w);
+        in.keys = U32(P.big_nr);   // the work chunk of every point, written by the chunk split
         in.pay = U64(P.code_perm);
         MsOutput o;
         o.pay = U64(P.wc_code);

@@ -201,6 +201,11 @@ struct MsOutput {
     uint32_t *keys = nullptr;          // keys in sorted order (optional)
     uint32_t *src = nullptr;           // input position of every output (optional, one pass only)
     uint64_t *pay = nullptr;           // payload in sorted order (optional)
+    // optional, with pay: the entry of a second cut holding each output's
+    // payload cell (pay >> cut2_shift), in sorted order (last pass only)
+    uint32_t *cut2_keys = nullptr;
+    CutIndex cut2{};
+    int cut2_shift = 0;
 };
 // Segments: contiguous input ranges, each sorted into its own contiguous
 // bucket range [b0, b0 + nb) (nb <= MS_MAX_BINS); output positions are global.
@@ -228,6 +233,10 @@ struct MsArgs {
     const uint64_t *bucket_begin;
     unsigned long long *status;
     uint32_t *tile_ctr, *err;
+    // MsOutput::cut2_keys
+    uint32_t *cut2_out;
+    CutIndex cut2;
+    int cut2_shift;
 };
 size_t multisplit_temp_bytes(uint64_t n, uint32_t nbins);
 size_t multisplit_temp_bound(uint64_t n, uint64_t max_bins);   // for any nbins <= max_bins

@@ -1213,6 +1213,7 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
             const uint32_t k = i * MS_BLOCK + threadIdx.x;
             if (k >= cnt) continue;
             if (A.pay_out) A.pay_out[gp[i]] = stage[k];
+            if (A.cut2_out) A.cut2_out[gp[i]] = cut_find(A.cut2, stage[k] >> A.cut2_shift);
         }
         if (A.src_out && A.pay_out) {
             __syncthreads();
@@ -1347,6 +1348,9 @@ void multisplit(const MsInput &in, uint64_t n, uint32_t nbins, const MsOutput &o
         A.pay_out = out.pay;
         A.src_out = out.src;
         A.bucket_begin = in.bucket_begin;
+        A.cut2_out = out.cut2_keys;
+        A.cut2 = out.cut2;
+        A.cut2_shift = out.cut2_shift;
         A.status = reinterpret_cast<unsigned long long *>(counts);
         A.tile_ctr = static_cast<uint32_t *>(stemp);
         A.err = in.err;
@@ -1365,6 +1369,9 @@ void multisplit(const MsInput &in, uint64_t n, uint32_t nbins, const MsOutput &o
         A.keys_out = last ? out.keys : kb[ps & 1];
         A.pay_out = last ? out.pay : (in.pay ? pb[ps & 1] : nullptr);
         A.src_out = (last && ps == 0) ? out.src : nullptr;
+        A.cut2_out = last ? out.cut2_keys : nullptr;
+        A.cut2 = out.cut2;
+        A.cut2_shift = out.cut2_shift;
         hipLaunchKernelGGL(k_ms_count<false>, dim3(L.tiles), dim3(MS_BLOCK), 0, st, A);
         scan_exclusive(counts, offs, (uint64_t)L.nb[ps] * L.tiles, nullptr, stemp, st);
         if (scatter_timer) scatter_timer->begin(st);
