@@ -631,6 +631,86 @@ __global__ __launch_bounds__(FR_BLOCK) void k_frontier(const uint32_t *pyr, int 
     if (over) atomicOr(a.over, 1u);
 }
 
+// Both cuts in one launch when every level's heavy nodes are few (at most
+// CS_MAX_OPEN per level, from the plan): one block per cut takes the levels
+// one after another, with block-wide scans instead of a launch per level and
+// a chained scan across tiles.  The same classification, the same lists in
+// the same key order, and the same capacity checks as k_cut_init and
+// k_frontier.
+constexpr uint32_t CS_BLOCK = 1024, CS_MAX_OPEN = 16384;
+__global__ __launch_bounds__(CS_BLOCK) void k_cut_small(const uint32_t *pyr, CutArgs c0, CutArgs c1)
+{
+    const CutArgs &a = blockIdx.x ? c1 : c0;
+    __shared__ uint32_t lds[CS_BLOCK / 64 + 1];
+    if (threadIdx.x == 0) {
+        for (int l = 0; l < MAXD; ++l) a.n_open[l] = a.n_ent[l] = a.tile_ctr[l] = 0u;
+        const uint32_t n = pyr[0];
+        if (n != 0) {
+            if (a.lmin == 0 && (n <= a.thresh || a.lam == 0)) {
+                a.ent[a.ent_off[0]] = 0ull;   // the root is the only entry
+                a.n_ent[0] = 1u;
+                if (n > a.thresh) atomicOr(a.over, 1u);
+            } else {
+                a.open[0][0] = 0ull;
+                a.n_open[0] = 1u;
+            }
+        }
+    }
+    __syncthreads();
+    for (int l = 1; l <= a.lam; ++l) {
+        const uint32_t n_in = min(a.n_open[l - 1], a.open_cap);
+        const uint64_t *in = a.open[(l - 1) & 1];
+        uint64_t *out = a.open[l & 1];
+        const uint64_t ecap = a.ent_off[l + 1] - a.ent_off[l];
+        uint64_t bo_run = 0, be_run = 0;   // heavy children and entries of the parents before this round
+        bool full = false, over = false;
+        for (uint32_t i0 = 0; i0 < n_in; i0 += CS_BLOCK) {
+            const uint32_t i = i0 + threadIdx.x;
+            uint64_t pk = 0;
+            uint32_t om = 0, em = 0;
+            if (i < n_in) {
+                pk = in[i];
+                const uint32_t *ch = pyr + pyr_off(l) + (pk << 3);
+#pragma unroll
+                for (int o = 0; o < 8; ++o) {
+                    const uint32_t c = ch[o];
+                    if (c == 0) continue;
+                    if (l < a.lmin || (c > a.thresh && l < a.lam)) {
+                        om |= 1u << o;
+                    } else {
+                        em |= 1u << o;
+                        over |= c > a.thresh;
+                    }
+                }
+            }
+            uint32_t tot;
+            // at most 8 * CS_BLOCK of each: both counts fit 16 bits
+            const uint32_t ex = block_excl_scan<CS_BLOCK>(__popc(om) | __popc(em) << 16, lds, &tot);
+            uint64_t oo = bo_run + (ex & 0xffffu), oe = be_run + (ex >> 16);
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                if (om >> o & 1u) {
+                    if (oo < a.open_cap) out[oo] = pk << 3 | (uint64_t)o; else full = true;
+                    ++oo;
+                }
+                if (em >> o & 1u) {
+                    if (oe < ecap) a.ent[a.ent_off[l] + oe] = pk << 3 | (uint64_t)o; else full = true;
+                    ++oe;
+                }
+            }
+            bo_run += tot & 0xffffu;
+            be_run += tot >> 16;
+        }
+        if (full) atomicOr(a.err, 1u);
+        if (over) atomicOr(a.over, 1u);
+        if (threadIdx.x == 0) {
+            a.n_open[l] = (uint32_t)bo_run;
+            a.n_ent[l] = (uint32_t)be_run;
+        }
+        __syncthreads();   // the level's list and counts before the next level reads them
+    }
+}
+
 // First index of keys[0..n) not below v (keys ascending).
 __device__ __forceinline__ uint32_t fr_lower_bound(const uint64_t *keys, uint32_t n, uint64_t v)
 {
@@ -3418,13 +3498,18 @@ void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream
 
 void launch_cut(const uint32_t *pyr, const CutArgs &chunks, const CutArgs &wcs, hipStream_t st)
 {
-    const uint64_t ns = chunks.st_off[chunks.lam + 1] > wcs.st_off[wcs.lam + 1] ? chunks.st_off[chunks.lam + 1]
-                                                                                  : wcs.st_off[wcs.lam + 1];
-    hipLaunchKernelGGL(k_cut_init, dim3(grid_for(ns, 256, 1024)), dim3(256), 0, st, pyr, chunks, wcs);
-    for (int l = 1; l <= chunks.lam; ++l) {
-        const uint64_t t0 = chunks.st_off[l + 1] - chunks.st_off[l], t1 = wcs.st_off[l + 1] - wcs.st_off[l];
-        const uint64_t tiles = t0 > t1 ? t0 : t1;
-        if (tiles) hipLaunchKernelGGL(k_frontier, dim3((uint32_t)tiles, 2), dim3(FR_BLOCK), 0, st, pyr, l, chunks, wcs);
+    if (chunks.open_cap <= CS_MAX_OPEN && wcs.open_cap <= CS_MAX_OPEN) {
+        hipLaunchKernelGGL(k_cut_small, dim3(2), dim3(CS_BLOCK), 0, st, pyr, chunks, wcs);
+    } else {
+        const uint64_t ns = chunks.st_off[chunks.lam + 1] > wcs.st_off[wcs.lam + 1] ? chunks.st_off[chunks.lam + 1]
+                                                                                      : wcs.st_off[wcs.lam + 1];
+        hipLaunchKernelGGL(k_cut_init, dim3(grid_for(ns, 256, 1024)), dim3(256), 0, st, pyr, chunks, wcs);
+        for (int l = 1; l <= chunks.lam; ++l) {
+            const uint64_t t0 = chunks.st_off[l + 1] - chunks.st_off[l], t1 = wcs.st_off[l + 1] - wcs.st_off[l];
+            const uint64_t tiles = t0 > t1 ? t0 : t1;
+            if (tiles)
+                hipLaunchKernelGGL(k_frontier, dim3((uint32_t)tiles, 2), dim3(FR_BLOCK), 0, st, pyr, l, chunks, wcs);
+        }
     }
     const uint64_t slots = chunks.ent_off[chunks.lam + 1] > wcs.ent_off[wcs.lam + 1] ? chunks.ent_off[chunks.lam + 1]
                                                                                       : wcs.ent_off[wcs.lam + 1];
