@@ -376,8 +376,8 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
 
 // ---- step 2a: count pyramid ---------------------------------------------------------
 // Level l-1 cell k = sum of level-l cells 8k..8k+7 (Morton order).
-// The top levels (at most 4096 cells at level `top`) in one block: one launch
-// instead of one per level.
+// The top levels (at most 32768 cells at level `top`) in one block: one
+// launch instead of one per level.
 // The eight level-l cells 8k..8k+7 (Morton order) into the row-major export
 // of the finest level (l = g).
 __device__ __forceinline__ void pyr_export(const uint32_t *c, uint64_t k, int l, uint32_t *out)
@@ -3184,27 +3184,29 @@ __global__ void k_wc_chunks(const uint32_t *num_wc_dev, uint32_t max_wc, const u
     }
 }
 
-// Work-chunk range of every chunk (work chunks inside one chunk are
-// consecutive in Morton order).
-__global__ void k_wc_segs(const uint32_t *num_wc_dev, uint32_t max_wc, const uint32_t *wc_chunk, uint32_t *seg_b0,
-                          uint32_t *seg_end)
+// Work-chunk range of every chunk: the chunk of each work chunk (that of its
+// first finest cell) never decreases in Morton order, so chunk c's work chunks
+// are those from the first with a chunk >= c to the first with a chunk > c,
+// found by binary search.  flags[1]: a chunk holds more than MS_MAX_BINS.
+__device__ __forceinline__ uint32_t wc_first_of(const uint32_t *wc_chunk, uint32_t n, uint32_t c)
 {
-    const uint32_t num_wc = min(*num_wc_dev, max_wc);
-    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < num_wc; w += gridDim.x * blockDim.x) {
-        const uint32_t c = wc_chunk[w];
-        if (w == 0 || wc_chunk[w - 1] != c) seg_b0[c] = w;
-        if (w + 1 == num_wc || wc_chunk[w + 1] != c) seg_end[c] = w + 1;
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (wc_chunk[mid] < c) lo = mid + 1; else hi = mid;
     }
+    return lo;
 }
-
-__global__ void k_wc_chunks_nb(const uint32_t *num_chunks_dev, const uint32_t *seg_b0, uint32_t *seg_end_to_nb,
-                               uint32_t *flags)
+__global__ void k_wc_segs(const uint32_t *num_wc_dev, uint32_t max_wc, const uint32_t *num_chunks_dev,
+                          uint32_t max_chunks, const uint32_t *wc_chunk, uint32_t *seg_b0, uint32_t *seg_nb,
+                          uint32_t *flags)
 {
-    const uint32_t num_chunks = *num_chunks_dev;
+    const uint32_t num_wc = min(*num_wc_dev, max_wc), num_chunks = min(*num_chunks_dev, max_chunks);
     for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < num_chunks; c += gridDim.x * blockDim.x) {
-        const uint32_t nb = seg_end_to_nb[c] - seg_b0[c];
-        seg_end_to_nb[c] = nb;
-        if (nb > MS_MAX_BINS) atomicOr(&flags[1], 1u);
+        const uint32_t b0 = wc_first_of(wc_chunk, num_wc, c), e = wc_first_of(wc_chunk, num_wc, c + 1);
+        seg_b0[c] = b0;
+        seg_nb[c] = e - b0;
+        if (e - b0 > MS_MAX_BINS) atomicOr(&flags[1], 1u);
     }
 }
 
@@ -3458,8 +3460,8 @@ void launch_quantize(const float *x, const float *y, const float *z, uint64_t n,
 
 void launch_pyramid(uint32_t *pyr, int g, uint32_t *exp_out, hipStream_t st)
 {
-    // the finest level (g >= 5) with its export, levels above 4 one launch
-    // each, the rest (level 4 = 4096 cells and up) in one block
+    // the finest level (g >= 5) with its export, levels above 5 one launch
+    // each, the rest (level 5 = 32768 cells and up) in one block
     int l = g;
     if (g >= 5 && exp_out) {
         const uint64_t nboxes = (1ull << (3 * g)) / PE_CELLS;
@@ -3467,7 +3469,7 @@ void launch_pyramid(uint32_t *pyr, int g, uint32_t *exp_out, hipStream_t st)
                            pyr, g, exp_out);
         --l;
     }
-    for (; l >= 1 && l > 4; --l) {
+    for (; l >= 1 && l > 5; --l) {
         const uint64_t nchild = 1ull << (3 * l);
         hipLaunchKernelGGL(k_pyr_level, dim3(grid_for(nchild, 256)), dim3(256), 0, st, pyr, l);
     }
@@ -3586,10 +3588,8 @@ void launch_wc_chunks(const uint32_t *num_wc_dev, uint64_t max_wc, const uint64_
     hipLaunchKernelGGL(k_wc_chunks, dim3(grid_for(max_wc, 256)), dim3(256), 0, st, num_wc_dev, (uint32_t)max_wc, wc_key,
                        wc_level, g, pyr,
                        chunks, chunk_level, wc_chunk, wc_nested, flags, wc_count, L, s, class_counts);
-    hipLaunchKernelGGL(k_wc_segs, dim3(grid_for(max_wc, 256)), dim3(256), 0, st, num_wc_dev, (uint32_t)max_wc, wc_chunk,
-                       seg_b0, seg_nb);
-    hipLaunchKernelGGL(k_wc_chunks_nb, dim3(grid_for(max_chunks, 256)), dim3(256), 0, st, num_chunks_dev, seg_b0, seg_nb,
-                       flags);
+    hipLaunchKernelGGL(k_wc_segs, dim3(grid_for(max_chunks, 256)), dim3(256), 0, st, num_wc_dev, (uint32_t)max_wc,
+                       num_chunks_dev, (uint32_t)max_chunks, wc_chunk, seg_b0, seg_nb, flags);
 }
 
 void launch_node_fill(const WcArgs &a, const uint32_t *node_base, uint8_t *depth, uint64_t *key, uint8_t *mask,

@@ -61,7 +61,7 @@ def attribute(names, chunk_passes: int = 1):
     """Region of every dispatch in `names` (kernel names in dispatch order),
     or None for runtime copies.  Transitions follow a build's launch order:
     preview (counters' fill, preview kernels) -> bbox -> quantize -> cut
-    (through k_wc_chunks_nb) -> chunk_split (chunk_passes split passes) ->
+    (through k_wc_segs) -> chunk_split (chunk_passes split passes) ->
     subsample -> node_counts (k_np_pieces .. k_np_count) -> node_place ->
     node_sort (from the first k_np_sort)."""
     out = []
@@ -79,7 +79,7 @@ def attribute(names, chunk_passes: int = 1):
             state = "quantize"
         elif state == "quantize":
             state = "cut"
-        elif state == "cut" and "k_wc_chunks_nb" in prev:
+        elif state == "cut" and "k_wc_segs" in prev:
             state, left = "chunk_split", chunk_passes
         elif state == "chunk_split" and left == 0:
             state = "subsample"
