@@ -1328,6 +1328,35 @@ __global__ void k_ms_seg_prep(uint32_t nseg, const uint32_t *len, const uint32_t
     }
 }
 
+// The same for at most SEG_PREP_ONE segments in one block, with both scans:
+// tile_first (nseg + 1 entries, the last = all tiles), mat, tot[0] = tiles,
+// tot[1] = cells.
+constexpr uint32_t SEG_PREP_ONE = 1024;
+__global__ __launch_bounds__(SEG_PREP_ONE) void k_ms_seg_prep_one(uint32_t nseg, const uint32_t *len,
+                                                                  const uint32_t *nb, uint32_t tile,
+                                                                  uint32_t *tile_first, uint32_t *mat, uint32_t *tot)
+{
+    __shared__ uint32_t lds[SEG_PREP_ONE / 64 + 1];
+    const uint32_t sg = threadIdx.x;
+    uint32_t t = 0, c = 0;
+    if (sg < nseg) {
+        t = (len[sg] + tile - 1) / tile;
+        c = t * nb[sg];
+    }
+    uint32_t tiles, cells;
+    const uint32_t et = block_excl_scan<SEG_PREP_ONE>(t, lds, &tiles);
+    const uint32_t ec = block_excl_scan<SEG_PREP_ONE>(c, lds, &cells);
+    if (sg < nseg) {
+        tile_first[sg] = et;
+        mat[sg] = ec;
+    }
+    if (sg == 0) {
+        tile_first[nseg] = tiles;
+        tot[0] = tiles;
+        tot[1] = cells;
+    }
+}
+
 struct MsLayout {
     uint32_t passes, dbits[4], shift[4], nb[4];
     uint32_t tiles;
@@ -1482,11 +1511,16 @@ void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, u
     uint32_t *counts = reinterpret_cast<uint32_t *>(p); p += align256(4 * sg.max_cells);
     uint32_t *offs = reinterpret_cast<uint32_t *>(p); p += align256(4 * sg.max_cells);
     void *stemp = p;
-    hipLaunchKernelGGL(k_ms_seg_prep, dim3(div_up(sg.nseg, 256)), dim3(256), 0, st, sg.nseg, sg.len, sg.nb, ntile, cells,
-                       MS_SEG_TILE);
-    // tile_first has nseg + 1 entries (the last one = total tiles)
-    scan_exclusive(ntile, tile_first, sg.nseg + 1, tot, stemp, st);
-    scan_exclusive(cells, mat, sg.nseg, tot + 1, stemp, st);
+    if (sg.nseg <= SEG_PREP_ONE) {
+        hipLaunchKernelGGL(k_ms_seg_prep_one, dim3(1), dim3(SEG_PREP_ONE), 0, st, sg.nseg, sg.len, sg.nb, MS_SEG_TILE,
+                           tile_first, mat, tot);
+    } else {
+        hipLaunchKernelGGL(k_ms_seg_prep, dim3(div_up(sg.nseg, 256)), dim3(256), 0, st, sg.nseg, sg.len, sg.nb, ntile,
+                           cells, MS_SEG_TILE);
+        // tile_first has nseg + 1 entries (the last one = total tiles)
+        scan_exclusive(ntile, tile_first, sg.nseg + 1, tot, stemp, st);
+        scan_exclusive(cells, mat, sg.nseg, tot + 1, stemp, st);
+    }
     MsArgs A{};
     A.n = n;
     A.keys = in.keys;
