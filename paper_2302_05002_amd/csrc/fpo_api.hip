@@ -202,7 +202,11 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     P.n_count = take(4 * nn);
     P.n_points = take(4 * nn);
     P.pv_index = take(4 * nn);
+    // the Morton codes in input order and in chunk order, side by side: both
+    // are dead once the work-chunk split has read them, and the subsample
+    // path's hash values take their place
     P.code = take(8 * nn);
+    P.code_perm = take(8 * nn);
     P.pyr = take(4 * P.P);
     P.c_start = take(8 * P.maxC);
     P.cp[0] = cut_plan(nn, P.g, p.max_points_per_chunk, 0);
@@ -220,19 +224,49 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     P.w_start = take(8 * P.maxW);
     P.w_begin = take(4 * P.maxW);
     P.c_count_scan = take(4 * P.maxC);
-    P.code_perm = take(8 * nn);
     P.wc_orig = take(4 * nn);
     P.seg_b0 = take(4 * P.maxC);
     P.seg_nb = take(4 * P.maxC);
     P.wc_nested = take(P.maxW);
     P.wc_chunk = take(4 * P.maxW);
     P.wc_code = take(8 * nn);
-    // chunks, work chunks and nodes each number at most n
+    // One region serves three phases in turn, each done before the next
+    // begins on the stream: the stable splits' temporaries (the chunk split
+    // and the work-chunk split), then the global-memory subsample path's
+    // hash keys (4 slots per point, 8 B each) and node scratch (3 words per
+    // point), then the buffers of node_points.  The hash values (4 B per
+    // slot) go where the two code arrays were.
     {
+        // chunks, work chunks and nodes each number at most n
         const size_t a = multisplit_temp_bound(nn, nn);
         // segmented work-chunk scatter: count matrix bounded by n + #work chunks
         const size_t b = multisplit_seg_temp_bytes(nn, (uint32_t)P.maxC, nn + P.maxW);
-        P.ms_temp = take(a > b ? a : b);
+        const size_t split = a > b ? a : b;
+        const size_t base = o;
+        size_t q = base;
+        auto sub = [&](size_t bytes) {
+            size_t r = q;
+            q += a256(bytes ? bytes : 1);
+            return r;
+        };
+        P.big_hkey = sub(8 * 4 * nn);
+        P.big_node = sub(12 * nn);
+        P.big_hval = P.code;   // 16 B per point: code and code_perm, 256-aligned each
+        const size_t big = q - base;
+        q = base;
+        P.np_tmp = sub(4 * nn);
+        P.np_nb = sub(4 * (nn + 1));
+        P.np_l0 = sub(4 * np_list_entries(nn, 0));
+        P.np_l1 = sub(4 * np_list_entries(nn, 1));
+        P.np_l2 = sub(4 * np_list_entries(nn, 2));
+        P.np_l3 = sub(8 * np_list_entries(nn, 3));
+        P.np_jobs = sub(8 * np_job_entries(nn));
+        P.np_cp = sub(8 * np_copy_entries(nn));
+        P.np_single = sub(nn);
+        const size_t np = q - base;
+        size_t region = split > big ? split : big;
+        if (np > region) region = np;
+        P.ms_temp = take(region);
     }
     uint64_t scan_max = (uint64_t)MAXD * P.maxW;
     if (P.pv_ntiles > scan_max) scan_max = P.pv_ntiles;
@@ -254,22 +288,9 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     P.big_list = take(4 * P.maxW);
     P.cls_list = take(4 * (uint64_t)WC_CLASSES * P.maxW);
     P.big_nr = take(4 * nn);
-    P.big_node = take(12 * nn);
-    // hash slots for work chunks above the LDS capacity: at most 4n in total
-    P.big_hkey = take(8 * 4 * nn);
-    P.big_hval = take(4 * 4 * nn);
-    P.np_tmp = take(4 * nn);
     P.np_cnt = take(4 * MAXD * P.maxW);
     P.np_glist = take(4 * P.maxW);
     P.np_scan = take(4 * (MAXD * P.maxW + 1));
-    P.np_nb = take(4 * (nn + 1));
-    P.np_l0 = take(4 * np_list_entries(nn, 0));
-    P.np_l1 = take(4 * np_list_entries(nn, 1));
-    P.np_l2 = take(4 * np_list_entries(nn, 2));
-    P.np_l3 = take(8 * np_list_entries(nn, 3));
-    P.np_jobs = take(8 * np_job_entries(nn));
-    P.np_cp = take(8 * np_copy_entries(nn));
-    P.np_single = take(nn);
     P.pv_tiles = take(4 * P.pv_ntiles);
     P.pv_offs = take(4 * P.pv_ntiles);
     P.cellmin = (p.flags & FPO_PREVIEW_GRID) ? take(8 * P.G3) : 0;

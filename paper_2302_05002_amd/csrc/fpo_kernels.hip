@@ -866,67 +866,77 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(const uint32_t *in, ui
     }
 }
 
-// Short arrays: one block, 4096 elements per round with a running carry (one
-// launch instead of three).
+// Short arrays: one block, SS_ROUND elements per round with a running carry
+// (one launch instead of three).  A round loads coalesced rows into LDS
+// (padded by one word per 32 against bank conflicts), each thread scans 16
+// consecutive values, and the results leave the same way.
 constexpr uint64_t SCAN_SMALL_MAX = 16384;
+constexpr int SS_PT = 16;
+constexpr uint32_t SS_ROUND = 1024 * SS_PT;
+__device__ __forceinline__ uint32_t ss_pad(uint32_t i) { return i + (i >> 5); }
+
+// One round over in[b, min(n, b + SS_ROUND)): out (and wide, when given) get
+// carry + the exclusive prefix; returns the round's sum.
+__device__ __forceinline__ uint32_t ss_round(const uint32_t *in, uint32_t *out, uint64_t *wide, uint64_t n, uint64_t b,
+                                             uint32_t carry, uint32_t *buf, uint32_t *lds)
+{
+#pragma unroll
+    for (int j = 0; j < SS_PT; ++j) {
+        const uint64_t e = b + (uint64_t)j * 1024 + threadIdx.x;
+        buf[ss_pad(j * 1024 + threadIdx.x)] = e < n ? in[e] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[SS_PT], s = 0;
+#pragma unroll
+    for (int k = 0; k < SS_PT; ++k) {
+        v[k] = buf[ss_pad(SS_PT * threadIdx.x + k)];
+        s += v[k];
+    }
+    uint32_t t;
+    uint32_t run = carry + block_excl_scan<1024>(s, lds, &t);   // its barriers order the reads above
+#pragma unroll
+    for (int k = 0; k < SS_PT; ++k) {
+        buf[ss_pad(SS_PT * threadIdx.x + k)] = run;
+        run += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SS_PT; ++j) {
+        const uint64_t e = b + (uint64_t)j * 1024 + threadIdx.x;
+        if (e < n) {
+            const uint32_t r = buf[ss_pad(j * 1024 + threadIdx.x)];
+            out[e] = r;
+            if (wide) wide[e] = r;
+        }
+    }
+    __syncthreads();   // the next round refills buf
+    return t;
+}
 
 __global__ __launch_bounds__(1024) void k_scan_small(const uint32_t *in, uint32_t *out, uint64_t n,
                                                      const uint32_t *n_dev, uint32_t *total)
 {
     __shared__ uint32_t lds[1024 / 64 + 1];
+    __shared__ uint32_t buf[SS_ROUND + SS_ROUND / 32];
     if (n_dev && *n_dev < n) n = *n_dev;
     uint32_t carry = 0;
-    for (uint64_t b = 0; b < n; b += 4096) {
-        const uint64_t e0 = b + 4ull * threadIdx.x;
-        uint32_t v[4], s = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            v[j] = e0 + j < n ? in[e0 + j] : 0u;
-            s += v[j];
-        }
-        uint32_t t;
-        uint32_t run = carry + block_excl_scan<1024>(s, lds, &t);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (e0 + j < n) out[e0 + j] = run;
-            run += v[j];
-        }
-        carry += t;
-    }
+    for (uint64_t b = 0; b < n; b += SS_ROUND) carry += ss_round(in, out, nullptr, n, b, carry, buf, lds);
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
 // Block b scans its own array (b = 0: in0 into out0 and out0_wide; b = 1:
-// in1 into out1), 4096 values per round with a running carry.
+// in1 into out1), SS_ROUND values per round with a running carry.
 __global__ __launch_bounds__(1024) void k_scan_pair(const uint32_t *in0, uint32_t *out0, uint64_t *out0_wide,
                                                     uint64_t n0, const uint32_t *in1, uint32_t *out1, uint64_t n1)
 {
     __shared__ uint32_t lds[1024 / 64 + 1];
+    __shared__ uint32_t buf[SS_ROUND + SS_ROUND / 32];
     const uint32_t *in = blockIdx.x ? in1 : in0;
     uint32_t *out = blockIdx.x ? out1 : out0;
     uint64_t *wide = blockIdx.x ? nullptr : out0_wide;
     const uint64_t n = blockIdx.x ? n1 : n0;
     uint32_t carry = 0;
-    for (uint64_t b = 0; b < n; b += 4096) {
-        const uint64_t e0 = b + 4ull * threadIdx.x;
-        uint32_t v[4], s = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            v[j] = e0 + j < n ? in[e0 + j] : 0u;
-            s += v[j];
-        }
-        uint32_t t;
-        uint32_t run = carry + block_excl_scan<1024>(s, lds, &t);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (e0 + j < n) {
-                out[e0 + j] = run;
-                if (wide) wide[e0 + j] = run;
-            }
-            run += v[j];
-        }
-        carry += t;
-    }
+    for (uint64_t b = 0; b < n; b += SS_ROUND) carry += ss_round(in, out, wide, n, b, carry, buf, lds);
 }
 
 void scan_exclusive_pair(const uint32_t *in0, uint32_t *out0, uint64_t *out0_wide, uint64_t n0, const uint32_t *in1,

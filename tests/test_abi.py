@@ -59,6 +59,17 @@ def test_workspace_grows_with_n(lib):
     assert b > a
 
 
+def test_workspace_per_point(lib):
+    """The split temporaries, the global-memory subsample path's tables and
+    the node_points buffers share one region (they are live in turn), so the
+    worst-case workspace stays below 150 B per point for the 20M-point planes
+    parameters and below 175 B for 200M points at G = 512."""
+    import paper_2302_05002_amd as fpo
+    fpo.load_library(LIB)
+    assert fpo.workspace_size(20_000_000, fpo.Params(128, 1_000_000, 128, 10_000, 64)) < 150 * 20_000_000
+    assert fpo.workspace_size(200_000_000, fpo.Params(512, 2_000_000, 128, 10_000, 64)) < 175 * 200_000_000
+
+
 def test_preview_modulus_for_a_target(lib):
     """M = max(1, ceil(n / target)); the stride preview then has ceil(n / M)
     <= target indices (the paper decimates to a fixed one million points)."""
