@@ -355,23 +355,29 @@ void fpo_server_destroy(fpo_server *srv);
  * call.  Tuning a context while other builds run on it changes only their
  * speed. */
 typedef struct {
-    uint32_t quantize_variant;  /* the chosen shape of the quantise + count pass (0 .. 3) */
+    uint32_t quantize_variant;  /* the chosen shape of the quantise + count pass (0 .. 4) */
     uint32_t size_class;        /* floor(log2 n): the choice applies to clouds of this size class ... */
     uint32_t count_grid_log2;   /* ... built with this count grid */
-    uint32_t candidates;        /* number of shapes timed */
-    float quantize_ms[4];       /* median device time of the pass per shape */
+    uint32_t candidates;        /* number of shapes timed (4, or 5 with the binned pass) */
+    float quantize_ms[5];       /* median device time per shape of the pass and the box pass before it */
 } fpo_tuning;
 
-/* Times the quantise + count pass of `reps` builds (after one warm-up) of
- * *cloud with every candidate shape: one 1024-thread block per compute unit
- * with a 16K-slot LDS table, two 512-thread blocks with 8K slots, four
- * 256-thread blocks with 4K slots, each over a contiguous range of points and
- * taking eight points per thread between table flushes, or the first shape
- * taking two points per thread between flushes (the table then keeps up to
- * 10K cells between flushes: for count grids with few points per cell).
- * Later builds of the size class and count grid use the fastest.  workspace
- * as for fpo_build_submit; reps 1..100.  Blocks until done.  Not for the
- * grid preview (FPO_ERR_INVALID_ARG), which has one shape. */
+/* Times the quantise + count pass, with the bounding-box pass before it, of
+ * `reps` builds (after one warm-up) of *cloud with every candidate shape: one
+ * 1024-thread block per compute unit with a 16K-slot LDS table, two
+ * 512-thread blocks with 8K slots, four 256-thread blocks with 4K slots, each
+ * over a contiguous range of points and taking eight points per thread
+ * between table flushes, or the first shape taking two points per thread
+ * between flushes (the table then keeps up to 10K cells between flushes: for
+ * count grids with few points per cell).  For device input with G = 256 or
+ * 512 and at least 2^20 points also shape 4, the binned pass: codes and
+ * per-block histograms of 2^15-cell bins of the grid's Morton order, each
+ * point's cell put into its bin's range, then one workgroup per bin counting
+ * in LDS and writing its part of the grid whole (no clearing).  Untuned
+ * builds take shape 4 where it applies with G = 512, else shape 0.  Later
+ * builds of the size class and count grid use the fastest.  workspace as for
+ * fpo_build_submit; reps 1..100.  Blocks until done.  Not for the grid
+ * preview (FPO_ERR_INVALID_ARG), which has one shape. */
 fpo_status fpo_autotune(fpo_context *ctx, const fpo_cloud *cloud, const fpo_params *p, void *workspace,
                         uint64_t workspace_bytes, uint32_t reps, fpo_tuning *out);
 
@@ -384,8 +390,9 @@ fpo_status fpo_autotune_batch(fpo_context *ctx, const fpo_cloud *clouds, const f
                               void *workspace, uint64_t workspace_bytes, uint32_t reps, uint32_t *workers_out,
                               float *ms_out);
 
-/* Forces the quantise shape of later builds of ctx (0..3), or -1 to use the
- * tuned choices again (for tests: every shape gives the same result). */
+/* Forces the quantise shape of later builds of ctx (0..4; shape 4 where it
+ * does not apply runs shape 0), or -1 to use the tuned choices again (for
+ * tests: every shape gives the same result). */
 fpo_status fpo_context_force_quantize_variant(fpo_context *ctx, int variant);
 
 /* ---- single-workgroup builds ------------------------------------------------

@@ -45,7 +45,7 @@ SELECT_STATIC_BYTES = 655360
 TIMERS = {"bbox": 0, "quantize": 1, "chunk_split": 2, "subsample": 3, "node_counts": 4, "node_place": 5,
           "preview": 6, "node_sort": 7, "cut": 8, "fused": 9}
 #: quantise-pass shapes the autotuner chooses among (include/fpo.h, fpo_tuning)
-QUANTIZE_VARIANTS = 4
+QUANTIZE_VARIANTS = 5
 #: largest n fpo_context_set_single_block_max accepts (include/fpo.h)
 SINGLE_BLOCK_MAX_POINTS = 262143
 
@@ -113,7 +113,7 @@ class _Stats(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("quantize_variant", ctypes.c_uint32), ("size_class", ctypes.c_uint32),
                 ("count_grid_log2", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
-                ("quantize_ms", ctypes.c_float * 4)]
+                ("quantize_ms", ctypes.c_float * 5)]
 
 
 class _Result(ctypes.Structure):

@@ -148,6 +148,7 @@ struct Plan {
     size_t np_tmp, np_glist, np_cnt, np_scan, np_nb, np_l0, np_l1, np_l2, np_l3, np_jobs, np_cp, np_single, pv_tiles, pv_offs,
         cellmin, pv_bits;
     uint64_t pv_ntiles;
+    size_t shared_bytes;   // the region of ms_temp (split temporaries, then the subsample and node_points buffers)
 };
 
 Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
@@ -267,6 +268,7 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
         size_t region = split > big ? split : big;
         if (np > region) region = np;
         P.ms_temp = take(region);
+        P.shared_bytes = region;
     }
     uint64_t scan_max = (uint64_t)MAXD * P.maxW;
     if (P.pv_ntiles > scan_max) scan_max = P.pv_ntiles;
@@ -798,6 +800,11 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     // ---- step 1: bbox, quantise, count ----
     const int given = (p->flags & FPO_BBOX_GIVEN) ? 1 : 0;
     const int qv = quantize_variant(ctx, n, P.g);
+    // the binned quantise + count pass: one pass over device-resident input
+    // without the grid preview; its temporaries sit in the region the splits
+    // use later and where the chunk-ordered codes go
+    const bool binned = qv == QZ_BINNED && !host_in && pa.mode != PV_GRID && quantize_binned_ok(n, P.g) &&
+                        quantize_binned_temp_bytes(P.g) <= P.shared_bytes;
     // Timed regions (when timing): contiguous runs of launches that together
     // cover every kernel of the build; only the host round trips fall between
     // them.
@@ -844,10 +851,10 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     uint32_t *fine = pyr + pyr_off(g);
     const bool box_region = !given;   // a given box has no bounding-box pass: its fills go with quantise
     // the count grid is cleared by the bounding-box pass of a one-batch build
-    // (device input), else here
-    const bool zero_in_bbox = !given && !host_in;
+    // (device input), else here; the binned pass writes every cell
+    const bool zero_in_bbox = !given && !host_in && !binned;
     (box_region ? t_bbox : t_quant).begin(st);
-    if (!zero_in_bbox) launch_fill_u32(fine, 0u, P.G3, st);
+    if (!zero_in_bbox && !binned) launch_fill_u32(fine, 0u, P.G3, st);
     uint64_t *cellmin = pa.mode == PV_GRID ? U64(P.cellmin) : nullptr;
     if (cellmin) launch_fill_u32(U32(P.cellmin), 0xffffffffu, 2 * P.G3, st);
     (box_region ? t_bbox : t_quant).end(st);
@@ -863,7 +870,11 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
             const uint64_t c = n - o < sbatch ? n - o : sbatch;
             if (host_in) JCHK(hipStreamWaitEvent(st, job->stream_events[bi++], 0));
             t_quant.begin(st);
-            launch_quantize(X + o, Y + o, Z + o, c, box, g, 1, U64(P.code) + o, fine, box, o, cellmin, st, qv);
+            if (binned)
+                launch_quantize_binned(X, Y, Z, n, box, g, 1, U64(P.code), fine, box, ws + P.ms_temp,
+                                       reinterpret_cast<uint16_t *>(ws + P.code_perm), stemp, st);
+            else
+                launch_quantize(X + o, Y + o, Z + o, c, box, g, 1, U64(P.code) + o, fine, box, o, cellmin, st, qv);
             t_quant.end(st);
         }
     } else {
@@ -884,7 +895,11 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         launch_setup(box, U32(P.bbox_part), nparts, 0, p->bbox_min, p->bbox_max, 0, st);
         t_bbox.end(st);
         t_quant.begin(st);
-        launch_quantize(X, Y, Z, n, box, g, 0, U64(P.code), fine, box, 0, cellmin, st, qv);
+        if (binned)
+            launch_quantize_binned(X, Y, Z, n, box, g, 0, U64(P.code), fine, box, ws + P.ms_temp,
+                                   reinterpret_cast<uint16_t *>(ws + P.code_perm), stemp, st);
+        else
+            launch_quantize(X, Y, Z, n, box, g, 0, U64(P.code), fine, box, 0, cellmin, st, qv);
         t_quant.end(st);
     }
 

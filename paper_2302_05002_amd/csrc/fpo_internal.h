@@ -106,10 +106,23 @@ void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given,
 // receives the least H64 of each count-grid cell.
 // variant: the pass's block and LDS-table shape, 0..QZ_VARIANTS-1 (autotuned;
 // every variant gives the same codes and counts).
-constexpr int QZ_VARIANTS = 4;
+// Variant QZ_BINNED is the binned form (launch_quantize_binned), for device
+// input without the grid preview when quantize_binned_ok(n, g).
+constexpr int QZ_VARIANTS = 5;
+constexpr int QZ_BINNED = 4;
+constexpr uint64_t QB_MIN_POINTS = 1ull << 20;
 void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box,
                      int g, int given, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw,
                      uint64_t base, uint64_t *cellmin, hipStream_t st, int variant);
+// Count grids of 2^24 and 2^27 cells (g = 8, 9) and at least 2^20 points.
+bool quantize_binned_ok(uint64_t n, int g);
+// temp: quantize_binned_temp_bytes(g) bytes; cells: 2 B per point; scan_temp:
+// scan temporaries for 2^(3g - 15) * 256 values.  Writes every cell of the
+// count grid (no clearing needed) and the codes.
+size_t quantize_binned_temp_bytes(int g);
+void launch_quantize_binned(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box, int g,
+                            int given, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw, void *temp,
+                            uint16_t *cells, void *scan_temp, hipStream_t st);
 // exp_out (or null): the finest level's row-major export, written by the
 // launch that reads it.
 void launch_pyramid(uint32_t *pyr, int g, uint32_t *exp_out, hipStream_t st);

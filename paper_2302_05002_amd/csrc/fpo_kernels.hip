@@ -374,6 +374,145 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
     }
 }
 
+// Binned form of the pass (variant QZ_BINNED) for count grids of 2^24 cells
+// and more, where the per-cell atomics of the table form land all over a
+// grid larger than the last-level cache (G = 512: 512 MiB) at a few tens of
+// G atomics/s.  The grid's Morton order falls into bins of 2^15 cells; one
+// pass writes the codes and each block's histogram of bins, a scan of the
+// histograms (bin-major) gives every (bin, block) its range, a second pass
+// puts the 15 low bits of each point's cell into its bin's range, and one
+// block per bin counts its cells in LDS and writes its 2^15 counts whole, so
+// the grid needs no clearing.  Counts are sums: the order in which a bin's
+// points are placed does not matter.
+constexpr int QB_CELL_BITS = 15;
+constexpr uint32_t QB_CELLS = 1u << QB_CELL_BITS;   // 128 KB of LDS counters
+constexpr uint32_t QB_MAX_BINS = 4096;              // G = 512
+constexpr int QB_BLOCK = 1024, QB_IT = 8;
+constexpr uint32_t QB_BLOCKS = 256;                 // one range of points per compute unit
+
+__global__ __launch_bounds__(QB_BLOCK) void k_qz_bin_code(const float *__restrict__ x, const float *__restrict__ y,
+                                                          const float *__restrict__ z, uint64_t n, const DevBox *box,
+                                                          int g, int given, uint64_t *__restrict__ code,
+                                                          uint32_t *__restrict__ bhist, DevBox *box_rw,
+                                                          uint64_t per_block)
+{
+    constexpr uint32_t ROUND = QB_BLOCK * QB_IT;
+    __shared__ uint32_t hist[QB_MAX_BINS];
+    __shared__ uint32_t wsum[QB_BLOCK / 64];
+    const uint32_t nbins = 1u << (3 * g - QB_CELL_BITS);
+    for (uint32_t b = threadIdx.x; b < nbins; b += QB_BLOCK) hist[b] = 0;
+    const uint64_t lo = (uint64_t)blockIdx.x * per_block;
+    const uint32_t cnt = (uint32_t)((lo + per_block < n ? lo + per_block : n) - lo);
+    const float *bx = x + lo, *by = y + lo, *bz = z + lo;
+    uint64_t *bcode = code + lo;
+    float px[QB_IT], py[QB_IT], pz[QB_IT];
+#pragma unroll
+    for (int j = 0; j < QB_IT; ++j) {
+        const uint32_t o = (uint32_t)j * QB_BLOCK + threadIdx.x;
+        px[j] = o < cnt ? at_byte(bx, 4 * o) : 0.0f;
+        py[j] = o < cnt ? at_byte(by, 4 * o) : 0.0f;
+        pz[j] = o < cnt ? at_byte(bz, 4 * o) : 0.0f;
+    }
+    const float lx = box->lo[0], ly = box->lo[1], lz = box->lo[2], sc = box->scale;
+    const float hx = box->hi[0], hy = box->hi[1], hz = box->hi[2];
+    const int bsh = 3 * (KB - g) + QB_CELL_BITS;
+    __syncthreads();
+    uint32_t outside = 0;
+    bool bad = false;
+    for (uint32_t r0 = 0; r0 < cnt; r0 += ROUND) {
+#pragma unroll
+        for (int j = 0; j < QB_IT; ++j) {
+            const uint32_t o = r0 + (uint32_t)j * QB_BLOCK + threadIdx.x;
+            const uint32_t ux = quantize1(px[j], lx, sc), uy = quantize1(py[j], ly, sc), uz = quantize1(pz[j], lz, sc);
+            const uint64_t c = (split3(ux) << 2) | (split3(uy) << 1) | split3(uz);
+            if (o < cnt) {
+                at_byte(bcode, 8 * o) = c;
+                atomicAdd(&hist[(uint32_t)(c >> bsh)], 1u);
+            }
+            if (given && o < cnt) {
+                outside += (px[j] < lx || px[j] > hx || py[j] < ly || py[j] > hy || pz[j] < lz || pz[j] > hz) ? 1u : 0u;
+                bad |= !(fabsf(px[j]) <= FLT_MAX && fabsf(py[j]) <= FLT_MAX && fabsf(pz[j]) <= FLT_MAX);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < QB_IT; ++j) {
+            const uint32_t o = r0 + ROUND + (uint32_t)j * QB_BLOCK + threadIdx.x;
+            px[j] = o < cnt ? at_byte(bx, 4 * o) : 0.0f;
+            py[j] = o < cnt ? at_byte(by, 4 * o) : 0.0f;
+            pz[j] = o < cnt ? at_byte(bz, 4 * o) : 0.0f;
+        }
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nbins; b += QB_BLOCK) bhist[(uint64_t)b * gridDim.x + blockIdx.x] = hist[b];
+    if (given) {
+        outside = wave_sum(outside);
+        const bool wbad = __ballot(bad) != 0;
+        if (lane_id() == 0) wsum[threadIdx.x >> 6] = outside | (wbad ? 0x80000000u : 0u);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0, b = 0;
+            for (int w = 0; w < QB_BLOCK / 64; ++w) {
+                t += wsum[w] & 0x7fffffffu;
+                b |= wsum[w] >> 31;
+            }
+            if (t) atomicAdd(&box_rw->n_outside, (unsigned long long)t);
+            if (b) atomicOr(&box_rw->nonfinite, 1u);
+        }
+    }
+}
+
+// Each block re-reads the codes of its range and hands out the positions of
+// its (bin, block) ranges with LDS counters.
+__global__ __launch_bounds__(QB_BLOCK) void k_qz_bin_place(const uint64_t *__restrict__ code, uint64_t n, int g,
+                                                           const uint32_t *__restrict__ boff,
+                                                           uint16_t *__restrict__ cells, uint64_t per_block)
+{
+    constexpr uint32_t ROUND = QB_BLOCK * QB_IT;
+    __shared__ uint32_t fill[QB_MAX_BINS];
+    const uint32_t nbins = 1u << (3 * g - QB_CELL_BITS);
+    for (uint32_t b = threadIdx.x; b < nbins; b += QB_BLOCK) fill[b] = boff[(uint64_t)b * gridDim.x + blockIdx.x];
+    __syncthreads();
+    const uint64_t lo = (uint64_t)blockIdx.x * per_block;
+    const uint32_t cnt = (uint32_t)((lo + per_block < n ? lo + per_block : n) - lo);
+    const uint64_t *bcode = code + lo;
+    const int csh = 3 * (KB - g);
+    for (uint32_t r0 = 0; r0 < cnt; r0 += ROUND) {
+        uint64_t c[QB_IT];
+#pragma unroll
+        for (int j = 0; j < QB_IT; ++j) {
+            const uint32_t o = r0 + (uint32_t)j * QB_BLOCK + threadIdx.x;
+            c[j] = o < cnt ? at_byte(bcode, 8 * o) : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < QB_IT; ++j) {
+            const uint32_t o = r0 + (uint32_t)j * QB_BLOCK + threadIdx.x;
+            if (o >= cnt) continue;
+            const uint32_t cell = (uint32_t)(c[j] >> csh);
+            const uint32_t slot = atomicAdd(&fill[cell >> QB_CELL_BITS], 1u);
+            cells[slot] = (uint16_t)(cell & (QB_CELLS - 1u));
+        }
+    }
+}
+
+// One block per bin: its cells counted in LDS, its 2^15 counts written.
+__global__ __launch_bounds__(1024) void k_qz_bin_grid(const uint16_t *__restrict__ cells,
+                                                      const uint32_t *__restrict__ boff, uint32_t nblocks,
+                                                      uint32_t nbins, uint64_t n, uint32_t *__restrict__ fine)
+{
+    __shared__ uint32_t hist[QB_CELLS];
+    for (uint32_t bin = blockIdx.x; bin < nbins; bin += gridDim.x) {
+        for (uint32_t i = threadIdx.x; i < QB_CELLS; i += 1024) hist[i] = 0;
+        __syncthreads();
+        const uint32_t b0 = boff[(uint64_t)bin * nblocks];
+        const uint32_t b1 = bin + 1 < nbins ? boff[(uint64_t)(bin + 1) * nblocks] : (uint32_t)n;
+        for (uint32_t j = b0 + threadIdx.x; j < b1; j += 1024) atomicAdd(&hist[cells[j]], 1u);
+        __syncthreads();
+        uint32_t *dst = fine + ((uint64_t)bin << QB_CELL_BITS);
+        for (uint32_t i = threadIdx.x; i < QB_CELLS; i += 1024) dst[i] = hist[i];
+        __syncthreads();
+    }
+}
+
 // ---- step 2a: count pyramid ---------------------------------------------------------
 // Level l-1 cell k = sum of level-l cells 8k..8k+7 (Morton order).
 // The top levels (at most 32768 cells at level `top`) in one block: one
@@ -3500,6 +3639,34 @@ void launch_quantize(const float *x, const float *y, const float *z, uint64_t n,
     else
         hipLaunchKernelGGL((k_quantize<false>), dim3(grid), dim3(1024), 0, st, x, y, z, n, box, g, given, code,
                            fine_cnt, box_rw, per, base, cm);
+}
+
+bool quantize_binned_ok(uint64_t n, int g) { return g >= 8 && g <= 9 && n >= QB_MIN_POINTS; }
+
+size_t quantize_binned_temp_bytes(int g)
+{
+    const uint64_t words = (1ull << (3 * g - QB_CELL_BITS)) * QB_BLOCKS;
+    return 2 * ((4 * words + 255) & ~(size_t)255);
+}
+
+void launch_quantize_binned(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box, int g,
+                            int given, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw, void *temp,
+                            uint16_t *cells, void *scan_temp, hipStream_t st)
+{
+    if (n == 0) return;
+    uint64_t per = (n + QB_BLOCKS - 1) / QB_BLOCKS;
+    per = (per + 63) / 64 * 64;
+    const uint32_t grid = (uint32_t)((n + per - 1) / per);
+    const uint32_t nbins = 1u << (3 * g - QB_CELL_BITS);
+    const uint64_t words = (uint64_t)nbins * grid;
+    uint32_t *bhist = static_cast<uint32_t *>(temp);
+    uint32_t *boff = bhist + (((4 * (uint64_t)nbins * QB_BLOCKS + 255) & ~255ull) / 4);
+    hipLaunchKernelGGL(k_qz_bin_code, dim3(grid), dim3(QB_BLOCK), 0, st, x, y, z, n, box, g, given, code, bhist, box_rw,
+                       per);
+    scan_exclusive(bhist, boff, words, nullptr, scan_temp, st);
+    hipLaunchKernelGGL(k_qz_bin_place, dim3(grid), dim3(QB_BLOCK), 0, st, code, n, g, boff, cells, per);
+    hipLaunchKernelGGL(k_qz_bin_grid, dim3(nbins < 1024 ? nbins : 1024), dim3(1024), 0, st, cells, boff, grid, nbins,
+                       n, fine_cnt);
 }
 
 void launch_pyramid(uint32_t *pyr, int g, uint32_t *exp_out, hipStream_t st)

@@ -103,7 +103,8 @@ int quantize_variant(fpo_context *c, uint64_t n, int g)
     std::lock_guard<std::mutex> lk(c->mu);
     if (c->qz_force >= 0) return c->qz_force;
     const uint8_t v = c->qz_variant[ilog2_floor(n ? n : 1)][g];
-    return v < QZ_VARIANTS ? v : 0;
+    // untuned: the binned pass for the 2^27-cell grid (G = 512), else shape 0
+    return v < QZ_VARIANTS ? v : g >= 9 ? QZ_BINNED : 0;
 }
 
 void tune_cache_load(fpo_context *c)
@@ -153,12 +154,17 @@ fpo_status fpo_autotune(fpo_context *ctx, const fpo_cloud *cloud, const fpo_para
     ctx->small_max.store(0);
     memset(out, 0, sizeof(*out));
     uint64_t ref = 0;
-    for (int v = 0; v < QZ_VARIANTS; ++v) {
+    // the binned pass (the last variant) needs device input and a count grid
+    // of 2^24 cells or more; it also spares the bounding-box pass the
+    // clearing of the grid, so every shape is timed over both regions
+    const bool binned_ok = cloud->location == FPO_DEVICE && quantize_binned_ok(cloud->n, ilog2_ceil(p->count_grid));
+    const int nv = binned_ok ? QZ_VARIANTS : QZ_BINNED;
+    for (int v = 0; v < nv; ++v) {
         {
             std::lock_guard<std::mutex> g(ctx->mu);
             ctx->qz_force = v;
             ctx->timing = true;
-            ctx->timer_mask = 1u << FPO_TIMER_QUANTIZE;
+            ctx->timer_mask = 1u << FPO_TIMER_QUANTIZE | 1u << FPO_TIMER_BBOX;
         }
         std::vector<double> ms;
         for (uint32_t r = 0; r <= reps; ++r) {   // the first build also warms up the shape
@@ -166,8 +172,10 @@ fpo_status fpo_autotune(fpo_context *ctx, const fpo_cloud *cloud, const fpo_para
             fpo_status s = fpo_build_submit(ctx, cloud, p, workspace, workspace_bytes, nullptr, &job);
             if (s != FPO_OK) return s;
             s = fpo_job_wait(job);
-            float t = 0.0f;
+            float t = 0.0f, tb = 0.0f;
             if (s == FPO_OK) s = fpo_job_timer(job, FPO_TIMER_QUANTIZE, &t, nullptr);
+            if (s == FPO_OK) s = fpo_job_timer(job, FPO_TIMER_BBOX, &tb, nullptr);
+            t += tb;
             if (s == FPO_OK && r == 0) {
                 uint64_t fp = 0;
                 s = job_fingerprint(job, &fp);
@@ -183,7 +191,7 @@ fpo_status fpo_autotune(fpo_context *ctx, const fpo_cloud *cloud, const fpo_para
         out->quantize_ms[v] = (float)median(ms);
     }
     int best = 0;
-    for (int v = 1; v < QZ_VARIANTS; ++v)
+    for (int v = 1; v < nv; ++v)
         if (out->quantize_ms[v] < out->quantize_ms[best]) best = v;
     const int k = ilog2_floor(cloud->n), gl = ilog2_ceil(p->count_grid);
     {
@@ -193,7 +201,7 @@ fpo_status fpo_autotune(fpo_context *ctx, const fpo_cloud *cloud, const fpo_para
     out->quantize_variant = (uint32_t)best;
     out->size_class = (uint32_t)k;
     out->count_grid_log2 = (uint32_t)gl;
-    out->candidates = QZ_VARIANTS;
+    out->candidates = (uint32_t)nv;
     tune_cache_save(ctx);
     return FPO_OK;
 }
