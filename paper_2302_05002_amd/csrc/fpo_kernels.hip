@@ -905,14 +905,36 @@ __global__ void k_cut_rank(const uint32_t *pyr, CutArgs c0, CutArgs c1)
 
 // idx[c] = number of entries whose first finest cell lies before coarse cell
 // c of level lt (c = 0 .. 8^lt).
-__global__ void k_cut_index(CutArgs c0, CutArgs c1)
+// A thread takes CI_RUN consecutive coarse cells: one binary search for the
+// first, then a walk over the few entries that start inside the run (the
+// index is monotone); the block stages its cells in LDS and writes them
+// coalesced.
+constexpr int CI_BLOCK = 256, CI_RUN = 16;
+constexpr uint32_t CI_SPAN = CI_BLOCK * CI_RUN;
+
+__global__ __launch_bounds__(CI_BLOCK) void k_cut_index(CutArgs c0, CutArgs c1)
 {
+    __shared__ uint32_t buf[CI_SPAN + CI_SPAN / 32];   // one pad word per 32 against bank conflicts
     const CutArgs &a = blockIdx.y ? c1 : c0;
     const uint32_t num = min(*a.num_out, a.max_out);
-    const uint64_t cells = 1ull << (3 * a.lt);
-    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= cells;
-         c += (uint64_t)gridDim.x * blockDim.x)
-        a.idx[c] = fr_lower_bound(a.out_start, num, c << (3 * (a.lam - a.lt)));
+    const uint64_t cells = 1ull << (3 * a.lt);   // the index has cells + 1 words
+    const int sh = 3 * (a.lam - a.lt);
+    for (uint64_t cb = (uint64_t)blockIdx.x * CI_SPAN; cb <= cells; cb += (uint64_t)gridDim.x * CI_SPAN) {
+        const uint64_t first = cb + (uint64_t)threadIdx.x * CI_RUN;
+        uint32_t lo = first <= cells ? fr_lower_bound(a.out_start, num, first << sh) : num;
+        for (int k = 0; k < CI_RUN; ++k) {
+            const uint64_t bound = (first + k) << sh;
+            while (lo < num && a.out_start[lo] < bound) ++lo;
+            const uint32_t i = threadIdx.x * CI_RUN + k;
+            buf[i + (i >> 5)] = lo;
+        }
+        __syncthreads();
+        for (int k = 0; k < CI_RUN; ++k) {
+            const uint32_t i = k * CI_BLOCK + threadIdx.x;
+            if (cb + i <= cells) a.idx[cb + i] = buf[i + (i >> 5)];
+        }
+        __syncthreads();
+    }
 }
 
 __global__ void k_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n)
@@ -3728,7 +3750,7 @@ void launch_cut(const uint32_t *pyr, const CutArgs &chunks, const CutArgs &wcs, 
                                                                                       : wcs.ent_off[wcs.lam + 1];
     hipLaunchKernelGGL(k_cut_rank, dim3(grid_for(slots, 256, 2048), 2), dim3(256), 0, st, pyr, chunks, wcs);
     const uint64_t cells = (1ull << (3 * chunks.lt)) + 1;
-    hipLaunchKernelGGL(k_cut_index, dim3(grid_for(cells, 256, 2048), 2), dim3(256), 0, st, chunks, wcs);
+    hipLaunchKernelGGL(k_cut_index, dim3(grid_for(cells, CI_SPAN, 2048), 2), dim3(CI_BLOCK), 0, st, chunks, wcs);
 }
 
 
