@@ -143,7 +143,7 @@ struct Plan {
     CutPlan cp[2];   // chunk cut, work-chunk cut
     size_t cut_open[2], cut_ent[2], cut_st[2], cut_ctr[2], cut_idx[2];
     size_t c_count_scan, code_perm, wc_orig, wc_code, ms_temp, scan_temp, seg_b0, seg_nb, wc_nested, wc_chunk;
-    size_t gtab, t, fr, alive, alive_scan, kd, loff, owned, node_base, lnode_key, lnode_mask, cut;
+    size_t gtab, gtab2, t, fr, alive, alive_scan, kd, loff, owned, node_base, lnode_key, lnode_mask, cut;
     size_t big_list, big_nr, big_node, big_hkey, big_hval, cls_list;
     size_t np_tmp, np_glist, np_cnt, np_scan, np_nb, np_l0, np_l1, np_l2, np_l3, np_jobs, np_cp, np_single, pv_tiles, pv_offs,
         cellmin, pv_bits;
@@ -276,6 +276,7 @@ Plan make_plan(uint64_t n, const fpo_params &p, bool host_in = false)
     P.scan_temp = take(scan_temp_bytes(scan_max));
     // cells of the deepest globally decided depth (level d0 - 1 + s)
     P.gtab = P.d0 > 0 ? take(4ull << (3 * (P.d0 - 1 + P.s))) : 0;
+    P.gtab2 = P.d0 > 1 ? take(4ull << (3 * (P.d0 - 2 + P.s))) : 0;
     P.t = take(nn);
     P.fr = take(4 * nn);
     P.alive = take(4 * MAXD * P.maxW);
@@ -1054,10 +1055,10 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         FillSpec f[4];
         f[0] = {U32(P.kd), 0u, (uint64_t)MAXD * num_wc};
         f[1] = {reinterpret_cast<uint32_t *>(U8(P.t)), 0xffffffffu, (n + 3) / 4};
-        if (P.d0 > 0) f[2] = {U32(P.gtab), 0xffffffffu, 1ull << (3 * P.s)};
+        if (P.d0 > 0) f[2] = {global_depth_table(U32(P.gtab), U32(P.gtab2), P.d0, 0), 0xffffffffu, 1ull << (3 * P.s)};
         launch_fill_many(f, st);
     }
-    launch_global_depths(A, n, U32(P.gtab), st, true);
+    launch_global_depths(A, n, U32(P.gtab), U32(P.gtab2), st, true);
     // only the lists the counters read back show non-empty are launched; a
     // general-class work chunk whose table overflows LDS joins the
     // global-memory list, so that list runs whenever a general class does

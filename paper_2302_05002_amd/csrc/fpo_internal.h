@@ -305,10 +305,15 @@ struct WcArgs {
     int dmax;
 };
 // Shared depths d < d0 over all points (t filled with 0xff before): winners
-// get t = d, and the reaching-count rows of those depths are written.
-// gtab: 4 * 8^(d0 - 1 + s) bytes.
+// get t = d, and the reaching-count rows of those depths are written.  Two
+// cell tables alternate over the depths (the pass of depth d reads the table
+// of depth d - 1): depth d uses global_depth_table(gtab, gtab2, d0, d), so
+// gtab (4 * 8^(d0 - 1 + s) bytes) serves d0 - 1, d0 - 3, ... and gtab2
+// (4 * 8^(d0 - 2 + s) bytes, only when d0 >= 2) serves d0 - 2, d0 - 4, ...
 // first_filled: the table of depth 0 was cleared to all ones already.
-void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream_t st, bool first_filled = false);
+uint32_t *global_depth_table(uint32_t *gtab, uint32_t *gtab2, int d0, int d);
+void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, uint32_t *gtab2, hipStream_t st,
+                          bool first_filled = false);
 // lists[c] (host): number of work chunks in list c, 0 .. WC_CLASSES (the last:
 // the global-memory path), as counted by the cut; empty lists are skipped.
 void launch_subsample_small(const WcArgs &a, const uint32_t *lists, hipStream_t st);

@@ -1737,7 +1737,10 @@ void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, u
 // tentative depth is at or below the cut belong to that leaf.
 
 // Global shared depths d < d0, in work-chunk order.  Every alive point
-// (state 0xff) offers its original index to its cell of level d + s.  The
+// (state 0xff) offers its original index to its cell of level d + s; with
+// the table of depth d - 1 given (prev), a point first checks whether it
+// holds its cell's minimum there, and then stays at depth d - 1 instead (the
+// marking of depth d - 1 rides on this pass).  The
 // order is spatially coherent, so a tile of GD_TILE consecutive points falls
 // in few cells: the tile keeps the minimum of each of its cells in an LDS
 // hash table (at least twice as many slots as points, so it never fills),
@@ -1748,8 +1751,9 @@ constexpr uint32_t GD_TILE = GD_BLOCK * GD_ITEMS;   // 2048 points
 constexpr uint32_t GD_HASH = 2 * GD_TILE;           // slots
 __global__ __launch_bounds__(GD_BLOCK) void k_gdepth_min(const uint64_t *__restrict__ code,
                                                          const uint32_t *__restrict__ orig,
-                                                         const uint8_t *__restrict__ t, uint64_t n, int csh,
-                                                         uint32_t *gtab)
+                                                         uint8_t *__restrict__ t, uint64_t n, int csh,
+                                                         uint32_t *gtab, const uint32_t *__restrict__ prev,
+                                                         int csh_prev, int d_prev)
 {
     __shared__ uint32_t hk[GD_HASH], hv[GD_HASH];
     __shared__ uint16_t taken[GD_TILE];   // slots in use (at most one per point of the tile)
@@ -1767,9 +1771,15 @@ __global__ __launch_bounds__(GD_BLOCK) void k_gdepth_min(const uint64_t *__restr
 #pragma unroll
         for (int j = 0; j < GD_ITEMS; ++j) {
             const uint64_t q = tile * GD_TILE + (uint64_t)j * GD_BLOCK + threadIdx.x;
-            const bool alive = q < n && t[q] == 0xffu;
-            cell[j] = alive ? (uint32_t)(code[q] >> csh) : 0xffffffffu;
-            o[j] = alive ? orig[q] : 0xffffffffu;
+            bool alive = q < n && t[q] == 0xffu;
+            const uint64_t c = alive ? code[q] : 0ull;
+            const uint32_t oi = alive ? orig[q] : 0xffffffffu;
+            if (prev && alive && prev[c >> csh_prev] == oi) {   // the winner of its cell at depth d - 1
+                t[q] = (uint8_t)d_prev;
+                alive = false;
+            }
+            cell[j] = alive ? (uint32_t)(c >> csh) : 0xffffffffu;
+            o[j] = alive ? oi : 0xffffffffu;
         }
 #pragma unroll
         for (int j = 0; j < GD_ITEMS; ++j) {
@@ -1808,22 +1818,14 @@ __global__ __launch_bounds__(GD_BLOCK) void k_gdepth_min(const uint64_t *__restr
     }
 }
 
-// The winners of depth d: alive points holding their cell's minimum.
-__global__ void k_gdepth_mark(const uint64_t *__restrict__ code, const uint32_t *__restrict__ orig, uint8_t *t,
-                              uint64_t n, int csh, const uint32_t *gtab, int d)
-{
-    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (uint64_t)gridDim.x * blockDim.x) {
-        if (t[q] != 0xffu) continue;
-        if (gtab[code[q] >> csh] == orig[q]) t[q] = (uint8_t)d;
-    }
-}
-
 // Rows of the global shared depths: points of each WC alive at depth d < d0
-// (d0 = g - s <= 9), one block per WC: every thread counts its points placed
-// at each global depth, the block sums them in LDS.
+// (d0 = g - s <= 9), one block per WC: every thread marks the winners of the
+// last global depth (alive points holding their cell's minimum in `last`),
+// counts its points placed at each global depth, and the block sums them in
+// LDS.
 constexpr int AR_BLOCK = 256;
 constexpr int AR_MAXD0 = 10;   // global depths d < d0 <= 9
-__global__ __launch_bounds__(AR_BLOCK) void k_wc_alive_rows(WcArgs a)
+__global__ __launch_bounds__(AR_BLOCK) void k_wc_alive_rows(WcArgs a, const uint32_t *__restrict__ last, int csh_last)
 {
     __shared__ uint32_t placed[AR_MAXD0];
     const int d0 = a.d0 < AR_MAXD0 ? a.d0 : AR_MAXD0;
@@ -1835,7 +1837,11 @@ __global__ __launch_bounds__(AR_BLOCK) void k_wc_alive_rows(WcArgs a)
 #pragma unroll
         for (int d = 0; d < AR_MAXD0; ++d) c[d] = 0;
         for (uint32_t p = threadIdx.x; p < n; p += AR_BLOCK) {
-            const uint32_t t = a.t[base + p];
+            uint32_t t = a.t[base + p];
+            if (t == 0xffu && last[a.wc_code[base + p] >> csh_last] == a.wc_orig[base + p]) {
+                t = (uint32_t)(d0 - 1);
+                a.t[base + p] = (uint8_t)t;
+            }
 #pragma unroll
             for (int d = 0; d < AR_MAXD0; ++d) c[d] += t == (uint32_t)d ? 1u : 0u;
         }
@@ -3716,19 +3722,22 @@ void launch_grid_export(const uint32_t *fine, int g, uint32_t *out, hipStream_t 
 }
 
 
-void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, hipStream_t st, bool first_filled)
+uint32_t *global_depth_table(uint32_t *gtab, uint32_t *gtab2, int d0, int d) { return ((d0 - 1 - d) & 1) ? gtab2 : gtab; }
+
+void launch_global_depths(const WcArgs &a, uint64_t n, uint32_t *gtab, uint32_t *gtab2, hipStream_t st,
+                          bool first_filled)
 {
-    if (n == 0) return;
+    if (n == 0 || a.d0 == 0) return;
     for (int d = 0; d < a.d0; ++d) {
-        const int csh = 3 * (KB - d - a.s);
-        if (d > 0 || !first_filled) launch_fill_u32(gtab, 0xffffffffu, 1ull << (3 * (d + a.s)), st);
+        uint32_t *tab = global_depth_table(gtab, gtab2, a.d0, d);
+        const uint32_t *prev = d > 0 ? global_depth_table(gtab, gtab2, a.d0, d - 1) : nullptr;
+        if (d > 0 || !first_filled) launch_fill_u32(tab, 0xffffffffu, 1ull << (3 * (d + a.s)), st);
         hipLaunchKernelGGL(k_gdepth_min, dim3(grid_for(n, GD_TILE, 8192)), dim3(GD_BLOCK), 0, st, a.wc_code, a.wc_orig,
-                           a.t, n, csh, gtab);
-        hipLaunchKernelGGL(k_gdepth_mark, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, a.wc_code, a.wc_orig, a.t, n,
-                           csh, gtab, d);
+                           a.t, n, 3 * (KB - d - a.s), tab, prev, 3 * (KB - d + 1 - a.s), d - 1);
     }
-    if (a.d0 > 0 && a.num_wc > 0)
-        hipLaunchKernelGGL(k_wc_alive_rows, dim3(a.num_wc < 8192 ? a.num_wc : 8192), dim3(AR_BLOCK), 0, st, a);
+    // a work chunk holds at least one point, so every point is marked
+    hipLaunchKernelGGL(k_wc_alive_rows, dim3(a.num_wc < 8192 ? a.num_wc : 8192), dim3(AR_BLOCK), 0, st, a,
+                       global_depth_table(gtab, gtab2, a.d0, a.d0 - 1), 3 * (KB - (a.d0 - 1) - a.s));
 }
 
 void launch_cut(const uint32_t *pyr, const CutArgs &chunks, const CutArgs &wcs, hipStream_t st)
