@@ -1534,18 +1534,29 @@ struct MsLayout {
     uint64_t counts_words;
 };
 
+// With many buckets a tile's elements fall into short runs per bucket (344
+// chunks of 200M points: about six of a tile's 2048 per bucket), and the
+// scatter's writes, spread over hundreds of destinations per tile, ran at a
+// third of its rate with long runs.  Two stable passes by digits of half the
+// key bits (LSD order) keep the runs long: twice the bytes, still faster
+// (200M points, 344 chunks: the chunk split 5.6 -> 4.8 ms).
+constexpr uint32_t MS_TWO_PASS_BINS = 128;
+constexpr uint64_t MS_TWO_PASS_MIN_N = 1ull << 24;
+
 static MsLayout ms_layout(uint64_t n, uint32_t nbins)
 {
     MsLayout L{};
     L.tiles = div_up(n ? n : 1, MS_TILE);
     const uint32_t bits = ceil_log2(nbins);
-    if (nbins <= MS_ONE_PASS_BINS) {
+    const bool two = nbins >= MS_TWO_PASS_BINS && n >= MS_TWO_PASS_MIN_N;
+    if (nbins <= MS_ONE_PASS_BINS && !two) {
         L.passes = 1;
         L.dbits[0] = bits;
         L.nb[0] = nbins;
         L.shift[0] = 0;
     } else {
         L.passes = (bits + MS_DIGIT_BITS - 1) / MS_DIGIT_BITS;
+        if (L.passes < 2) L.passes = 2;
         const uint32_t per = (bits + L.passes - 1) / L.passes;
         uint32_t done = 0;
         for (uint32_t p = 0; p < L.passes; ++p) {
