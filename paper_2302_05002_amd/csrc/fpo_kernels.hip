@@ -495,6 +495,9 @@ __global__ __launch_bounds__(QB_BLOCK) void k_qz_bin_place(const uint64_t *__res
 }
 
 // One block per bin: its cells counted in LDS, its 2^15 counts written.
+// Sixteen loads per thread are issued before their atomics, so a bin's
+// points are not read one memory latency at a time.
+constexpr int QB_GRID_IT = 16;
 __global__ __launch_bounds__(1024) void k_qz_bin_grid(const uint16_t *__restrict__ cells,
                                                       const uint32_t *__restrict__ boff, uint32_t nblocks,
                                                       uint32_t nbins, uint64_t n, uint32_t *__restrict__ fine)
@@ -505,7 +508,17 @@ __global__ __launch_bounds__(1024) void k_qz_bin_grid(const uint16_t *__restrict
         __syncthreads();
         const uint32_t b0 = boff[(uint64_t)bin * nblocks];
         const uint32_t b1 = bin + 1 < nbins ? boff[(uint64_t)(bin + 1) * nblocks] : (uint32_t)n;
-        for (uint32_t j = b0 + threadIdx.x; j < b1; j += 1024) atomicAdd(&hist[cells[j]], 1u);
+        for (uint32_t j0 = b0; j0 < b1; j0 += 1024 * QB_GRID_IT) {
+            uint32_t c[QB_GRID_IT];
+#pragma unroll
+            for (int k = 0; k < QB_GRID_IT; ++k) {
+                const uint32_t j = j0 + (uint32_t)k * 1024 + threadIdx.x;
+                c[k] = j < b1 ? cells[j] : 0xffffffffu;
+            }
+#pragma unroll
+            for (int k = 0; k < QB_GRID_IT; ++k)
+                if (c[k] != 0xffffffffu) atomicAdd(&hist[c[k]], 1u);
+        }
         __syncthreads();
         uint32_t *dst = fine + ((uint64_t)bin << QB_CELL_BITS);
         for (uint32_t i = threadIdx.x; i < QB_CELLS; i += 1024) dst[i] = hist[i];

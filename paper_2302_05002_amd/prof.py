@@ -60,7 +60,8 @@ def _short(name: str) -> str:
 def attribute(names, chunk_passes: int = 1):
     """Region of every dispatch in `names` (kernel names in dispatch order),
     or None for runtime copies.  Transitions follow a build's launch order:
-    preview (counters' fill, preview kernels) -> bbox -> quantize -> cut
+    preview (counters' fill, preview kernels) -> bbox -> quantize (through
+    k_qz_bin_grid in the binned form) -> cut
     (through k_wc_segs) -> chunk_split (chunk_passes split passes) ->
     subsample -> node_counts (k_np_pieces .. k_np_count) -> node_place ->
     node_sort (from the first k_np_sort)."""
@@ -75,9 +76,9 @@ def attribute(names, chunk_passes: int = 1):
             state = "preview"
         elif state == "preview" and "k_bits_write" in prev:
             state = "bbox"
-        elif "k_quantize" in k:
+        elif "k_quantize" in k or "k_qz_bin" in k:
             state = "quantize"
-        elif state == "quantize":
+        elif state == "quantize" and ("k_quantize" in prev or "k_qz_bin_grid" in prev):
             state = "cut"
         elif state == "cut" and "k_wc_segs" in prev:
             state, left = "chunk_split", chunk_passes
