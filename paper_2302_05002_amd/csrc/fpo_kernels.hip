@@ -1848,6 +1848,7 @@ __global__ __launch_bounds__(GD_BLOCK) void k_gdepth_min(const uint64_t *__restr
 // counts its points placed at each global depth, and the block sums them in
 // LDS.
 constexpr int AR_BLOCK = 256;
+constexpr int AR_IT = 8;
 constexpr int AR_MAXD0 = 10;   // global depths d < d0 <= 9
 __global__ __launch_bounds__(AR_BLOCK) void k_wc_alive_rows(WcArgs a, const uint32_t *__restrict__ last, int csh_last)
 {
@@ -1860,14 +1861,34 @@ __global__ __launch_bounds__(AR_BLOCK) void k_wc_alive_rows(WcArgs a, const uint
         uint32_t c[AR_MAXD0];
 #pragma unroll
         for (int d = 0; d < AR_MAXD0; ++d) c[d] = 0;
-        for (uint32_t p = threadIdx.x; p < n; p += AR_BLOCK) {
-            uint32_t t = a.t[base + p];
-            if (t == 0xffu && last[a.wc_code[base + p] >> csh_last] == a.wc_orig[base + p]) {
-                t = (uint32_t)(d0 - 1);
-                a.t[base + p] = (uint8_t)t;
+        // AR_IT points per thread and round, each level of loads (state,
+        // then code and index, then the table) issued before it is used
+        for (uint32_t p0 = 0; p0 < n; p0 += AR_BLOCK * AR_IT) {
+            uint32_t t[AR_IT], oi[AR_IT], win[AR_IT];
+            uint64_t cd[AR_IT];
+#pragma unroll
+            for (int k = 0; k < AR_IT; ++k) {
+                const uint32_t p = p0 + (uint32_t)k * AR_BLOCK + threadIdx.x;
+                t[k] = p < n ? a.t[base + p] : 0xfeu;
             }
 #pragma unroll
-            for (int d = 0; d < AR_MAXD0; ++d) c[d] += t == (uint32_t)d ? 1u : 0u;
+            for (int k = 0; k < AR_IT; ++k) {
+                const uint32_t p = p0 + (uint32_t)k * AR_BLOCK + threadIdx.x;
+                cd[k] = t[k] == 0xffu ? a.wc_code[base + p] : 0ull;
+                oi[k] = t[k] == 0xffu ? a.wc_orig[base + p] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < AR_IT; ++k) win[k] = t[k] == 0xffu ? last[cd[k] >> csh_last] : 0xffffffffu;
+#pragma unroll
+            for (int k = 0; k < AR_IT; ++k) {
+                const uint32_t p = p0 + (uint32_t)k * AR_BLOCK + threadIdx.x;
+                if (t[k] == 0xffu && win[k] == oi[k]) {
+                    t[k] = (uint32_t)(d0 - 1);
+                    a.t[base + p] = (uint8_t)t[k];
+                }
+#pragma unroll
+                for (int d = 0; d < AR_MAXD0; ++d) c[d] += t[k] == (uint32_t)d ? 1u : 0u;
+            }
         }
 #pragma unroll
         for (int d = 0; d < AR_MAXD0; ++d) {
