@@ -2586,23 +2586,39 @@ __device__ __forceinline__ uint32_t wc_lower_bound(const uint64_t *start, uint32
     return lo;
 }
 
+// The depths of a work chunk in parallel: DC_LANES lanes per work chunk,
+// lane d finds the reaching count of its depth-d ancestor; a ballot gives
+// the first leaf (the cut), and lanes up to it replace their rows.  (Work
+// chunks sit at levels up to g <= 9, so they have at most nine shared depths.)
+constexpr int DC_LANES = 16;
 __global__ void k_decide(WcArgs a)
 {
     const uint32_t W = a.num_wc;
-    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
-        const int lw = a.wc_level[w];
-        const uint64_t key = a.wc_key[w];
-        int cut = lw;
-        for (int d = 0; d < lw; ++d) {
+    const uint32_t lane = lane_id();
+    const int d = (int)(lane & (DC_LANES - 1)), grp = (int)(lane / DC_LANES);
+    constexpr int PER_WAVE = 64 / DC_LANES;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t w0 = wave * PER_WAVE; w0 < W; w0 += nwaves * PER_WAVE) {
+        const uint32_t w = (uint32_t)w0 + (uint32_t)grp;
+        const bool valid = w < W;
+        const int lw = valid ? a.wc_level[w] : 0;
+        const bool mine = valid && d < lw;
+        uint32_t R = 0;
+        bool leaf = false;
+        if (mine) {
+            const uint64_t key = a.wc_key[w];
             const int sh = 3 * (a.lam_w - d);
             const uint64_t node_start = (key >> (3 * (lw - d))) << sh;
             const uint32_t lo = wc_lower_bound(a.wc_start, 0, w, node_start);
             const uint32_t hi = wc_lower_bound(a.wc_start, w + 1, W, node_start + (1ull << sh));
-            const uint32_t R = a.alive_scan[(uint64_t)d * W + hi] - a.alive_scan[(uint64_t)d * W + lo];
-            a.alive[(uint64_t)d * W + w] = R;
-            if (R <= a.L || d >= a.dmax) { cut = d; break; }
+            R = a.alive_scan[(uint64_t)d * W + hi] - a.alive_scan[(uint64_t)d * W + lo];
+            leaf = R <= a.L || d >= a.dmax;
         }
-        a.cut[w] = (uint8_t)cut;
+        const uint32_t leaves = (uint32_t)(__ballot(leaf) >> (grp * DC_LANES)) & ((1u << DC_LANES) - 1u);
+        const int cut = leaves ? __ffs((int)leaves) - 1 : lw;
+        if (mine && d <= cut) a.alive[(uint64_t)d * W + w] = R;
+        if (valid && d == 0) a.cut[w] = (uint8_t)cut;
     }
 }
 
@@ -3858,7 +3874,7 @@ void launch_subsample_big(const WcArgs &a, hipStream_t st)
 
 void launch_decide(const WcArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_decide, dim3(grid_for(a.num_wc, 256)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_decide, dim3(grid_for(a.num_wc, 256 / DC_LANES)), dim3(256), 0, st, a);
 }
 
 void launch_node_counts(const WcArgs &a, uint32_t *owned, hipStream_t st)
