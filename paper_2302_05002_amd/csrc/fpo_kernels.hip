@@ -1250,7 +1250,9 @@ __device__ __forceinline__ MsTile ms_tile(const MsArgs &A, uint32_t t)
 
 // Count pass: equal keys of a wave round are grouped by a ballot match and
 // added once (consecutive points usually share their chunk), so LDS atomics
-// do not pile up on one counter.
+// do not pile up on one counter.  The segmented split (work chunks inside a
+// chunk) adds each element on its own (20M planes: subsample region 0.532 ->
+// 0.518 ms).
 template <bool SEG, int IT = MS_ITEMS>
 __global__ __launch_bounds__(MS_BLOCK) void k_ms_count(MsArgs A)
 {
@@ -1272,8 +1274,14 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_count(MsArgs A)
         const uint64_t e = wlo + (uint64_t)r * 64 + lane;
         const bool valid = e < T.hi;
         const uint32_t key = valid ? ((full[r] >> A.shift) & dmask) - T.b0 : 0u;
-        const uint64_t peers = match_peers(key, valid, nbits);
-        if (valid && (peers & ((1ull << lane) - 1ull)) == 0) atomicAdd(&hist[key], (uint32_t)__popcll(peers));
+        if constexpr (SEG) {
+            // work-chunk keys in chunk order rarely repeat inside a round:
+            // one atomic per element is cheaper than the ballot match
+            if (valid) atomicAdd(&hist[key], 1u);
+        } else {
+            const uint64_t peers = match_peers(key, valid, nbits);
+            if (valid && (peers & ((1ull << lane) - 1ull)) == 0) atomicAdd(&hist[key], (uint32_t)__popcll(peers));
+        }
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < T.nb; b += MS_BLOCK)
