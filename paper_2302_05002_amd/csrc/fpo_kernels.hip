@@ -2402,7 +2402,8 @@ void k_subsample_fast(WcArgs a, int cls)
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t pos = j * BLOCK + threadIdx.x;
             const uint64_t c = a.wc_code[base + (pos < n ? pos : n - 1)];
-            const uint32_t st = a.t[base + (pos < n ? pos : n - 1)];   // alive, or placed at a global depth
+            // alive, or placed at a global depth (none without global depths)
+            const uint32_t st = a.d0 > 0 ? a.t[base + (pos < n ? pos : n - 1)] : 0xffu;
             it[j] = pos < n ? ((uint32_t)(c >> ksh) & kmask) | (st << 24) : 0u;
         }
         if (threadIdx.x < (uint32_t)MAXD) alive_at[threadIdx.x] = 0;
@@ -2485,14 +2486,13 @@ void k_subsample_fast(WcArgs a, int cls)
             A = block_sum2(surv, par);
             par ^= 1;
         }
-        // the rest sits in the root (a leaf) at depth lw
+        // the rest sits in the root (a leaf) at depth lw; ranks among own
+        // nodes (fr) are read only for work chunks with nodes below their
+        // root, so none is written here
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t pos = j * BLOCK + threadIdx.x;
-            if (pos < n) {
-                a.t[base + pos] = (uint8_t)(it[j] >= ALIVE ? (uint32_t)lw : it[j] >> 24);
-                a.fr[base + pos] = 0;
-            }
+            if (pos < n) a.t[base + pos] = (uint8_t)(it[j] >= ALIVE ? (uint32_t)lw : it[j] >> 24);
         }
         __syncthreads();
         if (threadIdx.x < (uint32_t)MAXD && (int)threadIdx.x >= a.d0) {   // rows above d0: the global pass
