@@ -369,12 +369,13 @@ typedef struct {
  * over a contiguous range of points and taking eight points per thread
  * between table flushes, or the first shape taking two points per thread
  * between flushes (the table then keeps up to 10K cells between flushes: for
- * count grids with few points per cell).  For device input with G = 256 or
- * 512 and at least 2^20 points also shape 4, the binned pass: codes and
- * per-block histograms of 2^15-cell bins of the grid's Morton order, each
- * point's cell put into its bin's range, then one workgroup per bin counting
- * in LDS and writing its part of the grid whole (no clearing).  Untuned
- * builds take shape 4 where it applies with G = 512, else shape 0.  Later
+ * count grids with few points per cell).  For device input of at least 2^16
+ * points and G >= 8 (and 256 points per bin or more) also shape 4, the
+ * binned pass: codes and per-block histograms of bins of the grid's Morton
+ * order (2^15 cells each from G = 256 on, else 64 bins), each point's cell
+ * put into its bin's range, then one workgroup per bin counting in LDS and
+ * writing its part of the grid whole (no clearing).  Untuned builds take
+ * shape 4 where it applies with G = 512, else shape 0.  Later
  * builds of the size class and count grid use the fastest.  workspace as for
  * fpo_build_submit; reps 1..100.  Blocks until done.  Not for the grid
  * preview (FPO_ERR_INVALID_ARG), which has one shape. */

@@ -110,11 +110,12 @@ void launch_setup(DevBox *box, const uint32_t *part, uint32_t nparts, int given,
 // input without the grid preview when quantize_binned_ok(n, g).
 constexpr int QZ_VARIANTS = 5;
 constexpr int QZ_BINNED = 4;
-constexpr uint64_t QB_MIN_POINTS = 1ull << 20;
+constexpr uint64_t QB_MIN_POINTS = 1ull << 16;
 void launch_quantize(const float *x, const float *y, const float *z, uint64_t n, const DevBox *box,
                      int g, int given, uint64_t *code, uint32_t *fine_cnt, DevBox *box_rw,
                      uint64_t base, uint64_t *cellmin, hipStream_t st, int variant);
-// Count grids of 2^24 and 2^27 cells (g = 8, 9) and at least 2^20 points.
+// G >= 8 and at least 2^16 points, and at least 256 points per bin (64 bins
+// up to G = 128, 512 at G = 256, 4096 at G = 512).
 bool quantize_binned_ok(uint64_t n, int g);
 // temp: quantize_binned_temp_bytes(g) bytes; cells: 2 B per point; scan_temp:
 // scan temporaries for 2^(3g - 15) * 256 values.  Writes every cell of the

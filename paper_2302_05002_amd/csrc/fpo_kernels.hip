@@ -374,18 +374,21 @@ __global__ __launch_bounds__(QZ_BLOCK) void k_quantize(const float *__restrict__
     }
 }
 
-// Binned form of the pass (variant QZ_BINNED) for count grids of 2^24 cells
-// and more, where the per-cell atomics of the table form land all over a
-// grid larger than the last-level cache (G = 512: 512 MiB) at a few tens of
-// G atomics/s.  The grid's Morton order falls into bins of 2^15 cells; one
-// pass writes the codes and each block's histogram of bins, a scan of the
-// histograms (bin-major) gives every (bin, block) its range, a second pass
-// puts the 15 low bits of each point's cell into its bin's range, and one
-// block per bin counts its cells in LDS and writes its 2^15 counts whole, so
-// the grid needs no clearing.  Counts are sums: the order in which a bin's
-// points are placed does not matter.
-constexpr int QB_CELL_BITS = 15;
-constexpr uint32_t QB_CELLS = 1u << QB_CELL_BITS;   // 128 KB of LDS counters
+// Binned form of the pass (variant QZ_BINNED), for clouds whose points
+// mostly fall in cells of their own, where the table form flushes about one
+// global atomic per point (the uniform cube), and for count grids of 2^24
+// cells and more, where those atomics land all over a grid larger than the
+// last-level cache (G = 512: 512 MiB) at a few tens of G atomics/s.  The
+// grid's Morton order falls into bins of 2^cb cells (cb = qb_cell_bits(g):
+// 2^15 from G = 256 on, else 64 bins); one pass writes the codes and each
+// block's histogram of bins, a scan of the histograms (bin-major) gives every
+// (bin, block) its range, a second pass puts the cb low bits of each point's
+// cell into its bin's range, and one block per bin counts its cells in LDS
+// and writes its counts whole, so the grid needs no clearing.  Counts are
+// sums: the order in which a bin's points are placed does not matter.
+constexpr int QB_MAX_CELL_BITS = 15;
+constexpr uint32_t QB_CELLS = 1u << QB_MAX_CELL_BITS;   // 128 KB of LDS counters
+__host__ __device__ constexpr int qb_cell_bits(int g) { return 3 * g - 6 < QB_MAX_CELL_BITS ? 3 * g - 6 : QB_MAX_CELL_BITS; }
 constexpr uint32_t QB_MAX_BINS = 4096;              // G = 512
 constexpr int QB_BLOCK = 1024, QB_IT = 8;
 constexpr uint32_t QB_BLOCKS = 256;                 // one range of points per compute unit
@@ -399,7 +402,8 @@ __global__ __launch_bounds__(QB_BLOCK) void k_qz_bin_code(const float *__restric
     constexpr uint32_t ROUND = QB_BLOCK * QB_IT;
     __shared__ uint32_t hist[QB_MAX_BINS];
     __shared__ uint32_t wsum[QB_BLOCK / 64];
-    const uint32_t nbins = 1u << (3 * g - QB_CELL_BITS);
+    const int cb = qb_cell_bits(g);
+    const uint32_t nbins = 1u << (3 * g - cb);
     for (uint32_t b = threadIdx.x; b < nbins; b += QB_BLOCK) hist[b] = 0;
     const uint64_t lo = (uint64_t)blockIdx.x * per_block;
     const uint32_t cnt = (uint32_t)((lo + per_block < n ? lo + per_block : n) - lo);
@@ -415,7 +419,7 @@ __global__ __launch_bounds__(QB_BLOCK) void k_qz_bin_code(const float *__restric
     }
     const float lx = box->lo[0], ly = box->lo[1], lz = box->lo[2], sc = box->scale;
     const float hx = box->hi[0], hy = box->hi[1], hz = box->hi[2];
-    const int bsh = 3 * (KB - g) + QB_CELL_BITS;
+    const int bsh = 3 * (KB - g) + cb;
     __syncthreads();
     uint32_t outside = 0;
     bool bad = false;
@@ -469,7 +473,8 @@ __global__ __launch_bounds__(QB_BLOCK) void k_qz_bin_place(const uint64_t *__res
 {
     constexpr uint32_t ROUND = QB_BLOCK * QB_IT;
     __shared__ uint32_t fill[QB_MAX_BINS];
-    const uint32_t nbins = 1u << (3 * g - QB_CELL_BITS);
+    const int cb = qb_cell_bits(g);
+    const uint32_t nbins = 1u << (3 * g - cb);
     for (uint32_t b = threadIdx.x; b < nbins; b += QB_BLOCK) fill[b] = boff[(uint64_t)b * gridDim.x + blockIdx.x];
     __syncthreads();
     const uint64_t lo = (uint64_t)blockIdx.x * per_block;
@@ -488,23 +493,25 @@ __global__ __launch_bounds__(QB_BLOCK) void k_qz_bin_place(const uint64_t *__res
             const uint32_t o = r0 + (uint32_t)j * QB_BLOCK + threadIdx.x;
             if (o >= cnt) continue;
             const uint32_t cell = (uint32_t)(c[j] >> csh);
-            const uint32_t slot = atomicAdd(&fill[cell >> QB_CELL_BITS], 1u);
-            cells[slot] = (uint16_t)(cell & (QB_CELLS - 1u));
+            const uint32_t slot = atomicAdd(&fill[cell >> cb], 1u);
+            cells[slot] = (uint16_t)(cell & ((1u << cb) - 1u));
         }
     }
 }
 
-// One block per bin: its cells counted in LDS, its 2^15 counts written.
+// One block per bin: its cells counted in LDS, its 2^cb counts written.
 // Sixteen loads per thread are issued before their atomics, so a bin's
 // points are not read one memory latency at a time.
 constexpr int QB_GRID_IT = 16;
 __global__ __launch_bounds__(1024) void k_qz_bin_grid(const uint16_t *__restrict__ cells,
                                                       const uint32_t *__restrict__ boff, uint32_t nblocks,
-                                                      uint32_t nbins, uint64_t n, uint32_t *__restrict__ fine)
+                                                      uint32_t nbins, int cb, uint64_t n,
+                                                      uint32_t *__restrict__ fine)
 {
     __shared__ uint32_t hist[QB_CELLS];
+    const uint32_t cells_per_bin = 1u << cb;
     for (uint32_t bin = blockIdx.x; bin < nbins; bin += gridDim.x) {
-        for (uint32_t i = threadIdx.x; i < QB_CELLS; i += 1024) hist[i] = 0;
+        for (uint32_t i = threadIdx.x; i < cells_per_bin; i += 1024) hist[i] = 0;
         __syncthreads();
         const uint32_t b0 = boff[(uint64_t)bin * nblocks];
         const uint32_t b1 = bin + 1 < nbins ? boff[(uint64_t)(bin + 1) * nblocks] : (uint32_t)n;
@@ -520,8 +527,8 @@ __global__ __launch_bounds__(1024) void k_qz_bin_grid(const uint16_t *__restrict
                 if (c[k] != 0xffffffffu) atomicAdd(&hist[c[k]], 1u);
         }
         __syncthreads();
-        uint32_t *dst = fine + ((uint64_t)bin << QB_CELL_BITS);
-        for (uint32_t i = threadIdx.x; i < QB_CELLS; i += 1024) dst[i] = hist[i];
+        uint32_t *dst = fine + ((uint64_t)bin << cb);
+        for (uint32_t i = threadIdx.x; i < cells_per_bin; i += 1024) dst[i] = hist[i];
         __syncthreads();
     }
 }
@@ -3738,11 +3745,16 @@ void launch_quantize(const float *x, const float *y, const float *z, uint64_t n,
                            fine_cnt, box_rw, per, base, cm);
 }
 
-bool quantize_binned_ok(uint64_t n, int g) { return g >= 8 && g <= 9 && n >= QB_MIN_POINTS; }
+// 64 bins or more, and no more (bin, block) histogram words than points (the
+// scan's temporaries are sized by n)
+bool quantize_binned_ok(uint64_t n, int g)
+{
+    return g >= 3 && g <= 9 && n >= QB_MIN_POINTS && n >= (1ull << (3 * g - qb_cell_bits(g))) * QB_BLOCKS;
+}
 
 size_t quantize_binned_temp_bytes(int g)
 {
-    const uint64_t words = (1ull << (3 * g - QB_CELL_BITS)) * QB_BLOCKS;
+    const uint64_t words = (1ull << (3 * g - qb_cell_bits(g))) * QB_BLOCKS;
     return 2 * ((4 * words + 255) & ~(size_t)255);
 }
 
@@ -3754,7 +3766,8 @@ void launch_quantize_binned(const float *x, const float *y, const float *z, uint
     uint64_t per = (n + QB_BLOCKS - 1) / QB_BLOCKS;
     per = (per + 63) / 64 * 64;
     const uint32_t grid = (uint32_t)((n + per - 1) / per);
-    const uint32_t nbins = 1u << (3 * g - QB_CELL_BITS);
+    const int cb = qb_cell_bits(g);
+    const uint32_t nbins = 1u << (3 * g - cb);
     const uint64_t words = (uint64_t)nbins * grid;
     uint32_t *bhist = static_cast<uint32_t *>(temp);
     uint32_t *boff = bhist + (((4 * (uint64_t)nbins * QB_BLOCKS + 255) & ~255ull) / 4);
@@ -3763,7 +3776,7 @@ void launch_quantize_binned(const float *x, const float *y, const float *z, uint
     scan_exclusive(bhist, boff, words, nullptr, scan_temp, st);
     hipLaunchKernelGGL(k_qz_bin_place, dim3(grid), dim3(QB_BLOCK), 0, st, code, n, g, boff, cells, per);
     hipLaunchKernelGGL(k_qz_bin_grid, dim3(nbins < 1024 ? nbins : 1024), dim3(1024), 0, st, cells, boff, grid, nbins,
-                       n, fine_cnt);
+                       cb, n, fine_cnt);
 }
 
 void launch_pyramid(uint32_t *pyr, int g, uint32_t *exp_out, hipStream_t st)

@@ -1,7 +1,7 @@
 """The autotuner's candidates change speed only: every shape of the quantise
 + count pass gives the oracle's result bit for bit (device and streamed
 inputs, computed and given boxes, scans and uniform clouds, the binned shape
-at G = 256 and 512 with a given box that leaves points outside), the tuner keeps
+from G = 32 to 512, with a given box that leaves points outside), the tuner keeps
 its choice in the context and in the FPO_AUTOTUNE_CACHE file, and the batch
 tuner's worker counts give identical batches."""
 import os
@@ -88,7 +88,8 @@ def test_binned_shape_edges():
 
 
 def test_autotune_with_the_binned_shape():
-    """At G = 512 and 2^20 points or more the tuner times five shapes."""
+    """At G = 512 and 2^20 points or more the tuner times five shapes; below
+    2^16 points the binned one is not a candidate."""
     import torch
     import paper_2302_05002_amd as fpo
     c = synth.planes(1_100_000, seed=37, num_planes=60)
@@ -100,6 +101,10 @@ def test_autotune_with_the_binned_shape():
         assert len(t["quantize_ms"]) == fpo.QUANTIZE_VARIANTS and all(ms > 0 for ms in t["quantize_ms"])
         assert t["quantize_ms"][t["quantize_variant"]] == min(t["quantize_ms"])
         compare(ctx.build(*dev, fpo.Params(*case)).to_numpy(), _oracle(c, *case), label="tuned at G = 512: ")
+        small = synth.uniform(60_000, seed=38)
+        dev = [torch.from_numpy(a).cuda() for a in (small.x, small.y, small.z)]
+        t = ctx.autotune(*dev, fpo.Params(64, 100_000, 32, 1_000, 8), reps=1)
+        assert len(t["quantize_ms"]) == fpo.QUANTIZE_VARIANTS - 1
     finally:
         ctx.close()
 
@@ -117,8 +122,8 @@ def test_autotune_keeps_and_stores_its_choice(tmp_path):
         try:
             dev = [torch.from_numpy(a).cuda() for a in (c.x, c.y, c.z)]
             t = ctx.autotune(*dev, fpo.Params(*case), reps=2)
-            assert t["quantize_variant"] in range(fpo.QUANTIZE_VARIANTS - 1)
-            assert len(t["quantize_ms"]) == fpo.QUANTIZE_VARIANTS - 1   # no binned shape at G = 64
+            assert t["quantize_variant"] in range(fpo.QUANTIZE_VARIANTS)
+            assert len(t["quantize_ms"]) == fpo.QUANTIZE_VARIANTS   # the binned shape too (64 bins)
             assert all(ms > 0 for ms in t["quantize_ms"])
             assert t["size_class"] == 18 and t["count_grid_log2"] == 6   # 2^18 <= 400k < 2^19
             assert t["quantize_ms"][t["quantize_variant"]] == min(t["quantize_ms"])
