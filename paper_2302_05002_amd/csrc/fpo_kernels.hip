@@ -3006,10 +3006,12 @@ __global__ void k_np_copy(const uint64_t *list, const uint32_t *list_cnt, const 
 
 // One wave per work chunk: every point into its node's range.  Where one
 // offset places a depth's points (a piece of a shared node, or the own root),
-// positions are handed out from it in registers: lane d holds depth d's next
-// position, and each distinct depth of a row of 64 points is one ballot.
-// Points of own nodes below a subdivided root take theirs from global fill
-// counters (zeroed before).
+// positions are handed out from it: the wave keeps depth d's next position in
+// LDS, a row of 64 points groups its lanes by depth with a ballot match over
+// the depth's five bits, each lane takes the group's base plus its rank in
+// the group (so a piece keeps the row order), and the group's first lane
+// advances the base.  Points of own nodes below a subdivided root take
+// theirs from global fill counters (zeroed before).
 constexpr int NPP_ITEMS = 8;    // positions per lane and step (measured: 4, 16 and 32 slower)
 constexpr int NPP_WAVES = 4;
 
@@ -3017,18 +3019,23 @@ __global__ __launch_bounds__(64 * NPP_WAVES) void k_np_place(WcArgs a, const uin
                                                              const uint32_t *poff, const uint32_t *nb, uint32_t *fill,
                                                              uint32_t *out, uint32_t n_total, uint32_t *err)
 {
+    static_assert(MAXD <= 32, "depths fit five bits");
+    __shared__ uint32_t nxt_all[NPP_WAVES][MAXD];
     const uint32_t lane = lane_id();
     const uint64_t below = (1ull << lane) - 1ull;
     const uint32_t W = a.num_wc;
+    uint32_t *nxt = nxt_all[threadIdx.x >> 6];   // this wave's next position per depth
     for (uint32_t w = blockIdx.x * NPP_WAVES + (threadIdx.x >> 6); w < W; w += gridDim.x * NPP_WAVES) {
         const int lw = a.wc_level[w], cut = a.cut[w];
         const uint32_t base = a.wc_begin[w], n = a.wc_count[w];
-        uint32_t next = NP_NONE;   // lane d < MAXD: next position of depth d
+        uint32_t next = NP_NONE;   // lane d < MAXD: first position of depth d
         if (lane < (uint32_t)MAXD) {
             const uint64_t i = (uint64_t)lane * W + w;
             const uint32_t node = pnode[i];
             if (node != NP_NONE) next = nb[node] + poff[i];
+            nxt[lane] = next;
         }
+        __builtin_amdgcn_wave_barrier();
         // own nodes below a subdivided root (their points find no offset)
         const bool general = cut == lw && (uint32_t)__builtin_amdgcn_readlane((int)next, lw) == NP_NONE;
         bool bad = false;
@@ -3047,19 +3054,13 @@ __global__ __launch_bounds__(64 * NPP_WAVES) void k_np_place(WcArgs a, const uin
                 bad |= p < n && t >= MAXD;   // never placed: an internal error
                 const bool ok = p < n && t < MAXD;
                 t = np_final_depth(ok ? t : 0, lw, cut);
-                uint32_t dst = NP_NONE;
-                uint64_t todo = __ballot(ok);
-                while (todo) {
-                    const int leader = __ffsll((long long)todo) - 1;
-                    const int k = __builtin_amdgcn_readlane(t, leader);
-                    const uint64_t m = __ballot(ok && t == k);
-                    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)next, k);
-                    if (b != NP_NONE) {
-                        dst = (ok && t == k) ? b + (uint32_t)__popcll(m & below) : dst;
-                        next += (int)lane == k ? (uint32_t)__popcll(m) : 0u;
-                    }
-                    todo &= ~m;
-                }
+                const uint64_t peers = match_peers((uint32_t)t, ok, 5);
+                const uint32_t rank = (uint32_t)__popcll(peers & below);
+                const uint32_t b = ok ? nxt[t] : NP_NONE;
+                __builtin_amdgcn_wave_barrier();
+                if (ok && rank == 0 && b != NP_NONE) nxt[t] = b + (uint32_t)__popcll(peers);
+                __builtin_amdgcn_wave_barrier();
+                uint32_t dst = (ok && b != NP_NONE) ? b + rank : NP_NONE;
                 if (general && ok && dst == NP_NONE && t >= lw) {
                     const uint32_t id = node_base[(uint64_t)t * W + w] + a.fr[base + p];
                     dst = nb[id] + atomicAdd(&fill[id], 1u);
