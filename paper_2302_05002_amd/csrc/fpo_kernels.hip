@@ -1907,8 +1907,7 @@ __global__ __launch_bounds__(AR_BLOCK) void k_wc_alive_rows(WcArgs a, const uint
         }
 #pragma unroll
         for (int d = 0; d < AR_MAXD0; ++d) {
-            if (d >= d0) break;
-            const uint32_t s = wave_sum(c[d]);
+            const uint32_t s = d < d0 ? wave_sum(c[d]) : 0u;
             if (lane_id() == 0 && s) atomicAdd(&placed[d], s);
         }
         __syncthreads();
