@@ -28,6 +28,9 @@ WORKLOADS = {
     # name: (generator, params attribute, description)
     "planes20m": ("config2", "CONFIG2", "20M points on 200 planes, G=128, C=1M, S=128, L=10k, M=64"),
     "uniform1m": ("config1", "CONFIG1", "1M uniform points, G=64, C=100k, S=32, L=10k, M=64"),
+    # the out-of-core workload built from device memory (profiling of the G = 512 path)
+    "terrain200m": ("config3", "CONFIG3", "200M points of terrain and clusters in device memory, G=512, C=2M, S=128, "
+                                          "L=10k, M=64"),
 }
 
 

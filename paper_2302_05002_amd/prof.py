@@ -57,12 +57,18 @@ def _short(name: str) -> str:
     return name.split("(")[0].replace("void ", "").strip()
 
 
-def attribute(names, chunk_passes: int = 1):
+# kernels of the chunk split (its passes and scans); the first other kernel
+# after it begins the subsample region
+CHUNK_SPLIT_KERNELS = ("k_ms_count<false", "k_ms_scatter<false", "k_scan_", "k_u32_to_u64", "k_fill_u32")
+
+
+def attribute(names, chunk_passes: int = 0):
     """Region of every dispatch in `names` (kernel names in dispatch order),
     or None for runtime copies.  Transitions follow a build's launch order:
     preview (counters' fill, preview kernels) -> bbox -> quantize (through
     k_qz_bin_grid in the binned form) -> cut
-    (through k_wc_segs) -> chunk_split (chunk_passes split passes) ->
+    (through k_wc_segs) -> chunk_split (its count, scan and scatter kernels, in
+    one or two passes; with chunk_passes > 0, exactly that many scatters) ->
     subsample -> node_counts (k_np_pieces .. k_np_count) -> node_place ->
     node_sort (from the first k_np_sort)."""
     out = []
@@ -82,7 +88,8 @@ def attribute(names, chunk_passes: int = 1):
             state = "cut"
         elif state == "cut" and "k_wc_segs" in prev:
             state, left = "chunk_split", chunk_passes
-        elif state == "chunk_split" and left == 0:
+        elif state == "chunk_split" and (left == 0 if chunk_passes else
+                                         not any(c in k for c in CHUNK_SPLIT_KERNELS)):
             state = "subsample"
         elif "k_np_pieces" in k:
             state = "node_counts"
@@ -114,7 +121,7 @@ def _builds(names) -> int:
     return sum(1 for k in names if "k_preview_bits" in k)
 
 
-def trace_groups(path: str, chunk_passes: int = 1):
+def trace_groups(path: str, chunk_passes: int = 0):
     """(region -> (ms per build, kernels per build)), builds, from a kernel trace."""
     rows = list(csv.DictReader(open(path)))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
@@ -144,7 +151,7 @@ def _dispatches(path: str, counter: str):
     return [(names[d], acc[d]) for d in sorted(acc)]
 
 
-def groups_per_build(path: str, counter: str, chunk_passes: int = 1):
+def groups_per_build(path: str, counter: str, chunk_passes: int = 0):
     """Per build, the counter summed over each region (averaged over builds)."""
     seq = _dispatches(path, counter)
     names = [k for k, _ in seq]
@@ -157,7 +164,7 @@ def groups_per_build(path: str, counter: str, chunk_passes: int = 1):
     return {k: v / nb for k, v in sums.items()}, nb
 
 
-def traffic(fetch_csv: str, write_csv: str, workload: str, out_json: str, chunk_passes: int = 1):
+def traffic(fetch_csv: str, write_csv: str, workload: str, out_json: str, chunk_passes: int = 0):
     f, nf = groups_per_build(fetch_csv, "FETCH_SIZE", chunk_passes)
     w, nw = groups_per_build(write_csv, "WRITE_SIZE", chunk_passes)
     data = {"read_factor": READ_FACTOR, "write_factor": WRITE_FACTOR, "unit": "KiB per build", "kernels": {}}

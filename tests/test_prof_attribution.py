@@ -1,8 +1,9 @@
 """The profiler helper's attribution of kernel dispatches to the library's
 timed regions (paper_2302_05002_amd/prof.py), which the traffic summaries
 and `roofline.traffic` rest on: one 20M-point build as the trace lists it,
-the same build with the binned quantise pass, and with a two-pass chunk
-split.  Runtime copies belong to no region."""
+the same build with the binned quantise pass, with a two-pass chunk split
+(found from the kernel names, or from a given number of passes) and with the
+one-pass form.  Runtime copies belong to no region."""
 from paper_2302_05002_amd import prof
 
 # (region, kernel) of one build of the 20M-point planes workload, in launch order
@@ -35,7 +36,7 @@ def _names(build):
     return [f"void fpo::{k}(WcArgs)" for _, k in build]
 
 
-def _check(build, chunk_passes=1):
+def _check(build, chunk_passes=0):
     got = prof.attribute(_names(build) * 2, chunk_passes)
     assert got == [r for r, _ in build] * 2
 
@@ -64,3 +65,13 @@ def test_two_pass_chunk_split():
     second = [("chunk_split", "k_ms_count<false, 8>"), ("chunk_split", "k_scan_reduce"),
               ("chunk_split", "k_scan_down<true>"), ("chunk_split", "k_ms_scatter<false, 8, false>")]
     _check(BUILD[:i + 4] + second + BUILD[i + 4:], chunk_passes=2)
+    _check(BUILD[:i + 4] + second + BUILD[i + 4:])   # found without the count
+
+
+def test_one_pass_chunk_split():
+    """The look-back form: a fill and one scatter, no counting pass."""
+    i = BUILD.index(("chunk_split", "k_ms_count<false, 8>"))
+    one = BUILD[:i - 4] + [("chunk_split", "k_scan_pair"), ("chunk_split", "k_fill_u32"),
+                           ("chunk_split", "k_ms_scatter<false, 8, true>")] + BUILD[i + 4:]
+    _check(one)
+    _check(one, chunk_passes=1)
