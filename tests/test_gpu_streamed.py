@@ -77,11 +77,22 @@ def test_streamed_rejects_pageable(ctx):
 def test_config3_full(ctx):
     """The 200M-point terrain workload as the benchmark runs it: pinned host
     input in 16M-point batches, the exact box given as a header, every output
-    compared with the oracle."""
+    compared with the oracle; then the same build from device memory (the
+    binned count, the default at G = 512, and the two-pass chunk split),
+    compared with the streamed one."""
+    import torch
+    import paper_2302_05002_amd as fpo
     p = synth.CONFIG3
     c = synth.config3()
-    streamed_vs_oracle(ctx, c, p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity,
-                       p.preview_modulus, exact_box(c), 16_000_000, "config3: ")
+    box = exact_box(c)
+    got = streamed_vs_oracle(ctx, c, p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity,
+                             p.preview_modulus, box, 16_000_000, "config3: ")
+    print("[streamed] config3 from device memory", flush=True)
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (c.x, c.y, c.z)]
+    res = ctx.build(*dev, fpo.Params(p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity,
+                                     p.preview_modulus, box)).to_numpy()
+    for k in got:
+        assert np.array_equal(np.asarray(res[k]), np.asarray(got[k])), f"config3 resident: {k} differs"
 
 
 def test_streamed_nonfinite_with_given_box(ctx):
