@@ -285,8 +285,6 @@ typedef struct {
     uint64_t workspace_bytes;     /* the build's worst-case plan (what fpo_workspace_size_cloud returns) */
     uint64_t submitted_ns, started_ns, completed_ns;   /* as fpo_job_timestamps */
     float region_ms[16];          /* device ms of each fpo_timer region when the job was timed, else -1 */
-    uint32_t node_points_by_chunk; /* 1 when node_points came from the split of perm order by chunk
-                                      (fpo_context_set_node_points_by_chunk), 0 otherwise */
 } fpo_job_stats;
 
 /* Fills *out for a completed job (after fpo_job_wait returned FPO_OK); reads
@@ -413,18 +411,6 @@ fpo_status fpo_context_force_quantize_variant(fpo_context *ctx, int variant);
  * turns the path off.  The results are those of the multi-kernel path, in
  * the same workspace. */
 fpo_status fpo_context_set_single_block_max(fpo_context *ctx, uint32_t plain_max, uint32_t batch_max);
-
-/* How node_points is produced (step 4's per-node point lists, "Octree
- * Construction": every node's points in ascending original index).  With
- * enable = 1 (the default) a build whose work chunks each lie inside one chunk
- * (always so when max_points_per_chunk >= 4096) splits perm order stably
- * by node, chunk by chunk: a chunk's part of perm order ascends, so every node
- * inside one chunk is final after that split, and only the nodes spanning
- * several chunks (their ancestors) are sorted.  A chunk may hold points of at
- * most 2048 nodes for this; else, and with enable = 0, every point is placed in
- * work-chunk order and the ranges are sorted.  Both give the same result;
- * fpo_job_stats.node_points_by_chunk tells which one ran. */
-fpo_status fpo_context_set_node_points_by_chunk(fpo_context *ctx, int enable);
 
 /* ---- kernel timing (for benchmarks) ----------------------------------------
  * With timing enabled on a context, every later submit of it brackets each

@@ -36,8 +36,7 @@ EXPORTS = ("fpo_context_create", "fpo_context_destroy", "fpo_last_error", "fpo_w
            "fpo_preview_modulus", "fpo_las_parse_header", "fpo_las_header_box", "fpo_las_decode",
            "fpo_select_workspace_size", "fpo_select_nodes", "fpo_select_nodes_static",
            "fpo_job_get_stats", "fpo_context_set_batch_workers", "fpo_autotune", "fpo_autotune_batch",
-           "fpo_context_force_quantize_variant", "fpo_context_set_single_block_max",
-           "fpo_context_set_node_points_by_chunk")
+           "fpo_context_force_quantize_variant", "fpo_context_set_single_block_max")
 #: fpo_select_nodes_static's limits (include/fpo.h)
 SELECT_STATIC_MAX_NODES = 4194304
 SELECT_STATIC_BYTES = 655360
@@ -108,7 +107,7 @@ class _Stats(ctypes.Structure):
                 ("n_outside", ctypes.c_uint64), ("preview_count", ctypes.c_uint64),
                 ("workspace_bytes", ctypes.c_uint64), ("submitted_ns", ctypes.c_uint64),
                 ("started_ns", ctypes.c_uint64), ("completed_ns", ctypes.c_uint64),
-                ("region_ms", ctypes.c_float * 16), ("node_points_by_chunk", ctypes.c_uint32)]
+                ("region_ms", ctypes.c_float * 16)]
 
 
 class _Tuning(ctypes.Structure):
@@ -213,8 +212,6 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fpo_context_set_batch_workers.restype = ctypes.c_int
     lib.fpo_context_set_single_block_max.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32]
     lib.fpo_context_set_single_block_max.restype = ctypes.c_int
-    lib.fpo_context_set_node_points_by_chunk.argtypes = [vp, ctypes.c_int]
-    lib.fpo_context_set_node_points_by_chunk.restype = ctypes.c_int
     lib.fpo_autotune.argtypes = [vp, P(_Cloud), P(_Params), vp, u64, ctypes.c_uint32, P(_Tuning)]
     lib.fpo_autotune.restype = ctypes.c_int
     lib.fpo_autotune_batch.argtypes = [vp, P(_Cloud), P(_Params), ctypes.c_uint32, vp, u64, ctypes.c_uint32,
@@ -509,12 +506,6 @@ class Context:
         limits, are built by one workgroup in one launch; 0 turns that off."""
         bm = plain_max if batch_max is None else batch_max
         _check(_lib.fpo_context_set_single_block_max(self._h, int(plain_max), int(bm)))
-
-    def set_node_points_by_chunk(self, enable: bool):
-        """node_points by a split of perm order chunk by chunk where a build
-        allows it (True, the default), or always by placement in work-chunk
-        order and sorts (False); the results are the same."""
-        _check(_lib.fpo_context_set_node_points_by_chunk(self._h, 1 if enable else 0))
 
     def build_batch(self, clouds, params, workspace=None, stream=None) -> list:
         """Enqueue one build per (x, y, z) device-tensor triple in `clouds`,

@@ -987,46 +987,6 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         multisplit(in, n, num_chunks, o, ws + P.ms_temp, st);
     }
     t_chunk.end(st);
-    // node_points by chunk (split of perm order by node, chunk by chunk) needs
-    // every work chunk inside one chunk and its tables to fit the codes'
-    // region (free once the subsample is done); the node and bucket counts
-    // decide after the next read-back.  The work-chunk split leaves every
-    // perm position's place in work-chunk order in the node begins' output,
-    // which is written last.
-    const bool segmented = hctrs->wc_flags[0] == 0 && hctrs->wc_flags[1] == 0;
-    bool big = hctrs->lists_pre[WC_CLASSES] != 0;
-    for (int k = WC_GENERAL; k < WC_CLASSES; ++k) big = big || hctrs->lists_pre[k] != 0;
-    NpcTables npc{};
-    size_t npc_split_off = 0, npc_region = 0;
-    uint64_t npc_cap_buckets = 0;
-    bool npc_try = false;
-    if (segmented && n > 0 && num_wc > 0 && num_chunks > 0 && job->ctx->np_by_chunk.load()) {
-        const size_t nn = n;
-        npc_region = (P.code_perm - P.code) + ((8 * nn + 255) & ~(size_t)255);
-        const uint64_t pairs = (uint64_t)MAXD * num_chunks;
-        npc_cap_buckets = (uint64_t)num_chunks * MS_MAX_BINS;
-        if (npc_cap_buckets > nn + pairs) npc_cap_buckets = nn + pairs;
-        size_t o = 0;
-        auto take = [&](size_t bytes) {
-            const size_t r = o;
-            o += (bytes + 255) & ~(size_t)255;
-            return r;
-        };
-        char *r0 = ws + P.code;
-        npc.nch = num_chunks;
-        npc.first = reinterpret_cast<uint32_t *>(r0 + take(4 * pairs));
-        npc.last = reinterpret_cast<uint32_t *>(r0 + take(4 * pairs));
-        npc.loff = reinterpret_cast<uint32_t *>(r0 + take(4 * pairs));
-        npc.cells = reinterpret_cast<uint32_t *>(r0 + take(4 * pairs));
-        npc.cellb = reinterpret_cast<uint32_t *>(r0 + take(4 * pairs));
-        npc.bucket_cell = reinterpret_cast<uint32_t *>(r0 + take(4 * npc_cap_buckets));
-        npc.nbk = U32(P.seg_nb);   // the work-chunk split's segments are read by then
-        npc.b0 = U32(P.seg_b0);
-        npc.c_count = U32(P.c_count);
-        npc.wc_chunk = U32(P.wc_chunk);
-        npc_split_off = o;
-        npc_try = o < npc_region / 2;
-    }
     // work-chunk order from perm order: chunk by chunk when every work chunk
     // lies inside one chunk (one pass, few buckets per chunk), else globally
     t_sub.begin(st);
@@ -1046,7 +1006,6 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
             sg.max_cells = n + num_wc;
             in.vals = U32(P.perm);   // original indices ride along
             o.vals = U32(P.wc_orig);
-            if (npc_try) o.dst = U32(P.n_begin);   // every perm position's place in work-chunk order
             multisplit_segmented(in, n, sg, (n + MS_SEG_TILE - 1) / MS_SEG_TILE + num_chunks, o, ws + P.ms_temp, st);
         } else {
             in.vals = U32(P.perm);
@@ -1104,6 +1063,8 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     // general-class work chunk whose table overflows LDS joins the
     // global-memory list, so that list runs whenever a general class does
     launch_subsample_small(A, hctrs->lists_pre, st);
+    bool big = hctrs->lists_pre[WC_CLASSES] != 0;
+    for (int k = WC_GENERAL; k < WC_CLASSES; ++k) big = big || hctrs->lists_pre[k] != 0;
     if (big) launch_subsample_big(A, st);
     scan_exclusive(U32(P.alive), U32(P.alive_scan), (uint64_t)MAXD * num_wc, U32(P.alive_scan) + (uint64_t)MAXD * num_wc,
                    stemp, st);
@@ -1116,7 +1077,6 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
     t_ncnt.begin(st);
     launch_np_counts(A, U32(P.node_base), U32(P.np_cnt), U32(P.np_scan), U32(P.n_count), U32(P.owned),
                      U32(P.np_glist), &ctrs->np_general, &ctrs->np_max, U8(P.np_single), stemp, st);
-    if (npc_try) launch_npc_tables(A, U32(P.node_base), U32(P.owned), npc, ctrs, stemp, st);
     t_ncnt.end(st);
     JCHK(hipMemcpyAsync(hctrs, ctrs, sizeof(Ctrs), hipMemcpyDeviceToHost, st));
     JCHK(hipStreamSynchronize(st));
@@ -1146,19 +1106,8 @@ fpo_status issue_build(fpo_context *ctx, const fpo_cloud *cloud, const fpo_param
         w.scan_temp = stemp;
         w.place_timer = &t_place;
         w.sort_timer = &t_nsort;
-        const uint64_t cells = hctrs->npc_cells;
-        const bool by_chunk = npc_try && hctrs->npc_maxnb <= MS_MAX_BINS && hctrs->npc_buckets <= npc_cap_buckets &&
-                              npc_split_off + multisplit_seg_temp_bytes(n, num_chunks, cells) <= npc_region;
-        job->np_by_chunk = by_chunk;
-        if (by_chunk) {
-            w.lists.placed = true;
-            launch_npc_points(A, U32(P.node_base), U32(P.owned), npc, U32(P.n_count), num_nodes, hctrs->np_max, n,
-                              U32(P.perm), U32(P.c_count_scan), U32(P.n_begin), U32(P.wc_code), cells,
-                              ws + P.code + npc_split_off, w, st);
-        } else {
-            launch_np_points(A, U32(P.node_base), U32(P.owned), U32(P.np_cnt), U32(P.n_count), num_nodes,
-                             hctrs->np_max, n, w, st);
-        }
+        launch_np_points(A, U32(P.node_base), U32(P.owned), U32(P.np_cnt), U32(P.n_count), num_nodes, hctrs->np_max, n,
+                         w, st);
     }
     launch_u32_to_u64(U32(P.np_nb), U64(P.n_begin), num_nodes, st);
     t_nsort.end(st);
@@ -1487,7 +1436,6 @@ fpo_status fpo_job_get_stats(fpo_job *job, fpo_job_stats *out)
     st.n_outside = R.n_outside;
     st.preview_count = R.preview_count;
     st.workspace_bytes = job->plan_bytes;
-    st.node_points_by_chunk = job->np_by_chunk ? 1u : 0u;
     if (R.num_nodes) {
         // nodes are listed by depth: the last one is the deepest
         uint8_t d = 0;
@@ -1542,13 +1490,6 @@ fpo_status fpo_context_set_single_block_max(fpo_context *ctx, uint32_t plain_max
         return fail(FPO_ERR_INVALID_ARG, "limits must be at most %u (got %u, %u)", SB_MAX_N, plain_max, batch_max);
     ctx->small_max.store(plain_max);
     ctx->small_max_batch.store(batch_max);
-    return FPO_OK;
-}
-
-fpo_status fpo_context_set_node_points_by_chunk(fpo_context *ctx, int enable)
-{
-    if (!ctx) return fail(FPO_ERR_INVALID_ARG, "context is NULL");
-    ctx->np_by_chunk.store(enable ? 1 : 0);
     return FPO_OK;
 }
 

@@ -61,9 +61,6 @@ struct fpo_context {
     // served builds, batches
     std::atomic<uint32_t> small_max{65536};
     std::atomic<uint32_t> small_max_batch{262143};
-    // node_points by a split of perm order, chunk by chunk, where a build
-    // allows it (fpo_context_set_node_points_by_chunk)
-    std::atomic<int> np_by_chunk{1};
 };
 
 struct fpo_job {
@@ -76,7 +73,6 @@ struct fpo_job {
     bool waited;
     bool timed;
     uint32_t timer_mask = 0;      // the context's timers when it was submitted
-    bool np_by_chunk = false;     // node_points came from the split of perm order by chunk
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tm[FPO_TIMER_COUNT];
     uint64_t t_submit, t_done;    // host steady clock, ns (t_done: when a wait or poll saw it end)
     uint64_t grid_cells;          // G^3

@@ -68,8 +68,6 @@ struct Ctrs {
     uint32_t np_general;            // work chunks with own nodes below their root
     uint32_t wc_over;               // a work chunk holds more than WC_CAP points (one finest cell)
     uint32_t lists_pre[WC_CLASSES + 1];   // work chunks per subsample list (and the global-memory path)
-    // node_points by chunk: the most buckets of a chunk, all buckets, all count-matrix cells
-    uint32_t npc_maxnb, npc_buckets, npc_cells;
 };
 static_assert(sizeof(Ctrs) <= 256, "the box follows the counters 256 bytes later");
 
@@ -211,16 +209,11 @@ struct MsInput {
     // look-back ever gives up waiting (never expected).
     const uint64_t *bucket_begin = nullptr;
     uint32_t *err = nullptr;
-    // optional, with keys: element e's key is keys[key_idx[e]] (segmented split)
-    const uint32_t *key_idx = nullptr;
 };
 struct MsOutput {
     uint32_t *vals = nullptr;          // values in sorted order (optional)
     uint32_t *keys = nullptr;          // keys in sorted order (optional)
     uint32_t *src = nullptr;           // input position of every output (optional, one pass only)
-    // output position of every input (optional, segmented split only); may be
-    // the input's own key array, which each tile reads before it writes
-    uint32_t *dst = nullptr;
     uint64_t *pay = nullptr;           // payload in sorted order (optional)
     // optional, with pay: the entry of a second cut holding each output's
     // payload cell (pay >> cut2_shift), in sorted order (last pass only)
@@ -234,11 +227,6 @@ struct MsSegments {
     uint32_t nseg = 0;
     const uint32_t *begin = nullptr, *len = nullptr, *b0 = nullptr, *nb = nullptr;
     uint64_t max_cells = 0;            // bound on sum(nb * tiles)
-    // optional: first count-matrix cell of every bucket (its tiles follow
-    // it), in place of segment-major, bucket-minor cells.  The scan then runs
-    // in the order these cells give, so each bucket can be put anywhere in
-    // the output (cells must tile [0, sum(nb * tiles)) exactly).
-    const uint32_t *bucket_cell = nullptr;
 };
 struct MsArgs {
     uint64_t n;
@@ -263,10 +251,6 @@ struct MsArgs {
     uint32_t *cut2_out;
     CutIndex cut2;
     int cut2_shift;
-    // MsInput::key_idx, MsSegments::bucket_cell, MsOutput::dst
-    const uint32_t *key_idx;
-    const uint32_t *bucket_cell;
-    uint32_t *dst_out;
 };
 size_t multisplit_temp_bytes(uint64_t n, uint32_t nbins);
 size_t multisplit_temp_bound(uint64_t n, uint64_t max_bins);   // for any nbins <= max_bins
@@ -358,7 +342,6 @@ struct NpLists {
     uint64_t *cp;             // parts of up to 16384 values of nodes (or groups) already in order: copied
     const uint8_t *single;    // per node: 1 when one piece in work-chunk order fills it (already ascending)
     uint32_t *counts;         // 6 list lengths (c0..c3, jobs, cp), zeroed before
-    bool placed;              // nodes marked single are in their final place already: nothing to copy
 };
 struct NpWork {
     uint32_t *nb;         // node begins (num_nodes + 1)
@@ -375,36 +358,6 @@ struct NpWork {
 void launch_np_points(const WcArgs &a, const uint32_t *node_base, const uint32_t *pnode, const uint32_t *poff,
                       const uint32_t *cnt_node, uint32_t num_nodes, uint32_t max_count, uint64_t n, const NpWork &w,
                       hipStream_t st);
-// node_points by chunk (every work chunk inside one chunk): the node-id
-// range of every (depth, chunk) pair gives each chunk a bucket per node it
-// holds points of, and a stable split of perm order by those buckets, chunk by
-// chunk, puts every point in its node's range; the buckets' count-matrix cells
-// follow node order, so the split's scan yields node_points positions.  A
-// node's points inside one chunk then ascend; only nodes spanning several
-// chunks (ancestors of chunks) are sorted afterwards.
-struct NpcTables {
-    uint32_t nch;                 // chunks
-    uint32_t *first, *last;       // [d * nch + c]: node-id range of depth d in chunk c (empty: first > last)
-    uint32_t *loff;               // [d * nch + c]: buckets of chunk c before depth d
-    uint32_t *cells, *cellb;      // [d * nch + c]: count-matrix cells of the pair, their exclusive scan
-    uint32_t *nbk, *b0;           // per chunk: buckets, first bucket (exclusive scan)
-    uint32_t *bucket_cell;        // per bucket: its first cell
-    const uint32_t *c_count;      // points per chunk
-    const uint32_t *wc_chunk;     // chunk of every work chunk
-};
-// Before the node count is read back: the ranges, bucket and cell counts,
-// their scans; ctrs->npc_maxnb / npc_buckets / npc_cells.
-void launch_npc_tables(const WcArgs &a, const uint32_t *node_base, const uint32_t *pnode, const NpcTables &t,
-                       Ctrs *ctrs, void *scan_temp, hipStream_t st);
-// Then: node begins, the bucket cells and single flags, lists, every point's
-// bucket key (in work-chunk order), the split of perm order into node_points,
-// and the sorts of the nodes spanning chunks.  wc_dst: the work-chunk order
-// position of every perm position; keys: n words of scratch; split_temp holds
-// multisplit_seg_temp_bytes(n, nch, cells).
-void launch_npc_points(const WcArgs &a, const uint32_t *node_base, const uint32_t *pnode, const NpcTables &t,
-                       const uint32_t *cnt_node, uint32_t num_nodes, uint32_t max_count, uint64_t n,
-                       const uint32_t *perm, const uint32_t *c_begin, const uint32_t *wc_dst, uint32_t *keys,
-                       uint64_t cells, void *split_temp, const NpWork &w, hipStream_t st);
 uint64_t np_list_entries(uint64_t n, int cls);   // entries of tile list cls (0..3) for n points
 uint64_t np_job_entries(uint64_t n);
 uint64_t np_copy_entries(uint64_t n);

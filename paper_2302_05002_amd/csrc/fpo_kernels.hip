@@ -1195,16 +1195,7 @@ void scan_exclusive_dev(const uint32_t *in, uint32_t *out, const uint32_t *n_dev
 template <int N>
 __device__ __forceinline__ void ms_load_keys(const MsArgs &A, uint64_t wlo, uint64_t hi, int lane, uint32_t (&full)[N])
 {
-    if (A.keys && A.key_idx) {
-        uint32_t q[N];
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            const uint64_t e = wlo + (uint64_t)r * 64 + lane;
-            q[r] = A.key_idx[e < hi ? e : hi - 1];
-        }
-#pragma unroll
-        for (int r = 0; r < N; ++r) full[r] = A.keys[q[r]];
-    } else if (A.keys) {
+    if (A.keys) {
 #pragma unroll
         for (int r = 0; r < N; ++r) {
             const uint64_t e = wlo + (uint64_t)r * 64 + lane;
@@ -1264,15 +1255,6 @@ __device__ __forceinline__ MsTile ms_tile(const MsArgs &A, uint32_t t)
     return T;
 }
 
-// Count-matrix cell of bucket b (local) of tile T: segment-major,
-// bucket-minor, or where the per-bucket table puts the bucket's first tile.
-template <bool SEG>
-__device__ __forceinline__ uint64_t ms_cell(const MsArgs &A, const MsTile &T, uint32_t b)
-{
-    if (SEG && A.bucket_cell) return (uint64_t)A.bucket_cell[T.b0 + b] + T.tis;
-    return (uint64_t)T.mat + (uint64_t)b * T.ntile + T.tis;
-}
-
 // Count pass: equal keys of a wave round are grouped by a ballot match and
 // added once (consecutive points usually share their chunk), so LDS atomics
 // do not pile up on one counter.  The segmented split (work chunks inside a
@@ -1310,7 +1292,7 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_count(MsArgs A)
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < T.nb; b += MS_BLOCK)
-        A.counts[ms_cell<SEG>(A, T, b)] = hist[b];
+        A.counts[(uint64_t)T.mat + (uint64_t)b * T.ntile + T.tis] = hist[b];
 }
 
 // ONE (unsegmented, at most MS_ONE_PASS_BINS buckets, known bucket starts):
@@ -1464,7 +1446,7 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
                     pre[k][b] = (uint16_t)run;
                     run += h;
                 }
-                gbase[b] = A.offsets[ms_cell<SEG>(A, T, b)] - loff;
+                gbase[b] = A.offsets[(uint64_t)T.mat + (uint64_t)b * T.ntile + T.tis] - loff;
             }
         }
     }
@@ -1478,17 +1460,6 @@ __global__ __launch_bounds__(MS_BLOCK) void k_ms_scatter(MsArgs A)
         const uint32_t slot = pre[w][key] + wof[r];
         stage[slot] = ((unsigned long long)full[r] << 32) | val[r];
         wof[r] = (uint16_t)slot;
-    }
-    if (SEG && A.dst_out) {
-        // every input's output position, in input order (the keys were read
-        // at the start, so this may overwrite them)
-#pragma unroll
-        for (int r = 0; r < IT; ++r) {
-            const uint64_t e = wlo + (uint64_t)r * 64 + lane;
-            if (e >= T.hi) continue;
-            const uint32_t key = ((full[r] >> A.shift) & dmask) - T.b0;
-            A.dst_out[e] = gbase[key] + wof[r];
-        }
     }
     __syncthreads();
     // phase 4: write bucket runs
@@ -1784,9 +1755,6 @@ void multisplit_segmented(const MsInput &in, uint64_t n, const MsSegments &sg, u
     A.keys_out = out.keys;
     A.pay_out = out.pay;
     A.src_out = out.src;
-    A.key_idx = in.key_idx;
-    A.bucket_cell = sg.bucket_cell;
-    A.dst_out = out.dst;
     hipLaunchKernelGGL((k_ms_count<true, MS_SEG_ITEMS>), dim3((uint32_t)max_tiles), dim3(MS_BLOCK), 0, st, A);
     scan_exclusive_dev(counts, offs, tot + 1, sg.max_cells, stemp, st);
     hipLaunchKernelGGL((k_ms_scatter<true, MS_SEG_ITEMS>), dim3((uint32_t)max_tiles), dim3(MS_BLOCK), 0, st, A);
@@ -2973,14 +2941,14 @@ __global__ void k_np_lists(const uint32_t *nb, uint32_t nn, NpLists L)
                     bool all = true;   // every node of the group already ascends: copied
                     for (uint32_t y = gx0; y < gx1 && all; ++y) all = L.single[y] != 0;
                     if (all) {
-                        ncp = L.placed ? 0u : 1u;
+                        ncp = 1;
                     } else {
                         n0 = gt <= NP_T0 ? 1u : 0u;
                         n1 = 1u - n0;
                     }
                 }
             } else if (L.single[x]) {
-                ncp = c && !L.placed ? (c + NP_T3 - 1) / NP_T3 : 0u;
+                ncp = c ? (c + NP_T3 - 1) / NP_T3 : 0u;
             } else if (c <= NP_T0) {
                 n0 = 1;
             } else if (c <= NP_T1) {
@@ -3578,172 +3546,6 @@ __global__ void k_node_fill(WcArgs a, const uint32_t *node_base, uint8_t *depth,
     }
 }
 
-// ---- node_points by chunk -----------------------------------------------------------------------
-//
-// When every work chunk lies inside one chunk, perm order (chunk-major,
-// ascending original index inside a chunk) already lists every node's points
-// of one chunk in ascending order.  Node ids run depth by depth in key order,
-// and a chunk is a Morton range, so at depth d the nodes holding points of
-// chunk c are one id range [first, last]: the nodes inside the chunk, or the
-// one ancestor above it.  Each such (chunk, node) pair is a bucket of a stable
-// split of the chunk's perm range; its count-matrix cells are laid out depth
-// by depth, chunk by chunk, node by node (the same order as node_points, as a
-// node spanning chunks c..c' is the last of c's range and the first of the
-// next ones'), so the scan of the cells gives every point's final position.
-// Only the nodes spanning several chunks then need their pieces sorted.
-
-constexpr uint32_t NPC_NONE = 0xffffffffu;
-
-// Per (depth d, work chunk w): the node-id range of w's points of final depth
-// d (the piece of a shared node, the own root alone, or the own nodes of
-// depth d), folded into its chunk's range.
-__global__ void k_npc_ranges(WcArgs a, const uint32_t *node_base, const uint32_t *pnode, NpcTables t)
-{
-    const uint32_t W = a.num_wc;
-    const uint64_t total = (uint64_t)MAXD * W;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
-        const int d = (int)(i / W);
-        const uint32_t w = (uint32_t)(i % W);
-        const int lw = a.wc_level[w], cut = a.cut[w];
-        uint32_t lo = NPC_NONE, hi = 0;
-        if (d < lw && d <= cut) {
-            const uint32_t node = pnode[i];
-            if (node != NP_NONE) lo = hi = node;
-        } else if (d >= lw && cut == lw) {
-            const uint32_t node = d == lw ? pnode[i] : NP_NONE;
-            if (node != NP_NONE) {
-                lo = hi = node;
-            } else {
-                const uint32_t k = a.kd[(uint64_t)w * MAXD + d];
-                if (k) {
-                    lo = node_base[i];
-                    hi = lo + k - 1;
-                }
-            }
-        }
-        if (lo != NPC_NONE) {
-            const uint64_t j = (uint64_t)d * t.nch + t.wc_chunk[w];
-            atomicMin(&t.first[j], lo);
-            atomicMax(&t.last[j], hi);
-        }
-    }
-}
-
-__device__ __forceinline__ uint32_t npc_count(const NpcTables &t, uint64_t j)
-{
-    const uint32_t f = t.first[j], l = t.last[j];
-    return f <= l ? l - f + 1 : 0u;
-}
-
-// Per chunk: buckets before each depth, cells of each (depth, chunk) pair,
-// buckets in all; the largest bucket count.
-__global__ void k_npc_chunks(NpcTables t, uint32_t *maxnb)
-{
-    uint32_t mymax = 0;
-    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < t.nch; c += gridDim.x * blockDim.x) {
-        const uint32_t tiles = (t.c_count[c] + MS_SEG_TILE - 1) / MS_SEG_TILE;
-        uint32_t nb = 0;
-        for (int d = 0; d < MAXD; ++d) {
-            const uint64_t j = (uint64_t)d * t.nch + c;
-            const uint32_t k = npc_count(t, j);
-            t.loff[j] = nb;
-            t.cells[j] = k * tiles;
-            nb += k;
-        }
-        t.nbk[c] = nb;
-        mymax = max(mymax, nb);
-    }
-    mymax = wave_max(mymax);
-    if (lane_id() == 0 && mymax) atomicMax(maxnb, mymax);
-}
-
-// Per (depth, chunk) pair, a block each: the first cell of every bucket, and
-// one count per chunk range at the range's end nodes (appear, zeroed before):
-// only those can be shared with other chunks.
-__global__ void k_npc_buckets(NpcTables t, uint32_t *appear)
-{
-    const uint64_t pairs = (uint64_t)MAXD * t.nch;
-    for (uint64_t j = blockIdx.x; j < pairs; j += gridDim.x) {
-        const uint32_t k = npc_count(t, j);
-        if (k == 0) continue;
-        const uint32_t c = (uint32_t)(j % t.nch);
-        const uint32_t tiles = (t.c_count[c] + MS_SEG_TILE - 1) / MS_SEG_TILE;
-        const uint32_t b = t.b0[c] + t.loff[j], cb = t.cellb[j];
-        for (uint32_t q = threadIdx.x; q < k; q += blockDim.x) t.bucket_cell[b + q] = cb + q * tiles;
-        if (threadIdx.x == 0) {
-            atomicAdd(&appear[t.first[j]], 1u);
-            if (k > 1) atomicAdd(&appear[t.last[j]], 1u);
-        }
-    }
-}
-
-// A node in the ranges of several chunks is not in order after the split.
-__global__ void k_npc_multi(NpcTables t, const uint32_t *appear, uint8_t *single)
-{
-    const uint64_t pairs = (uint64_t)MAXD * t.nch;
-    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < pairs; j += (uint64_t)gridDim.x * blockDim.x) {
-        if (npc_count(t, j) == 0) continue;
-        const uint32_t f = t.first[j], l = t.last[j];
-        if (appear[f] > 1) single[f] = 0;
-        if (appear[l] > 1) single[l] = 0;
-    }
-}
-
-// One wave per work chunk: every point's bucket (the chunk's first bucket,
-// plus its depth's offset, plus the node id's place in the depth's range), in
-// work-chunk order.
-constexpr int NPK_ITEMS = 8;
-constexpr int NPK_WAVES = 4;
-__global__ __launch_bounds__(64 * NPK_WAVES) void k_npc_keys(WcArgs a, const uint32_t *node_base, const uint32_t *pnode,
-                                                             NpcTables t, uint32_t *keys, uint32_t *err)
-{
-    const uint32_t lane = lane_id();
-    const uint32_t W = a.num_wc;
-    for (uint32_t w = blockIdx.x * NPK_WAVES + (threadIdx.x >> 6); w < W; w += gridDim.x * NPK_WAVES) {
-        const int lw = a.wc_level[w], cut = a.cut[w];
-        const uint32_t base = a.wc_begin[w], n = a.wc_count[w], c = t.wc_chunk[w];
-        const uint32_t cb0 = t.b0[c], cnb = t.nbk[c];   // the chunk's buckets
-        // lane d < MAXD: depth d's node when one holds all of w's points of
-        // that depth, the first own node, and the key of node id 0
-        uint32_t pn = NP_NONE, ob = 0, kb = 0;
-        if (lane < (uint32_t)MAXD) {
-            const uint64_t i = (uint64_t)lane * W + w;
-            const uint64_t j = (uint64_t)lane * t.nch + c;
-            pn = pnode[i];
-            ob = node_base[i];
-            kb = t.b0[c] + t.loff[j] - t.first[j];
-        }
-        bool bad = false;
-        for (uint32_t c0 = 0; c0 < n; c0 += 64 * NPK_ITEMS) {
-            uint32_t t8[NPK_ITEMS];
-#pragma unroll
-            for (int k = 0; k < NPK_ITEMS; ++k) {
-                const uint32_t p = c0 + k * 64 + lane;
-                t8[k] = p < n ? a.t[base + p] : 0u;
-            }
-#pragma unroll
-            for (int k = 0; k < NPK_ITEMS; ++k) {
-                const uint32_t p = c0 + k * 64 + lane;
-                const bool ok = p < n && t8[k] < (uint32_t)MAXD;
-                bad |= p < n && !ok;
-                const int d = np_final_depth(ok ? (int)t8[k] : 0, lw, cut);
-                const uint32_t node = (uint32_t)__shfl((int)pn, d, 64);
-                const uint32_t own = (uint32_t)__shfl((int)ob, d, 64);
-                const uint32_t key0 = (uint32_t)__shfl((int)kb, d, 64);
-                uint32_t id = node;
-                if (ok && node == NP_NONE) id = own + a.fr[base + p];
-                uint32_t key = key0 + id;
-                if (ok && key - cb0 >= cnb) {   // outside the chunk's buckets: never expected
-                    bad = true;
-                    key = cb0;
-                }
-                if (ok) keys[base + p] = key;
-            }
-        }
-        if (__ballot(bad) && lane == 0) atomicOr(err, 1u);
-    }
-}
-
 // ---- step 5: preview ---------------------------------------------------------------------------
 // Modes: keep index i iff H64(i) mod M == 0, iff i mod M == 0 (an exact
 // stride), or iff i is the point of least H64 in its count-grid cell (one pick
@@ -4163,84 +3965,6 @@ void launch_np_points(const WcArgs &a, const uint32_t *node_base, const uint32_t
                        w.lists.counts + 2, w.nb, num_nodes, w.tmp, w.out, w.tmp);
     hipLaunchKernelGGL((k_np_sort<512, 32, true>), dim3(n3 < 1024 ? (uint32_t)n3 : 1024), dim3(512), 0, st, w.lists.c3,
                        w.lists.counts + 3, w.nb, num_nodes, w.tmp, w.out, w.tmp);
-    const uint32_t rounds = ceil_log2((max_count + NP_T3 - 1) / NP_T3);
-    const uint64_t njobs = np_job_entries(n);
-    for (uint32_t r = 0; r < rounds; ++r)
-        hipLaunchKernelGGL(k_np_merge, dim3(njobs < 4096 ? (uint32_t)njobs : 4096), dim3(NPM_BLOCK), 0, st,
-                           w.lists.jobs, w.lists.counts + 4, w.nb, (int)r, w.out, w.tmp);
-}
-
-void launch_npc_tables(const WcArgs &a, const uint32_t *node_base, const uint32_t *pnode, const NpcTables &t,
-                       Ctrs *ctrs, void *scan_temp, hipStream_t st)
-{
-    if (a.num_wc == 0 || t.nch == 0) return;
-    const uint64_t pairs = (uint64_t)MAXD * t.nch;
-    {
-        FillSpec f[4];
-        f[0] = {t.first, NPC_NONE, pairs};
-        f[1] = {t.last, 0u, pairs};
-        launch_fill_many(f, st);
-    }
-    hipLaunchKernelGGL(k_npc_ranges, dim3(grid_for((uint64_t)MAXD * a.num_wc, 256)), dim3(256), 0, st, a, node_base,
-                       pnode, t);
-    hipLaunchKernelGGL(k_npc_chunks, dim3(grid_for(t.nch, 256)), dim3(256), 0, st, t, &ctrs->npc_maxnb);
-    scan_exclusive(t.nbk, t.b0, t.nch, &ctrs->npc_buckets, scan_temp, st);
-    scan_exclusive(t.cells, t.cellb, pairs, &ctrs->npc_cells, scan_temp, st);
-}
-
-void launch_npc_points(const WcArgs &a, const uint32_t *node_base, const uint32_t *pnode, const NpcTables &t,
-                       const uint32_t *cnt_node, uint32_t num_nodes, uint32_t max_count, uint64_t n,
-                       const uint32_t *perm, const uint32_t *c_begin, const uint32_t *wc_dst, uint32_t *keys,
-                       uint64_t cells, void *split_temp, const NpWork &w, hipStream_t st)
-{
-    if (n == 0 || num_nodes == 0) return;
-    scan_exclusive(cnt_node, w.nb, num_nodes, w.nb + num_nodes, w.scan_temp, st);
-    // every node ascends once split, except the ones spanning chunks (the
-    // merges' buffer counts the chunk ranges holding each node until then)
-    uint8_t *single = const_cast<uint8_t *>(w.lists.single);
-    {
-        FillSpec f[4];
-        f[0] = {reinterpret_cast<uint32_t *>(single), 0x01010101u, (num_nodes + 3) / 4};
-        f[1] = {w.tmp, 0u, num_nodes};
-        launch_fill_many(f, st);
-    }
-    const uint64_t pairs = (uint64_t)MAXD * t.nch;
-    hipLaunchKernelGGL(k_npc_buckets, dim3(pairs < 8192 ? (uint32_t)pairs : 8192), dim3(256), 0, st, t, w.tmp);
-    hipLaunchKernelGGL(k_npc_multi, dim3(grid_for(pairs, 256)), dim3(256), 0, st, t, w.tmp, single);
-    hipLaunchKernelGGL(k_np_lists, dim3(grid_for(num_nodes, 256, 1024)), dim3(256), 0, st, w.nb, num_nodes, w.lists);
-    const uint32_t kg = (a.num_wc + NPK_WAVES - 1) / NPK_WAVES;
-    hipLaunchKernelGGL(k_npc_keys, dim3(kg < 4096 ? kg : 4096), dim3(64 * NPK_WAVES), 0, st, a, node_base, pnode, t,
-                       keys, w.err);
-    {
-        MsInput in;
-        in.keys = keys;
-        in.key_idx = wc_dst;
-        in.vals = perm;
-        MsSegments sg;
-        sg.nseg = t.nch;
-        sg.begin = c_begin;
-        sg.len = t.c_count;
-        sg.b0 = t.b0;
-        sg.nb = t.nbk;
-        sg.max_cells = cells;
-        sg.bucket_cell = t.bucket_cell;
-        MsOutput o;
-        o.vals = w.out;
-        multisplit_segmented(in, n, sg, (n + MS_SEG_TILE - 1) / MS_SEG_TILE + t.nch, o, split_temp, st);
-    }
-    if (w.place_timer) w.place_timer->end(st);
-    if (w.sort_timer) w.sort_timer->begin(st);
-    // the nodes spanning chunks, sorted in place (their pieces lie in chunk order)
-    const uint32_t g0 = num_nodes < 8192 ? num_nodes : 8192;
-    const uint64_t n1 = n / 1024 + num_nodes / NP_GROUP + 1, n2 = n / 4096 + 1, n3 = n / 8192 + n / NP_T3 + 1;
-    hipLaunchKernelGGL((k_np_sort<64, 16, false>), dim3(g0), dim3(64), 0, st, w.lists.c0, w.lists.counts, w.nb,
-                       num_nodes, w.out, w.out, w.tmp);
-    hipLaunchKernelGGL((k_np_sort<256, 16, false>), dim3(n1 < 4096 ? (uint32_t)n1 : 4096), dim3(256), 0, st, w.lists.c1,
-                       w.lists.counts + 1, w.nb, num_nodes, w.out, w.out, w.tmp);
-    hipLaunchKernelGGL((k_np_sort<256, 32, false, true>), dim3(n2 < 2048 ? (uint32_t)n2 : 2048), dim3(256), 0, st,
-                       w.lists.c2, w.lists.counts + 2, w.nb, num_nodes, w.out, w.out, w.tmp);
-    hipLaunchKernelGGL((k_np_sort<512, 32, true>), dim3(n3 < 1024 ? (uint32_t)n3 : 1024), dim3(512), 0, st, w.lists.c3,
-                       w.lists.counts + 3, w.nb, num_nodes, w.out, w.out, w.tmp);
     const uint32_t rounds = ceil_log2((max_count + NP_T3 - 1) / NP_T3);
     const uint64_t njobs = np_job_entries(n);
     for (uint32_t r = 0; r < rounds; ++r)
