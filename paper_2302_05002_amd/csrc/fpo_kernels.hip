@@ -3574,16 +3574,19 @@ __global__ __launch_bounds__(PV_BLOCK) void k_preview_bits(PreviewArgs p, uint32
         for (uint32_t i = threadIdx.x; i < p.zero_words; i += PV_BLOCK) p.zero[i] = 0u;
     const uint64_t words = (p.n + 31) / 32;
     const uint64_t base = (uint64_t)blockIdx.x * PV_TILE + (uint64_t)(threadIdx.x >> 6) * (64 * PV_ITEMS);
-    uint32_t cnt = 0;
+    const uint32_t lane = lane_id();
+    uint32_t cnt = 0, mine = 0;   // lane k < 2 * PV_ITEMS keeps word k of the wave's run
+#pragma unroll
     for (int j = 0; j < PV_ITEMS; ++j) {
-        const uint64_t i0 = base + (uint64_t)j * 64;
-        const uint64_t i = i0 + lane_id();
+        const uint64_t i = base + (uint64_t)j * 64 + lane;
         const uint64_t m = __ballot(i < p.n && keep(p, i));
         cnt += (uint32_t)__popcll(m);
-        const uint64_t w = i0 / 32;
-        if (lane_id() == 0 && w < words) bits[w] = (uint32_t)m;
-        if (lane_id() == 1 && w + 1 < words) bits[w + 1] = (uint32_t)(m >> 32);
+        if (lane == (uint32_t)(2 * j)) mine = (uint32_t)m;
+        if (lane == (uint32_t)(2 * j + 1)) mine = (uint32_t)(m >> 32);
     }
+    // the wave's words in one store
+    const uint64_t w = base / 32 + lane;
+    if (lane < (uint32_t)(2 * PV_ITEMS) && w < words) bits[w] = mine;
     if (tile_counts) {
         if (lane_id() == 0) wsum[threadIdx.x >> 6] = cnt;
         __syncthreads();
