@@ -166,3 +166,19 @@ def test_full_size_planes(ctx):
                                         p.preview_modulus, None, "stride")).to_numpy()
     torch.cuda.synchronize()
     np.testing.assert_array_equal(got["preview_index"], np.arange(0, c.n, p.preview_modulus, dtype=np.uint32))
+
+
+@pytest.mark.parametrize("mode", ["hash", "stride", "grid"])
+def test_ragged_sizes_multi_kernel(mode):
+    """The multi-kernel preview (bit map per wave of 1024 indices, 4096-index
+    compaction tiles) at sizes around its word, wave and tile boundaries, with
+    single-workgroup builds turned off."""
+    import paper_2302_05002_amd as fpo
+    ctx = fpo.Context(0)
+    try:
+        ctx.set_single_block_max(0)
+        for n in (1, 31, 33, 63, 65, 1023, 1025, 4095, 4097, 5121, 70_001):
+            c = synth.uniform(n, seed=n)
+            both(ctx, c, 16, 2_000, 8, 100, 7 if mode != "grid" else 3, mode, label=f"ragged {n}")
+    finally:
+        ctx.close()
