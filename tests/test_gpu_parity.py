@@ -282,3 +282,21 @@ def test_node_points_many_own_nodes(ctx):
     c = synth.Cloud(p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy())
     got, exp = run_both(ctx, c, 4, 1_000_000, 2, 1, 5)
     assert exp["node_depth"].shape[0] > 4096 + 1000
+
+
+LARGEST_GRID_CASES = [
+    # (label, cloud, G, C, S, L, M): the largest subsample grid (2^24 cells per
+    # node: general subsample classes, hashed cell tables) at millions of points
+    ("planes 2M G128 S256", lambda: synth.planes(2_000_000, seed=61, num_planes=30), 128, 200_000, 256, 10_000, 64),
+    ("clusters 1M G64 S256 L1000", lambda: synth.clusters(1_000_000, 62, 25), 64, 100_000, 256, 1_000, 16),
+    ("uniform 3M G256 S256", lambda: synth.uniform(3_000_000, seed=63), 256, 500_000, 256, 20_000, 64),
+    ("planes 2M G512 S256", lambda: synth.planes(2_000_000, seed=64, num_planes=30), 512, 100_000, 256, 5_000, 64),
+    ("clusters 2M G256 S256 tight", lambda: synth.clusters(2_000_000, 65, 8, sigma_frac=0.002), 256, 300_000, 256,
+     1_000, 64),
+]
+
+
+@pytest.mark.parametrize("case", LARGEST_GRID_CASES, ids=[c[0] for c in LARGEST_GRID_CASES])
+def test_largest_subsample_grid(ctx, case):
+    label, make_cloud, G, C, S, L, M = case
+    run_both(ctx, make_cloud(), G, C, S, L, M, label=f"{label}: ")
