@@ -26,10 +26,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
 WORKLOADS = {
     # name: (generator, params attribute, description)
-    "planes20m": ("config2", "CONFIG2", "20M points on 200 planes, G=128, C=1M, S=128, L=10k, M=64"),
-    "uniform1m": ("config1", "CONFIG1", "1M uniform points, G=64, C=100k, S=32, L=10k, M=64"),
+    "planes20m": ("planes_20m", "PLANES_20M", "20M points on 200 planes, G=128, C=1M, S=128, L=10k, M=64"),
+    "uniform1m": ("uniform_1m", "UNIFORM_1M", "1M uniform points, G=64, C=100k, S=32, L=10k, M=64"),
     # the out-of-core workload built from device memory (profiling of the G = 512 path)
-    "terrain200m": ("config3", "CONFIG3", "200M points of terrain and clusters in device memory, G=512, C=2M, S=128, "
+    "terrain200m": ("terrain_200m", "TERRAIN_200M", "200M points of terrain and clusters in device memory, G=512, C=2M, S=128, "
                                           "L=10k, M=64"),
 }
 
@@ -352,8 +352,8 @@ def bench_streamed(fpo, torch, ctx, steps: int = 3) -> dict:
     the host link: reported against a plain pinned copy of the same bytes.
     Also the time until the preview is ready (it depends only on n)."""
     import synth
-    c = synth.config3()
-    p = synth.CONFIG3
+    c = synth.terrain_200m()
+    p = synth.TERRAIN_200M
     box = ((float(c.x.min()), float(c.y.min()), float(c.z.min())),
            (float(c.x.max()), float(c.y.max()), float(c.z.max())))
     params = fpo.Params(p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity, p.preview_modulus,
@@ -460,12 +460,12 @@ def measure(fpo, torch, ctx, xyz, params, ws, stream, steps: int, workload: str,
     return {"ms_per_build": ms, "roofline": roofline, "path": path}
 
 
-def bench_config1(fpo, torch, ctx, steps: int) -> dict:
+def bench_uniform1m(fpo, torch, ctx, steps: int) -> dict:
     """The plain 1M-point build (uniform cube, G=64, C=100k, S=32, L=10k,
     M=64): ms per build and the fraction of HBM peak for the whole path."""
     import synth
-    p = synth.CONFIG1
-    c = synth.config1()
+    p = synth.UNIFORM_1M
+    c = synth.uniform_1m()
     xyz = to_device(torch, c)
     params = fpo_params_of(fpo, p)
     ws = torch.empty(fpo.workspace_size(c.n, params), dtype=torch.uint8, device="cuda")
@@ -493,7 +493,7 @@ def main():
     ap.add_argument("--no-mix", action="store_true", help="skip the batched and served comparisons")
     ap.add_argument("--no-stream", action="store_true", help="skip the streamed 200M-point build")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel shapes (profiling runs)")
-    ap.add_argument("--no-config1", action="store_true", help="skip the 1M-point leg (profiling runs)")
+    ap.add_argument("--no-uniform1m", action="store_true", help="skip the 1M-point leg (profiling runs)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the LAS decode, preview variant, gather and node selection legs")
     args = ap.parse_args()
@@ -734,10 +734,10 @@ def main():
         "autotuned": tuned,
         **extras,
     }
-    if args.workload != "uniform1m" and not args.no_config1:
-        out["config1"] = bench_config1(fpo, torch, ctx, args.steps)
-        print(f"[bench] 1M uniform: {out['config1']['ms_per_build']:.3f} ms per build, "
-              f"{out['config1']['path']['frac_of_step']:.4f} of HBM peak", file=sys.stderr, flush=True)
+    if args.workload != "uniform1m" and not args.no_uniform1m:
+        out["uniform1m"] = bench_uniform1m(fpo, torch, ctx, args.steps)
+        print(f"[bench] 1M uniform: {out['uniform1m']['ms_per_build']:.3f} ms per build, "
+              f"{out['uniform1m']['path']['frac_of_step']:.4f} of HBM peak", file=sys.stderr, flush=True)
     if not args.no_mix:
         del ws
         torch.cuda.empty_cache()

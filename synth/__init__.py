@@ -224,22 +224,22 @@ def params_for_size(n: int) -> BuildParams:
     return BuildParams(g, c, s)
 
 
-CONFIG1 = BuildParams(count_grid=64, max_points_per_chunk=100_000, subsample_grid=32)
-CONFIG2 = BuildParams(count_grid=128, max_points_per_chunk=1_000_000, subsample_grid=128)
-CONFIG3 = BuildParams(count_grid=512, max_points_per_chunk=2_000_000, subsample_grid=128)
+UNIFORM_1M = BuildParams(count_grid=64, max_points_per_chunk=100_000, subsample_grid=32)
+PLANES_20M = BuildParams(count_grid=128, max_points_per_chunk=1_000_000, subsample_grid=128)
+TERRAIN_200M = BuildParams(count_grid=512, max_points_per_chunk=2_000_000, subsample_grid=128)
 
 
-def config1(n: int = 1_000_000) -> Cloud:
+def uniform_1m(n: int = 1_000_000) -> Cloud:
     """Plain build, uniform cube (1M points at full size)."""
     return uniform(n, seed=1)
 
 
-def config2(n: int = 20_000_000) -> Cloud:
+def planes_20m(n: int = 20_000_000) -> Cloud:
     """Plain build, 200 random planes with 5 mm noise (20M points at full size)."""
     return planes(n, seed=2)
 
 
-def config3(n: int = 200_000_000) -> Cloud:
+def terrain_200m(n: int = 200_000_000) -> Cloud:
     """Out-of-core build: terrain plus clusters (200M points at full size)."""
     return terrain_clusters(n, seed=3, colors=False)
 

@@ -105,7 +105,7 @@ def test_extreme_integers(ctx):
 
 def test_full_size_planes(ctx):
     """The 20M-point planes workload as LAS 1.2 format 3 (34-byte records)."""
-    c = synth.config2()
+    c = synth.planes_20m()
     f = write_las(c.x + 330_000.0, c.y + 4_200_000.0, c.z, scale=(0.0001, 0.0001, 0.0001),
                   offset=(330_000.0, 4_200_000.0, 0.0), point_format=3)
     decode_both(ctx, f, (330_000.0, 4_200_000.0, 0.0), misalign=5, label="planes20m")

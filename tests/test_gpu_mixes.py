@@ -41,12 +41,12 @@ def _oracle(x, y, z, p):
     return r
 
 
-def test_config4_batch_of_256_clouds(ctx):
+def test_batch_of_256_clouds(ctx):
     import torch
     import paper_2302_05002_amd as fpo
     mix = synth.batch_mix(256, seed=4)
     total = sum(c.n for c, _ in mix)
-    print(f"[config4] 256 clouds, {total} points", flush=True)
+    print(f"[batch] 256 clouds, {total} points", flush=True)
     assert 100_000_000 < total < 250_000_000
     dev = [tuple(torch.from_numpy(a).cuda() for a in (c.x, c.y, c.z)) for c, _ in mix]
     jobs = ctx.build_batch(dev, [_params(fpo, p) for _, p in mix])
@@ -56,13 +56,13 @@ def test_config4_batch_of_256_clouds(ctx):
         j.release()
 
 
-def test_config5_served_trace(ctx):
+def test_served_trace_of_2000_requests(ctx):
     import torch
     import paper_2302_05002_amd as fpo
     torch.cuda.empty_cache()   # the arena below takes 200 GB of the device
     pool, reqs = synth.serve_trace(2000, seed=5)
     points = sum(r.n for r in reqs)
-    print(f"[config5] 2000 requests, {points} points", flush=True)
+    print(f"[served] 2000 requests, {points} points", flush=True)
     dev = [tuple(torch.from_numpy(a).cuda() for a in (c.x, c.y, c.z)) for c in pool]
     rng = np.random.default_rng(55)
     small = [i for i, r in enumerate(reqs) if r.n <= 5_000_000]

@@ -184,10 +184,10 @@ def test_nonfinite_rejected_with_given_box(ctx):
     run_both(ctx, synth.Cloud(*a), 16, 10_000, 8, 100, 4, box, label="outside: ")
 
 
-def test_config1_full(ctx):
+def test_uniform_1m_full(ctx):
     """The uniform 1M-point workload, every output compared."""
-    c = synth.config1()
-    p = synth.CONFIG1
+    c = synth.uniform_1m()
+    p = synth.UNIFORM_1M
     got, exp = run_both(ctx, c, p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity,
                         p.preview_modulus)
     assert got["preview_index"].shape[0] == 15761
@@ -203,10 +203,10 @@ def test_quantize_table_flushes(ctx):
     run_both(ctx, c, 128, 1_000_000, 32, 10_000, 64)
 
 
-def test_config2_reduced_with_invariants(ctx):
+def test_planes_20m_reduced_with_invariants(ctx):
     """The 200-plane workload at 2M points: full comparison plus invariants."""
     c = synth.planes(2_000_000, seed=2)
-    p = synth.CONFIG2
+    p = synth.PLANES_20M
     got, _ = run_both(ctx, c, p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity,
                       p.preview_modulus)
     u = oracle.build_octree(c.x, c.y, c.z, oracle.Params(p.count_grid, p.max_points_per_chunk, p.subsample_grid,
@@ -215,11 +215,11 @@ def test_config2_reduced_with_invariants(ctx):
     check_octree_invariants(got, u, p.subsample_grid, p.leaf_capacity)
 
 
-def test_config2_full(ctx):
+def test_planes_20m_full(ctx):
     """The 200-plane workload at its full 20M points, in the configuration the
     benchmark times: every output compared with the oracle."""
-    c = synth.config2()
-    p = synth.CONFIG2
+    c = synth.planes_20m()
+    p = synth.PLANES_20M
     run_both(ctx, c, p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity, p.preview_modulus)
 
 

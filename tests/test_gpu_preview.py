@@ -144,8 +144,8 @@ def test_full_size_planes(ctx):
     the closed form."""
     import torch
     import paper_2302_05002_amd as fpo
-    c = synth.config2()
-    p = synth.CONFIG2
+    c = synth.planes_20m()
+    p = synth.PLANES_20M
     x, y, z = dev(c)
     print(f"[preview] full-size planes n={c.n} G={p.count_grid}", flush=True)
     got = ctx.build(x, y, z, fpo.Params(p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity,

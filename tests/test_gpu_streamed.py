@@ -74,7 +74,7 @@ def test_streamed_rejects_pageable(ctx):
     assert st == fpo.FPO_ERR_INVALID_ARG
 
 
-def test_config3_full(ctx):
+def test_terrain_200m_streamed_full(ctx):
     """The 200M-point terrain workload as the benchmark runs it: pinned host
     input in 16M-point batches, the exact box given as a header, every output
     compared with the oracle; then the same build from device memory (the
@@ -82,17 +82,17 @@ def test_config3_full(ctx):
     compared with the streamed one."""
     import torch
     import paper_2302_05002_amd as fpo
-    p = synth.CONFIG3
-    c = synth.config3()
+    p = synth.TERRAIN_200M
+    c = synth.terrain_200m()
     box = exact_box(c)
     got = streamed_vs_oracle(ctx, c, p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity,
-                             p.preview_modulus, box, 16_000_000, "config3: ")
-    print("[streamed] config3 from device memory", flush=True)
+                             p.preview_modulus, box, 16_000_000, "terrain 200M: ")
+    print("[streamed] terrain 200M from device memory", flush=True)
     dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (c.x, c.y, c.z)]
     res = ctx.build(*dev, fpo.Params(p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity,
                                      p.preview_modulus, box)).to_numpy()
     for k in got:
-        assert np.array_equal(np.asarray(res[k]), np.asarray(got[k])), f"config3 resident: {k} differs"
+        assert np.array_equal(np.asarray(res[k]), np.asarray(got[k])), f"terrain 200M resident: {k} differs"
 
 
 def test_streamed_nonfinite_with_given_box(ctx):

@@ -115,8 +115,8 @@ def test_full_size_planes_tree_from_gpu_build(ctx):
     over the same table."""
     import torch
     import paper_2302_05002_amd as fpo
-    c = synth.config2()
-    p = synth.CONFIG2
+    c = synth.planes_20m()
+    p = synth.PLANES_20M
     x, y, z = (torch.from_numpy(a).cuda() for a in (c.x, c.y, c.z))
     res = ctx.build(x, y, z, fpo.Params(p.count_grid, p.max_points_per_chunk, p.subsample_grid, p.leaf_capacity,
                                         p.preview_modulus))

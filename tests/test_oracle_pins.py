@@ -67,13 +67,13 @@ def test_h64_known_answers():
     assert idx[:10].tolist() == pv["first10"] and idx[-3:].tolist() == pv["last3"]
 
 
-def test_config1_closed_forms():
+def test_uniform_1m_closed_forms():
     """Uniform 1M points, G=64, C=100k, S=32, L=10k: all 64 level-2 chunks
     (level-2 cells hold ~15.6k <= C, level-1 ~125k > C); the root's 32^3 grid is
     fully occupied (P(empty) = e^-30.5 per cell); a depth-1 node receives
     125000 - 4096 points and keeps about 32768 (1 - e^-3.69); depth-2 nodes receive about 11.1k > L and keep about
     9.4k; the 512 depth-3 nodes are leaves of about 211 points: 585 nodes."""
-    c = synth.config1()
+    c = synth.uniform_1m()
     r = _run(c, 64, 100_000, 32, 10_000, 64)
     assert r["chunk_level"].shape[0] == 64 and np.all(r["chunk_level"] == 2)
     assert r["chunk_oversized_any"] == 0
