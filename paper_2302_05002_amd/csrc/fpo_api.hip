@@ -367,8 +367,12 @@ hipEvent_t get_event(fpo_context *c)
             return e;
         }
     }
+    // timing only: their elapsed times are read once the job's completion
+    // event (system-scope release) has been seen, so they need no fence of
+    // their own, whose cache writeback and invalidation would slow the work
+    // they bracket
     hipEvent_t e = nullptr;
-    if (alloc_fault(c) || hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (alloc_fault(c) || hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
